@@ -1,0 +1,180 @@
+"""Seeded synthetic electrode/electrolyte slabs.
+
+This module only places particles and assigns charges (numpy, seeded); it holds
+none of the method's arithmetic.  It feeds the same inputs to the GPU library and,
+in the tests, to the CPU checker.
+
+Units: nm, e, V.  Every workload is a dict with keys
+
+  params   : dict(Lx, Ly, H, lam, alpha, eta, rc, coulomb_k, M, P)
+  ion_pos  : float64 (N_ion, 3)      ion_q : float64 (N_ion,)
+  ele_pos  : float64 (N_ele, 3)      ele_side : int8 (N_ele,) (-1 negative, +1 positive)
+  dpsi     : float (V)
+
+Placement recipes (the inputs stand in for the paper's MD snapshots of
+graphene / coarse-grained ionic liquid, Sec. 4, which need a force field and an
+equilibration run this project does not have):
+
+* tiny slab: two 12x12 square walls (0.2 nm) at z = 0 and z = H = 8 nm in a
+  2.4 x 2.4 nm cell; 100 + 100 ions of +-0.78 e placed by random sequential
+  addition (RSA, 0.3 nm minimum separation, periodic in x and y) in
+  z in [0.4, 7.6]; alpha = 3 /nm, eta = 1/19.79 nm, rc = 1.2 nm, M = 10, P = 100.
+* paper-shaped cell: 3.4 x 3.7 x 12 nm; three honeycomb-topology layers of 360
+  atoms per electrode (10 x 9 four-atom rectangular cells stretched to the box,
+  AB-shifted, 0.335 nm apart); 320 rigid bent three-site cations
+  (+0.1135, +0.2, +0.4665 e; 0.30 nm bonds at 120 degrees; random orientation)
+  and 320 one-site anions (-0.78 e), RSA 0.3 nm in z in [1.07, H - 1.07];
+  alpha = 3.5 /nm, eta = 0.0556 nm, rc = 1.2 nm, M = 13, P = 200.
+* replica batch: R copies of the paper-shaped cell with placement seeds
+  1100 + r and voltages drawn uniformly from [0, 4] V.
+* per-step jitter: N(0, 0.01^2 nm^2) per axis and site; x, y wrap, z reflects
+  back into the electrolyte interval.
+"""
+
+import numpy as np
+
+COULOMB_K = 1.43996454784  # e^2 / (4 pi eps0), in eV nm / e^2
+
+
+def _rsa_accept(cand, placed, Lx, Ly, dmin):
+    """True if every candidate site is at least dmin from every placed site (periodic in x, y)."""
+    if placed is None or len(placed) == 0:
+        return True
+    d = cand[:, None, :] - placed[None, :, :]
+    d[..., 0] -= Lx * np.round(d[..., 0] / Lx)
+    d[..., 1] -= Ly * np.round(d[..., 1] / Ly)
+    return bool(np.all(np.sum(d * d, axis=2) >= dmin * dmin))
+
+
+def _rsa_sites(rng, n, Lx, Ly, zlo, zhi, dmin, max_tries=200000):
+    placed = np.zeros((0, 3))
+    tries = 0
+    while len(placed) < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("random sequential addition did not converge")
+        c = np.array([[rng.uniform(0, Lx), rng.uniform(0, Ly), rng.uniform(zlo, zhi)]])
+        if _rsa_accept(c, placed, Lx, Ly, dmin):
+            placed = np.vstack([placed, c])
+    return placed
+
+
+def square_wall(n, a, z):
+    g = (np.arange(n) + 0.5) * a
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    return np.column_stack([X.ravel(), Y.ravel(), np.full(n * n, float(z))])
+
+
+def honeycomb_layer(nx, ny, Lx, Ly, z, shift_frac=0.0):
+    """4-atom rectangular honeycomb cells (fractions (0,0),(1/2,1/6),(1/2,1/2),(0,2/3)) stretched to Lx x Ly."""
+    base = np.array([[0.0, 0.0], [0.5, 1.0 / 6.0], [0.5, 0.5], [0.0, 2.0 / 3.0]])
+    cx, cy = Lx / nx, Ly / ny
+    pts = []
+    for i in range(nx):
+        for j in range(ny):
+            for b in base:
+                x = (i + b[0]) * cx
+                y = (j + b[1] + shift_frac) * cy
+                pts.append([x % Lx, y % Ly, z])
+    return np.array(pts)
+
+
+def tiny_slab(seed=1000, dpsi=2.0):
+    rng = np.random.default_rng(seed)
+    Lx = Ly = 2.4
+    H = 8.0
+    ele = np.vstack([square_wall(12, 0.2, 0.0), square_wall(12, 0.2, H)])
+    side = np.array([-1] * 144 + [1] * 144, dtype=np.int8)
+    ion = _rsa_sites(rng, 200, Lx, Ly, 0.4, H - 0.4, 0.3)
+    q = np.array([0.78] * 100 + [-0.78] * 100)
+    params = dict(Lx=Lx, Ly=Ly, H=H, lam=3.0, alpha=3.0, eta=1.0 / 19.79, rc=1.2,
+                  coulomb_k=COULOMB_K, M=10, P=100)
+    return dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=float(dpsi))
+
+
+CATION_Q = (0.1135, 0.2, 0.4665)
+ANION_Q = -0.78
+
+
+def _random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    a, b, c, d = q
+    return np.array([[a * a + b * b - c * c - d * d, 2 * (b * c - a * d), 2 * (b * d + a * c)],
+                     [2 * (b * c + a * d), a * a - b * b + c * c - d * d, 2 * (c * d - a * b)],
+                     [2 * (b * d - a * c), 2 * (c * d + a * b), a * a - b * b - c * c + d * d]])
+
+
+def _cation_template():
+    bond = 0.30
+    ang = np.deg2rad(120.0)
+    mid = np.zeros(3)
+    e1 = np.array([bond, 0.0, 0.0])
+    e2 = bond * np.array([np.cos(ang), np.sin(ang), 0.0])
+    return np.array([e1, mid, e2])
+
+
+def paper_cell(seed=1001, dpsi=2.0, n_pairs=320):
+    rng = np.random.default_rng(seed)
+    Lx, Ly, H = 3.4, 3.7, 12.0
+    dz = 0.335
+    layers = []
+    for li, z in enumerate([0.0, dz, 2 * dz]):
+        layers.append(honeycomb_layer(10, 9, Lx, Ly, z, shift_frac=(li % 2) / 3.0))
+    for li, z in enumerate([H - 2 * dz, H - dz, H]):
+        layers.append(honeycomb_layer(10, 9, Lx, Ly, z, shift_frac=(li % 2) / 3.0))
+    ele = np.vstack(layers)
+    side = np.array([-1] * 1080 + [1] * 1080, dtype=np.int8)
+    zlo, zhi = 1.07, H - 1.07
+    tmpl = _cation_template()
+    placed = np.zeros((0, 3))
+    cations = []
+    tries = 0
+    while len(cations) < n_pairs:
+        tries += 1
+        if tries > 500000:
+            raise RuntimeError("cation placement did not converge")
+        c = np.array([rng.uniform(0, Lx), rng.uniform(0, Ly), rng.uniform(zlo, zhi)])
+        sites = c[None, :] + tmpl @ _random_rotation(rng).T
+        if np.any(sites[:, 2] < zlo) or np.any(sites[:, 2] > zhi):
+            continue
+        sites[:, 0] %= Lx
+        sites[:, 1] %= Ly
+        if _rsa_accept(sites, placed, Lx, Ly, 0.3):
+            placed = np.vstack([placed, sites])
+            cations.append(sites)
+    anions = []
+    while len(anions) < n_pairs:
+        tries += 1
+        if tries > 1000000:
+            raise RuntimeError("anion placement did not converge")
+        c = np.array([[rng.uniform(0, Lx), rng.uniform(0, Ly), rng.uniform(zlo, zhi)]])
+        if _rsa_accept(c, placed, Lx, Ly, 0.3):
+            placed = np.vstack([placed, c])
+            anions.append(c[0])
+    ion = np.vstack([np.vstack(cations), np.array(anions)])
+    q = np.concatenate([np.tile(CATION_Q, n_pairs), np.full(n_pairs, ANION_Q)])
+    params = dict(Lx=Lx, Ly=Ly, H=H, lam=3.0, alpha=3.5, eta=0.0556, rc=1.2,
+                  coulomb_k=COULOMB_K, M=13, P=200)
+    return dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=float(dpsi))
+
+
+def replica_batch(R=64, base_seed=1100, dpsi_seed=3000, n_pairs=320):
+    """R paper-shaped cells sharing one electrode geometry; per-replica ions and voltage."""
+    reps = [paper_cell(seed=base_seed + r, n_pairs=n_pairs) for r in range(R)]
+    dpsi = np.random.default_rng(dpsi_seed).uniform(0.0, 4.0, size=R)
+    out = dict(params=reps[0]["params"], ele_pos=reps[0]["ele_pos"], ele_side=reps[0]["ele_side"],
+               ion_pos=[r["ion_pos"] for r in reps], ion_q=[r["ion_q"] for r in reps], dpsi=dpsi)
+    return out
+
+
+def jitter(pos, sigma, rng, Lx, Ly, zlo, zhi):
+    """Gaussian per-axis displacement; x, y wrap into the cell, z reflects into [zlo, zhi]."""
+    out = pos + rng.normal(scale=sigma, size=pos.shape)
+    out[:, 0] %= Lx
+    out[:, 1] %= Ly
+    z = out[:, 2]
+    z = np.where(z < zlo, 2 * zlo - z, z)
+    z = np.where(z > zhi, 2 * zhi - z, z)
+    out[:, 2] = z
+    return out

@@ -1,0 +1,405 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test compares the oracle with something other than itself: a library
+routine, a closed form, a brute-force sum, a derivative taken numerically, or an
+identity the paper states.  A dropped term, a wrong sign or factor, or a
+transposed operand in the oracle fails at least one of them.
+"""
+
+import numpy as np
+import pytest
+from scipy.stats import norm
+
+from oracle import cp, ewald, ewald2d, philox, sampler, srbe
+
+
+# ---------------------------------------------------------------- helpers
+
+
+def tiny_system(seed=5, n_ion=6, lam=3.0, alpha=5.0, M=4, P=20, tol=1e-14):
+    """Two 3x3 Gaussian walls and a few ions (cheap enough for finite differences)."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly, H = 1.2, 1.2, 2.0
+    g = (np.arange(3) + 0.5) * 0.4
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    wall = np.column_stack([X.ravel(), Y.ravel()])
+    ele = np.vstack([np.column_stack([wall, np.zeros(9)]), np.column_stack([wall, np.full(9, H)])])
+    side = np.array([-1] * 9 + [1] * 9)
+    ion = np.column_stack([rng.uniform(0, Lx, n_ion), rng.uniform(0, Ly, n_ion),
+                           rng.uniform(0.4, H - 0.4, n_ion)])
+    q = np.resize([0.8, -0.8], n_ion).astype(float)
+    p = ewald.Params(Lx=Lx, Ly=Ly, H=H, lam=lam, alpha=alpha, eta=0.08, rc=0.6, coulomb_k=1.44,
+                     M=M, P=P, kspace_tol=tol)
+    return p, ion, q, ele, side
+
+
+# ---------------------------------------------------------------- Philox
+
+
+def test_philox_matches_numpy_reference():
+    # numpy's Philox bit generator is Philox4x64-10; it increments its counter
+    # before each block, so counter c with numpy gives our block c + 1.
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        key = rng.integers(0, 2 ** 63, size=2, dtype=np.uint64)
+        c = rng.integers(0, 2 ** 63, size=4, dtype=np.uint64)
+        ref = np.random.Philox(counter=c, key=key).random_raw(4)
+        c1 = c.copy()
+        c1[0] += np.uint64(1)
+        assert np.array_equal(philox.philox4x64_10(c1, key), ref)
+    # carry out of the low counter word
+    key = np.array([7, 9], dtype=np.uint64)
+    ref = np.random.Philox(counter=np.array([2 ** 64 - 1, 5, 0, 0], dtype=np.uint64), key=key).random_raw(4)
+    assert np.array_equal(philox.philox4x64_10(np.array([0, 6, 0, 0], dtype=np.uint64), key), ref)
+
+
+def test_uniforms_open_interval():
+    u = philox.u01_open(np.array([0, 2 ** 64 - 1], dtype=np.uint64))
+    assert 0.0 < u[0] < 1e-15 and 1.0 - 1e-15 < u[1] < 1.0
+    assert u[0] == 2.0 ** -53 and u[1] == 1.0 - 2.0 ** -53
+
+
+# ---------------------------------------------------------------- G and the proposal
+
+
+def test_G_equals_bruteforce_sum():
+    p = ewald.Params(Lx=2.4, Ly=2.4, H=8.0, lam=3.0, alpha=3.0, M=10)
+    m = ewald.enumerate_modes(p, tol=1e-300)
+    k2 = np.sum(ewald.kvectors(p, m) ** 2, axis=1)
+    inI = (m[:, 0] == 0) & (m[:, 1] == 0) & (np.abs(m[:, 2]) <= p.M)
+    brute = np.sum(np.exp(-k2[~inI] / (4 * p.alpha ** 2)))
+    assert srbe.normaliser_G(p) == pytest.approx(brute, rel=1e-12)
+    assert srbe.normaliser_G(p) == pytest.approx(650.6838622, rel=1e-8)
+
+
+def test_q_axis_is_pmf_of_rounded_gaussian():
+    # Eq. (28) with the proposal variance alpha^2 L^2/(2 pi^2): q_d(m) must be the
+    # probability that round(u) = m for u ~ N(0, sigma^2) (library normal CDF).
+    for alpha, L in [(3.0, 2.4), (3.5, 36.0), (3.0, 300.0)]:
+        sig = alpha * L / (np.sqrt(2) * np.pi)
+        m = np.arange(-int(9 * sig) - 3, int(9 * sig) + 4)
+        ref = norm.cdf((m + 0.5) / sig) - norm.cdf((m - 0.5) / sig)
+        got = sampler.q_axis(m, alpha, L)
+        assert np.max(np.abs(got - ref)) < 1e-14
+        assert abs(np.sum(got) - 1.0) < 1e-12
+
+
+def test_sampler_distribution_chi2():
+    # Frequencies of sampled modes against P(k) = exp(-k^2/4a^2)/G on L_k \ I.
+    # Chains are thinned (every 10th state; acceptance ~0.8, so states 10 apart
+    # are independent to ~1e-7) to give independent counts.
+    p = ewald.Params(Lx=1.2, Ly=1.2, H=1.5, lam=2.0, alpha=3.0, M=2)
+    P, thin, chains = 200, 10, 1000
+    counts = {}
+    nacc = 0
+    for c in range(chains):
+        ks, na = sampler.draw_kset(p, seed=42, stream=c, step=3, P=P)
+        assert np.all(sampler.valid(p, ks))
+        nacc += na
+        for row in map(tuple, ks[thin - 1::thin]):
+            counts[row] = counts.get(row, 0) + 1
+    n = sum(counts.values())
+    assert nacc / (chains * P) > 0.75
+    G = srbe.normaliser_G(p)
+    allm = ewald.enumerate_modes(p, tol=1e-30)
+    allm = allm[sampler.valid(p, allm)]
+    pk = np.exp(-np.sum(ewald.kvectors(p, allm) ** 2, axis=1) / (4 * p.alpha ** 2)) / G
+    order = np.argsort(-pk)[:40]
+    obs = np.array([counts.get(tuple(allm[i]), 0) for i in order], dtype=float)
+    exp = n * pk[order]
+    obs = np.append(obs, n - obs.sum())
+    exp = np.append(exp, n - exp.sum())
+    chi2 = np.sum((obs - exp) ** 2 / exp)
+    assert chi2 < 90.0  # 40 degrees of freedom: p ~ 1e-5
+
+
+def test_sampler_never_returns_deterministic_modes():
+    p = ewald.Params(Lx=3.4, Ly=3.7, H=12.0, lam=3.0, alpha=3.5, M=13)
+    for step in range(5):
+        ks, _ = sampler.draw_kset(p, seed=7, stream=0, step=step, P=500)
+        assert np.all(sampler.valid(p, ks))
+
+
+# ---------------------------------------------------------------- Ewald core
+
+
+def test_nacl_madelung():
+    a0 = 0.5
+    pts, qs = [], []
+    for i in range(4):
+        for j in range(4):
+            for k in range(4):
+                pts.append([i * a0 / 2, j * a0 / 2, k * a0 / 2])
+                qs.append((-1) ** (i + j + k))
+    pts, qs = np.array(pts), np.array(qs, float)
+    L = 2 * a0
+    p = ewald.Params(Lx=L, Ly=L, H=L, lam=1.0, alpha=12.0, rc=0.4995 * L, coulomb_k=1.0,
+                     slab=False, periodic_z=True, kspace_tol=1e-18)
+    E = ewald.energy(p, pts, qs, np.zeros((0, 3)), np.zeros(0))["total"]
+    madelung = 1.747564594633182
+    assert E == pytest.approx(-len(qs) / 2 * madelung / (a0 / 2), rel=1e-10)
+
+
+def test_alpha_independence_3d():
+    rng = np.random.default_rng(2)
+    L = 1.0
+    pos = rng.uniform(0, L, size=(8, 3))
+    q = np.array([1, -1, 0.5, -0.5, 0.3, -0.3, 1.2, -1.2])
+    Es, Fs = [], []
+    for alpha in (12.0, 14.0, 16.0):
+        p = ewald.Params(Lx=L, Ly=L, H=L, lam=1.0, alpha=alpha, rc=0.499, coulomb_k=1.0,
+                         slab=False, periodic_z=True, kspace_tol=1e-18)
+        Es.append(ewald.energy(p, pos, q, np.zeros((0, 3)), np.zeros(0))["total"])
+        Fs.append(ewald.forces(p, pos, q, np.zeros((0, 3)), np.zeros(0))[0])
+    assert np.ptp(Es) < 1e-10 * abs(Es[0])
+    assert np.max(np.abs(Fs[1] - Fs[0])) < 1e-9 * np.max(np.abs(Fs[0]))
+    assert np.max(np.abs(Fs[2] - Fs[0])) < 1e-9 * np.max(np.abs(Fs[0]))
+
+
+def test_ewald2d_closed_form_vs_image_sum():
+    rng = np.random.default_rng(3)
+    Lx, Ly, H = 1.0, 1.2, 1.5
+    pos = np.column_stack([rng.uniform(0, Lx, 6), rng.uniform(0, Ly, 6), rng.uniform(0.2, H - 0.2, 6)])
+    q = np.array([1, -1, 1, -1, 0.5, -0.5])
+    p = ewald.Params(Lx=Lx, Ly=Ly, H=H, lam=3.0, alpha=6.0, rc=0.5, coulomb_k=1.0)
+    e2d = ewald2d.energy_q2d(p, pos, q)
+    R = 80.0
+    ei = ewald2d.energy_images(p, pos, q, R) + ewald2d.disc_tail(p, pos, q, R)
+    assert abs(ei - e2d) < 2e-5 * abs(e2d)
+
+
+def test_ew3dc_converges_to_ewald2d_with_padding():
+    rng = np.random.default_rng(3)
+    Lx, Ly, H = 1.0, 1.2, 1.5
+    pos = np.column_stack([rng.uniform(0, Lx, 6), rng.uniform(0, Ly, 6), rng.uniform(0.2, H - 0.2, 6)])
+    q = np.array([1, -1, 1, -1, 0.5, -0.5])
+    p = ewald.Params(Lx=Lx, Ly=Ly, H=H, lam=3.0, alpha=6.0, rc=0.5, coulomb_k=1.0)
+    e2d = ewald2d.energy_q2d(p, pos, q)
+    errs = []
+    for lam in (2.0, 3.0, 6.0):
+        E = ewald.energy(p.with_(lam=lam), pos, q, np.zeros((0, 3)), np.zeros(0))["total"]
+        errs.append(abs(E - e2d) / abs(e2d))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 1e-7 and errs[2] < 1e-12
+    # without the slab term the padded sum does not approach the quasi-2D energy
+    E_noslab = ewald.energy(p.with_(lam=6.0, slab=False), pos, q, np.zeros((0, 3)), np.zeros(0))["total"]
+    assert abs(E_noslab - e2d) > 1e-3 * abs(e2d)
+
+
+def test_gaussian_electrodes_vs_image_sum():
+    # EW3DC at lambda = 6 equals the quasi-2D energy to ~1e-12; the brute-force
+    # image sum of point charges and Gaussians checks every kernel of Eq. (13)
+    # and the Gaussian self term of Eq. (17).
+    rng = np.random.default_rng(11)
+    Lx, Ly, H = 1.0, 1.1, 1.2
+    ion = np.column_stack([rng.uniform(0, Lx, 4), rng.uniform(0, Ly, 4), rng.uniform(0.3, H - 0.3, 4)])
+    ion[0] = [0.27, 0.31, 0.08]  # close enough to an electrode for the erfc(r/eta) part to matter
+    q = np.array([1.0, -1.0, 0.6, -0.2])
+    ele = np.array([[0.25, 0.3, 0.0], [0.75, 0.8, 0.0], [0.2, 0.7, H], [0.7, 0.2, H]])
+    Q = np.array([-0.3, -0.2, 0.1, 0.0])
+    p = ewald.Params(Lx=Lx, Ly=Ly, H=H, lam=6.0, alpha=6.0, eta=0.07, rc=0.5, coulomb_k=1.0, kspace_tol=1e-18)
+    E = ewald.energy(p, ion, q, ele, Q)["total"]
+    pos = np.vstack([ion, ele])
+    qq = np.concatenate([q, Q])
+    w = np.concatenate([np.zeros(4), np.full(4, p.eta)])
+    R = 80.0
+    ei = ewald2d.energy_images(p, pos, qq, R, w) + ewald2d.disc_tail(p, pos, qq, R)
+    assert abs(ei - E) < 1e-5 * abs(E)
+
+
+# ---------------------------------------------------------------- derivatives
+
+
+def test_forces_are_minus_gradient_full_ewald():
+    p, ion, q, ele, side = tiny_system()
+    modes = ewald.enumerate_modes(p)
+    Q = np.random.default_rng(1).normal(size=len(ele)) * 0.1
+    Fi, Fe = ewald.forces(p, ion, q, ele, Q, modes)
+    h = 1e-5
+    for i in range(len(ion)):
+        for d in range(3):
+            ip, im = ion.copy(), ion.copy()
+            ip[i, d] += h
+            im[i, d] -= h
+            fd = -(ewald.energy(p, ip, q, ele, Q, modes)["total"] - ewald.energy(p, im, q, ele, Q, modes)["total"]) / (2 * h)
+            assert abs(fd - Fi[i, d]) < 1e-6 * (1 + abs(Fi[i, d]))
+    # one electrode coordinate as well
+    for d in range(3):
+        ep, em = ele.copy(), ele.copy()
+        ep[4, d] += h
+        em[4, d] -= h
+        fd = -(ewald.energy(p, ion, q, ep, Q, modes)["total"] - ewald.energy(p, ion, q, em, Q, modes)["total"]) / (2 * h)
+        assert abs(fd - Fe[4, d]) < 1e-6 * (1 + abs(Fe[4, d]))
+
+
+def test_A_and_b_are_derivatives_of_energy():
+    # Pins the readings of Eqs. (18)-(19): A = d2U/dQ2 (slab entry 4 pi/V) and
+    # b = -dU/dQ at Q = 0 (slab entry with a minus sign), and U = 1/2 QAQ - bQ + c.
+    p, ion, q, ele, side = tiny_system()
+    modes = ewald.enumerate_modes(p)
+    A = ewald.electrode_matrix(p, ele, modes)
+    b = ewald.electrode_vector(p, ion, q, ele, modes)
+    c = ewald.constant_term(p, ion, q, modes)
+    rng = np.random.default_rng(4)
+    Q = rng.normal(size=len(ele)) * 0.1
+    U = lambda Qv: ewald.energy(p, ion, q, ele, Qv, modes)["total"]
+    assert U(Q) == pytest.approx(0.5 * Q @ A @ Q - b @ Q + c, rel=1e-12, abs=1e-12)
+    h = 1e-3
+    n = len(ele)
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = h
+        g = (U(e) - U(-e)) / (2 * h)
+        assert abs(g + b[j]) < 1e-9
+    for (i, j) in [(0, 0), (0, 1), (0, 10), (4, 13), (17, 17)]:
+        ei = np.zeros(n)
+        ej = np.zeros(n)
+        ei[i] = h
+        ej[j] = h
+        hess = (U(ei + ej) - U(ei - ej) - U(-ei + ej) + U(-ei - ej)) / (4 * h * h)
+        assert abs(hess - A[i, j]) < 1e-7 * (1 + abs(A[i, j]))
+    assert np.allclose(A, A.T, atol=1e-14 * np.max(np.abs(A)))
+    assert np.min(np.linalg.eigvalsh(A)) > 0
+
+
+def test_srbe_forces_are_minus_gradient_of_srbe_energy():
+    p, ion, q, ele, side = tiny_system()
+    modes = ewald.enumerate_modes(p)
+    A = ewald.electrode_matrix(p, ele, modes)
+    ks, _ = sampler.draw_kset(p, seed=9, stream=0, step=1)
+    Q = np.random.default_rng(8).normal(size=len(ele)) * 0.1
+    F = srbe.srbe_ion_forces(p, ks, ion, q, ele, Q)
+    h = 1e-5
+    for i in range(len(ion)):
+        for d in range(3):
+            ip, im = ion.copy(), ion.copy()
+            ip[i, d] += h
+            im[i, d] -= h
+            fd = -(srbe.srbe_energy(p, A, ks, ip, q, ele, Q) - srbe.srbe_energy(p, A, ks, im, q, ele, Q)) / (2 * h)
+            assert abs(fd - F[i, d]) < 1e-6 * (1 + abs(F[i, d]))
+
+
+# ---------------------------------------------------------------- constant-potential solve
+
+
+@pytest.fixture(scope="module")
+def cp_system():
+    p, ion, q, ele, side = tiny_system()
+    modes = ewald.enumerate_modes(p)
+    A = ewald.electrode_matrix(p, ele, modes)
+    b = ewald.electrode_vector(p, ion, q, ele, modes)
+    return p, ion, q, ele, side, A, b, cp.Solver(A)
+
+
+def test_cp_neutral_and_equipotential(cp_system):
+    p, ion, q, ele, side, A, b, sol = cp_system
+    dpsi = 2.0
+    Q, psibar = sol.solve(side, dpsi, b)
+    assert abs(np.sum(Q)) < 1e-14 * np.sum(np.abs(Q))
+    Psi = A @ Q - b
+    neg, pos = side < 0, side > 0
+    assert np.ptp(Psi[neg]) < 1e-12 and np.ptp(Psi[pos]) < 1e-12
+    assert Psi[neg].mean() == pytest.approx(psibar - dpsi / 2, abs=1e-12)
+    assert Psi[pos].mean() == pytest.approx(psibar + dpsi / 2, abs=1e-12)
+    assert np.sum(Q[neg]) == pytest.approx(-np.sum(Q[pos]), abs=1e-14)
+
+
+def test_cp_linear_in_voltage_and_gauge_invariant(cp_system):
+    p, ion, q, ele, side, A, b, sol = cp_system
+    Q0, _ = sol.solve(side, 0.0, b)
+    Q1, _ = sol.solve(side, 1.0, b)
+    Q3, _ = sol.solve(side, 3.0, b)
+    assert np.allclose(Q3 - Q0, 3.0 * (Q1 - Q0), atol=1e-13)
+    Qg, _ = sol.solve(side, 1.0, b + 0.37)  # any constant added to b (e.g. the Eq. (19) +dpsi)
+    assert np.allclose(Qg, Q1, atol=1e-13)
+    S = sol.inverse_projected()
+    assert np.allclose(S @ (1.0 * cp.side_vector(side) + b), Q1, atol=1e-12)
+
+
+def test_empty_capacitor():
+    # No ions: the negative electrode charges negatively for dpsi > 0, the charge is
+    # close to the parallel-plate value, and under neutrality it does not depend on
+    # the vacuum padding (Sec. 2, after Eq. (11)).
+    p, ion, q, ele, side = tiny_system()
+    outs = []
+    for lam in (3.0, 6.0):
+        pl = p.with_(lam=lam)
+        A = ewald.electrode_matrix(pl, ele)
+        Q, _ = cp.Solver(A).solve(side, 2.0, np.zeros(len(ele)))
+        outs.append(Q)
+    qneg = np.sum(outs[0][side < 0])
+    assert qneg < 0
+    plate = p.Lx * p.Ly * 2.0 / (4 * np.pi * p.coulomb_k * p.H)
+    assert abs(-qneg - plate) < 0.15 * plate
+    assert np.max(np.abs(outs[0] - outs[1])) < 1e-6 * np.max(np.abs(outs[0]))
+
+
+# ---------------------------------------------------------------- SRBE structure and statistics
+
+
+def test_srbe_deterministic_part_is_exact():
+    # With an empty batch only the modes of I remain; they must equal the full
+    # sum restricted to I, independently of any seed.
+    p, ion, q, ele, side = tiny_system(M=6)
+    mI = srbe.deterministic_modes(p.M)
+    bI = srbe.srbe_b_fourier(p, np.zeros((0, 3)), ion, q, ele)
+    S1 = ewald.structure_factor(p, mI, ion, q)
+    k2 = np.sum(ewald.kvectors(p, mI) ** 2, axis=1)
+    ref = np.zeros(len(ele))
+    for t in range(len(mI)):
+        ref -= ewald.ewald_weight(p, k2[t]) * np.real(np.exp(-1j * ele @ ewald.kvectors(p, mI[t:t + 1])[0]) * S1[t])
+    assert np.allclose(bI, p.coulomb_k * ref, rtol=0, atol=1e-13)
+
+
+def test_momentum_conserved_per_sample(cp_system):
+    p, ion, q, ele, side, A, b, sol = cp_system
+    ks, _ = sampler.draw_kset(p, seed=5, stream=0, step=2)
+    bs = srbe.srbe_b(p, ks, ion, q, ele)
+    Q, _ = sol.solve(side, 2.0, bs)
+    Fi = srbe.srbe_ion_forces(p, ks, ion, q, ele, Q)
+    Fe = srbe.srbe_ele_forces(p, ks, ion, q, ele, Q)
+    tot = Fi.sum(axis=0) + Fe.sum(axis=0)
+    assert np.max(np.abs(tot)) < 1e-12 * np.max(np.abs(Fi))
+
+
+def test_srbe_unbiased():
+    # Theorems 3.1, 3.2: b*_F and F*_F (fixed Q) have the full Ewald sums as mean.
+    p, ion, q, ele, side = tiny_system(M=3, P=10, tol=1e-16)
+    modes = ewald.enumerate_modes(p)
+    Q = np.random.default_rng(2).normal(size=len(ele)) * 0.1
+    k2 = np.sum(ewald.kvectors(p, modes) ** 2, axis=1)
+    w = ewald.ewald_weight(p, k2)
+    S1 = ewald.structure_factor(p, modes, ion, q)
+    b_ref = -p.coulomb_k * ewald.fourier_potential(p, modes, w * S1, ele)
+    S = S1 + ewald.structure_factor(p, modes, ele, Q)
+    F_ref = -p.coulomb_k * q[:, None] * ewald.fourier_gradient_term(p, modes, w * S, ion)
+    B = 3000
+    bs = np.zeros((B, len(ele)))
+    Fs = np.zeros((B, len(ion), 3))
+    for t in range(B):
+        ks, _ = sampler.draw_kset(p, seed=77, stream=0, step=t)
+        bs[t] = srbe.srbe_b_fourier(p, ks, ion, q, ele)
+        Fs[t] = srbe.srbe_force_fourier(p, ks, ion, q, ele, Q)
+    zb = (bs.mean(0) - b_ref) / (bs.std(0) / np.sqrt(B))
+    zF = (Fs.mean(0) - F_ref) / (Fs.std(0) / np.sqrt(B))
+    assert np.max(np.abs(zb)) < 5.0
+    assert np.max(np.abs(zF)) < 5.0
+    # variance shrinks like 1/P
+    bs4 = np.array([srbe.srbe_b_fourier(p.with_(P=40), sampler.draw_kset(p.with_(P=40), 78, 0, t)[0], ion, q, ele)
+                    for t in range(600)])
+    ratio = bs[:600].var(0).mean() / bs4.var(0).mean()
+    assert 2.5 < ratio < 6.0
+
+
+def test_srbe_weight_normalisation():
+    # E[sum_l w_l] over batches must equal sum over L_k \ I of 4 pi exp(-k^2/4a^2)/(V k^2):
+    # pins the G/P factor and the 4 pi/(V k^2) weight of Eq. (24) with no cancellation.
+    p = ewald.Params(Lx=1.2, Ly=1.3, H=1.5, lam=3.0, alpha=4.0, M=3, P=16)
+    modes = ewald.enumerate_modes(p, tol=1e-30)
+    modes = modes[sampler.valid(p, modes)]
+    exact = np.sum(ewald.ewald_weight(p, np.sum(ewald.kvectors(p, modes) ** 2, axis=1)))
+    B = 4000
+    tot = np.array([srbe.mode_weights(p, sampler.draw_kset(p, 3, 0, t)[0])[3].sum() for t in range(B)])
+    z = (tot.mean() - exact) / (tot.std() / np.sqrt(B))
+    assert abs(z) < 5.0
+    assert abs(tot.mean() / exact - 1.0) < 0.02
