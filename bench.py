@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""Throughput of the SRBE constant-potential step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Headline workload ("replica batch"): 64 paper-shaped electrode / ionic-liquid cells
+(3.4 x 3.7 x 12 nm, lambda = 3, 2160 electrode atoms in three honeycomb layers per
+side, 320 three-site cations + 320 anions = 1280 ion sites; alpha = 3.5 /nm,
+eta = 0.0556 nm, rc = 1.2 nm, M = 13, P = 200), one voltage in [0, 4] V and one seed
+per replica, all replicas in one srbe_step call, FP32 k-space and real space with
+the FP64 charge solve.  One "step" is one full SRBE step (sampling, structure
+factors, b*, charge solve, forces, energy) for all 64 replicas; inputs are resident
+in HBM.  The FP64 path on a single cell is timed beside it.
+
+Metric: k-particle pairs per second, pairs/step = sum over replicas of
+(N_ion + N_ele) (M + P); steps/s and the 1-fs ns/day equivalent are reported too.
+Printed as one JSON line.
+"""
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LANE_OPS_PEAK = 256 * 64 * 2.4e9  # VALU lane-ops per second: 256 CUs x 64 lanes x 2.4 GHz
+
+# VALU slot-equivalents per (particle, mode) pair for the FP32 k-space passes: exact
+# integer phase (3 multiplies + 1 three-way add), int->float + scale (2), sin and cos
+# of the phase (2 instructions issuing at half rate: 4 slots), then the accumulation:
+# structure factor 2 FMA; electrode potential 2 FMA; force 2 (Im part) + 3 FMA.
+SLOTS = {"sf_ions": 12, "sf_ele": 12, "ele_potential": 12, "ion_force": 15}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step has no multi-GPU path "
+              f"in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    R = args.replicas
+    t0 = time.time()
+    wb = wl.replica_batch(R=R)
+    gen_s = time.time() - t0
+    log(f"generated {R} replicas in {gen_s:.1f} s")
+    wp = dict(wb["params"], kspace_tol=1e-16)
+    t0 = time.time()
+    sysm = srbe_amd.System(wp, wb["ele_pos"], wb["ele_side"])
+    setup_s = time.time() - t0
+    log(f"electrode set-up (A, Cholesky, J A^-1) in {setup_s:.2f} s")
+    n_ele = sysm.n_ele
+    sizes = [len(q) for q in wb["ion_q"]]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate(wb["ion_pos"])
+    xyz = torch.tensor(np.ascontiguousarray(pos.T).ravel(), dtype=torch.float64, device=dev)
+    q = torch.tensor(np.concatenate(wb["ion_q"]), dtype=torch.float64, device=dev)
+    dpsi = torch.tensor(wb["dpsi"], dtype=torch.float64, device=dev)
+    seeds = torch.tensor(2100 + np.arange(R), dtype=torch.int64, device=dev).view(torch.uint64)
+    M, P = int(wp["M"]), int(wp["P"])
+    K = M + P
+    pairs_per_step = int(sum(n + n_ele for n in sizes)) * K
+    paper_pairs_per_step = int(sum(n + n_ele for n in sizes)) * (2 * M + P)
+
+    out = None
+    stream = torch.cuda.current_stream()
+
+    def run(steps, first, prec, offs, x, qq, dp, sd, o):
+        for i in range(steps):
+            o = sysm.step(offs, x, qq, dp, sd, first + i, precision=prec, want_kset=False, out=o)
+        return o
+
+    def timed(prec, offs, x, qq, dp, sd):
+        o = run(args.warmup, 0, prec, offs, x, qq, dp, sd, None)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        o = run(args.steps, args.warmup, prec, offs, x, qq, dp, sd, o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        code = srbe_amd.srbe_sync_status(sysm.h)
+        if code != 0:
+            raise RuntimeError(srbe_amd.srbe_last_error(sysm.h))
+        return e0.elapsed_time(e1) / args.steps, o
+
+    # ---- headline: FP32, all replicas in one step
+    ms_fp32, out = timed(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
+    log(f"FP32 batch: {ms_fp32 * 1e3:.1f} us/step")
+
+    # ---- per-phase durations (HIP events recorded by the library on the step's stream)
+    srbe_amd.srbe_profile_enable(sysm.h, True)
+    nprof = min(args.steps, 50)
+    run(nprof, args.warmup + args.steps, srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds, out)
+    torch.cuda.synchronize()
+    prof = srbe_amd.srbe_profile_read(sysm.h)
+    srbe_amd.srbe_profile_enable(sysm.h, False)
+    phases = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in prof.items() if v[1]}
+
+    # ---- FP64 plain path on one cell
+    off1 = np.array([0, sizes[0]], dtype=np.int64)
+    xyz1 = torch.tensor(np.ascontiguousarray(wb["ion_pos"][0].T).ravel(), dtype=torch.float64, device=dev)
+    q1 = torch.tensor(wb["ion_q"][0], dtype=torch.float64, device=dev)
+    ms_fp64_1, _ = timed(srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
+    pairs_1 = (sizes[0] + n_ele) * K
+    # FP32 on a single cell, for the batching gain
+    ms_fp32_1, _ = timed(srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
+    log(f"single cell: FP64 {ms_fp64_1 * 1e3:.1f} us/step, FP32 {ms_fp32_1 * 1e3:.1f} us/step")
+
+    # ---- roofline of the dominant k-space kernel
+    kpairs = {
+        "sf_ions": sum(sizes) * K,
+        "sf_ele": R * n_ele * K,
+        "ele_potential": R * n_ele * K,
+        "ion_force": sum(sizes) * K,
+    }
+    kdom = max((k for k in SLOTS if k in phases), key=lambda k: phases[k]["avg_us"])
+    ach = kpairs[kdom] * SLOTS[kdom] / (phases[kdom]["avg_us"] * 1e-6)
+    roofline = {"bound": "alu", "kernel": kdom, "achieved": ach / 1e12, "peak": LANE_OPS_PEAK / 1e12,
+                "unit": "TVALUop/s", "frac": ach / LANE_OPS_PEAK, "traffic": None}
+    top = max(phases, key=lambda k: phases[k]["avg_us"])
+
+    result = {
+        "metric": "SRBE k-particle pairs/s (FP32-batched step; FP64 plain beside it)",
+        "value": pairs_per_step / (ms_fp32 * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_fp32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (k-space, real space); f64 (charge solve, energy)",
+        "data": "synthetic",
+        "config": {"workload": f"replica batch: {R} paper-shaped cells (1280 ion sites + 2160 electrode atoms), "
+                               f"M={M}, P={P}, alpha=3.5/nm, rc=1.2 nm", "replicas": R,
+                   "pairs_per_step": pairs_per_step, "paper_pair_count_per_step": paper_pairs_per_step},
+        "steps_per_s": 1e3 / ms_fp32,
+        "ns_per_day_equiv_1fs": 1e3 / ms_fp32 * 0.0864,
+        "fp64_plain_single_cell": {"ms_per_step": ms_fp64_1, "pairs_per_s": pairs_1 / (ms_fp64_1 * 1e-3),
+                                   "steps_per_s": 1e3 / ms_fp64_1},
+        "fp32_single_cell": {"ms_per_step": ms_fp32_1, "pairs_per_s": pairs_1 / (ms_fp32_1 * 1e-3)},
+        "speedup_vs_fp64_plain_pairs_per_s": (pairs_per_step / ms_fp32) / (pairs_1 / ms_fp64_1),
+        "roofline": roofline,
+        "phases_us": {k: round(v["avg_us"], 2) for k, v in phases.items()},
+        "slowest_phase": top,
+        "setup_s": setup_s,
+        "workload_generation_s": gen_s,
+    }
+
+    if not args.no_cpu:
+        o = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, want_kset=False)
+        torch.cuda.synchronize()
+        acc = {"off": off, "F": o["F"].cpu().numpy(), "Q": o["Q"].cpu().numpy(), "E": o["E"].cpu().numpy()}
+        result.update(cpu_side(wb, wp, acc, R, sizes, n_ele, K))
+    print(json.dumps(result), flush=True)
+    sysm.close()
+
+
+def cpu_side(wb, wp, acc, R, sizes, n_ele, K):
+    """The oracle's own throughput on a bounded sample, and the FP32 errors of those replicas.
+
+    acc: host copies of one FP32 GPU step at step index 0 (Q, F SoA, E, offsets).
+    """
+    from oracle import cp, ewald, sampler, srbe
+
+    p = ewald.Params(Lx=wp["Lx"], Ly=wp["Ly"], H=wp["H"], lam=wp["lam"], alpha=wp["alpha"], eta=wp["eta"],
+                     rc=wp["rc"], coulomb_k=wp["coulomb_k"], M=int(wp["M"]), P=int(wp["P"]),
+                     kspace_tol=wp["kspace_tol"])
+    t0 = time.time()
+    log("building the oracle's electrode matrix ...")
+    solver = cp.Solver(ewald.electrode_matrix(p, wb["ele_pos"]))
+    oracle_setup_s = time.time() - t0
+    log(f"oracle A in {oracle_setup_s:.1f} s; timing oracle steps")
+    ru0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.time()
+    refs = []
+    for r in range(R):
+        ks, _ = sampler.draw_kset(p, 2100 + r, 0, 0)
+        refs.append(srbe.srbe_step(p, solver, ks, wb["ion_pos"][r], wb["ion_q"][r], wb["ele_pos"], wb["ele_side"],
+                                   float(wb["dpsi"][r])))
+        if time.time() - t0 > 15.0:
+            break
+    wall = time.time() - t0
+    ru1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+    nsample = len(refs)
+    pairs = sum(sizes[r] + n_ele for r in range(nsample)) * K
+    off = acc["off"]
+    N = int(off[-1])
+    F = acc["F"].reshape(3, N)
+    errF, errQ, errE = [], [], []
+    for r, ref in enumerate(refs):
+        Fg = F[:, off[r]:off[r + 1]].T
+        errF.append(np.linalg.norm(Fg - ref["F"]) / np.linalg.norm(ref["F"]))
+        Qg = acc["Q"][r * n_ele:(r + 1) * n_ele]
+        errQ.append(np.linalg.norm(Qg - ref["Q"]) / np.linalg.norm(ref["Q"]))
+        errE.append(abs(acc["E"][r] - ref["E"]) / abs(ref["E"]))
+    return {
+        "fp32_error_vs_fp64_oracle": {"force_rel_rms_max": max(errF), "charge_rel_rms_max": max(errQ),
+                                      "energy_rel_max": max(errE), "replicas_checked": nsample,
+                                      "target_force_rel_rms": 1e-5},
+        "cpu_baseline": {"value": pairs / wall, "unit": "pairs/s", "cores": max(1, round(cpu / wall)),
+                         "kind": "oracle",
+                         "sample": f"FP64 numpy oracle SRBE step (sample, b*, CP solve, forces, energy) on "
+                                   f"{nsample} of the {R} replicas, one step each (about 15 s); A built once "
+                                   f"beforehand ({oracle_setup_s:.1f} s, not timed); cpu_time/wall = "
+                                   f"{cpu / wall:.2f}; host threads available: {os.cpu_count()}"},
+        "oracle_setup_s": oracle_setup_s,
+    }
+
+
+if __name__ == "__main__":
+    main()

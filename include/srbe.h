@@ -1,0 +1,177 @@
+/*
+ * srbe.h -- C ABI of the SRBE constant-potential step on AMD MI355X (gfx950).
+ *
+ * The library implements the per-timestep electrostatics of the symmetry-
+ * preserving random batch Ewald (SRBE) method for electrode/electrolyte slabs
+ * (Gao, Zhou, Zhang, Xu, arXiv 2509.24742):
+ *
+ *   - structure factors S(k) = sum_j q_j exp(i k.r_j) (Eq. (15)) over the
+ *     deterministic modes I = {(0,0,2 pi m/Lz): 1 <= |m| <= M} and a random batch
+ *     of P modes drawn from exp(-k^2/(4 alpha^2))/G on the remaining lattice
+ *     (Eqs. (26)-(29));
+ *   - the electrode vector b* (Eq. (24) plus the exact slab and real-space terms of
+ *     Eq. (19)) and the constant-potential charges Q = J A^-1 (dpsi d + b*) with
+ *     the average potential psibar (Eqs. (9)-(11));
+ *   - the ion forces F* (Eq. (25) plus slab and real-space terms) and the energy.
+ *
+ * Conventions shared by every call
+ *   Units are the caller's; every Coulomb term carries params.coulomb_k
+ *   (1.43996454784 eV nm / e^2 for nm, e, V, eV).  Positions are structure-of-
+ *   arrays: x[0..n), y[0..n), z[0..n) contiguous in one buffer of 3n doubles.
+ *   The box is [0,Lx) x [0,Ly) x [0,H], periodic in x and y; z is padded to
+ *   Lz = lambda H with the slab correction of Eq. (17).
+ *   "host" pointers are read during the call and not retained; "device" pointers
+ *   are HIP device memory owned by the caller, read or written asynchronously on
+ *   the stream passed to the call, and not retained after the work completes.
+ *   A handle is not thread-safe; distinct handles are independent.  A handle
+ *   lives on the HIP device that was current when it was created.
+ *
+ * Errors
+ *   Every int-returning call returns SRBE_OK (0) or a negative code below.
+ *   Argument checks run synchronously before anything is enqueued.  Checks that
+ *   need device data (neutrality, z range, non-finite values) are made by the
+ *   kernels; they set a device status word that srbe_sync_status() reports.
+ */
+#ifndef SRBE_H
+#define SRBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRBE_OK 0
+#define SRBE_EINVAL (-1)     /* invalid argument                                  */
+#define SRBE_ENONNEUTRAL (-2) /* ions of a replica are not neutral               */
+#define SRBE_ERANGE (-3)     /* a particle lies outside [0,H] in z, or non-finite  */
+#define SRBE_ENOTSPD (-4)    /* electrode matrix A is not positive definite        */
+#define SRBE_ENOMEM (-5)     /* device allocation failed                           */
+#define SRBE_EHIP (-6)       /* HIP runtime or ROCm library error                  */
+#define SRBE_ENUMERIC (-7)   /* non-finite value produced on the device            */
+
+#define SRBE_FP64 0 /* every pass in FP64                                              */
+#define SRBE_FP32 1 /* structure factors, potentials and forces in FP32 with exact
+                       integer phases and FP64 carries; CP solve and energy in FP64   */
+
+#define SRBE_FLAG_NO_CP 1 /* skip the electrode matrix: only fixed-charge steps      */
+
+typedef struct srbe_params {
+  double Lx, Ly, H;   /* box (length); electrodes and ions have 0 <= z <= H           */
+  double lambda;      /* zero-padding ratio, Lz = lambda * H; lambda >= 1 and
+                         (lambda - 1) * H > rc                                        */
+  double alpha;       /* Ewald splitting parameter (1/length), Eq. (12)               */
+  double eta;         /* width of the electrode Gaussians (a length), Eq. (1)         */
+  double rc;          /* real-space cutoff, 0 < rc <= min(Lx, Ly) / 2                 */
+  double coulomb_k;   /* Coulomb constant multiplying every electrostatic term        */
+  double kspace_tol;  /* the reciprocal sum of A keeps every k with
+                         exp(-k^2/(4 alpha^2)) >= kspace_tol (0 < tol < 1)            */
+  int32_t M;          /* deterministic modes m_z = 1..M (M >= 0)                      */
+  int32_t P;          /* random batch size, 0 <= P <= 2048                            */
+  int32_t flags;      /* SRBE_FLAG_*                                                  */
+  int32_t reserved;   /* must be 0                                                    */
+} srbe_params;
+
+typedef struct srbe_system srbe_system;
+
+/*
+ * srbe_create -- set up one electrode geometry (Sec. 2, Eqs. (18), (9)-(11)).
+ *
+ * ele_xyz  host, 3*n_ele doubles (SoA), electrode positions R_j.
+ * ele_side host, n_ele int8: -1 for the negative, +1 for the positive electrode
+ *          (d_j = side_j / 2 in Eq. (7)).
+ * Builds A (Eq. (18); its slab entry is taken as (4 pi / V) Z_i Z_j, the Hessian of
+ * the slab term of Eq. (17)), factorises it, and keeps S = J A^-1 and
+ * -e^T A^-1 / (e^T A^-1 e) on the device.  Also evaluates G of Eq. (27).
+ * With SRBE_FLAG_NO_CP set, A is not built and n_ele may be large; steps must
+ * then pass Q_in.  On success *out receives the handle; on failure *out is NULL.
+ * Errors: SRBE_EINVAL, SRBE_ENOTSPD (A not positive definite, e.g. two electrodes
+ * at one position), SRBE_ENOMEM, SRBE_EHIP.
+ */
+int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
+                const int8_t* ele_side, srbe_system** out);
+
+/* srbe_destroy -- free the handle and its device memory (synchronises the device). */
+void srbe_destroy(srbe_system* h);
+
+/* srbe_last_error -- message of the last failure on this handle ("" if none). */
+const char* srbe_last_error(const srbe_system* h);
+
+/* srbe_error_string -- static description of an error code. */
+const char* srbe_error_string(int code);
+
+/*
+ * srbe_step -- one SRBE step for n_rep replicas sharing the handle's electrodes
+ * (Algorithm 1: sample P modes, compute b* by Eq. (24), update Q by Eq. (10),
+ * compute the forces of Eq. (25) and the real-space forces; no integration).
+ *
+ * precision   SRBE_FP64 or SRBE_FP32.
+ * n_rep       number of replicas, 1 <= n_rep <= 65535.
+ * ion_offsets host, n_rep+1 int64, CSR offsets: replica r owns ions
+ *             [ion_offsets[r], ion_offsets[r+1]); ion_offsets[0] == 0.
+ * ion_xyz     device, 3*N doubles SoA (N = ion_offsets[n_rep]).
+ * ion_q       device, N doubles.  Each replica's ions must be neutral.
+ * dpsi        device, n_rep doubles: potential difference Delta psi per replica.
+ * seed        device, n_rep uint64: sampler seed per replica.
+ * step        step index; with the seed it fixes the sample (counter-based RNG).
+ * kset_in     device, n_rep*P*3 int32 (m_x, m_y, m_z per sampled mode), or NULL to
+ *             sample on the device.  Each given mode must lie in L_k \ I.
+ * Q_in        device, n_rep*n_ele doubles, or NULL.  Non-NULL: fixed electrode
+ *             charges (the CP solve is skipped; Q_out receives a copy).
+ * Q_out       device, n_rep*n_ele doubles: electrode charges.
+ * F_out       device, 3*N doubles SoA: total force on every ion.
+ * b_out       device, n_rep*n_ele doubles (b* per replica) or NULL.
+ * psibar_out  device, n_rep doubles or NULL (NaN in fixed-charge steps).
+ * energy_out  device, n_rep doubles or NULL: E* = 1/2 Q^T A Q - b*^T Q + c*, with
+ *             c* the ion-ion energy using the same estimator (requires the CP
+ *             solve; NaN in fixed-charge steps).
+ * kset_out    device, n_rep*P*3 int32 or NULL: the modes used.
+ * stream      hipStream_t on which all work is enqueued (NULL = default stream).
+ * Errors: SRBE_EINVAL (synchronous); device-data errors via srbe_sync_status.
+ */
+int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+              const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
+              uint64_t step, const int32_t* kset_in, const double* Q_in, double* Q_out, double* F_out,
+              double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, void* stream);
+
+/*
+ * srbe_sample -- only the sampler of a step (Sec. 3, Eqs. (26)-(29)): writes the
+ * n_rep*P*3 int32 modes the step with the same (seed, step) would use.
+ * seed device n_rep uint64; kset_out device.  Returns SRBE_EINVAL on bad arguments.
+ */
+int srbe_sample(srbe_system* h, int32_t n_rep, const uint64_t* seed, uint64_t step, int32_t* kset_out,
+                int32_t* n_accepted_out, void* stream);
+
+/*
+ * srbe_sync_status -- wait for the handle's work and report device-side faults:
+ * SRBE_ENONNEUTRAL, SRBE_ERANGE, SRBE_ENUMERIC, SRBE_EHIP, or SRBE_OK.  Clears the
+ * status word.
+ */
+int srbe_sync_status(srbe_system* h);
+
+/*
+ * Per-phase timing (tracing).  When enabled, every later srbe_step records a HIP
+ * event before and after each of its SRBE_N_PHASES phases on the step's stream;
+ * srbe_profile_read waits for them and returns, per phase, the summed duration in
+ * milliseconds and the number of launches since the last read (then resets).
+ * Phases, in order: replica_scalars, sample, prep, sf_ions, finalize_ions,
+ * ele_potential, cp_gemm, post_charges, sf_ele, finalize_ele, ion_force, energy.
+ * srbe_phase_name(i) returns the name of phase i.
+ */
+#define SRBE_N_PHASES 12
+int srbe_profile_enable(srbe_system* h, int32_t enable);
+int srbe_profile_read(srbe_system* h, double* ms_out /*host [SRBE_N_PHASES]*/,
+                      int64_t* launches_out /*host [SRBE_N_PHASES]*/);
+const char* srbe_phase_name(int32_t phase);
+
+/* srbe_normaliser -- G of Eq. (27) for the handle's parameters (host double). */
+double srbe_normaliser(const srbe_system* h);
+
+/* srbe_n_ele -- number of electrode atoms of the handle. */
+int32_t srbe_n_ele(const srbe_system* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRBE_H */

@@ -19,6 +19,8 @@ Readings:
   sequence (at most 64 tries; if all 64 fail, the mode (1, 0, 0)); then P
   Metropolis iterations, each contributing its current state (a rejection repeats
   the state).  Duplicates count with multiplicity.
+* A proposal y in L_k \\ I is accepted when d = log r(y) - log r(x) >= 0 or
+  log U < d, the logarithm of U < min{1, r(y)/r(x)} with r the ratio of Eq. (29).
 * Rounding is round-half-up, m = floor(u + 1/2).
 
 Random numbers: Philox4x64-10 (``oracle.philox``) with key (seed, stream) and
@@ -119,10 +121,11 @@ def draw_kset(p, seed, stream, step, P=None):
     lx = float(log_ratio(p, x)[0])
     out = np.zeros((P, 3), dtype=np.int64)
     nacc = 0
+    lU = np.log(U)
     for l in range(P):
         if vy[l]:
             d = ly[l] - lx
-            if d >= 0.0 or U[l] < np.exp(d):
+            if d >= 0.0 or lU[l] < d:
                 x = y[l]
                 lx = float(ly[l])
                 nacc += 1

@@ -1,1 +1,59 @@
-"""SRBE constant-potential step on MI355X (gfx950)."""
+"""SRBE constant-potential step on AMD MI355X (gfx950).
+
+The compute path is libsrbe.so (hand-written HIP kernels behind the C ABI in
+include/srbe.h).  ``binding`` exposes that ABI function by function; ``System``
+below is a convenience wrapper that allocates the outputs with torch.  Importing
+this package does not load the library; the first call does, and raises if the
+library has not been built.
+"""
+
+import numpy as np
+
+from . import binding
+from .binding import (SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
+                      srbe_error_string, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
+                      srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status)
+
+
+class System:
+    """One electrode geometry (a handle) plus output allocation for steps over replicas."""
+
+    def __init__(self, params, ele_pos, ele_side, flags=0):
+        self.params = dict(params)
+        self.h = srbe_create(self.params, ele_pos, ele_side, flags=flags)
+        self.n_ele = srbe_n_ele(self.h)
+        self.G = srbe_normaliser(self.h)
+
+    def close(self):
+        if self.h is not None:
+            srbe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, precision=SRBE_FP64, kset_in=None, Q_in=None,
+             want_b=True, want_kset=True, out=None, stream=None):
+        """Run one step; returns a dict of CUDA tensors (Q, F, b, psibar, E, kset)."""
+        import torch
+        off = np.asarray(ion_offsets, dtype=np.int64)
+        R = len(off) - 1
+        N = int(off[-1])
+        P = int(self.params["P"])
+        dev = ion_xyz.device if N else dpsi.device
+        if out is None:
+            out = dict(
+                Q=torch.empty(R * self.n_ele, dtype=torch.float64, device=dev),
+                F=torch.empty(3 * N, dtype=torch.float64, device=dev),
+                b=torch.empty(R * self.n_ele, dtype=torch.float64, device=dev) if want_b else None,
+                psibar=torch.empty(R, dtype=torch.float64, device=dev),
+                E=torch.empty(R, dtype=torch.float64, device=dev),
+                kset=torch.empty(R * P * 3, dtype=torch.int32, device=dev) if (want_kset and P) else None,
+            )
+        srbe_step(self.h, precision, off, ion_xyz, ion_q, dpsi, seed, step, out["Q"], out["F"], kset_in=kset_in,
+                  Q_in=Q_in, b_out=out["b"], psibar_out=out["psibar"], energy_out=out["E"], kset_out=out["kset"],
+                  stream=stream)
+        return out

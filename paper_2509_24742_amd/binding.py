@@ -1,0 +1,227 @@
+"""ctypes binding of libsrbe.so (include/srbe.h), argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device buffers are
+torch CUDA tensors (HIP device memory); host buffers are numpy arrays.  There is
+no fallback: if libsrbe.so is missing or a call fails, an exception is raised.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+SRBE_OK = 0
+SRBE_EINVAL = -1
+SRBE_ENONNEUTRAL = -2
+SRBE_ERANGE = -3
+SRBE_ENOTSPD = -4
+SRBE_ENOMEM = -5
+SRBE_EHIP = -6
+SRBE_ENUMERIC = -7
+SRBE_FP64 = 0
+SRBE_FP32 = 1
+SRBE_FLAG_NO_CP = 1
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsrbe.so")
+
+
+class srbe_params(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("H", ctypes.c_double),
+        ("lam", ctypes.c_double), ("alpha", ctypes.c_double), ("eta", ctypes.c_double),
+        ("rc", ctypes.c_double), ("coulomb_k", ctypes.c_double), ("kspace_tol", ctypes.c_double),
+        ("M", ctypes.c_int32), ("P", ctypes.c_int32), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class SrbeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"SRBE error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_batch_size = {}  # handle value -> P, so that mode buffers can be size-checked
+
+
+def lib():
+    """Load libsrbe.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2509_24742_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.srbe_create.argtypes = [ctypes.POINTER(srbe_params), ctypes.c_int32, _vp, _vp, ctypes.POINTER(_vp)]
+    L.srbe_create.restype = ctypes.c_int
+    L.srbe_destroy.argtypes = [_vp]
+    L.srbe_destroy.restype = None
+    L.srbe_last_error.argtypes = [_vp]
+    L.srbe_last_error.restype = ctypes.c_char_p
+    L.srbe_error_string.argtypes = [ctypes.c_int]
+    L.srbe_error_string.restype = ctypes.c_char_p
+    L.srbe_step.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64,
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.srbe_step.restype = ctypes.c_int
+    L.srbe_sample.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_uint64, _vp, _vp, _vp]
+    L.srbe_sample.restype = ctypes.c_int
+    L.srbe_sync_status.argtypes = [_vp]
+    L.srbe_sync_status.restype = ctypes.c_int
+    L.srbe_normaliser.argtypes = [_vp]
+    L.srbe_normaliser.restype = ctypes.c_double
+    L.srbe_n_ele.argtypes = [_vp]
+    L.srbe_n_ele.restype = ctypes.c_int32
+    L.srbe_profile_enable.argtypes = [_vp, ctypes.c_int32]
+    L.srbe_profile_enable.restype = ctypes.c_int
+    L.srbe_profile_read.argtypes = [_vp, _vp, _vp]
+    L.srbe_profile_read.restype = ctypes.c_int
+    L.srbe_phase_name.argtypes = [ctypes.c_int32]
+    L.srbe_phase_name.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string", "srbe_step", "srbe_sample",
+            "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
+            "srbe_phase_name"]
+SRBE_N_PHASES = 12
+
+
+def _check(h, code):
+    if code != SRBE_OK:
+        msg = lib().srbe_last_error(h).decode() if h else ""
+        if not msg:
+            msg = lib().srbe_error_string(code).decode()
+        raise SrbeError(code, msg)
+
+
+def _dev(t, dtype, n, name, allow_none=False):
+    """Device pointer of a contiguous CUDA tensor with n elements of dtype."""
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def make_params(d, flags=0):
+    """srbe_params from a dict with keys Lx, Ly, H, lam, alpha, eta, rc, coulomb_k, M, P (+ kspace_tol)."""
+    return srbe_params(Lx=d["Lx"], Ly=d["Ly"], H=d["H"], lam=d["lam"], alpha=d["alpha"], eta=d["eta"], rc=d["rc"],
+                       coulomb_k=d["coulomb_k"], kspace_tol=d.get("kspace_tol", 1e-16), M=int(d["M"]),
+                       P=int(d["P"]), flags=int(flags), reserved=0)
+
+
+def srbe_create(params, ele_xyz, ele_side, flags=0):
+    """Create a handle.  params: dict or srbe_params; ele_xyz: (n, 3) host array; ele_side: n of -1/+1."""
+    p = params if isinstance(params, srbe_params) else make_params(params, flags)
+    xyz = np.ascontiguousarray(np.asarray(ele_xyz, dtype=np.float64).reshape(-1, 3).T)  # SoA
+    side = np.ascontiguousarray(np.asarray(ele_side, dtype=np.int8))
+    n = side.shape[0]
+    if xyz.shape[1] != n:
+        raise ValueError("ele_xyz and ele_side lengths differ")
+    h = _vp()
+    code = lib().srbe_create(ctypes.byref(p), n, xyz.ctypes.data, side.ctypes.data, ctypes.byref(h))
+    if code != SRBE_OK:
+        raise SrbeError(code, lib().srbe_error_string(code).decode())
+    _batch_size[h.value] = int(p.P)
+    return h
+
+
+def srbe_destroy(h):
+    _batch_size.pop(h.value, None)
+    lib().srbe_destroy(h)
+
+
+def srbe_last_error(h):
+    return lib().srbe_last_error(h).decode()
+
+
+def srbe_error_string(code):
+    return lib().srbe_error_string(code).decode()
+
+
+def srbe_normaliser(h):
+    return lib().srbe_normaliser(h)
+
+
+def srbe_n_ele(h):
+    return lib().srbe_n_ele(h)
+
+
+def srbe_sync_status(h):
+    return lib().srbe_sync_status(h)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def srbe_step(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in=None, Q_in=None,
+              b_out=None, psibar_out=None, energy_out=None, kset_out=None, stream=None, check=True):
+    """One step.  ion_offsets: host int64 (R+1); device tensors as in include/srbe.h."""
+    import torch
+    off = np.ascontiguousarray(np.asarray(ion_offsets, dtype=np.int64))
+    R = off.shape[0] - 1
+    N = int(off[-1])
+    n = srbe_n_ele(h)
+    P = _batch_size[h.value]
+    args = [
+        h, int(precision), R, off.ctypes.data,
+        _dev(ion_xyz, torch.float64, 3 * N, "ion_xyz", allow_none=N == 0),
+        _dev(ion_q, torch.float64, N, "ion_q", allow_none=N == 0),
+        _dev(dpsi, torch.float64, R, "dpsi"),
+        _dev(seed, torch.uint64, R, "seed", allow_none=True),
+        ctypes.c_uint64(int(step)),
+        _dev(kset_in, torch.int32, R * P * 3, "kset_in", allow_none=True),
+        _dev(Q_in, torch.float64, R * n, "Q_in", allow_none=True),
+        _dev(Q_out, torch.float64, R * n, "Q_out"),
+        _dev(F_out, torch.float64, 3 * N, "F_out", allow_none=N == 0),
+        _dev(b_out, torch.float64, R * n, "b_out", allow_none=True),
+        _dev(psibar_out, torch.float64, R, "psibar_out", allow_none=True),
+        _dev(energy_out, torch.float64, R, "energy_out", allow_none=True),
+        _dev(kset_out, torch.int32, R * P * 3, "kset_out", allow_none=True),
+        _stream(stream),
+    ]
+    code = lib().srbe_step(*args)
+    if check:
+        _check(h, code)
+    return code
+
+
+def srbe_sample(h, seed, step, kset_out, n_accepted_out=None, stream=None):
+    import torch
+    R = seed.numel()
+    P = _batch_size[h.value]
+    code = lib().srbe_sample(h, R, _dev(seed, torch.uint64, R, "seed"), ctypes.c_uint64(int(step)),
+                             _dev(kset_out, torch.int32, R * P * 3, "kset_out", allow_none=P == 0),
+                             _dev(n_accepted_out, torch.int32, R, "n_accepted_out", allow_none=True), _stream(stream))
+    _check(h, code)
+    return code
+
+
+def srbe_profile_enable(h, enable=True):
+    _check(h, lib().srbe_profile_enable(h, 1 if enable else 0))
+
+
+def srbe_phase_name(i):
+    return lib().srbe_phase_name(int(i)).decode()
+
+
+def srbe_profile_read(h):
+    """{phase name: (total ms, launches)} since the last read."""
+    ms = np.zeros(SRBE_N_PHASES, dtype=np.float64)
+    n = np.zeros(SRBE_N_PHASES, dtype=np.int64)
+    _check(h, lib().srbe_profile_read(h, ms.ctypes.data, n.ctypes.data))
+    return {srbe_phase_name(i): (float(ms[i]), int(n[i])) for i in range(SRBE_N_PHASES)}

@@ -1,0 +1,77 @@
+// Device-side helpers shared by the SRBE kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srbe {
+
+// Device status bits (OR-ed into a per-handle word, read by srbe_sync_status).
+enum : unsigned {
+  ST_NONNEUTRAL = 1u,  // a replica's ion charges do not sum to zero
+  ST_RANGE = 2u,       // z outside [0, H] or a non-finite coordinate/charge
+  ST_NUMERIC = 4u,     // non-finite value produced
+  ST_BADKSET = 8u,     // a caller-given mode lies in I or is the origin
+};
+
+// Per-handle constants, passed by value to every kernel.
+struct Geom {
+  double Lx, Ly, H, Lz, V;
+  double invLx, invLy, invLz;
+  double alpha, eta, rc, ke;
+  double G;        // normaliser of Eq. (27)
+  double sig[3];   // proposal standard deviation per axis (in units of m)
+  int M, P, K;     // K = M + P modes per replica
+  int n_ele;
+};
+
+// ------------------------------------------------------------------ Philox4x64-10
+// Salmon, Moraes, Dror, Shaw, SC'11: per round two 64x64->128 products, the
+// output (hi1^c1^k0, lo1, hi0^c3^k1, lo0), and a Weyl key bump between rounds.
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t lo0 = M0 * c.v[0], hi0 = __umul64hi(M0, c.v[0]);
+    const uint64_t lo1 = M1 * c.v[2], hi1 = __umul64hi(M1, c.v[2]);
+    U64x4 n;
+    n.v[0] = hi1 ^ c.v[1] ^ k0;
+    n.v[1] = lo1;
+    n.v[2] = hi0 ^ c.v[3] ^ k1;
+    n.v[3] = lo0;
+    c = n;
+  }
+  return c;
+}
+
+// (0,1) uniform with 52 random bits: ((w >> 12) + 1/2) 2^-52, exact in FP64.
+__device__ __forceinline__ double u01_open(uint64_t w) {
+  return (static_cast<double>(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
+// ------------------------------------------------------------------ fixed point
+// Fractional coordinate s in [0,1) -> 32-bit fixed point (s * 2^32 mod 2^32).
+__device__ __forceinline__ uint32_t to_fixed(double s) {
+  double t = s * 4294967296.0;
+  uint64_t u = static_cast<uint64_t>(t);
+  return static_cast<uint32_t>(u);
+}
+
+// Wrap x into [0, L) given 1/L.
+__device__ __forceinline__ double wrap_frac(double x, double invL) {
+  double s = x * invL;
+  s -= floor(s);
+  if (s >= 1.0) s -= 1.0;
+  return s;
+}
+
+}  // namespace srbe

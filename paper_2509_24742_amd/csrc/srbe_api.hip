@@ -1,0 +1,592 @@
+// C ABI of the SRBE step (include/srbe.h): argument checks, the one-time electrode
+// set-up (A of Eq. (18), its Cholesky factorisation and S = J A^-1 of Eqs. (10)-(11)),
+// workspace management and the per-step launch sequence.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/srbe.h"
+#include "kernels.h"
+
+using namespace srbe;
+
+struct srbe_system {
+  srbe_params p;
+  Geom g;
+  int device = 0;
+  int n_ele = 0;
+  bool has_cp = false;
+  double* ele_xyz = nullptr;
+  double* ele_frac = nullptr;
+  uint4* ele_fx = nullptr;
+  double* ele_d = nullptr;
+  double* Sext = nullptr;
+  unsigned* status = nullptr;
+  rocblas_handle blas = nullptr;
+  // workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<int64_t> off_cache;
+  // per-phase timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;   // pairs (start, stop) recorded but not yet read
+  std::vector<int> ev_phase;         // phase of each recorded pair
+  size_t ev_used = 0;                // pairs in use
+  double prof_ms[SRBE_N_PHASES] = {0};
+  int64_t prof_n[SRBE_N_PHASES] = {0};
+  int64_t* off_dev = nullptr;
+  size_t off_cap = 0;
+  std::string err;
+};
+
+namespace {
+
+int set_err(srbe_system* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIP_OK(h, call)                                                                              \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess)                                                                            \
+      return set_err(h, e_ == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP,                         \
+                     std::string(#call) + ": " + hipGetErrorString(e_));                             \
+  } while (0)
+
+#define BLAS_OK(h, call)                                                                             \
+  do {                                                                                               \
+    rocblas_status s_ = (call);                                                                      \
+    if (s_ != rocblas_status_success)                                                                \
+      return set_err(h, SRBE_EHIP, std::string(#call) + ": " + rocblas_status_to_string(s_));        \
+  } while (0)
+
+double theta(double alpha, double L) {
+  double s = 1.0;
+  for (int m = 1;; ++m) {
+    const double t = std::exp(-(M_PI * m / (alpha * L)) * (M_PI * m / (alpha * L)));
+    if (t < 1e-300) break;
+    s += 2.0 * t;
+  }
+  return s;
+}
+
+// G of Eq. (27): the Gaussian over the lattice factorises per axis; subtract the
+// origin and the 2M modes of I.
+double normaliser(const srbe_params& p) {
+  const double Lz = p.lambda * p.H;
+  double det = 0.0;
+  for (int m = 1; m <= p.M; ++m) {
+    const double kz = 2.0 * M_PI * m / Lz;
+    det += std::exp(-kz * kz / (4.0 * p.alpha * p.alpha));
+  }
+  return theta(p.alpha, p.Lx) * theta(p.alpha, p.Ly) * theta(p.alpha, Lz) - 1.0 - 2.0 * det;
+}
+
+std::string check_params(const srbe_params* p) {
+  if (!p) return "params is NULL";
+  auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+  if (!pos(p->Lx) || !pos(p->Ly) || !pos(p->H)) return "box lengths must be finite and positive";
+  if (!(std::isfinite(p->lambda) && p->lambda >= 1.0)) return "lambda must be >= 1";
+  if (!pos(p->alpha) || !pos(p->eta) || !pos(p->rc) || !pos(p->coulomb_k)) return "alpha, eta, rc, coulomb_k must be > 0";
+  if (p->rc > 0.5 * std::fmin(p->Lx, p->Ly)) return "rc must not exceed min(Lx, Ly)/2";
+  if (!((p->lambda - 1.0) * p->H > p->rc)) return "(lambda - 1) * H must exceed rc";
+  if (!(p->kspace_tol > 0.0 && p->kspace_tol < 1.0)) return "kspace_tol must lie in (0, 1)";
+  if (p->M < 0 || p->P < 0) return "M and P must be >= 0";
+  if (p->P > 2048) return "P must be <= 2048";
+  if (p->flags & ~SRBE_FLAG_NO_CP) return "unknown flag";
+  if (p->reserved != 0) return "reserved must be 0";
+  return "";
+}
+
+Geom make_geom(const srbe_params& p, int n_ele) {
+  Geom g{};
+  g.Lx = p.Lx;
+  g.Ly = p.Ly;
+  g.H = p.H;
+  g.Lz = p.lambda * p.H;
+  g.V = p.Lx * p.Ly * g.Lz;
+  g.invLx = 1.0 / p.Lx;
+  g.invLy = 1.0 / p.Ly;
+  g.invLz = 1.0 / g.Lz;
+  g.alpha = p.alpha;
+  g.eta = p.eta;
+  g.rc = p.rc;
+  g.ke = p.coulomb_k;
+  g.G = normaliser(p);
+  // proposal standard deviation alpha L_d / (sqrt(2) pi), in the order (alpha L) / (sqrt(2) pi)
+  g.sig[0] = p.alpha * p.Lx / (std::sqrt(2.0) * M_PI);
+  g.sig[1] = p.alpha * p.Ly / (std::sqrt(2.0) * M_PI);
+  g.sig[2] = p.alpha * g.Lz / (std::sqrt(2.0) * M_PI);
+  g.M = p.M;
+  g.P = p.P;
+  g.K = p.M + p.P;
+  g.n_ele = n_ele;
+  return g;
+}
+
+// Build A (Eq. (18)), factorise, and form S_ext on the device.
+int build_electrode_solve(srbe_system* h, hipStream_t s) {
+  const srbe_params& p = h->p;
+  const Geom& g = h->g;
+  const int n = h->n_ele;
+  // half-space modes (m and -m give the same cos), weight doubled
+  const double k2max = 4.0 * p.alpha * p.alpha * std::log(1.0 / p.kspace_tol);
+  const double Ls[3] = {p.Lx, p.Ly, g.Lz};
+  int mmax[3];
+  for (int d = 0; d < 3; ++d) mmax[d] = (int)std::floor(std::sqrt(k2max) * Ls[d] / (2.0 * M_PI));
+  std::vector<int> modes;
+  std::vector<double> sqrtw;
+  for (int mx = 0; mx <= mmax[0]; ++mx)
+    for (int my = -mmax[1]; my <= mmax[1]; ++my)
+      for (int mz = -mmax[2]; mz <= mmax[2]; ++mz) {
+        const bool half = mx > 0 || (mx == 0 && my > 0) || (mx == 0 && my == 0 && mz > 0);
+        if (!half) continue;
+        const double kx = 2.0 * M_PI * mx / p.Lx, ky = 2.0 * M_PI * my / p.Ly, kz = 2.0 * M_PI * mz / g.Lz;
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > k2max) continue;
+        const double w = 4.0 * M_PI * std::exp(-k2 / (4.0 * p.alpha * p.alpha)) / (g.V * k2);
+        modes.push_back(mx);
+        modes.push_back(my);
+        modes.push_back(mz);
+        sqrtw.push_back(std::sqrt(2.0 * p.coulomb_k * w));
+      }
+  const int nk_total = (int)sqrtw.size();
+  const int chunk = std::max(256, std::min(nk_total, (int)(16 * 1024 * 1024 / std::max(n, 1))));
+  double *A = nullptr, *E = nullptr, *dsw = nullptr, *gv = nullptr;
+  int *dm = nullptr, *dinfo = nullptr;
+  auto cleanup = [&]() {
+    if (A) (void)hipFree(A);
+    if (E) (void)hipFree(E);
+    if (dsw) (void)hipFree(dsw);
+    if (gv) (void)hipFree(gv);
+    if (dm) (void)hipFree(dm);
+    if (dinfo) (void)hipFree(dinfo);
+  };
+  int rc = SRBE_OK;
+  do {
+    hipError_t e;
+#define TRY(call)                                                                                   \
+  if ((e = (call)) != hipSuccess) {                                                                 \
+    rc = set_err(h, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, std::string(#call) + ": " + \
+                                                                            hipGetErrorString(e));  \
+    break;                                                                                          \
+  }
+    TRY(hipMalloc(&A, (size_t)n * n * sizeof(double)));
+    TRY(hipMemsetAsync(A, 0, (size_t)n * n * sizeof(double), s));
+    if (nk_total > 0) {
+      TRY(hipMalloc(&E, (size_t)n * 2 * chunk * sizeof(double)));
+      TRY(hipMalloc(&dsw, (size_t)nk_total * sizeof(double)));
+      TRY(hipMalloc(&dm, (size_t)nk_total * 3 * sizeof(int)));
+      TRY(hipMemcpy(dsw, sqrtw.data(), sqrtw.size() * sizeof(double), hipMemcpyHostToDevice));
+      TRY(hipMemcpy(dm, modes.data(), modes.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    TRY(hipMalloc(&gv, (size_t)n * sizeof(double)));
+    TRY(hipMalloc(&dinfo, sizeof(int)));
+    rocblas_status bs = rocblas_set_stream(h->blas, s);
+    if (bs != rocblas_status_success) {
+      rc = set_err(h, SRBE_EHIP, "rocblas_set_stream failed");
+      break;
+    }
+    const double one = 1.0;
+    bool fail = false;
+    for (int c0 = 0; c0 < nk_total; c0 += chunk) {
+      const int nk = std::min(chunk, nk_total - c0);
+      launch_ele_phase_block(h->ele_xyz, n, dm + 3 * c0, dsw + c0, nk, n, E, g, s);
+      bs = rocblas_dsyrk(h->blas, rocblas_fill_lower, rocblas_operation_none, n, 2 * nk, &one, E, n, &one, A, n);
+      if (bs != rocblas_status_success) {
+        rc = set_err(h, SRBE_EHIP, std::string("rocblas_dsyrk: ") + rocblas_status_to_string(bs));
+        fail = true;
+        break;
+      }
+    }
+    if (fail) break;
+    launch_ele_realspace_matrix(g, h->ele_xyz, n, A, s);
+    bs = rocsolver_dpotrf(h->blas, rocblas_fill_lower, n, A, n, dinfo);
+    if (bs != rocblas_status_success) {
+      rc = set_err(h, SRBE_EHIP, std::string("rocsolver_dpotrf: ") + rocblas_status_to_string(bs));
+      break;
+    }
+    int info = 0;
+    TRY(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    if (info != 0) {
+      rc = set_err(h, SRBE_ENOTSPD, "electrode matrix A is not positive definite (pivot " + std::to_string(info) + ")");
+      break;
+    }
+    bs = rocsolver_dpotri(h->blas, rocblas_fill_lower, n, A, n, dinfo);
+    if (bs != rocblas_status_success) {
+      rc = set_err(h, SRBE_EHIP, std::string("rocsolver_dpotri: ") + rocblas_status_to_string(bs));
+      break;
+    }
+    launch_symmetrize_lower(A, n, n, s);
+    launch_rowsum(A, n, n, gv, s);
+    std::vector<double> hg(n);
+    TRY(hipMemcpyAsync(hg.data(), gv, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    double eg = 0.0;
+    for (int i = 0; i < n; ++i) eg += hg[i];
+    if (!(std::isfinite(eg) && eg > 0.0)) {
+      rc = set_err(h, SRBE_ENOTSPD, "e^T A^-1 e is not positive");
+      break;
+    }
+    TRY(hipMalloc(&h->Sext, (size_t)(n + 1) * n * sizeof(double)));
+    launch_build_sext(A, n, gv, eg, h->Sext, s);
+    launch_check_finite(h->Sext, (size_t)(n + 1) * n, h->status, s);
+    TRY(hipStreamSynchronize(s));
+    unsigned st = 0;
+    TRY(hipMemcpy(&st, h->status, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (st) {
+      rc = set_err(h, SRBE_ENUMERIC, "non-finite entries in J A^-1");
+      break;
+    }
+#undef TRY
+  } while (0);
+  cleanup();
+  return rc;
+}
+
+inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+const char* kPhaseNames[SRBE_N_PHASES] = {"replica_scalars", "sample",       "prep",    "sf_ions",
+                                          "finalize_ions",   "ele_potential", "cp_gemm", "post_charges",
+                                          "sf_ele",          "finalize_ele", "ion_force", "energy"};
+
+// Record an event pair around a phase when profiling is enabled.
+struct PhaseTimer {
+  srbe_system* h;
+  hipStream_t s;
+  int phase;
+  size_t slot = 0;
+  bool on;
+  PhaseTimer(srbe_system* h_, hipStream_t s_, int phase_) : h(h_), s(s_), phase(phase_), on(h_->prof) {
+    if (!on) return;
+    if (h->ev_used * 2 + 2 > h->ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        h->ev_pool.push_back(e);
+      }
+    }
+    slot = h->ev_used++;
+    if (h->ev_phase.size() < h->ev_used) h->ev_phase.resize(h->ev_used);
+    h->ev_phase[slot] = phase;
+    (void)hipEventRecord(h->ev_pool[2 * slot], s);
+  }
+  ~PhaseTimer() {
+    if (on) (void)hipEventRecord(h->ev_pool[2 * slot + 1], s);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* srbe_error_string(int code) {
+  switch (code) {
+    case SRBE_OK: return "ok";
+    case SRBE_EINVAL: return "invalid argument";
+    case SRBE_ENONNEUTRAL: return "ions of a replica are not neutral";
+    case SRBE_ERANGE: return "particle outside [0, H] in z or non-finite input";
+    case SRBE_ENOTSPD: return "electrode matrix is not positive definite";
+    case SRBE_ENOMEM: return "device out of memory";
+    case SRBE_EHIP: return "HIP runtime or ROCm library error";
+    case SRBE_ENUMERIC: return "non-finite value produced on the device";
+    default: return "unknown error";
+  }
+}
+
+const char* srbe_last_error(const srbe_system* h) { return h ? h->err.c_str() : "null handle"; }
+
+double srbe_normaliser(const srbe_system* h) { return h ? h->g.G : NAN; }
+
+int32_t srbe_n_ele(const srbe_system* h) { return h ? h->n_ele : -1; }
+
+void srbe_destroy(srbe_system* h) {
+  if (!h) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  if (h->blas) rocblas_destroy_handle(h->blas);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  void* bufs[] = {h->ele_xyz, h->ele_frac, h->ele_fx, h->ele_d, h->Sext, h->status, h->ws, h->off_dev};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  (void)hipSetDevice(prev);
+  delete h;
+}
+
+int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz, const int8_t* ele_side,
+                srbe_system** out) {
+  if (!out) return SRBE_EINVAL;
+  *out = nullptr;
+  const std::string msg = check_params(params);
+  if (!msg.empty()) return SRBE_EINVAL;
+  if (n_ele <= 0 || !ele_xyz || !ele_side) return SRBE_EINVAL;
+  const bool cp = !(params->flags & SRBE_FLAG_NO_CP);
+  if (cp && n_ele > 65535) return SRBE_EINVAL;
+  std::vector<double> d(n_ele);
+  for (int j = 0; j < n_ele; ++j) {
+    if (ele_side[j] != 1 && ele_side[j] != -1) return SRBE_EINVAL;
+    d[j] = 0.5 * ele_side[j];
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(ele_xyz[(size_t)a * n_ele + j])) return SRBE_ERANGE;
+    const double z = ele_xyz[2 * (size_t)n_ele + j];
+    if (z < 0.0 || z > params->H) return SRBE_ERANGE;
+  }
+  srbe_system* h = new srbe_system();
+  h->p = *params;
+  h->n_ele = n_ele;
+  h->has_cp = cp;
+  h->g = make_geom(*params, n_ele);
+  (void)hipGetDevice(&h->device);
+  hipStream_t s = nullptr;
+  int rc = SRBE_OK;
+  auto fail = [&](int code) {
+    srbe_destroy(h);
+    return code;
+  };
+  {
+    hipError_t e;
+    if ((e = hipMalloc(&h->ele_xyz, (size_t)3 * n_ele * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->ele_frac, (size_t)3 * n_ele * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->ele_fx, (size_t)n_ele * sizeof(uint4))) != hipSuccess ||
+        (e = hipMalloc(&h->ele_d, (size_t)n_ele * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&h->status, sizeof(unsigned))) != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP);
+    if (hipMemcpy(h->ele_xyz, ele_xyz, (size_t)3 * n_ele * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ele_d, d.data(), (size_t)n_ele * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess)
+      return fail(SRBE_EHIP);
+  }
+  launch_ele_fixed(h->g, h->ele_xyz, n_ele, h->ele_frac, h->ele_fx, s);
+  if (rocblas_create_handle(&h->blas) != rocblas_status_success) return fail(SRBE_EHIP);
+  if (cp) {
+    rc = build_electrode_solve(h, s);
+    if (rc != SRBE_OK) {
+      fprintf(stderr, "srbe_create: %s\n", h->err.c_str());
+      return fail(rc);
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(SRBE_EHIP);
+  *out = h;
+  return SRBE_OK;
+}
+
+int srbe_sync_status(srbe_system* h) {
+  if (!h) return SRBE_EINVAL;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(h->device);
+  hipError_t e = hipDeviceSynchronize();
+  unsigned st = 0;
+  if (e == hipSuccess) e = hipMemcpy(&st, h->status, sizeof(unsigned), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(h->status, 0, sizeof(unsigned));
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return set_err(h, SRBE_EHIP, hipGetErrorString(e));
+  if (st & ST_NONNEUTRAL) return set_err(h, SRBE_ENONNEUTRAL, "ions of a replica are not neutral");
+  if (st & ST_RANGE) return set_err(h, SRBE_ERANGE, "particle outside [0, H] in z or non-finite input");
+  if (st & ST_BADKSET) return set_err(h, SRBE_EINVAL, "a given mode lies in I or is the origin");
+  if (st & ST_NUMERIC) return set_err(h, SRBE_ENUMERIC, "non-finite value produced on the device");
+  return SRBE_OK;
+}
+
+int srbe_sample(srbe_system* h, int32_t n_rep, const uint64_t* seed, uint64_t step, int32_t* kset_out,
+                int32_t* n_accepted_out, void* stream) {
+  if (!h || n_rep <= 0 || n_rep > 65535 || !seed || (!kset_out && h->p.P > 0))
+    return set_err(h, SRBE_EINVAL, "bad sample arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = align_up((size_t)n_rep * h->g.K * sizeof(int4)) + align_up((size_t)n_rep * h->g.K * sizeof(double));
+  void* tmp = nullptr;
+  HIP_OK(h, hipMallocAsync(&tmp, need, s));
+  StepBufs b{};
+  b.R = n_rep;
+  b.seed = seed;
+  b.step = step;
+  b.modes = (int4*)tmp;
+  b.w = (double*)((char*)tmp + align_up((size_t)n_rep * h->g.K * sizeof(int4)));
+  b.kset_out = kset_out;
+  b.nacc_out = n_accepted_out;
+  b.status = h->status;
+  launch_sample(h->g, b, s);
+  HIP_OK(h, hipFreeAsync(tmp, s));
+  return SRBE_OK;
+}
+
+int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets, const double* ion_xyz,
+              const double* ion_q, const double* dpsi, const uint64_t* seed, uint64_t step, const int32_t* kset_in,
+              const double* Q_in, double* Q_out, double* F_out, double* b_out, double* psibar_out,
+              double* energy_out, int32_t* kset_out, void* stream) {
+  if (!h) return SRBE_EINVAL;
+  if (precision != SRBE_FP64 && precision != SRBE_FP32) return set_err(h, SRBE_EINVAL, "unknown precision");
+  if (n_rep <= 0 || !ion_offsets) return set_err(h, SRBE_EINVAL, "n_rep must be positive and offsets given");
+  if (ion_offsets[0] != 0) return set_err(h, SRBE_EINVAL, "ion_offsets[0] must be 0");
+  int64_t max_nrep = 0;
+  for (int r = 0; r < n_rep; ++r) {
+    const int64_t c = ion_offsets[r + 1] - ion_offsets[r];
+    if (c < 0) return set_err(h, SRBE_EINVAL, "ion_offsets must be non-decreasing");
+    max_nrep = std::max(max_nrep, c);
+  }
+  const int64_t N = ion_offsets[n_rep];
+  if (N > 0 && (!ion_xyz || !ion_q)) return set_err(h, SRBE_EINVAL, "ion arrays are NULL");
+  if (!dpsi || !Q_out || (N > 0 && !F_out)) return set_err(h, SRBE_EINVAL, "dpsi, Q_out and F_out are required");
+  if (!kset_in && !seed && h->p.P > 0) return set_err(h, SRBE_EINVAL, "seed or kset_in is required");
+  if (!Q_in && !h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: pass Q_in");
+  if (max_nrep > (int64_t)1 << 31) return set_err(h, SRBE_EINVAL, "replica too large");
+  if (n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
+  const int fp32 = precision == SRBE_FP32;
+  const int fixedQ = Q_in != nullptr;
+  const Geom& g = h->g;
+  const int R = n_rep, K = g.K, n = h->n_ele;
+  hipStream_t s = (hipStream_t)stream;
+
+  // chunking of the structure-factor passes: aim for >= 2048 blocks of 256 threads
+  const int ktiles = std::max(1, (K + 255) / 256);
+  auto chunks_for = [&](int64_t np) {
+    int64_t c = (2048 + (int64_t)ktiles * R - 1) / ((int64_t)ktiles * R);
+    c = std::min<int64_t>(c, std::max<int64_t>(1, (np + 31) / 32));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(c, 4096));
+  };
+  const int nch_ion = chunks_for(max_nrep);
+  const int nch_ele = chunks_for(n);
+  const int nch = std::max(nch_ion, nch_ele);
+
+  // workspace
+  struct Item {
+    void** ptr;
+    size_t bytes;
+  };
+  StepBufs b{};
+  std::vector<Item> items = {
+      {(void**)&b.scal, (size_t)R * 4 * sizeof(double)},
+      {(void**)&b.modes, (size_t)R * std::max(K, 1) * sizeof(int4)},
+      {(void**)&b.w, (size_t)R * std::max(K, 1) * sizeof(double)},
+      {(void**)&b.ion_frac, fp32 ? 0 : (size_t)3 * N * sizeof(double)},
+      {(void**)&b.ion_fx, fp32 ? (size_t)N * sizeof(uint4) : 0},
+      {(void**)&b.part, (size_t)R * nch * std::max(K, 1) * sizeof(double2)},
+      {(void**)&b.S1, (size_t)R * std::max(K, 1) * sizeof(double2)},
+      {(void**)&b.coef, (size_t)R * std::max(K, 1) * sizeof(double2)},
+      {(void**)&b.rec, fp32 ? (size_t)R * std::max(K, 1) * sizeof(ModeRec32) : 0},
+      {(void**)&b.bstar, b_out ? 0 : (size_t)R * n * sizeof(double)},
+      {(void**)&b.V, (size_t)R * n * sizeof(double)},
+      {(void**)&b.Qext, fixedQ ? 0 : (size_t)R * (n + 1) * sizeof(double)},
+      {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
+      {(void**)&b.rsum, (size_t)R * 8 * sizeof(double)},
+      {(void**)&b.phi, (size_t)std::max<int64_t>(N, 1) * sizeof(double)},
+      {(void**)&b.energy_out, energy_out ? 0 : (size_t)R * sizeof(double)},
+  };
+  size_t total = 0;
+  for (auto& it : items) total += align_up(it.bytes);
+  if (total > h->ws_bytes) {
+    if (h->ws) HIP_OK(h, hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    HIP_OK(h, hipMalloc(&h->ws, total));
+    h->ws_bytes = total;
+  }
+  {
+    char* base = (char*)h->ws;
+    for (auto& it : items) {
+      *it.ptr = it.bytes ? (void*)base : nullptr;
+      base += align_up(it.bytes);
+    }
+  }
+  // CSR offsets: uploaded only when they change
+  if ((int)h->off_cache.size() != R + 1 || std::memcmp(h->off_cache.data(), ion_offsets, (R + 1) * sizeof(int64_t))) {
+    if (h->off_cap < (size_t)(R + 1)) {
+      if (h->off_dev) HIP_OK(h, hipFree(h->off_dev));
+      HIP_OK(h, hipMalloc(&h->off_dev, (size_t)(R + 1) * sizeof(int64_t)));
+      h->off_cap = R + 1;
+    }
+    HIP_OK(h, hipStreamSynchronize(s));
+    HIP_OK(h, hipMemcpy(h->off_dev, ion_offsets, (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    h->off_cache.assign(ion_offsets, ion_offsets + R + 1);
+  }
+  b.R = R;
+  b.N = N;
+  b.max_nrep = (int)max_nrep;
+  b.off = h->off_dev;
+  b.ion_xyz = ion_xyz;
+  b.ion_q = ion_q;
+  b.dpsi = dpsi;
+  b.seed = seed;
+  b.step = step;
+  b.kset_in = kset_in;
+  b.ele_xyz = h->ele_xyz;
+  b.ele_frac = h->ele_frac;
+  b.ele_fx = h->ele_fx;
+  b.ele_d = h->ele_d;
+  b.nchunk_ion = nch_ion;
+  b.nchunk_ele = nch_ele;
+  if (b_out) b.bstar = b_out;
+  b.status = h->status;
+  b.Q_out = Q_out;
+  b.F_out = F_out;
+  b.psibar_out = psibar_out;
+  if (energy_out) b.energy_out = energy_out;
+  b.kset_out = kset_out;
+  b.nacc_out = nullptr;
+  b.Q_in = Q_in;
+
+  { PhaseTimer t(h, s, 0); launch_replica_scalars(g, b, s); }
+  { PhaseTimer t(h, s, 1); launch_sample(g, b, s); }
+  { PhaseTimer t(h, s, 2); launch_prep(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 3); launch_sf_ions(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 4); launch_sf_finalize(g, b, 1, fp32, s); }
+  { PhaseTimer t(h, s, 5); launch_ele_potential(g, b, fp32, s); }
+  if (!fixedQ) {
+    PhaseTimer t(h, s, 6);
+    BLAS_OK(h, rocblas_set_stream(h->blas, s));
+    const double one = 1.0, zero = 0.0;
+    BLAS_OK(h, rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, n + 1, R, n, &one, h->Sext,
+                             n + 1, b.V, n, &zero, b.Qext, n + 1));
+  }
+  { PhaseTimer t(h, s, 7); launch_post_charges(g, b, fixedQ, s); }
+  { PhaseTimer t(h, s, 8); launch_sf_ele(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 9); launch_sf_finalize(g, b, 2, fp32, s); }
+  { PhaseTimer t(h, s, 10); launch_ion_force(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 11); launch_energy(g, b, fixedQ, s); }
+  HIP_OK(h, hipGetLastError());
+  return SRBE_OK;
+}
+
+const char* srbe_phase_name(int32_t phase) {
+  return (phase >= 0 && phase < SRBE_N_PHASES) ? kPhaseNames[phase] : "";
+}
+
+int srbe_profile_enable(srbe_system* h, int32_t enable) {
+  if (!h) return SRBE_EINVAL;
+  h->prof = enable != 0;
+  return SRBE_OK;
+}
+
+int srbe_profile_read(srbe_system* h, double* ms_out, int64_t* launches_out) {
+  if (!h || !ms_out || !launches_out) return SRBE_EINVAL;
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    HIP_OK(h, hipEventSynchronize(h->ev_pool[2 * i + 1]));
+    float ms = 0.f;
+    HIP_OK(h, hipEventElapsedTime(&ms, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]));
+    h->prof_ms[h->ev_phase[i]] += ms;
+    h->prof_n[h->ev_phase[i]] += 1;
+  }
+  h->ev_used = 0;
+  for (int p = 0; p < SRBE_N_PHASES; ++p) {
+    ms_out[p] = h->prof_ms[p];
+    launches_out[p] = h->prof_n[p];
+    h->prof_ms[p] = 0.0;
+    h->prof_n[p] = 0;
+  }
+  return SRBE_OK;
+}
+
+}  // extern "C"
