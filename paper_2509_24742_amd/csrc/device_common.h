@@ -23,7 +23,29 @@ struct Geom {
   double sig[3];   // proposal standard deviation per axis (in units of m)
   int M, P, K;     // K = M + P modes per replica
   int n_ele;
+  // real-space cell grid: ncx x ncy cells over the periodic x, y extent, ncz over
+  // z in [0, H]; cells are wider than rc in x, y and than rc / nzs in z, so all pairs
+  // closer than rc lie within one cell in x, y and nzs cells in z of each other
+  int ncx, ncy, ncz, ncell;
+  int nzs;          // the z-stencil reaches nzs cells up and down (cells are >= rc / nzs thick)
+  float eta_skip;   // FP32 path: beyond this distance erfc(r/eta)/r and its derivative are below
+                    // 2^-30 of the alpha terms at rc and are not evaluated
 };
+
+constexpr int kMaxBinParticles = 8192;  // particles per replica the one-block cell sort handles
+constexpr int kMaxCells = 2048;
+constexpr int kNbMax = 63;  // neighbour cells per cell: 3 x 3 x (2 nzs + 1) with nzs <= 3
+
+// Cell of a position (x, y wrapped by the caller into fractions sx, sy in [0,1)).
+__device__ __forceinline__ int cell_index(const Geom& g, double sx, double sy, double z) {
+  int cx = (int)(sx * g.ncx);
+  int cy = (int)(sy * g.ncy);
+  int cz = (int)(z / g.H * g.ncz);
+  cx = cx < 0 ? 0 : (cx >= g.ncx ? g.ncx - 1 : cx);
+  cy = cy < 0 ? 0 : (cy >= g.ncy ? g.ncy - 1 : cy);
+  cz = cz < 0 ? 0 : (cz >= g.ncz ? g.ncz - 1 : cz);
+  return (cz * g.ncy + cy) * g.ncx + cx;
+}
 
 // ------------------------------------------------------------------ Philox4x64-10
 // Salmon, Moraes, Dror, Shaw, SC'11: per round two 64x64->128 products, the

@@ -28,26 +28,41 @@ struct StepBufs {
   const uint64_t* seed;     // R
   uint64_t step;
   const int32_t* kset_in;   // R*P*3 or null
-  // electrodes (device, fixed)
+  // electrodes (device, fixed): original order and cell-sorted order
   const double* ele_xyz;    // SoA 3*n_ele
-  const double* ele_frac;   // SoA 3*n_ele fractional coordinates
-  const uint4* ele_fx;      // AoS fixed point
   const double* ele_d;      // n_ele
+  const uint4* ele_fx;      // n_ele fixed point (original order)
+  const double4* ele_d4;    // n_ele fractional coordinates (original order), w = 0
+  const int* ele_perm;      // sorted position -> electrode index
+  const int* ele_scell;     // cell of each sorted electrode
+  const int* ele_cstart;    // ncell + 1
+  const double2* ele_czr;   // ncell: z-extent of the electrodes of each cell
+  const int* nbr;           // ncell x kNbMax neighbour cells of each cell, -1 terminated
+  const uint4* ele_sfx;     // sorted fixed point
+  const double4* ele_sd4;   // sorted fractional coordinates
   // workspace
   double* scal;             // R*4: sum q, sum |q|, sum q z, sum q^2
   int4* modes;              // R*K
   double* w;                // R*K
-  double* ion_frac;         // SoA 3N (FP64 path)
-  uint4* ion_fx;            // N (FP32 path)
-  double2* part;            // R*nchunk*K
-  int nchunk_ion, nchunk_ele;
+  uint4* ion_fx;            // N fixed point + FP32 charge, original order (FP32 path)
+  double4* ion_d4;          // N fractional coordinates + charge, original order (FP64 path)
+  int* perm;                // N sorted position (within the replica's range) -> global ion index
+  int* scell;               // N cell of each sorted ion
+  int* cstart;              // R*(ncell+1) cell starts, relative to the replica's first ion
+  uint4* sfx;               // N sorted fixed point (FP32 path)
+  double4* sd4;             // N sorted fractional coordinates (FP64 path)
+  double2* part;            // R*nchunk*K partial structure factors
+  int nchunk_ion, nchunk_ele, ktiles;
   double2* S1;              // R*K
   double2* coef;            // R*K
   ModeRec32* rec;           // R*K (FP32 path)
+  double* bN;               // R*n_ele real-space electrode potential from the ions
   double* bstar;            // R*n_ele
   double* V;                // R*n_ele (dpsi d + b*), GEMM right-hand side, ld n_ele
   double* Qext;             // R*(n_ele+1) GEMM output (Q then psibar), ld n_ele+1
-  float* Qf;                // R*n_ele FP32 copy of Q (FP32 path)
+  float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
+  float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
+  double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)
   double* rsum;             // R*8 per-replica reductions after the charge solve
   double* phi;              // N real-space ion-ion potential per ion
   unsigned* status;
@@ -61,22 +76,26 @@ struct StepBufs {
   const double* Q_in;
 };
 
-void launch_replica_scalars(const Geom& g, const StepBufs& b, hipStream_t s);
+void launch_prepare(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s);
-void launch_prep(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_sf_finalize(const Geom& g, const StepBufs& b, int stage, int fp32, hipStream_t s);
+void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
+void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
 void launch_sf_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_real_ion(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_energy(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 
 // setup kernels
+void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, uint4* fx,
+                           double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4, unsigned* status,
+                           hipStream_t s);
+void launch_cell_zrange(const Geom& g, const int* cstart, const double* ele_xyz, const int* perm, double2* zr,
+                        hipStream_t s);
 void launch_ele_phase_block(const double* ele_xyz, int n_ele, const int* m, const double* sqrtw, int nk, int ld,
                             double* E, const Geom& g, hipStream_t s);
 void launch_ele_realspace_matrix(const Geom& g, const double* ele_xyz, int n_ele, double* A, hipStream_t s);
-void launch_ele_fixed(const Geom& g, const double* ele_xyz, int n_ele, double* frac, uint4* fx, hipStream_t s);
 void launch_symmetrize_lower(double* A, int n, int ld, hipStream_t s);
 void launch_rowsum(const double* A, int n, int ld, double* out, hipStream_t s);
 void launch_build_sext(const double* Ainv, int n, const double* g, double eg, double* Sext, hipStream_t s);

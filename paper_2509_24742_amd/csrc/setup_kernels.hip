@@ -65,23 +65,6 @@ void launch_ele_realspace_matrix(const Geom& g, const double* ele_xyz, int n_ele
   hipLaunchKernelGGL(k_ele_realspace_matrix, dim3(cdiv(n_ele, 256), n_ele), dim3(256), 0, s, g, ele_xyz, n_ele, A);
 }
 
-// Fractional and fixed-point electrode coordinates.
-__global__ __launch_bounds__(256) void k_ele_fixed(Geom g, const double* __restrict__ xyz, int n,
-                                                   double* __restrict__ frac, uint4* __restrict__ fx) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  const double sx = wrap_frac(xyz[j], g.invLx), sy = wrap_frac(xyz[n + j], g.invLy);
-  const double sz = wrap_frac(xyz[2 * n + j], g.invLz);
-  frac[j] = sx;
-  frac[n + j] = sy;
-  frac[2 * n + j] = sz;
-  fx[j] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), 0u);
-}
-
-void launch_ele_fixed(const Geom& g, const double* ele_xyz, int n_ele, double* frac, uint4* fx, hipStream_t s) {
-  hipLaunchKernelGGL(k_ele_fixed, dim3(cdiv(n_ele, 256)), dim3(256), 0, s, g, ele_xyz, n_ele, frac, fx);
-}
-
 // Copy the lower triangle onto the upper one.
 __global__ __launch_bounds__(256) void k_symmetrize_lower(double* A, int n, int ld) {
   const int i = blockIdx.x * 256 + threadIdx.x;

@@ -23,12 +23,22 @@ struct srbe_system {
   int n_ele = 0;
   bool has_cp = false;
   double* ele_xyz = nullptr;
-  double* ele_frac = nullptr;
-  uint4* ele_fx = nullptr;
   double* ele_d = nullptr;
+  uint4* ele_fx = nullptr;     // fixed point, input order
+  double4* ele_d4 = nullptr;   // fractional coordinates, input order
+  int* ele_perm = nullptr;     // cell-sorted position -> electrode index
+  int* ele_scell = nullptr;    // cell of each sorted electrode
+  int* ele_cstart = nullptr;   // ncell + 1
+  double2* ele_czr = nullptr;  // ncell: z-extent of each cell's electrodes
+  int* nbr = nullptr;          // ncell x kNbMax neighbour cells, -1 terminated
+  uint4* ele_sfx = nullptr;    // sorted fixed point
+  double4* ele_sd4 = nullptr;  // sorted fractional coordinates
   double* Sext = nullptr;
   unsigned* status = nullptr;
   rocblas_handle blas = nullptr;
+  // the sampler runs on a second stream, forked from and joined back to the step's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -128,6 +138,38 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   g.P = p.P;
   g.K = p.M + p.P;
   g.n_ele = n_ele;
+  // real-space cells at least rc wide in x and y and rc / nzs thick in z (the
+  // z-stencil then reaches nzs cells each way); coarsened, never below those
+  // widths, to stay within kMaxCells
+  g.nzs = 3;
+  // (the 1e-9 margin keeps cells strictly wider than rc and rc / nzs, so rounding in
+  // the cell index never puts a pair closer than rc outside the stencil)
+  const double shrink = 1.0 - 1e-9;
+  g.ncx = std::max(1, (int)std::floor(p.Lx / p.rc * shrink));
+  g.ncy = std::max(1, (int)std::floor(p.Ly / p.rc * shrink));
+  g.ncz = std::max(1, (int)std::floor(p.H * g.nzs / p.rc * shrink));
+  while (g.ncx * g.ncy * g.ncz > kMaxCells) {
+    if (g.ncz >= g.ncx && g.ncz >= g.ncy)
+      g.ncz = (g.ncz + 1) / 2;
+    else if (g.ncx >= g.ncy)
+      g.ncx = (g.ncx + 1) / 2;
+    else
+      g.ncy = (g.ncy + 1) / 2;
+  }
+  g.ncell = g.ncx * g.ncy * g.ncz;
+  // eta_skip = eta x*, the smallest x with erfc(x) and exp(-x^2)/eta below 2^-30 of
+  // erfc(alpha rc) and alpha exp(-alpha^2 rc^2) (bisection)
+  {
+    const double ar = p.alpha * p.rc;
+    const double t1 = std::ldexp(std::erfc(ar), -30), t2 = std::ldexp(p.alpha * std::exp(-ar * ar), -30);
+    auto ok = [&](double x) { return std::erfc(x) <= t1 && std::exp(-x * x) / p.eta <= t2; };
+    double lo = 0.0, hi = 64.0;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (ok(mid)) hi = mid; else lo = mid;
+    }
+    g.eta_skip = (float)(p.eta * hi);
+  }
   return g;
 }
 
@@ -254,9 +296,9 @@ int build_electrode_solve(srbe_system* h, hipStream_t s) {
 
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-const char* kPhaseNames[SRBE_N_PHASES] = {"replica_scalars", "sample",       "prep",    "sf_ions",
-                                          "finalize_ions",   "ele_potential", "cp_gemm", "post_charges",
-                                          "sf_ele",          "finalize_ele", "ion_force", "energy"};
+const char* kPhaseNames[SRBE_N_PHASES] = {"prepare", "sample",       "sf_ions",   "real_ele",
+                                          "ele_potential", "cp_gemm", "post_charges", "sf_ele",
+                                          "ion_force", "real_ion", "energy", "unused"};
 
 // Record an event pair around a phase when profiling is enabled.
 struct PhaseTimer {
@@ -319,7 +361,11 @@ void srbe_destroy(srbe_system* h) {
   (void)hipDeviceSynchronize();
   if (h->blas) rocblas_destroy_handle(h->blas);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  void* bufs[] = {h->ele_xyz, h->ele_frac, h->ele_fx, h->ele_d, h->Sext, h->status, h->ws, h->off_dev};
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  void* bufs[] = {h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
+                  h->ele_czr, h->nbr,    h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -334,7 +380,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
   if (!msg.empty()) return SRBE_EINVAL;
   if (n_ele <= 0 || !ele_xyz || !ele_side) return SRBE_EINVAL;
   const bool cp = !(params->flags & SRBE_FLAG_NO_CP);
-  if (cp && n_ele > 65535) return SRBE_EINVAL;
+  if (n_ele > kMaxBinParticles) return SRBE_EINVAL;
   std::vector<double> d(n_ele);
   for (int j = 0; j < n_ele; ++j) {
     if (ele_side[j] != 1 && ele_side[j] != -1) return SRBE_EINVAL;
@@ -357,20 +403,68 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     return code;
   };
   {
-    hipError_t e;
-    if ((e = hipMalloc(&h->ele_xyz, (size_t)3 * n_ele * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&h->ele_frac, (size_t)3 * n_ele * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&h->ele_fx, (size_t)n_ele * sizeof(uint4))) != hipSuccess ||
-        (e = hipMalloc(&h->ele_d, (size_t)n_ele * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&h->status, sizeof(unsigned))) != hipSuccess)
+    hipError_t e = hipSuccess;
+    const size_t n = (size_t)n_ele;
+    const Geom& g = h->g;
+    auto al = [&](void** p, size_t bytes) {
+      if (e == hipSuccess) e = hipMalloc(p, bytes);
+    };
+    al((void**)&h->ele_xyz, 3 * n * sizeof(double));
+    al((void**)&h->ele_d, n * sizeof(double));
+    al((void**)&h->ele_fx, n * sizeof(uint4));
+    al((void**)&h->ele_d4, n * sizeof(double4));
+    al((void**)&h->ele_perm, n * sizeof(int));
+    al((void**)&h->ele_scell, n * sizeof(int));
+    al((void**)&h->ele_cstart, (size_t)(g.ncell + 1) * sizeof(int));
+    al((void**)&h->ele_czr, (size_t)g.ncell * sizeof(double2));
+    al((void**)&h->nbr, (size_t)g.ncell * kNbMax * sizeof(int));
+    al((void**)&h->ele_sfx, n * sizeof(uint4));
+    al((void**)&h->ele_sd4, n * sizeof(double4));
+    al((void**)&h->status, sizeof(unsigned));
+    int64_t* off2 = nullptr;
+    al((void**)&off2, 2 * sizeof(int64_t));
+    if (e != hipSuccess) {
+      if (off2) (void)hipFree(off2);
       return fail(e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP);
-    if (hipMemcpy(h->ele_xyz, ele_xyz, (size_t)3 * n_ele * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->ele_d, d.data(), (size_t)n_ele * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess)
+    }
+    const int64_t h_off[2] = {0, n_ele};
+    // neighbour cells of every cell: 3 x 3 in x, y (periodic; an axis with fewer than 3
+    // cells contributes each of its cells once) times cz - nzs .. cz + nzs, clipped in z
+    std::vector<int> nb((size_t)g.ncell * kNbMax, -1);
+    for (int c = 0; c < g.ncell; ++c) {
+      const int cx = c % g.ncx, cy = (c / g.ncx) % g.ncy, cz = c / (g.ncx * g.ncy);
+      std::vector<int> xs, ys;
+      if (g.ncx >= 3) xs = {(cx + g.ncx - 1) % g.ncx, cx, (cx + 1) % g.ncx};
+      else for (int x = 0; x < g.ncx; ++x) xs.push_back(x);
+      if (g.ncy >= 3) ys = {(cy + g.ncy - 1) % g.ncy, cy, (cy + 1) % g.ncy};
+      else for (int y = 0; y < g.ncy; ++y) ys.push_back(y);
+      int k = 0;
+      for (int z = std::max(0, cz - g.nzs); z <= std::min(g.ncz - 1, cz + g.nzs); ++z)
+        for (int y : ys)
+          for (int x : xs) nb[(size_t)c * kNbMax + k++] = (z * g.ncy + y) * g.ncx + x;
+    }
+    if (hipMemcpy(h->ele_xyz, ele_xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ele_d, d.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(off2, h_off, sizeof(h_off), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->nbr, nb.data(), nb.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) {
+      (void)hipFree(off2);
       return fail(SRBE_EHIP);
+    }
+    launch_bin_electrodes(g, off2, h->ele_xyz, n_ele, h->ele_fx, h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
+                          h->ele_sfx, h->ele_sd4, h->status, s);
+    launch_cell_zrange(g, h->ele_cstart, h->ele_xyz, h->ele_perm, h->ele_czr, s);
+    if (hipDeviceSynchronize() != hipSuccess) {
+      (void)hipFree(off2);
+      return fail(SRBE_EHIP);
+    }
+    (void)hipFree(off2);
   }
-  launch_ele_fixed(h->g, h->ele_xyz, n_ele, h->ele_frac, h->ele_fx, s);
   if (rocblas_create_handle(&h->blas) != rocblas_status_success) return fail(SRBE_EHIP);
+  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+    return fail(SRBE_EHIP);
   if (cp) {
     rc = build_electrode_solve(h, s);
     if (rc != SRBE_OK) {
@@ -444,6 +538,8 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   if (!Q_in && !h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: pass Q_in");
   if (max_nrep > (int64_t)1 << 31) return set_err(h, SRBE_EINVAL, "replica too large");
   if (n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
+  if (max_nrep > kMaxBinParticles)
+    return set_err(h, SRBE_EINVAL, "a replica has more ions than the one-block cell sort handles (8192)");
   const int fp32 = precision == SRBE_FP32;
   const int fixedQ = Q_in != nullptr;
   const Geom& g = h->g;
@@ -453,7 +549,7 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   // chunking of the structure-factor passes: aim for >= 2048 blocks of 256 threads
   const int ktiles = std::max(1, (K + 255) / 256);
   auto chunks_for = [&](int64_t np) {
-    int64_t c = (2048 + (int64_t)ktiles * R - 1) / ((int64_t)ktiles * R);
+    int64_t c = (1024 + (int64_t)ktiles * R - 1) / ((int64_t)ktiles * R);
     c = std::min<int64_t>(c, std::max<int64_t>(1, (np + 31) / 32));
     return (int)std::max<int64_t>(1, std::min<int64_t>(c, 4096));
   };
@@ -471,16 +567,24 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
       {(void**)&b.scal, (size_t)R * 4 * sizeof(double)},
       {(void**)&b.modes, (size_t)R * std::max(K, 1) * sizeof(int4)},
       {(void**)&b.w, (size_t)R * std::max(K, 1) * sizeof(double)},
-      {(void**)&b.ion_frac, fp32 ? 0 : (size_t)3 * N * sizeof(double)},
-      {(void**)&b.ion_fx, fp32 ? (size_t)N * sizeof(uint4) : 0},
+      {(void**)&b.ion_fx, fp32 ? (size_t)std::max<int64_t>(N, 1) * sizeof(uint4) : 0},
+      {(void**)&b.ion_d4, fp32 ? 0 : (size_t)std::max<int64_t>(N, 1) * sizeof(double4)},
+      {(void**)&b.perm, (size_t)std::max<int64_t>(N, 1) * sizeof(int)},
+      {(void**)&b.scell, (size_t)std::max<int64_t>(N, 1) * sizeof(int)},
+      {(void**)&b.cstart, (size_t)R * (g.ncell + 1) * sizeof(int)},
+      {(void**)&b.sfx, fp32 ? (size_t)std::max<int64_t>(N, 1) * sizeof(uint4) : 0},
+      {(void**)&b.sd4, fp32 ? 0 : (size_t)std::max<int64_t>(N, 1) * sizeof(double4)},
       {(void**)&b.part, (size_t)R * nch * std::max(K, 1) * sizeof(double2)},
       {(void**)&b.S1, (size_t)R * std::max(K, 1) * sizeof(double2)},
       {(void**)&b.coef, (size_t)R * std::max(K, 1) * sizeof(double2)},
       {(void**)&b.rec, fp32 ? (size_t)R * std::max(K, 1) * sizeof(ModeRec32) : 0},
+      {(void**)&b.bN, (size_t)R * n * sizeof(double)},
       {(void**)&b.bstar, b_out ? 0 : (size_t)R * n * sizeof(double)},
       {(void**)&b.V, (size_t)R * n * sizeof(double)},
       {(void**)&b.Qext, fixedQ ? 0 : (size_t)R * (n + 1) * sizeof(double)},
       {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
+      {(void**)&b.Qsf, fp32 ? (size_t)R * n * sizeof(float) : 0},
+      {(void**)&b.Qsd, fp32 ? 0 : (size_t)R * n * sizeof(double)},
       {(void**)&b.rsum, (size_t)R * 8 * sizeof(double)},
       {(void**)&b.phi, (size_t)std::max<int64_t>(N, 1) * sizeof(double)},
       {(void**)&b.energy_out, energy_out ? 0 : (size_t)R * sizeof(double)},
@@ -523,11 +627,19 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   b.step = step;
   b.kset_in = kset_in;
   b.ele_xyz = h->ele_xyz;
-  b.ele_frac = h->ele_frac;
-  b.ele_fx = h->ele_fx;
   b.ele_d = h->ele_d;
+  b.ele_fx = h->ele_fx;
+  b.ele_d4 = h->ele_d4;
+  b.ele_perm = h->ele_perm;
+  b.ele_scell = h->ele_scell;
+  b.ele_cstart = h->ele_cstart;
+  b.ele_czr = h->ele_czr;
+  b.nbr = h->nbr;
+  b.ele_sfx = h->ele_sfx;
+  b.ele_sd4 = h->ele_sd4;
   b.nchunk_ion = nch_ion;
   b.nchunk_ele = nch_ele;
+  b.ktiles = ktiles;
   if (b_out) b.bstar = b_out;
   b.status = h->status;
   b.Q_out = Q_out;
@@ -538,24 +650,28 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   b.nacc_out = nullptr;
   b.Q_in = Q_in;
 
-  { PhaseTimer t(h, s, 0); launch_replica_scalars(g, b, s); }
-  { PhaseTimer t(h, s, 1); launch_sample(g, b, s); }
-  { PhaseTimer t(h, s, 2); launch_prep(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 3); launch_sf_ions(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 4); launch_sf_finalize(g, b, 1, fp32, s); }
-  { PhaseTimer t(h, s, 5); launch_ele_potential(g, b, fp32, s); }
+  // the sampler only reads the seeds: it runs beside the preparation pass
+  HIP_OK(h, hipEventRecord(h->ev_fork, s));
+  HIP_OK(h, hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+  { PhaseTimer t(h, h->aux, 1); launch_sample(g, b, h->aux); }
+  HIP_OK(h, hipEventRecord(h->ev_join, h->aux));
+  { PhaseTimer t(h, s, 0); launch_prepare(g, b, fp32, s); }
+  HIP_OK(h, hipStreamWaitEvent(s, h->ev_join, 0));
+  { PhaseTimer t(h, s, 2); launch_sf_ions(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 3); launch_real_ele(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 4); launch_ele_potential(g, b, fp32, s); }
   if (!fixedQ) {
-    PhaseTimer t(h, s, 6);
+    PhaseTimer t(h, s, 5);
     BLAS_OK(h, rocblas_set_stream(h->blas, s));
     const double one = 1.0, zero = 0.0;
     BLAS_OK(h, rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, n + 1, R, n, &one, h->Sext,
                              n + 1, b.V, n, &zero, b.Qext, n + 1));
   }
-  { PhaseTimer t(h, s, 7); launch_post_charges(g, b, fixedQ, s); }
-  { PhaseTimer t(h, s, 8); launch_sf_ele(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 9); launch_sf_finalize(g, b, 2, fp32, s); }
-  { PhaseTimer t(h, s, 10); launch_ion_force(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 11); launch_energy(g, b, fixedQ, s); }
+  { PhaseTimer t(h, s, 6); launch_post_charges(g, b, fixedQ, fp32, s); }
+  { PhaseTimer t(h, s, 7); launch_sf_ele(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 8); launch_ion_force(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 9); launch_real_ion(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 10); launch_energy(g, b, fixedQ, s); }
   HIP_OK(h, hipGetLastError());
   return SRBE_OK;
 }

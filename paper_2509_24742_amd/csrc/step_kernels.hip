@@ -1,12 +1,14 @@
 // Per-step kernels of the SRBE constant-potential step (gfx950).
 //
-// Pipeline of one step (Algorithm 1 of the paper, integration excluded), all on
-// one stream, for R replicas sharing one electrode geometry:
-//   replica_scalars -> sample -> prep -> sf(ions) -> finalize(1) -> ele_potential
-//   -> [FP64 GEMM: (Q; psibar) = S_ext V] -> post_charges -> sf(electrodes)
-//   -> finalize(2) -> ion_force -> energy
-// Every reduction has a fixed order (no floating-point atomics), so two runs on
-// the same inputs give bitwise-identical results.
+// One step (Algorithm 1 of the paper, integration excluded), all on one stream,
+// for R replicas sharing one electrode geometry:
+//   prepare -> sample -> sf(ions) -> real_ele -> ele_potential
+//   -> [FP64 GEMM: (Q; psibar) = S_ext (dpsi d + b*)] -> post_charges -> sf(electrodes)
+//   -> ion_force -> real_ion -> energy
+// Structure-factor partial sums are reduced by the last block of each mode tile, in
+// a fixed order; real-space neighbours are visited in a fixed (cell, index) order.
+// There are no floating-point atomics, so two runs on the same inputs give
+// bitwise-identical results.
 #include <math.h>
 
 #include "kernels.h"
@@ -18,60 +20,148 @@ static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); 
 #define TWO_PI 6.283185307179586
 #define INV_SQRT_PI 0.5641895835477563
 
-// Deterministic block reduction of NV doubles over a 256-thread block; result in
-// thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[256]) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int a = 0; a < NV; ++a) sh[a][t] = v[a];
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deterministic sum over a block of NT threads of NV doubles; result valid in thread 0.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[NT / 64]) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 #pragma unroll
-      for (int a = 0; a < NV; ++a) sh[a][t] += sh[a][t + s];
-    }
-    __syncthreads();
+  for (int a = 0; a < NV; ++a) {
+    const double s = wave_sum(v[a]);
+    if (lane == 0) sh[a][wv] = s;
   }
+  __syncthreads();
+  if (t == 0) {
 #pragma unroll
-  for (int a = 0; a < NV; ++a) v[a] = sh[a][0];
+    for (int a = 0; a < NV; ++a) {
+      double s = 0.0;
+      for (int u = 0; u < NT / 64; ++u) s += sh[a][u];
+      v[a] = s;
+    }
+  }
   __syncthreads();
 }
 
-// ============================================================ replica scalars
-// sum q (neutrality), sum |q|, sum q z (slab term of Eq. (17)), sum q^2 (self term);
-// flags z outside [0, H] and non-finite inputs.
-__global__ __launch_bounds__(256) void k_replica_scalars(Geom g, const int64_t* __restrict__ off,
-                                                         const double* __restrict__ xyz,
-                                                         const double* __restrict__ q, int64_t N,
-                                                         double* __restrict__ scal, unsigned* status) {
-  __shared__ double sh[4][256];
+// ============================================================ prepare
+// Per replica (one block of 1024 threads): sum q (neutrality), sum |q|, sum q z
+// (slab term of Eq. (17)), sum q^2 (self term); range checks; the particle records
+// of the k-space passes in input order; and the cell lists of the real-space
+// passes: a bitonic sort of the unique keys (cell << 13 | index) gives every cell
+// its particles in index order.
+template <bool FP32>
+__global__ __launch_bounds__(1024) void k_prepare(Geom g, const int64_t* __restrict__ off,
+                                                  const double* __restrict__ xyz, const double* __restrict__ q,
+                                                  int64_t N, double* __restrict__ scal, uint4* __restrict__ fx,
+                                                  double4* __restrict__ d4, int* __restrict__ perm,
+                                                  int* __restrict__ scell, int* __restrict__ cstart,
+                                                  uint4* __restrict__ sfx, double4* __restrict__ sd4,
+                                                  unsigned* status, int is_ions) {
+  __shared__ unsigned keys[kMaxBinParticles];
+  __shared__ int cnt[kMaxCells + 1];
+  __shared__ double red[4][16];
   const int r = blockIdx.x;
-  const int64_t b = off[r], e = off[r + 1];
+  const int t = threadIdx.x;
+  const int64_t b0 = off[r];
+  const int n = (int)(off[r + 1] - b0);
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int c = t; c <= g.ncell; c += 1024) cnt[c] = 0;
+  __syncthreads();
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   int bad = 0;
-  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
-    const double qi = q[i], x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
-    if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) bad = 1;
-    v[0] += qi;
-    v[1] += fabs(qi);
-    v[2] += qi * z;
-    v[3] += qi * qi;
+  for (int k = t; k < np; k += 1024) {
+    if (k < n) {
+      const int64_t i = b0 + k;
+      const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
+      const double qi = is_ions ? q[i] : 0.0;
+      if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) bad = 1;
+      v[0] += qi;
+      v[1] += fabs(qi);
+      v[2] += qi * z;
+      v[3] += qi * qi;
+      const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
+      const int c = cell_index(g, sx, sy, z);
+      atomicAdd(&cnt[c], 1);
+      keys[k] = ((unsigned)c << 13) | (unsigned)k;
+      if (FP32 || !is_ions) fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
+      if (!FP32 || !is_ions) d4[i] = make_double4(sx, sy, sz, qi);
+    } else {
+      keys[k] = 0xFFFFFFFFu;
+    }
   }
   if (bad) atomicOr(status, ST_RANGE);
-  block_sum<4>(v, sh);
-  if (threadIdx.x == 0) {
+  block_sum<1024, 4>(v, red);
+  if (t == 0 && is_ions) {
     scal[4 * r + 0] = v[0];
     scal[4 * r + 1] = v[1];
     scal[4 * r + 2] = v[2];
     scal[4 * r + 3] = v[3];
     if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(status, ST_NONNEUTRAL);
   }
+  // bitonic sort of the keys (ascending)
+  for (int k = 2; k <= np; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = t; i < np; i += 1024) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned a = keys[i], b = keys[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // exclusive scan of the cell counts (Hillis-Steele over ncell + 1 entries)
+  __shared__ int scan[2][kMaxCells + 1];
+  for (int c = t; c <= g.ncell; c += 1024) scan[0][c] = c == 0 ? 0 : cnt[c - 1];
+  __syncthreads();
+  int src = 0;
+  for (int o = 1; o <= g.ncell; o <<= 1) {
+    for (int c = t; c <= g.ncell; c += 1024) scan[src ^ 1][c] = scan[src][c] + (c >= o ? scan[src][c - o] : 0);
+    __syncthreads();
+    src ^= 1;
+  }
+  int* cs = cstart + (size_t)r * (g.ncell + 1);
+  for (int c = t; c <= g.ncell; c += 1024) cs[c] = scan[src][c];
+  for (int k = t; k < n; k += 1024) {
+    const unsigned key = keys[k];
+    const int loc = (int)(key & 0x1FFFu);
+    const int64_t i = b0 + loc;
+    perm[b0 + k] = (int)i;
+    scell[b0 + k] = (int)(key >> 13);
+    const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
+    const double qi = is_ions ? q[i] : 0.0;
+    const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
+    if (FP32 || !is_ions) sfx[b0 + k] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
+    if (!FP32 || !is_ions) sd4[b0 + k] = make_double4(sx, sy, sz, qi);
+  }
 }
 
-void launch_replica_scalars(const Geom& g, const StepBufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_replica_scalars, dim3(b.R), dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.scal,
-                     b.status);
+void launch_prepare(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_prepare<true>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.scal,
+                       b.ion_fx, b.ion_d4, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status, 1);
+  else
+    hipLaunchKernelGGL(k_prepare<false>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.scal,
+                       b.ion_fx, b.ion_d4, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status, 1);
+}
+
+// Electrodes are binned once per handle with the same kernel (both record formats).
+// off2: device {0, n_ele}; status: device word.
+void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, uint4* fx,
+                           double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4, unsigned* status,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_prepare<true>, dim3(1), dim3(1024), 0, s, g, off2, ele_xyz, (const double*)nullptr,
+                     (int64_t)n_ele, (double*)nullptr, fx, d4, perm, scell, cstart, sfx, sd4, status, 0);
 }
 
 // ============================================================ sampler
@@ -134,6 +224,12 @@ __device__ double sampled_weight(const Geom& g, int mx, int my, int mz) {
 }
 #pragma clang fp contract(fast)
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restrict__ seeds, uint64_t step,
                                                 const int32_t* __restrict__ kset_in, int4* __restrict__ modes,
                                                 double* __restrict__ wout, int32_t* __restrict__ kset_out,
@@ -171,11 +267,12 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
     return;
   }
   const uint64_t seed = seeds[r];
-  // LDS layout: ly[P] (double), lu[P] (double), ym[P][3] (int), ok[P] (char)
+  // LDS: ly[P], lu[P] (double), state[P] (int), ym[P][3] (int16).  An invalid
+  // proposal (target probability zero) has ly = NaN, which fails both accept tests.
   double* ly = reinterpret_cast<double*>(smem);
   double* lu = ly + P;
-  int* ym = reinterpret_cast<int*>(lu + P);
-  unsigned char* ok = reinterpret_cast<unsigned char*>(ym + 3 * P);
+  int* state = reinterpret_cast<int*>(lu + P);
+  short* ym = reinterpret_cast<short*>(state + P);
   __shared__ int first_valid;
   __shared__ int start_m[3];
   if (t == 0) first_valid = 1 << 30;
@@ -206,38 +303,45 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
     c.v[3] = 0;
     const U64x4 wa = philox4x64_10(c, seed, 0);
     const bool v = valid_mode(g, mx, my, mz);
-    ym[3 * l + 0] = mx;
-    ym[3 * l + 1] = my;
-    ym[3 * l + 2] = mz;
-    ok[l] = v ? 1 : 0;
-    ly[l] = v ? log_ratio(g, mx, my, mz) : 0.0;
+    if (abs(mx) > 32767 || abs(my) > 32767 || abs(mz) > 32767) atomicOr(status, ST_NUMERIC);
+    ym[3 * l + 0] = (short)mx;
+    ym[3 * l + 1] = (short)my;
+    ym[3 * l + 2] = (short)mz;
+    ly[l] = v ? log_ratio(g, mx, my, mz) : (double)NAN;
     lu[l] = log(u01_open(wa.v[0]));
   }
   __syncthreads();
-  if (t == 0) {
-    int cx = start_m[0], cy = start_m[1], cz = start_m[2];
-    double lx = log_ratio(g, cx, cy, cz);
-    int nacc = 0;
-    for (int l = 0; l < P; ++l) {
-      if (ok[l]) {
-        const double d = ly[l] - lx;
-        if (d >= 0.0 || lu[l] < d) {
-          cx = ym[3 * l + 0];
-          cy = ym[3 * l + 1];
-          cz = ym[3 * l + 2];
-          lx = ly[l];
+  // the chain: one wave walks the P decisions; lane j of a 64-wide chunk holds
+  // proposal base + j and the decision data are broadcast with readlane
+  if (t < 64) {
+    double lx = log_ratio(g, start_m[0], start_m[1], start_m[2]);
+    int cur = -1, nacc = 0;
+    for (int base = 0; base < P; base += 64) {
+      const int l = base + t;
+      const double myly = l < P ? ly[l] : (double)NAN;
+      const double mylu = l < P ? lu[l] : 0.0;
+      const int cnt = min(64, P - base);
+      int mine = -1;
+      for (int j = 0; j < cnt; ++j) {
+        const double lyj = readlane_f64(myly, j);
+        const double d = lyj - lx;
+        if (d >= 0.0 || readlane_f64(mylu, j) < d) {
+          lx = lyj;
+          cur = base + j;
           ++nacc;
         }
+        if (t == j) mine = cur;
       }
-      ym[3 * l + 0] = cx;
-      ym[3 * l + 1] = cy;
-      ym[3 * l + 2] = cz;
+      if (l < P) state[l] = mine;
     }
-    if (nacc_out) nacc_out[r] = nacc;
+    if (t == 0 && nacc_out) nacc_out[r] = nacc;
   }
   __syncthreads();
   for (int l = t; l < P; l += 256) {
-    const int mx = ym[3 * l + 0], my = ym[3 * l + 1], mz = ym[3 * l + 2];
+    const int s_ = state[l];
+    const int mx = s_ < 0 ? start_m[0] : ym[3 * s_ + 0];
+    const int my = s_ < 0 ? start_m[1] : ym[3 * s_ + 1];
+    const int mz = s_ < 0 ? start_m[2] : ym[3 * s_ + 2];
     modes[(size_t)r * K + M + l] = make_int4(mx, my, mz, 0);
     wout[(size_t)r * K + M + l] = sampled_weight(g, mx, my, mz);
     if (kset_out) {
@@ -249,156 +353,39 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
   }
 }
 
-size_t sample_lds_bytes(int P) { return (size_t)P * (8 + 8 + 12 + 1) + 16; }
+size_t sample_lds_bytes(int P) { return (size_t)P * (8 + 8 + 4 + 6) + 16; }
 
 void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s) {
   hipLaunchKernelGGL(k_sample, dim3(b.R), dim3(256), sample_lds_bytes(g.P), s, g, b.seed, b.step, b.kset_in, b.modes,
                      b.w, b.kset_out, b.nacc_out, b.status);
 }
 
-// ============================================================ prep
-// FP64 path: fractional coordinates s = x/L wrapped into [0,1).  FP32 path: the
-// same as 32-bit fixed point (s 2^32 mod 2^32) with the charge as FP32, one
-// 16-byte record per ion.  With fixed point, k.r in revolutions is the exact
-// wrap-around integer m_x u_x + m_y u_y + m_z u_z mod 2^32.
-__global__ __launch_bounds__(256) void k_prep(Geom g, const double* __restrict__ xyz, const double* __restrict__ q,
-                                              int64_t N, double* __restrict__ frac, uint4* __restrict__ fx, int fp32) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= N) return;
-  const double sx = wrap_frac(xyz[i], g.invLx);
-  const double sy = wrap_frac(xyz[N + i], g.invLy);
-  const double sz = wrap_frac(xyz[2 * N + i], g.invLz);
-  if (fp32) {
-    fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)q[i]));
-  } else {
-    frac[i] = sx;
-    frac[N + i] = sy;
-    frac[2 * N + i] = sz;
-  }
-}
-
-void launch_prep(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (b.N == 0) return;
-  hipLaunchKernelGGL(k_prep, dim3(cdiv64(b.N, 256)), dim3(256), 0, s, g, b.ion_xyz, b.ion_q, b.N, b.ion_frac, b.ion_fx,
-                     fp32);
-}
-
 // ============================================================ structure factors
-// S(k) = sum_j q_j exp(i k.r_j), Eq. (15).  One thread per mode, the particle loop
-// is uniform across the wave (particle data arrive by scalar loads).  Grid:
-// (mode tiles of 256, particle chunks, replicas); partial sums per chunk are
-// combined in a fixed order by k_sf_finalize.
-template <bool ION>
-__global__ __launch_bounds__(256) void k_sf64(Geom g, const int64_t* __restrict__ off, int n_fixed,
-                                              const double* __restrict__ fr, int64_t nstride,
-                                              const double* __restrict__ q, const int4* __restrict__ modes,
-                                              double2* __restrict__ part, int nchunk) {
-  const int r = blockIdx.z;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  int64_t b, e;
-  if (ION) {
-    b = off[r];
-    e = off[r + 1];
-  } else {
-    b = 0;
-    e = n_fixed;
-  }
-  const int64_t chunk = (e - b + nchunk - 1) / nchunk;
-  const int64_t j0 = b + (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = min(e, j0 + chunk);
-  const double* qq = ION ? q : q + (size_t)r * n_fixed;
+// S(k) = sum_j q_j exp(i k.r_j), Eq. (15).  One thread per mode; the particle loop
+// is uniform across the wave, so particle records arrive by scalar loads.  Grid:
+// (mode tiles of 256, particle chunks, replicas); each block writes partial sums
+// and k_sf_finalize adds them in chunk order and writes S, the coefficients w S
+// and (FP32) the mode records.  stage 1: ions, S1.  stage 2: electrodes with the
+// new charges, S = S1 + S2.  (A last-arriving-block reduction would need an
+// agent-scope release fence per block, which writes back L2 and costs far more
+// than the extra launch on a multi-XCD device.)
+__device__ __forceinline__ void finalize_tile(const Geom& g, int r, int k, const double2* part, int nchunk,
+                                              const int4* modes, const double* w, double2* S1, double2* coef,
+                                              ModeRec32* rec, int stage, unsigned* status) {
   if (k >= g.K) return;
-  const int4 m = modes[(size_t)r * g.K + k];
-  const double mx = m.x, my = m.y, mz = m.z;
   double sr = 0.0, si = 0.0;
-  for (int64_t j = j0; j < j1; ++j) {
-    double t = fma(mx, fr[j], fma(my, fr[nstride + j], mz * fr[2 * nstride + j]));
-    t -= rint(t);
-    double sn, cs;
-    sincospi(2.0 * t, &sn, &cs);
-    const double qj = ION ? qq[j] : qq[j];
-    sr = fma(qj, cs, sr);
-    si = fma(qj, sn, si);
-  }
-  part[((size_t)r * nchunk + blockIdx.y) * g.K + k] = make_double2(sr, si);
-}
-
-// FP32: exact integer phase, hardware sin/cos of the phase in revolutions, FP32
-// sums over blocks of 64 particles carried in FP64.
-template <bool ION>
-__global__ __launch_bounds__(256) void k_sf32(Geom g, const int64_t* __restrict__ off, int n_fixed,
-                                              const uint4* __restrict__ pts, const float* __restrict__ qe,
-                                              const int4* __restrict__ modes, double2* __restrict__ part, int nchunk) {
-  const int r = blockIdx.z;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  int64_t b, e;
-  if (ION) {
-    b = off[r];
-    e = off[r + 1];
-  } else {
-    b = 0;
-    e = n_fixed;
-  }
-  const int64_t chunk = (e - b + nchunk - 1) / nchunk;
-  const int64_t j0 = b + (int64_t)blockIdx.y * chunk;
-  const int64_t j1 = min(e, j0 + chunk);
-  if (k >= g.K) return;
-  const float* qq = ION ? nullptr : qe + (size_t)r * n_fixed;
-  const int4 m = modes[(size_t)r * g.K + k];
-  const uint32_t mx = (uint32_t)m.x, my = (uint32_t)m.y, mz = (uint32_t)m.z;
-  double dr = 0.0, di = 0.0;
-  for (int64_t jb = j0; jb < j1; jb += 64) {
-    const int64_t je = min(j1, jb + 64);
-    float ar = 0.f, ai = 0.f;
-    for (int64_t j = jb; j < je; ++j) {
-      const uint4 p = pts[j];
-      const float qj = ION ? __uint_as_float(p.w) : qq[j];
-      const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
-      const float x = (float)(int32_t)ph * 0x1.0p-32f;
-      const float sn = __builtin_amdgcn_sinf(x);
-      const float cs = __builtin_amdgcn_cosf(x);
-      ar = fmaf(qj, cs, ar);
-      ai = fmaf(qj, sn, ai);
+  int c = 0;
+  for (; c + 4 <= nchunk; c += 4) {
+    double2 p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[u] = part[((size_t)r * nchunk + c + u) * g.K + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sr += p[u].x;
+      si += p[u].y;
     }
-    dr += (double)ar;
-    di += (double)ai;
   }
-  part[((size_t)r * nchunk + blockIdx.y) * g.K + k] = make_double2(dr, di);
-}
-
-void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (g.K == 0) return;
-  dim3 grid(cdiv64(g.K, 256), b.nchunk_ion, b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_sf32<true>, grid, dim3(256), 0, s, g, b.off, 0, b.ion_fx, (const float*)nullptr, b.modes,
-                       b.part, b.nchunk_ion);
-  else
-    hipLaunchKernelGGL(k_sf64<true>, grid, dim3(256), 0, s, g, b.off, 0, b.ion_frac, b.N, b.ion_q, b.modes, b.part,
-                       b.nchunk_ion);
-}
-
-void launch_sf_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (g.K == 0) return;
-  dim3 grid(cdiv64(g.K, 256), b.nchunk_ele, b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_sf32<false>, grid, dim3(256), 0, s, g, b.off, g.n_ele, b.ele_fx, b.Qf, b.modes, b.part,
-                       b.nchunk_ele);
-  else
-    hipLaunchKernelGGL(k_sf64<false>, grid, dim3(256), 0, s, g, b.off, g.n_ele, b.ele_frac, (int64_t)g.n_ele, b.Q_out,
-                       b.modes, b.part, b.nchunk_ele);
-}
-
-// stage 1: S1 = sum of partials; coef = w S1.  stage 2: S = S1 + sum of partials
-// (electrodes); coef = w S.  The FP32 path also fills the mode records.
-__global__ __launch_bounds__(256) void k_sf_finalize(Geom g, const double2* __restrict__ part, int nchunk,
-                                                     const int4* __restrict__ modes, const double* __restrict__ w,
-                                                     double2* __restrict__ S1, double2* __restrict__ coef,
-                                                     ModeRec32* __restrict__ rec, int stage, unsigned* status) {
-  const int r = blockIdx.y;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= g.K) return;
-  double sr = 0.0, si = 0.0;
-  for (int c = 0; c < nchunk; ++c) {
+  for (; c < nchunk; ++c) {
     const double2 p = part[((size_t)r * nchunk + c) * g.K + k];
     sr += p.x;
     si += p.y;
@@ -429,11 +416,116 @@ __global__ __launch_bounds__(256) void k_sf_finalize(Geom g, const double2* __re
   }
 }
 
-void launch_sf_finalize(const Geom& g, const StepBufs& b, int stage, int fp32, hipStream_t s) {
+template <bool ION>
+__global__ __launch_bounds__(256) void k_sf64(Geom g, const int64_t* __restrict__ off,
+                                              const double4* __restrict__ pts, const double* __restrict__ qe,
+                                              const int4* __restrict__ modes, double2* __restrict__ part,
+                                              int nchunk) {
+  const int r = blockIdx.z;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int b = ION ? (int)off[r] : 0;
+  const int e = ION ? (int)off[r + 1] : g.n_ele;
+  const int chunk = (e - b + nchunk - 1) / nchunk;
+  const int j0 = b + (int)blockIdx.y * chunk;
+  const int j1 = min(e, j0 + chunk);
+  const double* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
+  double sr = 0.0, si = 0.0;
+  if (k < g.K) {
+    const int4 m = modes[(size_t)r * g.K + k];
+    const double mx = m.x, my = m.y, mz = m.z;
+    for (int j = j0; j < j1; ++j) {
+      const double4 p = pts[j];
+      double t = fma(mx, p.x, fma(my, p.y, mz * p.z));
+      t -= rint(t);
+      double sn, cs;
+      sincospi(2.0 * t, &sn, &cs);
+      const double qj = ION ? p.w : qq[j];
+      sr = fma(qj, cs, sr);
+      si = fma(qj, sn, si);
+    }
+    part[((size_t)r * nchunk + blockIdx.y) * g.K + k] = make_double2(sr, si);
+  }
+}
+
+// FP32: exact integer phase m.u mod 2^32 (u = 32-bit fixed-point fractions), the
+// hardware sin/cos of the phase in revolutions, FP32 sums over blocks of 64
+// particles carried in FP64.
+template <bool ION>
+__global__ __launch_bounds__(256) void k_sf32(Geom g, const int64_t* __restrict__ off, const uint4* __restrict__ pts,
+                                              const float* __restrict__ qe, const int4* __restrict__ modes,
+                                              double2* __restrict__ part, int nchunk) {
+  const int r = blockIdx.z;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int b = ION ? (int)off[r] : 0;
+  const int e = ION ? (int)off[r + 1] : g.n_ele;
+  const int chunk = (e - b + nchunk - 1) / nchunk;
+  const int j0 = b + (int)blockIdx.y * chunk;
+  const int j1 = min(e, j0 + chunk);
+  const float* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
+  if (k < g.K) {
+    const int4 m = modes[(size_t)r * g.K + k];
+    const uint32_t mx = (uint32_t)m.x, my = (uint32_t)m.y, mz = (uint32_t)m.z;
+    double dr = 0.0, di = 0.0;
+    for (int jb = j0; jb < j1; jb += 64) {
+      const int je = min(j1, jb + 64);
+      float ar = 0.f, ai = 0.f;
+      int j = jb;
+      for (; j + 4 <= je; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint4 p = pts[j + u];
+          const float qj = ION ? __uint_as_float(p.w) : qq[j + u];
+          const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
+          const float x = (float)(int32_t)ph * 0x1.0p-32f;
+          ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
+          ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
+        }
+      }
+      for (; j < je; ++j) {
+        const uint4 p = pts[j];
+        const float qj = ION ? __uint_as_float(p.w) : qq[j];
+        const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
+        const float x = (float)(int32_t)ph * 0x1.0p-32f;
+        ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
+        ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
+      }
+      dr += (double)ar;
+      di += (double)ai;
+    }
+    part[((size_t)r * nchunk + blockIdx.y) * g.K + k] = make_double2(dr, di);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sf_finalize(Geom g, const double2* __restrict__ part, int nchunk,
+                                                     const int4* __restrict__ modes, const double* __restrict__ w,
+                                                     double2* __restrict__ S1, double2* __restrict__ coef,
+                                                     ModeRec32* __restrict__ rec, int stage, unsigned* status) {
+  finalize_tile(g, blockIdx.y, blockIdx.x * 256 + threadIdx.x, part, nchunk, modes, w, S1, coef, rec, stage, status);
+}
+
+void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (g.K == 0) return;
-  const int nchunk = stage == 1 ? b.nchunk_ion : b.nchunk_ele;
-  hipLaunchKernelGGL(k_sf_finalize, dim3(cdiv64(g.K, 256), b.R), dim3(256), 0, s, g, b.part, nchunk, b.modes, b.w,
-                     b.S1, b.coef, fp32 ? b.rec : nullptr, stage, b.status);
+  dim3 grid(b.ktiles, b.nchunk_ion, b.R);
+  if (fp32)
+    hipLaunchKernelGGL(k_sf32<true>, grid, dim3(256), 0, s, g, b.off, b.ion_fx, (const float*)nullptr, b.modes, b.part,
+                       b.nchunk_ion);
+  else
+    hipLaunchKernelGGL(k_sf64<true>, grid, dim3(256), 0, s, g, b.off, b.ion_d4, (const double*)nullptr, b.modes,
+                       b.part, b.nchunk_ion);
+  hipLaunchKernelGGL(k_sf_finalize, dim3(b.ktiles, b.R), dim3(256), 0, s, g, b.part, b.nchunk_ion, b.modes, b.w, b.S1,
+                     b.coef, fp32 ? b.rec : nullptr, 1, b.status);
+}
+
+void launch_sf_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (g.K == 0) return;
+  dim3 grid(b.ktiles, b.nchunk_ele, b.R);
+  if (fp32)
+    hipLaunchKernelGGL(k_sf32<false>, grid, dim3(256), 0, s, g, b.off, b.ele_fx, b.Qf, b.modes, b.part, b.nchunk_ele);
+  else
+    hipLaunchKernelGGL(k_sf64<false>, grid, dim3(256), 0, s, g, b.off, b.ele_d4, b.Q_out, b.modes, b.part,
+                       b.nchunk_ele);
+  hipLaunchKernelGGL(k_sf_finalize, dim3(b.ktiles, b.R), dim3(256), 0, s, g, b.part, b.nchunk_ele, b.modes, b.w, b.S1,
+                     b.coef, fp32 ? b.rec : nullptr, 2, b.status);
 }
 
 // ============================================================ real-space kernels
@@ -445,82 +537,302 @@ __device__ __forceinline__ void erfc_over_r(double a, double r, double& f, doubl
   df = -e * inv * inv - 2.0 * a * INV_SQRT_PI * exp(-(a * r) * (a * r)) * inv;
 }
 
-__device__ __forceinline__ void erfc_over_r_f(float a, float r, float& f, float& df) {
-  const float e = erfcf(a * r);
-  const float inv = 1.0f / r;
-  f = e * inv;
-  df = -e * inv * inv - 2.0f * a * (float)INV_SQRT_PI * __expf(-(a * r) * (a * r)) * inv;
+// FP32 pair kernel: with x = a r, f = erfc(x) / r and h = -(1/r) d/dr [erfc(x) / r]
+// = (f + (2a / sqrt(pi)) exp(-x^2)) / r^2.  erfc(x) = exp(-x^2) t p(t) with
+// t = 1 / (1 + x/2), p of degree 9 fitted to the scaled complementary error function
+// (coefficients from fit_erfc.py beside this file; relative error 3.3e-7 in FP32 on
+// x in [0, 10], beyond which erfc underflows FP32).  One exp serves both terms.
+__device__ __forceinline__ void erfc_pair_f(float a, float r, float rinv, float& f, float& h) {
+  const float x = a * r;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+  float p = 1.228336431e-02f;
+  p = fmaf(p, t, -1.232539415e-01f);
+  p = fmaf(p, t, 4.289312065e-01f);
+  p = fmaf(p, t, -6.700319052e-01f);
+  p = fmaf(p, t, 4.212864637e-01f);
+  p = fmaf(p, t, -9.832625091e-02f);
+  p = fmaf(p, t, 2.255454361e-01f);
+  p = fmaf(p, t, 2.386439592e-01f);
+  p = fmaf(p, t, 2.828571498e-01f);
+  p = fmaf(p, t, 2.820644975e-01f);
+  const float e = __builtin_amdgcn_exp2f(-x * x * 1.4426950408889634f);  // exp(-x^2)
+  f = e * t * p * rinv;
+  h = fmaf(2.0f * (float)INV_SQRT_PI * a, e, f) * (rinv * rinv);
+}
+
+// Four lanes per particle share its neighbour list (lane p takes every fourth
+// candidate of each cell, so the four lanes read consecutive records); their partial
+// sums are combined with a butterfly, which gives every lane the same value.
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
+
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
+
+// Neighbour scan with hit compaction.  Lanes walk their candidates (every fourth
+// record of each cell of the stencil, from offset `part`) in lockstep rounds with
+// only the cheap distance test, four candidates per lane per round so that four
+// independent loads are in flight; candidates closer than rc are queued in the
+// lane's LDS slots, and when any lane's queue is nearly full every lane of the
+// wave evaluates its queued pairs, kBatch at a time: the records of a batch are
+// fetched together (so their loads overlap), then evaluated.  The expensive pair
+// terms (erfc, exp) thus run only for real neighbours.  Each lane handles its
+// pairs in candidate order.  Cell ranges come from `range`, which reads LDS copies
+// of the cell starts.  A lane with fewer queued pairs than the batch fetches
+// record 0 in their place and drops the result: record 0 exists whenever any lane
+// of the wave has a pair, since every queued index is a valid record.
+constexpr int kHitSlots = 20;
+constexpr int kUnroll = 4;
+constexpr int kBatch = 4;
+
+template <class RangeF, class TestF, class FetchF, class EvalF>
+__device__ __forceinline__ void scan_cells(const int* __restrict__ nb, bool live, int part, int* __restrict__ q,
+                                           RangeF range, TestF test, FetchF fetch, EvalF eval) {
+  const int tid = threadIdx.x;
+  int s = 0, j = 0, jend = 0, cnt = 0;
+  // nb: the home cell's neighbour cells, -1 terminated (at most kNbMax)
+  auto advance = [&]() {
+    while (j >= jend && s < kNbMax) {
+      const int c = nb[s];
+      if (c < 0) {
+        s = kNbMax;
+        break;
+      }
+      int b, e;
+      range(c, b, e);
+      j = b + part;
+      jend = e;
+      ++s;
+    }
+  };
+  auto flush = [&]() {
+    for (int h = 0; __any(h < cnt); h += kBatch) {
+      decltype(fetch(0)) rec[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) rec[u] = fetch(h + u < cnt ? q[(h + u) * 256 + tid] : 0);
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (h + u < cnt) eval(rec[u]);
+    }
+    cnt = 0;
+  };
+  if (live) advance();
+  while (__any(j < jend)) {
+    if (j < jend) {
+      bool hitu[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int ju = j + 4 * u;
+        hitu[u] = test(ju < jend ? ju : j) && ju < jend;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (hitu[u]) q[(cnt++) * 256 + tid] = j + 4 * u;
+      j += 4 * kUnroll;
+      if (j >= jend) advance();
+    }
+    if (__any(cnt > kHitSlots - kUnroll)) flush();
+  }
+  flush();
+}
+
+// LDS copy of a table of ncell + 1 cell starts (falls back to global memory for
+// grids larger than the copy).
+__device__ __forceinline__ const int* stage_cells(const int* __restrict__ src, int ncell, int* lds) {
+  if (ncell + 1 > kMaxCells + 1) return src;
+  for (int c = threadIdx.x; c <= ncell; c += blockDim.x) lds[c] = src[c];
+  __syncthreads();
+  return lds;
+}
+
+// Real-space potential of the ions at each electrode, visiting the ions of the
+// neighbouring cells: bN_j = ke sum_i q_i [erfc(alpha r) - erfc(r/eta)]/r, r < rc.
+// In FP32 the erfc(r/eta) term is not evaluated beyond eta_skip, where it is below
+// 2^-30 of the kept term.
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_real_ele(Geom g, const int64_t* __restrict__ off,
+                                                  const int* __restrict__ cstart, const uint4* __restrict__ sfx,
+                                                  const double4* __restrict__ sd4, const int* __restrict__ ele_perm,
+                                                  const int* __restrict__ ele_scell, const int* __restrict__ nbr,
+                                                  const uint4* __restrict__ ele_sfx,
+                                                  const double4* __restrict__ ele_sd4, double* __restrict__ bN) {
+  __shared__ int q[kHitSlots * 256];
+  __shared__ int cs_lds[kMaxCells + 1];
+  const int r = blockIdx.y;
+  const int e = blockIdx.x * 64 + (threadIdx.x >> 2);
+  const int part = threadIdx.x & 3;
+  const bool live = e < g.n_ele;
+  const int b0 = (int)off[r];
+  const int* cs = stage_cells(cstart + (size_t)r * (g.ncell + 1), g.ncell, cs_lds);
+  const int* nb = nbr + kNbMax * (live ? ele_scell[e] : 0);
+  auto range = [&](int c, int& b, int& en) {
+    b = b0 + cs[c];
+    en = b0 + cs[c + 1];
+  };
+  double sum = 0.0;
+  if (FP32) {
+    const uint4 pe = live ? ele_sfx[e] : make_uint4(0, 0, 0, 0);
+    const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
+    const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
+    float acc = 0.f;
+    auto delta = [&](const uint4& p, float& dx, float& dy, float& dz) {
+      dx = (float)(int32_t)(pe.x - p.x) * lx;
+      dy = (float)(int32_t)(pe.y - p.y) * ly;
+      dz = (float)(int32_t)(pe.z - p.z) * lz;
+    };
+    scan_cells(nb, live, part, q, range,
+               [&](int k) {
+                 float dx, dy, dz;
+                 delta(sfx[k], dx, dy, dz);
+                 return dx * dx + dy * dy + dz * dz < rc2;
+               },
+               [&](int k) { return sfx[k]; },
+               [&](const uint4& p) {
+                 float dx, dy, dz;
+                 delta(p, dx, dy, dz);
+                 const float r2 = dx * dx + dy * dy + dz * dz;
+                 const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+                 float f1, h1, f2 = 0.f, h2;
+                 erfc_pair_f(a1, rr, rinv, f1, h1);
+                 if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+                 acc = fmaf(__uint_as_float(p.w), f1 - f2, acc);
+               });
+    sum = (double)quad_sum(acc);
+  } else {
+    const double4 pe = live ? ele_sd4[e] : make_double4(0, 0, 0, 0);
+    const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
+    auto delta = [&](const double4& p, double& dx, double& dy, double& dz) {
+      double sx = pe.x - p.x, sy = pe.y - p.y;
+      sx -= rint(sx);
+      sy -= rint(sy);
+      dx = sx * g.Lx;
+      dy = sy * g.Ly;
+      dz = (pe.z - p.z) * g.Lz;
+    };
+    scan_cells(nb, live, part, q, range,
+               [&](int k) {
+                 double dx, dy, dz;
+                 delta(sd4[k], dx, dy, dz);
+                 return dx * dx + dy * dy + dz * dz < rc2;
+               },
+               [&](int k) { return sd4[k]; },
+               [&](const double4& p) {
+                 double dx, dy, dz;
+                 delta(p, dx, dy, dz);
+                 const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+                 double f1, d1, f2, dd2;
+                 erfc_over_r(a, rr, f1, d1);
+                 erfc_over_r(ai, rr, f2, dd2);
+                 sum += p.w * (f1 - f2);
+               });
+    sum = quad_sum(sum);
+  }
+  if (live && part == 0) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
+}
+
+void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  dim3 grid(cdiv64(g.n_ele, 64), b.R);
+  if (fp32)
+    hipLaunchKernelGGL(k_real_ele<true>, grid, dim3(256), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_perm,
+                       b.ele_scell, b.nbr, b.ele_sfx, b.ele_sd4, b.bN);
+  else
+    hipLaunchKernelGGL(k_real_ele<false>, grid, dim3(256), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_perm,
+                       b.ele_scell, b.nbr, b.ele_sfx, b.ele_sd4, b.bN);
+}
+
+// The force and potential passes: 64 particles per block, the mode list split
+// into four quarters, one per wave (so each wave still walks a uniform mode list),
+// and the four partial results added in wave order through LDS.
+__device__ __forceinline__ void quarter(int K, int& lo, int& hi) {
+  const int q = (K + 3) / 4;
+  const int w = threadIdx.x >> 6;
+  lo = min(K, w * q);
+  hi = min(K, lo + q);
 }
 
 // ============================================================ electrode potential b*
-// b*_j = -sum_k Re(coef_k exp(-i k.R_j))                     (Eq. (24), coef = w S1)
-//        - (4 pi ke / V) Z_j sum_i q_i z_i                    (slab term, minus sign)
-//        - ke sum_i q_i [erfc(alpha r) - erfc(r/eta)]/r        (real space, r < rc)
+// b*_j = -sum_k Re(coef_k exp(-i k.R_j))           (Eq. (24), coef = w S1)
+//        - (4 pi ke / V) Z_j sum_i q_i z_i          (slab term, minus sign)
+//        - bN_j                                     (real space)
 // and V_j = b*_j + dpsi d_j, the right-hand side of the charge solve.
-__global__ __launch_bounds__(256) void k_elepot64(Geom g, const int64_t* __restrict__ off,
-                                                  const double* __restrict__ ion_xyz, const double* __restrict__ ion_q,
-                                                  int64_t N, const double* __restrict__ ele_xyz,
-                                                  const double* __restrict__ ele_frac, const double* __restrict__ ele_d,
-                                                  const int4* __restrict__ modes, const double2* __restrict__ coef,
-                                                  const double* __restrict__ scal, const double* __restrict__ dpsi,
+__device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double acc_quarter, double (*sh)[64],
+                                             const double* ele_xyz, const double* ele_d, const double* scal,
+                                             const double* dpsi, const double* bN, double* bstar, double* V) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  sh[w][lane] = acc_quarter;
+  __syncthreads();
+  if (w == 0 && j < g.n_ele) {
+    const double acc = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+    const int n = g.n_ele;
+    const double Z = ele_xyz[2 * n + j];
+    const size_t idx = (size_t)r * n + j;
+    const double b = -acc - (4.0 * M_PI * g.ke / g.V) * Z * scal[4 * r + 2] - bN[idx];
+    bstar[idx] = b;
+    V[idx] = b + dpsi[r] * ele_d[j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_elepot64(Geom g, const double* __restrict__ ele_xyz,
+                                                  const double4* __restrict__ ele_d4,
+                                                  const double* __restrict__ ele_d, const int4* __restrict__ modes,
+                                                  const double2* __restrict__ coef, const double* __restrict__ scal,
+                                                  const double* __restrict__ dpsi, const double* __restrict__ bN,
                                                   double* __restrict__ bstar, double* __restrict__ V) {
+  __shared__ double sh[4][64];
   const int r = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const int n = g.n_ele;
-  if (j >= n) return;
-  const double sx = ele_frac[j], sy = ele_frac[n + j], sz = ele_frac[2 * n + j];
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const double4 p = j < g.n_ele ? ele_d4[j] : make_double4(0, 0, 0, 0);
+  int lo, hi;
+  quarter(g.K, lo, hi);
   double acc = 0.0;
   const int4* mr = modes + (size_t)r * g.K;
   const double2* cr = coef + (size_t)r * g.K;
-  for (int k = 0; k < g.K; ++k) {
+  for (int k = lo; k < hi; ++k) {
     const int4 m = mr[k];
-    double t = fma((double)m.x, sx, fma((double)m.y, sy, (double)m.z * sz));
+    double t = fma((double)m.x, p.x, fma((double)m.y, p.y, (double)m.z * p.z));
     t -= rint(t);
     double sn, cs;
     sincospi(2.0 * t, &sn, &cs);
     const double2 c = cr[k];
     acc = fma(c.x, cs, fma(c.y, sn, acc));
   }
-  const double X = ele_xyz[j], Y = ele_xyz[n + j], Z = ele_xyz[2 * n + j];
-  double b = -acc - (4.0 * M_PI * g.ke / g.V) * Z * scal[4 * r + 2];
-  double real = 0.0;
-  const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
-  for (int64_t i = off[r]; i < off[r + 1]; ++i) {
-    double dx = X - ion_xyz[i], dy = Y - ion_xyz[N + i];
-    const double dz = Z - ion_xyz[2 * N + i];
-    dx -= g.Lx * rint(dx * g.invLx);
-    dy -= g.Ly * rint(dy * g.invLy);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const double rr = sqrt(r2);
-      double f1, d1, f2, d2;
-      erfc_over_r(a, rr, f1, d1);
-      erfc_over_r(ai, rr, f2, d2);
-      real += ion_q[i] * (f1 - f2);
-    }
-  }
-  b -= g.ke * real;
-  bstar[(size_t)r * n + j] = b;
-  V[(size_t)r * n + j] = b + dpsi[r] * ele_d[j];
+  elepot_write(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
 }
 
-__global__ __launch_bounds__(256) void k_elepot32(Geom g, const int64_t* __restrict__ off,
-                                                  const uint4* __restrict__ ion_fx, const uint4* __restrict__ ele_fx,
+__global__ __launch_bounds__(256) void k_elepot32(Geom g, const uint4* __restrict__ ele_fx,
                                                   const double* __restrict__ ele_xyz, const double* __restrict__ ele_d,
                                                   const ModeRec32* __restrict__ rec, const double* __restrict__ scal,
-                                                  const double* __restrict__ dpsi, double* __restrict__ bstar,
-                                                  double* __restrict__ V) {
+                                                  const double* __restrict__ dpsi, const double* __restrict__ bN,
+                                                  double* __restrict__ bstar, double* __restrict__ V) {
+  __shared__ double sh[4][64];
   const int r = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const int n = g.n_ele;
-  if (j >= n) return;
-  const uint4 pe = ele_fx[j];
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const uint4 pe = j < g.n_ele ? ele_fx[j] : make_uint4(0, 0, 0, 0);
+  int lo, hi;
+  quarter(g.K, lo, hi);
   const ModeRec32* mr = rec + (size_t)r * g.K;
   double acc = 0.0;
-  for (int kb = 0; kb < g.K; kb += 64) {
-    const int ke_ = min(g.K, kb + 64);
+  for (int kb = lo; kb < hi; kb += 64) {
+    const int ke_ = min(hi, kb + 64);
     float a = 0.f;
-    for (int k = kb; k < ke_; ++k) {
+    int k = kb;
+    for (; k + 4 <= ke_; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const ModeRec32 m = mr[k + u];
+        const uint32_t ph = (uint32_t)m.mx * pe.x + (uint32_t)m.my * pe.y + (uint32_t)m.mz * pe.z;
+        const float x = (float)(int32_t)ph * 0x1.0p-32f;
+        a = fmaf(m.cre, __builtin_amdgcn_cosf(x), a);
+        a = fmaf(m.cim, __builtin_amdgcn_sinf(x), a);
+      }
+    }
+    for (; k < ke_; ++k) {
       const ModeRec32 m = mr[k];
       const uint32_t ph = (uint32_t)m.mx * pe.x + (uint32_t)m.my * pe.y + (uint32_t)m.mz * pe.z;
       const float x = (float)(int32_t)ph * 0x1.0p-32f;
@@ -529,52 +841,31 @@ __global__ __launch_bounds__(256) void k_elepot32(Geom g, const int64_t* __restr
     }
     acc += (double)a;
   }
-  const double Z = ele_xyz[2 * n + j];
-  double b = -acc - (4.0 * M_PI * g.ke / g.V) * Z * scal[4 * r + 2];
-  // real space in FP32 from fixed-point differences (exact periodic wrap in x, y)
-  const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
-  const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
-  float real = 0.f;
-  for (int64_t i = off[r]; i < off[r + 1]; ++i) {
-    const uint4 p = ion_fx[i];
-    const float dx = (float)(int32_t)(pe.x - p.x) * lx;
-    const float dy = (float)(int32_t)(pe.y - p.y) * ly;
-    const float dz = (float)(int32_t)(pe.z - p.z) * lz;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const float rr = sqrtf(r2);
-      float f1, d1, f2, d2;
-      erfc_over_r_f(a1, rr, f1, d1);
-      erfc_over_r_f(a2, rr, f2, d2);
-      real = fmaf(__uint_as_float(p.w), f1 - f2, real);
-    }
-  }
-  b -= g.ke * (double)real;
-  bstar[(size_t)r * n + j] = b;
-  V[(size_t)r * n + j] = b + dpsi[r] * ele_d[j];
+  elepot_write(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
 }
 
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  dim3 grid(cdiv64(g.n_ele, 256), b.R);
+  dim3 grid(cdiv64(g.n_ele, 64), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_elepot32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.ele_fx, b.ele_xyz, b.ele_d, b.rec,
-                       b.scal, b.dpsi, b.bstar, b.V);
+    hipLaunchKernelGGL(k_elepot32, grid, dim3(256), 0, s, g, b.ele_fx, b.ele_xyz, b.ele_d, b.rec, b.scal, b.dpsi,
+                       b.bN, b.bstar, b.V);
   else
-    hipLaunchKernelGGL(k_elepot64, grid, dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.ele_xyz, b.ele_frac,
-                       b.ele_d, b.modes, b.coef, b.scal, b.dpsi, b.bstar, b.V);
+    hipLaunchKernelGGL(k_elepot64, grid, dim3(256), 0, s, g, b.ele_xyz, b.ele_d4, b.ele_d, b.modes, b.coef, b.scal,
+                       b.dpsi, b.bN, b.bstar, b.V);
 }
 
 // ============================================================ after the charge solve
-// Per replica: copy Q (and psibar) out of the GEMM result (or the fixed charges),
-// an FP32 copy of Q for the FP32 passes, and sum Q Z (slab term), d.Q, b*.Q
-// (energy).
+// Per replica: copy Q (and psibar) out of the GEMM result (or the fixed charges);
+// the copies of Q the later passes read (FP32 original order and cell-sorted
+// order); sums of Q Z (slab term), d.Q and b*.Q (energy).
 __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __restrict__ Qext,
                                                       const double* __restrict__ Q_in, const double* __restrict__ ele_xyz,
-                                                      const double* __restrict__ ele_d,
+                                                      const double* __restrict__ ele_d, const int* __restrict__ ele_perm,
                                                       const double* __restrict__ bstar, double* __restrict__ Q_out,
-                                                      float* __restrict__ Qf, double* __restrict__ psibar,
+                                                      float* __restrict__ Qf, float* __restrict__ Qsf,
+                                                      double* __restrict__ Qsd, double* __restrict__ psibar,
                                                       double* __restrict__ rsum, unsigned* status) {
-  __shared__ double sh[3][256];
+  __shared__ double sh[3][4];
   const int r = blockIdx.x;
   const int n = g.n_ele;
   double v[3] = {0.0, 0.0, 0.0};
@@ -588,8 +879,14 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
     v[1] += Qj * ele_d[j];
     v[2] += Qj * bstar[(size_t)r * n + j];
   }
+  for (int k = threadIdx.x; k < n; k += 256) {
+    const int j = ele_perm[k];
+    const double Qj = Q_in ? Q_in[(size_t)r * n + j] : Qext[(size_t)r * (n + 1) + j];
+    if (Qsf) Qsf[(size_t)r * n + k] = (float)Qj;
+    if (Qsd) Qsd[(size_t)r * n + k] = Qj;
+  }
   if (bad) atomicOr(status, ST_NUMERIC);
-  block_sum<3>(v, sh);
+  block_sum<256, 3>(v, sh);
   if (threadIdx.x == 0) {
     rsum[8 * r + 0] = v[0];
     rsum[8 * r + 1] = v[1];
@@ -598,35 +895,53 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
   }
 }
 
-void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s) {
+void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s) {
   hipLaunchKernelGGL(k_post_charges, dim3(b.R), dim3(256), 0, s, g, b.Qext, fixedQ ? b.Q_in : nullptr, b.ele_xyz,
-                     b.ele_d, b.bstar, b.Q_out, b.Qf, b.psibar_out, b.rsum, b.status);
+                     b.ele_d, b.ele_perm, b.bstar, b.Q_out, fp32 ? b.Qf : nullptr, fp32 ? b.Qsf : nullptr,
+                     fp32 ? nullptr : b.Qsd, b.psibar_out, b.rsum, b.status);
 }
 
-// ============================================================ ion forces
-// F_i = -q_i sum_k k Im(coef_k exp(-i k.r_i))     (Eq. (25), coef = w (S1 + S2))
-//       - (4 pi ke / V) q_i M_z e_z               (slab force, M_z = sum q z + sum Q Z)
-//       - ke q_i sum_j q_j K_ii'(r) r^/ - ke q_i sum_e Q_e K_ig'(r) r^   (real space)
-// phi_i = ke sum_j q_j K_ii(r) (ion-ion real-space potential, for the energy).
+// ============================================================ ion forces, reciprocal part
+// F_i = -q_i sum_k k Im(coef_k exp(-i k.r_i))   (Eq. (25), coef = w (S1 + S2))
+//       - (4 pi ke / V) q_i M_z e_z             (slab force, M_z = sum q z + sum Q Z)
+__device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, bool live, double qi, double gx,
+                                               double gy, double gz, double (*sh)[3][64], const double* scal,
+                                               const double* rsum, int64_t N, double* F) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  sh[w][0][lane] = gx;
+  sh[w][1][lane] = gy;
+  sh[w][2][lane] = gz;
+  __syncthreads();
+  if (w == 0 && live) {
+    double gsum[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gsum[d] = ((sh[0][d][lane] + sh[1][d][lane]) + sh[2][d][lane]) + sh[3][d][lane];
+    F[i] = -qi * gsum[0];
+    F[N + i] = -qi * gsum[1];
+    F[2 * N + i] = -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum[8 * r + 0]);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __restrict__ off,
-                                                    const double* __restrict__ ion_xyz,
-                                                    const double* __restrict__ ion_q,
-                                                    const double* __restrict__ ion_frac, int64_t N,
-                                                    const double* __restrict__ ele_xyz, const double* __restrict__ Q,
+                                                    const double4* __restrict__ ion_d4, int64_t N,
                                                     const int4* __restrict__ modes, const double2* __restrict__ coef,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    double* __restrict__ F, double* __restrict__ phi) {
+                                                    double* __restrict__ F) {
+  __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
-  const int64_t i = b0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= b1) return;
-  const double sx = ion_frac[i], sy = ion_frac[N + i], sz = ion_frac[2 * N + i];
+  const int64_t i = b0 + (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (b0 + (int64_t)blockIdx.x * 64 >= b1) return;  // whole block past this replica's ions
+  const bool live = i < b1;
+  const double4 p = live ? ion_d4[i] : make_double4(0, 0, 0, 0);
+  int lo, hi;
+  quarter(g.K, lo, hi);
   double gx = 0.0, gy = 0.0, gz = 0.0;
   const int4* mr = modes + (size_t)r * g.K;
   const double2* cr = coef + (size_t)r * g.K;
-  for (int k = 0; k < g.K; ++k) {
+  for (int k = lo; k < hi; ++k) {
     const int4 m = mr[k];
-    double t = fma((double)m.x, sx, fma((double)m.y, sy, (double)m.z * sz));
+    double t = fma((double)m.x, p.x, fma((double)m.y, p.y, (double)m.z * p.z));
     t -= rint(t);
     double sn, cs;
     sincospi(2.0 * t, &sn, &cs);
@@ -636,74 +951,29 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
     gy = fma(TWO_PI * (double)m.y * g.invLy, im, gy);
     gz = fma(TWO_PI * (double)m.z * g.invLz, im, gz);
   }
-  const double qi = ion_q[i];
-  double Fx = -qi * gx, Fy = -qi * gy, Fz = -qi * gz;
-  Fz -= (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum[8 * r + 0]);
-  const double X = ion_xyz[i], Y = ion_xyz[N + i], Z = ion_xyz[2 * N + i];
-  const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
-  double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
-  for (int64_t j = b0; j < b1; ++j) {
-    if (j == i) continue;
-    double dx = X - ion_xyz[j], dy = Y - ion_xyz[N + j];
-    const double dz = Z - ion_xyz[2 * N + j];
-    dx -= g.Lx * rint(dx * g.invLx);
-    dy -= g.Ly * rint(dy * g.invLy);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const double rr = sqrt(r2);
-      double f, df;
-      erfc_over_r(a, rr, f, df);
-      const double qj = ion_q[j];
-      ph += qj * f;
-      const double s = -qj * df / rr;
-      fx += s * dx;
-      fy += s * dy;
-      fz += s * dz;
-    }
-  }
-  const int n = g.n_ele;
-  const double* Qr = Q + (size_t)r * n;
-  for (int e = 0; e < n; ++e) {
-    double dx = X - ele_xyz[e], dy = Y - ele_xyz[n + e];
-    const double dz = Z - ele_xyz[2 * n + e];
-    dx -= g.Lx * rint(dx * g.invLx);
-    dy -= g.Ly * rint(dy * g.invLy);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const double rr = sqrt(r2);
-      double f1, d1, f2, d2;
-      erfc_over_r(a, rr, f1, d1);
-      erfc_over_r(ai, rr, f2, d2);
-      const double s = -Qr[e] * (d1 - d2) / rr;
-      fx += s * dx;
-      fy += s * dy;
-      fz += s * dz;
-    }
-  }
-  const double kq = g.ke * qi;
-  F[i] = Fx + kq * fx;
-  F[N + i] = Fy + kq * fy;
-  F[2 * N + i] = Fz + kq * fz;
-  phi[i] = g.ke * ph;
+  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, N, F);
 }
 
 __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __restrict__ off,
                                                     const uint4* __restrict__ ion_fx, int64_t N,
-                                                    const uint4* __restrict__ ele_fx, const float* __restrict__ Qf,
                                                     const ModeRec32* __restrict__ rec,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    double* __restrict__ F, double* __restrict__ phi) {
+                                                    double* __restrict__ F) {
+  __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
-  const int64_t i = b0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= b1) return;
-  const uint4 pi_ = ion_fx[i];
+  const int64_t i = b0 + (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (b0 + (int64_t)blockIdx.x * 64 >= b1) return;  // whole block past this replica's ions
+  const bool live = i < b1;
+  const uint4 pi_ = live ? ion_fx[i] : make_uint4(0, 0, 0, 0);
+  int lo, hi;
+  quarter(g.K, lo, hi);
   const ModeRec32* mr = rec + (size_t)r * g.K;
   double gx = 0.0, gy = 0.0, gz = 0.0;
-  // deterministic modes: k = (0, 0, kz); only the z component
+  // deterministic modes k = (0, 0, kz) in this quarter: only the z component
   {
     float az = 0.f;
-    for (int k = 0; k < g.M; ++k) {
+    for (int k = lo; k < min(hi, g.M); ++k) {
       const ModeRec32 m = mr[k];
       const uint32_t ph = (uint32_t)m.mz * pi_.z;
       const float x = (float)(int32_t)ph * 0x1.0p-32f;
@@ -712,10 +982,23 @@ __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __res
     }
     gz += (double)az;
   }
-  for (int kb = g.M; kb < g.K; kb += 64) {
-    const int ke_ = min(g.K, kb + 64);
+  for (int kb = max(lo, g.M); kb < hi; kb += 64) {
+    const int ke_ = min(hi, kb + 64);
     float ax = 0.f, ay = 0.f, az = 0.f;
-    for (int k = kb; k < ke_; ++k) {
+    int k = kb;
+    for (; k + 4 <= ke_; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const ModeRec32 m = mr[k + u];
+        const uint32_t ph = (uint32_t)m.mx * pi_.x + (uint32_t)m.my * pi_.y + (uint32_t)m.mz * pi_.z;
+        const float x = (float)(int32_t)ph * 0x1.0p-32f;
+        const float im = m.cim * __builtin_amdgcn_cosf(x) - m.cre * __builtin_amdgcn_sinf(x);
+        ax = fmaf(m.kx, im, ax);
+        ay = fmaf(m.ky, im, ay);
+        az = fmaf(m.kz, im, az);
+      }
+    }
+    for (; k < ke_; ++k) {
       const ModeRec32 m = mr[k];
       const uint32_t ph = (uint32_t)m.mx * pi_.x + (uint32_t)m.my * pi_.y + (uint32_t)m.mz * pi_.z;
       const float x = (float)(int32_t)ph * 0x1.0p-32f;
@@ -728,65 +1011,230 @@ __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __res
     gy += (double)ay;
     gz += (double)az;
   }
-  const double qi = (double)__uint_as_float(pi_.w);
-  double Fx = -qi * gx, Fy = -qi * gy, Fz = -qi * gz;
-  Fz -= (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum[8 * r + 0]);
-  const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
-  const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
-  float fx = 0.f, fy = 0.f, fz = 0.f, ph = 0.f;
-  for (int64_t j = b0; j < b1; ++j) {
-    const uint4 p = ion_fx[j];
-    const float dx = (float)(int32_t)(pi_.x - p.x) * lx;
-    const float dy = (float)(int32_t)(pi_.y - p.y) * ly;
-    const float dz = (float)(int32_t)(pi_.z - p.z) * lz;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2 && j != i) {
-      const float rr = sqrtf(r2);
-      float f, df;
-      erfc_over_r_f(a1, rr, f, df);
-      const float qj = __uint_as_float(p.w);
-      ph = fmaf(qj, f, ph);
-      const float s = -qj * df / rr;
-      fx = fmaf(s, dx, fx);
-      fy = fmaf(s, dy, fy);
-      fz = fmaf(s, dz, fz);
-    }
-  }
-  const int n = g.n_ele;
-  const float* Qr = Qf + (size_t)r * n;
-  for (int e = 0; e < n; ++e) {
-    const uint4 p = ele_fx[e];
-    const float dx = (float)(int32_t)(pi_.x - p.x) * lx;
-    const float dy = (float)(int32_t)(pi_.y - p.y) * ly;
-    const float dz = (float)(int32_t)(pi_.z - p.z) * lz;
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < rc2) {
-      const float rr = sqrtf(r2);
-      float f1, d1, f2, d2;
-      erfc_over_r_f(a1, rr, f1, d1);
-      erfc_over_r_f(a2, rr, f2, d2);
-      const float s = -Qr[e] * (d1 - d2) / rr;
-      fx = fmaf(s, dx, fx);
-      fy = fmaf(s, dy, fy);
-      fz = fmaf(s, dz, fz);
-    }
-  }
-  const double kq = g.ke * qi;
-  F[i] = Fx + kq * (double)fx;
-  F[N + i] = Fy + kq * (double)fy;
-  F[2 * N + i] = Fz + kq * (double)fz;
-  phi[i] = g.ke * (double)ph;
+  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, N, F);
 }
 
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
-  dim3 grid(cdiv64(b.max_nrep, 256), b.R);
+  dim3 grid(cdiv64(b.max_nrep, 64), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.ele_fx, b.Qf, b.rec, b.scal,
-                       b.rsum, b.F_out, b.phi);
+    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum, b.F_out);
   else
-    hipLaunchKernelGGL(k_ionforce64, grid, dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.ion_frac, b.N, b.ele_xyz,
-                       b.Q_out, b.modes, b.coef, b.scal, b.rsum, b.F_out, b.phi);
+    hipLaunchKernelGGL(k_ionforce64, grid, dim3(256), 0, s, g, b.off, b.ion_d4, b.N, b.modes, b.coef, b.scal, b.rsum,
+                       b.F_out);
+}
+
+// ============================================================ ion forces, real space
+// F_i += -ke q_i sum_j q_j K_ii'(r) r^ - ke q_i sum_e Q_e K_ig'(r) r^ over the
+// neighbouring cells (r < rc), phi_i = ke sum_j q_j K_ii(r) (for the energy).
+// Four lanes per cell-sorted ion (see quad_sum); results go to the ion's input
+// position.  An electrode cell whose z-extent lies farther than rc from the ion
+// cannot hold a partner and is skipped.
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restrict__ off, int64_t N,
+                                                  const int* __restrict__ cstart, const int* __restrict__ perm,
+                                                  const int* __restrict__ scell, const int* __restrict__ nbr,
+                                                  const uint4* __restrict__ sfx,
+                                                  const double4* __restrict__ sd4, const int* ele_cstart,
+                                                  const double2* __restrict__ ele_czr,
+                                                  const uint4* __restrict__ ele_sfx,
+                                                  const double4* __restrict__ ele_sd4, const float* __restrict__ Qsf,
+                                                  const double* __restrict__ Qsd, double* __restrict__ F,
+                                                  double* __restrict__ phi) {
+  __shared__ int q[kHitSlots * 256];
+  __shared__ int cs_lds[kMaxCells + 1];
+  __shared__ int ecs_lds[kMaxCells + 1];
+  const int r = blockIdx.y;
+  const int b0 = (int)off[r], b1 = (int)off[r + 1];
+  const int k = b0 + blockIdx.x * 64 + (threadIdx.x >> 2);
+  if (b0 + (int)blockIdx.x * 64 >= b1) return;  // whole block past this replica's ions
+  const int part = threadIdx.x & 3;
+  const bool live = k < b1;
+  const int* cs = stage_cells(cstart + (size_t)r * (g.ncell + 1), g.ncell, cs_lds);
+  ele_cstart = stage_cells(ele_cstart, g.ncell, ecs_lds);
+  const int* nb = nbr + kNbMax * (live ? scell[k] : 0);
+  const int n = g.n_ele;
+  const double zlim = g.rc + 1e-6;  // skip test margin (fixed-point z is exact to ~1e-8 of the box)
+  auto ion_range = [&](int c, int& b, int& e) {
+    b = b0 + cs[c];
+    e = b0 + cs[c + 1];
+  };
+  double fx, fy, fz, ph, qi;
+  if (FP32) {
+    const uint4 pi_ = live ? sfx[k] : make_uint4(0, 0, 0, 0);
+    const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
+    const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
+    const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
+    const float* Qr = Qsf + (size_t)r * n;
+    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+    auto delta = [&](const uint4& p, float& dx, float& dy, float& dz) {
+      dx = (float)(int32_t)(pi_.x - p.x) * lx;
+      dy = (float)(int32_t)(pi_.y - p.y) * ly;
+      dz = (float)(int32_t)(pi_.z - p.z) * lz;
+    };
+    scan_cells(nb, live, part, q, ion_range,
+               [&](int j) {
+                 float dx, dy, dz;
+                 delta(sfx[j], dx, dy, dz);
+                 return dx * dx + dy * dy + dz * dz < rc2 && j != k;
+               },
+               [&](int j) { return sfx[j]; },
+               [&](const uint4& p) {
+                 float dx, dy, dz;
+                 delta(p, dx, dy, dz);
+                 const float r2 = dx * dx + dy * dy + dz * dz;
+                 const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+                 float f, h;
+                 erfc_pair_f(a1, rr, rinv, f, h);
+                 const float qj = __uint_as_float(p.w);
+                 ap = fmaf(qj, f, ap);
+                 const float s_ = qj * h;
+                 ax = fmaf(s_, dx, ax);
+                 ay = fmaf(s_, dy, ay);
+                 az = fmaf(s_, dz, az);
+               });
+    // electrode records carry the electrode's charge in place of w
+    scan_cells(nb, live, part, q,
+               [&](int c, int& b, int& e) {
+                 const double2 zr = ele_czr[c];
+                 b = ele_cstart[c];
+                 e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[c + 1];
+               },
+               [&](int j) {
+                 float dx, dy, dz;
+                 delta(ele_sfx[j], dx, dy, dz);
+                 return dx * dx + dy * dy + dz * dz < rc2;
+               },
+               [&](int j) {
+                 uint4 p = ele_sfx[j];
+                 p.w = __float_as_uint(Qr[j]);
+                 return p;
+               },
+               [&](const uint4& p) {
+                 float dx, dy, dz;
+                 delta(p, dx, dy, dz);
+                 const float r2 = dx * dx + dy * dy + dz * dz;
+                 const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+                 float f1, h1, f2, h2 = 0.f;
+                 erfc_pair_f(a1, rr, rinv, f1, h1);
+                 if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+                 const float s_ = __uint_as_float(p.w) * (h1 - h2);
+                 ax = fmaf(s_, dx, ax);
+                 ay = fmaf(s_, dy, ay);
+                 az = fmaf(s_, dz, az);
+               });
+    fx = quad_sum(ax);
+    fy = quad_sum(ay);
+    fz = quad_sum(az);
+    ph = quad_sum(ap);
+    qi = (double)__uint_as_float(pi_.w);
+  } else {
+    const double4 pi_ = live ? sd4[k] : make_double4(0, 0, 0, 0);
+    const double zi = pi_.z * g.Lz;
+    const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
+    const double* Qr = Qsd + (size_t)r * n;
+    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
+    auto delta = [&](const double4& p, double& dx, double& dy, double& dz) {
+      double sx = pi_.x - p.x, sy = pi_.y - p.y;
+      sx -= rint(sx);
+      sy -= rint(sy);
+      dx = sx * g.Lx;
+      dy = sy * g.Ly;
+      dz = (pi_.z - p.z) * g.Lz;
+    };
+    scan_cells(nb, live, part, q, ion_range,
+               [&](int j) {
+                 double dx, dy, dz;
+                 delta(sd4[j], dx, dy, dz);
+                 return dx * dx + dy * dy + dz * dz < rc2 && j != k;
+               },
+               [&](int j) { return sd4[j]; },
+               [&](const double4& p) {
+                 double dx, dy, dz;
+                 delta(p, dx, dy, dz);
+                 const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+                 double f, df;
+                 erfc_over_r(a, rr, f, df);
+                 ap += p.w * f;
+                 const double s_ = -p.w * df / rr;
+                 ax += s_ * dx;
+                 ay += s_ * dy;
+                 az += s_ * dz;
+               });
+    scan_cells(nb, live, part, q,
+               [&](int c, int& b, int& e) {
+                 const double2 zr = ele_czr[c];
+                 b = ele_cstart[c];
+                 e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[c + 1];
+               },
+               [&](int j) {
+                 double dx, dy, dz;
+                 delta(ele_sd4[j], dx, dy, dz);
+                 return dx * dx + dy * dy + dz * dz < rc2;
+               },
+               [&](int j) {
+                 double4 p = ele_sd4[j];
+                 p.w = Qr[j];
+                 return p;
+               },
+               [&](const double4& p) {
+                 double dx, dy, dz;
+                 delta(p, dx, dy, dz);
+                 const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+                 double f1, d1, f2, d2;
+                 erfc_over_r(a, rr, f1, d1);
+                 erfc_over_r(ai, rr, f2, d2);
+                 const double s_ = -p.w * (d1 - d2) / rr;
+                 ax += s_ * dx;
+                 ay += s_ * dy;
+                 az += s_ * dz;
+               });
+    fx = quad_sum(ax);
+    fy = quad_sum(ay);
+    fz = quad_sum(az);
+    ph = quad_sum(ap);
+    qi = pi_.w;
+  }
+  if (live && part == 0) {
+    const int i = perm[k];
+    const double kq = g.ke * qi;
+    F[i] += kq * fx;
+    F[N + i] += kq * fy;
+    F[2 * N + i] += kq * fz;
+    phi[i] = g.ke * ph;
+  }
+}
+
+void launch_real_ion(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (b.max_nrep == 0) return;
+  dim3 grid(cdiv64(b.max_nrep, 64), b.R);
+  if (fp32)
+    hipLaunchKernelGGL(k_real_ion<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.nbr, b.sfx,
+                       b.sd4, b.ele_cstart, b.ele_czr, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
+  else
+    hipLaunchKernelGGL(k_real_ion<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.nbr,
+                       b.sfx, b.sd4, b.ele_cstart, b.ele_czr, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
+}
+
+// z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
+// empty interval.
+__global__ __launch_bounds__(256) void k_cell_zrange(Geom g, const int* __restrict__ cstart,
+                                                     const double* __restrict__ ele_xyz,
+                                                     const int* __restrict__ perm, double2* __restrict__ zr) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= g.ncell) return;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int k = cstart[c]; k < cstart[c + 1]; ++k) {
+    const double z = ele_xyz[2 * g.n_ele + perm[k]];
+    lo = fmin(lo, z);
+    hi = fmax(hi, z);
+  }
+  zr[c] = make_double2(lo, hi);
+}
+
+void launch_cell_zrange(const Geom& g, const int* cstart, const double* ele_xyz, const int* perm, double2* zr,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_zrange, dim3(cdiv64(g.ncell, 256)), dim3(256), 0, s, g, cstart, ele_xyz, perm, zr);
 }
 
 // ============================================================ energy
@@ -799,7 +1247,7 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int64_t* __restric
                                                 const double* __restrict__ scal, const double* __restrict__ rsum,
                                                 const double* __restrict__ dpsi, double* __restrict__ energy,
                                                 int fixedQ, unsigned* status) {
-  __shared__ double sh[2][256];
+  __shared__ double sh[2][4];
   const int r = blockIdx.x;
   double v[2] = {0.0, 0.0};
   for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
@@ -807,7 +1255,7 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int64_t* __restric
     const double2 s = S1[(size_t)r * g.K + k];
     v[1] += w[(size_t)r * g.K + k] * (s.x * s.x + s.y * s.y);
   }
-  block_sum<2>(v, sh);
+  block_sum<256, 2>(v, sh);
   if (threadIdx.x == 0) {
     const double c = 0.5 * v[0] + 0.5 * v[1] - g.ke * g.alpha * INV_SQRT_PI * scal[4 * r + 3] +
                      g.ke * (2.0 * M_PI / g.V) * scal[4 * r + 2] * scal[4 * r + 2];
