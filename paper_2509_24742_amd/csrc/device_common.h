@@ -34,7 +34,10 @@ struct Geom {
 
 constexpr int kMaxBinParticles = 8192;  // particles per replica the one-block cell sort handles
 constexpr int kMaxCells = 2048;
-constexpr int kNbMax = 63;  // neighbour cells per cell: 3 x 3 x (2 nzs + 1) with nzs <= 3
+// Neighbour runs per cell: the cells within reach of a cell, sorted, as runs of
+// consecutive cell indices (whose particles are adjacent in the cell-sorted order).
+// At most 7 z-layers (nzs <= 3) x 3 rows x 2 pieces (a periodic wrap splits a row).
+constexpr int kRunMax = 42;
 
 // Cell of a position (x, y wrapped by the caller into fractions sx, sy in [0,1)).
 __device__ __forceinline__ int cell_index(const Geom& g, double sx, double sy, double z) {

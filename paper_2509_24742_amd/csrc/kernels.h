@@ -37,7 +37,9 @@ struct StepBufs {
   const int* ele_scell;     // cell of each sorted electrode
   const int* ele_cstart;    // ncell + 1
   const double2* ele_czr;   // ncell: z-extent of the electrodes of each cell
-  const int* nbr;           // ncell x kNbMax neighbour cells of each cell, -1 terminated
+  const int2* ion_runs;     // ncell x kRunMax neighbour runs [c0, c1), merged across z; c0 = -1 ends
+  const int2* ele_runs;     // ncell x kRunMax neighbour runs split by z-layer (electrode side)
+  const double2* ele_run_zr;  // ncell x kRunMax z-extent of the electrodes of each ele_runs entry
   const uint4* ele_sfx;     // sorted fixed point
   const double4* ele_sd4;   // sorted fractional coordinates
   // workspace

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/srbe.h"
@@ -30,7 +31,9 @@ struct srbe_system {
   int* ele_scell = nullptr;    // cell of each sorted electrode
   int* ele_cstart = nullptr;   // ncell + 1
   double2* ele_czr = nullptr;  // ncell: z-extent of each cell's electrodes
-  int* nbr = nullptr;          // ncell x kNbMax neighbour cells, -1 terminated
+  int2* ion_runs = nullptr;    // ncell x kRunMax neighbour runs, merged across z-layers
+  int2* ele_runs = nullptr;    // ncell x kRunMax neighbour runs, one z-layer each
+  double2* ele_run_zr = nullptr;  // ncell x kRunMax electrode z-extent of each ele_runs entry
   uint4* ele_sfx = nullptr;    // sorted fixed point
   double4* ele_sd4 = nullptr;  // sorted fractional coordinates
   double* Sext = nullptr;
@@ -365,7 +368,7 @@ void srbe_destroy(srbe_system* h) {
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   if (h->aux) (void)hipStreamDestroy(h->aux);
   void* bufs[] = {h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
-                  h->ele_czr, h->nbr,    h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
+                  h->ele_czr, h->ion_runs, h->ele_runs, h->ele_run_zr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -417,7 +420,9 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ele_scell, n * sizeof(int));
     al((void**)&h->ele_cstart, (size_t)(g.ncell + 1) * sizeof(int));
     al((void**)&h->ele_czr, (size_t)g.ncell * sizeof(double2));
-    al((void**)&h->nbr, (size_t)g.ncell * kNbMax * sizeof(int));
+    al((void**)&h->ion_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
+    al((void**)&h->ele_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
+    al((void**)&h->ele_run_zr, (size_t)g.ncell * kRunMax * sizeof(double2));
     al((void**)&h->ele_sfx, n * sizeof(uint4));
     al((void**)&h->ele_sd4, n * sizeof(double4));
     al((void**)&h->status, sizeof(unsigned));
@@ -429,8 +434,11 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     }
     const int64_t h_off[2] = {0, n_ele};
     // neighbour cells of every cell: 3 x 3 in x, y (periodic; an axis with fewer than 3
-    // cells contributes each of its cells once) times cz - nzs .. cz + nzs, clipped in z
-    std::vector<int> nb((size_t)g.ncell * kNbMax, -1);
+    // cells contributes each of its cells once) times cz - nzs .. cz + nzs, clipped in z;
+    // sorted and cut into runs of consecutive cell indices, once merged across z-layers
+    // (ion side) and once per z-layer (electrode side, which is skipped by z-extent)
+    std::vector<int2> iruns((size_t)g.ncell * kRunMax, make_int2(-1, -1));
+    std::vector<int2> eruns((size_t)g.ncell * kRunMax, make_int2(-1, -1));
     for (int c = 0; c < g.ncell; ++c) {
       const int cx = c % g.ncx, cy = (c / g.ncx) % g.ncy, cz = c / (g.ncx * g.ncy);
       std::vector<int> xs, ys;
@@ -438,15 +446,30 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
       else for (int x = 0; x < g.ncx; ++x) xs.push_back(x);
       if (g.ncy >= 3) ys = {(cy + g.ncy - 1) % g.ncy, cy, (cy + 1) % g.ncy};
       else for (int y = 0; y < g.ncy; ++y) ys.push_back(y);
-      int k = 0;
+      std::vector<int> cells;
       for (int z = std::max(0, cz - g.nzs); z <= std::min(g.ncz - 1, cz + g.nzs); ++z)
         for (int y : ys)
-          for (int x : xs) nb[(size_t)c * kNbMax + k++] = (z * g.ncy + y) * g.ncx + x;
+          for (int x : xs) cells.push_back((z * g.ncy + y) * g.ncx + x);
+      std::sort(cells.begin(), cells.end());
+      const int layer = g.ncx * g.ncy;
+      int ni = 0, ne = 0;
+      for (size_t u = 0; u < cells.size(); ++u) {
+        const int cc = cells[u];
+        if (ni > 0 && iruns[(size_t)c * kRunMax + ni - 1].y == cc)
+          iruns[(size_t)c * kRunMax + ni - 1].y = cc + 1;
+        else
+          iruns[(size_t)c * kRunMax + ni++] = make_int2(cc, cc + 1);
+        if (ne > 0 && eruns[(size_t)c * kRunMax + ne - 1].y == cc && (cc - 1) / layer == cc / layer)
+          eruns[(size_t)c * kRunMax + ne - 1].y = cc + 1;
+        else
+          eruns[(size_t)c * kRunMax + ne++] = make_int2(cc, cc + 1);
+      }
     }
     if (hipMemcpy(h->ele_xyz, ele_xyz, 3 * n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->ele_d, d.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(off2, h_off, sizeof(h_off), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->nbr, nb.data(), nb.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ion_runs, iruns.data(), iruns.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ele_runs, eruns.data(), eruns.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) {
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
@@ -454,11 +477,22 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     launch_bin_electrodes(g, off2, h->ele_xyz, n_ele, h->ele_fx, h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
                           h->ele_sfx, h->ele_sd4, h->status, s);
     launch_cell_zrange(g, h->ele_cstart, h->ele_xyz, h->ele_perm, h->ele_czr, s);
-    if (hipDeviceSynchronize() != hipSuccess) {
+    std::vector<double2> czr(g.ncell);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(czr.data(), h->ele_czr, czr.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess) {
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
     }
     (void)hipFree(off2);
+    // z-extent of the electrodes of each electrode-side run (empty: an empty interval)
+    std::vector<double2> rzr(eruns.size(), make_double2(INFINITY, -INFINITY));
+    for (size_t u = 0; u < eruns.size(); ++u)
+      for (int cc = eruns[u].x; eruns[u].x >= 0 && cc < eruns[u].y; ++cc) {
+        rzr[u].x = std::min(rzr[u].x, czr[cc].x);
+        rzr[u].y = std::max(rzr[u].y, czr[cc].y);
+      }
+    if (hipMemcpy(h->ele_run_zr, rzr.data(), rzr.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(SRBE_EHIP);
   }
   if (rocblas_create_handle(&h->blas) != rocblas_status_success) return fail(SRBE_EHIP);
   if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
@@ -634,7 +668,9 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   b.ele_scell = h->ele_scell;
   b.ele_cstart = h->ele_cstart;
   b.ele_czr = h->ele_czr;
-  b.nbr = h->nbr;
+  b.ion_runs = h->ion_runs;
+  b.ele_runs = h->ele_runs;
+  b.ele_run_zr = h->ele_run_zr;
   b.ele_sfx = h->ele_sfx;
   b.ele_sd4 = h->ele_sd4;
   b.nchunk_ion = nch_ion;

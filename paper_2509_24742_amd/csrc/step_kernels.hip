@@ -11,6 +11,8 @@
 // bitwise-identical results.
 #include <math.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace srbe {
@@ -20,6 +22,8 @@ static inline int cdiv64(int64_t a, int64_t b) { return (int)((a + b - 1) / b); 
 #define TWO_PI 6.283185307179586
 #define INV_SQRT_PI 0.5641895835477563
 
+// Sum over the 64 lanes of a wave by an xor butterfly: every lane ends with the same
+// value, added in the same order on every run.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -560,198 +564,198 @@ __device__ __forceinline__ void erfc_pair_f(float a, float r, float rinv, float&
   h = fmaf(2.0f * (float)INV_SQRT_PI * a, e, f) * (rinv * rinv);
 }
 
-// Four lanes per particle share its neighbour list (lane p takes every fourth
-// candidate of each cell, so the four lanes read consecutive records); their partial
-// sums are combined with a butterfly, which gives every lane the same value.
-__device__ __forceinline__ float quad_sum(float v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
+// FP32 wave sum (the FP64 one is at the top of this file).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-__device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  return v;
+// Lanes below this one with their bit set in m.
+__device__ __forceinline__ unsigned lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// Neighbour scan with hit compaction.  Lanes walk their candidates (every fourth
-// record of each cell of the stencil, from offset `part`) in lockstep rounds with
-// only the cheap distance test, four candidates per lane per round so that four
-// independent loads are in flight; candidates closer than rc are queued in the
-// lane's LDS slots, and when any lane's queue is nearly full every lane of the
-// wave evaluates its queued pairs, kBatch at a time: the records of a batch are
-// fetched together (so their loads overlap), then evaluated.  The expensive pair
-// terms (erfc, exp) thus run only for real neighbours.  Each lane handles its
-// pairs in candidate order.  Cell ranges come from `range`, which reads LDS copies
-// of the cell starts.  A lane with fewer queued pairs than the batch fetches
-// record 0 in their place and drops the result: record 0 exists whenever any lane
-// of the wave has a pair, since every queued index is a valid record.
-constexpr int kHitSlots = 20;
-constexpr int kUnroll = 4;
-constexpr int kBatch = 4;
+// Neighbour scan of ONE particle by a whole wave.  The candidates are the records of
+// the particle's neighbour runs (runs of consecutive cells, -1 terminated, at most
+// kRunMax; range(s, run, b, e) turns run s into a record range [b, e), empty if the
+// run can be skipped).  A wave round tests 64 candidates, one per lane (coalesced
+// loads): inside a run a round is 64 consecutive records; the remainder of a run
+// is topped up with the heads of the following runs (up to kSegMax pieces), so
+// short runs do not leave lanes idle.  test(j, entry) loads record j, fills the
+// pair entry and says whether the pair is within range (evaluated branch-free:
+// every lane of a round holds a valid j).  The hits of a round are appended in
+// candidate order to a wave-private LDS ring (positions from a ballot and a lane
+// prefix count; lanes without a hit write to their own slot past the ring, so the
+// store needs no branch).  Whenever 64 entries are queued every lane evaluates one;
+// the rest are evaluated at the end.  The ring holds at most 63 + 64 entries, so
+// kRing = 128 never overflows.  All control flow is wave-uniform; each lane
+// accumulates its share and the caller reduces them with wave_sum, so the result
+// does not depend on timing.
+constexpr int kRing = 128;
+constexpr int kRingAlloc = kRing + 64;  // ring + one discard slot per lane
+constexpr int kSegMax = 4;
 
-template <class RangeF, class TestF, class FetchF, class EvalF>
-__device__ __forceinline__ void scan_cells(const int* __restrict__ nb, bool live, int part, int* __restrict__ q,
-                                           RangeF range, TestF test, FetchF fetch, EvalF eval) {
-  const int tid = threadIdx.x;
-  int s = 0, j = 0, jend = 0, cnt = 0;
-  // nb: the home cell's neighbour cells, -1 terminated (at most kNbMax)
-  auto advance = [&]() {
-    while (j >= jend && s < kNbMax) {
-      const int c = nb[s];
-      if (c < 0) {
-        s = kNbMax;
+template <class Entry, class RangeF, class TestF, class EvalF>
+__device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* __restrict__ ring, RangeF range,
+                                          TestF test, EvalF eval) {
+  const int lane = threadIdx.x & 63;
+  int s = 0, pos = 0, end = 0;
+  unsigned head = 0, tail = 0;
+  auto next_run = [&]() {
+    while (pos >= end && s < kRunMax) {
+      const int2 rc = runs[s];
+      if (rc.x < 0) {
+        s = kRunMax;
         break;
       }
-      int b, e;
-      range(c, b, e);
-      j = b + part;
-      jend = e;
+      range(s, rc, pos, end);
       ++s;
     }
+    return pos < end;
   };
-  auto flush = [&]() {
-    for (int h = 0; __any(h < cnt); h += kBatch) {
-      decltype(fetch(0)) rec[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) rec[u] = fetch(h + u < cnt ? q[(h + u) * 256 + tid] : 0);
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u)
-        if (h + u < cnt) eval(rec[u]);
+  auto round = [&](int j, bool valid) {
+    Entry ent;
+    const bool hit = test(j, ent) & valid;
+    const uint64_t m = __ballot(hit);
+    const unsigned slot = hit ? ((tail + lanes_below(m)) & (kRing - 1)) : (unsigned)(kRing + lane);
+    ring[slot] = ent;
+    tail += (unsigned)__popcll(m);
+    if (tail - head >= 64) {
+      __builtin_amdgcn_wave_barrier();
+      eval(ring[(head + lane) & (kRing - 1)]);
+      head += 64;
     }
-    cnt = 0;
   };
-  if (live) advance();
-  while (__any(j < jend)) {
-    if (j < jend) {
-      bool hitu[kUnroll];
+  while (next_run()) {
+    while (end - pos >= 64) {
+      round(pos + lane, true);
+      pos += 64;
+    }
+    if (pos >= end) continue;
+    // the run's remainder (< 64 records), topped up from the following runs:
+    // lanes [from[u], from[u+1]) take records lane + base[u]
+    int base[kSegMax], from[kSegMax];
+    int filled = end - pos;
+    base[0] = pos;
+    from[0] = 0;
+    pos = end;
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int ju = j + 4 * u;
-        hitu[u] = test(ju < jend ? ju : j) && ju < jend;
+    for (int u = 1; u < kSegMax; ++u) {
+      base[u] = 0;
+      from[u] = 64;
+      if (filled < 64 && next_run()) {
+        const int take = min(64 - filled, end - pos);
+        base[u] = pos - filled;
+        from[u] = filled;
+        filled += take;
+        pos += take;
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-        if (hitu[u]) q[(cnt++) * 256 + tid] = j + 4 * u;
-      j += 4 * kUnroll;
-      if (j >= jend) advance();
     }
-    if (__any(cnt > kHitSlots - kUnroll)) flush();
+    int j = lane + base[0];
+#pragma unroll
+    for (int u = 1; u < kSegMax; ++u)
+      if (lane >= from[u]) j = lane + base[u];
+    const bool valid = lane < filled;
+    round(valid ? j : base[0], valid);  // lane 0 always holds a valid record
   }
-  flush();
-}
-
-// LDS copy of a table of ncell + 1 cell starts (falls back to global memory for
-// grids larger than the copy).
-__device__ __forceinline__ const int* stage_cells(const int* __restrict__ src, int ncell, int* lds) {
-  if (ncell + 1 > kMaxCells + 1) return src;
-  for (int c = threadIdx.x; c <= ncell; c += blockDim.x) lds[c] = src[c];
-  __syncthreads();
-  return lds;
+  __builtin_amdgcn_wave_barrier();
+  if ((unsigned)lane < tail - head) eval(ring[(head + lane) & (kRing - 1)]);
 }
 
 // Real-space potential of the ions at each electrode, visiting the ions of the
 // neighbouring cells: bN_j = ke sum_i q_i [erfc(alpha r) - erfc(r/eta)]/r, r < rc.
-// In FP32 the erfc(r/eta) term is not evaluated beyond eta_skip, where it is below
-// 2^-30 of the kept term.
+// One wave per cell-sorted electrode.  In FP32 the erfc(r/eta) term is not
+// evaluated beyond eta_skip, where it is below 2^-30 of the kept term.
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_real_ele(Geom g, const int64_t* __restrict__ off,
                                                   const int* __restrict__ cstart, const uint4* __restrict__ sfx,
                                                   const double4* __restrict__ sd4, const int* __restrict__ ele_perm,
-                                                  const int* __restrict__ ele_scell, const int* __restrict__ nbr,
+                                                  const int* __restrict__ ele_scell,
+                                                  const int2* __restrict__ ion_runs,
                                                   const uint4* __restrict__ ele_sfx,
                                                   const double4* __restrict__ ele_sd4, double* __restrict__ bN) {
-  __shared__ int q[kHitSlots * 256];
-  __shared__ int cs_lds[kMaxCells + 1];
+  using Entry = typename std::conditional<FP32, float2, double2>::type;
+  __shared__ Entry ring_all[4][kRingAlloc];
   const int r = blockIdx.y;
-  const int e = blockIdx.x * 64 + (threadIdx.x >> 2);
-  const int part = threadIdx.x & 3;
-  const bool live = e < g.n_ele;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int e = blockIdx.x * 4 + w;
+  if (e >= g.n_ele) return;  // whole wave
+  Entry* ring = ring_all[w];
   const int b0 = (int)off[r];
-  const int* cs = stage_cells(cstart + (size_t)r * (g.ncell + 1), g.ncell, cs_lds);
-  const int* nb = nbr + kNbMax * (live ? ele_scell[e] : 0);
-  auto range = [&](int c, int& b, int& en) {
-    b = b0 + cs[c];
-    en = b0 + cs[c + 1];
+  const int* cs = cstart + (size_t)r * (g.ncell + 1);
+  const int2* runs = ion_runs + kRunMax * __builtin_amdgcn_readfirstlane(ele_scell[e]);
+  auto range = [&](int, int2 rc, int& b, int& en) {
+    b = b0 + cs[rc.x];
+    en = b0 + cs[rc.y];
   };
-  double sum = 0.0;
-  if (FP32) {
-    const uint4 pe = live ? ele_sfx[e] : make_uint4(0, 0, 0, 0);
+  double sum;
+  if constexpr (FP32) {
+    const uint4 pe = ele_sfx[e];
     const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
     const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
     float acc = 0.f;
-    auto delta = [&](const uint4& p, float& dx, float& dy, float& dz) {
-      dx = (float)(int32_t)(pe.x - p.x) * lx;
-      dy = (float)(int32_t)(pe.y - p.y) * ly;
-      dz = (float)(int32_t)(pe.z - p.z) * lz;
-    };
-    scan_cells(nb, live, part, q, range,
-               [&](int k) {
-                 float dx, dy, dz;
-                 delta(sfx[k], dx, dy, dz);
-                 return dx * dx + dy * dy + dz * dz < rc2;
-               },
-               [&](int k) { return sfx[k]; },
-               [&](const uint4& p) {
-                 float dx, dy, dz;
-                 delta(p, dx, dy, dz);
-                 const float r2 = dx * dx + dy * dy + dz * dz;
-                 const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
-                 float f1, h1, f2 = 0.f, h2;
-                 erfc_pair_f(a1, rr, rinv, f1, h1);
-                 if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
-                 acc = fmaf(__uint_as_float(p.w), f1 - f2, acc);
-               });
-    sum = (double)quad_sum(acc);
+    wave_scan(runs, ring, range,
+              [&](int j, float2& ent) {
+                const uint4 p = sfx[j];
+                const float dx = (float)(int32_t)(pe.x - p.x) * lx;
+                const float dy = (float)(int32_t)(pe.y - p.y) * ly;
+                const float dz = (float)(int32_t)(pe.z - p.z) * lz;
+                ent = make_float2(dx * dx + dy * dy + dz * dz, __uint_as_float(p.w));
+                return ent.x < rc2;
+              },
+              [&](const float2& en) {
+                const float rinv = __builtin_amdgcn_rsqf(en.x), rr = en.x * rinv;
+                float f1, h1, f2 = 0.f, h2;
+                erfc_pair_f(a1, rr, rinv, f1, h1);
+                if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+                acc = fmaf(en.y, f1 - f2, acc);
+              });
+    sum = (double)wave_sum(acc);
   } else {
-    const double4 pe = live ? ele_sd4[e] : make_double4(0, 0, 0, 0);
+    const double4 pe = ele_sd4[e];
     const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
-    auto delta = [&](const double4& p, double& dx, double& dy, double& dz) {
-      double sx = pe.x - p.x, sy = pe.y - p.y;
-      sx -= rint(sx);
-      sy -= rint(sy);
-      dx = sx * g.Lx;
-      dy = sy * g.Ly;
-      dz = (pe.z - p.z) * g.Lz;
-    };
-    scan_cells(nb, live, part, q, range,
-               [&](int k) {
-                 double dx, dy, dz;
-                 delta(sd4[k], dx, dy, dz);
-                 return dx * dx + dy * dy + dz * dz < rc2;
-               },
-               [&](int k) { return sd4[k]; },
-               [&](const double4& p) {
-                 double dx, dy, dz;
-                 delta(p, dx, dy, dz);
-                 const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-                 double f1, d1, f2, dd2;
-                 erfc_over_r(a, rr, f1, d1);
-                 erfc_over_r(ai, rr, f2, dd2);
-                 sum += p.w * (f1 - f2);
-               });
-    sum = quad_sum(sum);
+    double acc = 0.0;
+    wave_scan(runs, ring, range,
+              [&](int j, double2& ent) {
+                const double4 p = sd4[j];
+                double sx = pe.x - p.x, sy = pe.y - p.y;
+                sx -= rint(sx);
+                sy -= rint(sy);
+                const double dx = sx * g.Lx, dy = sy * g.Ly, dz = (pe.z - p.z) * g.Lz;
+                ent = make_double2(dx * dx + dy * dy + dz * dz, p.w);
+                return ent.x < rc2;
+              },
+              [&](const double2& en) {
+                const double rr = sqrt(en.x);
+                double f1, d1, f2, d2;
+                erfc_over_r(a, rr, f1, d1);
+                erfc_over_r(ai, rr, f2, d2);
+                acc += en.y * (f1 - f2);
+              });
+    sum = wave_sum(acc);
   }
-  if (live && part == 0) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
+  if ((threadIdx.x & 63) == 0) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
 }
 
 void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  dim3 grid(cdiv64(g.n_ele, 64), b.R);
+  if (g.n_ele == 0) return;
+  dim3 grid(cdiv64(g.n_ele, 4), b.R);
   if (fp32)
     hipLaunchKernelGGL(k_real_ele<true>, grid, dim3(256), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_perm,
-                       b.ele_scell, b.nbr, b.ele_sfx, b.ele_sd4, b.bN);
+                       b.ele_scell, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
   else
     hipLaunchKernelGGL(k_real_ele<false>, grid, dim3(256), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_perm,
-                       b.ele_scell, b.nbr, b.ele_sfx, b.ele_sd4, b.bN);
+                       b.ele_scell, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
 }
 
 // The force and potential passes: 64 particles per block, the mode list split
-// into four quarters, one per wave (so each wave still walks a uniform mode list),
-// and the four partial results added in wave order through LDS.
+// into four quarters, one per wave (so each wave still walks a uniform mode list:
+// the wave index is made explicitly uniform so that the mode records are read
+// with scalar loads), and the four partial results added in wave order through LDS.
 __device__ __forceinline__ void quarter(int K, int& lo, int& hi) {
   const int q = (K + 3) / 4;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   lo = min(K, w * q);
   hi = min(K, lo + q);
 }
@@ -1027,175 +1031,157 @@ void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s)
 // ============================================================ ion forces, real space
 // F_i += -ke q_i sum_j q_j K_ii'(r) r^ - ke q_i sum_e Q_e K_ig'(r) r^ over the
 // neighbouring cells (r < rc), phi_i = ke sum_j q_j K_ii(r) (for the energy).
-// Four lanes per cell-sorted ion (see quad_sum); results go to the ion's input
-// position.  An electrode cell whose z-extent lies farther than rc from the ion
-// cannot hold a partner and is skipped.
+// One wave per cell-sorted ion (see wave_scan); results go to the ion's input
+// position.  An electrode run (one z-layer) whose z-extent lies farther than rc
+// from the ion cannot hold a partner and is skipped.
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restrict__ off, int64_t N,
                                                   const int* __restrict__ cstart, const int* __restrict__ perm,
-                                                  const int* __restrict__ scell, const int* __restrict__ nbr,
+                                                  const int* __restrict__ scell,
+                                                  const int2* __restrict__ ion_runs,
+                                                  const int2* __restrict__ ele_runs,
+                                                  const double2* __restrict__ ele_run_zr,
                                                   const uint4* __restrict__ sfx,
-                                                  const double4* __restrict__ sd4, const int* ele_cstart,
-                                                  const double2* __restrict__ ele_czr,
+                                                  const double4* __restrict__ sd4, const int* __restrict__ ele_cstart,
                                                   const uint4* __restrict__ ele_sfx,
                                                   const double4* __restrict__ ele_sd4, const float* __restrict__ Qsf,
                                                   const double* __restrict__ Qsd, double* __restrict__ F,
                                                   double* __restrict__ phi) {
-  __shared__ int q[kHitSlots * 256];
-  __shared__ int cs_lds[kMaxCells + 1];
-  __shared__ int ecs_lds[kMaxCells + 1];
+  using Entry = typename std::conditional<FP32, float4, double4>::type;
+  __shared__ Entry ring_all[4][kRingAlloc];
   const int r = blockIdx.y;
   const int b0 = (int)off[r], b1 = (int)off[r + 1];
-  const int k = b0 + blockIdx.x * 64 + (threadIdx.x >> 2);
-  if (b0 + (int)blockIdx.x * 64 >= b1) return;  // whole block past this replica's ions
-  const int part = threadIdx.x & 3;
-  const bool live = k < b1;
-  const int* cs = stage_cells(cstart + (size_t)r * (g.ncell + 1), g.ncell, cs_lds);
-  ele_cstart = stage_cells(ele_cstart, g.ncell, ecs_lds);
-  const int* nb = nbr + kNbMax * (live ? scell[k] : 0);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int k = b0 + blockIdx.x * 4 + w;
+  if (k >= b1) return;  // whole wave
+  Entry* ring = ring_all[w];
+  const int* cs = cstart + (size_t)r * (g.ncell + 1);
+  const int home = __builtin_amdgcn_readfirstlane(scell[k]);
+  const int2* iruns = ion_runs + kRunMax * home;
+  const int2* eruns = ele_runs + kRunMax * home;
+  const double2* erz = ele_run_zr + kRunMax * home;
   const int n = g.n_ele;
   const double zlim = g.rc + 1e-6;  // skip test margin (fixed-point z is exact to ~1e-8 of the box)
-  auto ion_range = [&](int c, int& b, int& e) {
-    b = b0 + cs[c];
-    e = b0 + cs[c + 1];
+  auto ion_range = [&](int, int2 rc, int& b, int& e) {
+    b = b0 + cs[rc.x];
+    e = b0 + cs[rc.y];
   };
   double fx, fy, fz, ph, qi;
-  if (FP32) {
-    const uint4 pi_ = live ? sfx[k] : make_uint4(0, 0, 0, 0);
+  if constexpr (FP32) {
+    const uint4 pi_ = sfx[k];
     const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
+    auto ele_range = [&](int si, int2 rc, int& b, int& e) {
+      const double2 zr = erz[si];
+      b = ele_cstart[rc.x];
+      e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[rc.y];
+    };
     const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
     const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
     const float* Qr = Qsf + (size_t)r * n;
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
-    auto delta = [&](const uint4& p, float& dx, float& dy, float& dz) {
-      dx = (float)(int32_t)(pi_.x - p.x) * lx;
-      dy = (float)(int32_t)(pi_.y - p.y) * ly;
-      dz = (float)(int32_t)(pi_.z - p.z) * lz;
-    };
-    scan_cells(nb, live, part, q, ion_range,
-               [&](int j) {
-                 float dx, dy, dz;
-                 delta(sfx[j], dx, dy, dz);
-                 return dx * dx + dy * dy + dz * dz < rc2 && j != k;
-               },
-               [&](int j) { return sfx[j]; },
-               [&](const uint4& p) {
-                 float dx, dy, dz;
-                 delta(p, dx, dy, dz);
-                 const float r2 = dx * dx + dy * dy + dz * dz;
-                 const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
-                 float f, h;
-                 erfc_pair_f(a1, rr, rinv, f, h);
-                 const float qj = __uint_as_float(p.w);
-                 ap = fmaf(qj, f, ap);
-                 const float s_ = qj * h;
-                 ax = fmaf(s_, dx, ax);
-                 ay = fmaf(s_, dy, ay);
-                 az = fmaf(s_, dz, az);
-               });
-    // electrode records carry the electrode's charge in place of w
-    scan_cells(nb, live, part, q,
-               [&](int c, int& b, int& e) {
-                 const double2 zr = ele_czr[c];
-                 b = ele_cstart[c];
-                 e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[c + 1];
-               },
-               [&](int j) {
-                 float dx, dy, dz;
-                 delta(ele_sfx[j], dx, dy, dz);
-                 return dx * dx + dy * dy + dz * dz < rc2;
-               },
-               [&](int j) {
-                 uint4 p = ele_sfx[j];
-                 p.w = __float_as_uint(Qr[j]);
-                 return p;
-               },
-               [&](const uint4& p) {
-                 float dx, dy, dz;
-                 delta(p, dx, dy, dz);
-                 const float r2 = dx * dx + dy * dy + dz * dz;
-                 const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
-                 float f1, h1, f2, h2 = 0.f;
-                 erfc_pair_f(a1, rr, rinv, f1, h1);
-                 if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
-                 const float s_ = __uint_as_float(p.w) * (h1 - h2);
-                 ax = fmaf(s_, dx, ax);
-                 ay = fmaf(s_, dy, ay);
-                 az = fmaf(s_, dz, az);
-               });
-    fx = quad_sum(ax);
-    fy = quad_sum(ay);
-    fz = quad_sum(az);
-    ph = quad_sum(ap);
+    wave_scan(iruns, ring, ion_range,
+              [&](int j, float4& ent) {
+                const uint4 p = sfx[j];
+                ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
+                ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
+                ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
+                ent.w = __uint_as_float(p.w);
+                return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
+              },
+              [&](const float4& en) {
+                const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
+                const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+                float f, h;
+                erfc_pair_f(a1, rr, rinv, f, h);
+                ap = fmaf(en.w, f, ap);
+                const float s_ = en.w * h;
+                ax = fmaf(s_, en.x, ax);
+                ay = fmaf(s_, en.y, ay);
+                az = fmaf(s_, en.z, az);
+              });
+    wave_scan(eruns, ring, ele_range,
+              [&](int j, float4& ent) {
+                const uint4 p = ele_sfx[j];
+                ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
+                ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
+                ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
+                ent.w = Qr[j];
+                return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+              },
+              [&](const float4& en) {
+                const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
+                const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+                float f1, h1, f2, h2 = 0.f;
+                erfc_pair_f(a1, rr, rinv, f1, h1);
+                if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+                const float s_ = en.w * (h1 - h2);
+                ax = fmaf(s_, en.x, ax);
+                ay = fmaf(s_, en.y, ay);
+                az = fmaf(s_, en.z, az);
+              });
+    fx = (double)wave_sum(ax);
+    fy = (double)wave_sum(ay);
+    fz = (double)wave_sum(az);
+    ph = (double)wave_sum(ap);
     qi = (double)__uint_as_float(pi_.w);
   } else {
-    const double4 pi_ = live ? sd4[k] : make_double4(0, 0, 0, 0);
+    const double4 pi_ = sd4[k];
     const double zi = pi_.z * g.Lz;
+    auto ele_range = [&](int si, int2 rc, int& b, int& e) {
+      const double2 zr = erz[si];
+      b = ele_cstart[rc.x];
+      e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[rc.y];
+    };
     const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
     const double* Qr = Qsd + (size_t)r * n;
     double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
-    auto delta = [&](const double4& p, double& dx, double& dy, double& dz) {
+    auto delta = [&](const double4& p, double4& ent) {
       double sx = pi_.x - p.x, sy = pi_.y - p.y;
       sx -= rint(sx);
       sy -= rint(sy);
-      dx = sx * g.Lx;
-      dy = sy * g.Ly;
-      dz = (pi_.z - p.z) * g.Lz;
+      ent.x = sx * g.Lx;
+      ent.y = sy * g.Ly;
+      ent.z = (pi_.z - p.z) * g.Lz;
+      return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
     };
-    scan_cells(nb, live, part, q, ion_range,
-               [&](int j) {
-                 double dx, dy, dz;
-                 delta(sd4[j], dx, dy, dz);
-                 return dx * dx + dy * dy + dz * dz < rc2 && j != k;
-               },
-               [&](int j) { return sd4[j]; },
-               [&](const double4& p) {
-                 double dx, dy, dz;
-                 delta(p, dx, dy, dz);
-                 const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-                 double f, df;
-                 erfc_over_r(a, rr, f, df);
-                 ap += p.w * f;
-                 const double s_ = -p.w * df / rr;
-                 ax += s_ * dx;
-                 ay += s_ * dy;
-                 az += s_ * dz;
-               });
-    scan_cells(nb, live, part, q,
-               [&](int c, int& b, int& e) {
-                 const double2 zr = ele_czr[c];
-                 b = ele_cstart[c];
-                 e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[c + 1];
-               },
-               [&](int j) {
-                 double dx, dy, dz;
-                 delta(ele_sd4[j], dx, dy, dz);
-                 return dx * dx + dy * dy + dz * dz < rc2;
-               },
-               [&](int j) {
-                 double4 p = ele_sd4[j];
-                 p.w = Qr[j];
-                 return p;
-               },
-               [&](const double4& p) {
-                 double dx, dy, dz;
-                 delta(p, dx, dy, dz);
-                 const double rr = sqrt(dx * dx + dy * dy + dz * dz);
-                 double f1, d1, f2, d2;
-                 erfc_over_r(a, rr, f1, d1);
-                 erfc_over_r(ai, rr, f2, d2);
-                 const double s_ = -p.w * (d1 - d2) / rr;
-                 ax += s_ * dx;
-                 ay += s_ * dy;
-                 az += s_ * dz;
-               });
-    fx = quad_sum(ax);
-    fy = quad_sum(ay);
-    fz = quad_sum(az);
-    ph = quad_sum(ap);
+    wave_scan(iruns, ring, ion_range,
+              [&](int j, double4& ent) {
+                const double4 p = sd4[j];
+                ent.w = p.w;
+                return delta(p, ent) & (j != k);
+              },
+              [&](const double4& en) {
+                const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
+                double f, df;
+                erfc_over_r(a, rr, f, df);
+                ap += en.w * f;
+                const double s_ = -en.w * df / rr;
+                ax += s_ * en.x;
+                ay += s_ * en.y;
+                az += s_ * en.z;
+              });
+    wave_scan(eruns, ring, ele_range,
+              [&](int j, double4& ent) {
+                ent.w = Qr[j];
+                return delta(ele_sd4[j], ent);
+              },
+              [&](const double4& en) {
+                const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
+                double f1, d1, f2, d2;
+                erfc_over_r(a, rr, f1, d1);
+                erfc_over_r(ai, rr, f2, d2);
+                const double s_ = -en.w * (d1 - d2) / rr;
+                ax += s_ * en.x;
+                ay += s_ * en.y;
+                az += s_ * en.z;
+              });
+    fx = wave_sum(ax);
+    fy = wave_sum(ay);
+    fz = wave_sum(az);
+    ph = wave_sum(ap);
     qi = pi_.w;
   }
-  if (live && part == 0) {
+  if ((threadIdx.x & 63) == 0) {
     const int i = perm[k];
     const double kq = g.ke * qi;
     F[i] += kq * fx;
@@ -1207,13 +1193,13 @@ __global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restr
 
 void launch_real_ion(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
-  dim3 grid(cdiv64(b.max_nrep, 64), b.R);
+  dim3 grid(cdiv64(b.max_nrep, 4), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_real_ion<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.nbr, b.sfx,
-                       b.sd4, b.ele_cstart, b.ele_czr, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
+    hipLaunchKernelGGL(k_real_ion<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
+                       b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
   else
-    hipLaunchKernelGGL(k_real_ion<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.nbr,
-                       b.sfx, b.sd4, b.ele_cstart, b.ele_czr, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
+    hipLaunchKernelGGL(k_real_ion<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
+                       b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
