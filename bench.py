@@ -30,12 +30,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 LANE_OPS_PEAK = 256 * 64 * 2.4e9  # VALU lane-ops per second: 256 CUs x 64 lanes x 2.4 GHz
+FP64_PEAK = 78.6e12                # FP64 MFMA FLOP/s
 
-# VALU slot-equivalents per (particle, mode) pair for the FP32 k-space passes: exact
-# integer phase (3 multiplies + 1 three-way add), int->float + scale (2), sin and cos
-# of the phase (2 instructions issuing at half rate: 4 slots), then the accumulation:
-# structure factor 2 FMA; electrode potential 2 FMA; force 2 (Im part) + 3 FMA.
-SLOTS = {"sf_ions": 12, "sf_ele": 12, "ele_potential": 12, "ion_force": 15}
+# Algorithmic VALU slots per unit of work of each FP32 kernel (a transcendental --
+# sin, cos, exp, rsqrt, rcp -- issues at quarter rate and counts 4 slots; sin/cos
+# at half rate, 2).  k-space passes, per (particle, mode) pair: exact integer phase
+# (3 multiplies + 1 three-way add), int->float + scale (2), sin and cos (4), then
+# the accumulation: structure factor 2 FMA; electrode potential 2 FMA; force
+# 2 (Im part) + 3 FMA.  Real-space passes, per pair closer than rc: fixed-point
+# difference (3 sub, 3 convert, 3 scale), r^2 (3), rsqrt (4), r and alpha r (2),
+# t = 1/(1 + x/2) (1 + 4), the degree-9 polynomial (9), exp(-x^2) (2 + 4), erfc/r (3),
+# then ion-ion: the force factor (3), potential (1), force (1 + 3) = 49; ion-
+# electrode force: 48 (no potential); electrode potential: r^2 from the
+# difference (9 + 3), rsqrt, r, x, t, polynomial, exp, erfc/r (30) and 1 FMA = 43.
+SLOTS = {"sf_ions": 12, "sf_ele": 12, "ele_potential": 12, "ion_force": 15,
+         "real_ii": 49, "real_ie": 48, "real_ele": 43}
 
 
 def log(msg):
@@ -89,6 +98,8 @@ def main():
 
     out = None
     stream = torch.cuda.current_stream()
+    log("counting real-space pairs ...")
+    npair_ii, npair_ie = count_pairs(wb, wp)
 
     def run(steps, first, prec, offs, x, qq, dp, sd, o):
         for i in range(steps):
@@ -109,9 +120,29 @@ def main():
             raise RuntimeError(srbe_amd.srbe_last_error(sysm.h))
         return e0.elapsed_time(e1) / args.steps, o
 
-    # ---- headline: FP32, all replicas in one step
-    ms_fp32, out = timed(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
-    log(f"FP32 batch: {ms_fp32 * 1e3:.1f} us/step")
+    def timed_graph(prec, offs, x, qq, dp, sd):
+        gr = sysm.capture(offs, x, qq, dp, sd, 0, precision=prec, want_kset=False)
+        for _ in range(args.warmup):
+            gr.launch()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            gr.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        code = srbe_amd.srbe_sync_status(sysm.h)
+        if code != 0:
+            raise RuntimeError(srbe_amd.srbe_last_error(sysm.h))
+        gr.close()
+        return e0.elapsed_time(e1) / args.steps
+
+    # ---- headline: FP32, all replicas in one step, replayed as a captured graph
+    ms_fp32 = timed_graph(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
+    log(f"FP32 batch (graph): {ms_fp32 * 1e3:.1f} us/step")
+    ms_fp32_eager, out = timed(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
+    log(f"FP32 batch (eager): {ms_fp32_eager * 1e3:.1f} us/step")
 
     # ---- per-phase durations (HIP events recorded by the library on the step's stream)
     srbe_amd.srbe_profile_enable(sysm.h, True)
@@ -126,23 +157,42 @@ def main():
     off1 = np.array([0, sizes[0]], dtype=np.int64)
     xyz1 = torch.tensor(np.ascontiguousarray(wb["ion_pos"][0].T).ravel(), dtype=torch.float64, device=dev)
     q1 = torch.tensor(wb["ion_q"][0], dtype=torch.float64, device=dev)
-    ms_fp64_1, _ = timed(srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
+    ms_fp64_1 = timed_graph(srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
     pairs_1 = (sizes[0] + n_ele) * K
     # FP32 on a single cell, for the batching gain
-    ms_fp32_1, _ = timed(srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
+    ms_fp32_1 = timed_graph(srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
     log(f"single cell: FP64 {ms_fp64_1 * 1e3:.1f} us/step, FP32 {ms_fp32_1 * 1e3:.1f} us/step")
 
-    # ---- roofline of the dominant k-space kernel
-    kpairs = {
+    # ---- roofline of the dominant kernel (longest phase with a roofline figure)
+    units = {
         "sf_ions": sum(sizes) * K,
         "sf_ele": R * n_ele * K,
         "ele_potential": R * n_ele * K,
         "ion_force": sum(sizes) * K,
+        "real_ii": npair_ii,
+        "real_ie": npair_ie,
+        "real_ele": npair_ie,
     }
-    kdom = max((k for k in SLOTS if k in phases), key=lambda k: phases[k]["avg_us"])
-    ach = kpairs[kdom] * SLOTS[kdom] / (phases[kdom]["avg_us"] * 1e-6)
-    roofline = {"bound": "alu", "kernel": kdom, "achieved": ach / 1e12, "peak": LANE_OPS_PEAK / 1e12,
-                "unit": "TVALUop/s", "frac": ach / LANE_OPS_PEAK, "traffic": None}
+    gemm_flop = 2.0 * (n_ele + 1) * n_ele * R
+    cands = [k for k in list(SLOTS) + ["cp_gemm"] if k in phases]
+    kdom = max(cands, key=lambda k: phases[k]["avg_us"])
+    dur = phases[kdom]["avg_us"] * 1e-6
+    if kdom == "cp_gemm":
+        ach = gemm_flop / dur
+        roofline = {"bound": "mfma", "kernel": kdom, "achieved": ach / 1e12, "peak": FP64_PEAK / 1e12,
+                    "unit": "TFLOP/s", "frac": ach / FP64_PEAK, "traffic": None}
+    else:
+        ach = units[kdom] * SLOTS[kdom] / dur
+        roofline = {"bound": "alu", "kernel": kdom, "achieved": ach / 1e12, "peak": LANE_OPS_PEAK / 1e12,
+                    "unit": "TVALUop/s", "frac": ach / LANE_OPS_PEAK, "traffic": None}
+    other = {}
+    for k in cands:
+        d = phases[k]["avg_us"] * 1e-6
+        if k == "cp_gemm":
+            other[k] = {"us": round(d * 1e6, 2), "frac": round(gemm_flop / d / FP64_PEAK, 4), "of": "FP64 MFMA peak"}
+        else:
+            other[k] = {"us": round(d * 1e6, 2), "frac": round(units[k] * SLOTS[k] / d / LANE_OPS_PEAK, 4),
+                        "of": "VALU slot peak"}
     top = max(phases, key=lambda k: phases[k]["avg_us"])
 
     result = {
@@ -168,6 +218,9 @@ def main():
         "fp32_single_cell": {"ms_per_step": ms_fp32_1, "pairs_per_s": pairs_1 / (ms_fp32_1 * 1e-3)},
         "speedup_vs_fp64_plain_pairs_per_s": (pairs_per_step / ms_fp32) / (pairs_1 / ms_fp64_1),
         "roofline": roofline,
+        "kernel_rooflines": other,
+        "ms_per_step_eager": ms_fp32_eager,
+        "real_space_pairs_per_step": {"ion_ion_ordered": npair_ii, "ion_electrode": npair_ie},
         "phases_us": {k: round(v["avg_us"], 2) for k, v in phases.items()},
         "slowest_phase": top,
         "setup_s": setup_s,
@@ -181,6 +234,32 @@ def main():
         result.update(cpu_side(wb, wp, acc, R, sizes, n_ele, K))
     print(json.dumps(result), flush=True)
     sysm.close()
+
+
+def count_pairs(wb, wp):
+    """Ordered ion-ion pairs and ion-electrode pairs closer than rc (minimum image in x, y), summed over replicas."""
+    Lx, Ly, rc2 = wp["Lx"], wp["Ly"], wp["rc"] ** 2
+    ele = np.asarray(wb["ele_pos"], dtype=np.float64)
+
+    def count(a, b, same):
+        tot = 0
+        for i0 in range(0, len(a), 256):
+            d = a[i0:i0 + 256, None, :] - b[None, :, :]
+            d[..., 0] -= Lx * np.rint(d[..., 0] / Lx)
+            d[..., 1] -= Ly * np.rint(d[..., 1] / Ly)
+            m = (d * d).sum(-1) < rc2
+            if same:
+                idx = np.arange(i0, min(i0 + 256, len(a)))
+                m[idx - i0, idx] = False
+            tot += int(m.sum())
+        return tot
+
+    nii = nie = 0
+    for pos in wb["ion_pos"]:
+        pos = np.asarray(pos, dtype=np.float64)
+        nii += count(pos, pos, True)
+        nie += count(pos, ele, False)
+    return nii, nie
 
 
 def cpu_side(wb, wp, acc, R, sizes, n_ele, K):

@@ -135,6 +135,29 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
               double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, void* stream);
 
 /*
+ * Captured steps.  srbe_graph_create records one srbe_step with fixed arguments
+ * (the same meaning and checks as srbe_step, all device pointers kept by the
+ * graph) into a HIP graph with its own workspace; srbe_graph_launch replays it on
+ * any stream as one launch.  The sample of a replay is fixed by (seed, step) as in
+ * srbe_step, where step comes from a device counter: first_step for the first
+ * replay, advanced by one at the end of every replay, and reset by
+ * srbe_graph_set_step (enqueued on the given stream).  The buffers passed at
+ * creation must stay allocated, and their contents are read and written at each
+ * replay.  Replays on one graph must not overlap in time (they share the
+ * workspace); the graph must be destroyed before its handle.  Errors:
+ * SRBE_EINVAL, SRBE_ENOMEM, SRBE_EHIP; device-data errors via srbe_sync_status.
+ */
+typedef struct srbe_graph srbe_graph;
+int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                      const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
+                      uint64_t first_step, const int32_t* kset_in, const double* Q_in, double* Q_out,
+                      double* F_out, double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out,
+                      srbe_graph** out);
+int srbe_graph_launch(srbe_graph* g, void* stream);
+int srbe_graph_set_step(srbe_graph* g, uint64_t step, void* stream);
+void srbe_graph_destroy(srbe_graph* g);
+
+/*
  * srbe_sample -- only the sampler of a step (Sec. 3, Eqs. (26)-(29)): writes the
  * n_rep*P*3 int32 modes the step with the same (seed, step) would use.
  * seed device n_rep uint64; kset_out device.  Returns SRBE_EINVAL on bad arguments.
@@ -151,14 +174,17 @@ int srbe_sync_status(srbe_system* h);
 
 /*
  * Per-phase timing (tracing).  When enabled, every later srbe_step records a HIP
- * event before and after each of its SRBE_N_PHASES phases on the step's stream;
- * srbe_profile_read waits for them and returns, per phase, the summed duration in
- * milliseconds and the number of launches since the last read (then resets).
- * Phases, in order: replica_scalars, sample, prep, sf_ions, finalize_ions,
- * ele_potential, cp_gemm, post_charges, sf_ele, finalize_ele, ion_force, energy.
- * srbe_phase_name(i) returns the name of phase i.
+ * event before and after each of its phases on the stream that runs it (the step
+ * is a small graph of kernels over the caller's stream and two internal streams,
+ * so phases of different streams overlap); srbe_profile_read waits for them and
+ * returns, per phase, the summed duration in milliseconds and the number of
+ * launches since the last read (then resets).  Phases, in order: records, sample,
+ * sf_ions, cellsort, real_ele, real_ii, ele_potential, cp_gemm, post_charges,
+ * sf_ele, ion_force, real_ie, energy; the remaining slots are unused ("").
+ * srbe_phase_name(i) returns the name of phase i.  Captured steps (srbe_graph_*)
+ * record no phase events.
  */
-#define SRBE_N_PHASES 12
+#define SRBE_N_PHASES 16
 int srbe_profile_enable(srbe_system* h, int32_t enable);
 int srbe_profile_read(srbe_system* h, double* ms_out /*host [SRBE_N_PHASES]*/,
                       int64_t* launches_out /*host [SRBE_N_PHASES]*/);

@@ -11,7 +11,8 @@ import numpy as np
 
 from . import binding
 from .binding import (SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
-                      srbe_error_string, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
+                      srbe_error_string, srbe_graph_create, srbe_graph_destroy, srbe_graph_launch,
+                      srbe_graph_set_step, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
                       srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status)
 
 
@@ -35,25 +36,69 @@ class System:
         except Exception:
             pass
 
-    def step(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, precision=SRBE_FP64, kset_in=None, Q_in=None,
-             want_b=True, want_kset=True, out=None, stream=None):
-        """Run one step; returns a dict of CUDA tensors (Q, F, b, psibar, E, kset)."""
+    def outputs(self, ion_offsets, device, want_b=True, want_kset=True):
+        """Output tensors of a step over the given replicas (Q, F, b, psibar, E, kset)."""
         import torch
         off = np.asarray(ion_offsets, dtype=np.int64)
         R = len(off) - 1
         N = int(off[-1])
         P = int(self.params["P"])
-        dev = ion_xyz.device if N else dpsi.device
+        return dict(
+            Q=torch.empty(R * self.n_ele, dtype=torch.float64, device=device),
+            F=torch.empty(3 * N, dtype=torch.float64, device=device),
+            b=torch.empty(R * self.n_ele, dtype=torch.float64, device=device) if want_b else None,
+            psibar=torch.empty(R, dtype=torch.float64, device=device),
+            E=torch.empty(R, dtype=torch.float64, device=device),
+            kset=torch.empty(R * P * 3, dtype=torch.int32, device=device) if (want_kset and P) else None,
+        )
+
+    def capture(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, precision=SRBE_FP64, kset_in=None,
+                Q_in=None, want_b=True, want_kset=True, out=None):
+        """Capture one step with fixed buffers; returns a StepGraph (replay with .launch())."""
+        off = np.asarray(ion_offsets, dtype=np.int64)
         if out is None:
-            out = dict(
-                Q=torch.empty(R * self.n_ele, dtype=torch.float64, device=dev),
-                F=torch.empty(3 * N, dtype=torch.float64, device=dev),
-                b=torch.empty(R * self.n_ele, dtype=torch.float64, device=dev) if want_b else None,
-                psibar=torch.empty(R, dtype=torch.float64, device=dev),
-                E=torch.empty(R, dtype=torch.float64, device=dev),
-                kset=torch.empty(R * P * 3, dtype=torch.int32, device=dev) if (want_kset and P) else None,
-            )
+            out = self.outputs(off, dpsi.device, want_b, want_kset)
+        gr = srbe_graph_create(self.h, precision, off, ion_xyz, ion_q, dpsi, seed, first_step, out["Q"], out["F"],
+                               kset_in=kset_in, Q_in=Q_in, b_out=out["b"], psibar_out=out["psibar"],
+                               energy_out=out["E"], kset_out=out["kset"])
+        # the graph keeps raw pointers: hold the inputs and outputs for its lifetime
+        return StepGraph(self, gr, out, (ion_xyz, ion_q, dpsi, seed, kset_in, Q_in))
+
+    def step(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, precision=SRBE_FP64, kset_in=None, Q_in=None,
+             want_b=True, want_kset=True, out=None, stream=None):
+        """Run one step; returns a dict of CUDA tensors (Q, F, b, psibar, E, kset)."""
+        off = np.asarray(ion_offsets, dtype=np.int64)
+        if out is None:
+            out = self.outputs(off, dpsi.device, want_b, want_kset)
         srbe_step(self.h, precision, off, ion_xyz, ion_q, dpsi, seed, step, out["Q"], out["F"], kset_in=kset_in,
                   Q_in=Q_in, b_out=out["b"], psibar_out=out["psibar"], energy_out=out["E"], kset_out=out["kset"],
                   stream=stream)
         return out
+
+
+class StepGraph:
+    """A captured step: launch() replays it (the step counter advances by one per replay)."""
+
+    def __init__(self, system, gr, out, inputs):
+        self.system = system
+        self.gr = gr
+        self.out = out
+        self._inputs = inputs
+
+    def launch(self, stream=None):
+        srbe_graph_launch(self.gr, stream)
+        return self.out
+
+    def set_step(self, step, stream=None):
+        srbe_graph_set_step(self.gr, step, stream)
+
+    def close(self):
+        if self.gr is not None:
+            srbe_graph_destroy(self.gr)
+            self.gr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

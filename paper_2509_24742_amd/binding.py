@@ -78,14 +78,24 @@ def lib():
     L.srbe_profile_read.restype = ctypes.c_int
     L.srbe_phase_name.argtypes = [ctypes.c_int32]
     L.srbe_phase_name.restype = ctypes.c_char_p
+    L.srbe_graph_create.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64,
+                                    _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+    L.srbe_graph_create.restype = ctypes.c_int
+    L.srbe_graph_launch.argtypes = [_vp, _vp]
+    L.srbe_graph_launch.restype = ctypes.c_int
+    L.srbe_graph_set_step.argtypes = [_vp, ctypes.c_uint64, _vp]
+    L.srbe_graph_set_step.restype = ctypes.c_int
+    L.srbe_graph_destroy.argtypes = [_vp]
+    L.srbe_graph_destroy.restype = None
     _lib = L
     return L
 
 
 EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string", "srbe_step", "srbe_sample",
             "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
-            "srbe_phase_name"]
-SRBE_N_PHASES = 12
+            "srbe_phase_name", "srbe_graph_create", "srbe_graph_launch", "srbe_graph_set_step",
+            "srbe_graph_destroy"]
+SRBE_N_PHASES = 16
 
 
 def _check(h, code):
@@ -168,16 +178,15 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def srbe_step(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in=None, Q_in=None,
-              b_out=None, psibar_out=None, energy_out=None, kset_out=None, stream=None, check=True):
-    """One step.  ion_offsets: host int64 (R+1); device tensors as in include/srbe.h."""
+def _step_args(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in, Q_in, b_out,
+               psibar_out, energy_out, kset_out):
     import torch
     off = np.ascontiguousarray(np.asarray(ion_offsets, dtype=np.int64))
     R = off.shape[0] - 1
     N = int(off[-1])
     n = srbe_n_ele(h)
     P = _batch_size[h.value]
-    args = [
+    return off, [
         h, int(precision), R, off.ctypes.data,
         _dev(ion_xyz, torch.float64, 3 * N, "ion_xyz", allow_none=N == 0),
         _dev(ion_q, torch.float64, N, "ion_q", allow_none=N == 0),
@@ -192,12 +201,44 @@ def srbe_step(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out
         _dev(psibar_out, torch.float64, R, "psibar_out", allow_none=True),
         _dev(energy_out, torch.float64, R, "energy_out", allow_none=True),
         _dev(kset_out, torch.int32, R * P * 3, "kset_out", allow_none=True),
-        _stream(stream),
     ]
-    code = lib().srbe_step(*args)
+
+
+def srbe_step(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in=None, Q_in=None,
+              b_out=None, psibar_out=None, energy_out=None, kset_out=None, stream=None, check=True):
+    """One step.  ion_offsets: host int64 (R+1); device tensors as in include/srbe.h."""
+    off, args = _step_args(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in, Q_in,
+                           b_out, psibar_out, energy_out, kset_out)
+    code = lib().srbe_step(*args, _stream(stream))
     if check:
         _check(h, code)
     return code
+
+
+def srbe_graph_create(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, Q_out, F_out, kset_in=None,
+                      Q_in=None, b_out=None, psibar_out=None, energy_out=None, kset_out=None):
+    """Capture one step with fixed buffers; returns the graph handle (see include/srbe.h)."""
+    off, args = _step_args(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, Q_out, F_out, kset_in,
+                           Q_in, b_out, psibar_out, energy_out, kset_out)
+    gr = _vp()
+    _check(h, lib().srbe_graph_create(*args, ctypes.byref(gr)))
+    return gr
+
+
+def srbe_graph_launch(gr, stream=None):
+    code = lib().srbe_graph_launch(gr, _stream(stream))
+    if code != SRBE_OK:
+        raise SrbeError(code, lib().srbe_error_string(code).decode())
+
+
+def srbe_graph_set_step(gr, step, stream=None):
+    code = lib().srbe_graph_set_step(gr, ctypes.c_uint64(int(step)), _stream(stream))
+    if code != SRBE_OK:
+        raise SrbeError(code, lib().srbe_error_string(code).decode())
+
+
+def srbe_graph_destroy(gr):
+    lib().srbe_graph_destroy(gr)
 
 
 def srbe_sample(h, seed, step, kset_out, n_accepted_out=None, stream=None):

@@ -32,6 +32,10 @@ struct Geom {
                     // 2^-30 of the alpha terms at rc and are not evaluated
 };
 
+// Leading dimension of the charge-solve operands (S_ext rows, right-hand sides):
+// n rounded up to a multiple of 16 doubles, the padding held at zero.
+__host__ __device__ inline int ldcp(int n) { return (n + 15) & ~15; }
+
 constexpr int kMaxBinParticles = 8192;  // particles per replica the one-block cell sort handles
 constexpr int kMaxCells = 2048;
 // Neighbour runs per cell: the cells within reach of a cell, sorted, as runs of

@@ -27,6 +27,7 @@ struct StepBufs {
   const double* dpsi;       // R
   const uint64_t* seed;     // R
   uint64_t step;
+  const uint64_t* step_dev; // graph replays: the step is read from here (null: use step)
   const int32_t* kset_in;   // R*P*3 or null
   // electrodes (device, fixed): original order and cell-sorted order
   const double* ele_xyz;    // SoA 3*n_ele
@@ -40,6 +41,10 @@ struct StepBufs {
   const int2* ion_runs;     // ncell x kRunMax neighbour runs [c0, c1), merged across z; c0 = -1 ends
   const int2* ele_runs;     // ncell x kRunMax neighbour runs split by z-layer (electrode side)
   const double2* ele_run_zr;  // ncell x kRunMax z-extent of the electrodes of each ele_runs entry
+  const int2* reach;        // cell ranges [c0, c1) whose ions can be within rc of an electrode
+  int nreach;
+  const int4* ele_chunks;   // (cell, first, end) runs of <= 64 cell-sorted electrodes of one cell
+  int n_ele_chunks;
   const uint4* ele_sfx;     // sorted fixed point
   const double4* ele_sd4;   // sorted fractional coordinates
   // workspace
@@ -48,6 +53,7 @@ struct StepBufs {
   double* w;                // R*K
   uint4* ion_fx;            // N fixed point + FP32 charge, original order (FP32 path)
   double4* ion_d4;          // N fractional coordinates + charge, original order (FP64 path)
+  unsigned* keys;           // N cell sort keys (cell << 13 | index within the replica), input order
   int* perm;                // N sorted position (within the replica's range) -> global ion index
   int* scell;               // N cell of each sorted ion
   int* cstart;              // R*(ncell+1) cell starts, relative to the replica's first ion
@@ -60,13 +66,16 @@ struct StepBufs {
   ModeRec32* rec;           // R*K (FP32 path)
   double* bN;               // R*n_ele real-space electrode potential from the ions
   double* bstar;            // R*n_ele
-  double* V;                // R*n_ele (dpsi d + b*), GEMM right-hand side, ld n_ele
-  double* Qext;             // R*(n_ele+1) GEMM output (Q then psibar), ld n_ele+1
+  double* V;                // R*ldcp(n_ele) (dpsi d + b*), GEMM right-hand side, V[r ldcp(n) + j]
+  double* Qext;             // ksplit*R*(n_ele+1) GEMM partials over k-ranges (Q then psibar),
+                            // Qext[(h R + r)(n+1) + i], summed in h order after the GEMM
+  int ksplit;
   float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
   float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
   double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)
-  double* rsum;             // R*8 per-replica reductions after the charge solve
+  double* rsum;             // R*16 per-replica reductions after the charge solve (4 partial sums of 3)
   double* phi;              // N real-space ion-ion potential per ion
+  double* Fii;              // 3N ion-ion real-space force sums (SoA, input order), before the ke q_i factor
   unsigned* status;
   // outputs
   double* Q_out;
@@ -78,21 +87,27 @@ struct StepBufs {
   const double* Q_in;
 };
 
-void launch_prepare(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_records(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_cellsort(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s);
+void launch_set_step(uint64_t* step_dev, uint64_t v, hipStream_t s);
+void launch_advance_step(uint64_t* step_dev, hipStream_t s);
 void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+int cp_gemm_ksplit(int n_ele, int R);
+void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
 void launch_sf_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_real_ion(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_real_ie(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_energy(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 
 // setup kernels
-void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, uint4* fx,
-                           double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4, unsigned* status,
-                           hipStream_t s);
+void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,
+                           uint4* fx, double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4,
+                           unsigned* status, hipStream_t s);
 void launch_cell_zrange(const Geom& g, const int* cstart, const double* ele_xyz, const int* perm, double2* zr,
                         hipStream_t s);
 void launch_ele_phase_block(const double* ele_xyz, int n_ele, const int* m, const double* sqrtw, int nk, int ld,

@@ -96,24 +96,24 @@ void launch_rowsum(const double* A, int n, int ld, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_rowsum, dim3(n), dim3(256), 0, s, A, n, ld, out);
 }
 
-// S_ext, (n+1) x n column-major: rows 0..n-1 hold S = A^-1 - g g^T / (e^T g)
-// (= J A^-1, Eq. (10)); row n holds -g^T / (e^T g), so that the last entry of
-// S_ext (dpsi d + b) is psibar of Eq. (9).
+// S_ext, (n+1) rows of ldcp(n) doubles, row-major: rows 0..n-1 hold
+// S = A^-1 - g g^T / (e^T g) (= J A^-1, Eq. (10), symmetric); row n holds
+// -g^T / (e^T g), so that row n times (dpsi d + b) is psibar of Eq. (9).  Columns
+// n .. ldcp(n)-1 are zero.
 __global__ __launch_bounds__(256) void k_build_sext(const double* __restrict__ Ainv, int n,
                                                     const double* __restrict__ gv, double eg,
                                                     double* __restrict__ Sext) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i > n) return;
-  const size_t ld = (size_t)n + 1;
-  if (i < n)
-    Sext[(size_t)j * ld + i] = Ainv[(size_t)j * n + i] - gv[i] * gv[j] / eg;
-  else
-    Sext[(size_t)j * ld + n] = -gv[j] / eg;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  const int ld = ldcp(n);
+  if (j >= ld) return;
+  double v = 0.0;
+  if (j < n) v = i < n ? Ainv[(size_t)j * n + i] - gv[i] * gv[j] / eg : -gv[j] / eg;
+  Sext[(size_t)i * ld + j] = v;
 }
 
 void launch_build_sext(const double* Ainv, int n, const double* gv, double eg, double* Sext, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_sext, dim3(cdiv(n + 1, 256), n), dim3(256), 0, s, Ainv, n, gv, eg, Sext);
+  hipLaunchKernelGGL(k_build_sext, dim3(cdiv(ldcp(n), 256), n + 1), dim3(256), 0, s, Ainv, n, gv, eg, Sext);
 }
 
 __global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ a, size_t n, unsigned* status) {

@@ -36,12 +36,21 @@ struct srbe_system {
   double2* ele_run_zr = nullptr;  // ncell x kRunMax electrode z-extent of each ele_runs entry
   uint4* ele_sfx = nullptr;    // sorted fixed point
   double4* ele_sd4 = nullptr;  // sorted fractional coordinates
-  double* Sext = nullptr;
+  double* Sext = nullptr;      // (n+1) x ldcp(n) row-major: J A^-1 and the psibar row
   unsigned* status = nullptr;
   rocblas_handle blas = nullptr;
-  // the sampler runs on a second stream, forked from and joined back to the step's stream
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the step is a small DAG over three streams: the caller's (records, k-space chain,
+  // charge solve), aux[0] (sampler) and aux[1] (cell lists, real space); cap is the
+  // stream graphs are captured on
+  hipStream_t aux[2] = {nullptr, nullptr};
+  hipStream_t cap = nullptr;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool capturing = false;
+  unsigned* bin_keys = nullptr;  // n_ele scratch for the electrode binning
+  int2* reach = nullptr;         // cell ranges whose ions can be within rc of an electrode
+  int nreach = 0;
+  int4* ele_chunks = nullptr;    // (cell, first, end): <= 64 cell-sorted electrodes of one cell
+  int n_ele_chunks = 0;
   // workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -56,6 +65,15 @@ struct srbe_system {
   int64_t* off_dev = nullptr;
   size_t off_cap = 0;
   std::string err;
+};
+
+struct srbe_graph {
+  srbe_system* h = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;           // the graph's own workspace (fixed addresses)
+  int64_t* off_dev = nullptr;   // its CSR offsets
+  uint64_t* step_dev = nullptr; // step counter read by the sampler, advanced by each replay
 };
 
 namespace {
@@ -281,9 +299,9 @@ int build_electrode_solve(srbe_system* h, hipStream_t s) {
       rc = set_err(h, SRBE_ENOTSPD, "e^T A^-1 e is not positive");
       break;
     }
-    TRY(hipMalloc(&h->Sext, (size_t)(n + 1) * n * sizeof(double)));
+    TRY(hipMalloc(&h->Sext, (size_t)(n + 1) * ldcp(n) * sizeof(double)));
     launch_build_sext(A, n, gv, eg, h->Sext, s);
-    launch_check_finite(h->Sext, (size_t)(n + 1) * n, h->status, s);
+    launch_check_finite(h->Sext, (size_t)(n + 1) * ldcp(n), h->status, s);
     TRY(hipStreamSynchronize(s));
     unsigned st = 0;
     TRY(hipMemcpy(&st, h->status, sizeof(unsigned), hipMemcpyDeviceToHost));
@@ -299,9 +317,10 @@ int build_electrode_solve(srbe_system* h, hipStream_t s) {
 
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-const char* kPhaseNames[SRBE_N_PHASES] = {"prepare", "sample",       "sf_ions",   "real_ele",
-                                          "ele_potential", "cp_gemm", "post_charges", "sf_ele",
-                                          "ion_force", "real_ion", "energy", "unused"};
+const char* kPhaseNames[SRBE_N_PHASES] = {"records",  "sample",   "sf_ions",      "cellsort", "real_ele",
+                                          "real_ii",  "ele_potential", "cp_gemm", "post_charges", "sf_ele",
+                                          "ion_force", "real_ie", "energy",  "",             "",
+                                          ""};
 
 // Record an event pair around a phase when profiling is enabled.
 struct PhaseTimer {
@@ -310,7 +329,8 @@ struct PhaseTimer {
   int phase;
   size_t slot = 0;
   bool on;
-  PhaseTimer(srbe_system* h_, hipStream_t s_, int phase_) : h(h_), s(s_), phase(phase_), on(h_->prof) {
+  PhaseTimer(srbe_system* h_, hipStream_t s_, int phase_)
+      : h(h_), s(s_), phase(phase_), on(h_->prof && !h_->capturing) {
     if (!on) return;
     if (h->ev_used * 2 + 2 > h->ev_pool.size()) {
       for (int i = 0; i < 64; ++i) {
@@ -331,6 +351,186 @@ struct PhaseTimer {
     if (on) (void)hipEventRecord(h->ev_pool[2 * slot + 1], s);
   }
 };
+
+struct StepArgs {
+  int32_t precision;
+  int32_t n_rep;
+  const int64_t* ion_offsets;
+  const double* ion_xyz;
+  const double* ion_q;
+  const double* dpsi;
+  const uint64_t* seed;
+  uint64_t step;
+  const int32_t* kset_in;
+  const double* Q_in;
+  double* Q_out;
+  double* F_out;
+  double* b_out;
+  double* psibar_out;
+  double* energy_out;
+  int32_t* kset_out;
+};
+
+int check_step(srbe_system* h, const StepArgs& a, int64_t& max_nrep) {
+  if (a.precision != SRBE_FP64 && a.precision != SRBE_FP32) return set_err(h, SRBE_EINVAL, "unknown precision");
+  if (a.n_rep <= 0 || !a.ion_offsets) return set_err(h, SRBE_EINVAL, "n_rep must be positive and offsets given");
+  if (a.n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
+  if (a.ion_offsets[0] != 0) return set_err(h, SRBE_EINVAL, "ion_offsets[0] must be 0");
+  max_nrep = 0;
+  for (int r = 0; r < a.n_rep; ++r) {
+    const int64_t c = a.ion_offsets[r + 1] - a.ion_offsets[r];
+    if (c < 0) return set_err(h, SRBE_EINVAL, "ion_offsets must be non-decreasing");
+    max_nrep = std::max(max_nrep, c);
+  }
+  const int64_t N = a.ion_offsets[a.n_rep];
+  if (N > 0 && (!a.ion_xyz || !a.ion_q)) return set_err(h, SRBE_EINVAL, "ion arrays are NULL");
+  if (!a.dpsi || !a.Q_out || (N > 0 && !a.F_out)) return set_err(h, SRBE_EINVAL, "dpsi, Q_out and F_out are required");
+  if (!a.kset_in && !a.seed && h->p.P > 0) return set_err(h, SRBE_EINVAL, "seed or kset_in is required");
+  if (!a.Q_in && !h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: pass Q_in");
+  if (max_nrep > kMaxBinParticles)
+    return set_err(h, SRBE_EINVAL, "a replica has more ions than the one-block cell sort handles (8192)");
+  return SRBE_OK;
+}
+
+// Everything but the workspace pointers and the device offsets.
+void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b) {
+  const Geom& g = h->g;
+  const int R = a.n_rep, K = g.K, n = h->n_ele;
+  b.R = R;
+  b.N = a.ion_offsets[R];
+  b.max_nrep = (int)max_nrep;
+  // chunking of the structure-factor passes: aim for >= 1024 blocks of 256 threads
+  b.ktiles = std::max(1, (K + 255) / 256);
+  auto chunks_for = [&](int64_t np) {
+    int64_t c = (1024 + (int64_t)b.ktiles * R - 1) / ((int64_t)b.ktiles * R);
+    c = std::min<int64_t>(c, std::max<int64_t>(1, (np + 31) / 32));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(c, 4096));
+  };
+  b.nchunk_ion = chunks_for(max_nrep);
+  b.nchunk_ele = chunks_for(n);
+  b.ksplit = cp_gemm_ksplit(n, R);
+  b.ion_xyz = a.ion_xyz;
+  b.ion_q = a.ion_q;
+  b.dpsi = a.dpsi;
+  b.seed = a.seed;
+  b.step = a.step;
+  b.step_dev = nullptr;
+  b.kset_in = a.kset_in;
+  b.ele_xyz = h->ele_xyz;
+  b.ele_d = h->ele_d;
+  b.ele_fx = h->ele_fx;
+  b.ele_d4 = h->ele_d4;
+  b.ele_perm = h->ele_perm;
+  b.ele_scell = h->ele_scell;
+  b.ele_cstart = h->ele_cstart;
+  b.ele_czr = h->ele_czr;
+  b.ion_runs = h->ion_runs;
+  b.ele_runs = h->ele_runs;
+  b.ele_run_zr = h->ele_run_zr;
+  b.reach = h->reach;
+  b.nreach = h->nreach;
+  b.ele_chunks = h->ele_chunks;
+  b.n_ele_chunks = h->n_ele_chunks;
+  b.ele_sfx = h->ele_sfx;
+  b.ele_sd4 = h->ele_sd4;
+  b.status = h->status;
+  b.Q_out = a.Q_out;
+  b.F_out = a.F_out;
+  b.psibar_out = a.psibar_out;
+  b.energy_out = a.energy_out;
+  b.bstar = a.b_out;
+  b.kset_out = a.kset_out;
+  b.nacc_out = nullptr;
+  b.Q_in = a.Q_in;
+}
+
+// Workspace layout: returns the bytes needed; with a base pointer, also assigns the
+// workspace members of b (caller-given b_out / energy_out are kept).
+size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* base) {
+  const Geom& g = h->g;
+  const int R = a.n_rep, K = std::max(g.K, 1), n = h->n_ele;
+  const int64_t N1 = std::max<int64_t>(a.ion_offsets[R], 1);
+  const bool fp32 = a.precision == SRBE_FP32, fixedQ = a.Q_in != nullptr;
+  const int nch = std::max(b.nchunk_ion, b.nchunk_ele);
+  struct Item {
+    void** ptr;
+    size_t bytes;
+  };
+  const Item items[] = {
+      {(void**)&b.scal, (size_t)R * 4 * sizeof(double)},
+      {(void**)&b.modes, (size_t)R * K * sizeof(int4)},
+      {(void**)&b.w, (size_t)R * K * sizeof(double)},
+      {(void**)&b.ion_fx, fp32 ? (size_t)N1 * sizeof(uint4) : 0},
+      {(void**)&b.ion_d4, fp32 ? 0 : (size_t)N1 * sizeof(double4)},
+      {(void**)&b.keys, (size_t)N1 * sizeof(unsigned)},
+      {(void**)&b.perm, (size_t)N1 * sizeof(int)},
+      {(void**)&b.scell, (size_t)N1 * sizeof(int)},
+      {(void**)&b.cstart, (size_t)R * (g.ncell + 1) * sizeof(int)},
+      {(void**)&b.sfx, fp32 ? (size_t)N1 * sizeof(uint4) : 0},
+      {(void**)&b.sd4, fp32 ? 0 : (size_t)N1 * sizeof(double4)},
+      {(void**)&b.part, (size_t)R * nch * K * sizeof(double2)},
+      {(void**)&b.S1, (size_t)R * K * sizeof(double2)},
+      {(void**)&b.coef, (size_t)R * K * sizeof(double2)},
+      {(void**)&b.rec, fp32 ? (size_t)R * K * sizeof(ModeRec32) : 0},
+      {(void**)&b.bN, (size_t)R * n * sizeof(double)},
+      {(void**)&b.bstar, a.b_out ? 0 : (size_t)R * n * sizeof(double)},
+      {(void**)&b.V, (size_t)R * ldcp(n) * sizeof(double)},
+      {(void**)&b.Qext, fixedQ ? 0 : (size_t)b.ksplit * R * (n + 1) * sizeof(double)},
+      {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
+      {(void**)&b.Qsf, fp32 ? (size_t)R * n * sizeof(float) : 0},
+      {(void**)&b.Qsd, fp32 ? 0 : (size_t)R * n * sizeof(double)},
+      {(void**)&b.rsum, (size_t)R * 16 * sizeof(double)},
+      {(void**)&b.phi, (size_t)N1 * sizeof(double)},
+      {(void**)&b.Fii, (size_t)3 * N1 * sizeof(double)},
+      {(void**)&b.energy_out, a.energy_out ? 0 : (size_t)R * sizeof(double)},
+  };
+  size_t total = 0;
+  for (const Item& it : items) {
+    if (base && it.bytes) *it.ptr = base + total;
+    total += align_up(it.bytes);
+  }
+  return total;
+}
+
+enum { EV_FORK = 0, EV_SAMPLE, EV_REC, EV_BN, EV_II };
+
+// The step as a DAG over three streams (Algorithm 1's order within each chain):
+//   aux[0]:  sample
+//   s:       records -> (sample) sf_ions -> (real_ele) ele_potential -> cp_gemm ->
+//            post_charges -> sf_ele -> (real_ii) ion_force -> real_ie -> energy
+//   aux[1]:  (records) cellsort -> real_ele -> real_ii
+int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStream_t s) {
+  const Geom& g = h->g;
+  hipStream_t s0 = h->aux[0], s1 = h->aux[1];
+  HIP_OK(h, hipEventRecord(h->ev[EV_FORK], s));
+  HIP_OK(h, hipStreamWaitEvent(s0, h->ev[EV_FORK], 0));
+  { PhaseTimer t(h, s0, 1); launch_sample(g, b, s0); }
+  HIP_OK(h, hipEventRecord(h->ev[EV_SAMPLE], s0));
+  { PhaseTimer t(h, s, 0); launch_records(g, b, fp32, s); }
+  HIP_OK(h, hipEventRecord(h->ev[EV_REC], s));
+  HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_REC], 0));
+  { PhaseTimer t(h, s1, 3); launch_cellsort(g, b, fp32, s1); }
+  { PhaseTimer t(h, s1, 4); launch_real_ele(g, b, fp32, s1); }
+  HIP_OK(h, hipEventRecord(h->ev[EV_BN], s1));
+  { PhaseTimer t(h, s1, 5); launch_real_ii(g, b, fp32, s1); }
+  HIP_OK(h, hipEventRecord(h->ev[EV_II], s1));
+  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_SAMPLE], 0));
+  { PhaseTimer t(h, s, 2); launch_sf_ions(g, b, fp32, s); }
+  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_BN], 0));
+  { PhaseTimer t(h, s, 6); launch_ele_potential(g, b, fp32, s); }
+  if (!fixedQ) {
+    PhaseTimer t(h, s, 7);
+    launch_cp_gemm(g, b, h->Sext, s);
+  }
+  { PhaseTimer t(h, s, 8); launch_post_charges(g, b, fixedQ, fp32, s); }
+  { PhaseTimer t(h, s, 9); launch_sf_ele(g, b, fp32, s); }
+  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_II], 0));
+  { PhaseTimer t(h, s, 10); launch_ion_force(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 11); launch_real_ie(g, b, fp32, s); }
+  { PhaseTimer t(h, s, 12); launch_energy(g, b, fixedQ, s); }
+  HIP_OK(h, hipGetLastError());
+  return SRBE_OK;
+}
 
 }  // namespace
 
@@ -364,10 +564,12 @@ void srbe_destroy(srbe_system* h) {
   (void)hipDeviceSynchronize();
   if (h->blas) rocblas_destroy_handle(h->blas);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-  if (h->aux) (void)hipStreamDestroy(h->aux);
-  void* bufs[] = {h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
+  for (hipEvent_t e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t st : h->aux)
+    if (st) (void)hipStreamDestroy(st);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  void* bufs[] = {h->bin_keys, h->reach, h->ele_chunks, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
                   h->ele_czr, h->ion_runs, h->ele_runs, h->ele_run_zr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -426,6 +628,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ele_sfx, n * sizeof(uint4));
     al((void**)&h->ele_sd4, n * sizeof(double4));
     al((void**)&h->status, sizeof(unsigned));
+    al((void**)&h->bin_keys, n * sizeof(unsigned));
     int64_t* off2 = nullptr;
     al((void**)&off2, 2 * sizeof(int64_t));
     if (e != hipSuccess) {
@@ -474,8 +677,8 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
     }
-    launch_bin_electrodes(g, off2, h->ele_xyz, n_ele, h->ele_fx, h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
-                          h->ele_sfx, h->ele_sd4, h->status, s);
+    launch_bin_electrodes(g, off2, h->ele_xyz, n_ele, h->bin_keys, h->ele_fx, h->ele_d4, h->ele_perm, h->ele_scell,
+                          h->ele_cstart, h->ele_sfx, h->ele_sd4, h->status, s);
     launch_cell_zrange(g, h->ele_cstart, h->ele_xyz, h->ele_perm, h->ele_czr, s);
     std::vector<double2> czr(g.ncell);
     if (hipDeviceSynchronize() != hipSuccess ||
@@ -491,14 +694,64 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
         rzr[u].x = std::min(rzr[u].x, czr[cc].x);
         rzr[u].y = std::max(rzr[u].y, czr[cc].y);
       }
-    if (hipMemcpy(h->ele_run_zr, rzr.data(), rzr.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+    // electrode-side runs without electrodes are dropped (they can never hold a partner)
+    for (int c = 0; c < g.ncell; ++c) {
+      int k = 0;
+      for (int u = 0; u < kRunMax && eruns[(size_t)c * kRunMax + u].x >= 0; ++u) {
+        const size_t src = (size_t)c * kRunMax + u;
+        if (rzr[src].x > rzr[src].y) continue;
+        eruns[(size_t)c * kRunMax + k] = eruns[src];
+        rzr[(size_t)c * kRunMax + k] = rzr[src];
+        ++k;
+      }
+      for (int u = k; u < kRunMax; ++u) {
+        eruns[(size_t)c * kRunMax + u] = make_int2(-1, -1);
+        rzr[(size_t)c * kRunMax + u] = make_double2(INFINITY, -INFINITY);
+      }
+    }
+    if (hipMemcpy(h->ele_runs, eruns.data(), eruns.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ele_run_zr, rzr.data(), rzr.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(SRBE_EHIP);
+    // electrode chunks for the electrode-side real-space pass, and the reach ranges:
+    // cells with an electrode run within rc (plus a rounding margin) of their z-slab
+    std::vector<int> ecs(g.ncell + 1);
+    if (hipMemcpy(ecs.data(), h->ele_cstart, ecs.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(SRBE_EHIP);
+    std::vector<int4> chunks;
+    for (int c = 0; c < g.ncell; ++c)
+      for (int e0 = ecs[c]; e0 < ecs[c + 1]; e0 += 64) chunks.push_back(make_int4(c, e0, std::min(e0 + 64, ecs[c + 1]), 0));
+    const double zlim = g.rc + 2e-6;
+    std::vector<int2> reach;
+    for (int c = 0; c < g.ncell; ++c) {
+      const int cz = c / (g.ncx * g.ncy);
+      const double zc0 = g.H * cz / g.ncz, zc1 = g.H * (cz + 1) / g.ncz;
+      bool flag = false;
+      for (int u = 0; u < kRunMax && eruns[(size_t)c * kRunMax + u].x >= 0; ++u) {
+        const double2 zr = rzr[(size_t)c * kRunMax + u];
+        if (zr.x <= zr.y && !(zr.x - zc1 >= zlim || zc0 - zr.y >= zlim)) flag = true;
+      }
+      if (!flag) continue;
+      if (!reach.empty() && reach.back().y == c)
+        reach.back().y = c + 1;
+      else
+        reach.push_back(make_int2(c, c + 1));
+    }
+    if (reach.size() > 64) reach = {make_int2(reach.front().x, reach.back().y)};
+    h->nreach = (int)reach.size();
+    h->n_ele_chunks = (int)chunks.size();
+    if (hipMalloc((void**)&h->reach, std::max<size_t>(1, reach.size()) * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&h->ele_chunks, std::max<size_t>(1, chunks.size()) * sizeof(int4)) != hipSuccess ||
+        (!reach.empty() &&
+         hipMemcpy(h->reach, reach.data(), reach.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess) ||
+        (!chunks.empty() &&
+         hipMemcpy(h->ele_chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess))
       return fail(SRBE_EHIP);
   }
   if (rocblas_create_handle(&h->blas) != rocblas_status_success) return fail(SRBE_EHIP);
-  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
-    return fail(SRBE_EHIP);
+  for (hipStream_t* st : {&h->aux[0], &h->aux[1], &h->cap})
+    if (hipStreamCreateWithFlags(st, hipStreamNonBlocking) != hipSuccess) return fail(SRBE_EHIP);
+  for (hipEvent_t& e : h->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(SRBE_EHIP);
   if (cp) {
     rc = build_electrode_solve(h, s);
     if (rc != SRBE_OK) {
@@ -556,75 +809,15 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
               const double* Q_in, double* Q_out, double* F_out, double* b_out, double* psibar_out,
               double* energy_out, int32_t* kset_out, void* stream) {
   if (!h) return SRBE_EINVAL;
-  if (precision != SRBE_FP64 && precision != SRBE_FP32) return set_err(h, SRBE_EINVAL, "unknown precision");
-  if (n_rep <= 0 || !ion_offsets) return set_err(h, SRBE_EINVAL, "n_rep must be positive and offsets given");
-  if (ion_offsets[0] != 0) return set_err(h, SRBE_EINVAL, "ion_offsets[0] must be 0");
+  const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, kset_in,
+                   Q_in, Q_out, F_out, b_out, psibar_out, energy_out, kset_out};
   int64_t max_nrep = 0;
-  for (int r = 0; r < n_rep; ++r) {
-    const int64_t c = ion_offsets[r + 1] - ion_offsets[r];
-    if (c < 0) return set_err(h, SRBE_EINVAL, "ion_offsets must be non-decreasing");
-    max_nrep = std::max(max_nrep, c);
-  }
-  const int64_t N = ion_offsets[n_rep];
-  if (N > 0 && (!ion_xyz || !ion_q)) return set_err(h, SRBE_EINVAL, "ion arrays are NULL");
-  if (!dpsi || !Q_out || (N > 0 && !F_out)) return set_err(h, SRBE_EINVAL, "dpsi, Q_out and F_out are required");
-  if (!kset_in && !seed && h->p.P > 0) return set_err(h, SRBE_EINVAL, "seed or kset_in is required");
-  if (!Q_in && !h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: pass Q_in");
-  if (max_nrep > (int64_t)1 << 31) return set_err(h, SRBE_EINVAL, "replica too large");
-  if (n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
-  if (max_nrep > kMaxBinParticles)
-    return set_err(h, SRBE_EINVAL, "a replica has more ions than the one-block cell sort handles (8192)");
-  const int fp32 = precision == SRBE_FP32;
-  const int fixedQ = Q_in != nullptr;
-  const Geom& g = h->g;
-  const int R = n_rep, K = g.K, n = h->n_ele;
+  int rc = check_step(h, a, max_nrep);
+  if (rc != SRBE_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
-
-  // chunking of the structure-factor passes: aim for >= 2048 blocks of 256 threads
-  const int ktiles = std::max(1, (K + 255) / 256);
-  auto chunks_for = [&](int64_t np) {
-    int64_t c = (1024 + (int64_t)ktiles * R - 1) / ((int64_t)ktiles * R);
-    c = std::min<int64_t>(c, std::max<int64_t>(1, (np + 31) / 32));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(c, 4096));
-  };
-  const int nch_ion = chunks_for(max_nrep);
-  const int nch_ele = chunks_for(n);
-  const int nch = std::max(nch_ion, nch_ele);
-
-  // workspace
-  struct Item {
-    void** ptr;
-    size_t bytes;
-  };
   StepBufs b{};
-  std::vector<Item> items = {
-      {(void**)&b.scal, (size_t)R * 4 * sizeof(double)},
-      {(void**)&b.modes, (size_t)R * std::max(K, 1) * sizeof(int4)},
-      {(void**)&b.w, (size_t)R * std::max(K, 1) * sizeof(double)},
-      {(void**)&b.ion_fx, fp32 ? (size_t)std::max<int64_t>(N, 1) * sizeof(uint4) : 0},
-      {(void**)&b.ion_d4, fp32 ? 0 : (size_t)std::max<int64_t>(N, 1) * sizeof(double4)},
-      {(void**)&b.perm, (size_t)std::max<int64_t>(N, 1) * sizeof(int)},
-      {(void**)&b.scell, (size_t)std::max<int64_t>(N, 1) * sizeof(int)},
-      {(void**)&b.cstart, (size_t)R * (g.ncell + 1) * sizeof(int)},
-      {(void**)&b.sfx, fp32 ? (size_t)std::max<int64_t>(N, 1) * sizeof(uint4) : 0},
-      {(void**)&b.sd4, fp32 ? 0 : (size_t)std::max<int64_t>(N, 1) * sizeof(double4)},
-      {(void**)&b.part, (size_t)R * nch * std::max(K, 1) * sizeof(double2)},
-      {(void**)&b.S1, (size_t)R * std::max(K, 1) * sizeof(double2)},
-      {(void**)&b.coef, (size_t)R * std::max(K, 1) * sizeof(double2)},
-      {(void**)&b.rec, fp32 ? (size_t)R * std::max(K, 1) * sizeof(ModeRec32) : 0},
-      {(void**)&b.bN, (size_t)R * n * sizeof(double)},
-      {(void**)&b.bstar, b_out ? 0 : (size_t)R * n * sizeof(double)},
-      {(void**)&b.V, (size_t)R * n * sizeof(double)},
-      {(void**)&b.Qext, fixedQ ? 0 : (size_t)R * (n + 1) * sizeof(double)},
-      {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
-      {(void**)&b.Qsf, fp32 ? (size_t)R * n * sizeof(float) : 0},
-      {(void**)&b.Qsd, fp32 ? 0 : (size_t)R * n * sizeof(double)},
-      {(void**)&b.rsum, (size_t)R * 8 * sizeof(double)},
-      {(void**)&b.phi, (size_t)std::max<int64_t>(N, 1) * sizeof(double)},
-      {(void**)&b.energy_out, energy_out ? 0 : (size_t)R * sizeof(double)},
-  };
-  size_t total = 0;
-  for (auto& it : items) total += align_up(it.bytes);
+  fill_bufs(h, a, max_nrep, b);
+  const size_t total = ws_layout(h, a, b, nullptr);
   if (total > h->ws_bytes) {
     if (h->ws) HIP_OK(h, hipFree(h->ws));
     h->ws = nullptr;
@@ -632,14 +825,9 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
     HIP_OK(h, hipMalloc(&h->ws, total));
     h->ws_bytes = total;
   }
-  {
-    char* base = (char*)h->ws;
-    for (auto& it : items) {
-      *it.ptr = it.bytes ? (void*)base : nullptr;
-      base += align_up(it.bytes);
-    }
-  }
+  ws_layout(h, a, b, (char*)h->ws);
   // CSR offsets: uploaded only when they change
+  const int R = n_rep;
   if ((int)h->off_cache.size() != R + 1 || std::memcmp(h->off_cache.data(), ion_offsets, (R + 1) * sizeof(int64_t))) {
     if (h->off_cap < (size_t)(R + 1)) {
       if (h->off_dev) HIP_OK(h, hipFree(h->off_dev));
@@ -650,66 +838,98 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
     HIP_OK(h, hipMemcpy(h->off_dev, ion_offsets, (size_t)(R + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     h->off_cache.assign(ion_offsets, ion_offsets + R + 1);
   }
-  b.R = R;
-  b.N = N;
-  b.max_nrep = (int)max_nrep;
   b.off = h->off_dev;
-  b.ion_xyz = ion_xyz;
-  b.ion_q = ion_q;
-  b.dpsi = dpsi;
-  b.seed = seed;
-  b.step = step;
-  b.kset_in = kset_in;
-  b.ele_xyz = h->ele_xyz;
-  b.ele_d = h->ele_d;
-  b.ele_fx = h->ele_fx;
-  b.ele_d4 = h->ele_d4;
-  b.ele_perm = h->ele_perm;
-  b.ele_scell = h->ele_scell;
-  b.ele_cstart = h->ele_cstart;
-  b.ele_czr = h->ele_czr;
-  b.ion_runs = h->ion_runs;
-  b.ele_runs = h->ele_runs;
-  b.ele_run_zr = h->ele_run_zr;
-  b.ele_sfx = h->ele_sfx;
-  b.ele_sd4 = h->ele_sd4;
-  b.nchunk_ion = nch_ion;
-  b.nchunk_ele = nch_ele;
-  b.ktiles = ktiles;
-  if (b_out) b.bstar = b_out;
-  b.status = h->status;
-  b.Q_out = Q_out;
-  b.F_out = F_out;
-  b.psibar_out = psibar_out;
-  if (energy_out) b.energy_out = energy_out;
-  b.kset_out = kset_out;
-  b.nacc_out = nullptr;
-  b.Q_in = Q_in;
+  return enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, s);
+}
 
-  // the sampler only reads the seeds: it runs beside the preparation pass
-  HIP_OK(h, hipEventRecord(h->ev_fork, s));
-  HIP_OK(h, hipStreamWaitEvent(h->aux, h->ev_fork, 0));
-  { PhaseTimer t(h, h->aux, 1); launch_sample(g, b, h->aux); }
-  HIP_OK(h, hipEventRecord(h->ev_join, h->aux));
-  { PhaseTimer t(h, s, 0); launch_prepare(g, b, fp32, s); }
-  HIP_OK(h, hipStreamWaitEvent(s, h->ev_join, 0));
-  { PhaseTimer t(h, s, 2); launch_sf_ions(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 3); launch_real_ele(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 4); launch_ele_potential(g, b, fp32, s); }
-  if (!fixedQ) {
-    PhaseTimer t(h, s, 5);
-    BLAS_OK(h, rocblas_set_stream(h->blas, s));
-    const double one = 1.0, zero = 0.0;
-    BLAS_OK(h, rocblas_dgemm(h->blas, rocblas_operation_none, rocblas_operation_none, n + 1, R, n, &one, h->Sext,
-                             n + 1, b.V, n, &zero, b.Qext, n + 1));
+int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                      const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
+                      uint64_t first_step, const int32_t* kset_in, const double* Q_in, double* Q_out, double* F_out,
+                      double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, srbe_graph** out) {
+  if (!h || !out) return SRBE_EINVAL;
+  *out = nullptr;
+  const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, kset_in,
+                   Q_in, Q_out, F_out, b_out, psibar_out, energy_out, kset_out};
+  int64_t max_nrep = 0;
+  int rc = check_step(h, a, max_nrep);
+  if (rc != SRBE_OK) return rc;
+  srbe_graph* gr = new srbe_graph();
+  gr->h = h;
+  auto fail = [&](int code) {
+    srbe_graph_destroy(gr);
+    return code;
+  };
+  StepBufs b{};
+  fill_bufs(h, a, max_nrep, b);
+  const size_t total = ws_layout(h, a, b, nullptr);
+  hipError_t e = hipMalloc(&gr->ws, std::max<size_t>(total, 256));
+  if (e == hipSuccess) e = hipMalloc((void**)&gr->off_dev, (size_t)(n_rep + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&gr->step_dev, sizeof(uint64_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(gr->off_dev, ion_offsets, (size_t)(n_rep + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(gr->step_dev, &first_step, sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_err(h, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP);
   }
-  { PhaseTimer t(h, s, 6); launch_post_charges(g, b, fixedQ, fp32, s); }
-  { PhaseTimer t(h, s, 7); launch_sf_ele(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 8); launch_ion_force(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 9); launch_real_ion(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 10); launch_energy(g, b, fixedQ, s); }
-  HIP_OK(h, hipGetLastError());
+  ws_layout(h, a, b, (char*)gr->ws);
+  b.off = gr->off_dev;
+  b.step_dev = gr->step_dev;
+  if ((e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    set_err(h, SRBE_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    return fail(SRBE_EHIP);
+  }
+  h->capturing = true;
+  rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, h->cap);
+  if (rc == SRBE_OK) launch_advance_step(gr->step_dev, h->cap);
+  h->capturing = false;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(h->cap, &graph);
+  if (rc != SRBE_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(rc);
+  }
+  if (e != hipSuccess) {
+    set_err(h, SRBE_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    return fail(SRBE_EHIP);
+  }
+  gr->graph = graph;
+  if ((e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+    set_err(h, SRBE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return fail(SRBE_EHIP);
+  }
+  *out = gr;
   return SRBE_OK;
+}
+
+int srbe_graph_launch(srbe_graph* gr, void* stream) {
+  if (!gr || !gr->exec) return SRBE_EINVAL;
+  HIP_OK(gr->h, hipGraphLaunch(gr->exec, (hipStream_t)stream));
+  return SRBE_OK;
+}
+
+int srbe_graph_set_step(srbe_graph* gr, uint64_t step, void* stream) {
+  if (!gr || !gr->step_dev) return SRBE_EINVAL;
+  launch_set_step(gr->step_dev, step, (hipStream_t)stream);
+  HIP_OK(gr->h, hipGetLastError());
+  return SRBE_OK;
+}
+
+void srbe_graph_destroy(srbe_graph* gr) {
+  if (!gr) return;
+  if (gr->h) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(gr->h->device);
+    (void)hipDeviceSynchronize();
+    (void)hipSetDevice(prev);
+  }
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  if (gr->ws) (void)hipFree(gr->ws);
+  if (gr->off_dev) (void)hipFree(gr->off_dev);
+  if (gr->step_dev) (void)hipFree(gr->step_dev);
+  delete gr;
 }
 
 const char* srbe_phase_name(int32_t phase) {

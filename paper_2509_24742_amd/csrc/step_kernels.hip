@@ -11,6 +11,7 @@
 // bitwise-identical results.
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels.h"
@@ -51,22 +52,49 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[NT / 64]
   __syncthreads();
 }
 
-// ============================================================ prepare
+// ============================================================ particle records
+// Per particle (grid: particle tiles x replicas): the fractional coordinates
+// s = (x/Lx, y/Ly, z/Lz), x and y wrapped into [0, 1), as 32-bit fixed point with
+// the FP32 charge (REC bit 0) and/or in FP64 with the FP64 charge (REC bit 1), in
+// input order; the range check (z in [0, H], finite coordinates and charge); and
+// the cell sort key (cell << 13 | index within the replica).
+template <int REC>
+__global__ __launch_bounds__(256) void k_records(Geom g, const int64_t* __restrict__ off,
+                                                 const double* __restrict__ xyz, const double* __restrict__ q,
+                                                 int64_t N, uint4* __restrict__ fx, double4* __restrict__ d4,
+                                                 unsigned* __restrict__ keys, unsigned* status) {
+  const int r = blockIdx.y;
+  const int64_t b0 = off[r];
+  const int n = (int)(off[r + 1] - b0);
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const int64_t i = b0 + k;
+  const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
+  const double qi = q ? q[i] : 0.0;
+  if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) atomicOr(status, ST_RANGE);
+  const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
+  keys[i] = ((unsigned)cell_index(g, sx, sy, z) << 13) | (unsigned)k;
+  if (REC & 1) fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
+  if (REC & 2) d4[i] = make_double4(sx, sy, sz, qi);
+}
+
+// ============================================================ cell lists
 // Per replica (one block of 1024 threads): sum q (neutrality), sum |q|, sum q z
-// (slab term of Eq. (17)), sum q^2 (self term); range checks; the particle records
-// of the k-space passes in input order; and the cell lists of the real-space
-// passes: a bitonic sort of the unique keys (cell << 13 | index) gives every cell
-// its particles in index order.
-template <bool FP32>
-__global__ __launch_bounds__(1024) void k_prepare(Geom g, const int64_t* __restrict__ off,
-                                                  const double* __restrict__ xyz, const double* __restrict__ q,
-                                                  int64_t N, double* __restrict__ scal, uint4* __restrict__ fx,
-                                                  double4* __restrict__ d4, int* __restrict__ perm,
-                                                  int* __restrict__ scell, int* __restrict__ cstart,
-                                                  uint4* __restrict__ sfx, double4* __restrict__ sd4,
-                                                  unsigned* status, int is_ions) {
-  __shared__ unsigned keys[kMaxBinParticles];
+// (slab term of Eq. (17)), sum q^2 (self term) when charges are given; a bitonic
+// sort of the unique keys gives every cell its particles in index order; the cell
+// starts (exclusive scan of the cell counts); and the records in cell order.
+template <int REC>
+__global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __restrict__ off,
+                                                   const double* __restrict__ xyz, const double* __restrict__ q,
+                                                   int64_t N, const unsigned* __restrict__ keys,
+                                                   const uint4* __restrict__ fx, const double4* __restrict__ d4,
+                                                   double* __restrict__ scal, int* __restrict__ perm,
+                                                   int* __restrict__ scell, int* __restrict__ cstart,
+                                                   uint4* __restrict__ sfx, double4* __restrict__ sd4,
+                                                   unsigned* status) {
+  __shared__ unsigned skeys[kMaxBinParticles];
   __shared__ int cnt[kMaxCells + 1];
+  __shared__ int scan[2][kMaxCells + 1];
   __shared__ double red[4][16];
   const int r = blockIdx.x;
   const int t = threadIdx.x;
@@ -77,35 +105,33 @@ __global__ __launch_bounds__(1024) void k_prepare(Geom g, const int64_t* __restr
   for (int c = t; c <= g.ncell; c += 1024) cnt[c] = 0;
   __syncthreads();
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  int bad = 0;
   for (int k = t; k < np; k += 1024) {
     if (k < n) {
-      const int64_t i = b0 + k;
-      const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
-      const double qi = is_ions ? q[i] : 0.0;
-      if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) bad = 1;
-      v[0] += qi;
-      v[1] += fabs(qi);
-      v[2] += qi * z;
-      v[3] += qi * qi;
-      const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
-      const int c = cell_index(g, sx, sy, z);
-      atomicAdd(&cnt[c], 1);
-      keys[k] = ((unsigned)c << 13) | (unsigned)k;
-      if (FP32 || !is_ions) fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
-      if (!FP32 || !is_ions) d4[i] = make_double4(sx, sy, sz, qi);
+      const unsigned key = keys[b0 + k];
+      skeys[k] = key;
+      atomicAdd(&cnt[key >> 13], 1);
+      if (q) {
+        const double qi = q[b0 + k], z = xyz[2 * N + b0 + k];
+        v[0] += qi;
+        v[1] += fabs(qi);
+        v[2] += qi * z;
+        v[3] += qi * qi;
+      }
     } else {
-      keys[k] = 0xFFFFFFFFu;
+      skeys[k] = 0xFFFFFFFFu;
     }
   }
-  if (bad) atomicOr(status, ST_RANGE);
-  block_sum<1024, 4>(v, red);
-  if (t == 0 && is_ions) {
-    scal[4 * r + 0] = v[0];
-    scal[4 * r + 1] = v[1];
-    scal[4 * r + 2] = v[2];
-    scal[4 * r + 3] = v[3];
-    if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(status, ST_NONNEUTRAL);
+  if (q) {
+    block_sum<1024, 4>(v, red);
+    if (t == 0) {
+      scal[4 * r + 0] = v[0];
+      scal[4 * r + 1] = v[1];
+      scal[4 * r + 2] = v[2];
+      scal[4 * r + 3] = v[3];
+      if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(status, ST_NONNEUTRAL);
+    }
+  } else {
+    __syncthreads();
   }
   // bitonic sort of the keys (ascending)
   for (int k = 2; k <= np; k <<= 1) {
@@ -113,11 +139,11 @@ __global__ __launch_bounds__(1024) void k_prepare(Geom g, const int64_t* __restr
       for (int i = t; i < np; i += 1024) {
         const int ixj = i ^ j;
         if (ixj > i) {
-          const unsigned a = keys[i], b = keys[ixj];
+          const unsigned a = skeys[i], b = skeys[ixj];
           const bool up = (i & k) == 0;
           if ((a > b) == up) {
-            keys[i] = b;
-            keys[ixj] = a;
+            skeys[i] = b;
+            skeys[ixj] = a;
           }
         }
       }
@@ -125,7 +151,6 @@ __global__ __launch_bounds__(1024) void k_prepare(Geom g, const int64_t* __restr
     }
   }
   // exclusive scan of the cell counts (Hillis-Steele over ncell + 1 entries)
-  __shared__ int scan[2][kMaxCells + 1];
   for (int c = t; c <= g.ncell; c += 1024) scan[0][c] = c == 0 ? 0 : cnt[c - 1];
   __syncthreads();
   int src = 0;
@@ -137,35 +162,45 @@ __global__ __launch_bounds__(1024) void k_prepare(Geom g, const int64_t* __restr
   int* cs = cstart + (size_t)r * (g.ncell + 1);
   for (int c = t; c <= g.ncell; c += 1024) cs[c] = scan[src][c];
   for (int k = t; k < n; k += 1024) {
-    const unsigned key = keys[k];
-    const int loc = (int)(key & 0x1FFFu);
-    const int64_t i = b0 + loc;
+    const unsigned key = skeys[k];
+    const int64_t i = b0 + (int)(key & 0x1FFFu);
     perm[b0 + k] = (int)i;
     scell[b0 + k] = (int)(key >> 13);
-    const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
-    const double qi = is_ions ? q[i] : 0.0;
-    const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
-    if (FP32 || !is_ions) sfx[b0 + k] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
-    if (!FP32 || !is_ions) sd4[b0 + k] = make_double4(sx, sy, sz, qi);
+    if (REC & 1) sfx[b0 + k] = fx[i];
+    if (REC & 2) sd4[b0 + k] = d4[i];
   }
 }
 
-void launch_prepare(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+void launch_records(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (b.max_nrep == 0) return;
+  dim3 grid(cdiv64(b.max_nrep, 256), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_prepare<true>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.scal,
-                       b.ion_fx, b.ion_d4, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status, 1);
+    hipLaunchKernelGGL(k_records<1>, grid, dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.ion_fx, b.ion_d4,
+                       b.keys, b.status);
   else
-    hipLaunchKernelGGL(k_prepare<false>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.scal,
-                       b.ion_fx, b.ion_d4, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status, 1);
+    hipLaunchKernelGGL(k_records<2>, grid, dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.ion_fx, b.ion_d4,
+                       b.keys, b.status);
 }
 
-// Electrodes are binned once per handle with the same kernel (both record formats).
-// off2: device {0, n_ele}; status: device word.
-void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, uint4* fx,
-                           double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4, unsigned* status,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_prepare<true>, dim3(1), dim3(1024), 0, s, g, off2, ele_xyz, (const double*)nullptr,
-                     (int64_t)n_ele, (double*)nullptr, fx, d4, perm, scell, cstart, sfx, sd4, status, 0);
+void launch_cellsort(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_cellsort<1>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.keys,
+                       b.ion_fx, b.ion_d4, b.scal, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status);
+  else
+    hipLaunchKernelGGL(k_cellsort<2>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.keys,
+                       b.ion_fx, b.ion_d4, b.scal, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status);
+}
+
+// Electrodes are binned once per handle with the same kernels (both record formats).
+// off2: device {0, n_ele}; keys: n_ele scratch words; status: device word.
+void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,
+                           uint4* fx, double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4,
+                           unsigned* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_records<3>, dim3(cdiv64(n_ele, 256), 1), dim3(256), 0, s, g, off2, ele_xyz,
+                     (const double*)nullptr, (int64_t)n_ele, fx, d4, keys, status);
+  hipLaunchKernelGGL(k_cellsort<3>, dim3(1), dim3(1024), 0, s, g, off2, ele_xyz, (const double*)nullptr,
+                     (int64_t)n_ele, (const unsigned*)keys, (const uint4*)fx, (const double4*)d4, (double*)nullptr,
+                     perm, scell, cstart, sfx, sd4, status);
 }
 
 // ============================================================ sampler
@@ -235,10 +270,12 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 
 __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restrict__ seeds, uint64_t step,
+                                                const uint64_t* __restrict__ step_dev,
                                                 const int32_t* __restrict__ kset_in, int4* __restrict__ modes,
                                                 double* __restrict__ wout, int32_t* __restrict__ kset_out,
                                                 int32_t* __restrict__ nacc_out, unsigned* status) {
   extern __shared__ unsigned char smem[];
+  if (step_dev) step = *step_dev;  // graph replays take the step from device memory
   const int r = blockIdx.x;
   const int P = g.P, M = g.M, K = g.K;
   const int t = threadIdx.x;
@@ -360,8 +397,21 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
 size_t sample_lds_bytes(int P) { return (size_t)P * (8 + 8 + 4 + 6) + 16; }
 
 void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample, dim3(b.R), dim3(256), sample_lds_bytes(g.P), s, g, b.seed, b.step, b.kset_in, b.modes,
-                     b.w, b.kset_out, b.nacc_out, b.status);
+  hipLaunchKernelGGL(k_sample, dim3(b.R), dim3(256), sample_lds_bytes(g.P), s, g, b.seed, b.step, b.step_dev,
+                     b.kset_in, b.modes, b.w, b.kset_out, b.nacc_out, b.status);
+}
+
+// Step counter of a captured step: set from the host, advanced at the end of each
+// replay.
+__global__ void k_set_step(uint64_t* step_dev, uint64_t v) { *step_dev = v; }
+__global__ void k_advance_step(uint64_t* step_dev) { *step_dev += 1; }
+
+void launch_set_step(uint64_t* step_dev, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, step_dev, v);
+}
+
+void launch_advance_step(uint64_t* step_dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, step_dev);
 }
 
 // ============================================================ structure factors
@@ -582,9 +632,10 @@ __device__ __forceinline__ unsigned lanes_below(uint64_t m) {
 // run can be skipped).  A wave round tests 64 candidates, one per lane (coalesced
 // loads): inside a run a round is 64 consecutive records; the remainder of a run
 // is topped up with the heads of the following runs (up to kSegMax pieces), so
-// short runs do not leave lanes idle.  test(j, entry) loads record j, fills the
-// pair entry and says whether the pair is within range (evaluated branch-free:
-// every lane of a round holds a valid j).  The hits of a round are appended in
+// short runs do not leave lanes idle.  load(j) reads record j (the records of the
+// next two full rounds are requested before the current round is tested);
+// test(record, j, entry) fills the pair entry and says whether the pair is within
+// range (evaluated branch-free: every lane of a round holds a valid j).  The hits of a round are appended in
 // candidate order to a wave-private LDS ring (positions from a ballot and a lane
 // prefix count; lanes without a hit write to their own slot past the ring, so the
 // store needs no branch).  Whenever 64 entries are queued every lane evaluates one;
@@ -596,9 +647,9 @@ constexpr int kRing = 128;
 constexpr int kRingAlloc = kRing + 64;  // ring + one discard slot per lane
 constexpr int kSegMax = 4;
 
-template <class Entry, class RangeF, class TestF, class EvalF>
+template <class Entry, class RangeF, class LoadF, class TestF, class EvalF>
 __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* __restrict__ ring, RangeF range,
-                                          TestF test, EvalF eval) {
+                                          LoadF load, TestF test, EvalF eval) {
   const int lane = threadIdx.x & 63;
   int s = 0, pos = 0, end = 0;
   unsigned head = 0, tail = 0;
@@ -614,9 +665,9 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
     }
     return pos < end;
   };
-  auto round = [&](int j, bool valid) {
+  auto round = [&](const auto& rec, int j, bool valid) {
     Entry ent;
-    const bool hit = test(j, ent) & valid;
+    const bool hit = test(rec, j, ent) & valid;
     const uint64_t m = __ballot(hit);
     const unsigned slot = hit ? ((tail + lanes_below(m)) & (kRing - 1)) : (unsigned)(kRing + lane);
     ring[slot] = ent;
@@ -628,9 +679,27 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
     }
   };
   while (next_run()) {
-    while (end - pos >= 64) {
-      round(pos + lane, true);
-      pos += 64;
+    if (end - pos >= 64) {
+      // full rounds inside the run, three record buffers in rotation: the records
+      // of the next two rounds are in flight while the current round is tested.
+      // Loads past the run are clamped to its last record and not used.  (Each
+      // buffer is reloaded in place after use, so no in-flight register is copied.)
+      auto ld = [&](int off) { return load(min(pos + off + lane, end - 1)); };
+      auto A = ld(0), B = ld(64), C = ld(128);
+      for (;;) {
+        round(A, pos + lane, true);
+        pos += 64;
+        if (end - pos < 64) break;
+        A = ld(128);
+        round(B, pos + lane, true);
+        pos += 64;
+        if (end - pos < 64) break;
+        B = ld(128);
+        round(C, pos + lane, true);
+        pos += 64;
+        if (end - pos < 64) break;
+        C = ld(128);
+      }
     }
     if (pos >= end) continue;
     // the run's remainder (< 64 records), topped up from the following runs:
@@ -657,96 +726,143 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
     for (int u = 1; u < kSegMax; ++u)
       if (lane >= from[u]) j = lane + base[u];
     const bool valid = lane < filled;
-    round(valid ? j : base[0], valid);  // lane 0 always holds a valid record
+    const int jj = valid ? j : base[0];  // lane 0 always holds a valid record
+    round(load(jj), jj, valid);
   }
   __builtin_amdgcn_wave_barrier();
   if ((unsigned)lane < tail - head) eval(ring[(head + lane) & (kRing - 1)]);
 }
 
-// Real-space potential of the ions at each electrode, visiting the ions of the
-// neighbouring cells: bN_j = ke sum_i q_i [erfc(alpha r) - erfc(r/eta)]/r, r < rc.
-// One wave per cell-sorted electrode.  In FP32 the erfc(r/eta) term is not
-// evaluated beyond eta_skip, where it is below 2^-30 of the kept term.
+// Real-space potential of the ions at each electrode (real-space part of Eq. (19)):
+// bN_j = ke sum_i q_i [erfc(alpha r) - erfc(r/eta)]/r over ions with r < rc.  One
+// lane per electrode: a wave takes up to 64 cell-sorted electrodes of one cell (the
+// chunk list is built at set-up), so its lanes share the cell's neighbour runs and
+// walk the same ion records in lockstep.  The records are uniform across the wave
+// (scalar loads, in groups requested one group ahead); each lane tests its own
+// distance and the pair
+// terms run only for the lanes in range.  Each lane adds its terms in record
+// order.  In FP32 the erfc(r/eta) term is not evaluated beyond eta_skip, where it
+// is below 2^-30 of the kept term.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_real_ele(Geom g, const int64_t* __restrict__ off,
-                                                  const int* __restrict__ cstart, const uint4* __restrict__ sfx,
-                                                  const double4* __restrict__ sd4, const int* __restrict__ ele_perm,
-                                                  const int* __restrict__ ele_scell,
-                                                  const int2* __restrict__ ion_runs,
-                                                  const uint4* __restrict__ ele_sfx,
-                                                  const double4* __restrict__ ele_sd4, double* __restrict__ bN) {
-  using Entry = typename std::conditional<FP32, float2, double2>::type;
-  __shared__ Entry ring_all[4][kRingAlloc];
+__global__ __launch_bounds__(64) void k_real_ele(Geom g, const int64_t* __restrict__ off,
+                                                 const int* __restrict__ cstart, const uint4* __restrict__ sfx,
+                                                 const double4* __restrict__ sd4, const int4* __restrict__ chunks,
+                                                 const int* __restrict__ ele_perm, const int2* __restrict__ ion_runs,
+                                                 const uint4* __restrict__ ele_sfx,
+                                                 const double4* __restrict__ ele_sd4, double* __restrict__ bN) {
   const int r = blockIdx.y;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int e = blockIdx.x * 4 + w;
-  if (e >= g.n_ele) return;  // whole wave
-  Entry* ring = ring_all[w];
+  const int4 ch = chunks[blockIdx.x];  // (cell, first, end) of this wave's electrodes
+  const int e = ch.y + (int)threadIdx.x;
+  const bool live = e < ch.z;
+  const int ec = live ? e : ch.y;
   const int b0 = (int)off[r];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
-  const int2* runs = ion_runs + kRunMax * __builtin_amdgcn_readfirstlane(ele_scell[e]);
-  auto range = [&](int, int2 rc, int& b, int& en) {
-    b = b0 + cs[rc.x];
-    en = b0 + cs[rc.y];
-  };
+  const int2* runs = ion_runs + kRunMax * ch.x;
   double sum;
   if constexpr (FP32) {
-    const uint4 pe = ele_sfx[e];
+    const uint4 pe = ele_sfx[ec];
     const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
     const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
     float acc = 0.f;
-    wave_scan(runs, ring, range,
-              [&](int j, float2& ent) {
-                const uint4 p = sfx[j];
-                const float dx = (float)(int32_t)(pe.x - p.x) * lx;
-                const float dy = (float)(int32_t)(pe.y - p.y) * ly;
-                const float dz = (float)(int32_t)(pe.z - p.z) * lz;
-                ent = make_float2(dx * dx + dy * dy + dz * dz, __uint_as_float(p.w));
-                return ent.x < rc2;
-              },
-              [&](const float2& en) {
-                const float rinv = __builtin_amdgcn_rsqf(en.x), rr = en.x * rinv;
-                float f1, h1, f2 = 0.f, h2;
-                erfc_pair_f(a1, rr, rinv, f1, h1);
-                if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
-                acc = fmaf(en.y, f1 - f2, acc);
-              });
-    sum = (double)wave_sum(acc);
+    auto pair = [&](const uint4& p) {
+      const float dx = (float)(int32_t)(pe.x - p.x) * lx;
+      const float dy = (float)(int32_t)(pe.y - p.y) * ly;
+      const float dz = (float)(int32_t)(pe.z - p.z) * lz;
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rc2) {
+        const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+        float f1, h1, f2 = 0.f, h2;
+        erfc_pair_f(a1, rr, rinv, f1, h1);
+        if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+        acc = fmaf(__uint_as_float(p.w), f1 - f2, acc);
+      }
+    };
+    for (int si = 0; si < kRunMax; ++si) {
+      const int2 rc = runs[si];
+      if (rc.x < 0) break;
+      const int je = b0 + cs[rc.y];
+      int j = b0 + cs[rc.x];
+      // groups of four records in two buffers: the next group is in flight while the
+      // current one is used (loads past the run are clamped to its last record)
+      if (j + 4 <= je) {
+        uint4 A[4], B[4];
+        auto ld = [&](uint4(&X)[4], int j0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) X[u] = sfx[min(j0 + u, je - 1)];
+        };
+        ld(A, j);
+        ld(B, j + 4);
+        for (;;) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pair(A[u]);
+          j += 4;
+          if (j + 4 > je) break;
+          ld(A, j + 4);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pair(B[u]);
+          j += 4;
+          if (j + 4 > je) break;
+          ld(B, j + 4);
+        }
+      }
+      for (; j < je; ++j) pair(sfx[j]);
+    }
+    sum = (double)acc;
   } else {
-    const double4 pe = ele_sd4[e];
+    const double4 pe = ele_sd4[ec];
     const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
     double acc = 0.0;
-    wave_scan(runs, ring, range,
-              [&](int j, double2& ent) {
-                const double4 p = sd4[j];
-                double sx = pe.x - p.x, sy = pe.y - p.y;
-                sx -= rint(sx);
-                sy -= rint(sy);
-                const double dx = sx * g.Lx, dy = sy * g.Ly, dz = (pe.z - p.z) * g.Lz;
-                ent = make_double2(dx * dx + dy * dy + dz * dz, p.w);
-                return ent.x < rc2;
-              },
-              [&](const double2& en) {
-                const double rr = sqrt(en.x);
-                double f1, d1, f2, d2;
-                erfc_over_r(a, rr, f1, d1);
-                erfc_over_r(ai, rr, f2, d2);
-                acc += en.y * (f1 - f2);
-              });
-    sum = wave_sum(acc);
+    auto pair = [&](const double4& p) {
+      double sx = pe.x - p.x, sy = pe.y - p.y;
+      sx -= rint(sx);
+      sy -= rint(sy);
+      const double dx = sx * g.Lx, dy = sy * g.Ly, dz = (pe.z - p.z) * g.Lz;
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 < rc2) {
+        const double rr = sqrt(r2);
+        double f1, d1, f2, d2;
+        erfc_over_r(a, rr, f1, d1);
+        erfc_over_r(ai, rr, f2, d2);
+        acc += p.w * (f1 - f2);
+      }
+    };
+    for (int si = 0; si < kRunMax; ++si) {
+      const int2 rc = runs[si];
+      if (rc.x < 0) break;
+      const int je = b0 + cs[rc.y];
+      int j = b0 + cs[rc.x];
+      if (j + 2 <= je) {
+        double4 cur[2], nxt[2];
+        cur[0] = sd4[j];
+        cur[1] = sd4[j + 1];
+        for (; j + 4 <= je; j += 2) {
+          nxt[0] = sd4[j + 2];
+          nxt[1] = sd4[j + 3];
+          pair(cur[0]);
+          pair(cur[1]);
+          cur[0] = nxt[0];
+          cur[1] = nxt[1];
+        }
+        pair(cur[0]);
+        pair(cur[1]);
+        j += 2;
+      }
+      for (; j < je; ++j) pair(sd4[j]);
+    }
+    sum = acc;
   }
-  if ((threadIdx.x & 63) == 0) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
+  if (live) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
 }
 
 void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (g.n_ele == 0) return;
-  dim3 grid(cdiv64(g.n_ele, 4), b.R);
+  dim3 grid(b.n_ele_chunks, b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_real_ele<true>, grid, dim3(256), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_perm,
-                       b.ele_scell, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
+    hipLaunchKernelGGL(k_real_ele<true>, grid, dim3(64), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_chunks,
+                       b.ele_perm, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
   else
-    hipLaunchKernelGGL(k_real_ele<false>, grid, dim3(256), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_perm,
-                       b.ele_scell, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
+    hipLaunchKernelGGL(k_real_ele<false>, grid, dim3(64), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_chunks,
+                       b.ele_perm, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
 }
 
 // The force and potential passes: 64 particles per block, the mode list split
@@ -764,13 +880,15 @@ __device__ __forceinline__ void quarter(int K, int& lo, int& hi) {
 // b*_j = -sum_k Re(coef_k exp(-i k.R_j))           (Eq. (24), coef = w S1)
 //        - (4 pi ke / V) Z_j sum_i q_i z_i          (slab term, minus sign)
 //        - bN_j                                     (real space)
-// and V_j = b*_j + dpsi d_j, the right-hand side of the charge solve.
+// and V_j = b*_j + dpsi d_j, the right-hand side of the charge solve (rows of
+// ldcp(n) doubles per replica for the GEMM below).
 __device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double acc_quarter, double (*sh)[64],
                                              const double* ele_xyz, const double* ele_d, const double* scal,
                                              const double* dpsi, const double* bN, double* bstar, double* V) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   sh[w][lane] = acc_quarter;
   __syncthreads();
+  if (w == 0 && j >= g.n_ele && j < ldcp(g.n_ele)) V[(size_t)r * ldcp(g.n_ele) + j] = 0.0;  // padding
   if (w == 0 && j < g.n_ele) {
     const double acc = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
     const int n = g.n_ele;
@@ -778,7 +896,7 @@ __device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double
     const size_t idx = (size_t)r * n + j;
     const double b = -acc - (4.0 * M_PI * g.ke / g.V) * Z * scal[4 * r + 2] - bN[idx];
     bstar[idx] = b;
-    V[idx] = b + dpsi[r] * ele_d[j];
+    V[(size_t)r * ldcp(n) + j] = b + dpsi[r] * ele_d[j];
   }
 }
 
@@ -858,11 +976,133 @@ void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_
                        b.dpsi, b.bN, b.bstar, b.V);
 }
 
+// ============================================================ charge solve
+// [Q; psibar] = S_ext V (Eqs. (9)-(11)).  S_ext: (n+1) rows of ld = ldcp(n) doubles
+// (row-major; the n x n block is symmetric); V: one row of ld doubles per replica;
+// both zero-padded to ld, a multiple of 16.  FP64 MFMA v_mfma_f64_16x16x4f64:
+// lane l supplies A[l%16][k(l)] and B[k(l)][l%16], the result register v of lane l
+// is row l/16 + 4 v, column l%16.  The contraction index k(l) may be any
+// assignment of the 4 k values to the 4 lane groups as long as A and B use the
+// same one: here a lane holds 4 consecutive k of its row (32-byte loads of S_ext
+// and V) and MFMA step u takes the u-th of them.  A wave computes 16 rows x 64
+// replicas (four 16 x 16 tiles sharing the A operand) over its k range, the loads
+// of the next 16 k in flight during the MFMAs of the current.  Rows past n and
+// replicas past R read row 0 / replica 0 (valid memory) and their results are not
+// stored.  Block = 4 waves splitting the block's k range; partial tiles are added
+// in wave order through LDS.  Grid: (row tiles, replica groups of 64, ksplit
+// k-ranges); each k-range writes its own partial, summed in order after the GEMM.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct GemmFrag {
+  double2 a[2], b[4][2];
+};
+
+__global__ __launch_bounds__(256) void k_cp_gemm(int n, int R, const double* __restrict__ S,
+                                                 const double* __restrict__ V, double* __restrict__ Qpart) {
+  __shared__ double red[4][1024];
+  const int ld = ldcp(n);
+  const int rt = blockIdx.x, cg = blockIdx.y, h = blockIdx.z, ks = gridDim.z;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // 16-k blocks: the whole range split into ks block ranges, each into 4 wave ranges
+  const int nb = ld / 16;
+  const int hb0 = (int)((int64_t)nb * h / ks), hb1 = (int)((int64_t)nb * (h + 1) / ks);
+  const int kb0 = hb0 + (int)((int64_t)(hb1 - hb0) * w / 4), kb1 = hb0 + (int)((int64_t)(hb1 - hb0) * (w + 1) / 4);
+  const int i = rt * 16 + (lane & 15);
+  const int kq = 4 * (lane >> 4);
+  const double* Ap = S + (size_t)(i <= n ? i : 0) * ld + kq;
+  const double* Bp[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = cg * 64 + t * 16 + (lane & 15);
+    Bp[t] = V + (size_t)(r < R ? r : 0) * ld + kq;
+  }
+  auto load = [&](int kb, GemmFrag& f) {
+    const int k0 = kb * 16;
+    f.a[0] = *(const double2*)(Ap + k0);
+    f.a[1] = *(const double2*)(Ap + k0 + 2);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f.b[t][0] = *(const double2*)(Bp[t] + k0);
+      f.b[t][1] = *(const double2*)(Bp[t] + k0 + 2);
+    }
+  };
+  f64x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto mma = [&](const GemmFrag& f) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double a = (u & 1) ? f.a[u >> 1].y : f.a[u >> 1].x;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double bv = (u & 1) ? f.b[t][u >> 1].y : f.b[t][u >> 1].x;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
+      }
+    }
+  };
+  if (kb0 < kb1) {
+    // the next block's loads are issued before the current block's MFMAs (a load
+    // past the range repeats the last block and is not used)
+    GemmFrag cur;
+    load(kb0, cur);
+    for (int kb = kb0; kb < kb1; ++kb) {
+      GemmFrag nxt;
+      load(min(kb + 1, kb1 - 1), nxt);
+      mma(cur);
+      cur = nxt;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][(t * 4 + v) * 64 + lane] = acc[t][v];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int f = threadIdx.x + 256 * q;
+    const double sum = ((red[0][f] + red[1][f]) + red[2][f]) + red[3][f];
+    const int l = f & 63, v = (f >> 6) & 3, t = f >> 8;
+    const int row = rt * 16 + (l >> 4) + 4 * v, r = cg * 64 + t * 16 + (l & 15);
+    if (row <= n && r < R) Qpart[((size_t)h * R + r) * (n + 1) + row] = sum;
+  }
+}
+
+// k-ranges: enough blocks for about two per CU of a 256-CU device, at most 8
+// partials.
+int cp_gemm_ksplit(int n_ele, int R) {
+  const int blocks = ((n_ele + 1 + 15) / 16) * ((R + 63) / 64);
+  return std::max(1, std::min(8, (512 + blocks - 1) / blocks));
+}
+
+void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s) {
+  const int n = g.n_ele;
+  hipLaunchKernelGGL(k_cp_gemm, dim3((n + 1 + 15) / 16, (b.R + 63) / 64, b.ksplit), dim3(256), 0, s, n, b.R, Sext,
+                     b.V, b.Qext);
+}
+
 // ============================================================ after the charge solve
 // Per replica: copy Q (and psibar) out of the GEMM result (or the fixed charges);
 // the copies of Q the later passes read (FP32 original order and cell-sorted
 // order); sums of Q Z (slab term), d.Q and b*.Q (energy).
-__global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __restrict__ Qext,
+// Per-replica sums after the charge solve (sum Q Z, sum Q d, sum Q b*), kept as
+// kRsumParts partial sums (one per post-charges block of the replica) and always
+// added in part order.
+constexpr int kRsumParts = 4;
+constexpr int kRsumStride = 4 * kRsumParts;
+
+__device__ __forceinline__ double rsum_total(const double* rsum, int r, int q) {
+  const double* rs = rsum + (size_t)r * kRsumStride + q;
+  return ((rs[0] + rs[4]) + rs[8]) + rs[12];
+}
+
+// Q_j of replica r: the given charges, or the GEMM partials added in k-range order.
+__device__ __forceinline__ double solved_q(const double* __restrict__ Qext, int ksplit, int R, int r, int n, int j) {
+  double q = Qext[(size_t)r * (n + 1) + j];
+  for (int h = 1; h < ksplit; ++h) q += Qext[((size_t)h * R + r) * (n + 1) + j];
+  return q;
+}
+
+__global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __restrict__ Qext, int ksplit,
                                                       const double* __restrict__ Q_in, const double* __restrict__ ele_xyz,
                                                       const double* __restrict__ ele_d, const int* __restrict__ ele_perm,
                                                       const double* __restrict__ bstar, double* __restrict__ Q_out,
@@ -870,12 +1110,13 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
                                                       double* __restrict__ Qsd, double* __restrict__ psibar,
                                                       double* __restrict__ rsum, unsigned* status) {
   __shared__ double sh[3][4];
-  const int r = blockIdx.x;
+  const int r = blockIdx.x, pc = blockIdx.y, R = gridDim.x;
   const int n = g.n_ele;
+  const int j0 = (int)((int64_t)n * pc / kRsumParts), j1 = (int)((int64_t)n * (pc + 1) / kRsumParts);
   double v[3] = {0.0, 0.0, 0.0};
   int bad = 0;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    const double Qj = Q_in ? Q_in[(size_t)r * n + j] : Qext[(size_t)r * (n + 1) + j];
+  for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+    const double Qj = Q_in ? Q_in[(size_t)r * n + j] : solved_q(Qext, ksplit, R, r, n, j);
     if (!isfinite(Qj)) bad = 1;
     Q_out[(size_t)r * n + j] = Qj;
     if (Qf) Qf[(size_t)r * n + j] = (float)Qj;
@@ -883,24 +1124,25 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
     v[1] += Qj * ele_d[j];
     v[2] += Qj * bstar[(size_t)r * n + j];
   }
-  for (int k = threadIdx.x; k < n; k += 256) {
+  for (int k = j0 + threadIdx.x; k < j1; k += 256) {
     const int j = ele_perm[k];
-    const double Qj = Q_in ? Q_in[(size_t)r * n + j] : Qext[(size_t)r * (n + 1) + j];
+    const double Qj = Q_in ? Q_in[(size_t)r * n + j] : solved_q(Qext, ksplit, R, r, n, j);
     if (Qsf) Qsf[(size_t)r * n + k] = (float)Qj;
     if (Qsd) Qsd[(size_t)r * n + k] = Qj;
   }
   if (bad) atomicOr(status, ST_NUMERIC);
   block_sum<256, 3>(v, sh);
   if (threadIdx.x == 0) {
-    rsum[8 * r + 0] = v[0];
-    rsum[8 * r + 1] = v[1];
-    rsum[8 * r + 2] = v[2];
-    if (psibar) psibar[r] = Q_in ? (double)NAN : Qext[(size_t)r * (n + 1) + n];
+    double* rs = rsum + (size_t)r * kRsumStride + 4 * pc;
+    rs[0] = v[0];
+    rs[1] = v[1];
+    rs[2] = v[2];
+    if (psibar && pc == 0) psibar[r] = Q_in ? (double)NAN : solved_q(Qext, ksplit, R, r, n, n);
   }
 }
 
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s) {
-  hipLaunchKernelGGL(k_post_charges, dim3(b.R), dim3(256), 0, s, g, b.Qext, fixedQ ? b.Q_in : nullptr, b.ele_xyz,
+  hipLaunchKernelGGL(k_post_charges, dim3(b.R, kRsumParts), dim3(256), 0, s, g, b.Qext, b.ksplit, fixedQ ? b.Q_in : nullptr, b.ele_xyz,
                      b.ele_d, b.ele_perm, b.bstar, b.Q_out, fp32 ? b.Qf : nullptr, fp32 ? b.Qsf : nullptr,
                      fp32 ? nullptr : b.Qsd, b.psibar_out, b.rsum, b.status);
 }
@@ -910,7 +1152,7 @@ void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32,
 //       - (4 pi ke / V) q_i M_z e_z             (slab force, M_z = sum q z + sum Q Z)
 __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, bool live, double qi, double gx,
                                                double gy, double gz, double (*sh)[3][64], const double* scal,
-                                               const double* rsum, int64_t N, double* F) {
+                                               const double* rsum, const double* Fii, int64_t N, double* F) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   sh[w][0][lane] = gx;
   sh[w][1][lane] = gy;
@@ -920,9 +1162,11 @@ __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, 
     double gsum[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) gsum[d] = ((sh[0][d][lane] + sh[1][d][lane]) + sh[2][d][lane]) + sh[3][d][lane];
-    F[i] = -qi * gsum[0];
-    F[N + i] = -qi * gsum[1];
-    F[2 * N + i] = -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum[8 * r + 0]);
+    const double kq = g.ke * qi;  // the ion-ion real-space sums join here
+    F[i] = -qi * gsum[0] + kq * Fii[i];
+    F[N + i] = -qi * gsum[1] + kq * Fii[N + i];
+    F[2 * N + i] = -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum_total(rsum, r, 0)) +
+                   kq * Fii[2 * N + i];
   }
 }
 
@@ -930,7 +1174,7 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
                                                     const double4* __restrict__ ion_d4, int64_t N,
                                                     const int4* __restrict__ modes, const double2* __restrict__ coef,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    double* __restrict__ F) {
+                                                    const double* __restrict__ Fii, double* __restrict__ F) {
   __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
@@ -955,14 +1199,14 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
     gy = fma(TWO_PI * (double)m.y * g.invLy, im, gy);
     gz = fma(TWO_PI * (double)m.z * g.invLz, im, gz);
   }
-  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, N, F);
+  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, Fii, N, F);
 }
 
 __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __restrict__ off,
                                                     const uint4* __restrict__ ion_fx, int64_t N,
                                                     const ModeRec32* __restrict__ rec,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    double* __restrict__ F) {
+                                                    const double* __restrict__ Fii, double* __restrict__ F) {
   __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
@@ -1015,38 +1259,36 @@ __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __res
     gy += (double)ay;
     gz += (double)az;
   }
-  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, N, F);
+  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, Fii, N, F);
 }
 
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   dim3 grid(cdiv64(b.max_nrep, 64), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum, b.F_out);
+    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum, b.Fii,
+                       b.F_out);
   else
     hipLaunchKernelGGL(k_ionforce64, grid, dim3(256), 0, s, g, b.off, b.ion_d4, b.N, b.modes, b.coef, b.scal, b.rsum,
-                       b.F_out);
+                       b.Fii, b.F_out);
 }
 
 // ============================================================ ion forces, real space
 // F_i += -ke q_i sum_j q_j K_ii'(r) r^ - ke q_i sum_e Q_e K_ig'(r) r^ over the
 // neighbouring cells (r < rc), phi_i = ke sum_j q_j K_ii(r) (for the energy).
-// One wave per cell-sorted ion (see wave_scan); results go to the ion's input
-// position.  An electrode run (one z-layer) whose z-extent lies farther than rc
-// from the ion cannot hold a partner and is skipped.
+// One wave per cell-sorted ion (see wave_scan).  Two kernels: the ion-ion part,
+// which does not depend on the electrode charges and runs beside the k-space and
+// charge-solve passes, leaves its sums in Fii (input order; the k-space force pass
+// adds them); the ion-electrode part, after the charge solve, visits only the ions
+// of the cells that can reach an electrode (reach ranges built at set-up) and adds
+// its sums to F.  An electrode run (one z-layer) whose z-extent lies farther than
+// rc from the ion cannot hold a partner and is skipped.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restrict__ off, int64_t N,
-                                                  const int* __restrict__ cstart, const int* __restrict__ perm,
-                                                  const int* __restrict__ scell,
-                                                  const int2* __restrict__ ion_runs,
-                                                  const int2* __restrict__ ele_runs,
-                                                  const double2* __restrict__ ele_run_zr,
-                                                  const uint4* __restrict__ sfx,
-                                                  const double4* __restrict__ sd4, const int* __restrict__ ele_cstart,
-                                                  const uint4* __restrict__ ele_sfx,
-                                                  const double4* __restrict__ ele_sd4, const float* __restrict__ Qsf,
-                                                  const double* __restrict__ Qsd, double* __restrict__ F,
-                                                  double* __restrict__ phi) {
+__global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restrict__ off, int64_t N,
+                                                 const int* __restrict__ cstart, const int* __restrict__ perm,
+                                                 const int* __restrict__ scell, const int2* __restrict__ ion_runs,
+                                                 const uint4* __restrict__ sfx, const double4* __restrict__ sd4,
+                                                 double* __restrict__ Fii, double* __restrict__ phi) {
   using Entry = typename std::conditional<FP32, float4, double4>::type;
   __shared__ Entry ring_all[4][kRingAlloc];
   const int r = blockIdx.y;
@@ -1056,32 +1298,19 @@ __global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restr
   if (k >= b1) return;  // whole wave
   Entry* ring = ring_all[w];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
-  const int home = __builtin_amdgcn_readfirstlane(scell[k]);
-  const int2* iruns = ion_runs + kRunMax * home;
-  const int2* eruns = ele_runs + kRunMax * home;
-  const double2* erz = ele_run_zr + kRunMax * home;
-  const int n = g.n_ele;
-  const double zlim = g.rc + 1e-6;  // skip test margin (fixed-point z is exact to ~1e-8 of the box)
+  const int2* iruns = ion_runs + kRunMax * __builtin_amdgcn_readfirstlane(scell[k]);
   auto ion_range = [&](int, int2 rc, int& b, int& e) {
     b = b0 + cs[rc.x];
     e = b0 + cs[rc.y];
   };
-  double fx, fy, fz, ph, qi;
+  double fx, fy, fz, ph;
   if constexpr (FP32) {
     const uint4 pi_ = sfx[k];
-    const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
-    auto ele_range = [&](int si, int2 rc, int& b, int& e) {
-      const double2 zr = erz[si];
-      b = ele_cstart[rc.x];
-      e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[rc.y];
-    };
     const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
-    const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
-    const float* Qr = Qsf + (size_t)r * n;
+    const float a1 = (float)g.alpha, rc2 = (float)(g.rc * g.rc);
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
-    wave_scan(iruns, ring, ion_range,
-              [&](int j, float4& ent) {
-                const uint4 p = sfx[j];
+    wave_scan(iruns, ring, ion_range, [&](int j) { return sfx[j]; },
+              [&](const uint4& p, int j, float4& ent) {
                 ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
                 ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
                 ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
@@ -1099,56 +1328,24 @@ __global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restr
                 ay = fmaf(s_, en.y, ay);
                 az = fmaf(s_, en.z, az);
               });
-    wave_scan(eruns, ring, ele_range,
-              [&](int j, float4& ent) {
-                const uint4 p = ele_sfx[j];
-                ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
-                ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
-                ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
-                ent.w = Qr[j];
-                return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
-              },
-              [&](const float4& en) {
-                const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
-                const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
-                float f1, h1, f2, h2 = 0.f;
-                erfc_pair_f(a1, rr, rinv, f1, h1);
-                if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
-                const float s_ = en.w * (h1 - h2);
-                ax = fmaf(s_, en.x, ax);
-                ay = fmaf(s_, en.y, ay);
-                az = fmaf(s_, en.z, az);
-              });
     fx = (double)wave_sum(ax);
     fy = (double)wave_sum(ay);
     fz = (double)wave_sum(az);
     ph = (double)wave_sum(ap);
-    qi = (double)__uint_as_float(pi_.w);
   } else {
     const double4 pi_ = sd4[k];
-    const double zi = pi_.z * g.Lz;
-    auto ele_range = [&](int si, int2 rc, int& b, int& e) {
-      const double2 zr = erz[si];
-      b = ele_cstart[rc.x];
-      e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? b : ele_cstart[rc.y];
-    };
-    const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
-    const double* Qr = Qsd + (size_t)r * n;
+    const double a = g.alpha, rc2 = g.rc * g.rc;
     double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
-    auto delta = [&](const double4& p, double4& ent) {
-      double sx = pi_.x - p.x, sy = pi_.y - p.y;
-      sx -= rint(sx);
-      sy -= rint(sy);
-      ent.x = sx * g.Lx;
-      ent.y = sy * g.Ly;
-      ent.z = (pi_.z - p.z) * g.Lz;
-      return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
-    };
-    wave_scan(iruns, ring, ion_range,
-              [&](int j, double4& ent) {
-                const double4 p = sd4[j];
+    wave_scan(iruns, ring, ion_range, [&](int j) { return sd4[j]; },
+              [&](const double4& p, int j, double4& ent) {
+                double sx = pi_.x - p.x, sy = pi_.y - p.y;
+                sx -= rint(sx);
+                sy -= rint(sy);
+                ent.x = sx * g.Lx;
+                ent.y = sy * g.Ly;
+                ent.z = (pi_.z - p.z) * g.Lz;
                 ent.w = p.w;
-                return delta(p, ent) & (j != k);
+                return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
               },
               [&](const double4& en) {
                 const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
@@ -1160,46 +1357,164 @@ __global__ __launch_bounds__(256) void k_real_ion(Geom g, const int64_t* __restr
                 ay += s_ * en.y;
                 az += s_ * en.z;
               });
-    wave_scan(eruns, ring, ele_range,
-              [&](int j, double4& ent) {
-                ent.w = Qr[j];
-                return delta(ele_sd4[j], ent);
-              },
-              [&](const double4& en) {
-                const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
-                double f1, d1, f2, d2;
-                erfc_over_r(a, rr, f1, d1);
-                erfc_over_r(ai, rr, f2, d2);
-                const double s_ = -en.w * (d1 - d2) / rr;
-                ax += s_ * en.x;
-                ay += s_ * en.y;
-                az += s_ * en.z;
-              });
     fx = wave_sum(ax);
     fy = wave_sum(ay);
     fz = wave_sum(az);
     ph = wave_sum(ap);
-    qi = pi_.w;
   }
   if ((threadIdx.x & 63) == 0) {
     const int i = perm[k];
-    const double kq = g.ke * qi;
-    F[i] += kq * fx;
-    F[N + i] += kq * fy;
-    F[2 * N + i] += kq * fz;
+    Fii[i] = fx;
+    Fii[N + i] = fy;
+    Fii[2 * N + i] = fz;
     phi[i] = g.ke * ph;
   }
 }
 
-void launch_real_ion(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_real_ie(Geom g, const int64_t* __restrict__ off, int64_t N,
+                                                 const int* __restrict__ cstart, const int2* __restrict__ reach,
+                                                 int nreach, const int* __restrict__ perm,
+                                                 const int* __restrict__ scell, const int2* __restrict__ ele_runs,
+                                                 const double2* __restrict__ ele_run_zr,
+                                                 const uint4* __restrict__ sfx, const double4* __restrict__ sd4,
+                                                 const int* __restrict__ ele_cstart,
+                                                 const uint4* __restrict__ ele_sfx,
+                                                 const double4* __restrict__ ele_sd4, const float* __restrict__ Qsf,
+                                                 const double* __restrict__ Qsd, double* __restrict__ F) {
+  using Entry = typename std::conditional<FP32, float4, double4>::type;
+  __shared__ Entry ring_all[4][kRingAlloc];
+  const int r = blockIdx.y;
+  const int b0 = (int)off[r];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gw = blockIdx.x * 4 + w, stride = gridDim.x * 4;
+  Entry* ring = ring_all[w];
+  const int* cs = cstart + (size_t)r * (g.ncell + 1);
+  const int n = g.n_ele;
+  const double zlim = g.rc + 1e-6;  // skip test margin (fixed-point z is exact to ~1e-8 of the box)
+  for (int qr = 0; qr < nreach; ++qr) {
+    const int2 cr = reach[qr];
+    const int kend = b0 + cs[cr.y];
+    for (int k = b0 + cs[cr.x] + gw; k < kend; k += stride) {
+      const int home = __builtin_amdgcn_readfirstlane(scell[k]);
+      const int2* eruns = ele_runs + kRunMax * home;
+      const double2* erz = ele_run_zr + kRunMax * home;
+      double fx, fy, fz, qi;
+      if constexpr (FP32) {
+        const uint4 pi_ = sfx[k];
+        const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
+        auto ele_range = [&](int si, int2 rc, int& bb, int& e) {
+          const double2 zr = erz[si];
+          bb = ele_cstart[rc.x];
+          e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb : ele_cstart[rc.y];
+        };
+        const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
+        const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
+        const float* Qr = Qsf + (size_t)r * n;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        wave_scan(eruns, ring, ele_range,
+                  [&](int j) {
+                    uint4 p = ele_sfx[j];
+                    p.w = __float_as_uint(Qr[j]);
+                    return p;
+                  },
+                  [&](const uint4& p, int, float4& ent) {
+                    ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
+                    ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
+                    ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
+                    ent.w = __uint_as_float(p.w);
+                    return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+                  },
+                  [&](const float4& en) {
+                    const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
+                    const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+                    float f1, h1, f2, h2 = 0.f;
+                    erfc_pair_f(a1, rr, rinv, f1, h1);
+                    if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+                    const float s_ = en.w * (h1 - h2);
+                    ax = fmaf(s_, en.x, ax);
+                    ay = fmaf(s_, en.y, ay);
+                    az = fmaf(s_, en.z, az);
+                  });
+        fx = (double)wave_sum(ax);
+        fy = (double)wave_sum(ay);
+        fz = (double)wave_sum(az);
+        qi = (double)__uint_as_float(pi_.w);
+      } else {
+        const double4 pi_ = sd4[k];
+        const double zi = pi_.z * g.Lz;
+        auto ele_range = [&](int si, int2 rc, int& bb, int& e) {
+          const double2 zr = erz[si];
+          bb = ele_cstart[rc.x];
+          e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb : ele_cstart[rc.y];
+        };
+        const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
+        const double* Qr = Qsd + (size_t)r * n;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        wave_scan(eruns, ring, ele_range,
+                  [&](int j) {
+                    double4 p = ele_sd4[j];
+                    p.w = Qr[j];
+                    return p;
+                  },
+                  [&](const double4& p, int, double4& ent) {
+                    double sx = pi_.x - p.x, sy = pi_.y - p.y;
+                    sx -= rint(sx);
+                    sy -= rint(sy);
+                    ent.x = sx * g.Lx;
+                    ent.y = sy * g.Ly;
+                    ent.z = (pi_.z - p.z) * g.Lz;
+                    ent.w = p.w;
+                    return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+                  },
+                  [&](const double4& en) {
+                    const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
+                    double f1, d1, f2, d2;
+                    erfc_over_r(a, rr, f1, d1);
+                    erfc_over_r(ai, rr, f2, d2);
+                    const double s_ = -en.w * (d1 - d2) / rr;
+                    ax += s_ * en.x;
+                    ay += s_ * en.y;
+                    az += s_ * en.z;
+                  });
+        fx = wave_sum(ax);
+        fy = wave_sum(ay);
+        fz = wave_sum(az);
+        qi = pi_.w;
+      }
+      if ((threadIdx.x & 63) == 0) {
+        const int i = perm[k];
+        const double kq = g.ke * qi;
+        F[i] += kq * fx;
+        F[N + i] += kq * fy;
+        F[2 * N + i] += kq * fz;
+      }
+    }
+  }
+}
+
+void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   dim3 grid(cdiv64(b.max_nrep, 4), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_real_ion<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
-                       b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
+    hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
+                       b.sfx, b.sd4, b.Fii, b.phi);
   else
-    hipLaunchKernelGGL(k_real_ion<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
-                       b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf, b.Qsd, b.F_out, b.phi);
+    hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
+                       b.sfx, b.sd4, b.Fii, b.phi);
+}
+
+void launch_real_ie(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (b.max_nrep == 0 || b.nreach == 0) return;
+  dim3 grid(64, b.R);  // 256 waves per replica walk its reach ranges
+  if (fp32)
+    hipLaunchKernelGGL(k_real_ie<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.reach, b.nreach, b.perm,
+                       b.scell, b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf,
+                       b.Qsd, b.F_out);
+  else
+    hipLaunchKernelGGL(k_real_ie<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.reach, b.nreach, b.perm,
+                       b.scell, b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf,
+                       b.Qsd, b.F_out);
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
@@ -1245,7 +1560,7 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int64_t* __restric
   if (threadIdx.x == 0) {
     const double c = 0.5 * v[0] + 0.5 * v[1] - g.ke * g.alpha * INV_SQRT_PI * scal[4 * r + 3] +
                      g.ke * (2.0 * M_PI / g.V) * scal[4 * r + 2] * scal[4 * r + 2];
-    const double E = 0.5 * dpsi[r] * rsum[8 * r + 1] - 0.5 * rsum[8 * r + 2] + c;
+    const double E = 0.5 * dpsi[r] * rsum_total(rsum, r, 1) - 0.5 * rsum_total(rsum, r, 2) + c;
     if (!fixedQ && !isfinite(E)) atomicOr(status, ST_NUMERIC);
     energy[r] = fixedQ ? (double)NAN : E;
   }
