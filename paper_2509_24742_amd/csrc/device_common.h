@@ -21,6 +21,7 @@ struct Geom {
   double alpha, eta, rc, ke;
   double G;        // normaliser of Eq. (27)
   double sig[3];   // proposal standard deviation per axis (in units of m)
+  int qmax[3];     // log q_d(m) is tabulated for |m| <= qmax[d]
   int M, P, K;     // K = M + P modes per replica
   int n_ele;
   // real-space cell grid: ncx x ncy cells over the periodic x, y extent, ncz over

@@ -29,6 +29,7 @@ struct StepBufs {
   uint64_t step;
   const uint64_t* step_dev; // graph replays: the step is read from here (null: use step)
   const int32_t* kset_in;   // R*P*3 or null
+  const double* logq;       // sampler table of log q_d(m), |m| <= qmax[d] (per handle)
   // electrodes (device, fixed): original order and cell-sorted order
   const double* ele_xyz;    // SoA 3*n_ele
   const double* ele_d;      // n_ele
@@ -91,6 +92,7 @@ void launch_records(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_cellsort(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s);
 void launch_set_step(uint64_t* step_dev, uint64_t v, hipStream_t s);
+void launch_logq_table(const Geom& g, double* T, hipStream_t s);
 void launch_advance_step(uint64_t* step_dev, hipStream_t s);
 void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);

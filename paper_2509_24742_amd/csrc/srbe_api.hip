@@ -44,12 +44,13 @@ struct srbe_system {
   // stream graphs are captured on
   hipStream_t aux[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[8] = {};
   bool capturing = false;
   unsigned* bin_keys = nullptr;  // n_ele scratch for the electrode binning
   int2* reach = nullptr;         // cell ranges whose ions can be within rc of an electrode
   int nreach = 0;
   int4* ele_chunks = nullptr;    // (cell, first, end): <= 64 cell-sorted electrodes of one cell
+  double* logq = nullptr;        // sampler table log q_d(m), |m| <= qmax[d]
   int n_ele_chunks = 0;
   // workspace
   void* ws = nullptr;
@@ -155,6 +156,8 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   g.sig[0] = p.alpha * p.Lx / (std::sqrt(2.0) * M_PI);
   g.sig[1] = p.alpha * p.Ly / (std::sqrt(2.0) * M_PI);
   g.sig[2] = p.alpha * g.Lz / (std::sqrt(2.0) * M_PI);
+  // proposals are sigma z with |z| <= sqrt(-2 ln 2^-53) < 9: tabulate log q_d(m) to 9 sigma + 2
+  for (int d = 0; d < 3; ++d) g.qmax[d] = std::min(1 << 20, (int)std::ceil(9.0 * g.sig[d]) + 2);
   g.M = p.M;
   g.P = p.P;
   g.K = p.M + p.P;
@@ -416,6 +419,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.step = a.step;
   b.step_dev = nullptr;
   b.kset_in = a.kset_in;
+  b.logq = h->logq;
   b.ele_xyz = h->ele_xyz;
   b.ele_d = h->ele_d;
   b.ele_fx = h->ele_fx;
@@ -492,42 +496,51 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
   return total;
 }
 
-enum { EV_FORK = 0, EV_SAMPLE, EV_REC, EV_BN, EV_II };
+enum { EV_FORK = 0, EV_SAMPLE, EV_REC, EV_BN, EV_PHI, EV_POST, EV_II, EV_E };
 
 // The step as a DAG over three streams (Algorithm 1's order within each chain):
-//   aux[0]:  sample
+//   aux[0]:  sample -> (post_charges, real_ii) energy
 //   s:       records -> (sample) sf_ions -> (real_ele) ele_potential -> cp_gemm ->
-//            post_charges -> sf_ele -> (real_ii) ion_force -> real_ie -> energy
-//   aux[1]:  (records) cellsort -> real_ele -> real_ii
+//            post_charges -> sf_ele -> (real_ie) ion_force -> (energy)
+//   aux[1]:  (records) cellsort -> real_ele -> real_ii -> (post_charges) real_ie
 int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStream_t s) {
   const Geom& g = h->g;
   hipStream_t s0 = h->aux[0], s1 = h->aux[1];
-  HIP_OK(h, hipEventRecord(h->ev[EV_FORK], s));
-  HIP_OK(h, hipStreamWaitEvent(s0, h->ev[EV_FORK], 0));
+  auto rec = [&](int e, hipStream_t st) { return hipEventRecord(h->ev[e], st); };
+  auto wait = [&](hipStream_t st, int e) { return hipStreamWaitEvent(st, h->ev[e], 0); };
+  HIP_OK(h, rec(EV_FORK, s));
+  HIP_OK(h, wait(s0, EV_FORK));
   { PhaseTimer t(h, s0, 1); launch_sample(g, b, s0); }
-  HIP_OK(h, hipEventRecord(h->ev[EV_SAMPLE], s0));
+  HIP_OK(h, rec(EV_SAMPLE, s0));
   { PhaseTimer t(h, s, 0); launch_records(g, b, fp32, s); }
-  HIP_OK(h, hipEventRecord(h->ev[EV_REC], s));
-  HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_REC], 0));
+  HIP_OK(h, rec(EV_REC, s));
+  HIP_OK(h, wait(s1, EV_REC));
   { PhaseTimer t(h, s1, 3); launch_cellsort(g, b, fp32, s1); }
   { PhaseTimer t(h, s1, 4); launch_real_ele(g, b, fp32, s1); }
-  HIP_OK(h, hipEventRecord(h->ev[EV_BN], s1));
+  HIP_OK(h, rec(EV_BN, s1));
   { PhaseTimer t(h, s1, 5); launch_real_ii(g, b, fp32, s1); }
-  HIP_OK(h, hipEventRecord(h->ev[EV_II], s1));
-  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_SAMPLE], 0));
+  HIP_OK(h, rec(EV_PHI, s1));
+  HIP_OK(h, wait(s, EV_SAMPLE));
   { PhaseTimer t(h, s, 2); launch_sf_ions(g, b, fp32, s); }
-  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_BN], 0));
+  HIP_OK(h, wait(s, EV_BN));
   { PhaseTimer t(h, s, 6); launch_ele_potential(g, b, fp32, s); }
   if (!fixedQ) {
     PhaseTimer t(h, s, 7);
     launch_cp_gemm(g, b, h->Sext, s);
   }
   { PhaseTimer t(h, s, 8); launch_post_charges(g, b, fixedQ, fp32, s); }
+  HIP_OK(h, rec(EV_POST, s));
+  HIP_OK(h, wait(s1, EV_POST));
+  { PhaseTimer t(h, s1, 11); launch_real_ie(g, b, fp32, s1); }
+  HIP_OK(h, rec(EV_II, s1));
+  HIP_OK(h, wait(s0, EV_POST));
+  HIP_OK(h, wait(s0, EV_PHI));
+  { PhaseTimer t(h, s0, 12); launch_energy(g, b, fixedQ, s0); }
+  HIP_OK(h, rec(EV_E, s0));
   { PhaseTimer t(h, s, 9); launch_sf_ele(g, b, fp32, s); }
-  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_II], 0));
+  HIP_OK(h, wait(s, EV_II));
   { PhaseTimer t(h, s, 10); launch_ion_force(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 11); launch_real_ie(g, b, fp32, s); }
-  { PhaseTimer t(h, s, 12); launch_energy(g, b, fixedQ, s); }
+  HIP_OK(h, wait(s, EV_E));
   HIP_OK(h, hipGetLastError());
   return SRBE_OK;
 }
@@ -569,7 +582,7 @@ void srbe_destroy(srbe_system* h) {
   for (hipStream_t st : h->aux)
     if (st) (void)hipStreamDestroy(st);
   if (h->cap) (void)hipStreamDestroy(h->cap);
-  void* bufs[] = {h->bin_keys, h->reach, h->ele_chunks, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
+  void* bufs[] = {h->bin_keys, h->reach, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
                   h->ele_czr, h->ion_runs, h->ele_runs, h->ele_run_zr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -629,6 +642,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ele_sd4, n * sizeof(double4));
     al((void**)&h->status, sizeof(unsigned));
     al((void**)&h->bin_keys, n * sizeof(unsigned));
+    al((void**)&h->logq, (size_t)(g.qmax[0] + g.qmax[1] + g.qmax[2] + 3) * sizeof(double));
     int64_t* off2 = nullptr;
     al((void**)&off2, 2 * sizeof(int64_t));
     if (e != hipSuccess) {
@@ -680,6 +694,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     launch_bin_electrodes(g, off2, h->ele_xyz, n_ele, h->bin_keys, h->ele_fx, h->ele_d4, h->ele_perm, h->ele_scell,
                           h->ele_cstart, h->ele_sfx, h->ele_sd4, h->status, s);
     launch_cell_zrange(g, h->ele_cstart, h->ele_xyz, h->ele_perm, h->ele_czr, s);
+    launch_logq_table(g, h->logq, s);
     std::vector<double2> czr(g.ncell);
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(czr.data(), h->ele_czr, czr.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess) {
@@ -799,6 +814,7 @@ int srbe_sample(srbe_system* h, int32_t n_rep, const uint64_t* seed, uint64_t st
   b.kset_out = kset_out;
   b.nacc_out = n_accepted_out;
   b.status = h->status;
+  b.logq = h->logq;
   launch_sample(h->g, b, s);
   HIP_OK(h, hipFreeAsync(tmp, s));
   return SRBE_OK;

@@ -80,9 +80,13 @@ __global__ __launch_bounds__(256) void k_records(Geom g, const int64_t* __restri
 
 // ============================================================ cell lists
 // Per replica (one block of 1024 threads): sum q (neutrality), sum |q|, sum q z
-// (slab term of Eq. (17)), sum q^2 (self term) when charges are given; a bitonic
-// sort of the unique keys gives every cell its particles in index order; the cell
-// starts (exclusive scan of the cell counts); and the records in cell order.
+// (slab term of Eq. (17)), sum q^2 (self term) when charges are given; a counting
+// sort of the particles by cell: cell counts (LDS integer atomics), their exclusive
+// scan (the cell starts), a provisional slot per particle from a per-cell cursor,
+// and then, since the provisional order inside a cell depends on timing, each
+// particle's final position inside its cell is the number of the cell's keys
+// (cell << 13 | index) below its own.  So every cell lists its particles in index
+// order, independent of timing.  Finally the records in cell order.
 template <int REC>
 __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __restrict__ off,
                                                    const double* __restrict__ xyz, const double* __restrict__ q,
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __rest
                                                    int* __restrict__ scell, int* __restrict__ cstart,
                                                    uint4* __restrict__ sfx, double4* __restrict__ sd4,
                                                    unsigned* status) {
-  __shared__ unsigned skeys[kMaxBinParticles];
+  __shared__ unsigned prov[kMaxBinParticles];
   __shared__ int cnt[kMaxCells + 1];
   __shared__ int scan[2][kMaxCells + 1];
   __shared__ double red[4][16];
@@ -100,25 +104,17 @@ __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __rest
   const int t = threadIdx.x;
   const int64_t b0 = off[r];
   const int n = (int)(off[r + 1] - b0);
-  int np = 1;
-  while (np < n) np <<= 1;
   for (int c = t; c <= g.ncell; c += 1024) cnt[c] = 0;
   __syncthreads();
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = t; k < np; k += 1024) {
-    if (k < n) {
-      const unsigned key = keys[b0 + k];
-      skeys[k] = key;
-      atomicAdd(&cnt[key >> 13], 1);
-      if (q) {
-        const double qi = q[b0 + k], z = xyz[2 * N + b0 + k];
-        v[0] += qi;
-        v[1] += fabs(qi);
-        v[2] += qi * z;
-        v[3] += qi * qi;
-      }
-    } else {
-      skeys[k] = 0xFFFFFFFFu;
+  for (int k = t; k < n; k += 1024) {
+    atomicAdd(&cnt[keys[b0 + k] >> 13], 1);
+    if (q) {
+      const double qi = q[b0 + k], z = xyz[2 * N + b0 + k];
+      v[0] += qi;
+      v[1] += fabs(qi);
+      v[2] += qi * z;
+      v[3] += qi * qi;
     }
   }
   if (q) {
@@ -133,23 +129,6 @@ __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __rest
   } else {
     __syncthreads();
   }
-  // bitonic sort of the keys (ascending)
-  for (int k = 2; k <= np; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = t; i < np; i += 1024) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const unsigned a = skeys[i], b = skeys[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            skeys[i] = b;
-            skeys[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
   // exclusive scan of the cell counts (Hillis-Steele over ncell + 1 entries)
   for (int c = t; c <= g.ncell; c += 1024) scan[0][c] = c == 0 ? 0 : cnt[c - 1];
   __syncthreads();
@@ -159,15 +138,32 @@ __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __rest
     __syncthreads();
     src ^= 1;
   }
+  const int* start = scan[src];
   int* cs = cstart + (size_t)r * (g.ncell + 1);
-  for (int c = t; c <= g.ncell; c += 1024) cs[c] = scan[src][c];
+  for (int c = t; c <= g.ncell; c += 1024) {
+    cs[c] = start[c];
+    cnt[c] = start[c];  // per-cell cursor
+  }
+  __syncthreads();
+  // provisional slots (timing-dependent order inside a cell)
   for (int k = t; k < n; k += 1024) {
-    const unsigned key = skeys[k];
+    const unsigned key = keys[b0 + k];
+    prov[atomicAdd(&cnt[key >> 13], 1)] = key;
+  }
+  __syncthreads();
+  // final position inside the cell: the number of the cell's keys below this one
+  for (int sidx = t; sidx < n; sidx += 1024) {
+    const unsigned key = prov[sidx];
+    const int c = (int)(key >> 13);
+    const int lo = start[c], hi = start[c + 1];
+    int rank = 0;
+    for (int u = lo; u < hi; ++u) rank += prov[u] < key;
+    const int pos = lo + rank;
     const int64_t i = b0 + (int)(key & 0x1FFFu);
-    perm[b0 + k] = (int)i;
-    scell[b0 + k] = (int)(key >> 13);
-    if (REC & 1) sfx[b0 + k] = fx[i];
-    if (REC & 2) sd4[b0 + k] = d4[i];
+    perm[b0 + pos] = (int)i;
+    scell[b0 + pos] = c;
+    if (REC & 1) sfx[b0 + pos] = fx[i];
+    if (REC & 2) sd4[b0 + pos] = d4[i];
   }
 }
 
@@ -222,15 +218,6 @@ __device__ double q_axis(int m, double alpha, double L) {
   return 0.5 * (erfc(c * (a - 0.5)) - erfc(c * (a + 0.5)));
 }
 
-__device__ double log_ratio(const Geom& g, int mx, int my, int mz) {
-  const double kx = TWO_PI * (double)mx / g.Lx;
-  const double ky = TWO_PI * (double)my / g.Ly;
-  const double kz = TWO_PI * (double)mz / g.Lz;
-  const double k2 = kx * kx + ky * ky + kz * kz;
-  const double lq = log(q_axis(mx, g.alpha, g.Lx)) + log(q_axis(my, g.alpha, g.Ly)) + log(q_axis(mz, g.alpha, g.Lz));
-  return -k2 / (4.0 * (g.alpha * g.alpha)) - lq;
-}
-
 __device__ void proposal(const Geom& g, uint64_t seed, uint64_t step, uint64_t purpose, uint64_t idx, int& mx,
                          int& my, int& mz) {
   U64x4 c;
@@ -248,6 +235,33 @@ __device__ void proposal(const Geom& g, uint64_t seed, uint64_t step, uint64_t p
   mx = (int)floor(g.sig[0] * zx + 0.5);
   my = (int)floor(g.sig[1] * zy + 0.5);
   mz = (int)floor(g.sig[2] * zz + 0.5);
+}
+
+// log q_d(m) for |m| <= qmax[d] from the table built at set-up by k_logq_table
+// with the same expression (so the value is the same bits), else computed here.
+__device__ double log_ratio_tab(const Geom& g, const double* __restrict__ T, int mx, int my, int mz) {
+  const double kx = TWO_PI * (double)mx / g.Lx;
+  const double ky = TWO_PI * (double)my / g.Ly;
+  const double kz = TWO_PI * (double)mz / g.Lz;
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  const int ax = abs(mx), ay = abs(my), az = abs(mz);
+  const double l0 = ax <= g.qmax[0] ? T[ax] : log(q_axis(mx, g.alpha, g.Lx));
+  const double l1 = ay <= g.qmax[1] ? T[g.qmax[0] + 1 + ay] : log(q_axis(my, g.alpha, g.Ly));
+  const double l2 = az <= g.qmax[2] ? T[g.qmax[0] + g.qmax[1] + 2 + az] : log(q_axis(mz, g.alpha, g.Lz));
+  const double lq = l0 + l1 + l2;
+  return -k2 / (4.0 * (g.alpha * g.alpha)) - lq;
+}
+
+__global__ __launch_bounds__(256) void k_logq_table(Geom g, double* __restrict__ T) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int n0 = g.qmax[0] + 1, n1 = g.qmax[1] + 1, n2 = g.qmax[2] + 1;
+  if (i >= n0 + n1 + n2) return;
+  if (i < n0)
+    T[i] = log(q_axis(i, g.alpha, g.Lx));
+  else if (i < n0 + n1)
+    T[i] = log(q_axis(i - n0, g.alpha, g.Ly));
+  else
+    T[i] = log(q_axis(i - n0 - n1, g.alpha, g.Lz));
 }
 
 __device__ __forceinline__ bool valid_mode(const Geom& g, int mx, int my, int mz) {
@@ -269,9 +283,14 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restrict__ seeds, uint64_t step,
+// One block per replica: wave 0 draws the 64 start tries while the other four
+// waves draw the P proposals; then wave 0 runs the chain.
+constexpr int kSampleThreads = 320;
+
+__global__ __launch_bounds__(kSampleThreads) void k_sample(Geom g, const uint64_t* __restrict__ seeds, uint64_t step,
                                                 const uint64_t* __restrict__ step_dev,
-                                                const int32_t* __restrict__ kset_in, int4* __restrict__ modes,
+                                                const int32_t* __restrict__ kset_in, const double* __restrict__ logq,
+                                                int4* __restrict__ modes,
                                                 double* __restrict__ wout, int32_t* __restrict__ kset_out,
                                                 int32_t* __restrict__ nacc_out, unsigned* status) {
   extern __shared__ unsigned char smem[];
@@ -280,7 +299,7 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
   const int P = g.P, M = g.M, K = g.K;
   const int t = threadIdx.x;
   // deterministic modes (0, 0, m), m = 1..M, weight doubled for the pair +-m
-  for (int m = 1 + t; m <= M; m += 256) {
+  for (int m = 1 + t; m <= M; m += kSampleThreads) {
     const double kz = TWO_PI * (double)m / g.Lz;
     const double k2 = kz * kz;
     modes[(size_t)r * K + (m - 1)] = make_int4(0, 0, m, 0);
@@ -291,7 +310,7 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
     return;
   }
   if (kset_in) {
-    for (int l = t; l < P; l += 256) {
+    for (int l = t; l < P; l += kSampleThreads) {
       const int32_t* m = kset_in + ((size_t)r * P + l) * 3;
       const int mx = m[0], my = m[1], mz = m[2];
       if (!valid_mode(g, mx, my, mz)) atomicOr(status, ST_BADKSET);
@@ -323,18 +342,7 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
     proposal(g, seed, step, 2, (uint64_t)t, sx, sy, sz);
     if (valid_mode(g, sx, sy, sz)) atomicMin(&first_valid, t);
   }
-  __syncthreads();
-  if (t < 64 && t == first_valid) {
-    start_m[0] = sx;
-    start_m[1] = sy;
-    start_m[2] = sz;
-  }
-  if (t == 0 && first_valid == (1 << 30)) {
-    start_m[0] = 1;
-    start_m[1] = 0;
-    start_m[2] = 0;
-  }
-  for (int l = t; l < P; l += 256) {
+  for (int l = t - 64; l >= 0 && l < P; l += kSampleThreads - 64) {
     int mx, my, mz;
     proposal(g, seed, step, 0, (uint64_t)l, mx, my, mz);
     U64x4 c;
@@ -348,37 +356,61 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
     ym[3 * l + 0] = (short)mx;
     ym[3 * l + 1] = (short)my;
     ym[3 * l + 2] = (short)mz;
-    ly[l] = v ? log_ratio(g, mx, my, mz) : (double)NAN;
+    ly[l] = v ? log_ratio_tab(g, logq, mx, my, mz) : (double)NAN;
     lu[l] = log(u01_open(wa.v[0]));
   }
   __syncthreads();
-  // the chain: one wave walks the P decisions; lane j of a 64-wide chunk holds
-  // proposal base + j and the decision data are broadcast with readlane
+  if (t < 64 && t == first_valid) {
+    start_m[0] = sx;
+    start_m[1] = sy;
+    start_m[2] = sz;
+  }
+  if (t == 0 && first_valid == (1 << 30)) {
+    start_m[0] = 1;
+    start_m[1] = 0;
+    start_m[2] = 0;
+  }
+  __syncthreads();
+  // the chain, one wave, 64 decisions at a time.  Lane j first decides as if
+  // proposal j-1 was accepted (the state's log ratio then being ly[j-1]); every
+  // decision up to the first rejection is then final (each used the state the
+  // sequential chain has at that point), the rejected one too, and the remaining
+  // lanes decide again from the known state.  Each final decision is the
+  // sequential one, d = ly[j] - lx with the same operands.  With acceptance near
+  // 1 a chunk takes one or two passes.
   if (t < 64) {
-    double lx = log_ratio(g, start_m[0], start_m[1], start_m[2]);
+    double lx = log_ratio_tab(g, logq, start_m[0], start_m[1], start_m[2]);
     int cur = -1, nacc = 0;
     for (int base = 0; base < P; base += 64) {
       const int l = base + t;
+      const int cnt = min(64, P - base);
       const double myly = l < P ? ly[l] : (double)NAN;
       const double mylu = l < P ? lu[l] : 0.0;
-      const int cnt = min(64, P - base);
-      int mine = -1;
-      for (int j = 0; j < cnt; ++j) {
-        const double lyj = readlane_f64(myly, j);
-        const double d = lyj - lx;
-        if (d >= 0.0 || readlane_f64(mylu, j) < d) {
-          lx = lyj;
-          cur = base + j;
-          ++nacc;
-        }
-        if (t == j) mine = cur;
+      const double prevly = __shfl_up(myly, 1, 64);
+      bool acc = false;
+      int done = 0;
+      while (done < cnt) {
+        const double prev = t == done ? lx : prevly;
+        const double d = myly - prev;
+        const bool a = d >= 0.0 || mylu < d;
+        const uint64_t rej = __ballot(!a && t >= done && t < cnt);
+        const int jstar = rej ? __ffsll((unsigned long long)rej) - 1 : cnt;
+        if (t >= done && t < jstar) acc = true;
+        if (jstar > done) lx = readlane_f64(myly, jstar - 1);
+        done = jstar + 1;
       }
+      const uint64_t am = __ballot(acc);
+      nacc += __popcll(am);
+      const uint64_t upto = t == 63 ? ~0ull : ((2ull << t) - 1);
+      const uint64_t below = am & upto;
+      const int mine = below ? base + 63 - __clzll(below) : cur;
       if (l < P) state[l] = mine;
+      if (am) cur = base + 63 - __clzll(am);
     }
     if (t == 0 && nacc_out) nacc_out[r] = nacc;
   }
   __syncthreads();
-  for (int l = t; l < P; l += 256) {
+  for (int l = t; l < P; l += kSampleThreads) {
     const int s_ = state[l];
     const int mx = s_ < 0 ? start_m[0] : ym[3 * s_ + 0];
     const int my = s_ < 0 ? start_m[1] : ym[3 * s_ + 1];
@@ -397,8 +429,13 @@ __global__ __launch_bounds__(256) void k_sample(Geom g, const uint64_t* __restri
 size_t sample_lds_bytes(int P) { return (size_t)P * (8 + 8 + 4 + 6) + 16; }
 
 void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample, dim3(b.R), dim3(256), sample_lds_bytes(g.P), s, g, b.seed, b.step, b.step_dev,
-                     b.kset_in, b.modes, b.w, b.kset_out, b.nacc_out, b.status);
+  hipLaunchKernelGGL(k_sample, dim3(b.R), dim3(kSampleThreads), sample_lds_bytes(g.P), s, g, b.seed, b.step, b.step_dev,
+                     b.kset_in, b.logq, b.modes, b.w, b.kset_out, b.nacc_out, b.status);
+}
+
+void launch_logq_table(const Geom& g, double* T, hipStream_t s) {
+  const int n = g.qmax[0] + g.qmax[1] + g.qmax[2] + 3;
+  hipLaunchKernelGGL(k_logq_table, dim3(cdiv64(n, 256)), dim3(256), 0, s, g, T);
 }
 
 // Step counter of a captured step: set from the host, advanced at the end of each
@@ -614,11 +651,42 @@ __device__ __forceinline__ void erfc_pair_f(float a, float r, float rinv, float&
   h = fmaf(2.0f * (float)INV_SQRT_PI * a, e, f) * (rinv * rinv);
 }
 
-// FP32 wave sum (the FP64 one is at the top of this file).
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Wave totals through DPP: within each 16-lane row, pairs (quad_perm 1,0,3,2),
+// quads (quad_perm 2,3,0,1), halves (row_half_mirror) and rows (row_mirror); then
+// the four row sums, read from lanes 0, 16, 32, 48, are added in row order.  The
+// result is wave-uniform and the same on every run.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return ((r0 + r1) + r2) + r3;
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16), r2 = readlane_f64(v, 32),
+               r3 = readlane_f64(v, 48);
+  return ((r0 + r1) + r2) + r3;
 }
 
 // Lanes below this one with their bit set in m.
@@ -1278,10 +1346,10 @@ void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s)
 // neighbouring cells (r < rc), phi_i = ke sum_j q_j K_ii(r) (for the energy).
 // One wave per cell-sorted ion (see wave_scan).  Two kernels: the ion-ion part,
 // which does not depend on the electrode charges and runs beside the k-space and
-// charge-solve passes, leaves its sums in Fii (input order; the k-space force pass
-// adds them); the ion-electrode part, after the charge solve, visits only the ions
-// of the cells that can reach an electrode (reach ranges built at set-up) and adds
-// its sums to F.  An electrode run (one z-layer) whose z-extent lies farther than
+// charge-solve passes, leaves its sums in Fii (input order); the ion-electrode part,
+// after the charge solve, visits only the ions of the cells that can reach an
+// electrode (reach ranges built at set-up) and adds its sums to Fii, beside the
+// reciprocal passes; the k-space force pass then adds ke q_i Fii to F.  An electrode run (one z-layer) whose z-extent lies farther than
 // rc from the ion cannot hold a partner and is skipped.
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restrict__ off, int64_t N,
@@ -1328,10 +1396,10 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
                 ay = fmaf(s_, en.y, ay);
                 az = fmaf(s_, en.z, az);
               });
-    fx = (double)wave_sum(ax);
-    fy = (double)wave_sum(ay);
-    fz = (double)wave_sum(az);
-    ph = (double)wave_sum(ap);
+    fx = (double)wave_total(ax);
+    fy = (double)wave_total(ay);
+    fz = (double)wave_total(az);
+    ph = (double)wave_total(ap);
   } else {
     const double4 pi_ = sd4[k];
     const double a = g.alpha, rc2 = g.rc * g.rc;
@@ -1357,10 +1425,10 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
                 ay += s_ * en.y;
                 az += s_ * en.z;
               });
-    fx = wave_sum(ax);
-    fy = wave_sum(ay);
-    fz = wave_sum(az);
-    ph = wave_sum(ap);
+    fx = wave_total(ax);
+    fy = wave_total(ay);
+    fz = wave_total(az);
+    ph = wave_total(ap);
   }
   if ((threadIdx.x & 63) == 0) {
     const int i = perm[k];
@@ -1381,7 +1449,7 @@ __global__ __launch_bounds__(256) void k_real_ie(Geom g, const int64_t* __restri
                                                  const int* __restrict__ ele_cstart,
                                                  const uint4* __restrict__ ele_sfx,
                                                  const double4* __restrict__ ele_sd4, const float* __restrict__ Qsf,
-                                                 const double* __restrict__ Qsd, double* __restrict__ F) {
+                                                 const double* __restrict__ Qsd, double* __restrict__ Fii) {
   using Entry = typename std::conditional<FP32, float4, double4>::type;
   __shared__ Entry ring_all[4][kRingAlloc];
   const int r = blockIdx.y;
@@ -1436,9 +1504,9 @@ __global__ __launch_bounds__(256) void k_real_ie(Geom g, const int64_t* __restri
                     ay = fmaf(s_, en.y, ay);
                     az = fmaf(s_, en.z, az);
                   });
-        fx = (double)wave_sum(ax);
-        fy = (double)wave_sum(ay);
-        fz = (double)wave_sum(az);
+        fx = (double)wave_total(ax);
+        fy = (double)wave_total(ay);
+        fz = (double)wave_total(az);
         qi = (double)__uint_as_float(pi_.w);
       } else {
         const double4 pi_ = sd4[k];
@@ -1477,17 +1545,16 @@ __global__ __launch_bounds__(256) void k_real_ie(Geom g, const int64_t* __restri
                     ay += s_ * en.y;
                     az += s_ * en.z;
                   });
-        fx = wave_sum(ax);
-        fy = wave_sum(ay);
-        fz = wave_sum(az);
+        fx = wave_total(ax);
+        fy = wave_total(ay);
+        fz = wave_total(az);
         qi = pi_.w;
       }
       if ((threadIdx.x & 63) == 0) {
         const int i = perm[k];
-        const double kq = g.ke * qi;
-        F[i] += kq * fx;
-        F[N + i] += kq * fy;
-        F[2 * N + i] += kq * fz;
+        Fii[i] += fx;
+        Fii[N + i] += fy;
+        Fii[2 * N + i] += fz;
       }
     }
   }
@@ -1510,11 +1577,11 @@ void launch_real_ie(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (fp32)
     hipLaunchKernelGGL(k_real_ie<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.reach, b.nreach, b.perm,
                        b.scell, b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf,
-                       b.Qsd, b.F_out);
+                       b.Qsd, b.Fii);
   else
     hipLaunchKernelGGL(k_real_ie<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.reach, b.nreach, b.perm,
                        b.scell, b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf,
-                       b.Qsd, b.F_out);
+                       b.Qsd, b.Fii);
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
