@@ -1047,104 +1047,104 @@ void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_
 // ============================================================ charge solve
 // [Q; psibar] = S_ext V (Eqs. (9)-(11)).  S_ext: (n+1) rows of ld = ldcp(n) doubles
 // (row-major; the n x n block is symmetric); V: one row of ld doubles per replica;
-// both zero-padded to ld, a multiple of 16.  FP64 MFMA v_mfma_f64_16x16x4f64:
-// lane l supplies A[l%16][k(l)] and B[k(l)][l%16], the result register v of lane l
-// is row l/16 + 4 v, column l%16.  The contraction index k(l) may be any
-// assignment of the 4 k values to the 4 lane groups as long as A and B use the
-// same one: here a lane holds 4 consecutive k of its row (32-byte loads of S_ext
-// and V) and MFMA step u takes the u-th of them.  A wave computes 16 rows x 64
-// replicas (four 16 x 16 tiles sharing the A operand) over its k range, the loads
-// of the next 16 k in flight during the MFMAs of the current.  Rows past n and
-// replicas past R read row 0 / replica 0 (valid memory) and their results are not
-// stored.  Block = 4 waves splitting the block's k range; partial tiles are added
-// in wave order through LDS.  Grid: (row tiles, replica groups of 64, ksplit
-// k-ranges); each k-range writes its own partial, summed in order after the GEMM.
+// both zero-padded to ld, a multiple of 16.  A block computes a 64-row x 64-replica
+// tile over one k-range: per 16-k block the two 64 x 16 operand tiles are loaded
+// by all 256 threads (32-byte coalesced loads) into LDS (double buffered, rows
+// padded to 18 doubles against bank conflicts), the next block's tiles travelling
+// from HBM while the current one is multiplied.  Each wave owns 16 rows: FP64 MFMA
+// v_mfma_f64_16x16x4f64, lane l supplying A[l%16][k(l)] and B[k(l)][l%16], the
+// result register v of lane l being row l/16 + 4 v, column l%16.  The contraction
+// index k(l) may be any assignment of the 4 k values to the 4 lane groups as long
+// as A and B use the same one: here a lane holds 4 consecutive k of its row (two
+// 16-byte LDS reads) and MFMA step u takes the u-th of them.  Rows past n and
+// replicas past R read row 0 / replica 0 (valid memory) and are not stored.  The
+// k range is split into ksplit ranges (grid z), sized so that the grid fits the
+// CUs in one pass; each range writes its own partial, summed in order after the
+// GEMM.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-struct GemmFrag {
-  double2 a[2], b[4][2];
-};
+constexpr int kGemmLd = 18;  // LDS row stride of an operand tile (doubles)
 
 __global__ __launch_bounds__(256) void k_cp_gemm(int n, int R, const double* __restrict__ S,
                                                  const double* __restrict__ V, double* __restrict__ Qpart) {
-  __shared__ double red[4][1024];
+  __shared__ double lds[2][2][64 * kGemmLd];  // [buffer][A or B][64 rows x 16 k, padded]
   const int ld = ldcp(n);
   const int rt = blockIdx.x, cg = blockIdx.y, h = blockIdx.z, ks = gridDim.z;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // 16-k blocks: the whole range split into ks block ranges, each into 4 wave ranges
+  const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nb = ld / 16;
-  const int hb0 = (int)((int64_t)nb * h / ks), hb1 = (int)((int64_t)nb * (h + 1) / ks);
-  const int kb0 = hb0 + (int)((int64_t)(hb1 - hb0) * w / 4), kb1 = hb0 + (int)((int64_t)(hb1 - hb0) * (w + 1) / 4);
-  const int i = rt * 16 + (lane & 15);
-  const int kq = 4 * (lane >> 4);
-  const double* Ap = S + (size_t)(i <= n ? i : 0) * ld + kq;
-  const double* Bp[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int r = cg * 64 + t * 16 + (lane & 15);
-    Bp[t] = V + (size_t)(r < R ? r : 0) * ld + kq;
-  }
-  auto load = [&](int kb, GemmFrag& f) {
+  const int kb0 = (int)((int64_t)nb * h / ks), kb1 = (int)((int64_t)nb * (h + 1) / ks);
+  // tile loader: thread t moves 4 consecutive k of row t/4 of each tile
+  const int lrow = t >> 2, lk = 4 * (t & 3);
+  const int arow = rt * 64 + lrow, brow = cg * 64 + lrow;
+  const double* Ag = S + (size_t)(arow <= n ? arow : 0) * ld + lk;
+  const double* Bg = V + (size_t)(brow < R ? brow : 0) * ld + lk;
+  double2 ra0, ra1, rb0, rb1;
+  auto gload = [&](int kb) {
     const int k0 = kb * 16;
-    f.a[0] = *(const double2*)(Ap + k0);
-    f.a[1] = *(const double2*)(Ap + k0 + 2);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f.b[t][0] = *(const double2*)(Bp[t] + k0);
-      f.b[t][1] = *(const double2*)(Bp[t] + k0 + 2);
-    }
+    ra0 = *(const double2*)(Ag + k0);
+    ra1 = *(const double2*)(Ag + k0 + 2);
+    rb0 = *(const double2*)(Bg + k0);
+    rb1 = *(const double2*)(Bg + k0 + 2);
+  };
+  auto lstore = [&](int buf) {
+    double* A = &lds[buf][0][lrow * kGemmLd + lk];
+    double* B = &lds[buf][1][lrow * kGemmLd + lk];
+    *(double2*)A = ra0;
+    *(double2*)(A + 2) = ra1;
+    *(double2*)B = rb0;
+    *(double2*)(B + 2) = rb1;
   };
   f64x4 acc[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-  auto mma = [&](const GemmFrag& f) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double a = (u & 1) ? f.a[u >> 1].y : f.a[u >> 1].x;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const double bv = (u & 1) ? f.b[t][u >> 1].y : f.b[t][u >> 1].x;
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
-      }
-    }
-  };
+  for (int c = 0; c < 4; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int kq = 4 * (lane >> 4);
   if (kb0 < kb1) {
-    // the next block's loads are issued before the current block's MFMAs (a load
-    // past the range repeats the last block and is not used)
-    GemmFrag cur;
-    load(kb0, cur);
+    gload(kb0);
+    lstore(0);
+    __syncthreads();
     for (int kb = kb0; kb < kb1; ++kb) {
-      GemmFrag nxt;
-      load(min(kb + 1, kb1 - 1), nxt);
-      mma(cur);
-      cur = nxt;
+      const int buf = (kb - kb0) & 1;
+      if (kb + 1 < kb1) gload(kb + 1);
+      const double* A = &lds[buf][0][(w * 16 + (lane & 15)) * kGemmLd + kq];
+      const double2 a01 = *(const double2*)A, a23 = *(const double2*)(A + 2);
+      double2 b01[4], b23[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double* B = &lds[buf][1][(c * 16 + (lane & 15)) * kGemmLd + kq];
+        b01[c] = *(const double2*)B;
+        b23[c] = *(const double2*)(B + 2);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01[c].x, acc[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01[c].y, acc[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23[c].x, acc[c], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23[c].y, acc[c], 0, 0, 0);
+      if (kb + 1 < kb1) lstore(buf ^ 1);
+      __syncthreads();
     }
   }
+  // this wave's 16 rows x 64 replicas of the partial
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w][(t * 4 + v) * 64 + lane] = acc[t][v];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int f = threadIdx.x + 256 * q;
-    const double sum = ((red[0][f] + red[1][f]) + red[2][f]) + red[3][f];
-    const int l = f & 63, v = (f >> 6) & 3, t = f >> 8;
-    const int row = rt * 16 + (l >> 4) + 4 * v, r = cg * 64 + t * 16 + (l & 15);
-    if (row <= n && r < R) Qpart[((size_t)h * R + r) * (n + 1) + row] = sum;
-  }
+    for (int v = 0; v < 4; ++v) {
+      const int row = rt * 64 + w * 16 + (lane >> 4) + 4 * v, r = cg * 64 + c * 16 + (lane & 15);
+      if (row <= n && r < R) Qpart[((size_t)h * R + r) * (n + 1) + row] = acc[c][v];
+    }
 }
 
-// k-ranges: enough blocks for about two per CU of a 256-CU device, at most 8
-// partials.
+// k-ranges: as many as keep the grid within one block per CU of a 256-CU device
+// (at most 16, at least 1).
 int cp_gemm_ksplit(int n_ele, int R) {
-  const int blocks = ((n_ele + 1 + 15) / 16) * ((R + 63) / 64);
-  return std::max(1, std::min(8, (512 + blocks - 1) / blocks));
+  const int tiles = ((n_ele + 1 + 63) / 64) * ((R + 63) / 64);
+  return std::max(1, std::min(16, 256 / std::max(tiles, 1)));
 }
 
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s) {
   const int n = g.n_ele;
-  hipLaunchKernelGGL(k_cp_gemm, dim3((n + 1 + 15) / 16, (b.R + 63) / 64, b.ksplit), dim3(256), 0, s, n, b.R, Sext,
+  hipLaunchKernelGGL(k_cp_gemm, dim3((n + 1 + 63) / 64, (b.R + 63) / 64, b.ksplit), dim3(256), 0, s, n, b.R, Sext,
                      b.V, b.Qext);
 }
 
