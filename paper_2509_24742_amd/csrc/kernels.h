@@ -28,6 +28,7 @@ struct StepBufs {
   const uint64_t* seed;     // R
   uint64_t step;
   const uint64_t* step_dev; // graph replays: the step is read from here (null: use step)
+  uint64_t* step_adv;       // graph replays: the step counter the last kernel advances (else null)
   const int32_t* kset_in;   // R*P*3 or null
   const double* logq;       // sampler table of log q_d(m), |m| <= qmax[d] (per handle)
   // electrodes (device, fixed): original order and cell-sorted order
@@ -44,6 +45,7 @@ struct StepBufs {
   const double2* ele_run_zr;  // ncell x kRunMax z-extent of the electrodes of each ele_runs entry
   const int2* reach;        // cell ranges [c0, c1) whose ions can be within rc of an electrode
   int nreach;
+  const unsigned char* reach_cell;  // ncell flags: 1 for the cells of those ranges
   const int4* ele_chunks;   // (cell, first, end) runs of <= 64 cell-sorted electrodes of one cell
   int n_ele_chunks;
   const uint4* ele_sfx;     // sorted fixed point
@@ -77,6 +79,7 @@ struct StepBufs {
   double* rsum;             // R*16 per-replica reductions after the charge solve (4 partial sums of 3)
   double* phi;              // N real-space ion-ion potential per ion
   double* Fii;              // 3N ion-ion real-space force sums (SoA, input order), before the ke q_i factor
+  double* Fie;              // 3N ion-electrode real-space force sums, written for ions of reach cells only
   unsigned* status;
   // outputs
   double* Q_out;
@@ -88,22 +91,23 @@ struct StepBufs {
   const double* Q_in;
 };
 
-void launch_records(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_cellsort(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s);
+// Parts of the fused launches (bit masks).  A step runs each fused launch whole; with
+// phase timing on, each part is launched on its own so that it can be timed.
+enum { FRONT_SAMPLE = 1, FRONT_SORT = 2 };
+enum { STAGE_SF = 1, STAGE_REAL = 2 };
+
+void launch_front(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_set_step(uint64_t* step_dev, uint64_t v, hipStream_t s);
 void launch_logq_table(const Geom& g, double* T, hipStream_t s);
-void launch_advance_step(uint64_t* step_dev, hipStream_t s);
-void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
+void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, hipStream_t s);
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 int cp_gemm_ksplit(int n_ele, int R);
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
-void launch_sf_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_real_ie(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_energy(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 
 // setup kernels

@@ -48,6 +48,7 @@ struct srbe_system {
   bool capturing = false;
   unsigned* bin_keys = nullptr;  // n_ele scratch for the electrode binning
   int2* reach = nullptr;         // cell ranges whose ions can be within rc of an electrode
+  unsigned char* reach_cell = nullptr;  // per-cell flag of those ranges
   int nreach = 0;
   int4* ele_chunks = nullptr;    // (cell, first, end): <= 64 cell-sorted electrodes of one cell
   double* logq = nullptr;        // sampler table log q_d(m), |m| <= qmax[d]
@@ -320,9 +321,9 @@ int build_electrode_solve(srbe_system* h, hipStream_t s) {
 
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-const char* kPhaseNames[SRBE_N_PHASES] = {"records",  "sample",   "sf_ions",      "cellsort", "real_ele",
-                                          "real_ii",  "ele_potential", "cp_gemm", "post_charges", "sf_ele",
-                                          "ion_force", "real_ie", "energy",  "",             "",
+const char* kPhaseNames[SRBE_N_PHASES] = {"sample",       "cellsort", "sf_ions", "real_ele",  "real_ii",
+                                          "ele_potential", "cp_gemm",  "post_charges", "sf_ele", "real_ie",
+                                          "ion_force",    "energy",   "",        "",          "",
                                           ""};
 
 // Record an event pair around a phase when profiling is enabled.
@@ -418,6 +419,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.seed = a.seed;
   b.step = a.step;
   b.step_dev = nullptr;
+  b.step_adv = nullptr;
   b.kset_in = a.kset_in;
   b.logq = h->logq;
   b.ele_xyz = h->ele_xyz;
@@ -433,6 +435,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.ele_run_zr = h->ele_run_zr;
   b.reach = h->reach;
   b.nreach = h->nreach;
+  b.reach_cell = h->reach_cell;
   b.ele_chunks = h->ele_chunks;
   b.n_ele_chunks = h->n_ele_chunks;
   b.ele_sfx = h->ele_sfx;
@@ -486,6 +489,7 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.rsum, (size_t)R * 16 * sizeof(double)},
       {(void**)&b.phi, (size_t)N1 * sizeof(double)},
       {(void**)&b.Fii, (size_t)3 * N1 * sizeof(double)},
+      {(void**)&b.Fie, (size_t)3 * N1 * sizeof(double)},
       {(void**)&b.energy_out, a.energy_out ? 0 : (size_t)R * sizeof(double)},
   };
   size_t total = 0;
@@ -496,51 +500,71 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
   return total;
 }
 
-enum { EV_FORK = 0, EV_SAMPLE, EV_REC, EV_BN, EV_PHI, EV_POST, EV_II, EV_E };
+enum { EV_CS = 0, EV_II };
+enum {
+  PH_SAMPLE = 0, PH_CELLSORT, PH_SF_IONS, PH_REAL_ELE, PH_REAL_II, PH_ELE_POTENTIAL, PH_CP_GEMM, PH_POST_CHARGES,
+  PH_SF_ELE, PH_REAL_IE, PH_ION_FORCE, PH_ENERGY
+};
 
-// The step as a DAG over three streams (Algorithm 1's order within each chain):
-//   aux[0]:  sample -> (post_charges, real_ii) energy
-//   s:       records -> (sample) sf_ions -> (real_ele) ele_potential -> cp_gemm ->
-//            post_charges -> sf_ele -> (real_ie) ion_force -> (energy)
-//   aux[1]:  (records) cellsort -> real_ele -> real_ii -> (post_charges) real_ie
+// The step (Algorithm 1's order) on the caller's stream, with the ion-ion real-space
+// pass beside it on aux[1]:
+//   s:      [sample | records + cell sort] -> [sf(ions) | real_ele] -> sf finalize ->
+//           ele_potential -> cp_gemm -> post_charges -> [sf(electrodes) | real_ie] ->
+//           sf finalize -> (real_ii) ion_force -> energy
+//   aux[1]: (cell sort) real_ii
+// [a | b] is one launch whose blocks run both parts.  Independent work shares a launch
+// rather than a second stream: a cross-stream wait costs several microseconds in a
+// replayed graph, while kernels on one stream follow each other without a gap.  The
+// ion-ion pass is long enough to pay for its two waits.  With phase timing on, every
+// part is launched on its own (same device code) so that each can be timed.
 int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStream_t s) {
   const Geom& g = h->g;
-  hipStream_t s0 = h->aux[0], s1 = h->aux[1];
-  auto rec = [&](int e, hipStream_t st) { return hipEventRecord(h->ev[e], st); };
-  auto wait = [&](hipStream_t st, int e) { return hipStreamWaitEvent(st, h->ev[e], 0); };
-  HIP_OK(h, rec(EV_FORK, s));
-  HIP_OK(h, wait(s0, EV_FORK));
-  { PhaseTimer t(h, s0, 1); launch_sample(g, b, s0); }
-  HIP_OK(h, rec(EV_SAMPLE, s0));
-  { PhaseTimer t(h, s, 0); launch_records(g, b, fp32, s); }
-  HIP_OK(h, rec(EV_REC, s));
-  HIP_OK(h, wait(s1, EV_REC));
-  { PhaseTimer t(h, s1, 3); launch_cellsort(g, b, fp32, s1); }
-  { PhaseTimer t(h, s1, 4); launch_real_ele(g, b, fp32, s1); }
-  HIP_OK(h, rec(EV_BN, s1));
-  { PhaseTimer t(h, s1, 5); launch_real_ii(g, b, fp32, s1); }
-  HIP_OK(h, rec(EV_PHI, s1));
-  HIP_OK(h, wait(s, EV_SAMPLE));
-  { PhaseTimer t(h, s, 2); launch_sf_ions(g, b, fp32, s); }
-  HIP_OK(h, wait(s, EV_BN));
-  { PhaseTimer t(h, s, 6); launch_ele_potential(g, b, fp32, s); }
-  if (!fixedQ) {
-    PhaseTimer t(h, s, 7);
-    launch_cp_gemm(g, b, h->Sext, s);
+  hipStream_t s1 = h->aux[1];
+  const bool split = h->prof && !h->capturing;
+  auto part = [&](int phase, hipStream_t st, auto&& launch) {
+    PhaseTimer t(h, st, phase);
+    launch();
+  };
+  if (split) {
+    part(PH_SAMPLE, s, [&] { launch_front(g, b, fp32, FRONT_SAMPLE, s); });
+    part(PH_CELLSORT, s, [&] { launch_front(g, b, fp32, FRONT_SORT, s); });
+  } else {
+    launch_front(g, b, fp32, FRONT_SAMPLE | FRONT_SORT, s);
   }
-  { PhaseTimer t(h, s, 8); launch_post_charges(g, b, fixedQ, fp32, s); }
-  HIP_OK(h, rec(EV_POST, s));
-  HIP_OK(h, wait(s1, EV_POST));
-  { PhaseTimer t(h, s1, 11); launch_real_ie(g, b, fp32, s1); }
-  HIP_OK(h, rec(EV_II, s1));
-  HIP_OK(h, wait(s0, EV_POST));
-  HIP_OK(h, wait(s0, EV_PHI));
-  { PhaseTimer t(h, s0, 12); launch_energy(g, b, fixedQ, s0); }
-  HIP_OK(h, rec(EV_E, s0));
-  { PhaseTimer t(h, s, 9); launch_sf_ele(g, b, fp32, s); }
-  HIP_OK(h, wait(s, EV_II));
-  { PhaseTimer t(h, s, 10); launch_ion_force(g, b, fp32, s); }
-  HIP_OK(h, wait(s, EV_E));
+  HIP_OK(h, hipEventRecord(h->ev[EV_CS], s));
+  // the critical stream's next launch is enqueued (and, in a graph, created) before
+  // the side stream's, so that it is dispatched first
+  if (split) {
+    part(PH_SF_IONS, s, [&] {
+      launch_stage_ions(g, b, fp32, STAGE_SF, s);
+      launch_sf_finalize(g, b, fp32, 1, s);
+    });
+  } else {
+    launch_stage_ions(g, b, fp32, STAGE_SF | STAGE_REAL, s);
+  }
+  HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_CS], 0));
+  part(PH_REAL_II, s1, [&] { launch_real_ii(g, b, fp32, s1); });
+  HIP_OK(h, hipEventRecord(h->ev[EV_II], s1));
+  if (split)
+    part(PH_REAL_ELE, s, [&] { launch_stage_ions(g, b, fp32, STAGE_REAL, s); });
+  else
+    launch_sf_finalize(g, b, fp32, 1, s);
+  part(PH_ELE_POTENTIAL, s, [&] { launch_ele_potential(g, b, fp32, s); });
+  if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, s); });
+  part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
+  if (split) {
+    part(PH_SF_ELE, s, [&] {
+      launch_stage_ele(g, b, fp32, STAGE_SF, s);
+      launch_sf_finalize(g, b, fp32, 2, s);
+    });
+    part(PH_REAL_IE, s, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s); });
+  } else {
+    launch_stage_ele(g, b, fp32, STAGE_SF | STAGE_REAL, s);
+    launch_sf_finalize(g, b, fp32, 2, s);
+  }
+  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_II], 0));
+  part(PH_ION_FORCE, s, [&] { launch_ion_force(g, b, fp32, s); });
+  part(PH_ENERGY, s, [&] { launch_energy(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());
   return SRBE_OK;
 }
@@ -582,7 +606,7 @@ void srbe_destroy(srbe_system* h) {
   for (hipStream_t st : h->aux)
     if (st) (void)hipStreamDestroy(st);
   if (h->cap) (void)hipStreamDestroy(h->cap);
-  void* bufs[] = {h->bin_keys, h->reach, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
+  void* bufs[] = {h->bin_keys, h->reach, h->reach_cell, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
                   h->ele_czr, h->ion_runs, h->ele_runs, h->ele_run_zr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -752,6 +776,12 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
         reach.push_back(make_int2(c, c + 1));
     }
     if (reach.size() > 64) reach = {make_int2(reach.front().x, reach.back().y)};
+    std::vector<unsigned char> rflag(g.ncell, 0);
+    for (const int2& cr : reach)
+      for (int c = cr.x; c < cr.y; ++c) rflag[c] = 1;
+    if (hipMalloc((void**)&h->reach_cell, g.ncell) != hipSuccess ||
+        hipMemcpy(h->reach_cell, rflag.data(), g.ncell, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(SRBE_EHIP);
     h->nreach = (int)reach.size();
     h->n_ele_chunks = (int)chunks.size();
     if (hipMalloc((void**)&h->reach, std::max<size_t>(1, reach.size()) * sizeof(int2)) != hipSuccess ||
@@ -815,7 +845,7 @@ int srbe_sample(srbe_system* h, int32_t n_rep, const uint64_t* seed, uint64_t st
   b.nacc_out = n_accepted_out;
   b.status = h->status;
   b.logq = h->logq;
-  launch_sample(h->g, b, s);
+  launch_front(h->g, b, 1, FRONT_SAMPLE, s);
   HIP_OK(h, hipFreeAsync(tmp, s));
   return SRBE_OK;
 }
@@ -891,13 +921,13 @@ int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const in
   ws_layout(h, a, b, (char*)gr->ws);
   b.off = gr->off_dev;
   b.step_dev = gr->step_dev;
+  b.step_adv = gr->step_dev;
   if ((e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
     set_err(h, SRBE_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     return fail(SRBE_EHIP);
   }
   h->capturing = true;
   rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, h->cap);
-  if (rc == SRBE_OK) launch_advance_step(gr->step_dev, h->cap);
   h->capturing = false;
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(h->cap, &graph);

@@ -1,14 +1,15 @@
 // Per-step kernels of the SRBE constant-potential step (gfx950).
 //
-// One step (Algorithm 1 of the paper, integration excluded), all on one stream,
-// for R replicas sharing one electrode geometry:
-//   prepare -> sample -> sf(ions) -> real_ele -> ele_potential
-//   -> [FP64 GEMM: (Q; psibar) = S_ext (dpsi d + b*)] -> post_charges -> sf(electrodes)
-//   -> ion_force -> real_ion -> energy
-// Structure-factor partial sums are reduced by the last block of each mode tile, in
-// a fixed order; real-space neighbours are visited in a fixed (cell, index) order.
-// There are no floating-point atomics, so two runs on the same inputs give
-// bitwise-identical results.
+// One step (Algorithm 1 of the paper, integration excluded) for R replicas sharing
+// one electrode geometry:
+//   [sample | records + cell sort] -> [sf(ions) | real_ele] -> sf finalize
+//   -> ele_potential -> [FP64 GEMM: (Q; psibar) = S_ext (dpsi d + b*)] -> post_charges
+//   -> [sf(electrodes) | real_ie] -> sf finalize -> ion_force -> energy,
+// with the ion-ion real-space pass beside the chain from the cell sort to the force
+// pass ([a | b]: one launch whose blocks run both parts).  Structure-factor partial
+// sums are added in chunk order by a finalize pass; real-space neighbours are
+// visited in a fixed (cell, index) order.  There are no floating-point atomics, so
+// two runs on the same inputs give bitwise-identical results.
 #include <math.h>
 
 #include <algorithm>
@@ -53,78 +54,72 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[NT / 64]
 }
 
 // ============================================================ particle records
-// Per particle (grid: particle tiles x replicas): the fractional coordinates
+// One block of 1024 threads per replica (the set-up binning of the electrodes uses
+// the same code).  Per particle, in input order: the fractional coordinates
 // s = (x/Lx, y/Ly, z/Lz), x and y wrapped into [0, 1), as 32-bit fixed point with
-// the FP32 charge (REC bit 0) and/or in FP64 with the FP64 charge (REC bit 1), in
-// input order; the range check (z in [0, H], finite coordinates and charge); and
-// the cell sort key (cell << 13 | index within the replica).
-template <int REC>
-__global__ __launch_bounds__(256) void k_records(Geom g, const int64_t* __restrict__ off,
-                                                 const double* __restrict__ xyz, const double* __restrict__ q,
-                                                 int64_t N, uint4* __restrict__ fx, double4* __restrict__ d4,
-                                                 unsigned* __restrict__ keys, unsigned* status) {
-  const int r = blockIdx.y;
-  const int64_t b0 = off[r];
-  const int n = (int)(off[r + 1] - b0);
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= n) return;
-  const int64_t i = b0 + k;
-  const double x = xyz[i], y = xyz[N + i], z = xyz[2 * N + i];
-  const double qi = q ? q[i] : 0.0;
-  if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) atomicOr(status, ST_RANGE);
-  const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
-  keys[i] = ((unsigned)cell_index(g, sx, sy, z) << 13) | (unsigned)k;
-  if (REC & 1) fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
-  if (REC & 2) d4[i] = make_double4(sx, sy, sz, qi);
-}
+// the FP32 charge (REC bit 0) and/or in FP64 with the FP64 charge (REC bit 1); the
+// range check (z in [0, H], finite coordinates and charge); the cell sort key
+// (cell << 13 | index within the replica); and the replica's charge sums.  Then the
+// sort by cell: cell counts (LDS integer atomics), their exclusive scan (the cell
+// starts), a provisional slot per particle from a per-cell cursor, and, since the
+// provisional order inside a cell depends on timing, each particle's final position
+// inside its cell is the number of the cell's keys below its own.  So every cell
+// lists its particles in index order, independent of timing.  Finally the records
+// in cell order.
+struct SortArgs {
+  const int64_t* off;
+  const double* xyz;  // SoA 3N
+  const double* q;    // N, or null (electrodes)
+  int64_t N;
+  unsigned* keys;
+  uint4* fx;
+  double4* d4;
+  double* scal;       // R*4 charge sums (q only)
+  int* perm;
+  int* scell;
+  int* cstart;
+  uint4* sfx;
+  double4* sd4;
+  unsigned* status;
+};
 
-// ============================================================ cell lists
-// Per replica (one block of 1024 threads): sum q (neutrality), sum |q|, sum q z
-// (slab term of Eq. (17)), sum q^2 (self term) when charges are given; a counting
-// sort of the particles by cell: cell counts (LDS integer atomics), their exclusive
-// scan (the cell starts), a provisional slot per particle from a per-cell cursor,
-// and then, since the provisional order inside a cell depends on timing, each
-// particle's final position inside its cell is the number of the cell's keys
-// (cell << 13 | index) below its own.  So every cell lists its particles in index
-// order, independent of timing.  Finally the records in cell order.
 template <int REC>
-__global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __restrict__ off,
-                                                   const double* __restrict__ xyz, const double* __restrict__ q,
-                                                   int64_t N, const unsigned* __restrict__ keys,
-                                                   const uint4* __restrict__ fx, const double4* __restrict__ d4,
-                                                   double* __restrict__ scal, int* __restrict__ perm,
-                                                   int* __restrict__ scell, int* __restrict__ cstart,
-                                                   uint4* __restrict__ sfx, double4* __restrict__ sd4,
-                                                   unsigned* status) {
+__device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs& a) {
   __shared__ unsigned prov[kMaxBinParticles];
   __shared__ int cnt[kMaxCells + 1];
   __shared__ int scan[2][kMaxCells + 1];
   __shared__ double red[4][16];
-  const int r = blockIdx.x;
   const int t = threadIdx.x;
-  const int64_t b0 = off[r];
-  const int n = (int)(off[r + 1] - b0);
+  const int64_t b0 = a.off[r];
+  const int n = (int)(a.off[r + 1] - b0);
+  const int64_t N = a.N;
   for (int c = t; c <= g.ncell; c += 1024) cnt[c] = 0;
   __syncthreads();
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = t; k < n; k += 1024) {
-    atomicAdd(&cnt[keys[b0 + k] >> 13], 1);
-    if (q) {
-      const double qi = q[b0 + k], z = xyz[2 * N + b0 + k];
-      v[0] += qi;
-      v[1] += fabs(qi);
-      v[2] += qi * z;
-      v[3] += qi * qi;
-    }
+    const int64_t i = b0 + k;
+    const double x = a.xyz[i], y = a.xyz[N + i], z = a.xyz[2 * N + i];
+    const double qi = a.q ? a.q[i] : 0.0;
+    if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) atomicOr(a.status, ST_RANGE);
+    const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
+    const unsigned key = ((unsigned)cell_index(g, sx, sy, z) << 13) | (unsigned)k;
+    a.keys[i] = key;
+    if (REC & 1) a.fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
+    if (REC & 2) a.d4[i] = make_double4(sx, sy, sz, qi);
+    atomicAdd(&cnt[key >> 13], 1);
+    v[0] += qi;
+    v[1] += fabs(qi);
+    v[2] += qi * z;
+    v[3] += qi * qi;
   }
-  if (q) {
+  if (a.q) {
     block_sum<1024, 4>(v, red);
     if (t == 0) {
-      scal[4 * r + 0] = v[0];
-      scal[4 * r + 1] = v[1];
-      scal[4 * r + 2] = v[2];
-      scal[4 * r + 3] = v[3];
-      if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(status, ST_NONNEUTRAL);
+      a.scal[4 * r + 0] = v[0];
+      a.scal[4 * r + 1] = v[1];
+      a.scal[4 * r + 2] = v[2];
+      a.scal[4 * r + 3] = v[3];
+      if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(a.status, ST_NONNEUTRAL);
     }
   } else {
     __syncthreads();
@@ -139,19 +134,22 @@ __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __rest
     src ^= 1;
   }
   const int* start = scan[src];
-  int* cs = cstart + (size_t)r * (g.ncell + 1);
+  int* cs = a.cstart + (size_t)r * (g.ncell + 1);
   for (int c = t; c <= g.ncell; c += 1024) {
     cs[c] = start[c];
     cnt[c] = start[c];  // per-cell cursor
   }
   __syncthreads();
-  // provisional slots (timing-dependent order inside a cell)
+  // provisional slots (timing-dependent order inside a cell); each thread reads back
+  // the keys it wrote itself
   for (int k = t; k < n; k += 1024) {
-    const unsigned key = keys[b0 + k];
+    const unsigned key = a.keys[b0 + k];
     prov[atomicAdd(&cnt[key >> 13], 1)] = key;
   }
   __syncthreads();
-  // final position inside the cell: the number of the cell's keys below this one
+  // final position inside the cell: the number of the cell's keys below this one.
+  // The records read here were written by other threads of this block before the
+  // barriers above.
   for (int sidx = t; sidx < n; sidx += 1024) {
     const unsigned key = prov[sidx];
     const int c = (int)(key >> 13);
@@ -160,43 +158,11 @@ __global__ __launch_bounds__(1024) void k_cellsort(Geom g, const int64_t* __rest
     for (int u = lo; u < hi; ++u) rank += prov[u] < key;
     const int pos = lo + rank;
     const int64_t i = b0 + (int)(key & 0x1FFFu);
-    perm[b0 + pos] = (int)i;
-    scell[b0 + pos] = c;
-    if (REC & 1) sfx[b0 + pos] = fx[i];
-    if (REC & 2) sd4[b0 + pos] = d4[i];
+    a.perm[b0 + pos] = (int)i;
+    a.scell[b0 + pos] = c;
+    if (REC & 1) a.sfx[b0 + pos] = a.fx[i];
+    if (REC & 2) a.sd4[b0 + pos] = a.d4[i];
   }
-}
-
-void launch_records(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (b.max_nrep == 0) return;
-  dim3 grid(cdiv64(b.max_nrep, 256), b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_records<1>, grid, dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.ion_fx, b.ion_d4,
-                       b.keys, b.status);
-  else
-    hipLaunchKernelGGL(k_records<2>, grid, dim3(256), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.ion_fx, b.ion_d4,
-                       b.keys, b.status);
-}
-
-void launch_cellsort(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (fp32)
-    hipLaunchKernelGGL(k_cellsort<1>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.keys,
-                       b.ion_fx, b.ion_d4, b.scal, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status);
-  else
-    hipLaunchKernelGGL(k_cellsort<2>, dim3(b.R), dim3(1024), 0, s, g, b.off, b.ion_xyz, b.ion_q, b.N, b.keys,
-                       b.ion_fx, b.ion_d4, b.scal, b.perm, b.scell, b.cstart, b.sfx, b.sd4, b.status);
-}
-
-// Electrodes are binned once per handle with the same kernels (both record formats).
-// off2: device {0, n_ele}; keys: n_ele scratch words; status: device word.
-void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,
-                           uint4* fx, double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4,
-                           unsigned* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_records<3>, dim3(cdiv64(n_ele, 256), 1), dim3(256), 0, s, g, off2, ele_xyz,
-                     (const double*)nullptr, (int64_t)n_ele, fx, d4, keys, status);
-  hipLaunchKernelGGL(k_cellsort<3>, dim3(1), dim3(1024), 0, s, g, off2, ele_xyz, (const double*)nullptr,
-                     (int64_t)n_ele, (const unsigned*)keys, (const uint4*)fx, (const double4*)d4, (double*)nullptr,
-                     perm, scell, cstart, sfx, sd4, status);
 }
 
 // ============================================================ sampler
@@ -283,23 +249,24 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// One block per replica: wave 0 draws the 64 start tries while the other four
-// waves draw the P proposals; then wave 0 runs the chain.
-constexpr int kSampleThreads = 320;
-
-__global__ __launch_bounds__(kSampleThreads) void k_sample(Geom g, const uint64_t* __restrict__ seeds, uint64_t step,
-                                                const uint64_t* __restrict__ step_dev,
-                                                const int32_t* __restrict__ kset_in, const double* __restrict__ logq,
-                                                int4* __restrict__ modes,
-                                                double* __restrict__ wout, int32_t* __restrict__ kset_out,
-                                                int32_t* __restrict__ nacc_out, unsigned* status) {
+// One block of NT threads per replica: wave 0 draws the 64 start tries while the
+// other waves draw the P proposals; then wave 0 runs the chain.
+template <int NT>
+__device__ __forceinline__ void sample_block(const Geom& g, int r, const StepBufs& b) {
   extern __shared__ unsigned char smem[];
-  if (step_dev) step = *step_dev;  // graph replays take the step from device memory
-  const int r = blockIdx.x;
+  const uint64_t* __restrict__ seeds = b.seed;
+  const int32_t* __restrict__ kset_in = b.kset_in;
+  const double* __restrict__ logq = b.logq;
+  int4* __restrict__ modes = b.modes;
+  double* __restrict__ wout = b.w;
+  int32_t* __restrict__ kset_out = b.kset_out;
+  int32_t* __restrict__ nacc_out = b.nacc_out;
+  unsigned* status = b.status;
+  const uint64_t step = b.step_dev ? *b.step_dev : b.step;  // graph replays take the step from device memory
   const int P = g.P, M = g.M, K = g.K;
   const int t = threadIdx.x;
   // deterministic modes (0, 0, m), m = 1..M, weight doubled for the pair +-m
-  for (int m = 1 + t; m <= M; m += kSampleThreads) {
+  for (int m = 1 + t; m <= M; m += NT) {
     const double kz = TWO_PI * (double)m / g.Lz;
     const double k2 = kz * kz;
     modes[(size_t)r * K + (m - 1)] = make_int4(0, 0, m, 0);
@@ -310,7 +277,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(Geom g, const uint64_
     return;
   }
   if (kset_in) {
-    for (int l = t; l < P; l += kSampleThreads) {
+    for (int l = t; l < P; l += NT) {
       const int32_t* m = kset_in + ((size_t)r * P + l) * 3;
       const int mx = m[0], my = m[1], mz = m[2];
       if (!valid_mode(g, mx, my, mz)) atomicOr(status, ST_BADKSET);
@@ -342,7 +309,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(Geom g, const uint64_
     proposal(g, seed, step, 2, (uint64_t)t, sx, sy, sz);
     if (valid_mode(g, sx, sy, sz)) atomicMin(&first_valid, t);
   }
-  for (int l = t - 64; l >= 0 && l < P; l += kSampleThreads - 64) {
+  for (int l = t - 64; l >= 0 && l < P; l += NT - 64) {
     int mx, my, mz;
     proposal(g, seed, step, 0, (uint64_t)l, mx, my, mz);
     U64x4 c;
@@ -410,7 +377,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(Geom g, const uint64_
     if (t == 0 && nacc_out) nacc_out[r] = nacc;
   }
   __syncthreads();
-  for (int l = t; l < P; l += kSampleThreads) {
+  for (int l = t; l < P; l += NT) {
     const int s_ = state[l];
     const int mx = s_ < 0 ? start_m[0] : ym[3 * s_ + 0];
     const int my = s_ < 0 ? start_m[1] : ym[3 * s_ + 1];
@@ -428,9 +395,43 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample(Geom g, const uint64_
 
 size_t sample_lds_bytes(int P) { return (size_t)P * (8 + 8 + 4 + 6) + 16; }
 
-void launch_sample(const Geom& g, const StepBufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_sample, dim3(b.R), dim3(kSampleThreads), sample_lds_bytes(g.P), s, g, b.seed, b.step, b.step_dev,
-                     b.kset_in, b.logq, b.modes, b.w, b.kset_out, b.nacc_out, b.status);
+// The step's first launch: blocks [0, nsamp) sample the replicas' modes, blocks
+// [nsamp, nsamp + nsort) make and sort the replicas' particle records (the two are
+// independent; one launch runs them side by side).
+template <int REC>
+__global__ __launch_bounds__(1024) void k_front(Geom g, StepBufs b, SortArgs sa, int nsamp) {
+  if ((int)blockIdx.x < nsamp)
+    sample_block<1024>(g, blockIdx.x, b);
+  else
+    sort_block<REC>(g, blockIdx.x - nsamp, sa);
+}
+
+static SortArgs ion_sort_args(const StepBufs& b) {
+  return SortArgs{b.off,  b.ion_xyz, b.ion_q, b.N,    b.keys,  b.ion_fx, b.ion_d4,
+                  b.scal, b.perm,    b.scell, b.cstart, b.sfx, b.sd4,    b.status};
+}
+
+void launch_front(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
+  const int nsamp = (parts & FRONT_SAMPLE) ? b.R : 0;
+  const int nsort = (parts & FRONT_SORT) ? b.R : 0;
+  if (nsamp + nsort == 0) return;
+  const size_t lds = nsamp ? sample_lds_bytes(g.P) : 0;
+  const SortArgs sa = ion_sort_args(b);
+  if (fp32)
+    hipLaunchKernelGGL(k_front<1>, dim3(nsamp + nsort), dim3(1024), lds, s, g, b, sa, nsamp);
+  else
+    hipLaunchKernelGGL(k_front<2>, dim3(nsamp + nsort), dim3(1024), lds, s, g, b, sa, nsamp);
+}
+
+// Electrodes are binned once per handle with the same code (both record formats).
+// off2: device {0, n_ele}; keys: n_ele scratch words; status: device word.
+void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,
+                           uint4* fx, double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4,
+                           unsigned* status, hipStream_t s) {
+  const SortArgs sa{off2, ele_xyz, nullptr, (int64_t)n_ele, keys, fx, d4, nullptr, perm, scell, cstart, sfx, sd4,
+                    status};
+  StepBufs none{};
+  hipLaunchKernelGGL(k_front<3>, dim3(1), dim3(1024), 0, s, g, none, sa, 0);
 }
 
 void launch_logq_table(const Geom& g, double* T, hipStream_t s) {
@@ -438,17 +439,12 @@ void launch_logq_table(const Geom& g, double* T, hipStream_t s) {
   hipLaunchKernelGGL(k_logq_table, dim3(cdiv64(n, 256)), dim3(256), 0, s, g, T);
 }
 
-// Step counter of a captured step: set from the host, advanced at the end of each
-// replay.
+// Step counter of a captured step: set from the host, advanced by the replay's
+// last kernel.
 __global__ void k_set_step(uint64_t* step_dev, uint64_t v) { *step_dev = v; }
-__global__ void k_advance_step(uint64_t* step_dev) { *step_dev += 1; }
 
 void launch_set_step(uint64_t* step_dev, uint64_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, step_dev, v);
-}
-
-void launch_advance_step(uint64_t* step_dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, step_dev);
 }
 
 // ============================================================ structure factors
@@ -507,17 +503,18 @@ __device__ __forceinline__ void finalize_tile(const Geom& g, int r, int k, const
   }
 }
 
+// Block (tile, chunk, r) of the partial sums: modes [256 tile, 256 tile + 256) over
+// the particle chunk.
 template <bool ION>
-__global__ __launch_bounds__(256) void k_sf64(Geom g, const int64_t* __restrict__ off,
-                                              const double4* __restrict__ pts, const double* __restrict__ qe,
-                                              const int4* __restrict__ modes, double2* __restrict__ part,
-                                              int nchunk) {
-  const int r = blockIdx.z;
-  const int k = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void sf64_block(const Geom& g, const int64_t* __restrict__ off,
+                                           const double4* __restrict__ pts, const double* __restrict__ qe,
+                                           const int4* __restrict__ modes, double2* __restrict__ part, int nchunk,
+                                           int tile, int ch, int r) {
+  const int k = tile * 256 + threadIdx.x;
   const int b = ION ? (int)off[r] : 0;
   const int e = ION ? (int)off[r + 1] : g.n_ele;
   const int chunk = (e - b + nchunk - 1) / nchunk;
-  const int j0 = b + (int)blockIdx.y * chunk;
+  const int j0 = b + ch * chunk;
   const int j1 = min(e, j0 + chunk);
   const double* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
   double sr = 0.0, si = 0.0;
@@ -534,7 +531,7 @@ __global__ __launch_bounds__(256) void k_sf64(Geom g, const int64_t* __restrict_
       sr = fma(qj, cs, sr);
       si = fma(qj, sn, si);
     }
-    part[((size_t)r * nchunk + blockIdx.y) * g.K + k] = make_double2(sr, si);
+    part[((size_t)r * nchunk + ch) * g.K + k] = make_double2(sr, si);
   }
 }
 
@@ -542,15 +539,15 @@ __global__ __launch_bounds__(256) void k_sf64(Geom g, const int64_t* __restrict_
 // hardware sin/cos of the phase in revolutions, FP32 sums over blocks of 64
 // particles carried in FP64.
 template <bool ION>
-__global__ __launch_bounds__(256) void k_sf32(Geom g, const int64_t* __restrict__ off, const uint4* __restrict__ pts,
-                                              const float* __restrict__ qe, const int4* __restrict__ modes,
-                                              double2* __restrict__ part, int nchunk) {
-  const int r = blockIdx.z;
-  const int k = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void sf32_block(const Geom& g, const int64_t* __restrict__ off,
+                                           const uint4* __restrict__ pts, const float* __restrict__ qe,
+                                           const int4* __restrict__ modes, double2* __restrict__ part, int nchunk,
+                                           int tile, int ch, int r) {
+  const int k = tile * 256 + threadIdx.x;
   const int b = ION ? (int)off[r] : 0;
   const int e = ION ? (int)off[r + 1] : g.n_ele;
   const int chunk = (e - b + nchunk - 1) / nchunk;
-  const int j0 = b + (int)blockIdx.y * chunk;
+  const int j0 = b + ch * chunk;
   const int j1 = min(e, j0 + chunk);
   const float* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
   if (k < g.K) {
@@ -583,7 +580,26 @@ __global__ __launch_bounds__(256) void k_sf32(Geom g, const int64_t* __restrict_
       dr += (double)ar;
       di += (double)ai;
     }
-    part[((size_t)r * nchunk + blockIdx.y) * g.K + k] = make_double2(dr, di);
+    part[((size_t)r * nchunk + ch) * g.K + k] = make_double2(dr, di);
+  }
+}
+
+// Partial-sum block lb of stage 1 (ions, ION) or 2 (electrodes with the new charges),
+// lb = (r nchunk + chunk) ktiles + tile.
+template <bool FP32, bool ION>
+__device__ __forceinline__ void sf_block(const Geom& g, const StepBufs& b, int lb) {
+  const int nchunk = ION ? b.nchunk_ion : b.nchunk_ele;
+  const int tile = lb % b.ktiles, ch = (lb / b.ktiles) % nchunk, r = lb / (b.ktiles * nchunk);
+  if constexpr (FP32) {
+    if constexpr (ION)
+      sf32_block<true>(g, b.off, b.ion_fx, nullptr, b.modes, b.part, nchunk, tile, ch, r);
+    else
+      sf32_block<false>(g, b.off, b.ele_fx, b.Qf, b.modes, b.part, nchunk, tile, ch, r);
+  } else {
+    if constexpr (ION)
+      sf64_block<true>(g, b.off, b.ion_d4, nullptr, b.modes, b.part, nchunk, tile, ch, r);
+    else
+      sf64_block<false>(g, b.off, b.ele_d4, b.Q_out, b.modes, b.part, nchunk, tile, ch, r);
   }
 }
 
@@ -594,29 +610,11 @@ __global__ __launch_bounds__(256) void k_sf_finalize(Geom g, const double2* __re
   finalize_tile(g, blockIdx.y, blockIdx.x * 256 + threadIdx.x, part, nchunk, modes, w, S1, coef, rec, stage, status);
 }
 
-void launch_sf_ions(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, hipStream_t s) {
   if (g.K == 0) return;
-  dim3 grid(b.ktiles, b.nchunk_ion, b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_sf32<true>, grid, dim3(256), 0, s, g, b.off, b.ion_fx, (const float*)nullptr, b.modes, b.part,
-                       b.nchunk_ion);
-  else
-    hipLaunchKernelGGL(k_sf64<true>, grid, dim3(256), 0, s, g, b.off, b.ion_d4, (const double*)nullptr, b.modes,
-                       b.part, b.nchunk_ion);
-  hipLaunchKernelGGL(k_sf_finalize, dim3(b.ktiles, b.R), dim3(256), 0, s, g, b.part, b.nchunk_ion, b.modes, b.w, b.S1,
-                     b.coef, fp32 ? b.rec : nullptr, 1, b.status);
-}
-
-void launch_sf_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (g.K == 0) return;
-  dim3 grid(b.ktiles, b.nchunk_ele, b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_sf32<false>, grid, dim3(256), 0, s, g, b.off, b.ele_fx, b.Qf, b.modes, b.part, b.nchunk_ele);
-  else
-    hipLaunchKernelGGL(k_sf64<false>, grid, dim3(256), 0, s, g, b.off, b.ele_d4, b.Q_out, b.modes, b.part,
-                       b.nchunk_ele);
-  hipLaunchKernelGGL(k_sf_finalize, dim3(b.ktiles, b.R), dim3(256), 0, s, g, b.part, b.nchunk_ele, b.modes, b.w, b.S1,
-                     b.coef, fp32 ? b.rec : nullptr, 2, b.status);
+  hipLaunchKernelGGL(k_sf_finalize, dim3(b.ktiles, b.R), dim3(256), 0, s, g, b.part,
+                     stage == 1 ? b.nchunk_ion : b.nchunk_ele, b.modes, b.w, b.S1, b.coef, fp32 ? b.rec : nullptr,
+                     stage, b.status);
 }
 
 // ============================================================ real-space kernels
@@ -812,15 +810,18 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
 // order.  In FP32 the erfc(r/eta) term is not evaluated beyond eta_skip, where it
 // is below 2^-30 of the kept term.
 template <bool FP32>
-__global__ __launch_bounds__(64) void k_real_ele(Geom g, const int64_t* __restrict__ off,
-                                                 const int* __restrict__ cstart, const uint4* __restrict__ sfx,
-                                                 const double4* __restrict__ sd4, const int4* __restrict__ chunks,
-                                                 const int* __restrict__ ele_perm, const int2* __restrict__ ion_runs,
-                                                 const uint4* __restrict__ ele_sfx,
-                                                 const double4* __restrict__ ele_sd4, double* __restrict__ bN) {
-  const int r = blockIdx.y;
-  const int4 ch = chunks[blockIdx.x];  // (cell, first, end) of this wave's electrodes
-  const int e = ch.y + (int)threadIdx.x;
+__device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb, int chunk, int r) {
+  const int64_t* __restrict__ off = bb.off;
+  const int* __restrict__ cstart = bb.cstart;
+  const uint4* __restrict__ sfx = bb.sfx;
+  const double4* __restrict__ sd4 = bb.sd4;
+  const int* __restrict__ ele_perm = bb.ele_perm;
+  const int2* __restrict__ ion_runs = bb.ion_runs;
+  const uint4* __restrict__ ele_sfx = bb.ele_sfx;
+  const double4* __restrict__ ele_sd4 = bb.ele_sd4;
+  double* __restrict__ bN = bb.bN;
+  const int4 ch = bb.ele_chunks[chunk];  // (cell, first, end) of this wave's electrodes
+  const int e = ch.y + (int)(threadIdx.x & 63);
   const bool live = e < ch.z;
   const int ec = live ? e : ch.y;
   const int b0 = (int)off[r];
@@ -922,15 +923,30 @@ __global__ __launch_bounds__(64) void k_real_ele(Geom g, const int64_t* __restri
   if (live) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
 }
 
-void launch_real_ele(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (g.n_ele == 0) return;
-  dim3 grid(b.n_ele_chunks, b.R);
+// k-space stage 1 beside the electrode-side real-space pass (both follow the sort and
+// the sampler): blocks [0, nre) hold four real-space waves each (wave unit
+// u = r n_chunks + chunk), blocks [nre, nre + nsf) are structure-factor partial
+// blocks.  The real-space waves are latency-bound, so they are dispatched first and
+// the arithmetic-bound partial blocks fill the issue slots they leave.
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf, int nre) {
+  const int bid = blockIdx.x;
+  if (bid < nre) {
+    const int u = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (u < b.n_ele_chunks * b.R) real_ele_wave<FP32>(g, b, u % b.n_ele_chunks, u / b.n_ele_chunks);
+  } else {
+    sf_block<FP32, true>(g, b, bid - nre);
+  }
+}
+
+void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
+  const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ion * b.R : 0;
+  const int nre = (parts & STAGE_REAL && g.n_ele > 0) ? (b.n_ele_chunks * b.R + 3) / 4 : 0;
+  if (nsf + nre == 0) return;
   if (fp32)
-    hipLaunchKernelGGL(k_real_ele<true>, grid, dim3(64), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_chunks,
-                       b.ele_perm, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
+    hipLaunchKernelGGL(k_stage_ions<true>, dim3(nsf + nre), dim3(256), 0, s, g, b, nsf, nre);
   else
-    hipLaunchKernelGGL(k_real_ele<false>, grid, dim3(64), 0, s, g, b.off, b.cstart, b.sfx, b.sd4, b.ele_chunks,
-                       b.ele_perm, b.ion_runs, b.ele_sfx, b.ele_sd4, b.bN);
+    hipLaunchKernelGGL(k_stage_ions<false>, dim3(nsf + nre), dim3(256), 0, s, g, b, nsf, nre);
 }
 
 // The force and potential passes: 64 particles per block, the mode list split
@@ -1220,7 +1236,9 @@ void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32,
 //       - (4 pi ke / V) q_i M_z e_z             (slab force, M_z = sum q z + sum Q Z)
 __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, bool live, double qi, double gx,
                                                double gy, double gz, double (*sh)[3][64], const double* scal,
-                                               const double* rsum, const double* Fii, int64_t N, double* F) {
+                                               const double* rsum, const double* Fii, const double* Fie,
+                                               const unsigned* keys, const unsigned char* reach_cell, int64_t N,
+                                               double* F) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   sh[w][0][lane] = gx;
   sh[w][1][lane] = gy;
@@ -1230,11 +1248,17 @@ __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, 
     double gsum[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) gsum[d] = ((sh[0][d][lane] + sh[1][d][lane]) + sh[2][d][lane]) + sh[3][d][lane];
-    const double kq = g.ke * qi;  // the ion-ion real-space sums join here
-    F[i] = -qi * gsum[0] + kq * Fii[i];
-    F[N + i] = -qi * gsum[1] + kq * Fii[N + i];
-    F[2 * N + i] = -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum_total(rsum, r, 0)) +
-                   kq * Fii[2 * N + i];
+    const double kq = g.ke * qi;  // the real-space sums join here
+    double rx = Fii[i], ry = Fii[N + i], rz = Fii[2 * N + i];
+    if (reach_cell[keys[i] >> 13]) {
+      rx += Fie[i];
+      ry += Fie[N + i];
+      rz += Fie[2 * N + i];
+    }
+    F[i] = -qi * gsum[0] + kq * rx;
+    F[N + i] = -qi * gsum[1] + kq * ry;
+    F[2 * N + i] =
+        -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum_total(rsum, r, 0)) + kq * rz;
   }
 }
 
@@ -1242,7 +1266,9 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
                                                     const double4* __restrict__ ion_d4, int64_t N,
                                                     const int4* __restrict__ modes, const double2* __restrict__ coef,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    const double* __restrict__ Fii, double* __restrict__ F) {
+                                                    const double* __restrict__ Fii, const double* __restrict__ Fie,
+                                                    const unsigned* __restrict__ keys,
+                                                    const unsigned char* __restrict__ reach_cell, double* __restrict__ F) {
   __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
@@ -1267,14 +1293,16 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
     gy = fma(TWO_PI * (double)m.y * g.invLy, im, gy);
     gz = fma(TWO_PI * (double)m.z * g.invLz, im, gz);
   }
-  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, Fii, N, F);
+  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, Fii, Fie, keys, reach_cell, N, F);
 }
 
 __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __restrict__ off,
                                                     const uint4* __restrict__ ion_fx, int64_t N,
                                                     const ModeRec32* __restrict__ rec,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    const double* __restrict__ Fii, double* __restrict__ F) {
+                                                    const double* __restrict__ Fii, const double* __restrict__ Fie,
+                                                    const unsigned* __restrict__ keys,
+                                                    const unsigned char* __restrict__ reach_cell, double* __restrict__ F) {
   __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
@@ -1327,7 +1355,8 @@ __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __res
     gy += (double)ay;
     gz += (double)az;
   }
-  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, Fii, N, F);
+  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, Fii, Fie, keys,
+                 reach_cell, N, F);
 }
 
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
@@ -1335,10 +1364,10 @@ void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s)
   dim3 grid(cdiv64(b.max_nrep, 64), b.R);
   if (fp32)
     hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum, b.Fii,
-                       b.F_out);
+                       b.Fie, b.keys, b.reach_cell, b.F_out);
   else
     hipLaunchKernelGGL(k_ionforce64, grid, dim3(256), 0, s, g, b.off, b.ion_d4, b.N, b.modes, b.coef, b.scal, b.rsum,
-                       b.Fii, b.F_out);
+                       b.Fii, b.Fie, b.keys, b.reach_cell, b.F_out);
 }
 
 // ============================================================ ion forces, real space
@@ -1348,8 +1377,9 @@ void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s)
 // which does not depend on the electrode charges and runs beside the k-space and
 // charge-solve passes, leaves its sums in Fii (input order); the ion-electrode part,
 // after the charge solve, visits only the ions of the cells that can reach an
-// electrode (reach ranges built at set-up) and adds its sums to Fii, beside the
-// reciprocal passes; the k-space force pass then adds ke q_i Fii to F.  An electrode run (one z-layer) whose z-extent lies farther than
+// electrode (reach ranges built at set-up) and leaves its sums in Fie (written for
+// exactly those ions); the k-space force pass then adds ke q_i (Fii + Fie) to F,
+// reading Fie only for ions of reach cells.  An electrode run (one z-layer) whose z-extent lies farther than
 // rc from the ion cannot hold a partner and is skipped.
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restrict__ off, int64_t N,
@@ -1439,23 +1469,31 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
   }
 }
 
+// Block bx of the nbx blocks that one replica's reach ranges are split over.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_real_ie(Geom g, const int64_t* __restrict__ off, int64_t N,
-                                                 const int* __restrict__ cstart, const int2* __restrict__ reach,
-                                                 int nreach, const int* __restrict__ perm,
-                                                 const int* __restrict__ scell, const int2* __restrict__ ele_runs,
-                                                 const double2* __restrict__ ele_run_zr,
-                                                 const uint4* __restrict__ sfx, const double4* __restrict__ sd4,
-                                                 const int* __restrict__ ele_cstart,
-                                                 const uint4* __restrict__ ele_sfx,
-                                                 const double4* __restrict__ ele_sd4, const float* __restrict__ Qsf,
-                                                 const double* __restrict__ Qsd, double* __restrict__ Fii) {
+__device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r) {
+  const int64_t* __restrict__ off = bb.off;
+  const int64_t N = bb.N;
+  const int* __restrict__ cstart = bb.cstart;
+  const int2* __restrict__ reach = bb.reach;
+  const int nreach = bb.nreach;
+  const int* __restrict__ perm = bb.perm;
+  const int* __restrict__ scell = bb.scell;
+  const int2* __restrict__ ele_runs = bb.ele_runs;
+  const double2* __restrict__ ele_run_zr = bb.ele_run_zr;
+  const uint4* __restrict__ sfx = bb.sfx;
+  const double4* __restrict__ sd4 = bb.sd4;
+  const int* __restrict__ ele_cstart = bb.ele_cstart;
+  const uint4* __restrict__ ele_sfx = bb.ele_sfx;
+  const double4* __restrict__ ele_sd4 = bb.ele_sd4;
+  const float* __restrict__ Qsf = bb.Qsf;
+  const double* __restrict__ Qsd = bb.Qsd;
+  double* __restrict__ Fie = bb.Fie;
   using Entry = typename std::conditional<FP32, float4, double4>::type;
   __shared__ Entry ring_all[4][kRingAlloc];
-  const int r = blockIdx.y;
   const int b0 = (int)off[r];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gw = blockIdx.x * 4 + w, stride = gridDim.x * 4;
+  const int gw = bx * 4 + w, stride = nbx * 4;
   Entry* ring = ring_all[w];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   const int n = g.n_ele;
@@ -1552,9 +1590,9 @@ __global__ __launch_bounds__(256) void k_real_ie(Geom g, const int64_t* __restri
       }
       if ((threadIdx.x & 63) == 0) {
         const int i = perm[k];
-        Fii[i] += fx;
-        Fii[N + i] += fy;
-        Fii[2 * N + i] += fz;
+        Fie[i] = fx;
+        Fie[N + i] = fy;
+        Fie[2 * N + i] = fz;
       }
     }
   }
@@ -1571,17 +1609,29 @@ void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
                        b.sfx, b.sd4, b.Fii, b.phi);
 }
 
-void launch_real_ie(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (b.max_nrep == 0 || b.nreach == 0) return;
-  dim3 grid(64, b.R);  // 256 waves per replica walk its reach ranges
-  if (fp32)
-    hipLaunchKernelGGL(k_real_ie<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.reach, b.nreach, b.perm,
-                       b.scell, b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf,
-                       b.Qsd, b.Fii);
+// k-space stage 2 beside the ion-electrode real-space pass (both follow the charge
+// solve): blocks [0, nie) are the real-space blocks, kIeBlocks per replica walking
+// its reach ranges (dispatched first, being latency-bound), blocks [nie, nie + nsf)
+// structure-factor partial blocks (electrodes with the new charges).
+constexpr int kIeBlocks = 64;
+
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie) {
+  const int bid = blockIdx.x;
+  if (bid < nie)
+    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks);
   else
-    hipLaunchKernelGGL(k_real_ie<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.reach, b.nreach, b.perm,
-                       b.scell, b.ele_runs, b.ele_run_zr, b.sfx, b.sd4, b.ele_cstart, b.ele_sfx, b.ele_sd4, b.Qsf,
-                       b.Qsd, b.Fii);
+    sf_block<FP32, false>(g, b, bid - nie);
+}
+
+void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
+  const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ele * b.R : 0;
+  const int nie = (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? kIeBlocks * b.R : 0;
+  if (nsf + nie == 0) return;
+  if (fp32)
+    hipLaunchKernelGGL(k_stage_ele<true>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
+  else
+    hipLaunchKernelGGL(k_stage_ele<false>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
@@ -1614,9 +1664,11 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int64_t* __restric
                                                 const double2* __restrict__ S1, const double* __restrict__ w,
                                                 const double* __restrict__ scal, const double* __restrict__ rsum,
                                                 const double* __restrict__ dpsi, double* __restrict__ energy,
-                                                int fixedQ, unsigned* status) {
+                                                int fixedQ, unsigned* status, uint64_t* __restrict__ step_adv) {
   __shared__ double sh[2][4];
   const int r = blockIdx.x;
+  if (step_adv && r == 0 && threadIdx.x == 0) *step_adv += 1;  // the replay's last kernel advances the step
+  if (!energy) return;
   double v[2] = {0.0, 0.0};
   for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
   for (int k = threadIdx.x; k < g.K; k += 256) {
@@ -1634,9 +1686,9 @@ __global__ __launch_bounds__(256) void k_energy(Geom g, const int64_t* __restric
 }
 
 void launch_energy(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s) {
-  if (!b.energy_out) return;
-  hipLaunchKernelGGL(k_energy, dim3(b.R), dim3(256), 0, s, g, b.off, b.ion_q, b.phi, b.S1, b.w, b.scal, b.rsum,
-                     b.dpsi, b.energy_out, fixedQ, b.status);
+  if (!b.energy_out && !b.step_adv) return;
+  hipLaunchKernelGGL(k_energy, dim3(b.energy_out ? b.R : 1), dim3(256), 0, s, g, b.off, b.ion_q, b.phi, b.S1, b.w,
+                     b.scal, b.rsum, b.dpsi, b.energy_out, fixedQ, b.status, b.step_adv);
 }
 
 }  // namespace srbe

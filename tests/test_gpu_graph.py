@@ -82,3 +82,31 @@ def test_graph_fixed_charges():
     finally:
         gr.close()
         sysm.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_split_launches_match_fused(precision):
+    """With phase timing on, the fused launches run part by part; the results are the
+    same bits as the fused step's."""
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import binding
+    R = 3
+    w, reps = _replicas(R)
+    sysm = srbe_amd.System(dict(w["params"], kspace_tol=1e-16), w["ele_pos"], w["ele_side"])
+    off, xyz, q, dp, sd = gpu_inputs([r[0] for r in reps], [r[1] for r in reps], [0.5, 1.0, 2.0], [21, 22, 23])
+    try:
+        ref = sysm.step(off, xyz, q, dp, sd, 9, precision=precision)
+        torch.cuda.synchronize()
+        ref = {k: (v.clone() if v is not None else None) for k, v in ref.items()}
+        binding.srbe_profile_enable(sysm.h, True)
+        got = sysm.step(off, xyz, q, dp, sd, 9, precision=precision)
+        torch.cuda.synchronize()
+        prof = binding.srbe_profile_read(sysm.h)
+        binding.srbe_profile_enable(sysm.h, False)
+        assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+        _same(got, ref)
+        for name in ("sample", "cellsort", "sf_ions", "real_ele", "real_ii", "ele_potential", "cp_gemm",
+                     "post_charges", "sf_ele", "real_ie", "ion_force", "energy"):
+            assert prof[name][1] == 1, (name, prof[name])
+    finally:
+        sysm.close()
