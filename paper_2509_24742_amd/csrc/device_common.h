@@ -43,6 +43,11 @@ constexpr int kMaxCells = 2048;
 // consecutive cell indices (whose particles are adjacent in the cell-sorted order).
 // At most 7 z-layers (nzs <= 3) x 3 rows x 2 pieces (a periodic wrap splits a row).
 constexpr int kRunMax = 42;
+// Entries past the end of every record array that the neighbour scan reads (its
+// full rounds request the records of up to three rounds ahead, which may reach 191
+// entries past the run's end; the values read there are never used).  Such arrays
+// are allocated with this many extra entries.
+constexpr int kScanPad = 192;
 
 // Cell of a position (x, y wrapped by the caller into fractions sx, sy in [0,1)).
 __device__ __forceinline__ int cell_index(const Geom& g, double sx, double sy, double z) {

@@ -473,8 +473,8 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.perm, (size_t)N1 * sizeof(int)},
       {(void**)&b.scell, (size_t)N1 * sizeof(int)},
       {(void**)&b.cstart, (size_t)R * (g.ncell + 1) * sizeof(int)},
-      {(void**)&b.sfx, fp32 ? (size_t)N1 * sizeof(uint4) : 0},
-      {(void**)&b.sd4, fp32 ? 0 : (size_t)N1 * sizeof(double4)},
+      {(void**)&b.sfx, fp32 ? (size_t)(N1 + kScanPad) * sizeof(uint4) : 0},
+      {(void**)&b.sd4, fp32 ? 0 : (size_t)(N1 + kScanPad) * sizeof(double4)},
       {(void**)&b.part, (size_t)R * nch * K * sizeof(double2)},
       {(void**)&b.S1, (size_t)R * K * sizeof(double2)},
       {(void**)&b.coef, (size_t)R * K * sizeof(double2)},
@@ -484,8 +484,8 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.V, (size_t)R * ldcp(n) * sizeof(double)},
       {(void**)&b.Qext, fixedQ ? 0 : (size_t)b.ksplit * R * (n + 1) * sizeof(double)},
       {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
-      {(void**)&b.Qsf, fp32 ? (size_t)R * n * sizeof(float) : 0},
-      {(void**)&b.Qsd, fp32 ? 0 : (size_t)R * n * sizeof(double)},
+      {(void**)&b.Qsf, fp32 ? ((size_t)R * n + kScanPad) * sizeof(float) : 0},
+      {(void**)&b.Qsd, fp32 ? 0 : ((size_t)R * n + kScanPad) * sizeof(double)},
       {(void**)&b.rsum, (size_t)R * 16 * sizeof(double)},
       {(void**)&b.phi, (size_t)N1 * sizeof(double)},
       {(void**)&b.Fii, (size_t)3 * N1 * sizeof(double)},
@@ -662,8 +662,8 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ion_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
     al((void**)&h->ele_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
     al((void**)&h->ele_run_zr, (size_t)g.ncell * kRunMax * sizeof(double2));
-    al((void**)&h->ele_sfx, n * sizeof(uint4));
-    al((void**)&h->ele_sd4, n * sizeof(double4));
+    al((void**)&h->ele_sfx, (n + kScanPad) * sizeof(uint4));
+    al((void**)&h->ele_sd4, (n + kScanPad) * sizeof(double4));
     al((void**)&h->status, sizeof(unsigned));
     al((void**)&h->bin_keys, n * sizeof(unsigned));
     al((void**)&h->logq, (size_t)(g.qmax[0] + g.qmax[1] + g.qmax[2] + 3) * sizeof(double));

@@ -695,7 +695,9 @@ __device__ __forceinline__ unsigned lanes_below(uint64_t m) {
 // Neighbour scan of ONE particle by a whole wave.  The candidates are the records of
 // the particle's neighbour runs (runs of consecutive cells, -1 terminated, at most
 // kRunMax; range(s, run, b, e) turns run s into a record range [b, e), empty if the
-// run can be skipped).  A wave round tests 64 candidates, one per lane (coalesced
+// run can be skipped).  Lane s resolves run s first, so the ranges of all runs are
+// loaded at once (not one dependent chain per run) and the scan then takes them
+// from the lanes in run order.  A wave round tests 64 candidates, one per lane (coalesced
 // loads): inside a run a round is 64 consecutive records; the remainder of a run
 // is topped up with the heads of the following runs (up to kSegMax pieces), so
 // short runs do not leave lanes idle.  load(j) reads record j (the records of the
@@ -713,23 +715,28 @@ constexpr int kRing = 128;
 constexpr int kRingAlloc = kRing + 64;  // ring + one discard slot per lane
 constexpr int kSegMax = 4;
 
-template <class Entry, class RangeF, class LoadF, class TestF, class EvalF>
+static_assert(kRunMax < 64, "one lane per run, and a terminator lane");
+
+template <class Entry, class RangeF, class LoadF, class RowF, class TestF, class EvalF>
 __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* __restrict__ ring, RangeF range,
-                                          LoadF load, TestF test, EvalF eval) {
+                                          LoadF load, RowF load_row, TestF test, EvalF eval) {
   const int lane = threadIdx.x & 63;
-  int s = 0, pos = 0, end = 0;
+  int rb = 0, re = 0;  // lane s: run s as a record range
+  const int2 rc = lane < kRunMax ? runs[lane] : make_int2(-1, -1);
+  const uint64_t term = __ballot(rc.x < 0);  // non-zero: the lanes >= kRunMax count as terminators
+  const uint64_t listed = (1ull << __builtin_ctzll(term)) - 1;  // the runs before the first terminator
+  if ((listed >> lane) & 1) range(lane, rc, rb, re);
+  uint64_t live = __ballot(rb < re);
+  int pos = 0, end = 0;
   unsigned head = 0, tail = 0;
   auto next_run = [&]() {
-    while (pos >= end && s < kRunMax) {
-      const int2 rc = runs[s];
-      if (rc.x < 0) {
-        s = kRunMax;
-        break;
-      }
-      range(s, rc, pos, end);
-      ++s;
-    }
-    return pos < end;
+    if (pos < end) return true;
+    if (!live) return false;
+    const int s = __builtin_ctzll(live);
+    live &= live - 1;
+    pos = __builtin_amdgcn_readlane(rb, s);
+    end = __builtin_amdgcn_readlane(re, s);
+    return true;
   };
   auto round = [&](const auto& rec, int j, bool valid) {
     Entry ent;
@@ -746,26 +753,28 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
   };
   while (next_run()) {
     if (end - pos >= 64) {
-      // full rounds inside the run, three record buffers in rotation: the records
-      // of the next two rounds are in flight while the current round is tested.
-      // Loads past the run are clamped to its last record and not used.  (Each
-      // buffer is reloaded in place after use, so no in-flight register is copied.)
-      auto ld = [&](int off) { return load(min(pos + off + lane, end - 1)); };
-      auto A = ld(0), B = ld(64), C = ld(128);
-      for (;;) {
-        round(A, pos + lane, true);
-        pos += 64;
-        if (end - pos < 64) break;
-        A = ld(128);
-        round(B, pos + lane, true);
-        pos += 64;
-        if (end - pos < 64) break;
-        B = ld(128);
-        round(C, pos + lane, true);
-        pos += 64;
-        if (end - pos < 64) break;
-        C = ld(128);
+      // full rounds inside the run in groups of three, three record buffers in
+      // rotation: the records of the next two rounds are in flight while the
+      // current round is tested, and each buffer is reloaded in place after use,
+      // unconditionally, so no in-flight register is copied or merged.  load_row(j0)
+      // reads record j0 + lane from a wave-uniform base, so a round's load needs no
+      // per-lane address arithmetic.  Requests past the run (at most kScanPad
+      // records, inside the arrays' padding) are not used.
+      const int p0 = pos, nfull = (end - pos) >> 6;
+      auto ld = [&](int t) { return load_row(p0 + 64 * t); };
+      auto A = ld(0), B = ld(1), C = ld(2);
+      int t = 0;
+      for (; t + 3 <= nfull; t += 3) {
+        round(A, p0 + 64 * t + lane, true);
+        A = ld(t + 3);
+        round(B, p0 + 64 * (t + 1) + lane, true);
+        B = ld(t + 4);
+        round(C, p0 + 64 * (t + 2) + lane, true);
+        C = ld(t + 5);
       }
+      if (t < nfull) round(A, p0 + 64 * t + lane, true);
+      if (t + 1 < nfull) round(B, p0 + 64 * (t + 1) + lane, true);
+      pos = p0 + 64 * nfull;
     }
     if (pos >= end) continue;
     // the run's remainder (< 64 records), topped up from the following runs:
@@ -1407,13 +1416,18 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
     const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
     const float a1 = (float)g.alpha, rc2 = (float)(g.rc * g.rc);
     float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
+    // the pair test 0 < r^2 < rc^2 as one unsigned compare of the bit patterns (r^2 is
+    // not negative); r = 0 is the ion itself (two ions at one point have no finite
+    // pair term)
+    const unsigned rc2m1 = __float_as_uint(rc2) - 1u;
     wave_scan(iruns, ring, ion_range, [&](int j) { return sfx[j]; },
-              [&](const uint4& p, int j, float4& ent) {
+              [&](int j0) { return (sfx + j0)[threadIdx.x & 63]; },
+              [&](const uint4& p, int, float4& ent) {
                 ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
                 ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
                 ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
                 ent.w = __uint_as_float(p.w);
-                return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
+                return __float_as_uint(ent.x * ent.x + ent.y * ent.y + ent.z * ent.z) - 1u < rc2m1;
               },
               [&](const float4& en) {
                 const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
@@ -1435,6 +1449,7 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
     const double a = g.alpha, rc2 = g.rc * g.rc;
     double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
     wave_scan(iruns, ring, ion_range, [&](int j) { return sd4[j]; },
+              [&](int j0) { return (sd4 + j0)[threadIdx.x & 63]; },
               [&](const double4& p, int j, double4& ent) {
                 double sx = pi_.x - p.x, sy = pi_.y - p.y;
                 sx -= rint(sx);
@@ -1524,6 +1539,12 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
                     p.w = __float_as_uint(Qr[j]);
                     return p;
                   },
+                  [&](int j0) {
+                    const int l = threadIdx.x & 63;
+                    uint4 p = (ele_sfx + j0)[l];
+                    p.w = __float_as_uint((Qr + j0)[l]);
+                    return p;
+                  },
                   [&](const uint4& p, int, float4& ent) {
                     ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
                     ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
@@ -1561,6 +1582,12 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
                   [&](int j) {
                     double4 p = ele_sd4[j];
                     p.w = Qr[j];
+                    return p;
+                  },
+                  [&](int j0) {
+                    const int l = threadIdx.x & 63;
+                    double4 p = (ele_sd4 + j0)[l];
+                    p.w = (Qr + j0)[l];
                     return p;
                   },
                   [&](const double4& p, int, double4& ent) {
