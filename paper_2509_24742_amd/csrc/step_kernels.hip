@@ -693,42 +693,49 @@ __device__ __forceinline__ unsigned lanes_below(uint64_t m) {
 }
 
 // Neighbour scan of ONE particle by a whole wave.  The candidates are the records of
-// the particle's neighbour runs (runs of consecutive cells, -1 terminated, at most
-// kRunMax; range(s, run, b, e) turns run s into a record range [b, e), empty if the
-// run can be skipped).  Lane s resolves run s first, so the ranges of all runs are
-// loaded at once (not one dependent chain per run) and the scan then takes them
-// from the lanes in run order.  A wave round tests 64 candidates, one per lane (coalesced
-// loads): inside a run a round is 64 consecutive records; the remainder of a run
-// is topped up with the heads of the following runs (up to kSegMax pieces), so
-// short runs do not leave lanes idle.  load(j) reads record j (the records of the
-// next two full rounds are requested before the current round is tested);
-// test(record, j, entry) fills the pair entry and says whether the pair is within
-// range (evaluated branch-free: every lane of a round holds a valid j).  The hits of a round are appended in
+// the particle's neighbour runs: lane s holds run s as a record range [rb, re) (see
+// resolve_runs; an empty range is skipped), and the scan takes the runs from the
+// lanes in order.  A wave round tests 64 candidates, one per lane (coalesced loads):
+// inside a run a round is 64 consecutive records; the remainder of a run is topped
+// up with the heads of the following runs (up to kSegMax pieces), so short runs do
+// not leave lanes idle.  load(j) reads record j; test(record, j, entry) fills the
+// pair entry and says whether the pair is within range (evaluated branch-free:
+// every lane of a round holds a valid j).  The hits of a round are appended in
 // candidate order to a wave-private LDS ring (positions from a ballot and a lane
 // prefix count; lanes without a hit write to their own slot past the ring, so the
-// store needs no branch).  Whenever 64 entries are queued every lane evaluates one;
-// the rest are evaluated at the end.  The ring holds at most 63 + 64 entries, so
-// kRing = 128 never overflows.  All control flow is wave-uniform; each lane
-// accumulates its share and the caller reduces them with wave_sum, so the result
-// does not depend on timing.
+// store needs no branch).  head and tail count the entries evaluated and queued;
+// whenever 64 entries are queued, eval_block(head, head + 64) evaluates them, one per
+// lane.  Entries left queued at the end stay in the ring: the caller evaluates them
+// later, possibly together with the next particle's (so a wave that scans several
+// particles in turn evaluates full blocks of 64 except at its very end).  The ring
+// holds at most 63 + 64 entries, so kRing = 128 never overflows.  All control flow
+// is wave-uniform; the evaluation order of the entries is fixed, so the result does
+// not depend on timing.
 constexpr int kRing = 128;
 constexpr int kRingAlloc = kRing + 64;  // ring + one discard slot per lane
 constexpr int kSegMax = 4;
-
 static_assert(kRunMax < 64, "one lane per run, and a terminator lane");
 
-template <class Entry, class RangeF, class LoadF, class RowF, class TestF, class EvalF>
-__device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* __restrict__ ring, RangeF range,
-                                          LoadF load, RowF load_row, TestF test, EvalF eval) {
+// Lane s turns run s of a -1-terminated run list into a record range [rb, re) with
+// range(s, run, rb, re) (empty when the run can be skipped); the ranges of all runs
+// are loaded at once rather than as one dependent chain per run.
+template <class RangeF>
+__device__ __forceinline__ void resolve_runs(const int2* __restrict__ runs, RangeF range, int& rb, int& re) {
   const int lane = threadIdx.x & 63;
-  int rb = 0, re = 0;  // lane s: run s as a record range
+  rb = 0;
+  re = 0;
   const int2 rc = lane < kRunMax ? runs[lane] : make_int2(-1, -1);
   const uint64_t term = __ballot(rc.x < 0);  // non-zero: the lanes >= kRunMax count as terminators
   const uint64_t listed = (1ull << __builtin_ctzll(term)) - 1;  // the runs before the first terminator
   if ((listed >> lane) & 1) range(lane, rc, rb, re);
+}
+
+template <class Entry, class LoadF, class RowF, class TestF, class EvalF>
+__device__ __forceinline__ void wave_scan(int rb, int re, Entry* __restrict__ ring, unsigned& head, unsigned& tail,
+                                          LoadF load, RowF load_row, TestF test, EvalF eval_block) {
+  const int lane = threadIdx.x & 63;
   uint64_t live = __ballot(rb < re);
   int pos = 0, end = 0;
-  unsigned head = 0, tail = 0;
   auto next_run = [&]() {
     if (pos < end) return true;
     if (!live) return false;
@@ -747,7 +754,7 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
     tail += (unsigned)__popcll(m);
     if (tail - head >= 64) {
       __builtin_amdgcn_wave_barrier();
-      eval(ring[(head + lane) & (kRing - 1)]);
+      eval_block(head, head + 64);
       head += 64;
     }
   };
@@ -804,8 +811,6 @@ __device__ __forceinline__ void wave_scan(const int2* __restrict__ runs, Entry* 
     const int jj = valid ? j : base[0];  // lane 0 always holds a valid record
     round(load(jj), jj, valid);
   }
-  __builtin_amdgcn_wave_barrier();
-  if ((unsigned)lane < tail - head) eval(ring[(head + lane) & (kRing - 1)]);
 }
 
 // Real-space potential of the ions at each electrode (real-space part of Eq. (19)):
@@ -1382,14 +1387,54 @@ void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s)
 // ============================================================ ion forces, real space
 // F_i += -ke q_i sum_j q_j K_ii'(r) r^ - ke q_i sum_e Q_e K_ig'(r) r^ over the
 // neighbouring cells (r < rc), phi_i = ke sum_j q_j K_ii(r) (for the energy).
-// One wave per cell-sorted ion (see wave_scan).  Two kernels: the ion-ion part,
+// A wave scans several consecutive cell-sorted ions in turn (see wave_scan), one
+// ion at a time, and carries its hit ring from one ion to the next: an evaluation
+// block may hold the previous ion's last entries and the current ion's first ones,
+// and each lane adds a term to the previous or the current ion's sums by the
+// entry's position (entries below `bound` are the previous ion's).  An ion's sums
+// are final once its last entry has been evaluated.  Two kernels: the ion-ion part,
 // which does not depend on the electrode charges and runs beside the k-space and
 // charge-solve passes, leaves its sums in Fii (input order); the ion-electrode part,
 // after the charge solve, visits only the ions of the cells that can reach an
 // electrode (reach ranges built at set-up) and leaves its sums in Fie (written for
 // exactly those ions); the k-space force pass then adds ke q_i (Fii + Fie) to F,
-// reading Fie only for ions of reach cells.  An electrode run (one z-layer) whose z-extent lies farther than
-// rc from the ion cannot hold a partner and is skipped.
+// reading Fie only for ions of reach cells.  An electrode run (one z-layer) whose
+// z-extent lies farther than rc from the ion cannot hold a partner and is skipped.
+
+// The previous and the current ion's per-lane sums (NV values each) and the ring
+// position where the previous ion's entries end.
+template <class T, int NV>
+struct CarriedSums {
+  T p[NV], c[NV];
+  unsigned bound = 0;
+  __device__ __forceinline__ CarriedSums() {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) p[v] = c[v] = T(0);
+  }
+  // adds term[v] * mul[v] to the previous ion's sums if entry e is one of its own,
+  // else to the current ion's (the other side gets an exact zero)
+  __device__ __forceinline__ void add(unsigned e, const T (&term)[NV], const T (&mul)[NV]) {
+    const bool prev = e < bound;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T tp = prev ? term[v] : T(0), tc = prev ? T(0) : term[v];
+      p[v] = fma(tp, mul[v], p[v]);
+      c[v] = fma(tc, mul[v], c[v]);
+    }
+  }
+  __device__ __forceinline__ void rotate(unsigned tail) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      p[v] = c[v];
+      c[v] = T(0);
+    }
+    bound = tail;
+  }
+};
+
+constexpr int kIiIonsPerWave = 4;  // consecutive sorted ions per wave (ion-ion pass)
+constexpr int kIeIonsPerWave = 1;  // per wave visit of a reach range (ion-electrode pass: latency-bound, so the ions are spread over as many waves as possible)
+
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restrict__ off, int64_t N,
                                                  const int* __restrict__ cstart, const int* __restrict__ perm,
@@ -1397,94 +1442,123 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
                                                  const uint4* __restrict__ sfx, const double4* __restrict__ sd4,
                                                  double* __restrict__ Fii, double* __restrict__ phi) {
   using Entry = typename std::conditional<FP32, float4, double4>::type;
+  using T = typename std::conditional<FP32, float, double>::type;
   __shared__ Entry ring_all[4][kRingAlloc];
   const int r = blockIdx.y;
   const int b0 = (int)off[r], b1 = (int)off[r + 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int k = b0 + blockIdx.x * 4 + w;
-  if (k >= b1) return;  // whole wave
+  const int lane = threadIdx.x & 63;
+  const int kbeg = b0 + (blockIdx.x * 4 + w) * kIiIonsPerWave;
+  if (kbeg >= b1) return;  // whole wave
+  const int kend = min(b1, kbeg + kIiIonsPerWave);
   Entry* ring = ring_all[w];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
-  const int2* iruns = ion_runs + kRunMax * __builtin_amdgcn_readfirstlane(scell[k]);
   auto ion_range = [&](int, int2 rc, int& b, int& e) {
     b = b0 + cs[rc.x];
     e = b0 + cs[rc.y];
   };
-  double fx, fy, fz, ph;
-  if constexpr (FP32) {
-    const uint4 pi_ = sfx[k];
-    const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
-    const float a1 = (float)g.alpha, rc2 = (float)(g.rc * g.rc);
-    float ax = 0.f, ay = 0.f, az = 0.f, ap = 0.f;
-    // the pair test 0 < r^2 < rc^2 as one unsigned compare of the bit patterns (r^2 is
-    // not negative); r = 0 is the ion itself (two ions at one point have no finite
-    // pair term)
-    const unsigned rc2m1 = __float_as_uint(rc2) - 1u;
-    wave_scan(iruns, ring, ion_range, [&](int j) { return sfx[j]; },
-              [&](int j0) { return (sfx + j0)[threadIdx.x & 63]; },
-              [&](const uint4& p, int, float4& ent) {
-                ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
-                ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
-                ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
-                ent.w = __uint_as_float(p.w);
-                return __float_as_uint(ent.x * ent.x + ent.y * ent.y + ent.z * ent.z) - 1u < rc2m1;
-              },
-              [&](const float4& en) {
-                const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
-                const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
-                float f, h;
-                erfc_pair_f(a1, rr, rinv, f, h);
-                ap = fmaf(en.w, f, ap);
-                const float s_ = en.w * h;
-                ax = fmaf(s_, en.x, ax);
-                ay = fmaf(s_, en.y, ay);
-                az = fmaf(s_, en.z, az);
-              });
-    fx = (double)wave_total(ax);
-    fy = (double)wave_total(ay);
-    fz = (double)wave_total(az);
-    ph = (double)wave_total(ap);
-  } else {
-    const double4 pi_ = sd4[k];
-    const double a = g.alpha, rc2 = g.rc * g.rc;
-    double ax = 0.0, ay = 0.0, az = 0.0, ap = 0.0;
-    wave_scan(iruns, ring, ion_range, [&](int j) { return sd4[j]; },
-              [&](int j0) { return (sd4 + j0)[threadIdx.x & 63]; },
-              [&](const double4& p, int j, double4& ent) {
-                double sx = pi_.x - p.x, sy = pi_.y - p.y;
-                sx -= rint(sx);
-                sy -= rint(sy);
-                ent.x = sx * g.Lx;
-                ent.y = sy * g.Ly;
-                ent.z = (pi_.z - p.z) * g.Lz;
-                ent.w = p.w;
-                return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
-              },
-              [&](const double4& en) {
-                const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
-                double f, df;
-                erfc_over_r(a, rr, f, df);
-                ap += en.w * f;
-                const double s_ = -en.w * df / rr;
-                ax += s_ * en.x;
-                ay += s_ * en.y;
-                az += s_ * en.z;
-              });
-    fx = wave_total(ax);
-    fy = wave_total(ay);
-    fz = wave_total(az);
-    ph = wave_total(ap);
+  unsigned head = 0, tail = 0;
+  CarriedSums<T, 4> acc;  // x, y, z force sums and the potential
+  const float a1 = (float)g.alpha;
+  auto eval_block = [&](unsigned e0, unsigned lim) {
+    const unsigned e = e0 + lane;
+    if (e >= lim) return;
+    const Entry en = ring[e & (kRing - 1)];
+    if constexpr (FP32) {
+      const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
+      const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+      float f, h;
+      erfc_pair_f(a1, rr, rinv, f, h);
+      const float s_ = en.w * h;
+      acc.add(e, {s_, s_, s_, en.w}, {en.x, en.y, en.z, f});
+    } else {
+      const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
+      double f, df;
+      erfc_over_r(g.alpha, rr, f, df);
+      const double s_ = -en.w * df / rr;
+      acc.add(e, {s_, s_, s_, en.w}, {en.x, en.y, en.z, f});
+    }
+  };
+  auto finish = [&](int k, const T (&a)[4]) {
+    const double fx = (double)wave_total(a[0]), fy = (double)wave_total(a[1]), fz = (double)wave_total(a[2]),
+                 ph = (double)wave_total(a[3]);
+    if (lane == 0) {
+      const int i = perm[k];
+      Fii[i] = fx;
+      Fii[N + i] = fy;
+      Fii[2 * N + i] = fz;
+      phi[i] = g.ke * ph;
+    }
+  };
+  int home = -1, rb = 0, re = 0;
+  for (int k = kbeg; k < kend; ++k) {
+    const int hk = __builtin_amdgcn_readfirstlane(scell[k]);
+    if (hk != home) {
+      home = hk;
+      resolve_runs(ion_runs + kRunMax * home, ion_range, rb, re);
+    }
+    if constexpr (FP32) {
+      const uint4 pi_ = sfx[k];
+      const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
+      // the pair test 0 < r^2 < rc^2 as one unsigned compare of the bit patterns (r^2
+      // is not negative); r = 0 is the ion itself (two ions at one point have no
+      // finite pair term)
+      const unsigned rc2m1 = __float_as_uint((float)(g.rc * g.rc)) - 1u;
+      wave_scan(rb, re, ring, head, tail, [&](int j) { return sfx[j]; },
+                [&](int j0) { return (sfx + j0)[lane]; },
+                [&](const uint4& p, int, float4& ent) {
+                  ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
+                  ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
+                  ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
+                  ent.w = __uint_as_float(p.w);
+                  return __float_as_uint(ent.x * ent.x + ent.y * ent.y + ent.z * ent.z) - 1u < rc2m1;
+                },
+                eval_block);
+    } else {
+      const double4 pi_ = sd4[k];
+      const double rc2 = g.rc * g.rc;
+      wave_scan(rb, re, ring, head, tail, [&](int j) { return sd4[j]; },
+                [&](int j0) { return (sd4 + j0)[lane]; },
+                [&](const double4& p, int j, double4& ent) {
+                  double sx = pi_.x - p.x, sy = pi_.y - p.y;
+                  sx -= rint(sx);
+                  sy -= rint(sy);
+                  ent.x = sx * g.Lx;
+                  ent.y = sy * g.Ly;
+                  ent.z = (pi_.z - p.z) * g.Lz;
+                  ent.w = p.w;
+                  return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
+                },
+                eval_block);
+    }
+    if (k > kbeg) {  // the previous ion is complete once its last entries are evaluated
+      if (head < acc.bound) {
+        __builtin_amdgcn_wave_barrier();
+        eval_block(head, tail);
+        head = tail;
+      }
+      finish(k - 1, acc.p);
+    }
+    acc.rotate(tail);
   }
-  if ((threadIdx.x & 63) == 0) {
-    const int i = perm[k];
-    Fii[i] = fx;
-    Fii[N + i] = fy;
-    Fii[2 * N + i] = fz;
-    phi[i] = g.ke * ph;
-  }
+  __builtin_amdgcn_wave_barrier();
+  eval_block(head, tail);
+  finish(kend - 1, acc.p);
 }
 
-// Block bx of the nbx blocks that one replica's reach ranges are split over.
+void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (b.max_nrep == 0) return;
+  dim3 grid(cdiv64(b.max_nrep, 4 * kIiIonsPerWave), b.R);
+  if (fp32)
+    hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
+                       b.sfx, b.sd4, b.Fii, b.phi);
+  else
+    hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
+                       b.sfx, b.sd4, b.Fii, b.phi);
+}
+
+// Block bx of the nbx blocks that one replica's reach ranges are split over; each
+// wave takes kIeIonsPerWave consecutive ions of a range at a time.
 template <bool FP32>
 __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r) {
   const int64_t* __restrict__ off = bb.off;
@@ -1505,135 +1579,145 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   const double* __restrict__ Qsd = bb.Qsd;
   double* __restrict__ Fie = bb.Fie;
   using Entry = typename std::conditional<FP32, float4, double4>::type;
+  using T = typename std::conditional<FP32, float, double>::type;
   __shared__ Entry ring_all[4][kRingAlloc];
   const int b0 = (int)off[r];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int gw = bx * 4 + w, stride = nbx * 4;
   Entry* ring = ring_all[w];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   const int n = g.n_ele;
   const double zlim = g.rc + 1e-6;  // skip test margin (fixed-point z is exact to ~1e-8 of the box)
+  const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta);
+  unsigned head = 0, tail = 0;
+  CarriedSums<T, 3> acc;
+  auto eval_block = [&](unsigned e0, unsigned lim) {
+    const unsigned e = e0 + lane;
+    if (e >= lim) return;
+    const Entry en = ring[e & (kRing - 1)];
+    if constexpr (FP32) {
+      const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
+      const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
+      float f1, h1, f2, h2 = 0.f;
+      erfc_pair_f(a1, rr, rinv, f1, h1);
+      if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
+      const float s_ = en.w * (h1 - h2);
+      acc.add(e, {s_, s_, s_}, {en.x, en.y, en.z});
+    } else {
+      const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
+      double f1, d1, f2, d2;
+      erfc_over_r(g.alpha, rr, f1, d1);
+      erfc_over_r(1.0 / g.eta, rr, f2, d2);
+      const double s_ = -en.w * (d1 - d2) / rr;
+      acc.add(e, {s_, s_, s_}, {en.x, en.y, en.z});
+    }
+  };
+  auto finish = [&](int k, const T (&a)[3]) {
+    const double fx = (double)wave_total(a[0]), fy = (double)wave_total(a[1]), fz = (double)wave_total(a[2]);
+    if (lane == 0) {
+      const int i = perm[k];
+      Fie[i] = fx;
+      Fie[N + i] = fy;
+      Fie[2 * N + i] = fz;
+    }
+  };
+  int kprev = -1;
   for (int qr = 0; qr < nreach; ++qr) {
     const int2 cr = reach[qr];
-    const int kend = b0 + cs[cr.y];
-    for (int k = b0 + cs[cr.x] + gw; k < kend; k += stride) {
-      const int home = __builtin_amdgcn_readfirstlane(scell[k]);
-      const int2* eruns = ele_runs + kRunMax * home;
-      const double2* erz = ele_run_zr + kRunMax * home;
-      double fx, fy, fz, qi;
-      if constexpr (FP32) {
-        const uint4 pi_ = sfx[k];
-        const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
-        auto ele_range = [&](int si, int2 rc, int& bb, int& e) {
-          const double2 zr = erz[si];
-          bb = ele_cstart[rc.x];
-          e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb : ele_cstart[rc.y];
-        };
-        const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
-        const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta), rc2 = (float)(g.rc * g.rc);
-        const float* Qr = Qsf + (size_t)r * n;
-        float ax = 0.f, ay = 0.f, az = 0.f;
-        wave_scan(eruns, ring, ele_range,
-                  [&](int j) {
-                    uint4 p = ele_sfx[j];
-                    p.w = __float_as_uint(Qr[j]);
-                    return p;
-                  },
-                  [&](int j0) {
-                    const int l = threadIdx.x & 63;
-                    uint4 p = (ele_sfx + j0)[l];
-                    p.w = __float_as_uint((Qr + j0)[l]);
-                    return p;
-                  },
-                  [&](const uint4& p, int, float4& ent) {
-                    ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
-                    ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
-                    ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
-                    ent.w = __uint_as_float(p.w);
-                    return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
-                  },
-                  [&](const float4& en) {
-                    const float r2 = en.x * en.x + en.y * en.y + en.z * en.z;
-                    const float rinv = __builtin_amdgcn_rsqf(r2), rr = r2 * rinv;
-                    float f1, h1, f2, h2 = 0.f;
-                    erfc_pair_f(a1, rr, rinv, f1, h1);
-                    if (rr < g.eta_skip) erfc_pair_f(a2, rr, rinv, f2, h2);
-                    const float s_ = en.w * (h1 - h2);
-                    ax = fmaf(s_, en.x, ax);
-                    ay = fmaf(s_, en.y, ay);
-                    az = fmaf(s_, en.z, az);
-                  });
-        fx = (double)wave_total(ax);
-        fy = (double)wave_total(ay);
-        fz = (double)wave_total(az);
-        qi = (double)__uint_as_float(pi_.w);
-      } else {
-        const double4 pi_ = sd4[k];
-        const double zi = pi_.z * g.Lz;
-        auto ele_range = [&](int si, int2 rc, int& bb, int& e) {
-          const double2 zr = erz[si];
-          bb = ele_cstart[rc.x];
-          e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb : ele_cstart[rc.y];
-        };
-        const double a = g.alpha, ai = 1.0 / g.eta, rc2 = g.rc * g.rc;
-        const double* Qr = Qsd + (size_t)r * n;
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        wave_scan(eruns, ring, ele_range,
-                  [&](int j) {
-                    double4 p = ele_sd4[j];
-                    p.w = Qr[j];
-                    return p;
-                  },
-                  [&](int j0) {
-                    const int l = threadIdx.x & 63;
-                    double4 p = (ele_sd4 + j0)[l];
-                    p.w = (Qr + j0)[l];
-                    return p;
-                  },
-                  [&](const double4& p, int, double4& ent) {
-                    double sx = pi_.x - p.x, sy = pi_.y - p.y;
-                    sx -= rint(sx);
-                    sy -= rint(sy);
-                    ent.x = sx * g.Lx;
-                    ent.y = sy * g.Ly;
-                    ent.z = (pi_.z - p.z) * g.Lz;
-                    ent.w = p.w;
-                    return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
-                  },
-                  [&](const double4& en) {
-                    const double rr = sqrt(en.x * en.x + en.y * en.y + en.z * en.z);
-                    double f1, d1, f2, d2;
-                    erfc_over_r(a, rr, f1, d1);
-                    erfc_over_r(ai, rr, f2, d2);
-                    const double s_ = -en.w * (d1 - d2) / rr;
-                    ax += s_ * en.x;
-                    ay += s_ * en.y;
-                    az += s_ * en.z;
-                  });
-        fx = wave_total(ax);
-        fy = wave_total(ay);
-        fz = wave_total(az);
-        qi = pi_.w;
-      }
-      if ((threadIdx.x & 63) == 0) {
-        const int i = perm[k];
-        Fie[i] = fx;
-        Fie[N + i] = fy;
-        Fie[2 * N + i] = fz;
+    const int kstop = b0 + cs[cr.y];
+    for (int kc = b0 + cs[cr.x] + gw * kIeIonsPerWave; kc < kstop; kc += stride * kIeIonsPerWave) {
+      const int kce = min(kstop, kc + kIeIonsPerWave);
+      for (int k = kc; k < kce; ++k) {
+        const int home = __builtin_amdgcn_readfirstlane(scell[k]);
+        const int2* eruns = ele_runs + kRunMax * home;
+        const double2* erz = ele_run_zr + kRunMax * home;
+        int rb, re;
+        if constexpr (FP32) {
+          const uint4 pi_ = sfx[k];
+          const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
+          resolve_runs(eruns,
+                       [&](int si, int2 rc, int& bb_, int& e) {
+                         const double2 zr = erz[si];
+                         bb_ = ele_cstart[rc.x];
+                         e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb_ : ele_cstart[rc.y];
+                       },
+                       rb, re);
+          const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32),
+                      lz = (float)(g.Lz * 0x1.0p-32), rc2 = (float)(g.rc * g.rc);
+          const float* Qr = Qsf + (size_t)r * n;
+          wave_scan(rb, re, ring, head, tail,
+                    [&](int j) {
+                      uint4 p = ele_sfx[j];
+                      p.w = __float_as_uint(Qr[j]);
+                      return p;
+                    },
+                    [&](int j0) {
+                      uint4 p = (ele_sfx + j0)[lane];
+                      p.w = __float_as_uint((Qr + j0)[lane]);
+                      return p;
+                    },
+                    [&](const uint4& p, int, float4& ent) {
+                      ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
+                      ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
+                      ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
+                      ent.w = __uint_as_float(p.w);
+                      return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+                    },
+                    eval_block);
+        } else {
+          const double4 pi_ = sd4[k];
+          const double zi = pi_.z * g.Lz;
+          resolve_runs(eruns,
+                       [&](int si, int2 rc, int& bb_, int& e) {
+                         const double2 zr = erz[si];
+                         bb_ = ele_cstart[rc.x];
+                         e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb_ : ele_cstart[rc.y];
+                       },
+                       rb, re);
+          const double rc2 = g.rc * g.rc;
+          const double* Qr = Qsd + (size_t)r * n;
+          wave_scan(rb, re, ring, head, tail,
+                    [&](int j) {
+                      double4 p = ele_sd4[j];
+                      p.w = Qr[j];
+                      return p;
+                    },
+                    [&](int j0) {
+                      double4 p = (ele_sd4 + j0)[lane];
+                      p.w = (Qr + j0)[lane];
+                      return p;
+                    },
+                    [&](const double4& p, int, double4& ent) {
+                      double sx = pi_.x - p.x, sy = pi_.y - p.y;
+                      sx -= rint(sx);
+                      sy -= rint(sy);
+                      ent.x = sx * g.Lx;
+                      ent.y = sy * g.Ly;
+                      ent.z = (pi_.z - p.z) * g.Lz;
+                      ent.w = p.w;
+                      return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+                    },
+                    eval_block);
+        }
+        if (kprev >= 0) {  // the previous ion is complete once its last entries are evaluated
+          if (head < acc.bound) {
+            __builtin_amdgcn_wave_barrier();
+            eval_block(head, tail);
+            head = tail;
+          }
+          finish(kprev, acc.p);
+        }
+        acc.rotate(tail);
+        kprev = k;
       }
     }
   }
-}
-
-void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (b.max_nrep == 0) return;
-  dim3 grid(cdiv64(b.max_nrep, 4), b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
-                       b.sfx, b.sd4, b.Fii, b.phi);
-  else
-    hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
-                       b.sfx, b.sd4, b.Fii, b.phi);
+  if (kprev >= 0) {
+    __builtin_amdgcn_wave_barrier();
+    eval_block(head, tail);
+    finish(kprev, acc.p);
+  }
 }
 
 // k-space stage 2 beside the ion-electrode real-space pass (both follow the charge
