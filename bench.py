@@ -18,6 +18,7 @@ Printed as one JSON line.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import resource
@@ -46,6 +47,31 @@ FP64_PEAK = 78.6e12                # FP64 MFMA FLOP/s
 SLOTS = {"sf_ions": 12, "sf_ele": 12, "ele_potential": 12, "ion_force": 15,
          "real_ii": 49, "real_ie": 48, "real_ele": 43}
 
+# HBM traffic per launch of the step's kernels, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs scaled by the same counters' reading for a plain copy of COPY_BYTES (see the
+# profile named below).  The figures hold only for the kernel source they were taken
+# on: its SHA-256 is recorded beside them, and a changed source reports null.
+COPY_BYTES = 1 << 29
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kernel_traffic_replica_batch64.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_24742_amd", "csrc", "step_kernels.hip")
+
+
+def measured_traffic():
+    """{phase: HBM bytes per launch} if the recorded figures match the current kernel source, else {}."""
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return {}
+    rec = {}
+    for ln in lines:
+        if ln.startswith("traffic ") or ln.startswith("source_sha256 "):
+            parts = ln.split()
+            rec[parts[1] if parts[0] == "traffic" else "sha"] = parts[-1]
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("sha") != sha:
+        return {}
+    return {k: float(v) for k, v in rec.items() if k != "sha"}
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -58,6 +84,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
+                         "are scaled by)")
     return ap.parse_args()
 
 
@@ -73,6 +102,13 @@ def main():
     from paper_2509_24742_amd import workloads as wl
 
     dev = torch.device("cuda:0")
+    if args.traffic_probe:
+        src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     R = args.replicas
     t0 = time.time()
     wb = wl.replica_batch(R=R)
@@ -185,6 +221,10 @@ def main():
         ach = units[kdom] * SLOTS[kdom] / dur
         roofline = {"bound": "alu", "kernel": kdom, "achieved": ach / 1e12, "peak": LANE_OPS_PEAK / 1e12,
                     "unit": "TVALUop/s", "frac": ach / LANE_OPS_PEAK, "traffic": None}
+    traffic = measured_traffic()
+    if kdom in traffic:
+        roofline["traffic"] = traffic[kdom]
+        roofline["traffic_unit"] = "HBM bytes per launch"
     other = {}
     for k in cands:
         d = phases[k]["avg_us"] * 1e-6
