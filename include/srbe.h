@@ -174,16 +174,17 @@ int srbe_sync_status(srbe_system* h);
 
 /*
  * Per-phase timing (tracing).  When enabled, every later srbe_step records a HIP
- * event before and after each of its phases on the stream that runs it (the ion-ion
- * real-space phase runs on an internal stream beside the others, so it overlaps
- * them).  Phases that a normal step runs together in one launch (the sampler beside
+ * event before and after each of its phases on the stream that runs it (the two
+ * real-space force phases run on an internal stream beside the others, so they
+ * overlap them).  Phases that a normal step runs together in one launch (the sampler beside
  * the cell sort; each structure-factor pass beside a real-space pass) are then
  * launched one after the other, with the same device code and results, so that each
  * can be timed.  srbe_profile_read waits for the events and returns, per phase, the
  * summed duration in milliseconds and the number of launches since the last read
  * (then resets).  Phases, in order: sample, cellsort (particle records and their
  * sort by cell), sf_ions, real_ele, real_ii, ele_potential, cp_gemm, post_charges,
- * sf_ele, real_ie, ion_force, energy; the remaining slots are unused ("").
+ * sf_ele, real_ie, ion_force (the k-space and slab force), energy (the energy and the
+ * real-space sums added to the forces); the remaining slots are unused ("").
  * srbe_phase_name(i) returns the name of phase i.  Captured steps (srbe_graph_*)
  * record no phase events.
  */

@@ -108,7 +108,7 @@ void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32,
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
-void launch_energy(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
+void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 
 // setup kernels
 void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,

@@ -500,23 +500,28 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
   return total;
 }
 
-enum { EV_CS = 0, EV_II };
+enum { EV_CS = 0, EV_POST, EV_AUX };
 enum {
   PH_SAMPLE = 0, PH_CELLSORT, PH_SF_IONS, PH_REAL_ELE, PH_REAL_II, PH_ELE_POTENTIAL, PH_CP_GEMM, PH_POST_CHARGES,
   PH_SF_ELE, PH_REAL_IE, PH_ION_FORCE, PH_ENERGY
 };
 
-// The step (Algorithm 1's order) on the caller's stream, with the ion-ion real-space
-// pass beside it on aux[1]:
+// The step (Algorithm 1's order) on the caller's stream, with the real-space force
+// passes on aux[1] beside it:
 //   s:      [sample | records + cell sort] -> [sf(ions) | real_ele] -> sf finalize ->
-//           ele_potential -> cp_gemm -> post_charges -> [sf(electrodes) | real_ie] ->
-//           sf finalize -> (real_ii) ion_force -> energy
-//   aux[1]: (cell sort) real_ii
+//           ele_potential -> cp_gemm -> post_charges -> sf(electrodes) -> sf finalize ->
+//           ion_force (k-space) -> (aux) final: F += real-space sums; energy
+//   aux[1]: (cell sort) real_ii -> (post_charges) real_ie
 // [a | b] is one launch whose blocks run both parts.  Independent work shares a launch
-// rather than a second stream: a cross-stream wait costs several microseconds in a
-// replayed graph, while kernels on one stream follow each other without a gap.  The
-// ion-ion pass is long enough to pay for its two waits.  With phase timing on, every
-// part is launched on its own (same device code) so that each can be timed.
+// rather than a second stream where it can: a cross-stream wait costs several
+// microseconds in a replayed graph, while kernels on one stream follow each other
+// without a gap.  The two real-space force passes are long enough to pay for the side
+// stream's three waits: the ion-ion pass runs beside the whole k-space chain and the
+// charge solve, the ion-electrode pass (which needs the new charges) beside the
+// electrode structure factors and the k-space force.  The critical stream's launch
+// after each fork is enqueued first, so that it is dispatched first.  With phase
+// timing on, the fused launches run part by part (same device code) so that each part
+// can be timed.
 int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStream_t s) {
   const Geom& g = h->g;
   hipStream_t s1 = h->aux[1];
@@ -532,8 +537,6 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
     launch_front(g, b, fp32, FRONT_SAMPLE | FRONT_SORT, s);
   }
   HIP_OK(h, hipEventRecord(h->ev[EV_CS], s));
-  // the critical stream's next launch is enqueued (and, in a graph, created) before
-  // the side stream's, so that it is dispatched first
   if (split) {
     part(PH_SF_IONS, s, [&] {
       launch_stage_ions(g, b, fp32, STAGE_SF, s);
@@ -544,7 +547,6 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   }
   HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_CS], 0));
   part(PH_REAL_II, s1, [&] { launch_real_ii(g, b, fp32, s1); });
-  HIP_OK(h, hipEventRecord(h->ev[EV_II], s1));
   if (split)
     part(PH_REAL_ELE, s, [&] { launch_stage_ions(g, b, fp32, STAGE_REAL, s); });
   else
@@ -552,19 +554,17 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   part(PH_ELE_POTENTIAL, s, [&] { launch_ele_potential(g, b, fp32, s); });
   if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, s); });
   part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
-  if (split) {
-    part(PH_SF_ELE, s, [&] {
-      launch_stage_ele(g, b, fp32, STAGE_SF, s);
-      launch_sf_finalize(g, b, fp32, 2, s);
-    });
-    part(PH_REAL_IE, s, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s); });
-  } else {
-    launch_stage_ele(g, b, fp32, STAGE_SF | STAGE_REAL, s);
+  HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
+  part(PH_SF_ELE, s, [&] {
+    launch_stage_ele(g, b, fp32, STAGE_SF, s);
     launch_sf_finalize(g, b, fp32, 2, s);
-  }
-  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_II], 0));
+  });
+  HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_POST], 0));
+  part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s1); });
+  HIP_OK(h, hipEventRecord(h->ev[EV_AUX], s1));
   part(PH_ION_FORCE, s, [&] { launch_ion_force(g, b, fp32, s); });
-  part(PH_ENERGY, s, [&] { launch_energy(g, b, fixedQ, s); });
+  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
+  part(PH_ENERGY, s, [&] { launch_final(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());
   return SRBE_OK;
 }

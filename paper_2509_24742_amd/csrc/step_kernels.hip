@@ -1248,11 +1248,10 @@ void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32,
 // ============================================================ ion forces, reciprocal part
 // F_i = -q_i sum_k k Im(coef_k exp(-i k.r_i))   (Eq. (25), coef = w (S1 + S2))
 //       - (4 pi ke / V) q_i M_z e_z             (slab force, M_z = sum q z + sum Q Z)
+// The real-space sums are added by the step's last launch (k_final).
 __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, bool live, double qi, double gx,
                                                double gy, double gz, double (*sh)[3][64], const double* scal,
-                                               const double* rsum, const double* Fii, const double* Fie,
-                                               const unsigned* keys, const unsigned char* reach_cell, int64_t N,
-                                               double* F) {
+                                               const double* rsum, int64_t N, double* F) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   sh[w][0][lane] = gx;
   sh[w][1][lane] = gy;
@@ -1262,17 +1261,9 @@ __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, 
     double gsum[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) gsum[d] = ((sh[0][d][lane] + sh[1][d][lane]) + sh[2][d][lane]) + sh[3][d][lane];
-    const double kq = g.ke * qi;  // the real-space sums join here
-    double rx = Fii[i], ry = Fii[N + i], rz = Fii[2 * N + i];
-    if (reach_cell[keys[i] >> 13]) {
-      rx += Fie[i];
-      ry += Fie[N + i];
-      rz += Fie[2 * N + i];
-    }
-    F[i] = -qi * gsum[0] + kq * rx;
-    F[N + i] = -qi * gsum[1] + kq * ry;
-    F[2 * N + i] =
-        -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum_total(rsum, r, 0)) + kq * rz;
+    F[i] = -qi * gsum[0];
+    F[N + i] = -qi * gsum[1];
+    F[2 * N + i] = -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum_total(rsum, r, 0));
   }
 }
 
@@ -1280,9 +1271,7 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
                                                     const double4* __restrict__ ion_d4, int64_t N,
                                                     const int4* __restrict__ modes, const double2* __restrict__ coef,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    const double* __restrict__ Fii, const double* __restrict__ Fie,
-                                                    const unsigned* __restrict__ keys,
-                                                    const unsigned char* __restrict__ reach_cell, double* __restrict__ F) {
+                                                    double* __restrict__ F) {
   __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
@@ -1307,16 +1296,14 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
     gy = fma(TWO_PI * (double)m.y * g.invLy, im, gy);
     gz = fma(TWO_PI * (double)m.z * g.invLz, im, gz);
   }
-  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, Fii, Fie, keys, reach_cell, N, F);
+  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, N, F);
 }
 
 __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __restrict__ off,
                                                     const uint4* __restrict__ ion_fx, int64_t N,
                                                     const ModeRec32* __restrict__ rec,
                                                     const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    const double* __restrict__ Fii, const double* __restrict__ Fie,
-                                                    const unsigned* __restrict__ keys,
-                                                    const unsigned char* __restrict__ reach_cell, double* __restrict__ F) {
+                                                    double* __restrict__ F) {
   __shared__ double sh[4][3][64];
   const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
@@ -1369,19 +1356,18 @@ __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __res
     gy += (double)ay;
     gz += (double)az;
   }
-  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, Fii, Fie, keys,
-                 reach_cell, N, F);
+  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, N, F);
 }
 
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   dim3 grid(cdiv64(b.max_nrep, 64), b.R);
   if (fp32)
-    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum, b.Fii,
-                       b.Fie, b.keys, b.reach_cell, b.F_out);
+    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum,
+                       b.F_out);
   else
     hipLaunchKernelGGL(k_ionforce64, grid, dim3(256), 0, s, g, b.off, b.ion_d4, b.N, b.modes, b.coef, b.scal, b.rsum,
-                       b.Fii, b.Fie, b.keys, b.reach_cell, b.F_out);
+                       b.F_out);
 }
 
 // ============================================================ ion forces, real space
@@ -1770,36 +1756,60 @@ void launch_cell_zrange(const Geom& g, const int* cstart, const double* ele_xyz,
 // E* = 1/2 dpsi d.Q - 1/2 b*.Q + c*,  c* = 1/2 sum_i q_i phi_i + 1/2 sum_k w_k |S1_k|^2
 //      - ke alpha/sqrt(pi) sum q^2 + ke (2 pi / V) (sum q z)^2
 // (1/2 Q^T A Q - b*^T Q + c* at the constrained charges, where Q^T A Q = b*.Q + dpsi d.Q).
-__global__ __launch_bounds__(256) void k_energy(Geom g, const int64_t* __restrict__ off,
-                                                const double* __restrict__ ion_q, const double* __restrict__ phi,
-                                                const double2* __restrict__ S1, const double* __restrict__ w,
-                                                const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                const double* __restrict__ dpsi, double* __restrict__ energy,
-                                                int fixedQ, unsigned* status, uint64_t* __restrict__ step_adv) {
+__device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBufs& b, int fixedQ) {
   __shared__ double sh[2][4];
-  const int r = blockIdx.x;
-  if (step_adv && r == 0 && threadIdx.x == 0) *step_adv += 1;  // the replay's last kernel advances the step
-  if (!energy) return;
+  const int64_t* __restrict__ off = b.off;
+  const double* __restrict__ ion_q = b.ion_q;
+  const double* __restrict__ phi = b.phi;
+  const double* __restrict__ scal = b.scal;
+  const double* __restrict__ rsum = b.rsum;
   double v[2] = {0.0, 0.0};
   for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
   for (int k = threadIdx.x; k < g.K; k += 256) {
-    const double2 s = S1[(size_t)r * g.K + k];
-    v[1] += w[(size_t)r * g.K + k] * (s.x * s.x + s.y * s.y);
+    const double2 s = b.S1[(size_t)r * g.K + k];
+    v[1] += b.w[(size_t)r * g.K + k] * (s.x * s.x + s.y * s.y);
   }
   block_sum<256, 2>(v, sh);
   if (threadIdx.x == 0) {
     const double c = 0.5 * v[0] + 0.5 * v[1] - g.ke * g.alpha * INV_SQRT_PI * scal[4 * r + 3] +
                      g.ke * (2.0 * M_PI / g.V) * scal[4 * r + 2] * scal[4 * r + 2];
-    const double E = 0.5 * dpsi[r] * rsum_total(rsum, r, 1) - 0.5 * rsum_total(rsum, r, 2) + c;
-    if (!fixedQ && !isfinite(E)) atomicOr(status, ST_NUMERIC);
-    energy[r] = fixedQ ? (double)NAN : E;
+    const double E = 0.5 * b.dpsi[r] * rsum_total(rsum, r, 1) - 0.5 * rsum_total(rsum, r, 2) + c;
+    if (!fixedQ && !isfinite(E)) atomicOr(b.status, ST_NUMERIC);
+    b.energy_out[r] = fixedQ ? (double)NAN : E;
   }
 }
 
-void launch_energy(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s) {
-  if (!b.energy_out && !b.step_adv) return;
-  hipLaunchKernelGGL(k_energy, dim3(b.energy_out ? b.R : 1), dim3(256), 0, s, g, b.off, b.ion_q, b.phi, b.S1, b.w,
-                     b.scal, b.rsum, b.dpsi, b.energy_out, fixedQ, b.status, b.step_adv);
+// The step's last launch, after every pass: blocks [0, ne) assemble E* per replica,
+// blocks [ne, ne + nf) add the real-space sums to the forces,
+//   F_i += ke q_i (Fii_i + Fie_i)   (Fie only for ions of reach cells),
+// and block 0 advances a replayed graph's step counter.
+__global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int fixedQ) {
+  if (b.step_adv && blockIdx.x == 0 && threadIdx.x == 0) *b.step_adv += 1;
+  if ((int)blockIdx.x < ne) {
+    energy_block(g, blockIdx.x, b, fixedQ);
+    return;
+  }
+  const int64_t N = b.N;
+  const int64_t i = (int64_t)(blockIdx.x - ne) * 256 + threadIdx.x;
+  if (i >= N) return;
+  const double kq = g.ke * b.ion_q[i];
+  double rx = b.Fii[i], ry = b.Fii[N + i], rz = b.Fii[2 * N + i];
+  if (b.reach_cell[b.keys[i] >> 13]) {
+    rx += b.Fie[i];
+    ry += b.Fie[N + i];
+    rz += b.Fie[2 * N + i];
+  }
+  double* F = b.F_out;
+  F[i] += kq * rx;
+  F[N + i] += kq * ry;
+  F[2 * N + i] += kq * rz;
+}
+
+void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s) {
+  const int ne = b.energy_out ? b.R : 0;
+  const int nf = cdiv64(b.N, 256);
+  if (ne + nf == 0) return;
+  hipLaunchKernelGGL(k_final, dim3(ne + nf), dim3(256), 0, s, g, b, ne, fixedQ);
 }
 
 }  // namespace srbe
