@@ -41,8 +41,8 @@ struct StepBufs {
   const int* ele_cstart;    // ncell + 1
   const double2* ele_czr;   // ncell: z-extent of the electrodes of each cell
   const int2* ion_runs;     // ncell x kRunMax neighbour runs [c0, c1), merged across z; c0 = -1 ends
-  const int2* ele_runs;     // ncell x kRunMax neighbour runs split by z-layer (electrode side)
-  const double2* ele_run_zr;  // ncell x kRunMax z-extent of the electrodes of each ele_runs entry
+  const int4* ele_rr;       // ncell x kRunMax electrode runs (one z-layer each): sorted range [x, y),
+                            // z-extent as float bits (z, w); x = -1 ends a cell's list
   const int2* reach;        // cell ranges [c0, c1) whose ions can be within rc of an electrode
   int nreach;
   const unsigned char* reach_cell;  // ncell flags: 1 for the cells of those ranges
@@ -103,10 +103,14 @@ void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hi
 void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, hipStream_t s);
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 int cp_gemm_ksplit(int n_ele, int R);
-void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
+// GEMM tiles (none if Sext is null) with nii blocks of the ion-ion pass from block ii0
+// on (of real_ii_tiles(b) x R) in the same launch.
+void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, int fp32, int ii0, int nii, hipStream_t s);
+int real_ii_tiles(const StepBufs& b);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
-void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
-void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
+void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, int ie_part, int ie_nparts,
+                      hipStream_t s);
+void launch_stage_force(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 

@@ -32,8 +32,8 @@ struct srbe_system {
   int* ele_cstart = nullptr;   // ncell + 1
   double2* ele_czr = nullptr;  // ncell: z-extent of each cell's electrodes
   int2* ion_runs = nullptr;    // ncell x kRunMax neighbour runs, merged across z-layers
-  int2* ele_runs = nullptr;    // ncell x kRunMax neighbour runs, one z-layer each
-  double2* ele_run_zr = nullptr;  // ncell x kRunMax electrode z-extent of each ele_runs entry
+  int4* ele_rr = nullptr;      // ncell x kRunMax electrode neighbour runs (one z-layer each) as sorted
+                               // ranges [x, y) with their z-extent (z, w: float bits); x = -1 ends
   uint4* ele_sfx = nullptr;    // sorted fixed point
   double4* ele_sd4 = nullptr;  // sorted fractional coordinates
   double* Sext = nullptr;      // (n+1) x ldcp(n) row-major: J A^-1 and the psibar row
@@ -431,8 +431,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.ele_cstart = h->ele_cstart;
   b.ele_czr = h->ele_czr;
   b.ion_runs = h->ion_runs;
-  b.ele_runs = h->ele_runs;
-  b.ele_run_zr = h->ele_run_zr;
+  b.ele_rr = h->ele_rr;
   b.reach = h->reach;
   b.nreach = h->nreach;
   b.reach_cell = h->reach_cell;
@@ -513,15 +512,15 @@ enum {
 //           ion_force (k-space) -> (aux) final: F += real-space sums; energy
 //   aux[1]: (cell sort) real_ii -> (post_charges) real_ie
 // [a | b] is one launch whose blocks run both parts.  Independent work shares a launch
-// rather than a second stream where it can: a cross-stream wait costs several
-// microseconds in a replayed graph, while kernels on one stream follow each other
-// without a gap.  The two real-space force passes are long enough to pay for the side
-// stream's three waits: the ion-ion pass runs beside the whole k-space chain and the
-// charge solve, the ion-electrode pass (which needs the new charges) beside the
-// electrode structure factors and the k-space force.  The critical stream's launch
-// after each fork is enqueued first, so that it is dispatched first.  With phase
-// timing on, the fused launches run part by part (same device code) so that each part
-// can be timed.
+// rather than a second stream where it can: a cross-stream dependency costs several
+// microseconds in a replayed graph (a fork ~5, a join ~9), while kernels on one stream
+// follow each other without a gap.  The two real-space force passes are long enough
+// to pay for the side stream's waits: the ion-ion pass runs beside the whole k-space
+// chain and the charge solve, the ion-electrode pass (which needs the new charges)
+// beside the electrode structure factors and the k-space force.  The critical
+// stream's launch after each fork is enqueued first, so that it is dispatched first.
+// With phase timing on, the fused launches run part by part (same device code) so
+// that each part can be timed.
 int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStream_t s) {
   const Geom& g = h->g;
   hipStream_t s1 = h->aux[1];
@@ -552,17 +551,17 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   else
     launch_sf_finalize(g, b, fp32, 1, s);
   part(PH_ELE_POTENTIAL, s, [&] { launch_ele_potential(g, b, fp32, s); });
-  if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, s); });
+  if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, fp32, 0, 0, s); });
   part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
   HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
   part(PH_SF_ELE, s, [&] {
-    launch_stage_ele(g, b, fp32, STAGE_SF, s);
+    launch_stage_ele(g, b, fp32, STAGE_SF, 0, 1, s);
     launch_sf_finalize(g, b, fp32, 2, s);
   });
   HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_POST], 0));
-  part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s1); });
+  part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, 0, 1, s1); });
   HIP_OK(h, hipEventRecord(h->ev[EV_AUX], s1));
-  part(PH_ION_FORCE, s, [&] { launch_ion_force(g, b, fp32, s); });
+  part(PH_ION_FORCE, s, [&] { launch_stage_force(g, b, fp32, STAGE_SF, s); });
   HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
   part(PH_ENERGY, s, [&] { launch_final(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());
@@ -607,7 +606,7 @@ void srbe_destroy(srbe_system* h) {
     if (st) (void)hipStreamDestroy(st);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   void* bufs[] = {h->bin_keys, h->reach, h->reach_cell, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
-                  h->ele_czr, h->ion_runs, h->ele_runs, h->ele_run_zr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
+                  h->ele_czr, h->ion_runs, h->ele_rr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -660,8 +659,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ele_cstart, (size_t)(g.ncell + 1) * sizeof(int));
     al((void**)&h->ele_czr, (size_t)g.ncell * sizeof(double2));
     al((void**)&h->ion_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
-    al((void**)&h->ele_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
-    al((void**)&h->ele_run_zr, (size_t)g.ncell * kRunMax * sizeof(double2));
+    al((void**)&h->ele_rr, (size_t)g.ncell * kRunMax * sizeof(int4));
     al((void**)&h->ele_sfx, (n + kScanPad) * sizeof(uint4));
     al((void**)&h->ele_sd4, (n + kScanPad) * sizeof(double4));
     al((void**)&h->status, sizeof(unsigned));
@@ -710,7 +708,6 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
         hipMemcpy(h->ele_d, d.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(off2, h_off, sizeof(h_off), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->ion_runs, iruns.data(), iruns.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->ele_runs, eruns.data(), eruns.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h->status, 0, sizeof(unsigned)) != hipSuccess) {
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
@@ -748,13 +745,22 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
         rzr[(size_t)c * kRunMax + u] = make_double2(INFINITY, -INFINITY);
       }
     }
-    if (hipMemcpy(h->ele_runs, eruns.data(), eruns.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->ele_run_zr, rzr.data(), rzr.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
-      return fail(SRBE_EHIP);
     // electrode chunks for the electrode-side real-space pass, and the reach ranges:
     // cells with an electrode run within rc (plus a rounding margin) of their z-slab
     std::vector<int> ecs(g.ncell + 1);
     if (hipMemcpy(ecs.data(), h->ele_cstart, ecs.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(SRBE_EHIP);
+    // the runs as sorted-electrode ranges with their z-extent (float bits), for the
+    // ion-electrode pass: one 16-byte entry per (cell, run), b = -1 ends a list
+    std::vector<int4> err(eruns.size(), make_int4(-1, -1, 0, 0));
+    for (size_t u = 0; u < eruns.size(); ++u)
+      if (eruns[u].x >= 0) {
+        float lo = (float)rzr[u].x, hi = (float)rzr[u].y;
+        err[u] = make_int4(ecs[eruns[u].x], ecs[eruns[u].y], 0, 0);
+        memcpy(&err[u].z, &lo, 4);
+        memcpy(&err[u].w, &hi, 4);
+      }
+    if (hipMemcpy(h->ele_rr, err.data(), err.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
       return fail(SRBE_EHIP);
     std::vector<int4> chunks;
     for (int c = 0; c < g.ncell; ++c)

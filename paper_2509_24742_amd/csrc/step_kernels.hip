@@ -714,6 +714,13 @@ __device__ __forceinline__ unsigned lanes_below(uint64_t m) {
 constexpr int kRing = 128;
 constexpr int kRingAlloc = kRing + 64;  // ring + one discard slot per lane
 constexpr int kSegMax = 4;
+
+// LDS of a block's four scanning waves: a ring of kRingAlloc entries each.
+template <bool FP32>
+constexpr int ring_bytes() {
+  return 4 * kRingAlloc * (FP32 ? (int)sizeof(float4) : (int)sizeof(double4));
+}
+
 static_assert(kRunMax < 64, "one lane per run, and a terminator lane");
 
 // Lane s turns run s of a -1-terminated run list into a record range [rb, re) with
@@ -1094,11 +1101,17 @@ void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kGemmLd = 18;  // LDS row stride of an operand tile (doubles)
 
-__global__ __launch_bounds__(256) void k_cp_gemm(int n, int R, const double* __restrict__ S,
-                                                 const double* __restrict__ V, double* __restrict__ Qpart) {
-  __shared__ double lds[2][2][64 * kGemmLd];  // [buffer][A or B][64 rows x 16 k, padded]
+int real_ii_tiles(const StepBufs& b);
+template <bool FP32>
+__device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb, int bx, int r, void* lds);
+constexpr int kGemmLdsBytes = 2 * 2 * 64 * kGemmLd * (int)sizeof(double);
+
+// Tile (rt, cg) of k-range h of ks.  lds_raw: kGemmLdsBytes bytes,
+// [buffer][A or B][64 rows x 16 k, padded].
+__device__ __forceinline__ void cp_gemm_tile(int n, int R, const double* __restrict__ S, const double* __restrict__ V,
+                                             double* __restrict__ Qpart, int rt, int cg, int h, int ks, void* lds_raw) {
+  double(*lds)[2][64 * kGemmLd] = reinterpret_cast<double(*)[2][64 * kGemmLd]>(lds_raw);
   const int ld = ldcp(n);
-  const int rt = blockIdx.x, cg = blockIdx.y, h = blockIdx.z, ks = gridDim.z;
   const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
   const int nb = ld / 16;
   const int kb0 = (int)((int64_t)nb * h / ks), kb1 = (int)((int64_t)nb * (h + 1) / ks);
@@ -1165,6 +1178,23 @@ __global__ __launch_bounds__(256) void k_cp_gemm(int n, int R, const double* __r
     }
 }
 
+// The GEMM's tiles, blocks [0, ntile) of the launch (rt fastest, then cg, then the
+// k-range), then nii blocks of the ion-ion real-space pass from block ii0 on (they
+// use the VALU the matrix cores leave idle; the tile LDS doubles as their rings).
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_cp_gemm(Geom g, StepBufs b, const double* __restrict__ S, int nrt, int ncg,
+                                                 int ntile, int ii0, int iitiles) {
+  __shared__ __align__(16) unsigned char lds[kGemmLdsBytes > ring_bytes<FP32>() ? kGemmLdsBytes
+                                                                                 : ring_bytes<FP32>()];
+  const int bid = blockIdx.x;
+  if (bid < ntile) {
+    cp_gemm_tile(g.n_ele, b.R, S, b.V, b.Qext, bid % nrt, (bid / nrt) % ncg, bid / (nrt * ncg), b.ksplit, lds);
+  } else {
+    const int u = ii0 + bid - ntile;
+    real_ii_block<FP32>(g, b, u % iitiles, u / iitiles, lds);
+  }
+}
+
 // k-ranges: as many as keep the grid within one block per CU of a 256-CU device
 // (at most 16, at least 1).
 int cp_gemm_ksplit(int n_ele, int R) {
@@ -1172,10 +1202,15 @@ int cp_gemm_ksplit(int n_ele, int R) {
   return std::max(1, std::min(16, 256 / std::max(tiles, 1)));
 }
 
-void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s) {
+void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, int fp32, int ii0, int nii, hipStream_t s) {
   const int n = g.n_ele;
-  hipLaunchKernelGGL(k_cp_gemm, dim3((n + 1 + 63) / 64, (b.R + 63) / 64, b.ksplit), dim3(256), 0, s, n, b.R, Sext,
-                     b.V, b.Qext);
+  const int nrt = (n + 1 + 63) / 64, ncg = (b.R + 63) / 64, ntile = Sext ? nrt * ncg * b.ksplit : 0;
+  if (ntile + nii == 0) return;
+  const int it = real_ii_tiles(b);
+  if (fp32)
+    hipLaunchKernelGGL(k_cp_gemm<true>, dim3(ntile + nii), dim3(256), 0, s, g, b, Sext, nrt, ncg, ntile, ii0, it);
+  else
+    hipLaunchKernelGGL(k_cp_gemm<false>, dim3(ntile + nii), dim3(256), 0, s, g, b, Sext, nrt, ncg, ntile, ii0, it);
 }
 
 // ============================================================ after the charge solve
@@ -1267,16 +1302,20 @@ __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __restrict__ off,
-                                                    const double4* __restrict__ ion_d4, int64_t N,
-                                                    const int4* __restrict__ modes, const double2* __restrict__ coef,
-                                                    const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    double* __restrict__ F) {
+// Block (bx, r): ions 64 bx .. 64 bx + 63 of replica r.
+__device__ __forceinline__ void ionforce64_block(const Geom& g, const StepBufs& b, int bx, int r) {
+  const int64_t* __restrict__ off = b.off;
+  const double4* __restrict__ ion_d4 = b.ion_d4;
+  const int64_t N = b.N;
+  const int4* __restrict__ modes = b.modes;
+  const double2* __restrict__ coef = b.coef;
+  const double* __restrict__ scal = b.scal;
+  const double* __restrict__ rsum = b.rsum;
+  double* __restrict__ F = b.F_out;
   __shared__ double sh[4][3][64];
-  const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
-  const int64_t i = b0 + (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  if (b0 + (int64_t)blockIdx.x * 64 >= b1) return;  // whole block past this replica's ions
+  const int64_t i = b0 + (int64_t)bx * 64 + (threadIdx.x & 63);
+  if (b0 + (int64_t)bx * 64 >= b1) return;  // whole block past this replica's ions
   const bool live = i < b1;
   const double4 p = live ? ion_d4[i] : make_double4(0, 0, 0, 0);
   int lo, hi;
@@ -1299,16 +1338,18 @@ __global__ __launch_bounds__(256) void k_ionforce64(Geom g, const int64_t* __res
   ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, N, F);
 }
 
-__global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __restrict__ off,
-                                                    const uint4* __restrict__ ion_fx, int64_t N,
-                                                    const ModeRec32* __restrict__ rec,
-                                                    const double* __restrict__ scal, const double* __restrict__ rsum,
-                                                    double* __restrict__ F) {
+__device__ __forceinline__ void ionforce32_block(const Geom& g, const StepBufs& b, int bx, int r) {
+  const int64_t* __restrict__ off = b.off;
+  const uint4* __restrict__ ion_fx = b.ion_fx;
+  const int64_t N = b.N;
+  const ModeRec32* __restrict__ rec = b.rec;
+  const double* __restrict__ scal = b.scal;
+  const double* __restrict__ rsum = b.rsum;
+  double* __restrict__ F = b.F_out;
   __shared__ double sh[4][3][64];
-  const int r = blockIdx.y;
   const int64_t b0 = off[r], b1 = off[r + 1];
-  const int64_t i = b0 + (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  if (b0 + (int64_t)blockIdx.x * 64 >= b1) return;  // whole block past this replica's ions
+  const int64_t i = b0 + (int64_t)bx * 64 + (threadIdx.x & 63);
+  if (b0 + (int64_t)bx * 64 >= b1) return;  // whole block past this replica's ions
   const bool live = i < b1;
   const uint4 pi_ = live ? ion_fx[i] : make_uint4(0, 0, 0, 0);
   int lo, hi;
@@ -1359,16 +1400,6 @@ __global__ __launch_bounds__(256) void k_ionforce32(Geom g, const int64_t* __res
   ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, N, F);
 }
 
-void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (b.max_nrep == 0) return;
-  dim3 grid(cdiv64(b.max_nrep, 64), b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_ionforce32, grid, dim3(256), 0, s, g, b.off, b.ion_fx, b.N, b.rec, b.scal, b.rsum,
-                       b.F_out);
-  else
-    hipLaunchKernelGGL(k_ionforce64, grid, dim3(256), 0, s, g, b.off, b.ion_d4, b.N, b.modes, b.coef, b.scal, b.rsum,
-                       b.F_out);
-}
 
 // ============================================================ ion forces, real space
 // F_i += -ke q_i sum_j q_j K_ii'(r) r^ - ke q_i sum_e Q_e K_ig'(r) r^ over the
@@ -1418,26 +1449,31 @@ struct CarriedSums {
   }
 };
 
-constexpr int kIiIonsPerWave = 4;  // consecutive sorted ions per wave (ion-ion pass)
-constexpr int kIeIonsPerWave = 1;  // per wave visit of a reach range (ion-electrode pass: latency-bound, so the ions are spread over as many waves as possible)
+constexpr int kIiIonsPerWave = 8;  // consecutive sorted ions per wave (ion-ion pass)
 
+// Ion-ion pass, block (bx, r): waves 4 bx .. 4 bx + 3 of replica r, each taking
+// kIiIonsPerWave consecutive sorted ions.  lds: ring_bytes<FP32>() bytes.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restrict__ off, int64_t N,
-                                                 const int* __restrict__ cstart, const int* __restrict__ perm,
-                                                 const int* __restrict__ scell, const int2* __restrict__ ion_runs,
-                                                 const uint4* __restrict__ sfx, const double4* __restrict__ sd4,
-                                                 double* __restrict__ Fii, double* __restrict__ phi) {
+__device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb, int bx, int r, void* lds) {
+  const int64_t* __restrict__ off = bb.off;
+  const int64_t N = bb.N;
+  const int* __restrict__ cstart = bb.cstart;
+  const int* __restrict__ perm = bb.perm;
+  const int* __restrict__ scell = bb.scell;
+  const int2* __restrict__ ion_runs = bb.ion_runs;
+  const uint4* __restrict__ sfx = bb.sfx;
+  const double4* __restrict__ sd4 = bb.sd4;
+  double* __restrict__ Fii = bb.Fii;
+  double* __restrict__ phi = bb.phi;
   using Entry = typename std::conditional<FP32, float4, double4>::type;
   using T = typename std::conditional<FP32, float, double>::type;
-  __shared__ Entry ring_all[4][kRingAlloc];
-  const int r = blockIdx.y;
   const int b0 = (int)off[r], b1 = (int)off[r + 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int kbeg = b0 + (blockIdx.x * 4 + w) * kIiIonsPerWave;
+  const int kbeg = b0 + (bx * 4 + w) * kIiIonsPerWave;
   if (kbeg >= b1) return;  // whole wave
   const int kend = min(b1, kbeg + kIiIonsPerWave);
-  Entry* ring = ring_all[w];
+  Entry* ring = reinterpret_cast<Entry*>(lds) + w * kRingAlloc;
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   auto ion_range = [&](int, int2 rc, int& b, int& e) {
     b = b0 + cs[rc.x];
@@ -1532,21 +1568,41 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, const int64_t* __restri
   finish(kend - 1, acc.p);
 }
 
-void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  if (b.max_nrep == 0) return;
-  dim3 grid(cdiv64(b.max_nrep, 4 * kIiIonsPerWave), b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
-                       b.sfx, b.sd4, b.Fii, b.phi);
-  else
-    hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b.off, b.N, b.cstart, b.perm, b.scell, b.ion_runs,
-                       b.sfx, b.sd4, b.Fii, b.phi);
+// One replica's blocks all run on one XCD (blocks are dealt to the 8 XCDs in turn by
+// launch index), so the replica's records are fetched into one L2 only:
+// launch block L goes to XCD L mod 8 and takes block bx of replica r = L mod 8 + 8 m.
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) {
+  __shared__ __align__(16) unsigned char lds[ring_bytes<FP32>()];
+  const int L = blockIdx.x, j = L >> 3, m = j / tiles;
+  const int r = (L & 7) + 8 * m;
+  if (r >= b.R) return;
+  real_ii_block<FP32>(g, b, j - m * tiles, r, lds);
 }
 
-// Block bx of the nbx blocks that one replica's reach ranges are split over; each
-// wave takes kIeIonsPerWave consecutive ions of a range at a time.
+int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * kIiIonsPerWave); }
+
+void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (b.max_nrep == 0) return;
+  const int tiles = real_ii_tiles(b);
+  const dim3 grid(8 * ((b.R + 7) / 8) * tiles);
+  if (fp32)
+    hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b, tiles);
+  else
+    hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b, tiles);
+}
+
+// Block bx of the nbx blocks that one replica's reach ranges are split over, for part
+// `part` of `nparts` (the parts take the wave's visits in turn, so that the pass can
+// be spread over several launches); each visit takes one ion.  The pass is
+// latency-bound, so each wave loads the next ion's cell and record while it scans the
+// current one, and an ion's electrode runs come from a set-up table of sorted ranges
+// with their z-extent (one 16-byte load per run, all runs at once).  A run whose
+// z-extent lies farther than rc from the ion cannot hold a partner and is skipped
+// (the extent is stored in FP32; the margin below covers its rounding).
 template <bool FP32>
-__device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r) {
+__device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r, int part,
+                                              int nparts) {
   const int64_t* __restrict__ off = bb.off;
   const int64_t N = bb.N;
   const int* __restrict__ cstart = bb.cstart;
@@ -1554,11 +1610,9 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   const int nreach = bb.nreach;
   const int* __restrict__ perm = bb.perm;
   const int* __restrict__ scell = bb.scell;
-  const int2* __restrict__ ele_runs = bb.ele_runs;
-  const double2* __restrict__ ele_run_zr = bb.ele_run_zr;
+  const int4* __restrict__ ele_rr = bb.ele_rr;
   const uint4* __restrict__ sfx = bb.sfx;
   const double4* __restrict__ sd4 = bb.sd4;
-  const int* __restrict__ ele_cstart = bb.ele_cstart;
   const uint4* __restrict__ ele_sfx = bb.ele_sfx;
   const double4* __restrict__ ele_sd4 = bb.ele_sd4;
   const float* __restrict__ Qsf = bb.Qsf;
@@ -1566,15 +1620,16 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   double* __restrict__ Fie = bb.Fie;
   using Entry = typename std::conditional<FP32, float4, double4>::type;
   using T = typename std::conditional<FP32, float, double>::type;
+  using Rec = typename std::conditional<FP32, uint4, double4>::type;
   __shared__ Entry ring_all[4][kRingAlloc];
   const int b0 = (int)off[r];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int gw = bx * 4 + w, stride = nbx * 4;
+  const int gw = bx * 4 + w, stride = nbx * 4 * nparts, first = gw * nparts + part;
   Entry* ring = ring_all[w];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   const int n = g.n_ele;
-  const double zlim = g.rc + 1e-6;  // skip test margin (fixed-point z is exact to ~1e-8 of the box)
+  const double zlim = g.rc + 1e-5;  // skip margin: FP32 z-extents (~1e-6 nm) and fixed-point z (~1e-8 of the box)
   const float a1 = (float)g.alpha, a2 = (float)(1.0 / g.eta);
   unsigned head = 0, tail = 0;
   CarriedSums<T, 3> acc;
@@ -1608,96 +1663,108 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
       Fie[2 * N + i] = fz;
     }
   };
+  // the wave's ions: positions first, first + stride, ... of each reach range in turn
+  int qr = -1, k = 0, kstop = 0;
+  auto advance = [&]() {
+    k += stride;
+    while (k >= kstop) {
+      if (++qr >= nreach) return false;
+      const int2 cr = reach[qr];
+      k = b0 + cs[cr.x] + first;
+      kstop = b0 + cs[cr.y];
+    }
+    return true;
+  };
+  k = -stride;  // so that the first advance lands on the first ion
+  bool have = advance();
+  int home = 0;
+  Rec pi_{};
+  if (have) {
+    home = __builtin_amdgcn_readfirstlane(scell[k]);
+    if constexpr (FP32) pi_ = sfx[k]; else pi_ = sd4[k];
+  }
   int kprev = -1;
-  for (int qr = 0; qr < nreach; ++qr) {
-    const int2 cr = reach[qr];
-    const int kstop = b0 + cs[cr.y];
-    for (int kc = b0 + cs[cr.x] + gw * kIeIonsPerWave; kc < kstop; kc += stride * kIeIonsPerWave) {
-      const int kce = min(kstop, kc + kIeIonsPerWave);
-      for (int k = kc; k < kce; ++k) {
-        const int home = __builtin_amdgcn_readfirstlane(scell[k]);
-        const int2* eruns = ele_runs + kRunMax * home;
-        const double2* erz = ele_run_zr + kRunMax * home;
-        int rb, re;
-        if constexpr (FP32) {
-          const uint4 pi_ = sfx[k];
-          const double zi = (double)pi_.z * (g.Lz * 0x1.0p-32);
-          resolve_runs(eruns,
-                       [&](int si, int2 rc, int& bb_, int& e) {
-                         const double2 zr = erz[si];
-                         bb_ = ele_cstart[rc.x];
-                         e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb_ : ele_cstart[rc.y];
-                       },
-                       rb, re);
-          const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32),
-                      lz = (float)(g.Lz * 0x1.0p-32), rc2 = (float)(g.rc * g.rc);
-          const float* Qr = Qsf + (size_t)r * n;
-          wave_scan(rb, re, ring, head, tail,
-                    [&](int j) {
-                      uint4 p = ele_sfx[j];
-                      p.w = __float_as_uint(Qr[j]);
-                      return p;
-                    },
-                    [&](int j0) {
-                      uint4 p = (ele_sfx + j0)[lane];
-                      p.w = __float_as_uint((Qr + j0)[lane]);
-                      return p;
-                    },
-                    [&](const uint4& p, int, float4& ent) {
-                      ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
-                      ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
-                      ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
-                      ent.w = __uint_as_float(p.w);
-                      return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
-                    },
-                    eval_block);
-        } else {
-          const double4 pi_ = sd4[k];
-          const double zi = pi_.z * g.Lz;
-          resolve_runs(eruns,
-                       [&](int si, int2 rc, int& bb_, int& e) {
-                         const double2 zr = erz[si];
-                         bb_ = ele_cstart[rc.x];
-                         e = (zr.x - zi >= zlim || zi - zr.y >= zlim) ? bb_ : ele_cstart[rc.y];
-                       },
-                       rb, re);
-          const double rc2 = g.rc * g.rc;
-          const double* Qr = Qsd + (size_t)r * n;
-          wave_scan(rb, re, ring, head, tail,
-                    [&](int j) {
-                      double4 p = ele_sd4[j];
-                      p.w = Qr[j];
-                      return p;
-                    },
-                    [&](int j0) {
-                      double4 p = (ele_sd4 + j0)[lane];
-                      p.w = (Qr + j0)[lane];
-                      return p;
-                    },
-                    [&](const double4& p, int, double4& ent) {
-                      double sx = pi_.x - p.x, sy = pi_.y - p.y;
-                      sx -= rint(sx);
-                      sy -= rint(sy);
-                      ent.x = sx * g.Lx;
-                      ent.y = sy * g.Ly;
-                      ent.z = (pi_.z - p.z) * g.Lz;
-                      ent.w = p.w;
-                      return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
-                    },
-                    eval_block);
-        }
-        if (kprev >= 0) {  // the previous ion is complete once its last entries are evaluated
-          if (head < acc.bound) {
-            __builtin_amdgcn_wave_barrier();
-            eval_block(head, tail);
-            head = tail;
-          }
-          finish(kprev, acc.p);
-        }
-        acc.rotate(tail);
-        kprev = k;
+  while (have) {
+    const int kc = k;
+    const int hc = home;
+    const Rec pc = pi_;
+    have = advance();
+    if (have) {  // the next ion's cell and record travel while this one is scanned
+      home = __builtin_amdgcn_readfirstlane(scell[k]);
+      if constexpr (FP32) pi_ = sfx[k]; else pi_ = sd4[k];
+    }
+    int rb = 0, re = 0;
+    {
+      const int4 t = lane < kRunMax ? ele_rr[kRunMax * hc + lane] : make_int4(-1, -1, 0, 0);
+      const uint64_t term = __ballot(t.x < 0);  // non-zero: the lanes >= kRunMax count as terminators
+      const uint64_t listed = (1ull << __builtin_ctzll(term)) - 1;
+      double zi;
+      if constexpr (FP32) zi = (double)pc.z * (g.Lz * 0x1.0p-32); else zi = pc.z * g.Lz;
+      if ((listed >> lane) & 1) {
+        const double zlo = (double)__int_as_float(t.z), zhi = (double)__int_as_float(t.w);
+        rb = t.x;
+        re = (zlo - zi >= zlim || zi - zhi >= zlim) ? t.x : t.y;
       }
     }
+    if constexpr (FP32) {
+      const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32),
+                  rc2 = (float)(g.rc * g.rc);
+      const float* Qr = Qsf + (size_t)r * n;
+      wave_scan(rb, re, ring, head, tail,
+                [&](int j) {
+                  uint4 p = ele_sfx[j];
+                  p.w = __float_as_uint(Qr[j]);
+                  return p;
+                },
+                [&](int j0) {
+                  uint4 p = (ele_sfx + j0)[lane];
+                  p.w = __float_as_uint((Qr + j0)[lane]);
+                  return p;
+                },
+                [&](const uint4& p, int, float4& ent) {
+                  ent.x = (float)(int32_t)(pc.x - p.x) * lx;
+                  ent.y = (float)(int32_t)(pc.y - p.y) * ly;
+                  ent.z = (float)(int32_t)(pc.z - p.z) * lz;
+                  ent.w = __uint_as_float(p.w);
+                  return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+                },
+                eval_block);
+    } else {
+      const double rc2 = g.rc * g.rc;
+      const double* Qr = Qsd + (size_t)r * n;
+      wave_scan(rb, re, ring, head, tail,
+                [&](int j) {
+                  double4 p = ele_sd4[j];
+                  p.w = Qr[j];
+                  return p;
+                },
+                [&](int j0) {
+                  double4 p = (ele_sd4 + j0)[lane];
+                  p.w = (Qr + j0)[lane];
+                  return p;
+                },
+                [&](const double4& p, int, double4& ent) {
+                  double sx = pc.x - p.x, sy = pc.y - p.y;
+                  sx -= rint(sx);
+                  sy -= rint(sy);
+                  ent.x = sx * g.Lx;
+                  ent.y = sy * g.Ly;
+                  ent.z = (pc.z - p.z) * g.Lz;
+                  ent.w = p.w;
+                  return ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2;
+                },
+                eval_block);
+    }
+    if (kprev >= 0) {  // the previous ion is complete once its last entries are evaluated
+      if (head < acc.bound) {
+        __builtin_amdgcn_wave_barrier();
+        eval_block(head, tail);
+        head = tail;
+      }
+      finish(kprev, acc.p);
+    }
+    acc.rotate(tail);
+    kprev = kc;
   }
   if (kprev >= 0) {
     __builtin_amdgcn_wave_barrier();
@@ -1706,29 +1773,64 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   }
 }
 
-// k-space stage 2 beside the ion-electrode real-space pass (both follow the charge
-// solve): blocks [0, nie) are the real-space blocks, kIeBlocks per replica walking
-// its reach ranges (dispatched first, being latency-bound), blocks [nie, nie + nsf)
-// structure-factor partial blocks (electrodes with the new charges).
+// The ion-electrode real-space pass needs the new charges and is latency-bound; it is
+// split in two parts that share launches with the rest of the step's tail:
+//   k_stage_ele:   [real_ie part 0 | electrode structure-factor partial blocks]
+//   k_stage_force: [real_ie part 1 | k-space ion force blocks]
+// The real-space blocks (kIeBlocks per replica walking its reach ranges) come first in
+// each grid: being latency-bound they start their chains at once, and the
+// arithmetic-bound blocks fill the issue slots they leave.
 constexpr int kIeBlocks = 64;
 
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie) {
+__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie, int part, int nparts) {
   const int bid = blockIdx.x;
   if (bid < nie)
-    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks);
+    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks, part, nparts);
   else
     sf_block<FP32, false>(g, b, bid - nie);
 }
 
-void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_stage_force(Geom g, StepBufs b, int nif, int nie, int ftiles) {
+  const int bid = blockIdx.x;
+  if (bid < nie) {
+    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks, 1, 2);
+  } else {
+    const int u = bid - nie;
+    if constexpr (FP32)
+      ionforce32_block(g, b, u % ftiles, u / ftiles);
+    else
+      ionforce64_block(g, b, u % ftiles, u / ftiles);
+  }
+}
+
+static int ie_blocks(const StepBufs& b, int parts) {
+  return (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? kIeBlocks * b.R : 0;
+}
+
+// ie_part of ie_nparts: the share of the ion-electrode pass this launch runs
+void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, int ie_part, int ie_nparts,
+                      hipStream_t s) {
   const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ele * b.R : 0;
-  const int nie = (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? kIeBlocks * b.R : 0;
+  const int nie = ie_blocks(b, parts);
   if (nsf + nie == 0) return;
   if (fp32)
-    hipLaunchKernelGGL(k_stage_ele<true>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
+    hipLaunchKernelGGL(k_stage_ele<true>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie, ie_part, ie_nparts);
   else
-    hipLaunchKernelGGL(k_stage_ele<false>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
+    hipLaunchKernelGGL(k_stage_ele<false>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie, ie_part, ie_nparts);
+}
+
+// parts: STAGE_REAL (real_ie part 1) and STAGE_SF standing for the k-space force blocks
+void launch_stage_force(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
+  const int ftiles = cdiv64(std::max(b.max_nrep, 1), 64);
+  const int nif = (parts & STAGE_SF && b.max_nrep > 0) ? ftiles * b.R : 0;
+  const int nie = ie_blocks(b, parts);
+  if (nif + nie == 0) return;
+  if (fp32)
+    hipLaunchKernelGGL(k_stage_force<true>, dim3(nif + nie), dim3(256), 0, s, g, b, nif, nie, ftiles);
+  else
+    hipLaunchKernelGGL(k_stage_force<false>, dim3(nif + nie), dim3(256), 0, s, g, b, nif, nie, ftiles);
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
