@@ -687,9 +687,35 @@ __device__ __forceinline__ double wave_total(double v) {
   return ((r0 + r1) + r2) + r3;
 }
 
-// Lanes below this one with their bit set in m.
-__device__ __forceinline__ unsigned lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+// base + the number of lanes below this one with their bit set in m.
+__device__ __forceinline__ unsigned lanes_below(uint64_t m, unsigned base = 0u) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, base));
+}
+
+// The wave totals of four per-lane values, added in a fixed order.  Pairs of lanes
+// exchange two values each (even lanes keep the sums of v0 and v2, odd lanes of v1 and
+// v3), then pairs of pairs (lane l keeps value l mod 4); two rotations by 4 and 8 lanes
+// inside each 16-lane row add the row's four lanes of each value; the four rows'
+// totals pass through a 16-float wave-private LDS scratch, and lane m < 4 adds them in
+// row order.  Every lane returns the same four totals.
+__device__ __forceinline__ void wave_total4(float v0, float v1, float v2, float v3, float* scratch, float& t0,
+                                            float& t1, float& t2, float& t3) {
+  const int lane = threadIdx.x & 63;
+  const bool odd = lane & 1, b1 = (lane & 2) != 0;
+  const float x = (odd ? v1 : v0) + dpp_f<0xB1>(odd ? v0 : v1);
+  const float y = (odd ? v3 : v2) + dpp_f<0xB1>(odd ? v2 : v3);
+  float z = (b1 ? y : x) + dpp_f<0x4E>(b1 ? x : y);
+  z += dpp_f<0x124>(z);  // row_ror:4
+  z += dpp_f<0x128>(z);  // row_ror:8
+  if ((lane & 15) < 4) scratch[(lane >> 4) * 4 + (lane & 15)] = z;
+  __builtin_amdgcn_wave_barrier();
+  float t = 0.f;
+  if (lane < 4) t = ((scratch[lane] + scratch[4 + lane]) + scratch[8 + lane]) + scratch[12 + lane];
+  __builtin_amdgcn_wave_barrier();
+  t0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 0));
+  t1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 1));
+  t2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 2));
+  t3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 3));
 }
 
 // Neighbour scan of ONE particle by a whole wave.  The candidates are the records of
@@ -702,8 +728,7 @@ __device__ __forceinline__ unsigned lanes_below(uint64_t m) {
 // pair entry and says whether the pair is within range (evaluated branch-free:
 // every lane of a round holds a valid j).  The hits of a round are appended in
 // candidate order to a wave-private LDS ring (positions from a ballot and a lane
-// prefix count; lanes without a hit write to their own slot past the ring, so the
-// store needs no branch).  head and tail count the entries evaluated and queued;
+// prefix count).  head and tail count the entries evaluated and queued;
 // whenever 64 entries are queued, eval_block(head, head + 64) evaluates them, one per
 // lane.  Entries left queued at the end stay in the ring: the caller evaluates them
 // later, possibly together with the next particle's (so a wave that scans several
@@ -712,7 +737,7 @@ __device__ __forceinline__ unsigned lanes_below(uint64_t m) {
 // is wave-uniform; the evaluation order of the entries is fixed, so the result does
 // not depend on timing.
 constexpr int kRing = 128;
-constexpr int kRingAlloc = kRing + 64;  // ring + one discard slot per lane
+constexpr int kRingAlloc = kRing + 16;  // ring + scratch for the wave's final reductions
 constexpr int kSegMax = 4;
 
 // LDS of a block's four scanning waves: a ring of kRingAlloc entries each.
@@ -756,8 +781,7 @@ __device__ __forceinline__ void wave_scan(int rb, int re, Entry* __restrict__ ri
     Entry ent;
     const bool hit = test(rec, j, ent) & valid;
     const uint64_t m = __ballot(hit);
-    const unsigned slot = hit ? ((tail + lanes_below(m)) & (kRing - 1)) : (unsigned)(kRing + lane);
-    ring[slot] = ent;
+    if (hit) ring[lanes_below(m, tail) & (kRing - 1)] = ent;
     tail += (unsigned)__popcll(m);
     if (tail - head >= 64) {
       __builtin_amdgcn_wave_barrier();
@@ -1502,8 +1526,14 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
     }
   };
   auto finish = [&](int k, const T (&a)[4]) {
-    const double fx = (double)wave_total(a[0]), fy = (double)wave_total(a[1]), fz = (double)wave_total(a[2]),
-                 ph = (double)wave_total(a[3]);
+    double fx, fy, fz, ph;
+    if constexpr (FP32) {
+      float t0, t1, t2, t3;
+      wave_total4(a[0], a[1], a[2], a[3], reinterpret_cast<float*>(ring + kRing), t0, t1, t2, t3);
+      fx = t0, fy = t1, fz = t2, ph = t3;
+    } else {
+      fx = wave_total(a[0]), fy = wave_total(a[1]), fz = wave_total(a[2]), ph = wave_total(a[3]);
+    }
     if (lane == 0) {
       const int i = perm[k];
       Fii[i] = fx;
@@ -1655,7 +1685,14 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
     }
   };
   auto finish = [&](int k, const T (&a)[3]) {
-    const double fx = (double)wave_total(a[0]), fy = (double)wave_total(a[1]), fz = (double)wave_total(a[2]);
+    double fx, fy, fz;
+    if constexpr (FP32) {
+      float t0, t1, t2, t3;
+      wave_total4(a[0], a[1], a[2], 0.f, reinterpret_cast<float*>(ring + kRing), t0, t1, t2, t3);
+      fx = t0, fy = t1, fz = t2;
+    } else {
+      fx = wave_total(a[0]), fy = wave_total(a[1]), fz = wave_total(a[2]);
+    }
     if (lane == 0) {
       const int i = perm[k];
       Fie[i] = fx;
