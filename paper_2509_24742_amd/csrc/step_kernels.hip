@@ -844,6 +844,12 @@ __device__ __forceinline__ void wave_scan(int rb, int re, Entry* __restrict__ ri
   }
 }
 
+// The electrode-potential pass can split each chunk's candidate records over esplit
+// waves (1, 2 or 4; a contiguous share of every neighbour run each), so that a small
+// batch, which would leave most of the chip idle, runs esplit times as many waves
+// over shorter chains; the shares' sums are added in wave order through LDS.
+int ele_split(int units) { return units >= 2048 ? 1 : units >= 1024 ? 2 : 4; }
+
 // Real-space potential of the ions at each electrode (real-space part of Eq. (19)):
 // bN_j = ke sum_i q_i [erfc(alpha r) - erfc(r/eta)]/r over ions with r < rc.  One
 // lane per electrode: a wave takes up to 64 cell-sorted electrodes of one cell (the
@@ -855,7 +861,8 @@ __device__ __forceinline__ void wave_scan(int rb, int re, Entry* __restrict__ ri
 // order.  In FP32 the erfc(r/eta) term is not evaluated beyond eta_skip, where it
 // is below 2^-30 of the kept term.
 template <bool FP32>
-__device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb, int chunk, int r) {
+__device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb, int chunk, int r, int q,
+                                              int esplit, bool live_wave, double* __restrict__ part_sums) {
   const int64_t* __restrict__ off = bb.off;
   const int* __restrict__ cstart = bb.cstart;
   const uint4* __restrict__ sfx = bb.sfx;
@@ -894,8 +901,9 @@ __device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb,
     for (int si = 0; si < kRunMax; ++si) {
       const int2 rc = runs[si];
       if (rc.x < 0) break;
-      const int je = b0 + cs[rc.y];
-      int j = b0 + cs[rc.x];
+      const int jb = b0 + cs[rc.x], jl = b0 + cs[rc.y] - jb;
+      const int je = jb + (jl * (q + 1)) / esplit;  // this wave's share of the run
+      int j = jb + (jl * q) / esplit;
       // groups of four records in two buffers: the next group is in flight while the
       // current one is used (loads past the run are clamped to its last record)
       if (j + 4 <= je) {
@@ -943,8 +951,9 @@ __device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb,
     for (int si = 0; si < kRunMax; ++si) {
       const int2 rc = runs[si];
       if (rc.x < 0) break;
-      const int je = b0 + cs[rc.y];
-      int j = b0 + cs[rc.x];
+      const int jb = b0 + cs[rc.x], jl = b0 + cs[rc.y] - jb;
+      const int je = jb + (jl * (q + 1)) / esplit;  // this wave's share of the run
+      int j = jb + (jl * q) / esplit;
       if (j + 2 <= je) {
         double4 cur[2], nxt[2];
         cur[0] = sd4[j];
@@ -965,20 +974,34 @@ __device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb,
     }
     sum = acc;
   }
-  if (live) bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * sum;
+  // the esplit waves' sums of each electrode, added in wave order
+  const int w = threadIdx.x >> 6;
+  part_sums[w * 64 + (threadIdx.x & 63)] = sum;
+  __syncthreads();
+  if (q == 0 && live && live_wave) {
+    double t = part_sums[w * 64 + (threadIdx.x & 63)];
+    for (int u = 1; u < esplit; ++u) t += part_sums[(w + u) * 64 + (threadIdx.x & 63)];
+    bN[(size_t)r * g.n_ele + ele_perm[e]] = g.ke * t;
+  }
 }
 
 // k-space stage 1 beside the electrode-side real-space pass (both follow the sort and
-// the sampler): blocks [0, nre) hold four real-space waves each (wave unit
+// the sampler): blocks [0, nre) are real-space blocks (4 / esplit electrode chunks
+// each, a chunk's esplit waves taking a share of its candidates each; chunk unit
 // u = r n_chunks + chunk), blocks [nre, nre + nsf) are structure-factor partial
 // blocks.  The real-space waves are latency-bound, so they are dispatched first and
 // the arithmetic-bound partial blocks fill the issue slots they leave.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf, int nre) {
+__global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf, int nre, int esplit) {
+  __shared__ double part_sums[4 * 64];
   const int bid = blockIdx.x;
   if (bid < nre) {
-    const int u = bid * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (u < b.n_ele_chunks * b.R) real_ele_wave<FP32>(g, b, u % b.n_ele_chunks, u / b.n_ele_chunks);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int units = b.n_ele_chunks * b.R;
+    const int u = bid * (4 / esplit) + w / esplit;  // chunk unit of this wave: u = r n_chunks + chunk
+    const bool live_wave = u < units;
+    const int uu = live_wave ? u : units - 1;       // a past-the-end wave repeats the last unit, unstored
+    real_ele_wave<FP32>(g, b, uu % b.n_ele_chunks, uu / b.n_ele_chunks, w % esplit, esplit, live_wave, part_sums);
   } else {
     sf_block<FP32, true>(g, b, bid - nre);
   }
@@ -986,12 +1009,13 @@ __global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf,
 
 void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
   const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ion * b.R : 0;
-  const int nre = (parts & STAGE_REAL && g.n_ele > 0) ? (b.n_ele_chunks * b.R + 3) / 4 : 0;
+  const int units = b.n_ele_chunks * b.R, esplit = ele_split(units);
+  const int nre = (parts & STAGE_REAL && g.n_ele > 0) ? (units * esplit + 3) / 4 : 0;
   if (nsf + nre == 0) return;
   if (fp32)
-    hipLaunchKernelGGL(k_stage_ions<true>, dim3(nsf + nre), dim3(256), 0, s, g, b, nsf, nre);
+    hipLaunchKernelGGL(k_stage_ions<true>, dim3(nsf + nre), dim3(256), 0, s, g, b, nsf, nre, esplit);
   else
-    hipLaunchKernelGGL(k_stage_ions<false>, dim3(nsf + nre), dim3(256), 0, s, g, b, nsf, nre);
+    hipLaunchKernelGGL(k_stage_ions<false>, dim3(nsf + nre), dim3(256), 0, s, g, b, nsf, nre, esplit);
 }
 
 // The force and potential passes: 64 particles per block, the mode list split
