@@ -69,7 +69,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[NT / 64]
 struct SortArgs {
   const int64_t* off;
   const double* xyz;  // SoA 3N
-  const double* q;    // N, or null (electrodes)
+  const double* q;    // N charges (ions; may be null when a replica batch has no ions); unused for electrodes
   int64_t N;
   unsigned* keys;
   uint4* fx;
@@ -85,6 +85,9 @@ struct SortArgs {
 
 template <int REC>
 __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs& a) {
+  // REC 1 or 2: ions (charges given, the replica's sums written, also for a replica
+  // without ions, whose charge pointer may be null); REC 3: the electrodes
+  constexpr bool kIons = REC != 3;
   __shared__ unsigned prov[kMaxBinParticles];
   __shared__ int cnt[kMaxCells + 1];
   __shared__ int scan[2][kMaxCells + 1];
@@ -99,7 +102,7 @@ __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs&
   for (int k = t; k < n; k += 1024) {
     const int64_t i = b0 + k;
     const double x = a.xyz[i], y = a.xyz[N + i], z = a.xyz[2 * N + i];
-    const double qi = a.q ? a.q[i] : 0.0;
+    const double qi = kIons ? a.q[i] : 0.0;
     if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) atomicOr(a.status, ST_RANGE);
     const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
     const unsigned key = ((unsigned)cell_index(g, sx, sy, z) << 13) | (unsigned)k;
@@ -112,7 +115,7 @@ __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs&
     v[2] += qi * z;
     v[3] += qi * qi;
   }
-  if (a.q) {
+  if (kIons) {
     block_sum<1024, 4>(v, red);
     if (t == 0) {
       a.scal[4 * r + 0] = v[0];
