@@ -103,14 +103,11 @@ void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hi
 void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, hipStream_t s);
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 int cp_gemm_ksplit(int n_ele, int R);
-// GEMM tiles (none if Sext is null) with nii blocks of the ion-ion pass from block ii0
-// on (of real_ii_tiles(b) x R) in the same launch.
-void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, int fp32, int ii0, int nii, hipStream_t s);
-int real_ii_tiles(const StepBufs& b);
+// nothing is launched if Sext is null (fixed charges)
+void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
-void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, int ie_part, int ie_nparts,
-                      hipStream_t s);
-void launch_stage_force(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
+void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
+void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 

@@ -551,17 +551,17 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   else
     launch_sf_finalize(g, b, fp32, 1, s);
   part(PH_ELE_POTENTIAL, s, [&] { launch_ele_potential(g, b, fp32, s); });
-  if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, fp32, 0, 0, s); });
+  if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, s); });
   part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
   HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
   part(PH_SF_ELE, s, [&] {
-    launch_stage_ele(g, b, fp32, STAGE_SF, 0, 1, s);
+    launch_stage_ele(g, b, fp32, STAGE_SF, s);
     launch_sf_finalize(g, b, fp32, 2, s);
   });
   HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_POST], 0));
-  part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, 0, 1, s1); });
+  part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s1); });
   HIP_OK(h, hipEventRecord(h->ev[EV_AUX], s1));
-  part(PH_ION_FORCE, s, [&] { launch_stage_force(g, b, fp32, STAGE_SF, s); });
+  part(PH_ION_FORCE, s, [&] { launch_ion_force(g, b, fp32, s); });
   HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
   part(PH_ENERGY, s, [&] { launch_final(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());

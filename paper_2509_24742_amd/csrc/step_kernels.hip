@@ -1152,9 +1152,6 @@ void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kGemmLd = 18;  // LDS row stride of an operand tile (doubles)
 
-int real_ii_tiles(const StepBufs& b);
-template <bool FP32>
-__device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb, int bx, int r, void* lds);
 constexpr int kGemmLdsBytes = 2 * 2 * 64 * kGemmLd * (int)sizeof(double);
 
 // Tile (rt, cg) of k-range h of ks.  lds_raw: kGemmLdsBytes bytes,
@@ -1229,21 +1226,11 @@ __device__ __forceinline__ void cp_gemm_tile(int n, int R, const double* __restr
     }
 }
 
-// The GEMM's tiles, blocks [0, ntile) of the launch (rt fastest, then cg, then the
-// k-range), then nii blocks of the ion-ion real-space pass from block ii0 on (they
-// use the VALU the matrix cores leave idle; the tile LDS doubles as their rings).
-template <bool FP32>
-__global__ __launch_bounds__(256) void k_cp_gemm(Geom g, StepBufs b, const double* __restrict__ S, int nrt, int ncg,
-                                                 int ntile, int ii0, int iitiles) {
-  __shared__ __align__(16) unsigned char lds[kGemmLdsBytes > ring_bytes<FP32>() ? kGemmLdsBytes
-                                                                                 : ring_bytes<FP32>()];
+// The GEMM's tiles, one block each (rt fastest, then cg, then the k-range).
+__global__ __launch_bounds__(256) void k_cp_gemm(Geom g, StepBufs b, const double* __restrict__ S, int nrt, int ncg) {
+  __shared__ __align__(16) unsigned char lds[kGemmLdsBytes];
   const int bid = blockIdx.x;
-  if (bid < ntile) {
-    cp_gemm_tile(g.n_ele, b.R, S, b.V, b.Qext, bid % nrt, (bid / nrt) % ncg, bid / (nrt * ncg), b.ksplit, lds);
-  } else {
-    const int u = ii0 + bid - ntile;
-    real_ii_block<FP32>(g, b, u % iitiles, u / iitiles, lds);
-  }
+  cp_gemm_tile(g.n_ele, b.R, S, b.V, b.Qext, bid % nrt, (bid / nrt) % ncg, bid / (nrt * ncg), b.ksplit, lds);
 }
 
 // k-ranges: as many as keep the grid within one block per CU of a 256-CU device
@@ -1253,15 +1240,11 @@ int cp_gemm_ksplit(int n_ele, int R) {
   return std::max(1, std::min(16, 256 / std::max(tiles, 1)));
 }
 
-void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, int fp32, int ii0, int nii, hipStream_t s) {
+void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s) {
   const int n = g.n_ele;
-  const int nrt = (n + 1 + 63) / 64, ncg = (b.R + 63) / 64, ntile = Sext ? nrt * ncg * b.ksplit : 0;
-  if (ntile + nii == 0) return;
-  const int it = real_ii_tiles(b);
-  if (fp32)
-    hipLaunchKernelGGL(k_cp_gemm<true>, dim3(ntile + nii), dim3(256), 0, s, g, b, Sext, nrt, ncg, ntile, ii0, it);
-  else
-    hipLaunchKernelGGL(k_cp_gemm<false>, dim3(ntile + nii), dim3(256), 0, s, g, b, Sext, nrt, ncg, ntile, ii0, it);
+  const int nrt = (n + 1 + 63) / 64, ncg = (b.R + 63) / 64, ntile = nrt * ncg * b.ksplit;
+  if (!Sext || ntile == 0) return;
+  hipLaunchKernelGGL(k_cp_gemm, dim3(ntile), dim3(256), 0, s, g, b, Sext, nrt, ncg);
 }
 
 // ============================================================ after the charge solve
@@ -1637,7 +1620,7 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) 
   real_ii_block<FP32>(g, b, j - m * tiles, r, lds);
 }
 
-int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * kIiIonsPerWave); }
+static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * kIiIonsPerWave); }
 
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
@@ -1649,17 +1632,15 @@ void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
     hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b, tiles);
 }
 
-// Block bx of the nbx blocks that one replica's reach ranges are split over, for part
-// `part` of `nparts` (the parts take the wave's visits in turn, so that the pass can
-// be spread over several launches); each visit takes one ion.  The pass is
+// Block bx of the nbx blocks that one replica's reach ranges are split over; the
+// block's waves take the replica's ions in turn, one ion per visit.  The pass is
 // latency-bound, so each wave loads the next ion's cell and record while it scans the
 // current one, and an ion's electrode runs come from a set-up table of sorted ranges
 // with their z-extent (one 16-byte load per run, all runs at once).  A run whose
 // z-extent lies farther than rc from the ion cannot hold a partner and is skipped
 // (the extent is stored in FP32; the margin below covers its rounding).
 template <bool FP32>
-__device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r, int part,
-                                              int nparts) {
+__device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r) {
   const int64_t* __restrict__ off = bb.off;
   const int64_t N = bb.N;
   const int* __restrict__ cstart = bb.cstart;
@@ -1682,7 +1663,7 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   const int b0 = (int)off[r];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int gw = bx * 4 + w, stride = nbx * 4 * nparts, first = gw * nparts + part;
+  const int gw = bx * 4 + w, stride = nbx * 4, first = gw;
   Entry* ring = ring_all[w];
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   const int n = g.n_ele;
@@ -1837,64 +1818,49 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   }
 }
 
-// The ion-electrode real-space pass needs the new charges and is latency-bound; it is
-// split in two parts that share launches with the rest of the step's tail:
-//   k_stage_ele:   [real_ie part 0 | electrode structure-factor partial blocks]
-//   k_stage_force: [real_ie part 1 | k-space ion force blocks]
+// The ion-electrode real-space pass needs the new charges and is latency-bound; it
+// shares its kernel with the electrode structure-factor partials:
+//   k_stage_ele: [real_ie | electrode structure-factor partial blocks]
 // The real-space blocks (kIeBlocks per replica walking its reach ranges) come first in
-// each grid: being latency-bound they start their chains at once, and the
+// the grid: being latency-bound they start their chains at once, and the
 // arithmetic-bound blocks fill the issue slots they leave.
 constexpr int kIeBlocks = 64;
 
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie, int part, int nparts) {
+__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie) {
   const int bid = blockIdx.x;
   if (bid < nie)
-    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks, part, nparts);
+    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks);
   else
     sf_block<FP32, false>(g, b, bid - nie);
 }
 
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_stage_force(Geom g, StepBufs b, int nif, int nie, int ftiles) {
-  const int bid = blockIdx.x;
-  if (bid < nie) {
-    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks, 1, 2);
-  } else {
-    const int u = bid - nie;
-    if constexpr (FP32)
-      ionforce32_block(g, b, u % ftiles, u / ftiles);
-    else
-      ionforce64_block(g, b, u % ftiles, u / ftiles);
-  }
+__global__ __launch_bounds__(256) void k_ion_force(Geom g, StepBufs b, int ftiles) {
+  const int u = blockIdx.x;
+  if constexpr (FP32)
+    ionforce32_block(g, b, u % ftiles, u / ftiles);
+  else
+    ionforce64_block(g, b, u % ftiles, u / ftiles);
 }
 
-static int ie_blocks(const StepBufs& b, int parts) {
-  return (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? kIeBlocks * b.R : 0;
-}
-
-// ie_part of ie_nparts: the share of the ion-electrode pass this launch runs
-void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, int ie_part, int ie_nparts,
-                      hipStream_t s) {
+void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
   const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ele * b.R : 0;
-  const int nie = ie_blocks(b, parts);
+  const int nie = (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? kIeBlocks * b.R : 0;
   if (nsf + nie == 0) return;
   if (fp32)
-    hipLaunchKernelGGL(k_stage_ele<true>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie, ie_part, ie_nparts);
+    hipLaunchKernelGGL(k_stage_ele<true>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
   else
-    hipLaunchKernelGGL(k_stage_ele<false>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie, ie_part, ie_nparts);
+    hipLaunchKernelGGL(k_stage_ele<false>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
 }
 
-// parts: STAGE_REAL (real_ie part 1) and STAGE_SF standing for the k-space force blocks
-void launch_stage_force(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
-  const int ftiles = cdiv64(std::max(b.max_nrep, 1), 64);
-  const int nif = (parts & STAGE_SF && b.max_nrep > 0) ? ftiles * b.R : 0;
-  const int nie = ie_blocks(b, parts);
-  if (nif + nie == 0) return;
+void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
+  if (b.max_nrep == 0) return;
+  const int ftiles = cdiv64(b.max_nrep, 64);
   if (fp32)
-    hipLaunchKernelGGL(k_stage_force<true>, dim3(nif + nie), dim3(256), 0, s, g, b, nif, nie, ftiles);
+    hipLaunchKernelGGL(k_ion_force<true>, dim3(ftiles * b.R), dim3(256), 0, s, g, b, ftiles);
   else
-    hipLaunchKernelGGL(k_stage_force<false>, dim3(nif + nie), dim3(256), 0, s, g, b, nif, nie, ftiles);
+    hipLaunchKernelGGL(k_ion_force<false>, dim3(ftiles * b.R), dim3(256), 0, s, g, b, ftiles);
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
