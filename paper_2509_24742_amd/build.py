@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libsrbe.so")
 SOURCES = ["step_kernels.hip", "setup_kernels.hip", "srbe_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
+    "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Werror=return-type", "-Wno-unused-function",
     # packed FP32 instructions are kept out of every kernel (the compiler would
     # otherwise form them from ordinary float code)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -48,6 +48,11 @@ constexpr int kRunMax = 42;
 // entries past the run's end; the values read there are never used).  Such arrays
 // are allocated with this many extra entries.
 constexpr int kScanPad = 192;
+// Per-replica sums after the charge solve (sum Q Z, sum Q d, sum Q b*) are kept as
+// kRsumParts partial sums, one per block of the pass that writes them, at
+// rsum[r kRsumStride + 4 part + q], and always added in part order.
+constexpr int kRsumParts = 16;
+constexpr int kRsumStride = 4 * kRsumParts;
 
 // Cell of a position (x, y wrapped by the caller into fractions sx, sy in [0,1)).
 __device__ __forceinline__ int cell_index(const Geom& g, double sx, double sy, double z) {

@@ -37,6 +37,7 @@ struct StepBufs {
   const uint4* ele_fx;      // n_ele fixed point (original order)
   const double4* ele_d4;    // n_ele fractional coordinates (original order), w = 0
   const int* ele_perm;      // sorted position -> electrode index
+  const int* ele_iperm;     // electrode index -> sorted position
   const int* ele_scell;     // cell of each sorted electrode
   const int* ele_cstart;    // ncell + 1
   const double2* ele_czr;   // ncell: z-extent of the electrodes of each cell
@@ -76,7 +77,7 @@ struct StepBufs {
   float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
   float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
   double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)
-  double* rsum;             // R*16 per-replica reductions after the charge solve (4 partial sums of 3)
+  double* rsum;             // R*kRsumStride per-replica sums after the charge solve (kRsumParts partials of 3)
   double* phi;              // N real-space ion-ion potential per ion
   double* Fii;              // 3N ion-ion real-space force sums (SoA, input order), before the ke q_i factor
   double* Fie;              // 3N ion-electrode real-space force sums, written for ions of reach cells only

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ A, in
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[col] = sh[0];

@@ -28,6 +28,7 @@ struct srbe_system {
   uint4* ele_fx = nullptr;     // fixed point, input order
   double4* ele_d4 = nullptr;   // fractional coordinates, input order
   int* ele_perm = nullptr;     // cell-sorted position -> electrode index
+  int* ele_iperm = nullptr;    // electrode index -> cell-sorted position
   int* ele_scell = nullptr;    // cell of each sorted electrode
   int* ele_cstart = nullptr;   // ncell + 1
   double2* ele_czr = nullptr;  // ncell: z-extent of each cell's electrodes
@@ -427,6 +428,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.ele_fx = h->ele_fx;
   b.ele_d4 = h->ele_d4;
   b.ele_perm = h->ele_perm;
+  b.ele_iperm = h->ele_iperm;
   b.ele_scell = h->ele_scell;
   b.ele_cstart = h->ele_cstart;
   b.ele_czr = h->ele_czr;
@@ -485,7 +487,7 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
       {(void**)&b.Qsf, fp32 ? ((size_t)R * n + kScanPad) * sizeof(float) : 0},
       {(void**)&b.Qsd, fp32 ? 0 : ((size_t)R * n + kScanPad) * sizeof(double)},
-      {(void**)&b.rsum, (size_t)R * 16 * sizeof(double)},
+      {(void**)&b.rsum, (size_t)R * kRsumStride * sizeof(double)},
       {(void**)&b.phi, (size_t)N1 * sizeof(double)},
       {(void**)&b.Fii, (size_t)3 * N1 * sizeof(double)},
       {(void**)&b.Fie, (size_t)3 * N1 * sizeof(double)},
@@ -605,7 +607,7 @@ void srbe_destroy(srbe_system* h) {
   for (hipStream_t st : h->aux)
     if (st) (void)hipStreamDestroy(st);
   if (h->cap) (void)hipStreamDestroy(h->cap);
-  void* bufs[] = {h->bin_keys, h->reach, h->reach_cell, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_scell, h->ele_cstart,
+  void* bufs[] = {h->bin_keys, h->reach, h->reach_cell, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_iperm, h->ele_scell, h->ele_cstart,
                   h->ele_czr, h->ion_runs, h->ele_rr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -655,6 +657,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ele_fx, n * sizeof(uint4));
     al((void**)&h->ele_d4, n * sizeof(double4));
     al((void**)&h->ele_perm, n * sizeof(int));
+    al((void**)&h->ele_iperm, n * sizeof(int));
     al((void**)&h->ele_scell, n * sizeof(int));
     al((void**)&h->ele_cstart, (size_t)(g.ncell + 1) * sizeof(int));
     al((void**)&h->ele_czr, (size_t)g.ncell * sizeof(double2));
@@ -717,8 +720,15 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     launch_cell_zrange(g, h->ele_cstart, h->ele_xyz, h->ele_perm, h->ele_czr, s);
     launch_logq_table(g, h->logq, s);
     std::vector<double2> czr(g.ncell);
+    std::vector<int> perm(n), iperm(n);
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(czr.data(), h->ele_czr, czr.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess) {
+        hipMemcpy(czr.data(), h->ele_czr, czr.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(perm.data(), h->ele_perm, n * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipFree(off2);
+      return fail(SRBE_EHIP);
+    }
+    for (size_t k = 0; k < n; ++k) iperm[perm[k]] = (int)k;
+    if (n > 0 && hipMemcpy(h->ele_iperm, iperm.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
     }

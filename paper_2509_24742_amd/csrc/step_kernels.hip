@@ -463,22 +463,19 @@ __device__ __forceinline__ void finalize_tile(const Geom& g, int r, int k, const
                                               const int4* modes, const double* w, double2* S1, double2* coef,
                                               ModeRec32* rec, int stage, unsigned* status) {
   if (k >= g.K) return;
+  // chunks 16 at a time, all requested before the first add, added in chunk order
   double sr = 0.0, si = 0.0;
-  int c = 0;
-  for (; c + 4 <= nchunk; c += 4) {
-    double2 p[4];
+  for (int c = 0; c < nchunk; c += 16) {
+    double2 p[16];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) p[u] = part[((size_t)r * nchunk + c + u) * g.K + k];
+    for (int u = 0; u < 16; ++u)
+      p[u] = c + u < nchunk ? part[((size_t)r * nchunk + c + u) * g.K + k] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      sr += p[u].x;
-      si += p[u].y;
-    }
-  }
-  for (; c < nchunk; ++c) {
-    const double2 p = part[((size_t)r * nchunk + c) * g.K + k];
-    sr += p.x;
-    si += p.y;
+    for (int u = 0; u < 16; ++u)
+      if (c + u < nchunk) {
+        sr += p[u].x;
+        si += p[u].y;
+      }
   }
   const size_t idx = (size_t)r * g.K + k;
   if (stage == 1) {
@@ -1251,27 +1248,34 @@ void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStr
 // Per replica: copy Q (and psibar) out of the GEMM result (or the fixed charges);
 // the copies of Q the later passes read (FP32 original order and cell-sorted
 // order); sums of Q Z (slab term), d.Q and b*.Q (energy).
-// Per-replica sums after the charge solve (sum Q Z, sum Q d, sum Q b*), kept as
-// kRsumParts partial sums (one per post-charges block of the replica) and always
-// added in part order.
-constexpr int kRsumParts = 4;
-constexpr int kRsumStride = 4 * kRsumParts;
-
 __device__ __forceinline__ double rsum_total(const double* rsum, int r, int q) {
   const double* rs = rsum + (size_t)r * kRsumStride + q;
-  return ((rs[0] + rs[4]) + rs[8]) + rs[12];
+  double t = rs[0];
+#pragma unroll
+  for (int p = 1; p < kRsumParts; ++p) t += rs[4 * p];
+  return t;
 }
 
-// Q_j of replica r: the given charges, or the GEMM partials added in k-range order.
+// Q_j of replica r from the GEMM partials, added in k-range order.  All partials are
+// requested before the first add (ksplit <= 16), so that one thread waits out one
+// memory latency rather than ksplit of them.
 __device__ __forceinline__ double solved_q(const double* __restrict__ Qext, int ksplit, int R, int r, int n, int j) {
-  double q = Qext[(size_t)r * (n + 1) + j];
-  for (int h = 1; h < ksplit; ++h) q += Qext[((size_t)h * R + r) * (n + 1) + j];
+  double p[16];
+#pragma unroll
+  for (int h = 0; h < 16; ++h) p[h] = h < ksplit ? Qext[((size_t)h * R + r) * (n + 1) + j] : 0.0;
+  double q = p[0];
+#pragma unroll
+  for (int h = 1; h < 16; ++h)
+    if (h < ksplit) q += p[h];
   return q;
 }
 
+// Block (r, pc): electrodes [j0, j1) of replica r, at most one per thread; their
+// positions in the cell-sorted order come from the set-up's inverse permutation, so
+// every load is independent of every other.
 __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __restrict__ Qext, int ksplit,
                                                       const double* __restrict__ Q_in, const double* __restrict__ ele_xyz,
-                                                      const double* __restrict__ ele_d, const int* __restrict__ ele_perm,
+                                                      const double* __restrict__ ele_d, const int* __restrict__ ele_iperm,
                                                       const double* __restrict__ bstar, double* __restrict__ Q_out,
                                                       float* __restrict__ Qf, float* __restrict__ Qsf,
                                                       double* __restrict__ Qsd, double* __restrict__ psibar,
@@ -1283,19 +1287,16 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
   double v[3] = {0.0, 0.0, 0.0};
   int bad = 0;
   for (int j = j0 + threadIdx.x; j < j1; j += 256) {
+    const int k = ele_iperm[j];
     const double Qj = Q_in ? Q_in[(size_t)r * n + j] : solved_q(Qext, ksplit, R, r, n, j);
     if (!isfinite(Qj)) bad = 1;
     Q_out[(size_t)r * n + j] = Qj;
     if (Qf) Qf[(size_t)r * n + j] = (float)Qj;
+    if (Qsf) Qsf[(size_t)r * n + k] = (float)Qj;
+    if (Qsd) Qsd[(size_t)r * n + k] = Qj;
     v[0] += Qj * ele_xyz[2 * n + j];
     v[1] += Qj * ele_d[j];
     v[2] += Qj * bstar[(size_t)r * n + j];
-  }
-  for (int k = j0 + threadIdx.x; k < j1; k += 256) {
-    const int j = ele_perm[k];
-    const double Qj = Q_in ? Q_in[(size_t)r * n + j] : solved_q(Qext, ksplit, R, r, n, j);
-    if (Qsf) Qsf[(size_t)r * n + k] = (float)Qj;
-    if (Qsd) Qsd[(size_t)r * n + k] = Qj;
   }
   if (bad) atomicOr(status, ST_NUMERIC);
   block_sum<256, 3>(v, sh);
@@ -1310,7 +1311,7 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
 
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s) {
   hipLaunchKernelGGL(k_post_charges, dim3(b.R, kRsumParts), dim3(256), 0, s, g, b.Qext, b.ksplit, fixedQ ? b.Q_in : nullptr, b.ele_xyz,
-                     b.ele_d, b.ele_perm, b.bstar, b.Q_out, fp32 ? b.Qf : nullptr, fp32 ? b.Qsf : nullptr,
+                     b.ele_d, b.ele_iperm, b.bstar, b.Q_out, fp32 ? b.Qf : nullptr, fp32 ? b.Qsf : nullptr,
                      fp32 ? nullptr : b.Qsd, b.psibar_out, b.rsum, b.status);
 }
 
@@ -1896,6 +1897,7 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
   const double* __restrict__ scal = b.scal;
   const double* __restrict__ rsum = b.rsum;
   double v[2] = {0.0, 0.0};
+#pragma unroll 8
   for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
   for (int k = threadIdx.x; k < g.K; k += 256) {
     const double2 s = b.S1[(size_t)r * g.K + k];
@@ -1926,10 +1928,13 @@ __global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int f
   if (i >= N) return;
   const double kq = g.ke * b.ion_q[i];
   double rx = b.Fii[i], ry = b.Fii[N + i], rz = b.Fii[2 * N + i];
+  // Fie is read for every ion (in bounds; stale for ions outside the reach cells) so
+  // that its loads do not wait for the flag, which then selects it
+  const double ex = b.Fie[i], ey = b.Fie[N + i], ez = b.Fie[2 * N + i];
   if (b.reach_cell[b.keys[i] >> 13]) {
-    rx += b.Fie[i];
-    ry += b.Fie[N + i];
-    rz += b.Fie[2 * N + i];
+    rx += ex;
+    ry += ey;
+    rz += ez;
   }
   double* F = b.F_out;
   F[i] += kq * rx;
