@@ -51,6 +51,10 @@ constexpr int kScanPad = 192;
 // Per-replica sums after the charge solve (sum Q Z, sum Q d, sum Q b*) are kept as
 // kRsumParts partial sums, one per block of the pass that writes them, at
 // rsum[r kRsumStride + 4 part + q], and always added in part order.
+// Resident waves per SIMD of the real-space passes (their register use allows this
+// many; the grids are sized from it).
+constexpr int kRealWavesPerSimd32 = 7;
+constexpr int kRealWavesPerSimd64 = 3;
 constexpr int kRsumParts = 16;
 constexpr int kRsumStride = 4 * kRsumParts;
 

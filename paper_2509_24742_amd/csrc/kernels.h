@@ -74,6 +74,8 @@ struct StepBufs {
   double* Qext;             // ksplit*R*(n_ele+1) GEMM partials over k-ranges (Q then psibar),
                             // Qext[(h R + r)(n+1) + i], summed in h order after the GEMM
   int ksplit;
+  int ii_ipw;               // ion-ion pass: consecutive sorted ions per wave
+  int ie_nbx;               // ion-electrode pass: blocks per replica
   float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
   float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
   double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)

@@ -21,6 +21,7 @@ struct srbe_system {
   srbe_params p;
   Geom g;
   int device = 0;
+  int ncu = 256;  // compute units of the device (sizes the latency-bound passes' grids)
   int n_ele = 0;
   bool has_cp = false;
   double* ele_xyz = nullptr;
@@ -414,6 +415,12 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.nchunk_ion = chunks_for(max_nrep);
   b.nchunk_ele = chunks_for(n);
   b.ksplit = cp_gemm_ksplit(n, R);
+  // Latency-bound real-space passes: as much work per wave as fills the device's wave
+  // slots (4 per block, kRealWavesPerSimd resident per SIMD) once, so that no second,
+  // mostly empty round of blocks follows the first.
+  const int64_t slots = (int64_t)h->ncu * 4 * (a.precision == SRBE_FP32 ? kRealWavesPerSimd32 : kRealWavesPerSimd64);
+  b.ii_ipw = (int)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)R * max_nrep + slots - 1) / slots));
+  b.ie_nbx = (int)std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(1, (max_nrep + 3) / 4), slots / 4 / std::max(R, 1)));
   b.ion_xyz = a.ion_xyz;
   b.ion_q = a.ion_q;
   b.dpsi = a.dpsi;
@@ -639,6 +646,10 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
   h->has_cp = cp;
   h->g = make_geom(*params, n_ele);
   (void)hipGetDevice(&h->device);
+  if (hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || h->ncu < 1) {
+    delete h;
+    return SRBE_EHIP;
+  }
   hipStream_t s = nullptr;
   int rc = SRBE_OK;
   auto fail = [&](int code) {

@@ -1484,10 +1484,8 @@ struct CarriedSums {
   }
 };
 
-constexpr int kIiIonsPerWave = 8;  // consecutive sorted ions per wave (ion-ion pass)
-
 // Ion-ion pass, block (bx, r): waves 4 bx .. 4 bx + 3 of replica r, each taking
-// kIiIonsPerWave consecutive sorted ions.  lds: ring_bytes<FP32>() bytes.
+// bb.ii_ipw consecutive sorted ions.  lds: ring_bytes<FP32>() bytes.
 template <bool FP32>
 __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb, int bx, int r, void* lds) {
   const int64_t* __restrict__ off = bb.off;
@@ -1505,9 +1503,10 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
   const int b0 = (int)off[r], b1 = (int)off[r + 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int kbeg = b0 + (bx * 4 + w) * kIiIonsPerWave;
+  const int ipw = bb.ii_ipw;
+  const int kbeg = b0 + (bx * 4 + w) * ipw;
   if (kbeg >= b1) return;  // whole wave
-  const int kend = min(b1, kbeg + kIiIonsPerWave);
+  const int kend = min(b1, kbeg + ipw);
   Entry* ring = reinterpret_cast<Entry*>(lds) + w * kRingAlloc;
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   auto ion_range = [&](int, int2 rc, int& b, int& e) {
@@ -1621,7 +1620,7 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) 
   real_ii_block<FP32>(g, b, j - m * tiles, r, lds);
 }
 
-static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * kIiIonsPerWave); }
+static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * b.ii_ipw); }
 
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
@@ -1822,16 +1821,14 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
 // The ion-electrode real-space pass needs the new charges and is latency-bound; it
 // shares its kernel with the electrode structure-factor partials:
 //   k_stage_ele: [real_ie | electrode structure-factor partial blocks]
-// The real-space blocks (kIeBlocks per replica walking its reach ranges) come first in
+// The real-space blocks (b.ie_nbx per replica walking its reach ranges) come first in
 // the grid: being latency-bound they start their chains at once, and the
 // arithmetic-bound blocks fill the issue slots they leave.
-constexpr int kIeBlocks = 64;
-
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie) {
   const int bid = blockIdx.x;
   if (bid < nie)
-    real_ie_block<FP32>(g, b, bid % kIeBlocks, kIeBlocks, bid / kIeBlocks);
+    real_ie_block<FP32>(g, b, bid % b.ie_nbx, b.ie_nbx, bid / b.ie_nbx);
   else
     sf_block<FP32, false>(g, b, bid - nie);
 }
@@ -1847,7 +1844,7 @@ __global__ __launch_bounds__(256) void k_ion_force(Geom g, StepBufs b, int ftile
 
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
   const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ele * b.R : 0;
-  const int nie = (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? kIeBlocks * b.R : 0;
+  const int nie = (parts & STAGE_REAL && b.max_nrep > 0 && b.nreach > 0) ? b.ie_nbx * b.R : 0;
   if (nsf + nie == 0) return;
   if (fp32)
     hipLaunchKernelGGL(k_stage_ele<true>, dim3(nsf + nie), dim3(256), 0, s, g, b, nsf, nie);
