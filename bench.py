@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time with the default launch parameters instead of tuning them first (srbe_tune)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -174,6 +176,28 @@ def main():
         gr.close()
         return e0.elapsed_time(e1) / args.steps
 
+    # single-cell inputs (replica 0)
+    off1 = np.array([0, sizes[0]], dtype=np.int64)
+    xyz1 = torch.tensor(np.ascontiguousarray(wb["ion_pos"][0].T).ravel(), dtype=torch.float64, device=dev)
+    q1 = torch.tensor(wb["ion_q"][0], dtype=torch.float64, device=dev)
+    dpsi1, seeds1 = dpsi[:1].contiguous(), seeds[:1].contiguous()
+
+    # ---- launch-parameter tuning (srbe_tune), outside the timed region
+    tuning = None
+    if not args.no_tune:
+        t0 = time.time()
+        tuning = {}
+        for name, prec, offs, x, qq, dp, sd in [("fp32_batch", srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds),
+                                                ("fp64_single_cell", srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi1, seeds1),
+                                                ("fp32_single_cell", srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi1, seeds1)]:
+            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, iters=30)
+            tuning[name] = {"params": dict(zip(srbe_amd.SRBE_TUNE_NAMES, t["params"])),
+                            "ms_default": t["ms_default"], "ms_tuned": t["ms_tuned"]}
+        tuning["seconds"] = time.time() - t0
+        log(f"tuned launch parameters in {tuning['seconds']:.2f} s: "
+            f"{tuning['fp32_batch']['params']} ({tuning['fp32_batch']['ms_default'] * 1e3:.1f} -> "
+            f"{tuning['fp32_batch']['ms_tuned'] * 1e3:.1f} us/step)")
+
     # ---- headline: FP32, all replicas in one step, replayed as a captured graph
     ms_fp32 = timed_graph(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
     log(f"FP32 batch (graph): {ms_fp32 * 1e3:.1f} us/step")
@@ -190,13 +214,10 @@ def main():
     phases = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     # ---- FP64 plain path on one cell
-    off1 = np.array([0, sizes[0]], dtype=np.int64)
-    xyz1 = torch.tensor(np.ascontiguousarray(wb["ion_pos"][0].T).ravel(), dtype=torch.float64, device=dev)
-    q1 = torch.tensor(wb["ion_q"][0], dtype=torch.float64, device=dev)
-    ms_fp64_1 = timed_graph(srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
+    ms_fp64_1 = timed_graph(srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi1, seeds1)
     pairs_1 = (sizes[0] + n_ele) * K
     # FP32 on a single cell, for the batching gain
-    ms_fp32_1 = timed_graph(srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi[:1].contiguous(), seeds[:1].contiguous())
+    ms_fp32_1 = timed_graph(srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi1, seeds1)
     log(f"single cell: FP64 {ms_fp64_1 * 1e3:.1f} us/step, FP32 {ms_fp32_1 * 1e3:.1f} us/step")
 
     # ---- roofline of the dominant kernel (longest phase with a roofline figure)
@@ -265,6 +286,7 @@ def main():
         "slowest_phase": top,
         "setup_s": setup_s,
         "workload_generation_s": gen_s,
+        "launch_tuning": tuning,
     }
 
     if not args.no_cpu:

@@ -194,6 +194,59 @@ int srbe_profile_read(srbe_system* h, double* ms_out /*host [SRBE_N_PHASES]*/,
                       int64_t* launches_out /*host [SRBE_N_PHASES]*/);
 const char* srbe_phase_name(int32_t phase);
 
+/*
+ * Launch-parameter tuning (the step's tile shapes; not a computation of the paper).
+ * Parameters, by index:
+ *   SRBE_TUNE_SF_BLOCKS   structure-factor passes (Eq. (15), ions and electrodes):
+ *                         target number of partial-sum blocks of 256 modes, which
+ *                         sets the particles each block sums (1 .. 2^20)
+ *   SRBE_TUNE_WAVES       electrode-potential (Eq. (24)) and ion k-space force
+ *                         (Eq. (25)) passes: waves per 64-particle block, each wave
+ *                         taking an equal share of the modes (2, 4 or 8)
+ *   SRBE_TUNE_UNROLL      the unroll depth of their FP32 mode loops (2, 4 or 8)
+ *   SRBE_TUNE_II_IONS     ion-ion real-space pass (Eq. (13)): consecutive cell-sorted
+ *                         ions per wave (1 .. 1024)
+ *   SRBE_TUNE_IE_BLOCKS   ion-electrode real-space pass: blocks per replica (1 .. 65536)
+ *   SRBE_TUNE_ELE_SPLIT   electrode-potential real-space pass: waves per chunk of 64
+ *                         electrodes (1, 2 or 4)
+ * A step (srbe_step, srbe_graph_create) uses the parameters stored in the handle
+ * for its shape -- precision, n_rep and the largest replica's ion count -- else
+ * defaults derived from the device's compute-unit count.  Results depend on the
+ * parameters only through the order of floating-point sums (each setting is
+ * bitwise repeatable).
+ *
+ * srbe_tune -- times captured steps (graph replays, `iters` timed after a warm-up,
+ * iters >= 1) of the given inputs on `stream`, varying one parameter at a time over
+ * its candidates starting from the defaults (coordinate descent, one pass), keeps
+ * the fastest, stores it for the shape and writes it to params_out (host int32
+ * [SRBE_TUNE_NPARAM], may be NULL).  ms_out (host double[2], may be NULL) receives
+ * the ms per step of the defaults and of the stored parameters.  Inputs as for
+ * srbe_step (sampled modes; seed required when P > 0); the outputs go to buffers the
+ * call allocates and frees.  Blocks until done.  Errors: SRBE_EINVAL (arguments),
+ * SRBE_ENOMEM, SRBE_EHIP, or a device fault of a timed step (then nothing is stored).
+ *
+ * srbe_get_tuning -- the parameters a step of this shape would use (host int32
+ * [SRBE_TUNE_NPARAM]).  ion_offsets: host, n_rep + 1.
+ * srbe_set_tuning -- stores the given parameters (host int32 [SRBE_TUNE_NPARAM]) for
+ * the shape, or with params NULL drops the stored entry (back to the defaults).
+ * SRBE_EINVAL, with srbe_last_error naming the parameter, for a value outside its
+ * range.  Graphs already created keep the parameters they were captured with.
+ */
+#define SRBE_TUNE_SF_BLOCKS 0
+#define SRBE_TUNE_WAVES 1
+#define SRBE_TUNE_UNROLL 2
+#define SRBE_TUNE_II_IONS 3
+#define SRBE_TUNE_IE_BLOCKS 4
+#define SRBE_TUNE_ELE_SPLIT 5
+#define SRBE_TUNE_NPARAM 6
+int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets, const double* ion_xyz,
+              const double* ion_q, const double* dpsi, const uint64_t* seed, int32_t iters, int32_t* params_out,
+              double* ms_out, void* stream);
+int srbe_get_tuning(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                    int32_t* params_out);
+int srbe_set_tuning(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                    const int32_t* params);
+
 /* srbe_normaliser -- G of Eq. (27) for the handle's parameters (host double). */
 double srbe_normaliser(const srbe_system* h);
 

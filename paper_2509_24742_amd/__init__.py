@@ -13,7 +13,8 @@ from . import binding
 from .binding import (SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
                       srbe_error_string, srbe_graph_create, srbe_graph_destroy, srbe_graph_launch,
                       srbe_graph_set_step, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
-                      srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status)
+                      srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status,
+                      SRBE_TUNE_NAMES, srbe_get_tuning, srbe_set_tuning, srbe_tune)
 
 
 class System:
@@ -51,6 +52,39 @@ class System:
             E=torch.empty(R, dtype=torch.float64, device=device),
             kset=torch.empty(R * P * 3, dtype=torch.int32, device=device) if (want_kset and P) else None,
         )
+
+    def tune(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, precision=SRBE_FP64, iters=10, cache=None):
+        """Choose the launch parameters for this batch shape (srbe_tune) and keep them in the handle.
+
+        cache: path of a JSON file of earlier choices, keyed by device architecture, precision,
+        replica count, largest replica, electrode count and P; a hit is applied without timing
+        and a miss is timed and added.  Returns dict(params, ms_default, ms_tuned, cached).
+        """
+        import json
+        import os
+        import torch
+        off = np.asarray(ion_offsets, dtype=np.int64)
+        key = None
+        entries = {}
+        if cache is not None:
+            arch = torch.cuda.get_device_properties(dpsi.device).gcnArchName
+            key = (f"{arch}|{'fp32' if precision == SRBE_FP32 else 'fp64'}|R={len(off) - 1}|"
+                   f"maxrep={int(np.diff(off).max()) if len(off) > 1 else 0}|n_ele={self.n_ele}|P={self.params['P']}")
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    entries = json.load(f)
+            if key in entries:
+                params = [int(entries[key]["params"][name]) for name in SRBE_TUNE_NAMES]
+                srbe_set_tuning(self.h, precision, off, params)
+                return dict(params=params, ms_default=None, ms_tuned=entries[key].get("ms_tuned"), cached=True)
+        params, ms0, ms1 = srbe_tune(self.h, precision, off, ion_xyz, ion_q, dpsi, seed, iters=iters)
+        if cache is not None:
+            entries[key] = dict(params=dict(zip(SRBE_TUNE_NAMES, params)), ms_default=ms0, ms_tuned=ms1)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(entries, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(params=params, ms_default=ms0, ms_tuned=ms1, cached=False)
 
     def capture(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, precision=SRBE_FP64, kset_in=None,
                 Q_in=None, want_b=True, want_kset=True, out=None):

@@ -87,6 +87,13 @@ def lib():
     L.srbe_graph_set_step.restype = ctypes.c_int
     L.srbe_graph_destroy.argtypes = [_vp]
     L.srbe_graph_destroy.restype = None
+    L.srbe_tune.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
+                            _vp]
+    L.srbe_tune.restype = ctypes.c_int
+    L.srbe_get_tuning.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+    L.srbe_get_tuning.restype = ctypes.c_int
+    L.srbe_set_tuning.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
+    L.srbe_set_tuning.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -94,7 +101,7 @@ def lib():
 EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string", "srbe_step", "srbe_sample",
             "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
             "srbe_phase_name", "srbe_graph_create", "srbe_graph_launch", "srbe_graph_set_step",
-            "srbe_graph_destroy"]
+            "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning"]
 SRBE_N_PHASES = 16
 
 
@@ -239,6 +246,54 @@ def srbe_graph_set_step(gr, step, stream=None):
 
 def srbe_graph_destroy(gr):
     lib().srbe_graph_destroy(gr)
+
+
+SRBE_TUNE_NAMES = ["sf_blocks", "waves", "unroll", "ii_ions", "ie_blocks", "ele_split"]
+SRBE_TUNE_NPARAM = len(SRBE_TUNE_NAMES)
+
+
+def _offsets(ion_offsets):
+    off = np.ascontiguousarray(np.asarray(ion_offsets, dtype=np.int64))
+    return off, off.shape[0] - 1
+
+
+def srbe_tune(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, iters=10, stream=None):
+    """Time candidate launch parameters on these inputs and store the fastest for the shape.
+
+    Returns (params as a list of SRBE_TUNE_NPARAM ints, ms per step with the defaults, ms with them).
+    """
+    import torch
+    off, R = _offsets(ion_offsets)
+    N = int(off[-1])
+    out = np.zeros(SRBE_TUNE_NPARAM, dtype=np.int32)
+    ms = np.zeros(2, dtype=np.float64)
+    _check(h, lib().srbe_tune(h, int(precision), R, off.ctypes.data,
+                              _dev(ion_xyz, torch.float64, 3 * N, "ion_xyz", allow_none=N == 0),
+                              _dev(ion_q, torch.float64, N, "ion_q", allow_none=N == 0),
+                              _dev(dpsi, torch.float64, R, "dpsi"),
+                              _dev(seed, torch.uint64, R, "seed", allow_none=True), int(iters), out.ctypes.data,
+                              ms.ctypes.data, _stream(stream)))
+    return [int(v) for v in out], float(ms[0]), float(ms[1])
+
+
+def srbe_get_tuning(h, precision, ion_offsets):
+    """The launch parameters a step of this shape uses (list of SRBE_TUNE_NPARAM ints)."""
+    off, R = _offsets(ion_offsets)
+    out = np.zeros(SRBE_TUNE_NPARAM, dtype=np.int32)
+    _check(h, lib().srbe_get_tuning(h, int(precision), R, off.ctypes.data, out.ctypes.data))
+    return [int(v) for v in out]
+
+
+def srbe_set_tuning(h, precision, ion_offsets, params):
+    """Store launch parameters for the shape (params None: back to the defaults)."""
+    off, R = _offsets(ion_offsets)
+    if params is None:
+        _check(h, lib().srbe_set_tuning(h, int(precision), R, off.ctypes.data, None))
+        return
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.int32))
+    if p.shape != (SRBE_TUNE_NPARAM,):
+        raise ValueError(f"params must have {SRBE_TUNE_NPARAM} entries")
+    _check(h, lib().srbe_set_tuning(h, int(precision), R, off.ctypes.data, p.ctypes.data))
 
 
 def srbe_sample(h, seed, step, kset_out, n_accepted_out=None, stream=None):

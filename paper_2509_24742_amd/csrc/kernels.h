@@ -76,6 +76,9 @@ struct StepBufs {
   int ksplit;
   int ii_ipw;               // ion-ion pass: consecutive sorted ions per wave
   int ie_nbx;               // ion-electrode pass: blocks per replica
+  int kw;                   // potential and force passes: waves per 64-particle block (2, 4, 8)
+  int unroll;               // their FP32 mode-loop unroll depth (2, 4, 8)
+  int esplit;               // electrode-potential real-space pass: waves per electrode chunk (1, 2, 4)
   float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
   float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
   double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)
@@ -106,6 +109,7 @@ void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hi
 void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, hipStream_t s);
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 int cp_gemm_ksplit(int n_ele, int R);
+int ele_split(int units);
 // nothing is launched if Sext is null (fixed charges)
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);

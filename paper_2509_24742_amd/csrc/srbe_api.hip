@@ -22,6 +22,13 @@ struct srbe_system {
   Geom g;
   int device = 0;
   int ncu = 256;  // compute units of the device (sizes the latency-bound passes' grids)
+  // launch parameters stored per batch shape (srbe_tune / srbe_set_tuning)
+  struct Tuned {
+    int precision, n_rep;
+    int64_t max_nrep;
+    int p[SRBE_TUNE_NPARAM];
+  };
+  std::vector<Tuned> tuned;
   int n_ele = 0;
   bool has_cp = false;
   double* ele_xyz = nullptr;
@@ -377,25 +384,87 @@ struct StepArgs {
   int32_t* kset_out;
 };
 
-int check_step(srbe_system* h, const StepArgs& a, int64_t& max_nrep) {
-  if (a.precision != SRBE_FP64 && a.precision != SRBE_FP32) return set_err(h, SRBE_EINVAL, "unknown precision");
-  if (a.n_rep <= 0 || !a.ion_offsets) return set_err(h, SRBE_EINVAL, "n_rep must be positive and offsets given");
-  if (a.n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
-  if (a.ion_offsets[0] != 0) return set_err(h, SRBE_EINVAL, "ion_offsets[0] must be 0");
+// Precision and batch shape (host offsets); max_nrep: the largest replica's ion count.
+int check_shape(srbe_system* h, int precision, int n_rep, const int64_t* ion_offsets, int64_t& max_nrep) {
+  if (precision != SRBE_FP64 && precision != SRBE_FP32) return set_err(h, SRBE_EINVAL, "unknown precision");
+  if (n_rep <= 0 || !ion_offsets) return set_err(h, SRBE_EINVAL, "n_rep must be positive and offsets given");
+  if (n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
+  if (ion_offsets[0] != 0) return set_err(h, SRBE_EINVAL, "ion_offsets[0] must be 0");
   max_nrep = 0;
-  for (int r = 0; r < a.n_rep; ++r) {
-    const int64_t c = a.ion_offsets[r + 1] - a.ion_offsets[r];
+  for (int r = 0; r < n_rep; ++r) {
+    const int64_t c = ion_offsets[r + 1] - ion_offsets[r];
     if (c < 0) return set_err(h, SRBE_EINVAL, "ion_offsets must be non-decreasing");
     max_nrep = std::max(max_nrep, c);
   }
+  if (max_nrep > kMaxBinParticles)
+    return set_err(h, SRBE_EINVAL, "a replica has more ions than the one-block cell sort handles (8192)");
+  return SRBE_OK;
+}
+
+int check_step(srbe_system* h, const StepArgs& a, int64_t& max_nrep) {
+  const int rc = check_shape(h, a.precision, a.n_rep, a.ion_offsets, max_nrep);
+  if (rc != SRBE_OK) return rc;
   const int64_t N = a.ion_offsets[a.n_rep];
   if (N > 0 && (!a.ion_xyz || !a.ion_q)) return set_err(h, SRBE_EINVAL, "ion arrays are NULL");
   if (!a.dpsi || !a.Q_out || (N > 0 && !a.F_out)) return set_err(h, SRBE_EINVAL, "dpsi, Q_out and F_out are required");
   if (!a.kset_in && !a.seed && h->p.P > 0) return set_err(h, SRBE_EINVAL, "seed or kset_in is required");
   if (!a.Q_in && !h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: pass Q_in");
-  if (max_nrep > kMaxBinParticles)
-    return set_err(h, SRBE_EINVAL, "a replica has more ions than the one-block cell sort handles (8192)");
   return SRBE_OK;
+}
+
+// Default launch parameters of a step of this shape.  Latency-bound real-space
+// passes get as much work per wave as fills the device's wave slots (4 per block,
+// kRealWavesPerSimd resident per SIMD) once, so that no second, mostly empty round of
+// blocks follows the first.
+void default_tuning(const srbe_system* h, int precision, int R, int64_t max_nrep, int* p) {
+  const int64_t slots = (int64_t)h->ncu * 4 * (precision == SRBE_FP32 ? kRealWavesPerSimd32 : kRealWavesPerSimd64);
+  p[SRBE_TUNE_SF_BLOCKS] = 1024;
+  p[SRBE_TUNE_WAVES] = 4;
+  p[SRBE_TUNE_UNROLL] = 4;
+  p[SRBE_TUNE_II_IONS] = (int)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)R * max_nrep + slots - 1) / slots));
+  p[SRBE_TUNE_IE_BLOCKS] = (int)std::max<int64_t>(
+      1, std::min<int64_t>(std::max<int64_t>(1, (max_nrep + 3) / 4), slots / 4 / std::max(R, 1)));
+  p[SRBE_TUNE_ELE_SPLIT] = ele_split(h->n_ele_chunks * R);
+}
+
+// The stored parameters of this shape, else the defaults.
+void tuning_for(const srbe_system* h, int precision, int R, int64_t max_nrep, int* p) {
+  for (const auto& t : h->tuned)
+    if (t.precision == precision && t.n_rep == R && t.max_nrep == max_nrep) {
+      std::memcpy(p, t.p, sizeof(t.p));
+      return;
+    }
+  default_tuning(h, precision, R, max_nrep, p);
+}
+
+const char* bad_tuning(const int* p) {
+  if (p[SRBE_TUNE_SF_BLOCKS] < 1 || p[SRBE_TUNE_SF_BLOCKS] > (1 << 20)) return "structure-factor blocks outside [1, 2^20]";
+  if (p[SRBE_TUNE_WAVES] != 2 && p[SRBE_TUNE_WAVES] != 4 && p[SRBE_TUNE_WAVES] != 8) return "waves per block not 2, 4 or 8";
+  if (p[SRBE_TUNE_UNROLL] != 2 && p[SRBE_TUNE_UNROLL] != 4 && p[SRBE_TUNE_UNROLL] != 8) return "unroll not 2, 4 or 8";
+  if (p[SRBE_TUNE_II_IONS] < 1 || p[SRBE_TUNE_II_IONS] > 1024) return "ions per wave outside [1, 1024]";
+  if (p[SRBE_TUNE_IE_BLOCKS] < 1 || p[SRBE_TUNE_IE_BLOCKS] > 65536) return "ion-electrode blocks outside [1, 65536]";
+  if (p[SRBE_TUNE_ELE_SPLIT] != 1 && p[SRBE_TUNE_ELE_SPLIT] != 2 && p[SRBE_TUNE_ELE_SPLIT] != 4)
+    return "electrode chunk split not 1, 2 or 4";
+  return nullptr;
+}
+
+void store_tuning(srbe_system* h, int precision, int R, int64_t max_nrep, const int* p) {
+  for (auto& t : h->tuned)
+    if (t.precision == precision && t.n_rep == R && t.max_nrep == max_nrep) {
+      std::memcpy(t.p, p, sizeof(t.p));
+      return;
+    }
+  srbe_system::Tuned t{precision, R, max_nrep, {}};
+  std::memcpy(t.p, p, sizeof(t.p));
+  h->tuned.push_back(t);
+}
+
+void forget_tuning(srbe_system* h, int precision, int R, int64_t max_nrep) {
+  for (size_t u = 0; u < h->tuned.size(); ++u)
+    if (h->tuned[u].precision == precision && h->tuned[u].n_rep == R && h->tuned[u].max_nrep == max_nrep) {
+      h->tuned.erase(h->tuned.begin() + u);
+      return;
+    }
 }
 
 // Everything but the workspace pointers and the device offsets.
@@ -405,22 +474,23 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.R = R;
   b.N = a.ion_offsets[R];
   b.max_nrep = (int)max_nrep;
-  // chunking of the structure-factor passes: aim for >= 1024 blocks of 256 threads
+  int tp[SRBE_TUNE_NPARAM];
+  tuning_for(h, a.precision, R, max_nrep, tp);
+  // chunking of the structure-factor passes: about tp[SF_BLOCKS] blocks of 256 threads
   b.ktiles = std::max(1, (K + 255) / 256);
   auto chunks_for = [&](int64_t np) {
-    int64_t c = (1024 + (int64_t)b.ktiles * R - 1) / ((int64_t)b.ktiles * R);
+    int64_t c = (tp[SRBE_TUNE_SF_BLOCKS] + (int64_t)b.ktiles * R - 1) / ((int64_t)b.ktiles * R);
     c = std::min<int64_t>(c, std::max<int64_t>(1, (np + 31) / 32));
     return (int)std::max<int64_t>(1, std::min<int64_t>(c, 4096));
   };
   b.nchunk_ion = chunks_for(max_nrep);
   b.nchunk_ele = chunks_for(n);
   b.ksplit = cp_gemm_ksplit(n, R);
-  // Latency-bound real-space passes: as much work per wave as fills the device's wave
-  // slots (4 per block, kRealWavesPerSimd resident per SIMD) once, so that no second,
-  // mostly empty round of blocks follows the first.
-  const int64_t slots = (int64_t)h->ncu * 4 * (a.precision == SRBE_FP32 ? kRealWavesPerSimd32 : kRealWavesPerSimd64);
-  b.ii_ipw = (int)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)R * max_nrep + slots - 1) / slots));
-  b.ie_nbx = (int)std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(1, (max_nrep + 3) / 4), slots / 4 / std::max(R, 1)));
+  b.kw = tp[SRBE_TUNE_WAVES];
+  b.unroll = tp[SRBE_TUNE_UNROLL];
+  b.ii_ipw = tp[SRBE_TUNE_II_IONS];
+  b.ie_nbx = tp[SRBE_TUNE_IE_BLOCKS];
+  b.esplit = tp[SRBE_TUNE_ELE_SPLIT];
   b.ion_xyz = a.ion_xyz;
   b.ion_q = a.ion_q;
   b.dpsi = a.dpsi;
@@ -1003,6 +1073,149 @@ void srbe_graph_destroy(srbe_graph* gr) {
   if (gr->off_dev) (void)hipFree(gr->off_dev);
   if (gr->step_dev) (void)hipFree(gr->step_dev);
   delete gr;
+}
+
+int srbe_get_tuning(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                    int32_t* params_out) {
+  if (!h || !params_out) return h ? set_err(h, SRBE_EINVAL, "params_out is NULL") : SRBE_EINVAL;
+  int64_t max_nrep = 0;
+  const int rc = check_shape(h, precision, n_rep, ion_offsets, max_nrep);
+  if (rc != SRBE_OK) return rc;
+  int p[SRBE_TUNE_NPARAM];
+  tuning_for(h, precision, n_rep, max_nrep, p);
+  for (int u = 0; u < SRBE_TUNE_NPARAM; ++u) params_out[u] = p[u];
+  return SRBE_OK;
+}
+
+int srbe_set_tuning(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                    const int32_t* params) {
+  if (!h) return SRBE_EINVAL;
+  int64_t max_nrep = 0;
+  const int rc = check_shape(h, precision, n_rep, ion_offsets, max_nrep);
+  if (rc != SRBE_OK) return rc;
+  if (!params) {
+    forget_tuning(h, precision, n_rep, max_nrep);
+    return SRBE_OK;
+  }
+  int p[SRBE_TUNE_NPARAM];
+  for (int u = 0; u < SRBE_TUNE_NPARAM; ++u) p[u] = params[u];
+  if (const char* why = bad_tuning(p)) return set_err(h, SRBE_EINVAL, why);
+  store_tuning(h, precision, n_rep, max_nrep, p);
+  return SRBE_OK;
+}
+
+int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets, const double* ion_xyz,
+              const double* ion_q, const double* dpsi, const uint64_t* seed, int32_t iters, int32_t* params_out,
+              double* ms_out, void* stream) {
+  if (!h) return SRBE_EINVAL;
+  if (iters < 1) return set_err(h, SRBE_EINVAL, "iters must be >= 1");
+  int64_t max_nrep = 0;
+  int rc = check_shape(h, precision, n_rep, ion_offsets, max_nrep);
+  if (rc != SRBE_OK) return rc;
+  if (!h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: nothing to tune against");
+  const int64_t N = ion_offsets[n_rep];
+  const size_t n = (size_t)h->n_ele;
+  hipStream_t s = (hipStream_t)stream;
+  // the step's outputs, and two events (allocated here; freed on every path)
+  double* Q = nullptr;
+  double* F = nullptr;
+  double* psi = nullptr;
+  double* E = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&] {
+    for (double* ptr : {Q, F, psi, E})
+      if (ptr) (void)hipFree(ptr);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  hipError_t e = hipMalloc(&Q, std::max<size_t>(1, (size_t)n_rep * n) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&F, std::max<int64_t>(1, 3 * N) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&psi, (size_t)n_rep * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&E, (size_t)n_rep * sizeof(double));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    cleanup();
+    return set_err(h, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, hipGetErrorString(e));
+  }
+  // the entry stored before the call, restored if timing fails
+  bool had = false;
+  int before[SRBE_TUNE_NPARAM];
+  for (const auto& t : h->tuned)
+    if (t.precision == precision && t.n_rep == n_rep && t.max_nrep == max_nrep) {
+      had = true;
+      std::memcpy(before, t.p, sizeof(before));
+    }
+  // ms per captured step with parameters p
+  auto time_params = [&](const int* p, double& ms) -> int {
+    store_tuning(h, precision, n_rep, max_nrep, p);
+    srbe_graph* gr = nullptr;
+    int r = srbe_graph_create(h, precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, 0, nullptr, nullptr, Q,
+                              F, nullptr, psi, E, nullptr, &gr);
+    if (r != SRBE_OK) return r;
+    hipError_t err = hipSuccess;
+    for (int w = 0; w < 3 && err == hipSuccess; ++w) err = hipGraphLaunch(gr->exec, s);
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int w = 0; w < iters && err == hipSuccess; ++w) err = hipGraphLaunch(gr->exec, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    srbe_graph_destroy(gr);
+    if (err != hipSuccess) return set_err(h, SRBE_EHIP, hipGetErrorString(err));
+    r = srbe_sync_status(h);
+    ms = (double)t / iters;
+    return r;
+  };
+  int cur[SRBE_TUNE_NPARAM];
+  default_tuning(h, precision, n_rep, max_nrep, cur);
+  // candidates per parameter, tried in this order
+  const int ii = cur[SRBE_TUNE_II_IONS], ie = cur[SRBE_TUNE_IE_BLOCKS];
+  std::vector<std::vector<int>> cand(SRBE_TUNE_NPARAM);
+  cand[SRBE_TUNE_SF_BLOCKS] = {256, 512, 1024, 2048, 4096};
+  cand[SRBE_TUNE_WAVES] = {2, 4, 8};
+  cand[SRBE_TUNE_UNROLL] = {2, 4, 8};
+  cand[SRBE_TUNE_II_IONS] = {std::max(1, ii / 2), std::max(1, (2 * ii) / 3), ii, (3 * ii + 1) / 2, 2 * ii};
+  cand[SRBE_TUNE_IE_BLOCKS] = {std::max(1, ie / 2), ie, (3 * ie + 1) / 2, 2 * ie};
+  cand[SRBE_TUNE_ELE_SPLIT] = {1, 2, 4};
+  if (precision == SRBE_FP64) cand[SRBE_TUNE_UNROLL] = {4};  // no FP64 unroll parameter
+  double best = 0.0, ms_default = 0.0;
+  rc = time_params(cur, best);
+  ms_default = best;
+  for (int k = 0; k < SRBE_TUNE_NPARAM && rc == SRBE_OK; ++k) {
+    std::sort(cand[k].begin(), cand[k].end());
+    cand[k].erase(std::unique(cand[k].begin(), cand[k].end()), cand[k].end());
+    const int keep = cur[k];
+    for (int v : cand[k]) {
+      if (v == keep) continue;
+      int trial[SRBE_TUNE_NPARAM];
+      std::memcpy(trial, cur, sizeof(trial));
+      trial[k] = v;
+      if (bad_tuning(trial)) continue;
+      double ms = 0.0;
+      if ((rc = time_params(trial, ms)) != SRBE_OK) break;
+      if (ms < best) {
+        best = ms;
+        cur[k] = v;
+      }
+    }
+  }
+  cleanup();
+  if (rc != SRBE_OK) {
+    if (had)
+      store_tuning(h, precision, n_rep, max_nrep, before);
+    else
+      forget_tuning(h, precision, n_rep, max_nrep);
+    return rc;
+  }
+  store_tuning(h, precision, n_rep, max_nrep, cur);
+  if (params_out)
+    for (int u = 0; u < SRBE_TUNE_NPARAM; ++u) params_out[u] = cur[u];
+  if (ms_out) {
+    ms_out[0] = ms_default;
+    ms_out[1] = best;
+  }
+  return SRBE_OK;
 }
 
 const char* srbe_phase_name(int32_t phase) {

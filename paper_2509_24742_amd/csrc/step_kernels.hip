@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf,
 
 void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
   const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ion * b.R : 0;
-  const int units = b.n_ele_chunks * b.R, esplit = ele_split(units);
+  const int units = b.n_ele_chunks * b.R, esplit = b.esplit;
   const int nre = (parts & STAGE_REAL && g.n_ele > 0) ? (units * esplit + 3) / 4 : 0;
   if (nsf + nre == 0) return;
   if (fp32)
@@ -1019,14 +1019,34 @@ void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hi
 }
 
 // The force and potential passes: 64 particles per block, the mode list split
-// into four quarters, one per wave (so each wave still walks a uniform mode list:
-// the wave index is made explicitly uniform so that the mode records are read
-// with scalar loads), and the four partial results added in wave order through LDS.
-__device__ __forceinline__ void quarter(int K, int& lo, int& hi) {
-  const int q = (K + 3) / 4;
+// into W parts, one per wave (so each wave still walks a uniform mode list: the
+// wave index is made explicitly uniform so that the mode records are read with
+// scalar loads), and the W partial results added in wave order through LDS.  W and
+// the unroll depth U of the FP32 mode loops are chosen per workload by the tuner.
+template <int W>
+__device__ __forceinline__ void mode_part(int K, int& lo, int& hi) {
+  const int q = (K + W - 1) / W;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   lo = min(K, w * q);
   hi = min(K, lo + q);
+}
+
+// Runs fn(W, U) with W in {2, 4, 8} waves per block and U in {2, 4, 8} as
+// compile-time constants (other values fall back to 4).
+template <typename Fn>
+void with_wu(int w, int u, Fn&& fn) {
+  auto pick_u = [&](auto W) {
+    switch (u) {
+      case 2: fn(W, std::integral_constant<int, 2>{}); break;
+      case 8: fn(W, std::integral_constant<int, 8>{}); break;
+      default: fn(W, std::integral_constant<int, 4>{}); break;
+    }
+  };
+  switch (w) {
+    case 2: pick_u(std::integral_constant<int, 2>{}); break;
+    case 8: pick_u(std::integral_constant<int, 8>{}); break;
+    default: pick_u(std::integral_constant<int, 4>{}); break;
+  }
 }
 
 // ============================================================ electrode potential b*
@@ -1035,15 +1055,18 @@ __device__ __forceinline__ void quarter(int K, int& lo, int& hi) {
 //        - bN_j                                     (real space)
 // and V_j = b*_j + dpsi d_j, the right-hand side of the charge solve (rows of
 // ldcp(n) doubles per replica for the GEMM below).
-__device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double acc_quarter, double (*sh)[64],
+template <int W>
+__device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double acc_part, double (*sh)[64],
                                              const double* ele_xyz, const double* ele_d, const double* scal,
                                              const double* dpsi, const double* bN, double* bstar, double* V) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  sh[w][lane] = acc_quarter;
+  sh[w][lane] = acc_part;
   __syncthreads();
   if (w == 0 && j >= g.n_ele && j < ldcp(g.n_ele)) V[(size_t)r * ldcp(g.n_ele) + j] = 0.0;  // padding
   if (w == 0 && j < g.n_ele) {
-    const double acc = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+    double acc = sh[0][lane];
+#pragma unroll
+    for (int u = 1; u < W; ++u) acc += sh[u][lane];
     const int n = g.n_ele;
     const double Z = ele_xyz[2 * n + j];
     const size_t idx = (size_t)r * n + j;
@@ -1053,18 +1076,19 @@ __device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double
   }
 }
 
-__global__ __launch_bounds__(256) void k_elepot64(Geom g, const double* __restrict__ ele_xyz,
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_elepot64(Geom g, const double* __restrict__ ele_xyz,
                                                   const double4* __restrict__ ele_d4,
                                                   const double* __restrict__ ele_d, const int4* __restrict__ modes,
                                                   const double2* __restrict__ coef, const double* __restrict__ scal,
                                                   const double* __restrict__ dpsi, const double* __restrict__ bN,
                                                   double* __restrict__ bstar, double* __restrict__ V) {
-  __shared__ double sh[4][64];
+  __shared__ double sh[W][64];
   const int r = blockIdx.y;
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
   const double4 p = j < g.n_ele ? ele_d4[j] : make_double4(0, 0, 0, 0);
   int lo, hi;
-  quarter(g.K, lo, hi);
+  mode_part<W>(g.K, lo, hi);
   double acc = 0.0;
   const int4* mr = modes + (size_t)r * g.K;
   const double2* cr = coef + (size_t)r * g.K;
@@ -1077,29 +1101,30 @@ __global__ __launch_bounds__(256) void k_elepot64(Geom g, const double* __restri
     const double2 c = cr[k];
     acc = fma(c.x, cs, fma(c.y, sn, acc));
   }
-  elepot_write(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
+  elepot_write<W>(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
 }
 
-__global__ __launch_bounds__(256) void k_elepot32(Geom g, const uint4* __restrict__ ele_fx,
+template <int W, int U>
+__global__ __launch_bounds__(64 * W) void k_elepot32(Geom g, const uint4* __restrict__ ele_fx,
                                                   const double* __restrict__ ele_xyz, const double* __restrict__ ele_d,
                                                   const ModeRec32* __restrict__ rec, const double* __restrict__ scal,
                                                   const double* __restrict__ dpsi, const double* __restrict__ bN,
                                                   double* __restrict__ bstar, double* __restrict__ V) {
-  __shared__ double sh[4][64];
+  __shared__ double sh[W][64];
   const int r = blockIdx.y;
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
   const uint4 pe = j < g.n_ele ? ele_fx[j] : make_uint4(0, 0, 0, 0);
   int lo, hi;
-  quarter(g.K, lo, hi);
+  mode_part<W>(g.K, lo, hi);
   const ModeRec32* mr = rec + (size_t)r * g.K;
   double acc = 0.0;
   for (int kb = lo; kb < hi; kb += 64) {
     const int ke_ = min(hi, kb + 64);
     float a = 0.f;
     int k = kb;
-    for (; k + 4 <= ke_; k += 4) {
+    for (; k + U <= ke_; k += U) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const ModeRec32 m = mr[k + u];
         const uint32_t ph = (uint32_t)m.mx * pe.x + (uint32_t)m.my * pe.y + (uint32_t)m.mz * pe.z;
         const float x = (float)(int32_t)ph * 0x1.0p-32f;
@@ -1116,17 +1141,20 @@ __global__ __launch_bounds__(256) void k_elepot32(Geom g, const uint4* __restric
     }
     acc += (double)a;
   }
-  elepot_write(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
+  elepot_write<W>(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
 }
 
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
-  dim3 grid(cdiv64(g.n_ele, 64), b.R);
-  if (fp32)
-    hipLaunchKernelGGL(k_elepot32, grid, dim3(256), 0, s, g, b.ele_fx, b.ele_xyz, b.ele_d, b.rec, b.scal, b.dpsi,
-                       b.bN, b.bstar, b.V);
-  else
-    hipLaunchKernelGGL(k_elepot64, grid, dim3(256), 0, s, g, b.ele_xyz, b.ele_d4, b.ele_d, b.modes, b.coef, b.scal,
-                       b.dpsi, b.bN, b.bstar, b.V);
+  const dim3 grid(cdiv64(g.n_ele, 64), b.R);
+  with_wu(b.kw, fp32 ? b.unroll : 4, [&](auto W, auto U) {
+    constexpr int w = decltype(W)::value, u = decltype(U)::value;
+    if (fp32)
+      hipLaunchKernelGGL((k_elepot32<w, u>), grid, dim3(64 * w), 0, s, g, b.ele_fx, b.ele_xyz, b.ele_d, b.rec, b.scal,
+                         b.dpsi, b.bN, b.bstar, b.V);
+    else if constexpr (u == 4)  // the FP64 loop has no unroll parameter
+      hipLaunchKernelGGL((k_elepot64<w>), grid, dim3(64 * w), 0, s, g, b.ele_xyz, b.ele_d4, b.ele_d, b.modes, b.coef,
+                         b.scal, b.dpsi, b.bN, b.bstar, b.V);
+  });
 }
 
 // ============================================================ charge solve
@@ -1319,6 +1347,7 @@ void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32,
 // F_i = -q_i sum_k k Im(coef_k exp(-i k.r_i))   (Eq. (25), coef = w (S1 + S2))
 //       - (4 pi ke / V) q_i M_z e_z             (slab force, M_z = sum q z + sum Q Z)
 // The real-space sums are added by the step's last launch (k_final).
+template <int W>
 __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, bool live, double qi, double gx,
                                                double gy, double gz, double (*sh)[3][64], const double* scal,
                                                const double* rsum, int64_t N, double* F) {
@@ -1330,7 +1359,11 @@ __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, 
   if (w == 0 && live) {
     double gsum[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) gsum[d] = ((sh[0][d][lane] + sh[1][d][lane]) + sh[2][d][lane]) + sh[3][d][lane];
+    for (int d = 0; d < 3; ++d) {
+      gsum[d] = sh[0][d][lane];
+#pragma unroll
+      for (int u = 1; u < W; ++u) gsum[d] += sh[u][d][lane];
+    }
     F[i] = -qi * gsum[0];
     F[N + i] = -qi * gsum[1];
     F[2 * N + i] = -qi * gsum[2] - (4.0 * M_PI * g.ke / g.V) * qi * (scal[4 * r + 2] + rsum_total(rsum, r, 0));
@@ -1338,6 +1371,7 @@ __device__ __forceinline__ void ionforce_write(const Geom& g, int r, int64_t i, 
 }
 
 // Block (bx, r): ions 64 bx .. 64 bx + 63 of replica r.
+template <int W>
 __device__ __forceinline__ void ionforce64_block(const Geom& g, const StepBufs& b, int bx, int r) {
   const int64_t* __restrict__ off = b.off;
   const double4* __restrict__ ion_d4 = b.ion_d4;
@@ -1347,14 +1381,14 @@ __device__ __forceinline__ void ionforce64_block(const Geom& g, const StepBufs& 
   const double* __restrict__ scal = b.scal;
   const double* __restrict__ rsum = b.rsum;
   double* __restrict__ F = b.F_out;
-  __shared__ double sh[4][3][64];
+  __shared__ double sh[W][3][64];
   const int64_t b0 = off[r], b1 = off[r + 1];
   const int64_t i = b0 + (int64_t)bx * 64 + (threadIdx.x & 63);
   if (b0 + (int64_t)bx * 64 >= b1) return;  // whole block past this replica's ions
   const bool live = i < b1;
   const double4 p = live ? ion_d4[i] : make_double4(0, 0, 0, 0);
   int lo, hi;
-  quarter(g.K, lo, hi);
+  mode_part<W>(g.K, lo, hi);
   double gx = 0.0, gy = 0.0, gz = 0.0;
   const int4* mr = modes + (size_t)r * g.K;
   const double2* cr = coef + (size_t)r * g.K;
@@ -1370,9 +1404,10 @@ __device__ __forceinline__ void ionforce64_block(const Geom& g, const StepBufs& 
     gy = fma(TWO_PI * (double)m.y * g.invLy, im, gy);
     gz = fma(TWO_PI * (double)m.z * g.invLz, im, gz);
   }
-  ionforce_write(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, N, F);
+  ionforce_write<W>(g, r, i, live, p.w, gx, gy, gz, sh, scal, rsum, N, F);
 }
 
+template <int W, int U>
 __device__ __forceinline__ void ionforce32_block(const Geom& g, const StepBufs& b, int bx, int r) {
   const int64_t* __restrict__ off = b.off;
   const uint4* __restrict__ ion_fx = b.ion_fx;
@@ -1381,17 +1416,17 @@ __device__ __forceinline__ void ionforce32_block(const Geom& g, const StepBufs& 
   const double* __restrict__ scal = b.scal;
   const double* __restrict__ rsum = b.rsum;
   double* __restrict__ F = b.F_out;
-  __shared__ double sh[4][3][64];
+  __shared__ double sh[W][3][64];
   const int64_t b0 = off[r], b1 = off[r + 1];
   const int64_t i = b0 + (int64_t)bx * 64 + (threadIdx.x & 63);
   if (b0 + (int64_t)bx * 64 >= b1) return;  // whole block past this replica's ions
   const bool live = i < b1;
   const uint4 pi_ = live ? ion_fx[i] : make_uint4(0, 0, 0, 0);
   int lo, hi;
-  quarter(g.K, lo, hi);
+  mode_part<W>(g.K, lo, hi);
   const ModeRec32* mr = rec + (size_t)r * g.K;
   double gx = 0.0, gy = 0.0, gz = 0.0;
-  // deterministic modes k = (0, 0, kz) in this quarter: only the z component
+  // deterministic modes k = (0, 0, kz) in this part: only the z component
   {
     float az = 0.f;
     for (int k = lo; k < min(hi, g.M); ++k) {
@@ -1407,9 +1442,9 @@ __device__ __forceinline__ void ionforce32_block(const Geom& g, const StepBufs& 
     const int ke_ = min(hi, kb + 64);
     float ax = 0.f, ay = 0.f, az = 0.f;
     int k = kb;
-    for (; k + 4 <= ke_; k += 4) {
+    for (; k + U <= ke_; k += U) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         const ModeRec32 m = mr[k + u];
         const uint32_t ph = (uint32_t)m.mx * pi_.x + (uint32_t)m.my * pi_.y + (uint32_t)m.mz * pi_.z;
         const float x = (float)(int32_t)ph * 0x1.0p-32f;
@@ -1432,7 +1467,7 @@ __device__ __forceinline__ void ionforce32_block(const Geom& g, const StepBufs& 
     gy += (double)ay;
     gz += (double)az;
   }
-  ionforce_write(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, N, F);
+  ionforce_write<W>(g, r, i, live, (double)__uint_as_float(pi_.w), gx, gy, gz, sh, scal, rsum, N, F);
 }
 
 
@@ -1833,13 +1868,13 @@ __global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, 
     sf_block<FP32, false>(g, b, bid - nie);
 }
 
-template <bool FP32>
-__global__ __launch_bounds__(256) void k_ion_force(Geom g, StepBufs b, int ftiles) {
+template <bool FP32, int W, int U>
+__global__ __launch_bounds__(64 * W) void k_ion_force(Geom g, StepBufs b, int ftiles) {
   const int u = blockIdx.x;
   if constexpr (FP32)
-    ionforce32_block(g, b, u % ftiles, u / ftiles);
+    ionforce32_block<W, U>(g, b, u % ftiles, u / ftiles);
   else
-    ionforce64_block(g, b, u % ftiles, u / ftiles);
+    ionforce64_block<W>(g, b, u % ftiles, u / ftiles);
 }
 
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
@@ -1855,10 +1890,13 @@ void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hip
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   const int ftiles = cdiv64(b.max_nrep, 64);
-  if (fp32)
-    hipLaunchKernelGGL(k_ion_force<true>, dim3(ftiles * b.R), dim3(256), 0, s, g, b, ftiles);
-  else
-    hipLaunchKernelGGL(k_ion_force<false>, dim3(ftiles * b.R), dim3(256), 0, s, g, b, ftiles);
+  with_wu(b.kw, fp32 ? b.unroll : 4, [&](auto W, auto U) {
+    constexpr int w = decltype(W)::value, u = decltype(U)::value;
+    if (fp32)
+      hipLaunchKernelGGL((k_ion_force<true, w, u>), dim3(ftiles * b.R), dim3(64 * w), 0, s, g, b, ftiles);
+    else if constexpr (u == 4)  // the FP64 loop has no unroll parameter
+      hipLaunchKernelGGL((k_ion_force<false, w, 4>), dim3(ftiles * b.R), dim3(64 * w), 0, s, g, b, ftiles);
+  });
 }
 
 // z-extent (min, max of Z) of the electrodes of every cell; empty cells get an
