@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
     ap.add_argument("--no-tune", action="store_true",
                     help="time with the default launch parameters instead of tuning them first (srbe_tune)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of launch-parameter choices: applied where it has the workload, else tuned "
+                         "and added (lets a profiled run use the choices of an unprofiled one)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -190,13 +193,12 @@ def main():
         for name, prec, offs, x, qq, dp, sd in [("fp32_batch", srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds),
                                                 ("fp64_single_cell", srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi1, seeds1),
                                                 ("fp32_single_cell", srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi1, seeds1)]:
-            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, iters=30)
+            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, iters=30, cache=args.tune_cache)
             tuning[name] = {"params": dict(zip(srbe_amd.SRBE_TUNE_NAMES, t["params"])),
-                            "ms_default": t["ms_default"], "ms_tuned": t["ms_tuned"]}
+                            "ms_default": t["ms_default"], "ms_tuned": t["ms_tuned"], "from_cache": t["cached"]}
         tuning["seconds"] = time.time() - t0
-        log(f"tuned launch parameters in {tuning['seconds']:.2f} s: "
-            f"{tuning['fp32_batch']['params']} ({tuning['fp32_batch']['ms_default'] * 1e3:.1f} -> "
-            f"{tuning['fp32_batch']['ms_tuned'] * 1e3:.1f} us/step)")
+        log(f"launch parameters in {tuning['seconds']:.2f} s: {tuning['fp32_batch']['params']}"
+            f"{' (from the cache)' if tuning['fp32_batch']['from_cache'] else ''}")
 
     # ---- headline: FP32, all replicas in one step, replayed as a captured graph
     ms_fp32 = timed_graph(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
