@@ -209,6 +209,8 @@ const char* srbe_phase_name(int32_t phase);
  *   SRBE_TUNE_IE_BLOCKS   ion-electrode real-space pass: blocks per replica (1 .. 65536)
  *   SRBE_TUNE_ELE_SPLIT   electrode-potential real-space pass: waves per chunk of 64
  *                         electrodes (1, 2 or 4)
+ *   SRBE_TUNE_GEMM_SPLIT  charge-solve GEMM (Eqs. (9)-(11)): ranges the contraction is
+ *                         split into, each a block per output tile (1 .. 16)
  * A step (srbe_step, srbe_graph_create) uses the parameters stored in the handle
  * for its shape -- precision, n_rep and the largest replica's ion count -- else
  * defaults derived from the device's compute-unit count.  Results depend on the
@@ -238,7 +240,8 @@ const char* srbe_phase_name(int32_t phase);
 #define SRBE_TUNE_II_IONS 3
 #define SRBE_TUNE_IE_BLOCKS 4
 #define SRBE_TUNE_ELE_SPLIT 5
-#define SRBE_TUNE_NPARAM 6
+#define SRBE_TUNE_GEMM_SPLIT 6
+#define SRBE_TUNE_NPARAM 7
 int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets, const double* ion_xyz,
               const double* ion_q, const double* dpsi, const uint64_t* seed, int32_t iters, int32_t* params_out,
               double* ms_out, void* stream);

@@ -56,6 +56,9 @@ constexpr int kScanPad = 192;
 constexpr int kRealWavesPerSimd32 = 7;
 constexpr int kRealWavesPerSimd64 = 3;
 constexpr int kRsumParts = 16;
+// Most k-ranges the charge-solve GEMM may be split into (the copy-out adds at most
+// this many partials, all requested at once).
+constexpr int kMaxGemmSplit = 16;
 constexpr int kRsumStride = 4 * kRsumParts;
 
 // Cell of a position (x, y wrapped by the caller into fractions sx, sy in [0,1)).

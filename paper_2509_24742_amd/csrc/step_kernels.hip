@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(256) void k_cp_gemm(Geom g, StepBufs b, const doubl
 // (at most 16, at least 1).
 int cp_gemm_ksplit(int n_ele, int R) {
   const int tiles = ((n_ele + 1 + 63) / 64) * ((R + 63) / 64);
-  return std::max(1, std::min(16, 256 / std::max(tiles, 1)));
+  return std::max(1, std::min(kMaxGemmSplit, 256 / std::max(tiles, 1)));
 }
 
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s) {
@@ -1285,15 +1285,15 @@ __device__ __forceinline__ double rsum_total(const double* rsum, int r, int q) {
 }
 
 // Q_j of replica r from the GEMM partials, added in k-range order.  All partials are
-// requested before the first add (ksplit <= 16), so that one thread waits out one
-// memory latency rather than ksplit of them.
+// requested before the first add (ksplit <= kMaxGemmSplit), so that one thread waits
+// out one memory latency rather than ksplit of them.
 __device__ __forceinline__ double solved_q(const double* __restrict__ Qext, int ksplit, int R, int r, int n, int j) {
-  double p[16];
+  double p[kMaxGemmSplit];
 #pragma unroll
-  for (int h = 0; h < 16; ++h) p[h] = h < ksplit ? Qext[((size_t)h * R + r) * (n + 1) + j] : 0.0;
+  for (int h = 0; h < kMaxGemmSplit; ++h) p[h] = h < ksplit ? Qext[((size_t)h * R + r) * (n + 1) + j] : 0.0;
   double q = p[0];
 #pragma unroll
-  for (int h = 1; h < 16; ++h)
+  for (int h = 1; h < kMaxGemmSplit; ++h)
     if (h < ksplit) q += p[h];
   return q;
 }
