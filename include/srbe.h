@@ -211,6 +211,9 @@ const char* srbe_phase_name(int32_t phase);
  *                         electrodes (1, 2 or 4)
  *   SRBE_TUNE_GEMM_SPLIT  charge-solve GEMM (Eqs. (9)-(11)): ranges the contraction is
  *                         split into, each a block per output tile (1 .. 16)
+ *   SRBE_TUNE_GEMM_DEPTH  its contraction block, in units of 16 indices (1 or 2): the
+ *                         loads of one block are in flight while the previous one
+ *                         is multiplied
  * A step (srbe_step, srbe_graph_create) uses the parameters stored in the handle
  * for its shape -- precision, n_rep and the largest replica's ion count -- else
  * defaults derived from the device's compute-unit count.  Results depend on the
@@ -241,7 +244,8 @@ const char* srbe_phase_name(int32_t phase);
 #define SRBE_TUNE_IE_BLOCKS 4
 #define SRBE_TUNE_ELE_SPLIT 5
 #define SRBE_TUNE_GEMM_SPLIT 6
-#define SRBE_TUNE_NPARAM 7
+#define SRBE_TUNE_GEMM_DEPTH 7
+#define SRBE_TUNE_NPARAM 8
 int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets, const double* ion_xyz,
               const double* ion_q, const double* dpsi, const uint64_t* seed, int32_t iters, int32_t* params_out,
               double* ms_out, void* stream);

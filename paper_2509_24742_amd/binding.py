@@ -248,7 +248,8 @@ def srbe_graph_destroy(gr):
     lib().srbe_graph_destroy(gr)
 
 
-SRBE_TUNE_NAMES = ["sf_blocks", "waves", "unroll", "ii_ions", "ie_blocks", "ele_split", "gemm_split"]
+SRBE_TUNE_NAMES = ["sf_blocks", "waves", "unroll", "ii_ions", "ie_blocks", "ele_split", "gemm_split",
+                   "gemm_depth"]
 SRBE_TUNE_NPARAM = len(SRBE_TUNE_NAMES)
 
 

@@ -34,8 +34,9 @@ struct Geom {
 };
 
 // Leading dimension of the charge-solve operands (S_ext rows, right-hand sides):
-// n rounded up to a multiple of 16 doubles, the padding held at zero.
-__host__ __device__ inline int ldcp(int n) { return (n + 15) & ~15; }
+// n rounded up to a multiple of 32 doubles (the GEMM's widest contraction block),
+// the padding held at zero.
+__host__ __device__ inline int ldcp(int n) { return (n + 31) & ~31; }
 
 constexpr int kMaxBinParticles = 8192;  // particles per replica the one-block cell sort handles
 constexpr int kMaxCells = 2048;

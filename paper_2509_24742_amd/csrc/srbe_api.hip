@@ -426,6 +426,7 @@ void default_tuning(const srbe_system* h, int precision, int R, int64_t max_nrep
       1, std::min<int64_t>(std::max<int64_t>(1, (max_nrep + 3) / 4), slots / 4 / std::max(R, 1)));
   p[SRBE_TUNE_ELE_SPLIT] = ele_split(h->n_ele_chunks * R);
   p[SRBE_TUNE_GEMM_SPLIT] = cp_gemm_ksplit(h->n_ele, R);
+  p[SRBE_TUNE_GEMM_DEPTH] = 1;
 }
 
 // The stored parameters of this shape, else the defaults.
@@ -447,6 +448,7 @@ const char* bad_tuning(const int* p) {
   if (p[SRBE_TUNE_ELE_SPLIT] != 1 && p[SRBE_TUNE_ELE_SPLIT] != 2 && p[SRBE_TUNE_ELE_SPLIT] != 4)
     return "electrode chunk split not 1, 2 or 4";
   if (p[SRBE_TUNE_GEMM_SPLIT] < 1 || p[SRBE_TUNE_GEMM_SPLIT] > kMaxGemmSplit) return "GEMM split outside [1, 16]";
+  if (p[SRBE_TUNE_GEMM_DEPTH] != 1 && p[SRBE_TUNE_GEMM_DEPTH] != 2) return "GEMM depth not 1 or 2";
   return nullptr;
 }
 
@@ -488,6 +490,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.nchunk_ion = chunks_for(max_nrep);
   b.nchunk_ele = chunks_for(n);
   b.ksplit = tp[SRBE_TUNE_GEMM_SPLIT];
+  b.gemm_depth = tp[SRBE_TUNE_GEMM_DEPTH];
   b.kw = tp[SRBE_TUNE_WAVES];
   b.unroll = tp[SRBE_TUNE_UNROLL];
   b.ii_ipw = tp[SRBE_TUNE_II_IONS];
@@ -1182,6 +1185,7 @@ int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   cand[SRBE_TUNE_ELE_SPLIT] = {1, 2, 4};
   const int ks = cur[SRBE_TUNE_GEMM_SPLIT];
   cand[SRBE_TUNE_GEMM_SPLIT] = {std::max(1, ks / 2), ks, std::min(kMaxGemmSplit, 2 * ks), kMaxGemmSplit};
+  cand[SRBE_TUNE_GEMM_DEPTH] = {1, 2};
   if (precision == SRBE_FP64) cand[SRBE_TUNE_UNROLL] = {4};  // no FP64 unroll parameter
   double best = 0.0, ms_default = 0.0;
   rc = time_params(cur, best);

@@ -1160,54 +1160,64 @@ void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_
 // ============================================================ charge solve
 // [Q; psibar] = S_ext V (Eqs. (9)-(11)).  S_ext: (n+1) rows of ld = ldcp(n) doubles
 // (row-major; the n x n block is symmetric); V: one row of ld doubles per replica;
-// both zero-padded to ld, a multiple of 16.  A block computes a 64-row x 64-replica
-// tile over one k-range: per 16-k block the two 64 x 16 operand tiles are loaded
-// by all 256 threads (32-byte coalesced loads) into LDS (double buffered, rows
-// padded to 18 doubles against bank conflicts), the next block's tiles travelling
-// from HBM while the current one is multiplied.  Each wave owns 16 rows: FP64 MFMA
+// both zero-padded to ld, a multiple of 32.  A block computes a 64-row x 64-replica
+// tile over one k-range: per KB-k block (KB = 16 or 32, chosen by the tuner) the two
+// 64 x KB operand tiles are loaded by all 256 threads (coalesced 16-byte loads,
+// KB / 4 doubles per thread and operand) into LDS (double buffered, rows padded by
+// 2 doubles against bank conflicts), the next block's tiles travelling from HBM
+// while the current one is multiplied: the wider block keeps twice the bytes in
+// flight for twice the multiply time.  Each wave owns 16 rows: FP64 MFMA
 // v_mfma_f64_16x16x4f64, lane l supplying A[l%16][k(l)] and B[k(l)][l%16], the
 // result register v of lane l being row l/16 + 4 v, column l%16.  The contraction
 // index k(l) may be any assignment of the 4 k values to the 4 lane groups as long
 // as A and B use the same one: here a lane holds 4 consecutive k of its row (two
-// 16-byte LDS reads) and MFMA step u takes the u-th of them.  Rows past n and
-// replicas past R read row 0 / replica 0 (valid memory) and are not stored.  The
-// k range is split into ksplit ranges (grid z), sized so that the grid fits the
+// 16-byte LDS reads) per 16 k and MFMA step u takes the u-th of them.  Rows past n
+// and replicas past R read row 0 / replica 0 (valid memory) and are not stored.
+// The k range is split into ksplit ranges (grid z), sized so that the grid fits the
 // CUs in one pass; each range writes its own partial, summed in order after the
 // GEMM.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kGemmLd = 18;  // LDS row stride of an operand tile (doubles)
+typedef double f64x2 __attribute__((ext_vector_type(2)));  // register staging (an array of
+                                                             // HIP's double2 is kept in scratch)
 
-constexpr int kGemmLdsBytes = 2 * 2 * 64 * kGemmLd * (int)sizeof(double);
+template <int KB>
+constexpr int gemm_ld() { return KB + 2; }  // LDS row stride of an operand tile (doubles)
+template <int KB>
+constexpr int gemm_lds_bytes() { return 2 * 2 * 64 * gemm_ld<KB>() * (int)sizeof(double); }
 
-// Tile (rt, cg) of k-range h of ks.  lds_raw: kGemmLdsBytes bytes,
-// [buffer][A or B][64 rows x 16 k, padded].
+// Tile (rt, cg) of k-range h of ks.  lds_raw: gemm_lds_bytes<KB>() bytes,
+// [buffer][A or B][64 rows x KB k, padded].
+template <int KB>
 __device__ __forceinline__ void cp_gemm_tile(int n, int R, const double* __restrict__ S, const double* __restrict__ V,
                                              double* __restrict__ Qpart, int rt, int cg, int h, int ks, void* lds_raw) {
-  double(*lds)[2][64 * kGemmLd] = reinterpret_cast<double(*)[2][64 * kGemmLd]>(lds_raw);
+  constexpr int LD = gemm_ld<KB>(), NL = KB / 8;  // NL: 16-byte loads per thread and operand
+  double(*lds)[2][64 * LD] = reinterpret_cast<double(*)[2][64 * LD]>(lds_raw);
   const int ld = ldcp(n);
   const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int nb = ld / 16;
+  const int nb = ld / KB;
   const int kb0 = (int)((int64_t)nb * h / ks), kb1 = (int)((int64_t)nb * (h + 1) / ks);
-  // tile loader: thread t moves 4 consecutive k of row t/4 of each tile
-  const int lrow = t >> 2, lk = 4 * (t & 3);
+  // tile loader: thread t moves KB / 4 consecutive k of row t / 4 of each tile
+  const int lrow = t >> 2, lk = (KB / 4) * (t & 3);
   const int arow = rt * 64 + lrow, brow = cg * 64 + lrow;
   const double* Ag = S + (size_t)(arow <= n ? arow : 0) * ld + lk;
   const double* Bg = V + (size_t)(brow < R ? brow : 0) * ld + lk;
-  double2 ra0, ra1, rb0, rb1;
+  f64x2 ra[NL], rb[NL];
   auto gload = [&](int kb) {
-    const int k0 = kb * 16;
-    ra0 = *(const double2*)(Ag + k0);
-    ra1 = *(const double2*)(Ag + k0 + 2);
-    rb0 = *(const double2*)(Bg + k0);
-    rb1 = *(const double2*)(Bg + k0 + 2);
+    const int k0 = kb * KB;
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      ra[u] = *(const f64x2*)(Ag + k0 + 2 * u);
+      rb[u] = *(const f64x2*)(Bg + k0 + 2 * u);
+    }
   };
   auto lstore = [&](int buf) {
-    double* A = &lds[buf][0][lrow * kGemmLd + lk];
-    double* B = &lds[buf][1][lrow * kGemmLd + lk];
-    *(double2*)A = ra0;
-    *(double2*)(A + 2) = ra1;
-    *(double2*)B = rb0;
-    *(double2*)(B + 2) = rb1;
+    double* A = &lds[buf][0][lrow * LD + lk];
+    double* B = &lds[buf][1][lrow * LD + lk];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      *(f64x2*)(A + 2 * u) = ra[u];
+      *(f64x2*)(B + 2 * u) = rb[u];
+    }
   };
   f64x4 acc[4];
 #pragma unroll
@@ -1220,23 +1230,26 @@ __device__ __forceinline__ void cp_gemm_tile(int n, int R, const double* __restr
     for (int kb = kb0; kb < kb1; ++kb) {
       const int buf = (kb - kb0) & 1;
       if (kb + 1 < kb1) gload(kb + 1);
-      const double* A = &lds[buf][0][(w * 16 + (lane & 15)) * kGemmLd + kq];
-      const double2 a01 = *(const double2*)A, a23 = *(const double2*)(A + 2);
-      double2 b01[4], b23[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double* B = &lds[buf][1][(c * 16 + (lane & 15)) * kGemmLd + kq];
-        b01[c] = *(const double2*)B;
-        b23[c] = *(const double2*)(B + 2);
+      for (int sub = 0; sub < KB / 16; ++sub) {
+        const double* A = &lds[buf][0][(w * 16 + (lane & 15)) * LD + 16 * sub + kq];
+        const double2 a01 = *(const double2*)A, a23 = *(const double2*)(A + 2);
+        double2 b01[4], b23[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double* B = &lds[buf][1][(c * 16 + (lane & 15)) * LD + 16 * sub + kq];
+          b01[c] = *(const double2*)B;
+          b23[c] = *(const double2*)(B + 2);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01[c].x, acc[c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01[c].y, acc[c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23[c].x, acc[c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23[c].y, acc[c], 0, 0, 0);
       }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01[c].x, acc[c], 0, 0, 0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01[c].y, acc[c], 0, 0, 0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23[c].x, acc[c], 0, 0, 0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23[c].y, acc[c], 0, 0, 0);
       if (kb + 1 < kb1) lstore(buf ^ 1);
       __syncthreads();
     }
@@ -1252,10 +1265,11 @@ __device__ __forceinline__ void cp_gemm_tile(int n, int R, const double* __restr
 }
 
 // The GEMM's tiles, one block each (rt fastest, then cg, then the k-range).
+template <int KB>
 __global__ __launch_bounds__(256) void k_cp_gemm(Geom g, StepBufs b, const double* __restrict__ S, int nrt, int ncg) {
-  __shared__ __align__(16) unsigned char lds[kGemmLdsBytes];
+  __shared__ __align__(16) unsigned char lds[gemm_lds_bytes<KB>()];
   const int bid = blockIdx.x;
-  cp_gemm_tile(g.n_ele, b.R, S, b.V, b.Qext, bid % nrt, (bid / nrt) % ncg, bid / (nrt * ncg), b.ksplit, lds);
+  cp_gemm_tile<KB>(g.n_ele, b.R, S, b.V, b.Qext, bid % nrt, (bid / nrt) % ncg, bid / (nrt * ncg), b.ksplit, lds);
 }
 
 // k-ranges: as many as keep the grid within one block per CU of a 256-CU device
@@ -1269,7 +1283,10 @@ void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStr
   const int n = g.n_ele;
   const int nrt = (n + 1 + 63) / 64, ncg = (b.R + 63) / 64, ntile = nrt * ncg * b.ksplit;
   if (!Sext || ntile == 0) return;
-  hipLaunchKernelGGL(k_cp_gemm, dim3(ntile), dim3(256), 0, s, g, b, Sext, nrt, ncg);
+  if (b.gemm_depth == 2)
+    hipLaunchKernelGGL(k_cp_gemm<32>, dim3(ntile), dim3(256), 0, s, g, b, Sext, nrt, ncg);
+  else
+    hipLaunchKernelGGL(k_cp_gemm<16>, dim3(ntile), dim3(256), 0, s, g, b, Sext, nrt, ncg);
 }
 
 // ============================================================ after the charge solve

@@ -4,9 +4,10 @@ Every tunable launch shape must give the oracle's results: each setting below is
 on a three-replica batch of the tiny slab and compared with the FP64 oracle on the
 same sample, to the tolerances of test_gpu_step.py (FP64: 1e-11 relative max-norm;
 FP32: force relative RMS <= 1e-5, b and Q <= 3e-5).  The settings cover every value
-of the waves-per-block, unroll and electrode-split parameters, GEMM splits from 1 to
-the maximum of 16, and extreme chunk and real-space sizes (one ion per wave, one
-block per replica, more blocks than work).
+of the waves-per-block, unroll, electrode-split and GEMM-depth parameters, GEMM
+splits from 1 to the maximum of 16 (with 32-k blocks, more ranges than blocks for
+the tiny cell: some ranges are empty), and extreme chunk and real-space sizes (one
+ion per wave, one block per replica, more blocks than work).
 """
 
 import numpy as np
@@ -65,14 +66,14 @@ def check(batch, precision, off, out, label):
             assert rel_rms(b, ref["b"]) < 3e-5 and rel_rms(Q, ref["Q"]) < 3e-5, (label, r)
 
 
-# sf_blocks, waves, unroll, ii_ions, ie_blocks, ele_split, gemm_split
+# sf_blocks, waves, unroll, ii_ions, ie_blocks, ele_split, gemm_split, gemm_depth
 SETTINGS = [
-    [256, 2, 2, 1, 1, 1, 1],
-    [4096, 8, 8, 7, 3, 4, 16],
-    [512, 4, 8, 2, 9, 2, 3],
-    [2048, 2, 4, 40, 64, 1, 7],
-    [100, 8, 2, 3, 2, 2, 15],
-    [1, 4, 4, 1024, 65536, 4, 2],
+    [256, 2, 2, 1, 1, 1, 1, 2],
+    [4096, 8, 8, 7, 3, 4, 16, 2],
+    [512, 4, 8, 2, 9, 2, 3, 1],
+    [2048, 2, 4, 40, 64, 1, 7, 1],
+    [100, 8, 2, 3, 2, 2, 15, 2],
+    [1, 4, 4, 1024, 65536, 4, 2, 2],
 ]
 
 
@@ -97,7 +98,7 @@ def test_bad_settings_rejected(batch):
     off = batch["inputs"][0]
     h = batch["sys"].h
     base = list(binding.srbe_get_tuning(h, 1, off))
-    for k, v in [(0, 0), (1, 3), (1, 16), (2, 1), (2, 16), (3, 0), (4, 0), (5, 3), (5, 8), (6, 0), (6, 17)]:
+    for k, v in [(0, 0), (1, 3), (1, 16), (2, 1), (2, 16), (3, 0), (4, 0), (5, 3), (5, 8), (6, 0), (6, 17), (7, 0), (7, 3)]:
         bad = list(base)
         bad[k] = v
         with pytest.raises(binding.SrbeError) as ei:
