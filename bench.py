@@ -294,7 +294,8 @@ def main():
     if not args.no_cpu:
         o = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, want_kset=False)
         torch.cuda.synchronize()
-        acc = {"off": off, "F": o["F"].cpu().numpy(), "Q": o["Q"].cpu().numpy(), "E": o["E"].cpu().numpy()}
+        acc = {"off": off, "F": o["F"].cpu().numpy(), "Q": o["Q"].cpu().numpy(), "E": o["E"].cpu().numpy(),
+               "b": o["b"].cpu().numpy()}
         result.update(cpu_side(wb, wp, acc, R, sizes, n_ele, K))
     print(json.dumps(result), flush=True)
     sysm.close()
@@ -329,7 +330,7 @@ def count_pairs(wb, wp):
 def cpu_side(wb, wp, acc, R, sizes, n_ele, K):
     """The oracle's own throughput on a bounded sample, and the FP32 errors of those replicas.
 
-    acc: host copies of one FP32 GPU step at step index 0 (Q, F SoA, E, offsets).
+    acc: host copies of one FP32 GPU step at step index 0 (Q, F SoA, b, E, offsets).
     """
     from oracle import cp, ewald, sampler, srbe
 
@@ -358,17 +359,23 @@ def cpu_side(wb, wp, acc, R, sizes, n_ele, K):
     off = acc["off"]
     N = int(off[-1])
     F = acc["F"].reshape(3, N)
-    errF, errQ, errE = [], [], []
+    errF, errFmax, errb, errQ, errE, neut = [], [], [], [], [], []
     for r, ref in enumerate(refs):
         Fg = F[:, off[r]:off[r + 1]].T
         errF.append(np.linalg.norm(Fg - ref["F"]) / np.linalg.norm(ref["F"]))
+        # worst ion's force error against the RMS force magnitude
+        errFmax.append(np.max(np.linalg.norm(Fg - ref["F"], axis=1)) / np.sqrt(np.mean(np.sum(ref["F"] ** 2, axis=1))))
+        bg = acc["b"][r * n_ele:(r + 1) * n_ele]
+        errb.append(np.linalg.norm(bg - ref["b"]) / np.linalg.norm(ref["b"]))
         Qg = acc["Q"][r * n_ele:(r + 1) * n_ele]
         errQ.append(np.linalg.norm(Qg - ref["Q"]) / np.linalg.norm(ref["Q"]))
+        neut.append(abs(np.sum(Qg)) / np.sum(np.abs(Qg)))
         errE.append(abs(acc["E"][r] - ref["E"]) / abs(ref["E"]))
     return {
-        "fp32_error_vs_fp64_oracle": {"force_rel_rms_max": max(errF), "charge_rel_rms_max": max(errQ),
-                                      "energy_rel_max": max(errE), "replicas_checked": nsample,
-                                      "target_force_rel_rms": 1e-5},
+        "fp32_error_vs_fp64_oracle": {"force_rel_rms_max": max(errF), "force_max_ion_over_rms_max": max(errFmax),
+                                      "b_rel_rms_max": max(errb), "charge_rel_rms_max": max(errQ),
+                                      "charge_sum_over_l1_max": max(neut), "energy_rel_max": max(errE),
+                                      "replicas_checked": nsample, "target_force_rel_rms": 1e-5},
         "cpu_baseline": {"value": pairs / wall, "unit": "pairs/s", "cores": max(1, round(cpu / wall)),
                          "kind": "oracle",
                          "sample": f"FP64 numpy oracle SRBE step (sample, b*, CP solve, forces, energy) on "
