@@ -55,6 +55,7 @@ extern "C" {
                        integer phases and FP64 carries; CP solve and energy in FP64   */
 
 #define SRBE_FLAG_NO_CP 1 /* skip the electrode matrix: only fixed-charge steps      */
+#define SRBE_FLAG_KSPACE_ONLY 2 /* leave out the real-space erfc terms (see below)   */
 
 typedef struct srbe_params {
   double Lx, Ly, H;   /* box (length); electrodes and ions have 0 <= z <= H           */
@@ -84,7 +85,12 @@ typedef struct srbe_system srbe_system;
  * the slab term of Eq. (17)), factorises it, and keeps S = J A^-1 and
  * -e^T A^-1 / (e^T A^-1 e) on the device.  Also evaluates G of Eq. (27).
  * With SRBE_FLAG_NO_CP set, A is not built and n_ele may be large; steps must
- * then pass Q_in.  On success *out receives the handle; on failure *out is NULL.
+ * then pass Q_in.  With SRBE_FLAG_KSPACE_ONLY set, steps leave out the short-range
+ * erfc terms of Eq. (13) -- the real-space part of b (Eq. (19)), the real-space
+ * forces and the ion-ion real-space energy -- and skip their passes: for use beside
+ * a pair code that computes them, and to attribute errors to the two parts (A, if
+ * built, stays complete).  On success *out receives the handle; on failure *out is
+ * NULL.
  * Errors: SRBE_EINVAL, SRBE_ENOTSPD (A not positive definite, e.g. two electrodes
  * at one position), SRBE_ENOMEM, SRBE_EHIP.
  */

@@ -21,6 +21,7 @@ SRBE_ENUMERIC = -7
 SRBE_FP64 = 0
 SRBE_FP32 = 1
 SRBE_FLAG_NO_CP = 1
+SRBE_FLAG_KSPACE_ONLY = 2
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsrbe.so")
 

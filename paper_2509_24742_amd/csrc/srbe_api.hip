@@ -142,7 +142,7 @@ std::string check_params(const srbe_params* p) {
   if (!(p->kspace_tol > 0.0 && p->kspace_tol < 1.0)) return "kspace_tol must lie in (0, 1)";
   if (p->M < 0 || p->P < 0) return "M and P must be >= 0";
   if (p->P > 2048) return "P must be <= 2048";
-  if (p->flags & ~SRBE_FLAG_NO_CP) return "unknown flag";
+  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY)) return "unknown flag";
   if (p->reserved != 0) return "reserved must be 0";
   return "";
 }
@@ -490,6 +490,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.nchunk_ion = chunks_for(max_nrep);
   b.nchunk_ele = chunks_for(n);
   b.ksplit = tp[SRBE_TUNE_GEMM_SPLIT];
+  b.real = (h->p.flags & SRBE_FLAG_KSPACE_ONLY) ? 0 : 1;
   b.gemm_depth = tp[SRBE_TUNE_GEMM_DEPTH];
   b.kw = tp[SRBE_TUNE_WAVES];
   b.unroll = tp[SRBE_TUNE_UNROLL];
@@ -619,34 +620,40 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   } else {
     launch_front(g, b, fp32, FRONT_SAMPLE | FRONT_SORT, s);
   }
-  HIP_OK(h, hipEventRecord(h->ev[EV_CS], s));
+  const bool real = b.real != 0;  // else k-space only: no real-space passes, no side stream
+  if (real) HIP_OK(h, hipEventRecord(h->ev[EV_CS], s));
   if (split) {
     part(PH_SF_IONS, s, [&] {
       launch_stage_ions(g, b, fp32, STAGE_SF, s);
       launch_sf_finalize(g, b, fp32, 1, s);
     });
   } else {
-    launch_stage_ions(g, b, fp32, STAGE_SF | STAGE_REAL, s);
+    launch_stage_ions(g, b, fp32, real ? STAGE_SF | STAGE_REAL : STAGE_SF, s);
   }
-  HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_CS], 0));
-  part(PH_REAL_II, s1, [&] { launch_real_ii(g, b, fp32, s1); });
-  if (split)
-    part(PH_REAL_ELE, s, [&] { launch_stage_ions(g, b, fp32, STAGE_REAL, s); });
-  else
+  if (real) {
+    HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_CS], 0));
+    part(PH_REAL_II, s1, [&] { launch_real_ii(g, b, fp32, s1); });
+  }
+  if (split) {
+    if (real) part(PH_REAL_ELE, s, [&] { launch_stage_ions(g, b, fp32, STAGE_REAL, s); });
+  } else {
     launch_sf_finalize(g, b, fp32, 1, s);
+  }
   part(PH_ELE_POTENTIAL, s, [&] { launch_ele_potential(g, b, fp32, s); });
   if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, s); });
   part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
-  HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
+  if (real) HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
   part(PH_SF_ELE, s, [&] {
     launch_stage_ele(g, b, fp32, STAGE_SF, s);
     launch_sf_finalize(g, b, fp32, 2, s);
   });
-  HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_POST], 0));
-  part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s1); });
-  HIP_OK(h, hipEventRecord(h->ev[EV_AUX], s1));
+  if (real) {
+    HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_POST], 0));
+    part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s1); });
+    HIP_OK(h, hipEventRecord(h->ev[EV_AUX], s1));
+  }
   part(PH_ION_FORCE, s, [&] { launch_ion_force(g, b, fp32, s); });
-  HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
+  if (real) HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
   part(PH_ENERGY, s, [&] { launch_final(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());
   return SRBE_OK;

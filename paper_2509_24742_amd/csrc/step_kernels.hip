@@ -1052,7 +1052,7 @@ void with_wu(int w, int u, Fn&& fn) {
 // ============================================================ electrode potential b*
 // b*_j = -sum_k Re(coef_k exp(-i k.R_j))           (Eq. (24), coef = w S1)
 //        - (4 pi ke / V) Z_j sum_i q_i z_i          (slab term, minus sign)
-//        - bN_j                                     (real space)
+//        - bN_j                                     (real space; left out if bN is null)
 // and V_j = b*_j + dpsi d_j, the right-hand side of the charge solve (rows of
 // ldcp(n) doubles per replica for the GEMM below).
 template <int W>
@@ -1070,7 +1070,7 @@ __device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double
     const int n = g.n_ele;
     const double Z = ele_xyz[2 * n + j];
     const size_t idx = (size_t)r * n + j;
-    const double b = -acc - (4.0 * M_PI * g.ke / g.V) * Z * scal[4 * r + 2] - bN[idx];
+    const double b = -acc - (4.0 * M_PI * g.ke / g.V) * Z * scal[4 * r + 2] - (bN ? bN[idx] : 0.0);
     bstar[idx] = b;
     V[(size_t)r * ldcp(n) + j] = b + dpsi[r] * ele_d[j];
   }
@@ -1150,10 +1150,10 @@ void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_
     constexpr int w = decltype(W)::value, u = decltype(U)::value;
     if (fp32)
       hipLaunchKernelGGL((k_elepot32<w, u>), grid, dim3(64 * w), 0, s, g, b.ele_fx, b.ele_xyz, b.ele_d, b.rec, b.scal,
-                         b.dpsi, b.bN, b.bstar, b.V);
+                         b.dpsi, b.real ? b.bN : nullptr, b.bstar, b.V);
     else if constexpr (u == 4)  // the FP64 loop has no unroll parameter
       hipLaunchKernelGGL((k_elepot64<w>), grid, dim3(64 * w), 0, s, g, b.ele_xyz, b.ele_d4, b.ele_d, b.modes, b.coef,
-                         b.scal, b.dpsi, b.bN, b.bstar, b.V);
+                         b.scal, b.dpsi, b.real ? b.bN : nullptr, b.bstar, b.V);
   });
 }
 
@@ -1949,8 +1949,10 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
   const double* __restrict__ scal = b.scal;
   const double* __restrict__ rsum = b.rsum;
   double v[2] = {0.0, 0.0};
+  if (b.real) {  // the ion-ion real-space energy (left out in k-space-only steps)
 #pragma unroll 8
-  for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
+    for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
+  }
   for (int k = threadIdx.x; k < g.K; k += 256) {
     const double2 s = b.S1[(size_t)r * g.K + k];
     v[1] += b.w[(size_t)r * g.K + k] * (s.x * s.x + s.y * s.y);
@@ -1977,7 +1979,7 @@ __global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int f
   }
   const int64_t N = b.N;
   const int64_t i = (int64_t)(blockIdx.x - ne) * 256 + threadIdx.x;
-  if (i >= N) return;
+  if (!b.real || i >= N) return;
   const double kq = g.ke * b.ion_q[i];
   double rx = b.Fii[i], ry = b.Fii[N + i], rz = b.Fii[2 * N + i];
   // Fie is read for every ion (in bounds; stale for ions outside the reach cells) so
@@ -1996,7 +1998,8 @@ __global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int f
 
 void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s) {
   const int ne = b.energy_out ? b.R : 0;
-  const int nf = cdiv64(b.N, 256);
+  int nf = b.real ? cdiv64(b.N, 256) : 0;
+  if (ne + nf == 0 && b.step_adv) nf = 1;  // a replayed graph's step counter still advances
   if (ne + nf == 0) return;
   hipLaunchKernelGGL(k_final, dim3(ne + nf), dim3(256), 0, s, g, b, ne, fixedQ);
 }
