@@ -54,6 +54,8 @@ SLOTS = {"sf_ions": 12, "sf_ele": 12, "ele_potential": 12, "ion_force": 15,
 COPY_BYTES = 1 << 29
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kernel_traffic_replica_batch64.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_24742_amd", "csrc", "step_kernels.hip")
+# launch parameters chosen by srbe_tune for these workloads on an MI355X (bench.py --tune)
+TUNING_CACHE = os.path.join(ROOT, "paper_2509_24742_amd", "tuning_cache.json")
 
 
 def measured_traffic():
@@ -85,10 +87,13 @@ def parse():
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
     ap.add_argument("--no-tune", action="store_true",
-                    help="time with the default launch parameters instead of tuning them first (srbe_tune)")
+                    help="time with the default launch parameters")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the launch parameters by timing candidates first (srbe_tune) instead of "
+                         "applying the shipped choices (paper_2509_24742_amd/tuning_cache.json)")
     ap.add_argument("--tune-cache", default=None,
-                    help="JSON file of launch-parameter choices: applied where it has the workload, else tuned "
-                         "and added (lets a profiled run use the choices of an unprofiled one)")
+                    help="with --tune: JSON file of choices, applied where it has the workload, else tuned "
+                         "and added")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -189,16 +194,16 @@ def main():
     tuning = None
     if not args.no_tune:
         t0 = time.time()
-        tuning = {}
+        tuning = {"source": "srbe_tune" if args.tune else "shipped choices (tuning_cache.json)"}
+        cache = args.tune_cache if args.tune else TUNING_CACHE
         for name, prec, offs, x, qq, dp, sd in [("fp32_batch", srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds),
                                                 ("fp64_single_cell", srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi1, seeds1),
                                                 ("fp32_single_cell", srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi1, seeds1)]:
-            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, iters=30, cache=args.tune_cache)
+            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, iters=30, cache=cache, tune_missing=args.tune)
             tuning[name] = {"params": dict(zip(srbe_amd.SRBE_TUNE_NAMES, t["params"])),
                             "ms_default": t["ms_default"], "ms_tuned": t["ms_tuned"], "from_cache": t["cached"]}
         tuning["seconds"] = time.time() - t0
-        log(f"launch parameters in {tuning['seconds']:.2f} s: {tuning['fp32_batch']['params']}"
-            f"{' (from the cache)' if tuning['fp32_batch']['from_cache'] else ''}")
+        log(f"launch parameters ({tuning['source']}) in {tuning['seconds']:.2f} s: {tuning['fp32_batch']['params']}")
 
     # ---- headline: FP32, all replicas in one step, replayed as a captured graph
     ms_fp32 = timed_graph(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
@@ -296,7 +301,10 @@ def main():
         torch.cuda.synchronize()
         acc = {"off": off, "F": o["F"].cpu().numpy(), "Q": o["Q"].cpu().numpy(), "E": o["E"].cpu().numpy(),
                "b": o["b"].cpu().numpy()}
-        result.update(cpu_side(wb, wp, acc, R, sizes, n_ele, K))
+        side, refs = cpu_side(wb, wp, acc, R, sizes, n_ele, K)
+        result.update(side)
+        result["fp32_error_vs_fp64_oracle"].update(error_split(srbe_amd, sysm, wb, wp, refs, off, xyz, q, dpsi,
+                                                               seeds, n_ele))
     print(json.dumps(result), flush=True)
     sysm.close()
 
@@ -383,7 +391,57 @@ def cpu_side(wb, wp, acc, R, sizes, n_ele, K):
                                    f"beforehand ({oracle_setup_s:.1f} s, not timed); cpu_time/wall = "
                                    f"{cpu / wall:.2f}; host threads available: {os.cpu_count()}"},
         "oracle_setup_s": oracle_setup_s,
-    }
+    }, refs
+
+
+def error_split(srbe_amd, sysm, wb, wp, refs, off, xyz, q, dpsi, seeds, n_ele, nsplit=8):
+    """FP32 force error of the k-space part, the real-space part and their sum, apart.
+
+    Both handles run the batch at the oracle's charges (fixed-charge steps, same
+    sampled modes): the k-space-only handle gives the Fourier and slab force, the
+    full handle minus it the real-space force; the oracle's parts come from the same
+    functions its step uses.
+    """
+    import torch
+    from oracle import ewald, sampler, srbe
+
+    p = ewald.Params(Lx=wp["Lx"], Ly=wp["Ly"], H=wp["H"], lam=wp["lam"], alpha=wp["alpha"], eta=wp["eta"],
+                     rc=wp["rc"], coulomb_k=wp["coulomb_k"], M=int(wp["M"]), P=int(wp["P"]),
+                     kspace_tol=wp["kspace_tol"])
+    R = len(off) - 1
+    m = min(nsplit, len(refs))
+    Qh = np.zeros(R * n_ele)
+    for r in range(m):
+        Qh[r * n_ele:(r + 1) * n_ele] = refs[r]["Q"]
+    Qin = torch.tensor(Qh, device=xyz.device)
+    kso = srbe_amd.System(wp, wb["ele_pos"], wb["ele_side"],
+                          flags=srbe_amd.SRBE_FLAG_NO_CP | srbe_amd.SRBE_FLAG_KSPACE_ONLY)
+    full = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, Q_in=Qin, want_kset=False)
+    kpart = kso.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, Q_in=Qin, want_kset=False)
+    torch.cuda.synchronize()
+    N = int(off[-1])
+    Ff = full["F"].cpu().numpy().reshape(3, N)
+    Fk = kpart["F"].cpu().numpy().reshape(3, N)
+    kso.close()
+    ek, er, et = [], [], []
+    ele = np.asarray(wb["ele_pos"], dtype=np.float64)
+    for r in range(m):
+        ion = np.asarray(wb["ion_pos"][r], dtype=np.float64)
+        qi = np.asarray(wb["ion_q"][r], dtype=np.float64)
+        Q = refs[r]["Q"]
+        ks, _ = sampler.draw_kset(p, 2100 + r, 0, 0)
+        Fk_ref = srbe.srbe_force_fourier(p, ks, ion, qi, ele, Q)
+        Fk_ref[:, 2] -= p.coulomb_k * (4.0 * np.pi / p.V) * qi * (qi @ ion[:, 2] + Q @ ele[:, 2])
+        _, gii = ewald.real_space(p, "ii", ion, ion, qi, same=True)
+        _, gig = ewald.real_space(p, "ig", ion, ele, Q)
+        Fr_ref = -p.coulomb_k * qi[:, None] * (gii + gig)
+        gk = Fk[:, off[r]:off[r + 1]].T
+        gt = Ff[:, off[r]:off[r + 1]].T
+        ek.append(np.linalg.norm(gk - Fk_ref) / np.linalg.norm(Fk_ref))
+        er.append(np.linalg.norm((gt - gk) - Fr_ref) / np.linalg.norm(Fr_ref))
+        et.append(np.linalg.norm(gt - (Fk_ref + Fr_ref)) / np.linalg.norm(Fk_ref + Fr_ref))
+    return {"at_oracle_charges": {"force_rel_rms_kspace_max": max(ek), "force_rel_rms_real_space_max": max(er),
+                                  "force_rel_rms_total_max": max(et), "replicas": m}}
 
 
 if __name__ == "__main__":

@@ -53,12 +53,14 @@ class System:
             kset=torch.empty(R * P * 3, dtype=torch.int32, device=device) if (want_kset and P) else None,
         )
 
-    def tune(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, precision=SRBE_FP64, iters=10, cache=None):
+    def tune(self, ion_offsets, ion_xyz, ion_q, dpsi, seed, precision=SRBE_FP64, iters=10, cache=None,
+             tune_missing=True):
         """Choose the launch parameters for this batch shape (srbe_tune) and keep them in the handle.
 
         cache: path of a JSON file of earlier choices, keyed by device architecture, precision,
         replica count, largest replica, electrode count and P; a hit is applied without timing
-        and a miss is timed and added.  Returns dict(params, ms_default, ms_tuned, cached).
+        and a miss is timed and added (with tune_missing false, a miss keeps the defaults and
+        nothing is timed or written).  Returns dict(params, ms_default, ms_tuned, cached).
         """
         import json
         import os
@@ -76,7 +78,11 @@ class System:
             if key in entries:
                 params = [int(entries[key]["params"][name]) for name in SRBE_TUNE_NAMES]
                 srbe_set_tuning(self.h, precision, off, params)
-                return dict(params=params, ms_default=None, ms_tuned=entries[key].get("ms_tuned"), cached=True)
+                return dict(params=params, ms_default=entries[key].get("ms_default"),
+                            ms_tuned=entries[key].get("ms_tuned"), cached=True)
+        if not tune_missing:
+            return dict(params=srbe_get_tuning(self.h, precision, off), ms_default=None, ms_tuned=None,
+                        cached=False)
         params, ms0, ms1 = srbe_tune(self.h, precision, off, ion_xyz, ion_q, dpsi, seed, iters=iters)
         if cache is not None:
             entries[key] = dict(params=dict(zip(SRBE_TUNE_NAMES, params)), ms_default=ms0, ms_tuned=ms1)
