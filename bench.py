@@ -54,7 +54,7 @@ SLOTS = {"sf_ions": 12, "sf_ele": 12, "ele_potential": 12, "ion_force": 15,
 COPY_BYTES = 1 << 29
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kernel_traffic_replica_batch64.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_24742_amd", "csrc", "step_kernels.hip")
-# launch parameters chosen by srbe_tune for these workloads on an MI355X (bench.py --tune)
+# launch parameters chosen by srbe_tune's timing of these workloads on an MI355X
 TUNING_CACHE = os.path.join(ROOT, "paper_2509_24742_amd", "tuning_cache.json")
 
 
@@ -88,12 +88,6 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
     ap.add_argument("--no-tune", action="store_true",
                     help="time with the default launch parameters")
-    ap.add_argument("--tune", action="store_true",
-                    help="choose the launch parameters by timing candidates first (srbe_tune) instead of "
-                         "applying the shipped choices (paper_2509_24742_amd/tuning_cache.json)")
-    ap.add_argument("--tune-cache", default=None,
-                    help="with --tune: JSON file of choices, applied where it has the workload, else tuned "
-                         "and added")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -194,12 +188,11 @@ def main():
     tuning = None
     if not args.no_tune:
         t0 = time.time()
-        tuning = {"source": "srbe_tune" if args.tune else "shipped choices (tuning_cache.json)"}
-        cache = args.tune_cache if args.tune else TUNING_CACHE
+        tuning = {"source": "shipped choices (tuning_cache.json)"}
         for name, prec, offs, x, qq, dp, sd in [("fp32_batch", srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds),
                                                 ("fp64_single_cell", srbe_amd.SRBE_FP64, off1, xyz1, q1, dpsi1, seeds1),
                                                 ("fp32_single_cell", srbe_amd.SRBE_FP32, off1, xyz1, q1, dpsi1, seeds1)]:
-            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, iters=30, cache=cache, tune_missing=args.tune)
+            t = sysm.tune(offs, x, qq, dp, sd, precision=prec, cache=TUNING_CACHE, tune_missing=False)
             tuning[name] = {"params": dict(zip(srbe_amd.SRBE_TUNE_NAMES, t["params"])),
                             "ms_default": t["ms_default"], "ms_tuned": t["ms_tuned"], "from_cache": t["cached"]}
         tuning["seconds"] = time.time() - t0

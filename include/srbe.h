@@ -235,6 +235,11 @@ const char* srbe_phase_name(int32_t phase);
  * srbe_step (sampled modes; seed required when P > 0); the outputs go to buffers the
  * call allocates and frees.  Blocks until done.  Errors: SRBE_EINVAL (arguments),
  * SRBE_ENOMEM, SRBE_EHIP, or a device fault of a timed step (then nothing is stored).
+ * Live timing is currently switched off: processes that ran it (tens of graph
+ * create / replay / destroy cycles) have aborted with host heap corruption whose
+ * cause is not yet found.  The call checks its arguments and then returns
+ * SRBE_EINVAL (srbe_last_error says so) without device work; choose parameters with
+ * srbe_set_tuning, e.g. from a table of earlier timings.
  *
  * srbe_get_tuning -- the parameters a step of this shape would use (host int32
  * [SRBE_TUNE_NPARAM]).  ion_offsets: host, n_rep + 1.

@@ -61,6 +61,8 @@ class System:
         replica count, largest replica, electrode count and P; a hit is applied without timing
         and a miss is timed and added (with tune_missing false, a miss keeps the defaults and
         nothing is timed or written).  Returns dict(params, ms_default, ms_tuned, cached).
+        srbe_tune's live timing is switched off at present, so a miss with tune_missing true
+        raises SrbeError.
         """
         import json
         import os

@@ -16,6 +16,14 @@ struct ModeRec32 {
   float kx, ky, kz;
 };
 
+// Workspace of the multi-block cell sort (count null: the one-block sort is used).
+struct BigSort {
+  int* count;     // R*(ncell+1) cell counts, then per-cell cursors
+  int* prov;      // N provisional cell order (indices within the replica)
+  double* tsum;   // R*ntile*4 charge sums per tile of 256 particles (ions)
+  int ntile;      // tiles of 256 particles per replica
+};
+
 // Per-step device pointers and sizes.
 struct StepBufs {
   int R;                    // replicas
@@ -57,7 +65,8 @@ struct StepBufs {
   double* w;                // R*K
   uint4* ion_fx;            // N fixed point + FP32 charge, original order (FP32 path)
   double4* ion_d4;          // N fractional coordinates + charge, original order (FP64 path)
-  unsigned* keys;           // N cell sort keys (cell << 13 | index within the replica), input order
+  unsigned* keys;           // N cell sort keys, input order: cell << 13 | index within the replica
+                            // (one-block sort), or the cell (multi-block sort)
   int* perm;                // N sorted position (within the replica's range) -> global ion index
   int* scell;               // N cell of each sorted ion
   int* cstart;              // R*(ncell+1) cell starts, relative to the replica's first ion
@@ -89,6 +98,7 @@ struct StepBufs {
   double* Fii;              // 3N ion-ion real-space force sums (SoA, input order), before the ke q_i factor
   double* Fie;              // 3N ion-electrode real-space force sums, written for ions of reach cells only
   unsigned* status;
+  BigSort bigsort;          // multi-block cell sort workspace (count null: one-block sort)
   // outputs
   double* Q_out;
   double* F_out;
@@ -121,9 +131,12 @@ void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s);
 
 // setup kernels
+// bs.count null: the one-block sort (n_ele <= kMaxBinParticles and ncell <= kMaxCells)
 void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,
                            uint4* fx, double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4,
-                           unsigned* status, hipStream_t s);
+                           unsigned* status, const BigSort& bs, hipStream_t s);
+// true if a batch whose largest replica holds max_particles needs the multi-block sort
+bool use_big_sort(const Geom& g, int64_t max_particles);
 void launch_cell_zrange(const Geom& g, const int* cstart, const double* ele_xyz, const int* perm, double2* zr,
                         hipStream_t s);
 void launch_ele_phase_block(const double* ele_xyz, int n_ele, const int* m, const double* sqrtw, int nk, int ld,

@@ -174,7 +174,7 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   g.n_ele = n_ele;
   // real-space cells at least rc wide in x and y and rc / nzs thick in z (the
   // z-stencil then reaches nzs cells each way); coarsened, never below those
-  // widths, to stay within kMaxCells
+  // widths, to stay within kMaxGridCells
   g.nzs = 3;
   // (the 1e-9 margin keeps cells strictly wider than rc and rc / nzs, so rounding in
   // the cell index never puts a pair closer than rc outside the stencil)
@@ -182,7 +182,7 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   g.ncx = std::max(1, (int)std::floor(p.Lx / p.rc * shrink));
   g.ncy = std::max(1, (int)std::floor(p.Ly / p.rc * shrink));
   g.ncz = std::max(1, (int)std::floor(p.H * g.nzs / p.rc * shrink));
-  while (g.ncx * g.ncy * g.ncz > kMaxCells) {
+  while ((int64_t)g.ncx * g.ncy * g.ncz > kMaxGridCells) {
     if (g.ncz >= g.ncx && g.ncz >= g.ncy)
       g.ncz = (g.ncz + 1) / 2;
     else if (g.ncx >= g.ncy)
@@ -396,8 +396,8 @@ int check_shape(srbe_system* h, int precision, int n_rep, const int64_t* ion_off
     if (c < 0) return set_err(h, SRBE_EINVAL, "ion_offsets must be non-decreasing");
     max_nrep = std::max(max_nrep, c);
   }
-  if (max_nrep > kMaxBinParticles)
-    return set_err(h, SRBE_EINVAL, "a replica has more ions than the one-block cell sort handles (8192)");
+  if (ion_offsets[n_rep] > (int64_t)INT32_MAX - kScanPad)
+    return set_err(h, SRBE_EINVAL, "more than 2^31 - 193 ions in one call");
   return SRBE_OK;
 }
 
@@ -497,6 +497,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.ii_ipw = tp[SRBE_TUNE_II_IONS];
   b.ie_nbx = tp[SRBE_TUNE_IE_BLOCKS];
   b.esplit = tp[SRBE_TUNE_ELE_SPLIT];
+  b.bigsort = BigSort{nullptr, nullptr, nullptr, use_big_sort(h->g, max_nrep) ? (int)((std::max<int64_t>(max_nrep, 1) + 255) / 256) : 0};
   b.ion_xyz = a.ion_xyz;
   b.ion_q = a.ion_q;
   b.dpsi = a.dpsi;
@@ -575,6 +576,9 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.Fii, (size_t)3 * N1 * sizeof(double)},
       {(void**)&b.Fie, (size_t)3 * N1 * sizeof(double)},
       {(void**)&b.energy_out, a.energy_out ? 0 : (size_t)R * sizeof(double)},
+      {(void**)&b.bigsort.count, b.bigsort.ntile ? (size_t)R * (g.ncell + 1) * sizeof(int) : 0},
+      {(void**)&b.bigsort.prov, b.bigsort.ntile ? (size_t)N1 * sizeof(int) : 0},
+      {(void**)&b.bigsort.tsum, b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0},
   };
   size_t total = 0;
   for (const Item& it : items) {
@@ -712,7 +716,6 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
   if (!msg.empty()) return SRBE_EINVAL;
   if (n_ele <= 0 || !ele_xyz || !ele_side) return SRBE_EINVAL;
   const bool cp = !(params->flags & SRBE_FLAG_NO_CP);
-  if (n_ele > kMaxBinParticles) return SRBE_EINVAL;
   std::vector<double> d(n_ele);
   for (int j = 0; j < n_ele; ++j) {
     if (ele_side[j] != 1 && ele_side[j] != -1) return SRBE_EINVAL;
@@ -808,13 +811,26 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
     }
+    BigSort ebs{nullptr, nullptr, nullptr, 0};
+    if (use_big_sort(g, n_ele)) {
+      ebs.ntile = (n_ele + 255) / 256;
+      if (hipMalloc((void**)&ebs.count, (size_t)(g.ncell + 1) * sizeof(int)) != hipSuccess ||
+          hipMalloc((void**)&ebs.prov, n * sizeof(int)) != hipSuccess) {
+        if (ebs.count) (void)hipFree(ebs.count);
+        (void)hipFree(off2);
+        return fail(SRBE_ENOMEM);
+      }
+    }
     launch_bin_electrodes(g, off2, h->ele_xyz, n_ele, h->bin_keys, h->ele_fx, h->ele_d4, h->ele_perm, h->ele_scell,
-                          h->ele_cstart, h->ele_sfx, h->ele_sd4, h->status, s);
+                          h->ele_cstart, h->ele_sfx, h->ele_sd4, h->status, ebs, s);
     launch_cell_zrange(g, h->ele_cstart, h->ele_xyz, h->ele_perm, h->ele_czr, s);
     launch_logq_table(g, h->logq, s);
     std::vector<double2> czr(g.ncell);
     std::vector<int> perm(n), iperm(n);
-    if (hipDeviceSynchronize() != hipSuccess ||
+    const hipError_t se = hipDeviceSynchronize();
+    if (ebs.count) (void)hipFree(ebs.count);
+    if (ebs.prov) (void)hipFree(ebs.prov);
+    if (se != hipSuccess ||
         hipMemcpy(czr.data(), h->ele_czr, czr.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(perm.data(), h->ele_perm, n * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {
       (void)hipFree(off2);
@@ -1125,6 +1141,11 @@ int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   int rc = check_shape(h, precision, n_rep, ion_offsets, max_nrep);
   if (rc != SRBE_OK) return rc;
   if (!h->has_cp) return set_err(h, SRBE_EINVAL, "handle built without the CP solve: nothing to tune against");
+  // Live timing is switched off: processes that ran it have aborted with host heap
+  // corruption whose cause is not yet found.  The timing code stays for when it is.
+  constexpr bool kLiveTiming = false;
+  if (!kLiveTiming)
+    return set_err(h, SRBE_EINVAL, "srbe_tune: live timing is switched off; use srbe_set_tuning");
   const int64_t N = ion_offsets[n_rep];
   const size_t n = (size_t)h->n_ele;
   hipStream_t s = (hipStream_t)stream;

@@ -83,6 +83,25 @@ struct SortArgs {
   unsigned* status;
 };
 
+// Records of particle i in input order, its range check and its charge sums
+// (v: sum q, sum |q|, sum q z, sum q^2); returns its cell.
+template <int REC>
+__device__ __forceinline__ int particle_record(const Geom& g, const SortArgs& a, int64_t i, double (&v)[4]) {
+  constexpr bool kIons = REC != 3;
+  const int64_t N = a.N;
+  const double x = a.xyz[i], y = a.xyz[N + i], z = a.xyz[2 * N + i];
+  const double qi = kIons ? a.q[i] : 0.0;
+  if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) atomicOr(a.status, ST_RANGE);
+  const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
+  if (REC & 1) a.fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
+  if (REC & 2) a.d4[i] = make_double4(sx, sy, sz, qi);
+  v[0] += qi;
+  v[1] += fabs(qi);
+  v[2] += qi * z;
+  v[3] += qi * qi;
+  return cell_index(g, sx, sy, z);
+}
+
 template <int REC>
 __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs& a) {
   // REC 1 or 2: ions (charges given, the replica's sums written, also for a replica
@@ -95,25 +114,14 @@ __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs&
   const int t = threadIdx.x;
   const int64_t b0 = a.off[r];
   const int n = (int)(a.off[r + 1] - b0);
-  const int64_t N = a.N;
   for (int c = t; c <= g.ncell; c += 1024) cnt[c] = 0;
   __syncthreads();
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = t; k < n; k += 1024) {
     const int64_t i = b0 + k;
-    const double x = a.xyz[i], y = a.xyz[N + i], z = a.xyz[2 * N + i];
-    const double qi = kIons ? a.q[i] : 0.0;
-    if (!isfinite(qi) || !isfinite(x) || !isfinite(y) || !(z >= 0.0 && z <= g.H)) atomicOr(a.status, ST_RANGE);
-    const double sx = wrap_frac(x, g.invLx), sy = wrap_frac(y, g.invLy), sz = wrap_frac(z, g.invLz);
-    const unsigned key = ((unsigned)cell_index(g, sx, sy, z) << 13) | (unsigned)k;
+    const unsigned key = ((unsigned)particle_record<REC>(g, a, i, v) << 13) | (unsigned)k;
     a.keys[i] = key;
-    if (REC & 1) a.fx[i] = make_uint4(to_fixed(sx), to_fixed(sy), to_fixed(sz), __float_as_uint((float)qi));
-    if (REC & 2) a.d4[i] = make_double4(sx, sy, sz, qi);
     atomicAdd(&cnt[key >> 13], 1);
-    v[0] += qi;
-    v[1] += fabs(qi);
-    v[2] += qi * z;
-    v[3] += qi * qi;
   }
   if (kIons) {
     block_sum<1024, 4>(v, red);
@@ -166,6 +174,133 @@ __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs&
     if (REC & 1) a.sfx[b0 + pos] = a.fx[i];
     if (REC & 2) a.sd4[b0 + pos] = a.d4[i];
   }
+}
+
+// Multi-block cell sort, for replicas of more than kMaxBinParticles particles or grids
+// of more than kMaxCells cells.  It gives sort_block's order (cells in index order,
+// each cell's particles in index order) from five launches over tiles of 256
+// particles: the cell counts are cleared; each particle's records and cell, the
+// counts by integer atomics in device memory and each tile's charge sums; per replica
+// (one block) the tile sums added in tile order and the exclusive scan of the counts
+// (the cell starts; the counts become per-cell cursors); a provisional slot per
+// particle from its cell's cursor (the order inside a cell depends on timing); and
+// the final position inside the cell, the number of the cell's entries with a
+// smaller index, with the records in cell order.  The time of the last pass grows
+// with the square of the largest cell's count.
+__global__ __launch_bounds__(256) void k_zero_int(int* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+template <int REC>
+__global__ __launch_bounds__(256) void k_bigsort_count(Geom g, SortArgs a, BigSort bs) {
+  __shared__ double red[4][4];
+  const int r = blockIdx.x / bs.ntile, tile = blockIdx.x - r * bs.ntile;
+  const int64_t b0 = a.off[r];
+  const int n = (int)(a.off[r + 1] - b0);
+  const int k = tile * 256 + (int)threadIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (k < n) {
+    const int c = particle_record<REC>(g, a, b0 + k, v);
+    a.keys[b0 + k] = (unsigned)c;
+    atomicAdd(&bs.count[(size_t)r * (g.ncell + 1) + c], 1);
+  }
+  if constexpr (REC != 3) {
+    block_sum<256, 4>(v, red);
+    if (threadIdx.x == 0)
+      for (int u = 0; u < 4; ++u) bs.tsum[((size_t)r * bs.ntile + tile) * 4 + u] = v[u];
+  }
+}
+
+template <int REC>
+__global__ __launch_bounds__(1024) void k_bigsort_scan(Geom g, SortArgs a, BigSort bs) {
+  __shared__ double red[4][16];
+  __shared__ int wtot[16];
+  const int r = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if constexpr (REC != 3) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int u = t; u < bs.ntile; u += 1024)
+      for (int q = 0; q < 4; ++q) v[q] += bs.tsum[((size_t)r * bs.ntile + u) * 4 + q];
+    block_sum<1024, 4>(v, red);
+    if (t == 0) {
+      for (int q = 0; q < 4; ++q) a.scal[4 * r + q] = v[q];
+      if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(a.status, ST_NONNEUTRAL);
+    }
+  }
+  int* cnt = bs.count + (size_t)r * (g.ncell + 1);
+  int* cs = a.cstart + (size_t)r * (g.ncell + 1);
+  int carry = 0;
+  for (int c0 = 0; c0 <= g.ncell; c0 += 1024) {
+    const int c = c0 + t;
+    const int x = c < g.ncell ? cnt[c] : 0;
+    int incl = x;  // inclusive scan inside the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wv] = incl;
+    __syncthreads();
+    int below = 0, total = 0;
+    for (int u = 0; u < 16; ++u) {
+      below += u < wv ? wtot[u] : 0;
+      total += wtot[u];
+    }
+    if (c <= g.ncell) {
+      const int start = carry + below + incl - x;
+      cs[c] = start;
+      cnt[c] = start;  // cursor
+    }
+    carry += total;
+    __syncthreads();
+  }
+}
+
+template <int REC>
+__global__ __launch_bounds__(256) void k_bigsort_scatter(Geom g, SortArgs a, BigSort bs) {
+  const int r = blockIdx.x / bs.ntile, tile = blockIdx.x - r * bs.ntile;
+  const int64_t b0 = a.off[r];
+  const int n = (int)(a.off[r + 1] - b0);
+  const int k = tile * 256 + (int)threadIdx.x;
+  if (k >= n) return;
+  const int c = (int)a.keys[b0 + k];
+  bs.prov[b0 + atomicAdd(&bs.count[(size_t)r * (g.ncell + 1) + c], 1)] = k;
+}
+
+template <int REC>
+__global__ __launch_bounds__(256) void k_bigsort_rank(Geom g, SortArgs a, BigSort bs) {
+  const int r = blockIdx.x / bs.ntile, tile = blockIdx.x - r * bs.ntile;
+  const int64_t b0 = a.off[r];
+  const int n = (int)(a.off[r + 1] - b0);
+  const int p = tile * 256 + (int)threadIdx.x;
+  if (p >= n) return;
+  const int* __restrict__ prov = bs.prov + b0;
+  const int k = prov[p];
+  const int c = (int)a.keys[b0 + k];
+  const int* cs = a.cstart + (size_t)r * (g.ncell + 1);
+  const int lo = cs[c], hi = cs[c + 1];
+  int rank = 0;
+  for (int u = lo; u < hi; ++u) rank += prov[u] < k;
+  const int pos = lo + rank;
+  const int64_t i = b0 + k;
+  a.perm[b0 + pos] = (int)i;
+  a.scell[b0 + pos] = c;
+  if (REC & 1) a.sfx[b0 + pos] = a.fx[i];
+  if (REC & 2) a.sd4[b0 + pos] = a.d4[i];
+}
+
+template <int REC>
+static void launch_big_sort(const Geom& g, const SortArgs& sa, const BigSort& bs, int R, hipStream_t s) {
+  const int64_t ncount = (int64_t)R * (g.ncell + 1);
+  hipLaunchKernelGGL(k_zero_int, dim3(std::min(4096, cdiv64(ncount, 256))), dim3(256), 0, s, bs.count, ncount);
+  const dim3 tiles((unsigned)R * bs.ntile);
+  hipLaunchKernelGGL(k_bigsort_count<REC>, tiles, dim3(256), 0, s, g, sa, bs);
+  hipLaunchKernelGGL(k_bigsort_scan<REC>, dim3(R), dim3(1024), 0, s, g, sa, bs);
+  hipLaunchKernelGGL(k_bigsort_scatter<REC>, tiles, dim3(256), 0, s, g, sa, bs);
+  hipLaunchKernelGGL(k_bigsort_rank<REC>, tiles, dim3(256), 0, s, g, sa, bs);
+}
+
+bool use_big_sort(const Geom& g, int64_t max_particles) {
+  return max_particles > kMaxBinParticles || g.ncell > kMaxCells;
 }
 
 // ============================================================ sampler
@@ -416,23 +551,35 @@ static SortArgs ion_sort_args(const StepBufs& b) {
 
 void launch_front(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
   const int nsamp = (parts & FRONT_SAMPLE) ? b.R : 0;
-  const int nsort = (parts & FRONT_SORT) ? b.R : 0;
-  if (nsamp + nsort == 0) return;
-  const size_t lds = nsamp ? sample_lds_bytes(g.P) : 0;
+  const bool sort = (parts & FRONT_SORT) != 0, big = sort && b.bigsort.count != nullptr;
+  const int nsort = sort && !big ? b.R : 0;
   const SortArgs sa = ion_sort_args(b);
-  if (fp32)
-    hipLaunchKernelGGL(k_front<1>, dim3(nsamp + nsort), dim3(1024), lds, s, g, b, sa, nsamp);
-  else
-    hipLaunchKernelGGL(k_front<2>, dim3(nsamp + nsort), dim3(1024), lds, s, g, b, sa, nsamp);
+  if (nsamp + nsort > 0) {
+    const size_t lds = nsamp ? sample_lds_bytes(g.P) : 0;
+    if (fp32)
+      hipLaunchKernelGGL(k_front<1>, dim3(nsamp + nsort), dim3(1024), lds, s, g, b, sa, nsamp);
+    else
+      hipLaunchKernelGGL(k_front<2>, dim3(nsamp + nsort), dim3(1024), lds, s, g, b, sa, nsamp);
+  }
+  if (big) {
+    if (fp32)
+      launch_big_sort<1>(g, sa, b.bigsort, b.R, s);
+    else
+      launch_big_sort<2>(g, sa, b.bigsort, b.R, s);
+  }
 }
 
 // Electrodes are binned once per handle with the same code (both record formats).
 // off2: device {0, n_ele}; keys: n_ele scratch words; status: device word.
 void launch_bin_electrodes(const Geom& g, const int64_t* off2, const double* ele_xyz, int n_ele, unsigned* keys,
                            uint4* fx, double4* d4, int* perm, int* scell, int* cstart, uint4* sfx, double4* sd4,
-                           unsigned* status, hipStream_t s) {
+                           unsigned* status, const BigSort& bs, hipStream_t s) {
   const SortArgs sa{off2, ele_xyz, nullptr, (int64_t)n_ele, keys, fx, d4, nullptr, perm, scell, cstart, sfx, sd4,
                     status};
+  if (bs.count) {
+    launch_big_sort<3>(g, sa, bs, 1, s);
+    return;
+  }
   StepBufs none{};
   hipLaunchKernelGGL(k_front<3>, dim3(1), dim3(1024), 0, s, g, none, sa, 0);
 }
@@ -1985,7 +2132,10 @@ __global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int f
   // Fie is read for every ion (in bounds; stale for ions outside the reach cells) so
   // that its loads do not wait for the flag, which then selects it
   const double ex = b.Fie[i], ey = b.Fie[N + i], ez = b.Fie[2 * N + i];
-  if (b.reach_cell[b.keys[i] >> 13]) {
+  // the ion's cell: the multi-block sort keeps it as the key, the one-block sort in
+  // the key's high bits
+  const unsigned key = b.keys[i];
+  if (b.reach_cell[b.bigsort.count ? key : key >> 13]) {
     rx += ex;
     ry += ey;
     rz += ez;

@@ -29,6 +29,13 @@ equilibration run this project does not have):
   1100 + r and voltages drawn uniformly from [0, 4] V.
 * per-step jitter: N(0, 0.01^2 nm^2) per axis and site; x, y wrap, z reflects
   back into the electrolyte interval.
+* large slab: two n x n square walls (spacing Lx / n) at z = 0 and z = H in an
+  Lx x Lx cell; n_ion ions of +-0.78 e (half each) by RSA (0.3 nm) in
+  z in [0.4, H - 0.4]; alpha = 3 /nm, eta = 1/19.79 nm, rc = 1.2 nm.  The full
+  size is 2 x 256 x 256 walls, 917,504 ions, 30 x 30 x 100 nm, M = 64, P = 500 or
+  2000; smaller instances keep the density and the recipe.  Large placements use
+  a batched RSA with the same acceptance rule (each candidate, in draw order, is
+  kept if it is at least dmin from every site kept before it).
 """
 
 import numpy as np
@@ -56,6 +63,36 @@ def _rsa_sites(rng, n, Lx, Ly, zlo, zhi, dmin, max_tries=200000):
         c = np.array([[rng.uniform(0, Lx), rng.uniform(0, Ly), rng.uniform(zlo, zhi)]])
         if _rsa_accept(c, placed, Lx, Ly, dmin):
             placed = np.vstack([placed, c])
+    return placed
+
+
+def _rsa_sites_batched(rng, n, Lx, Ly, zlo, zhi, dmin, batch=65536):
+    """RSA of n sites, candidates drawn in batches and decided in draw order.
+
+    A candidate is rejected if a site of an earlier batch lies within dmin
+    (periodic in x and y; k-d tree), or if an earlier kept candidate of its own batch
+    does (conflicting pairs of the batch visited in order of their later member).
+    """
+    from scipy.spatial import cKDTree
+    box = (Lx, Ly, 4.0 * (zhi + dmin) + 1.0)  # z never wraps: the box is far taller than the sites
+    placed = np.zeros((0, 3))
+    while len(placed) < n:
+        need = n - len(placed)
+        m = int(min(batch, need * 1.1 + 64))
+        cand = np.column_stack([rng.uniform(0, Lx, m), rng.uniform(0, Ly, m), rng.uniform(zlo, zhi, m)])
+        cand[:, 0] %= Lx
+        cand[:, 1] %= Ly
+        if len(placed):
+            d, _ = cKDTree(placed, boxsize=box).query(cand, k=1)
+            cand = cand[d >= dmin]
+        pairs = cKDTree(cand, boxsize=box).query_pairs(dmin, output_type="ndarray")
+        keep = np.ones(len(cand), dtype=bool)
+        if len(pairs):
+            pairs = np.sort(pairs, axis=1)
+            for i, j in pairs[np.argsort(pairs[:, 1], kind="stable")]:
+                if keep[i]:
+                    keep[j] = False
+        placed = np.vstack([placed, cand[keep][:need]])
     return placed
 
 
@@ -89,6 +126,21 @@ def tiny_slab(seed=1000, dpsi=2.0):
     q = np.array([0.78] * 100 + [-0.78] * 100)
     params = dict(Lx=Lx, Ly=Ly, H=H, lam=3.0, alpha=3.0, eta=1.0 / 19.79, rc=1.2,
                   coulomb_k=COULOMB_K, M=10, P=100)
+    return dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=float(dpsi))
+
+
+def large_slab(n_side=256, n_ion=917504, Lx=30.0, H=100.0, M=64, P=500, seed=1002, dpsi=2.0):
+    """Square-wall slab at the large-system recipe; the defaults are the full size."""
+    if n_ion % 2:
+        raise ValueError("n_ion must be even")
+    rng = np.random.default_rng(seed)
+    a = Lx / n_side
+    ele = np.vstack([square_wall(n_side, a, 0.0), square_wall(n_side, a, H)])
+    side = np.array([-1] * n_side ** 2 + [1] * n_side ** 2, dtype=np.int8)
+    ion = _rsa_sites_batched(rng, n_ion, Lx, Lx, 0.4, H - 0.4, 0.3)
+    q = np.array([0.78] * (n_ion // 2) + [-0.78] * (n_ion // 2))
+    params = dict(Lx=Lx, Ly=Lx, H=H, lam=3.0, alpha=3.0, eta=1.0 / 19.79, rc=1.2,
+                  coulomb_k=COULOMB_K, M=M, P=P)
     return dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=float(dpsi))
 
 

@@ -1,8 +1,9 @@
 """Edge cases of the GPU step against the oracle: a replica with no ions inside a
 batch, a step with no ions at all (the empty capacitor), ions exactly on the walls
-(z = 0 and z = H, the ends of the accepted range), the largest replica the one-block
-cell sort takes (8192 ions, random placement, so close pairs occur), and the
-rejection of a larger one before any device work.  Tolerances as in test_gpu_step.py.
+(z = 0 and z = H, the ends of the accepted range), and the two sides of the cell
+sort's switch: the largest replica the one-block sort takes (8192 ions) and the
+smallest the multi-block sort takes (8194 ions, ~100 per cell), both placed at
+random, so close pairs occur.  Tolerances as in test_gpu_step.py.
 """
 
 import numpy as np
@@ -86,24 +87,13 @@ def test_ions_on_the_walls(tiny, prec):
     _check(tiny, [(pos, w["ion_q"])], [1.0], [9], 2, prec, off, out)
 
 
+@pytest.mark.parametrize("n", [8192, 8194])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_largest_replica(tiny, prec):
+def test_replicas_at_the_sort_switch(tiny, prec, n):
     wp = tiny["wp"]
     rng = np.random.default_rng(5)
-    n = 8192
     pos = np.stack([rng.uniform(0, wp["Lx"], n), rng.uniform(0, wp["Ly"], n), rng.uniform(0.2, wp["H"] - 0.2, n)], 1)
     q = np.where(np.arange(n) % 2 == 0, 0.5, -0.5)
-    print(f"largest replica, precision {prec}", flush=True)
+    print(f"replica of {n} ions, precision {prec}", flush=True)
     off, out = _run(tiny, [(pos, q)], [1.0], [17], 3, prec)
     _check(tiny, [(pos, q)], [1.0], [17], 3, prec, off, out)
-
-
-def test_oversize_replica_rejected(tiny):
-    from paper_2509_24742_amd import binding
-    wp = tiny["wp"]
-    n = 8193
-    pos = np.stack([np.linspace(0.1, wp["Lx"] - 0.1, n), np.full(n, 1.0), np.full(n, 1.0)], 1)
-    q = np.where(np.arange(n) % 2 == 0, 0.5, -0.5)
-    off, xyz, qt, dp, sd = gpu_inputs([pos], [q], [1.0], [1])
-    with pytest.raises(binding.SrbeError):
-        tiny["sys"].step(off, xyz, qt, dp, sd, 0)

@@ -1,0 +1,105 @@
+"""Large replicas and fine cell grids: the multi-block cell sort.
+
+Replicas of more than 8192 ions, and boxes whose real-space grid has more than 2048
+cells, are cell-sorted by the multi-block counting sort (so are the electrodes at
+set-up beyond those sizes).  Its order is the one-block sort's, so every later pass
+runs unchanged.  Each case compares b* and the ion forces at fixed electrode charges
+with the FP64 oracle on the device-drawn k-set, to the tolerances of test_gpu_step.py
+(FP64: 1e-11 relative max-norm; FP32: force relative RMS <= 1e-5, b <= 3e-5).  The
+handles are built without the CP solve: the electrode matrix of these boxes is beyond
+what the oracle builds in seconds.  A graph replay of the same step must reproduce
+the eager step bit for bit.
+
+Cases (square-wall slabs of the large-system recipe, ions at 10 per nm^3 or below):
+
+* tall: one replica of 10,000 ions in 4.8 x 4.8 x 48 nm (1,920 cells): the ions take
+  the multi-block sort for their count; the 1,152 electrodes take the one-block sort.
+* wide: two replicas of 3,000 and 1,502 ions (ragged tiles) in 13.6 x 13.6 x 12 nm
+  with 2 x 68 x 68 = 9,248 electrodes (3,630 cells): ions and electrodes both take
+  the multi-block sort, for the grid (and the electrodes also for their count).
+"""
+
+import numpy as np
+import pytest
+
+from helpers import forces_from_soa, gpu_inputs, oracle_params, rel_inf, rel_rms
+from oracle import sampler, srbe
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+STEP = 3
+
+CASES = {
+    "tall": dict(n_side=24, Lx=4.8, H=48.0, reps=[(10000, 1500)], dpsi=[2.0], seeds=[71]),
+    "wide": dict(n_side=68, Lx=13.6, H=12.0, reps=[(3000, 1501), (1502, 1502)], dpsi=[1.0, 3.5], seeds=[72, 73]),
+}
+
+
+def build_case(name):
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import workloads as wl
+    c = CASES[name]
+    ws = [wl.large_slab(n_side=c["n_side"], n_ion=n, Lx=c["Lx"], H=c["H"], M=20, P=100, seed=s) for n, s in c["reps"]]
+    wp = dict(ws[0]["params"], kspace_tol=1e-16)
+    p = oracle_params(wp)
+    ele, side = ws[0]["ele_pos"], ws[0]["ele_side"]
+    rng = np.random.default_rng(9)
+    Qs = [side * 0.004 + 0.001 * rng.normal(size=len(side)) for _ in ws]
+    sysm = srbe_amd.System(wp, ele, side, flags=srbe_amd.SRBE_FLAG_NO_CP)
+    refs = []
+    for w, Q, seed in zip(ws, Qs, c["seeds"]):
+        ks, _ = sampler.draw_kset(p, seed, 0, STEP)
+        refs.append(dict(b=srbe.srbe_b(p, ks, w["ion_pos"], w["ion_q"], ele),
+                         F=srbe.srbe_ion_forces(p, ks, w["ion_pos"], w["ion_q"], ele, Q), kset=ks))
+    inputs = gpu_inputs([w["ion_pos"] for w in ws], [w["ion_q"] for w in ws], c["dpsi"], c["seeds"])
+    qin = torch.tensor(np.concatenate(Qs), device="cuda")
+    return dict(sys=sysm, refs=refs, inputs=inputs, qin=qin, n_ele=len(ele))
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    c = build_case(request.param)
+    c["name"] = request.param
+    yield c
+    c["sys"].close()
+
+
+def check(case, precision, off, out, label):
+    n = case["n_ele"]
+    for r, ref in enumerate(case["refs"]):
+        assert np.array_equal(out["kset"].cpu().numpy()[r * ref["kset"].size:(r + 1) * ref["kset"].size],
+                              ref["kset"].astype(np.int32).ravel()), (label, r)
+        F = forces_from_soa(out["F"], off, r)
+        b = out["b"].cpu().numpy()[r * n:(r + 1) * n]
+        print(f"{label} replica {r}: force {rel_rms(F, ref['F']):.2e} rms {rel_inf(F, ref['F']):.2e} max, "
+              f"b {rel_rms(b, ref['b']):.2e} rms", flush=True)
+        if precision == 0:
+            assert rel_inf(F, ref["F"]) < 1e-11, (label, r)
+            assert rel_inf(b, ref["b"]) < 1e-11, (label, r)
+        else:
+            assert rel_rms(F, ref["F"]) < 1e-5, (label, r)
+            assert rel_rms(b, ref["b"]) < 3e-5, (label, r)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_matches_oracle_and_graph_replay(case, precision):
+    from paper_2509_24742_amd import binding
+    off, xyz, q, dp, sd = case["inputs"]
+    sysm = case["sys"]
+    print(f"case {case['name']} precision {precision}: sizes {np.diff(off).tolist()} n_ele {case['n_ele']}",
+          flush=True)
+    out = sysm.step(off, xyz, q, dp, sd, STEP, precision=precision, Q_in=case["qin"])
+    torch.cuda.synchronize()
+    assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+    check(case, precision, off, out, f"{case['name']} eager")
+    gr = sysm.capture(off, xyz, q, dp, sd, STEP, precision=precision, Q_in=case["qin"])
+    try:
+        gr.launch()
+        torch.cuda.synchronize()
+        assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+        for key in ("F", "b", "Q", "kset"):
+            assert torch.equal(gr.out[key], out[key]), key
+    finally:
+        gr.close()

@@ -1,4 +1,4 @@
-"""Launch-parameter tuning (srbe_tune / srbe_get_tuning / srbe_set_tuning) through the C ABI.
+"""Launch parameters (srbe_get_tuning / srbe_set_tuning, the cache of choices) through the C ABI.
 
 Every tunable launch shape must give the oracle's results: each setting below is run
 on a three-replica batch of the tiny slab and compared with the FP64 oracle on the
@@ -66,6 +66,10 @@ def check(batch, precision, off, out, label):
             assert rel_rms(b, ref["b"]) < 3e-5 and rel_rms(Q, ref["Q"]) < 3e-5, (label, r)
 
 
+LIVE_TIMING_OFF = pytest.mark.skip(reason="srbe_tune live timing is switched off: processes that ran it "
+                                   "aborted (host heap corruption, cause not found)")
+
+
 # sf_blocks, waves, unroll, ii_ions, ie_blocks, ele_split, gemm_split, gemm_depth
 SETTINGS = [
     [256, 2, 2, 1, 1, 1, 1, 2],
@@ -107,6 +111,22 @@ def test_bad_settings_rejected(batch):
     assert binding.srbe_get_tuning(h, 1, off) == base  # nothing stored
 
 
+def test_live_timing_is_switched_off(batch):
+    # srbe_tune's live timing is switched off (processes that ran it have aborted with
+    # host heap corruption of unknown cause): it returns SRBE_EINVAL with a message
+    # and stores nothing
+    from paper_2509_24742_amd import binding
+    off, xyz, q, dp, sd = batch["inputs"]
+    h = batch["sys"].h
+    defaults = binding.srbe_get_tuning(h, 1, off)
+    with pytest.raises(binding.SrbeError) as ei:
+        binding.srbe_tune(h, 1, off, xyz, q, dp, sd, iters=3)
+    assert ei.value.code == binding.SRBE_EINVAL
+    assert "switched off" in binding.srbe_last_error(h)
+    assert binding.srbe_get_tuning(h, 1, off) == defaults
+
+
+@LIVE_TIMING_OFF
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tune_stores_a_valid_choice(batch, precision):
     from paper_2509_24742_amd import binding
@@ -124,6 +144,7 @@ def test_tune_stores_a_valid_choice(batch, precision):
     assert binding.srbe_get_tuning(h, precision, off) == defaults
 
 
+@LIVE_TIMING_OFF
 def test_tune_cache_round_trip(batch, tmp_path):
     from paper_2509_24742_amd import binding
     off, xyz, q, dp, sd = batch["inputs"]
@@ -136,3 +157,34 @@ def test_tune_cache_round_trip(batch, tmp_path):
     assert second["cached"] and second["params"] == first["params"]
     assert binding.srbe_get_tuning(sysm.h, 1, off) == first["params"]
     binding.srbe_set_tuning(sysm.h, 1, off, None)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cache_hit_applies_stored_choice(batch, precision, tmp_path):
+    # a cache entry for this shape is applied without timing, and the step it gives
+    # matches the oracle; a miss with tune_missing false keeps the defaults and
+    # writes nothing
+    import json
+    import torch as _torch
+    from paper_2509_24742_amd import SRBE_TUNE_NAMES, binding
+    off, xyz, q, dp, sd = batch["inputs"]
+    sysm = batch["sys"]
+    arch = _torch.cuda.get_device_properties(dp.device).gcnArchName
+    key = (f"{arch}|{'fp32' if precision else 'fp64'}|R={len(off) - 1}|maxrep={int(np.diff(off).max())}|"
+           f"n_ele={sysm.n_ele}|P={sysm.params['P']}")
+    chosen = SETTINGS[1]
+    path = tmp_path / "tuning.json"
+    path.write_text(json.dumps({key: dict(params=dict(zip(SRBE_TUNE_NAMES, chosen)), ms_default=None,
+                                          ms_tuned=None)}))
+    try:
+        hit = sysm.tune(off, xyz, q, dp, sd, precision=precision, cache=str(path))
+        assert hit["cached"] and hit["params"] == chosen
+        assert binding.srbe_get_tuning(sysm.h, precision, off) == chosen
+        off_, out = run(batch, precision)
+        check(batch, precision, off_, out, chosen)
+    finally:
+        binding.srbe_set_tuning(sysm.h, precision, off, None)
+    defaults = binding.srbe_get_tuning(sysm.h, precision, off)
+    miss = tmp_path / "empty.json"
+    got = sysm.tune(off, xyz, q, dp, sd, precision=precision, cache=str(miss), tune_missing=False)
+    assert not got["cached"] and got["params"] == defaults and not miss.exists()
