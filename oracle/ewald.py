@@ -118,13 +118,20 @@ def enumerate_modes(p, tol=None):
     return m[keep]
 
 
-def structure_factor(p, m, pos, q, chunk=4096):
-    """Eq. (15): S(k) = sum_j q_j exp(i k.r_j) for every mode m (returns complex (K,))."""
+def structure_factor(p, m, pos, q, chunk=4096, pchunk=65536):
+    """Eq. (15): S(k) = sum_j q_j exp(i k.r_j) for every mode m (returns complex (K,)).
+
+    Particles are taken pchunk at a time (their partial sums added in order), so the
+    phase matrix stays small for large systems.
+    """
     kv = kvectors(p, m)
+    pos = np.asarray(pos)
+    q = np.asarray(q)
     out = np.zeros(len(kv), dtype=np.complex128)
     for s in range(0, len(kv), chunk):
-        ph = np.asarray(pos) @ kv[s:s + chunk].T
-        out[s:s + chunk] = np.asarray(q) @ np.exp(1j * ph)
+        for j in range(0, len(pos), pchunk):
+            ph = pos[j:j + pchunk] @ kv[s:s + chunk].T
+            out[s:s + chunk] += q[j:j + pchunk] @ np.exp(1j * ph)
     return out
 
 
@@ -211,13 +218,17 @@ def wrap_xy(p, pos):
     return pos
 
 
-def real_space(p, kind, tgt, src, src_q, same=False, chunk=512):
+def real_space(p, kind, tgt, src, src_q, same=False, chunk=512, exclude=None):
     """Real-space potential and field of Eq. (13) kernels.
 
     phi_t = sum_s sum_n q_s K(|r_t - r_s - n o l|) over |.| < rc, excluding the
-    s = t, n = 0 term when ``same``.  grad_t = d phi_t / d r_t.
+    s = t, n = 0 term when ``same`` (the sources are the targets), or the
+    s = exclude[t], n = 0 term when ``exclude`` (one source index per target) is
+    given.  grad_t = d phi_t / d r_t.
     Returns (phi (T,), grad (T, 3)).
     """
+    if same:
+        exclude = np.arange(len(tgt))
     K, dK = KERNELS[kind]
     tgt = wrap_xy(p, tgt)
     src = wrap_xy(p, src)
@@ -233,8 +244,8 @@ def real_space(p, kind, tgt, src, src_q, same=False, chunk=512):
             d[..., 1] -= p.Ly * np.round(d[..., 1] / p.Ly)
             r = np.sqrt(np.sum(d * d, axis=2))
             mask = r < p.rc
-            if same:
-                mask[np.arange(len(tb)), np.arange(t0, t0 + len(tb))] = False
+            if exclude is not None:
+                mask[np.arange(len(tb)), exclude[t0:t0 + len(tb)]] = False
             rr = np.where(mask, r, 1.0)
             kv = np.where(mask, K(p, rr), 0.0)
             dk = np.where(mask, dK(p, rr), 0.0)
@@ -248,9 +259,8 @@ def real_space(p, kind, tgt, src, src_q, same=False, chunk=512):
             d = tb[:, None, :] - src[None, :, :] - sh[None, None, :]
             r = np.sqrt(np.sum(d * d, axis=2))
             mask = r < p.rc
-            if same and not np.any(sh):
-                idx = np.arange(t0, t0 + len(tb))
-                mask[np.arange(len(tb)), idx] = False
+            if exclude is not None and not np.any(sh):
+                mask[np.arange(len(tb)), exclude[t0:t0 + len(tb)]] = False
             rr = np.where(mask, r, 1.0)
             kv = np.where(mask, K(p, rr), 0.0)
             dk = np.where(mask, dK(p, rr), 0.0)

@@ -128,6 +128,45 @@ def srbe_ion_forces(p, kset, ion_pos, ion_q, ele_pos, Q):
     return p.coulomb_k * F
 
 
+def _real_chunk(n_src):
+    """Targets per real-space chunk so that a chunk's pair arrays stay near 2^22 entries."""
+    return max(1, (1 << 22) // max(n_src, 1))
+
+
+def srbe_b_at(p, kset, ion_pos, ion_q, ele_pos, idx):
+    """srbe_b at the electrodes ``idx`` only (same terms; for systems too large to do all)."""
+    ion_pos = np.asarray(ion_pos, dtype=np.float64).reshape(-1, 3)
+    ele_pos = np.asarray(ele_pos, dtype=np.float64).reshape(-1, 3)
+    ion_q = np.asarray(ion_q, dtype=np.float64)
+    tgt = ele_pos[np.asarray(idx)]
+    m, w = _combined(p, kset)
+    S1 = ewald.structure_factor(p, m, ion_pos, ion_q)
+    bF = -ewald.fourier_potential(p, m, w * S1, tgt)
+    bS = -(4.0 * np.pi / p.V) * tgt[:, 2] * (ion_q @ ion_pos[:, 2]) if p.slab else 0.0
+    phi, _ = ewald.real_space(p, "ig", tgt, ion_pos, ion_q, chunk=_real_chunk(len(ion_pos)))
+    return p.coulomb_k * (bF + bS - phi)
+
+
+def srbe_ion_forces_at(p, kset, ion_pos, ion_q, ele_pos, Q, idx):
+    """srbe_ion_forces on the ions ``idx`` only (same terms; for systems too large to do all)."""
+    ion_pos = np.asarray(ion_pos, dtype=np.float64).reshape(-1, 3)
+    ele_pos = np.asarray(ele_pos, dtype=np.float64).reshape(-1, 3)
+    ion_q = np.asarray(ion_q, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    idx = np.asarray(idx)
+    tgt, qt = ion_pos[idx], ion_q[idx]
+    m, w = _combined(p, kset)
+    S = ewald.structure_factor(p, m, ion_pos, ion_q) + ewald.structure_factor(p, m, ele_pos, Q)
+    F = -qt[:, None] * ewald.fourier_gradient_term(p, m, w * S, tgt)
+    if p.slab:
+        Mz = ion_q @ ion_pos[:, 2] + Q @ ele_pos[:, 2]
+        F[:, 2] -= (4.0 * np.pi / p.V) * qt * Mz
+    _, gii = ewald.real_space(p, "ii", tgt, ion_pos, ion_q, exclude=idx, chunk=_real_chunk(len(ion_pos)))
+    _, gig = ewald.real_space(p, "ig", tgt, ele_pos, Q, chunk=_real_chunk(len(ele_pos)))
+    F -= qt[:, None] * (gii + gig)
+    return p.coulomb_k * F
+
+
 def srbe_ele_forces(p, kset, ion_pos, ion_q, ele_pos, Q):
     """Forces on the electrode atoms from the same estimator (used for the momentum check)."""
     ion_pos = np.asarray(ion_pos, dtype=np.float64).reshape(-1, 3)

@@ -17,6 +17,8 @@ Cases (square-wall slabs of the large-system recipe, ions at 10 per nm^3 or belo
 * wide: two replicas of 3,000 and 1,502 ions (ragged tiles) in 13.6 x 13.6 x 12 nm
   with 2 x 68 x 68 = 9,248 electrodes (3,630 cells): ions and electrodes both take
   the multi-block sort, for the grid (and the electrodes also for their count).
+* full size: the large slab of 917,504 ions and 131,072 electrodes (155,625 cells),
+  checked at 64 sampled ions and electrodes against stored oracle values.
 """
 
 import numpy as np
@@ -103,3 +105,53 @@ def test_large_matches_oracle_and_graph_replay(case, precision):
             assert torch.equal(gr.out[key], out[key]), key
     finally:
         gr.close()
+
+
+# ---------------------------------------------------------------- the full-size large slab
+
+@pytest.fixture(scope="module")
+def full():
+    # 917,504 ions and 131,072 electrodes (2 x 256 x 256 walls) in 30 x 30 x 100 nm, M = 64,
+    # P = 500, fixed charges; oracle values at 64 sampled ions and electrodes come from
+    # tests/golden/large_slab_sample.json (written by make_large_slab_sample.py beside it)
+    import json
+    import os
+    import sys
+    import paper_2509_24742_amd as srbe_amd
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gdir)
+    import make_large_slab_sample as golden
+    with open(os.path.join(gdir, "large_slab_sample.json")) as f:
+        ref = json.load(f)
+    w, Q, ii, ie = golden.inputs()
+    assert float(np.sum(w["ion_pos"] * np.arange(1, 4))) == ref["ion_pos_checksum"]
+    assert ii.tolist() == ref["ion_index"] and ie.tolist() == ref["ele_index"]
+    wp = dict(w["params"], kspace_tol=1e-16)
+    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
+    inputs = gpu_inputs([w["ion_pos"]], [w["ion_q"]], [w["dpsi"]], [ref["seed"]])
+    yield dict(sys=sysm, ref=ref, inputs=inputs, qin=torch.tensor(Q, device="cuda"), p=oracle_params(wp),
+               ii=ii, ie=ie)
+    sysm.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_large_slab_at_sampled_targets(full, precision):
+    from paper_2509_24742_amd import binding
+    off, xyz, q, dp, sd = full["inputs"]
+    ref = full["ref"]
+    sysm = full["sys"]
+    print(f"full-size large slab, precision {precision}: {ref['n_ion']} ions, {ref['n_ele']} electrodes", flush=True)
+    out = sysm.step(off, xyz, q, dp, sd, ref["step"], precision=precision, Q_in=full["qin"])
+    torch.cuda.synchronize()
+    assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+    ks, _ = sampler.draw_kset(full["p"], ref["seed"], 0, ref["step"])
+    assert np.array_equal(out["kset"].cpu().numpy(), ks.astype(np.int32).ravel())
+    F = forces_from_soa(out["F"], off, 0)[full["ii"]]
+    b = out["b"].cpu().numpy()[full["ie"]]
+    Fr, br = np.asarray(ref["F"]), np.asarray(ref["b"])
+    print(f"  sampled force {rel_rms(F, Fr):.2e} rms {rel_inf(F, Fr):.2e} max, b {rel_rms(b, br):.2e} rms",
+          flush=True)
+    if precision == 0:
+        assert rel_inf(F, Fr) < 1e-11 and rel_inf(b, br) < 1e-11
+    else:
+        assert rel_rms(F, Fr) < 1e-5 and rel_rms(b, br) < 3e-5

@@ -384,6 +384,27 @@ def test_srbe_deterministic_part_is_exact():
     assert np.allclose(bI, p.coulomb_k * ref, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("rc", [0.6, 0.8])  # 0.6: minimum image; 0.8 > L/2: several images per pair
+def test_sampled_targets_match_the_full_functions(rc):
+    # The sampled-target forms (for systems too large to evaluate every target) give
+    # the full functions' values at the sampled targets, and the particle-chunked
+    # structure factor the one-chunk sum: the same terms, summed in another order.
+    import dataclasses
+    p, ion, q, ele, side = tiny_system(n_ion=12)
+    p = dataclasses.replace(p, rc=rc)
+    ks, _ = sampler.draw_kset(p, seed=3, stream=0, step=1)
+    Q = np.random.default_rng(2).normal(size=len(ele)) * 0.05
+    ii = np.array([7, 0, 11, 3])
+    ie = np.array([17, 2, 9])
+    F = srbe.srbe_ion_forces(p, ks, ion, q, ele, Q)
+    b = srbe.srbe_b(p, ks, ion, q, ele)
+    assert np.allclose(srbe.srbe_ion_forces_at(p, ks, ion, q, ele, Q, ii), F[ii], rtol=1e-13, atol=1e-13)
+    assert np.allclose(srbe.srbe_b_at(p, ks, ion, q, ele, ie), b[ie], rtol=1e-13, atol=1e-13)
+    m, _ = srbe._combined(p, ks)
+    assert np.allclose(ewald.structure_factor(p, m, ion, q, pchunk=5), ewald.structure_factor(p, m, ion, q),
+                       rtol=0, atol=1e-13)
+
+
 def test_momentum_conserved_per_sample(cp_system):
     p, ion, q, ele, side, A, b, sol = cp_system
     ks, _ = sampler.draw_kset(p, seed=5, stream=0, step=2)
