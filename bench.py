@@ -88,6 +88,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
     ap.add_argument("--no-tune", action="store_true",
                     help="time with the default launch parameters")
+    ap.add_argument("--large-slab", type=int, default=0, metavar="P",
+                    help="also time the full-size large slab (917,504 ions, 131,072 electrodes, M=64) with this "
+                         "batch size P (500 or 2000), at fixed electrode charges; reported as large_slab")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -289,6 +292,9 @@ def main():
         "launch_tuning": tuning,
     }
 
+    if args.large_slab:
+        result["large_slab"] = large_slab_bench(args, srbe_amd, stream)
+
     if not args.no_cpu:
         o = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, want_kset=False)
         torch.cuda.synchronize()
@@ -300,6 +306,55 @@ def main():
                                                                seeds, n_ele))
     print(json.dumps(result), flush=True)
     sysm.close()
+
+
+def large_slab_bench(args, srbe_amd, stream):
+    """Steps of the full-size large slab (one system, fixed electrode charges: its dense
+    charge solve would need a 131,072^2 matrix), FP32 and FP64, as graph replays."""
+    import torch
+    from paper_2509_24742_amd import workloads as wl
+    t0 = time.time()
+    w = wl.large_slab(P=args.large_slab)
+    gen_s = time.time() - t0
+    wp = dict(w["params"], kspace_tol=1e-16)
+    t0 = time.time()
+    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
+    setup_s = time.time() - t0
+    dev = torch.device("cuda")
+    n_ion, n_ele = len(w["ion_q"]), len(w["ele_side"])
+    off = np.array([0, n_ion], dtype=np.int64)
+    xyz = torch.tensor(np.ascontiguousarray(w["ion_pos"].T).ravel(), dtype=torch.float64, device=dev)
+    q = torch.tensor(w["ion_q"], dtype=torch.float64, device=dev)
+    dp = torch.tensor([w["dpsi"]], dtype=torch.float64, device=dev)
+    sd = torch.tensor([81], dtype=torch.int64, device=dev).view(torch.uint64)
+    Q = torch.tensor(w["ele_side"] * 0.004, dtype=torch.float64, device=dev)
+    steps = max(5, min(args.steps, 50))
+    out = {"workload": f"large slab: {n_ion} ions, {n_ele} electrode atoms (2x256x256), 30x30x100 nm, "
+                       f"M={wp['M']}, P={wp['P']}, fixed electrode charges", "steps": steps,
+           "workload_generation_s": gen_s, "setup_s": setup_s}
+    pairs = (n_ion + n_ele) * (wp["M"] + wp["P"])
+    for name, prec in [("fp32", srbe_amd.SRBE_FP32), ("fp64", srbe_amd.SRBE_FP64)]:
+        gr = sysm.capture(off, xyz, q, dp, sd, 0, precision=prec, Q_in=Q, want_kset=False)
+        for _ in range(3):
+            gr.launch()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            gr.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        code = srbe_amd.srbe_sync_status(sysm.h)
+        if code != 0:
+            raise RuntimeError(srbe_amd.srbe_last_error(sysm.h))
+        gr.close()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "steps_per_s": 1e3 / ms}
+        log(f"large slab {name}: {ms:.3f} ms/step")
+    out["pairs_per_step"] = pairs
+    sysm.close()
+    return out
 
 
 def count_pairs(wb, wp):

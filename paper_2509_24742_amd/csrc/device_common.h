@@ -41,6 +41,7 @@ __host__ __device__ inline int ldcp(int n) { return (n + 31) & ~31; }
 constexpr int kMaxBinParticles = 8192;  // particles per replica the one-block cell sort handles
 constexpr int kMaxCells = 2048;         // cells the one-block cell sort handles
 constexpr int kMaxGridCells = 1 << 18;  // cells of the real-space grid (coarsened beyond)
+static_assert((kMaxGridCells + 1024) / 1024 <= 1024, "the sort scans the chunk totals in one block round");
 // Neighbour runs per cell: the cells within reach of a cell, sorted, as runs of
 // consecutive cell indices (whose particles are adjacent in the cell-sorted order).
 // At most 7 z-layers (nzs <= 3) x 3 rows x 2 pieces (a periodic wrap splits a row).

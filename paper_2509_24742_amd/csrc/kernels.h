@@ -21,7 +21,9 @@ struct BigSort {
   int* count;     // R*(ncell+1) cell counts, then per-cell cursors
   int* prov;      // N provisional cell order (indices within the replica)
   double* tsum;   // R*ntile*4 charge sums per tile of 256 particles (ions)
+  int* ctot;      // R*nchunk totals, then offsets, of the chunks of 1024 cells
   int ntile;      // tiles of 256 particles per replica
+  int nchunk;     // chunks of 1024 cells: (ncell + 1024) / 1024 <= 1024
 };
 
 // Per-step device pointers and sizes.

@@ -497,7 +497,8 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.ii_ipw = tp[SRBE_TUNE_II_IONS];
   b.ie_nbx = tp[SRBE_TUNE_IE_BLOCKS];
   b.esplit = tp[SRBE_TUNE_ELE_SPLIT];
-  b.bigsort = BigSort{nullptr, nullptr, nullptr, use_big_sort(h->g, max_nrep) ? (int)((std::max<int64_t>(max_nrep, 1) + 255) / 256) : 0};
+  b.bigsort = BigSort{nullptr, nullptr, nullptr, nullptr, 0, (h->g.ncell + 1024) / 1024};
+  if (use_big_sort(h->g, max_nrep)) b.bigsort.ntile = (int)((std::max<int64_t>(max_nrep, 1) + 255) / 256);
   b.ion_xyz = a.ion_xyz;
   b.ion_q = a.ion_q;
   b.dpsi = a.dpsi;
@@ -579,6 +580,7 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.bigsort.count, b.bigsort.ntile ? (size_t)R * (g.ncell + 1) * sizeof(int) : 0},
       {(void**)&b.bigsort.prov, b.bigsort.ntile ? (size_t)N1 * sizeof(int) : 0},
       {(void**)&b.bigsort.tsum, b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0},
+      {(void**)&b.bigsort.ctot, b.bigsort.ntile ? (size_t)R * b.bigsort.nchunk * sizeof(int) : 0},
   };
   size_t total = 0;
   for (const Item& it : items) {
@@ -811,12 +813,14 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
       (void)hipFree(off2);
       return fail(SRBE_EHIP);
     }
-    BigSort ebs{nullptr, nullptr, nullptr, 0};
+    BigSort ebs{nullptr, nullptr, nullptr, nullptr, 0, (g.ncell + 1024) / 1024};
     if (use_big_sort(g, n_ele)) {
       ebs.ntile = (n_ele + 255) / 256;
       if (hipMalloc((void**)&ebs.count, (size_t)(g.ncell + 1) * sizeof(int)) != hipSuccess ||
-          hipMalloc((void**)&ebs.prov, n * sizeof(int)) != hipSuccess) {
+          hipMalloc((void**)&ebs.prov, n * sizeof(int)) != hipSuccess ||
+          hipMalloc((void**)&ebs.ctot, (size_t)ebs.nchunk * sizeof(int)) != hipSuccess) {
         if (ebs.count) (void)hipFree(ebs.count);
+        if (ebs.prov) (void)hipFree(ebs.prov);
         (void)hipFree(off2);
         return fail(SRBE_ENOMEM);
       }
@@ -830,6 +834,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     const hipError_t se = hipDeviceSynchronize();
     if (ebs.count) (void)hipFree(ebs.count);
     if (ebs.prov) (void)hipFree(ebs.prov);
+    if (ebs.ctot) (void)hipFree(ebs.ctot);
     if (se != hipSuccess ||
         hipMemcpy(czr.data(), h->ele_czr, czr.size() * sizeof(double2), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(perm.data(), h->ele_perm, n * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) {

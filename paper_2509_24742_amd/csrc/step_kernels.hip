@@ -179,14 +179,14 @@ __device__ __forceinline__ void sort_block(const Geom& g, int r, const SortArgs&
 // Multi-block cell sort, for replicas of more than kMaxBinParticles particles or grids
 // of more than kMaxCells cells.  It gives sort_block's order (cells in index order,
 // each cell's particles in index order) from five launches over tiles of 256
-// particles: the cell counts are cleared; each particle's records and cell, the
-// counts by integer atomics in device memory and each tile's charge sums; per replica
-// (one block) the tile sums added in tile order and the exclusive scan of the counts
-// (the cell starts; the counts become per-cell cursors); a provisional slot per
-// particle from its cell's cursor (the order inside a cell depends on timing); and
-// the final position inside the cell, the number of the cell's entries with a
-// smaller index, with the records in cell order.  The time of the last pass grows
-// with the square of the largest cell's count.
+// particles (and three over chunks of 1024 cells): the cell counts are cleared;
+// each particle's records and cell, the counts by integer atomics in device memory
+// and each tile's charge sums; the exclusive scan of the counts (the cell starts; the
+// counts become per-cell cursors) with the tile sums added in tile order; a
+// provisional slot per particle from its cell's cursor (the order inside a cell
+// depends on timing); and the final position inside the cell, the number of the
+// cell's entries with a smaller index, with the records in cell order.  The time of
+// the last pass grows with the square of the largest cell's count.
 __global__ __launch_bounds__(256) void k_zero_int(int* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
 }
@@ -211,11 +211,47 @@ __global__ __launch_bounds__(256) void k_bigsort_count(Geom g, SortArgs a, BigSo
   }
 }
 
+// Exclusive scan of the cell counts in three launches, so that the counts (just
+// written by device-scope atomics) are read by many CUs at once rather than by one:
+// each block of 1024 cells scans its chunk and records the chunk's total; per
+// replica one block adds the tile charge sums in tile order and scans the chunk
+// totals into chunk offsets; then each cell start gets its chunk's offset and the
+// counts become per-cell cursors.
+__device__ __forceinline__ int block_exclusive_scan_1024(int x, int& total, int* wtot) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wtot[wv] = incl;
+  __syncthreads();
+  int below = 0;
+  total = 0;
+  for (int u = 0; u < 16; ++u) {
+    below += u < wv ? wtot[u] : 0;
+    total += wtot[u];
+  }
+  return below + incl - x;
+}
+
+__global__ __launch_bounds__(1024) void k_bigsort_scan_chunks(Geom g, SortArgs a, BigSort bs) {
+  __shared__ int wtot[16];
+  const int r = blockIdx.x / bs.nchunk, ch = blockIdx.x - r * bs.nchunk;
+  const int c = ch * 1024 + (int)threadIdx.x;
+  const int* cnt = bs.count + (size_t)r * (g.ncell + 1);
+  int total;
+  const int excl = block_exclusive_scan_1024(c < g.ncell ? cnt[c] : 0, total, wtot);
+  if (c <= g.ncell) a.cstart[(size_t)r * (g.ncell + 1) + c] = excl;
+  if (threadIdx.x == 0) bs.ctot[(size_t)r * bs.nchunk + ch] = total;
+}
+
 template <int REC>
-__global__ __launch_bounds__(1024) void k_bigsort_scan(Geom g, SortArgs a, BigSort bs) {
+__global__ __launch_bounds__(1024) void k_bigsort_scan_totals(Geom g, SortArgs a, BigSort bs) {
   __shared__ double red[4][16];
   __shared__ int wtot[16];
-  const int r = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int r = blockIdx.x, t = threadIdx.x;
   if constexpr (REC != 3) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int u = t; u < bs.ntile; u += 1024)
@@ -226,33 +262,20 @@ __global__ __launch_bounds__(1024) void k_bigsort_scan(Geom g, SortArgs a, BigSo
       if (fabs(v[0]) > 1e-10 * v[1]) atomicOr(a.status, ST_NONNEUTRAL);
     }
   }
-  int* cnt = bs.count + (size_t)r * (g.ncell + 1);
-  int* cs = a.cstart + (size_t)r * (g.ncell + 1);
-  int carry = 0;
-  for (int c0 = 0; c0 <= g.ncell; c0 += 1024) {
-    const int c = c0 + t;
-    const int x = c < g.ncell ? cnt[c] : 0;
-    int incl = x;  // inclusive scan inside the wave
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) wtot[wv] = incl;
-    __syncthreads();
-    int below = 0, total = 0;
-    for (int u = 0; u < 16; ++u) {
-      below += u < wv ? wtot[u] : 0;
-      total += wtot[u];
-    }
-    if (c <= g.ncell) {
-      const int start = carry + below + incl - x;
-      cs[c] = start;
-      cnt[c] = start;  // cursor
-    }
-    carry += total;
-    __syncthreads();
-  }
+  int* ct = bs.ctot + (size_t)r * bs.nchunk;  // nchunk <= 1024: one round
+  int total;
+  const int excl = block_exclusive_scan_1024(t < bs.nchunk ? ct[t] : 0, total, wtot);
+  if (t < bs.nchunk) ct[t] = excl;
+}
+
+__global__ __launch_bounds__(1024) void k_bigsort_scan_offsets(Geom g, SortArgs a, BigSort bs) {
+  const int r = blockIdx.x / bs.nchunk, ch = blockIdx.x - r * bs.nchunk;
+  const int c = ch * 1024 + (int)threadIdx.x;
+  if (c > g.ncell) return;
+  const size_t at = (size_t)r * (g.ncell + 1) + c;
+  const int start = a.cstart[at] + bs.ctot[(size_t)r * bs.nchunk + ch];
+  a.cstart[at] = start;
+  bs.count[at] = start;  // cursor
 }
 
 template <int REC>
@@ -294,7 +317,10 @@ static void launch_big_sort(const Geom& g, const SortArgs& sa, const BigSort& bs
   hipLaunchKernelGGL(k_zero_int, dim3(std::min(4096, cdiv64(ncount, 256))), dim3(256), 0, s, bs.count, ncount);
   const dim3 tiles((unsigned)R * bs.ntile);
   hipLaunchKernelGGL(k_bigsort_count<REC>, tiles, dim3(256), 0, s, g, sa, bs);
-  hipLaunchKernelGGL(k_bigsort_scan<REC>, dim3(R), dim3(1024), 0, s, g, sa, bs);
+  const dim3 chunks((unsigned)R * bs.nchunk);
+  hipLaunchKernelGGL(k_bigsort_scan_chunks, chunks, dim3(1024), 0, s, g, sa, bs);
+  hipLaunchKernelGGL(k_bigsort_scan_totals<REC>, dim3(R), dim3(1024), 0, s, g, sa, bs);
+  hipLaunchKernelGGL(k_bigsort_scan_offsets, chunks, dim3(1024), 0, s, g, sa, bs);
   hipLaunchKernelGGL(k_bigsort_scatter<REC>, tiles, dim3(256), 0, s, g, sa, bs);
   hipLaunchKernelGGL(k_bigsort_rank<REC>, tiles, dim3(256), 0, s, g, sa, bs);
 }
@@ -1807,16 +1833,32 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
   finish(kend - 1, acc.p);
 }
 
-// One replica's blocks all run on one XCD (blocks are dealt to the 8 XCDs in turn by
-// launch index), so the replica's records are fetched into one L2 only:
-// launch block L goes to XCD L mod 8 and takes block bx of replica r = L mod 8 + 8 m.
+// Blocks are dealt to the 8 XCDs in turn by launch index (launch block L runs on XCD
+// L mod 8), and each XCD has its own L2.  With 8 or more replicas, one replica's
+// blocks all run on one XCD, so its records are fetched into one L2 only: block L
+// takes block bx of replica r = L mod 8 + 8 m.  With fewer replicas that would leave
+// XCDs idle; instead the (replica, block) items in order are cut into 8 contiguous
+// ranges, one per XCD, so each L2 holds the records of a slab of consecutive cells
+// (plus the stencil's reach) rather than of the whole system.  A wave's work depends
+// only on (r, bx), so the mapping does not change results.
 template <bool FP32>
 __global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) {
   __shared__ __align__(16) unsigned char lds[ring_bytes<FP32>()];
-  const int L = blockIdx.x, j = L >> 3, m = j / tiles;
-  const int r = (L & 7) + 8 * m;
+  const int L = blockIdx.x, j = L >> 3;
+  int r, bx;
+  if (b.R >= 8) {
+    const int m = j / tiles;
+    r = (L & 7) + 8 * m;
+    bx = j - m * tiles;
+  } else {
+    const int items = b.R * tiles, per = (items + 7) >> 3;
+    const int item = (L & 7) * per + j;
+    if (item >= items) return;
+    r = item / tiles;
+    bx = item - r * tiles;
+  }
   if (r >= b.R) return;
-  real_ii_block<FP32>(g, b, j - m * tiles, r, lds);
+  real_ii_block<FP32>(g, b, bx, r, lds);
 }
 
 static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * b.ii_ipw); }
@@ -1824,7 +1866,7 @@ static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep,
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   const int tiles = real_ii_tiles(b);
-  const dim3 grid(8 * ((b.R + 7) / 8) * tiles);
+  const dim3 grid(b.R >= 8 ? 8 * ((b.R + 7) / 8) * tiles : 8 * ((b.R * tiles + 7) / 8));
   if (fp32)
     hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b, tiles);
   else
@@ -2096,6 +2138,10 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
   const double* __restrict__ scal = b.scal;
   const double* __restrict__ rsum = b.rsum;
   double v[2] = {0.0, 0.0};
+  if (fixedQ) {  // no energy without the charge solve: nothing to sum
+    if (threadIdx.x == 0) b.energy_out[r] = (double)NAN;
+    return;
+  }
   if (b.real) {  // the ion-ion real-space energy (left out in k-space-only steps)
 #pragma unroll 8
     for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
@@ -2109,8 +2155,8 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
     const double c = 0.5 * v[0] + 0.5 * v[1] - g.ke * g.alpha * INV_SQRT_PI * scal[4 * r + 3] +
                      g.ke * (2.0 * M_PI / g.V) * scal[4 * r + 2] * scal[4 * r + 2];
     const double E = 0.5 * b.dpsi[r] * rsum_total(rsum, r, 1) - 0.5 * rsum_total(rsum, r, 2) + c;
-    if (!fixedQ && !isfinite(E)) atomicOr(b.status, ST_NUMERIC);
-    b.energy_out[r] = fixedQ ? (double)NAN : E;
+    if (!isfinite(E)) atomicOr(b.status, ST_NUMERIC);
+    b.energy_out[r] = E;
   }
 }
 
