@@ -90,7 +90,7 @@ def parse():
                     help="time with the default launch parameters")
     ap.add_argument("--large-slab", type=int, default=0, metavar="P",
                     help="also time the full-size large slab (917,504 ions, 131,072 electrodes, M=64) with this "
-                         "batch size P (500 or 2000), at fixed electrode charges; reported as large_slab")
+                         "batch size P (500 or 2000), charges by the lattice solve; reported as large_slab")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -309,8 +309,8 @@ def main():
 
 
 def large_slab_bench(args, srbe_amd, stream):
-    """Steps of the full-size large slab (one system, fixed electrode charges: its dense
-    charge solve would need a 131,072^2 matrix), FP32 and FP64, as graph replays."""
+    """Steps of the full-size large slab (one system; the charge update by the lattice solve,
+    since the dense one would need a 131,072^2 matrix), FP32 and FP64, as graph replays."""
     import torch
     from paper_2509_24742_amd import workloads as wl
     t0 = time.time()
@@ -318,7 +318,7 @@ def large_slab_bench(args, srbe_amd, stream):
     gen_s = time.time() - t0
     wp = dict(w["params"], kspace_tol=1e-16)
     t0 = time.time()
-    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
+    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
     setup_s = time.time() - t0
     dev = torch.device("cuda")
     n_ion, n_ele = len(w["ion_q"]), len(w["ele_side"])
@@ -327,14 +327,13 @@ def large_slab_bench(args, srbe_amd, stream):
     q = torch.tensor(w["ion_q"], dtype=torch.float64, device=dev)
     dp = torch.tensor([w["dpsi"]], dtype=torch.float64, device=dev)
     sd = torch.tensor([81], dtype=torch.int64, device=dev).view(torch.uint64)
-    Q = torch.tensor(w["ele_side"] * 0.004, dtype=torch.float64, device=dev)
     steps = max(5, min(args.steps, 50))
     out = {"workload": f"large slab: {n_ion} ions, {n_ele} electrode atoms (2x256x256), 30x30x100 nm, "
-                       f"M={wp['M']}, P={wp['P']}, fixed electrode charges", "steps": steps,
+                       f"M={wp['M']}, P={wp['P']}, constant potential (lattice charge solve)", "steps": steps,
            "workload_generation_s": gen_s, "setup_s": setup_s}
     pairs = (n_ion + n_ele) * (wp["M"] + wp["P"])
     for name, prec in [("fp32", srbe_amd.SRBE_FP32), ("fp64", srbe_amd.SRBE_FP64)]:
-        gr = sysm.capture(off, xyz, q, dp, sd, 0, precision=prec, Q_in=Q, want_kset=False)
+        gr = sysm.capture(off, xyz, q, dp, sd, 0, precision=prec, want_kset=False)
         for _ in range(3):
             gr.launch()
         torch.cuda.synchronize()

@@ -56,6 +56,8 @@ extern "C" {
 
 #define SRBE_FLAG_NO_CP 1 /* skip the electrode matrix: only fixed-charge steps      */
 #define SRBE_FLAG_KSPACE_ONLY 2 /* leave out the real-space erfc terms (see below)   */
+#define SRBE_FLAG_LATTICE_SOLVE 4 /* electrodes on two rectangular lattices: solve the
+                                     charges in lattice Fourier space (see below)     */
 
 typedef struct srbe_params {
   double Lx, Ly, H;   /* box (length); electrodes and ions have 0 <= z <= H           */
@@ -89,8 +91,18 @@ typedef struct srbe_system srbe_system;
  * erfc terms of Eq. (13) -- the real-space part of b (Eq. (19)), the real-space
  * forces and the ion-ion real-space energy -- and skip their passes: for use beside
  * a pair code that computes them, and to attribute errors to the two parts (A, if
- * built, stays complete).  On success *out receives the handle; on failure *out is
- * NULL.
+ * built, stays complete).
+ * With SRBE_FLAG_LATTICE_SOLVE set, the electrodes must form two walls (two distinct
+ * z), each a complete nx x ny rectangular lattice of spacing (Lx/nx, Ly/ny) with the
+ * same nx, ny on both walls and any in-plane offset per wall, and rc < min(Lx, Ly)/2.
+ * A (Eq. (18)) is then block-circulant over the lattice: it is never formed, and the
+ * charge update of Eqs. (9)-(11) runs per in-plane lattice mode (p, q) as a 2 x 2
+ * solve between discrete Fourier transforms over the walls, with O(n_ele) memory.
+ * Results equal the dense solve's to rounding, except where sites lie exactly rc
+ * apart: the dense build decides each such pair from rounded coordinate differences
+ * (A is then not exactly block-circulant), the lattice solve from the lattice
+ * displacement.  Not a lattice: SRBE_EINVAL.
+ * On success *out receives the handle; on failure *out is NULL.
  * Errors: SRBE_EINVAL, SRBE_ENOTSPD (A not positive definite, e.g. two electrodes
  * at one position), SRBE_ENOMEM, SRBE_EHIP.
  */

@@ -22,6 +22,7 @@ SRBE_FP64 = 0
 SRBE_FP32 = 1
 SRBE_FLAG_NO_CP = 1
 SRBE_FLAG_KSPACE_ONLY = 2
+SRBE_FLAG_LATTICE_SOLVE = 4
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsrbe.so")
 

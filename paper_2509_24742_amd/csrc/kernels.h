@@ -26,6 +26,20 @@ struct BigSort {
   int nchunk;     // chunks of 1024 cells: (ncell + 1024) / 1024 <= 1024
 };
 
+// Charge solve over two electrode lattices (SRBE_FLAG_LATTICE_SOLVE; nx 0: not used).
+// Sites (w, iy, ix) of wall w; modes (p, q) with p along x.
+struct LatticeSolve {
+  int nx, ny;               // sites per wall along x and y (<= 1024 each)
+  const int* site;          // 2*ny*nx electrode index of site (w, iy, ix)
+  const double2* tw_x;      // nx: exp(-2 pi i j / nx)
+  const double2* tw_y;      // ny: exp(-2 pi i j / ny)
+  const double2* linv;      // ny*nx*4: Lambda(p, q)^-1 (00, 01, 10, 11) at (q nx + p) 4
+  double c0, c1;            // A^-1 e on wall 0 and wall 1 (constant on each)
+  double etc;               // e^T A^-1 e
+  double2* T;               // workspace R*2*ny*nx: transforms along x
+  double2* U;               // workspace R*2*ny*nx: solved modes, inverted along y
+};
+
 // Per-step device pointers and sizes.
 struct StepBufs {
   int R;                    // replicas
@@ -101,6 +115,7 @@ struct StepBufs {
   double* Fie;              // 3N ion-electrode real-space force sums, written for ions of reach cells only
   unsigned* status;
   BigSort bigsort;          // multi-block cell sort workspace (count null: one-block sort)
+  LatticeSolve lat;         // lattice charge solve (lat.nx 0: the dense GEMM)
   // outputs
   double* Q_out;
   double* F_out;
@@ -126,6 +141,8 @@ int cp_gemm_ksplit(int n_ele, int R);
 int ele_split(int units);
 // nothing is launched if Sext is null (fixed charges)
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
+// the lattice charge solve: (Q; psibar) of every replica into Qext (one k-range)
+void launch_lattice_solve(const Geom& g, const StepBufs& b, hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);

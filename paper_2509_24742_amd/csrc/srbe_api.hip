@@ -6,6 +6,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -46,6 +47,14 @@ struct srbe_system {
   uint4* ele_sfx = nullptr;    // sorted fixed point
   double4* ele_sd4 = nullptr;  // sorted fractional coordinates
   double* Sext = nullptr;      // (n+1) x ldcp(n) row-major: J A^-1 and the psibar row
+  // lattice charge solve (SRBE_FLAG_LATTICE_SOLVE): the two walls' lattices
+  bool lattice = false;
+  int lat_nx = 0, lat_ny = 0;
+  double lat_o[2][3] = {};     // position of site (0, 0) of each wall
+  int* lat_site = nullptr;     // 2*ny*nx electrode index of site (w, iy, ix)
+  double2* lat_tw = nullptr;   // nx + ny twiddles (x then y)
+  double2* lat_linv = nullptr; // ny*nx*4 inverse 2 x 2 blocks
+  double lat_c[2] = {0.0, 0.0}, lat_etc = 0.0;
   unsigned* status = nullptr;
   rocblas_handle blas = nullptr;
   // the step is a small DAG over three streams: the caller's (records, k-space chain,
@@ -142,7 +151,7 @@ std::string check_params(const srbe_params* p) {
   if (!(p->kspace_tol > 0.0 && p->kspace_tol < 1.0)) return "kspace_tol must lie in (0, 1)";
   if (p->M < 0 || p->P < 0) return "M and P must be >= 0";
   if (p->P > 2048) return "P must be <= 2048";
-  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY)) return "unknown flag";
+  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY | SRBE_FLAG_LATTICE_SOLVE)) return "unknown flag";
   if (p->reserved != 0) return "reserved must be 0";
   return "";
 }
@@ -328,6 +337,217 @@ int build_electrode_solve(srbe_system* h, hipStream_t s) {
   return rc;
 }
 
+// Electrodes on two walls, each a complete nx x ny rectangular lattice of spacing
+// (Lx/nx, Ly/ny), nx and ny the same on both walls: fills h->lat_* and the site table
+// (host).  Returns an empty string, else why not.
+std::string detect_lattice(srbe_system* h, const double* xyz, int n, std::vector<int>& site) {
+  const double Lx = h->p.Lx, Ly = h->p.Ly, H = h->p.H;
+  if (n < 2 || n % 2) return "an odd number of electrodes";
+  const double ztol = 1e-9 * std::max(1.0, H);
+  double zlo = xyz[2 * (size_t)n], zhi = zlo;
+  for (int j = 0; j < n; ++j) {
+    zlo = std::min(zlo, xyz[2 * (size_t)n + j]);
+    zhi = std::max(zhi, xyz[2 * (size_t)n + j]);
+  }
+  if (zhi - zlo <= ztol) return "the electrodes do not form two walls";
+  std::vector<int> wall(n);
+  std::vector<int> members[2];
+  for (int j = 0; j < n; ++j) {
+    const double z = xyz[2 * (size_t)n + j];
+    if (std::fabs(z - zlo) <= ztol) wall[j] = 0;
+    else if (std::fabs(z - zhi) <= ztol) wall[j] = 1;
+    else return "electrodes at more than two heights";
+    members[wall[j]].push_back(j);
+  }
+  if (members[0].size() != members[1].size()) return "the two walls differ in size";
+  auto wrap = [](double x, double L) { return x - L * std::floor(x / L); };
+  auto distinct = [](std::vector<double> v, double tol) {
+    std::sort(v.begin(), v.end());
+    int c = 0;
+    for (size_t u = 0; u < v.size(); ++u)
+      if (u == 0 || v[u] - v[u - 1] > tol) ++c;
+    return c;
+  };
+  int nx = 0, ny = 0;
+  for (int w = 0; w < 2; ++w) {
+    std::vector<double> xs, ys;
+    for (int j : members[w]) {
+      xs.push_back(wrap(xyz[j], Lx));
+      ys.push_back(wrap(xyz[(size_t)n + j], Ly));
+    }
+    const int cx = distinct(xs, 1e-9 * Lx), cy = distinct(ys, 1e-9 * Ly);
+    if (w == 0) {
+      nx = cx;
+      ny = cy;
+    } else if (cx != nx || cy != ny) {
+      return "the walls' lattices differ";
+    }
+  }
+  if ((size_t)nx * ny != members[0].size()) return "a wall is not a complete rectangular lattice";
+  if (nx > 1024 || ny > 1024) return "more than 1024 sites along an axis";
+  const double ax = Lx / nx, ay = Ly / ny;
+  site.assign((size_t)2 * nx * ny, -1);
+  for (int w = 0; w < 2; ++w) {
+    // site (0, 0): the smallest wrapped x, then y
+    double ox = Lx, oy = Ly;
+    for (int j : members[w]) ox = std::min(ox, wrap(xyz[j], Lx));
+    for (int j : members[w]) oy = std::min(oy, wrap(xyz[(size_t)n + j], Ly));
+    for (int j : members[w]) {
+      const double fx = (wrap(xyz[j], Lx) - ox) / ax, fy = (wrap(xyz[(size_t)n + j], Ly) - oy) / ay;
+      const long ix = std::lround(fx), iy = std::lround(fy);
+      if (std::fabs(fx - ix) > 1e-6 || std::fabs(fy - iy) > 1e-6 || ix < 0 || ix >= nx || iy < 0 || iy >= ny)
+        return "a wall's sites are not on a lattice of spacing (Lx/nx, Ly/ny)";
+      int& slot = site[((size_t)w * ny + iy) * nx + ix];
+      if (slot >= 0) return "two electrodes on one lattice site";
+      slot = j;
+    }
+    h->lat_o[w][0] = ox;
+    h->lat_o[w][1] = oy;
+    h->lat_o[w][2] = w == 0 ? zlo : zhi;
+  }
+  h->lat_nx = nx;
+  h->lat_ny = ny;
+  return "";
+}
+
+// Lambda(p, q) of the lattice solve: the 2 x 2 Hermitian blocks
+//   Lambda_ww'(p, q) = sum_{d mod (nx, ny)} A_ww'(d) exp(-2 pi i (p dx / nx + q dy / ny)),
+// A_ww'(d) the entry of A (Eq. (18), the same terms as the dense build) between site
+// (0, 0) of wall w' and site d of wall w.  Its parts:
+//   k-space: every mode m (the dense build's set, its half-space with weight 2w) adds
+//     ke w nx ny exp(i phi) to the mode (m_x mod nx, m_y mod ny) and exp(-i phi) to
+//     (-m_x, -m_y), phi = k . (o_w - o_w') (the lattice sums of the phases collapse);
+//   real space: the Gaussian-Gaussian kernel at each lattice displacement closer than
+//     rc (nearest image, as in the dense build), transformed directly;
+//   self: the diagonal constant on every mode; slab: nx ny (4 pi / V) z_w z_w' at (0, 0).
+// Inverted per mode on the host; A^-1 e = Lambda(0, 0)^-1 (1, 1) on the two walls.
+int build_lattice_solve(srbe_system* h, const std::vector<int>& site) {
+  const srbe_params& p = h->p;
+  const Geom& g = h->g;
+  const int nx = h->lat_nx, ny = h->lat_ny;
+  const size_t nm = (size_t)nx * ny;
+  const double ke = p.coulomb_k, V = g.V;
+  const double dox = h->lat_o[0][0] - h->lat_o[1][0], doy = h->lat_o[0][1] - h->lat_o[1][1];
+  const double doz = h->lat_o[0][2] - h->lat_o[1][2];
+  using cd = std::complex<double>;
+  std::vector<double> L00(nm, 0.0), L11(nm, 0.0);
+  std::vector<cd> L01(nm, 0.0);  // L10 = conj(L01)
+  // k-space, the dense build's mode set
+  const double k2max = 4.0 * p.alpha * p.alpha * std::log(1.0 / p.kspace_tol);
+  const double Ls[3] = {p.Lx, p.Ly, g.Lz};
+  int mmax[3];
+  for (int d = 0; d < 3; ++d) mmax[d] = (int)std::floor(std::sqrt(k2max) * Ls[d] / (2.0 * M_PI));
+  const double scale = ke * (double)nm;
+  for (int mx = 0; mx <= mmax[0]; ++mx)
+    for (int my = -mmax[1]; my <= mmax[1]; ++my) {
+      const size_t cp = (size_t)((my % ny + ny) % ny) * nx + (size_t)(mx % nx);
+      const size_t cm = (size_t)(((-my) % ny + ny) % ny) * nx + (size_t)(((-mx) % nx + nx) % nx);
+      const double kx = 2.0 * M_PI * mx / p.Lx, ky = 2.0 * M_PI * my / p.Ly;
+      double sd = 0.0;
+      cd s01 = 0.0;
+      for (int mz = -mmax[2]; mz <= mmax[2]; ++mz) {
+        const bool half = mx > 0 || (mx == 0 && my > 0) || (mx == 0 && my == 0 && mz > 0);
+        if (!half) continue;
+        const double kz = 2.0 * M_PI * mz / g.Lz;
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > k2max) continue;
+        const double w = 4.0 * M_PI * std::exp(-k2 / (4.0 * p.alpha * p.alpha)) / (V * k2);
+        sd += w;
+        s01 += w * std::exp(cd(0.0, kx * dox + ky * doy + kz * doz));
+      }
+      L00[cp] += scale * sd;
+      L00[cm] += scale * sd;
+      L11[cp] += scale * sd;
+      L11[cm] += scale * sd;
+      L01[cp] += scale * s01;
+      L01[cm] += scale * std::conj(s01);
+    }
+  // real space, transformed directly over the few displacements within rc
+  std::vector<cd> twx(nx), twy(ny);
+  for (int j = 0; j < nx; ++j) twx[j] = std::exp(cd(0.0, -2.0 * M_PI * j / nx));
+  for (int j = 0; j < ny; ++j) twy[j] = std::exp(cd(0.0, -2.0 * M_PI * j / ny));
+  const double a = p.alpha, bg = 1.0 / (std::sqrt(2.0) * p.eta), rc2 = p.rc * p.rc;
+  struct Ent {
+    int pair, dx, dy;
+    double f;
+  };
+  std::vector<Ent> ents;
+  for (int pair = 0; pair < 3; ++pair) {  // (0,0), (0,1), (1,1): wall w of site d, wall w' of site 0
+    const int w = pair == 2 ? 1 : 0, wp = pair == 0 ? 0 : 1;
+    for (int dy = 0; dy < ny; ++dy)
+      for (int dx = 0; dx < nx; ++dx) {
+        if (w == wp && dx == 0 && dy == 0) continue;
+        double rx = h->lat_o[w][0] - h->lat_o[wp][0] + dx * (p.Lx / nx);
+        double ry = h->lat_o[w][1] - h->lat_o[wp][1] + dy * (p.Ly / ny);
+        const double rz = h->lat_o[w][2] - h->lat_o[wp][2];
+        rx -= p.Lx * std::rint(rx / p.Lx);
+        ry -= p.Ly * std::rint(ry / p.Ly);
+        const double r2 = rx * rx + ry * ry + rz * rz;
+        if (r2 >= rc2) continue;
+        const double r = std::sqrt(r2);
+        ents.push_back({pair, dx, dy, ke * (std::erfc(a * r) - std::erfc(bg * r)) / r});
+      }
+  }
+  for (int q = 0; q < ny; ++q)
+    for (int pp = 0; pp < nx; ++pp) {
+      const size_t m = (size_t)q * nx + pp;
+      double s00 = 0.0, s11 = 0.0;
+      cd s01 = 0.0;
+      for (const Ent& e : ents) {
+        const cd t = twx[((size_t)pp * e.dx) % nx] * twy[((size_t)q * e.dy) % ny];
+        if (e.pair == 0) s00 += e.f * t.real();
+        else if (e.pair == 2) s11 += e.f * t.real();
+        else s01 += e.f * t;
+      }
+      L00[m] += s00;  // the diagonal blocks' kernels are even in d: real transforms
+      L11[m] += s11;
+      L01[m] += s01;
+    }
+  // self and slab terms
+  const double self = ke * 2.0 * (1.0 / (std::sqrt(2.0 * M_PI) * p.eta) - p.alpha / std::sqrt(M_PI));
+  for (size_t m = 0; m < nm; ++m) {
+    L00[m] += self;
+    L11[m] += self;
+  }
+  const double slab = (double)nm * ke * (4.0 * M_PI / V);
+  L00[0] += slab * h->lat_o[0][2] * h->lat_o[0][2];
+  L11[0] += slab * h->lat_o[1][2] * h->lat_o[1][2];
+  L01[0] += slab * h->lat_o[0][2] * h->lat_o[1][2];
+  // invert each mode's block [[a, b], [conj(b), d]]
+  std::vector<double2> linv(nm * 4);
+  for (size_t m = 0; m < nm; ++m) {
+    const double A0 = L00[m], D = L11[m];
+    const cd B = L01[m];
+    const double det = A0 * D - std::norm(B);
+    if (!(A0 > 0.0 && det > 0.0 && std::isfinite(det))) return set_err(h, SRBE_ENOTSPD, "a lattice mode of A is not positive definite");
+    const cd i00 = D / det, i01 = -B / det, i10 = -std::conj(B) / det, i11 = A0 / det;
+    linv[m * 4 + 0] = make_double2(i00.real(), i00.imag());
+    linv[m * 4 + 1] = make_double2(i01.real(), i01.imag());
+    linv[m * 4 + 2] = make_double2(i10.real(), i10.imag());
+    linv[m * 4 + 3] = make_double2(i11.real(), i11.imag());
+  }
+  {
+    const double A0 = L00[0], D = L11[0], B = L01[0].real(), det = A0 * D - B * B;
+    h->lat_c[0] = (D - B) / det;
+    h->lat_c[1] = (A0 - B) / det;
+    h->lat_etc = (double)nm * (h->lat_c[0] + h->lat_c[1]);
+    if (!(h->lat_etc > 0.0)) return set_err(h, SRBE_ENOTSPD, "e^T A^-1 e is not positive");
+  }
+  std::vector<double2> tw(nx + ny);
+  for (int j = 0; j < nx; ++j) tw[j] = make_double2(twx[j].real(), twx[j].imag());
+  for (int j = 0; j < ny; ++j) tw[nx + j] = make_double2(twy[j].real(), twy[j].imag());
+  if (hipMalloc((void**)&h->lat_site, site.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&h->lat_tw, tw.size() * sizeof(double2)) != hipSuccess ||
+      hipMalloc((void**)&h->lat_linv, linv.size() * sizeof(double2)) != hipSuccess)
+    return set_err(h, SRBE_ENOMEM, "lattice solve tables");
+  if (hipMemcpy(h->lat_site, site.data(), site.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->lat_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->lat_linv, linv.data(), linv.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+    return set_err(h, SRBE_EHIP, "lattice solve tables: copy");
+  h->lattice = true;
+  return SRBE_OK;
+}
+
 inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 const char* kPhaseNames[SRBE_N_PHASES] = {"sample",       "cellsort", "sf_ions", "real_ele",  "real_ii",
@@ -489,7 +709,19 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   };
   b.nchunk_ion = chunks_for(max_nrep);
   b.nchunk_ele = chunks_for(n);
-  b.ksplit = tp[SRBE_TUNE_GEMM_SPLIT];
+  b.ksplit = h->lattice ? 1 : tp[SRBE_TUNE_GEMM_SPLIT];  // the lattice solve writes one k-range
+  b.lat = LatticeSolve{};
+  if (h->lattice) {
+    b.lat.nx = h->lat_nx;
+    b.lat.ny = h->lat_ny;
+    b.lat.site = h->lat_site;
+    b.lat.tw_x = h->lat_tw;
+    b.lat.tw_y = h->lat_tw + h->lat_nx;
+    b.lat.linv = h->lat_linv;
+    b.lat.c0 = h->lat_c[0];
+    b.lat.c1 = h->lat_c[1];
+    b.lat.etc = h->lat_etc;
+  }
   b.real = (h->p.flags & SRBE_FLAG_KSPACE_ONLY) ? 0 : 1;
   b.gemm_depth = tp[SRBE_TUNE_GEMM_DEPTH];
   b.kw = tp[SRBE_TUNE_WAVES];
@@ -581,6 +813,8 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.bigsort.prov, b.bigsort.ntile ? (size_t)N1 * sizeof(int) : 0},
       {(void**)&b.bigsort.tsum, b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0},
       {(void**)&b.bigsort.ctot, b.bigsort.ntile ? (size_t)R * b.bigsort.nchunk * sizeof(int) : 0},
+      {(void**)&b.lat.T, b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0},
+      {(void**)&b.lat.U, b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0},
   };
   size_t total = 0;
   for (const Item& it : items) {
@@ -646,7 +880,13 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
     launch_sf_finalize(g, b, fp32, 1, s);
   }
   part(PH_ELE_POTENTIAL, s, [&] { launch_ele_potential(g, b, fp32, s); });
-  if (!fixedQ) part(PH_CP_GEMM, s, [&] { launch_cp_gemm(g, b, h->Sext, s); });
+  if (!fixedQ)
+    part(PH_CP_GEMM, s, [&] {
+      if (b.lat.nx)
+        launch_lattice_solve(g, b, s);
+      else
+        launch_cp_gemm(g, b, h->Sext, s);
+    });
   part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
   if (real) HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
   part(PH_SF_ELE, s, [&] {
@@ -703,7 +943,8 @@ void srbe_destroy(srbe_system* h) {
     if (st) (void)hipStreamDestroy(st);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   void* bufs[] = {h->bin_keys, h->reach, h->reach_cell, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_iperm, h->ele_scell, h->ele_cstart,
-                  h->ele_czr, h->ion_runs, h->ele_rr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev};
+                  h->ele_czr, h->ion_runs, h->ele_rr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev,
+                  h->lat_site, h->lat_tw, h->lat_linv};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(prev);
@@ -732,6 +973,15 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
   h->n_ele = n_ele;
   h->has_cp = cp;
   h->g = make_geom(*params, n_ele);
+  std::vector<int> lat_site;
+  if (cp && (params->flags & SRBE_FLAG_LATTICE_SOLVE)) {
+    const std::string why = detect_lattice(h, ele_xyz, n_ele, lat_site);
+    if (!why.empty()) {
+      fprintf(stderr, "srbe_create: SRBE_FLAG_LATTICE_SOLVE: %s\n", why.c_str());
+      delete h;
+      return SRBE_EINVAL;
+    }
+  }
   (void)hipGetDevice(&h->device);
   if (hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || h->ncu < 1) {
     delete h;
@@ -928,7 +1178,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
   for (hipEvent_t& e : h->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(SRBE_EHIP);
   if (cp) {
-    rc = build_electrode_solve(h, s);
+    rc = lat_site.empty() ? build_electrode_solve(h, s) : build_lattice_solve(h, lat_site);
     if (rc != SRBE_OK) {
       fprintf(stderr, "srbe_create: %s\n", h->err.c_str());
       return fail(rc);

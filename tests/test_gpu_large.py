@@ -155,3 +155,44 @@ def test_full_size_large_slab_at_sampled_targets(full, precision):
         assert rel_inf(F, Fr) < 1e-11 and rel_inf(b, br) < 1e-11
     else:
         assert rel_rms(F, Fr) < 1e-5 and rel_rms(b, br) < 3e-5
+
+
+def test_full_size_large_slab_lattice_charge_solve(full):
+    # the constant-potential step of the full-size slab with the lattice charge solve
+    # (the dense S_ext would hold 131,072^2 doubles).  The ions' own induced charge
+    # (~18 e per wall here) dwarfs what 2 V across 100 nm induces (~1 e), so the checks
+    # are the voltage response: Q is neutral and exactly linear in dpsi (b* does not
+    # depend on it), raising dpsi moves positive charge onto the positive wall, and
+    # FP32 and FP64 agree to the FP32 path's error
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import binding, workloads as wl
+    off, xyz, q, dp, sd = full["inputs"]
+    w = wl.large_slab()
+    wp = dict(w["params"], kspace_tol=1e-16)
+    side = np.asarray(w["ele_side"])
+    sysm = srbe_amd.System(wp, w["ele_pos"], side, flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
+    try:
+        Q = {}
+        for precision, dpsi in [(0, 0.0), (0, 2.0), (0, 4.0), (1, 2.0)]:
+            dpt = torch.tensor([dpsi], dtype=torch.float64, device="cuda")
+            out = sysm.step(off, xyz, q, dpt, sd, full["ref"]["step"], precision=precision)
+            torch.cuda.synchronize()
+            assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+            Qv = out["Q"].cpu().numpy()
+            print(f"  lattice solve, precision {precision}, dpsi {dpsi}: sum Q / sum |Q| = "
+                  f"{np.sum(Qv) / np.sum(np.abs(Qv)):.2e}, wall charges {np.sum(Qv[side < 0]):.6f} "
+                  f"{np.sum(Qv[side > 0]):.6f}, psibar {float(out['psibar'][0]):.6f}", flush=True)
+            assert abs(np.sum(Qv)) < 1e-12 * np.sum(np.abs(Qv))
+            assert np.isfinite(float(out["E"][0])) and np.isfinite(float(out["psibar"][0]))
+            Q[(precision, dpsi)] = Qv
+        # the response to 2 V is ~1/20 of Q, and Q a ~1e-6 remnant of b* (~400): the
+        # difference of two FP64 solves carries ~1e-8 relative rounding
+        d1 = Q[(0, 2.0)] - Q[(0, 0.0)]
+        d2 = Q[(0, 4.0)] - Q[(0, 2.0)]
+        e32 = rel_rms(Q[(1, 2.0)], Q[(0, 2.0)])
+        print(f"  linearity {rel_inf(d2, d1):.2e}, FP32 vs FP64 charges {e32:.2e} rms", flush=True)
+        assert rel_inf(d2, d1) < 1e-7
+        assert np.sum(d1[side > 0]) > 0 > np.sum(d1[side < 0])
+        assert e32 < 1e-4
+    finally:
+        sysm.close()
