@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--large-slab", type=int, default=0, metavar="P",
                     help="also time the full-size large slab (917,504 ions, 131,072 electrodes, M=64) with this "
                          "batch size P (500 or 2000), charges by the lattice solve; reported as large_slab")
+    ap.add_argument("--uneven", action="store_true",
+                    help="also time the uneven batch (32 systems of 2e3-2e5 particles, each its own box, charges "
+                         "by the lattice solve): one step of every system, graph replays in turn; reported as "
+                         "uneven_batch")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -294,6 +298,8 @@ def main():
 
     if args.large_slab:
         result["large_slab"] = large_slab_bench(args, srbe_amd, stream)
+    if args.uneven:
+        result["uneven_batch"] = uneven_bench(args, srbe_amd, stream)
 
     if not args.no_cpu:
         o = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, want_kset=False)
@@ -353,6 +359,81 @@ def large_slab_bench(args, srbe_amd, stream):
         log(f"large slab {name}: {ms:.3f} ms/step")
     out["pairs_per_step"] = pairs
     sysm.close()
+    return out
+
+
+def uneven_bench(args, srbe_amd, stream):
+    """One step of each of the 32 uneven-batch systems (each its own handle and box, the
+    lattice charge solve), captured per system and replayed in turn, FP32 and FP64."""
+    import torch
+    from paper_2509_24742_amd import workloads as wl
+    t0 = time.time()
+    systems = wl.uneven_batch()
+    gen_s = time.time() - t0
+    dev = torch.device("cuda")
+    t0 = time.time()
+    items = []
+    for k, w in enumerate(systems):
+        wp = dict(w["params"], kspace_tol=1e-16)
+        sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
+        n_ion = len(w["ion_q"])
+        items.append(dict(sys=sysm, off=np.array([0, n_ion], dtype=np.int64),
+                          xyz=torch.tensor(np.ascontiguousarray(w["ion_pos"].T).ravel(), dtype=torch.float64,
+                                           device=dev),
+                          q=torch.tensor(w["ion_q"], dtype=torch.float64, device=dev),
+                          dp=torch.tensor([w["dpsi"]], dtype=torch.float64, device=dev),
+                          sd=torch.tensor([4100 + k], dtype=torch.int64, device=dev).view(torch.uint64),
+                          pairs=w["n_total"] * (wp["M"] + wp["P"])))
+    setup_s = time.time() - t0
+    pairs = sum(it["pairs"] for it in items)
+    steps = max(3, min(args.steps, 20))
+    out = {"workload": f"uneven batch: {len(items)} systems, {sum(w['n_total'] for w in systems)} particles in all "
+                       f"(2e3-2e5 each, log-uniform), aspect 3-12, P = round(100 sqrt(N/1e4)), M = ceil(aspect), "
+                       f"constant potential (lattice charge solve)", "systems": len(items), "steps": steps,
+           "pairs_per_batch_step": pairs, "workload_generation_s": gen_s, "setup_s": setup_s}
+    # the systems' graphs go to S streams (default priority), largest first, each to the
+    # stream with the least work so far; the batch step ends when every stream has
+    order = sorted(range(len(items)), key=lambda k: -items[k]["pairs"])
+    for name, prec in [("fp32", srbe_amd.SRBE_FP32), ("fp64", srbe_amd.SRBE_FP64)]:
+        graphs = [it["sys"].capture(it["off"], it["xyz"], it["q"], it["dp"], it["sd"], 0, precision=prec,
+                                    want_kset=False) for it in items]
+        for gr in graphs:
+            gr.launch()
+        torch.cuda.synchronize()
+        res = {}
+        for S in (1, 2, 4, 8):
+            side = [torch.cuda.Stream() for _ in range(S)]
+            load, plan = [0] * S, []
+            for k in order:
+                j = min(range(S), key=lambda u: load[u])
+                load[j] += items[k]["pairs"]
+                plan.append((k, j))
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for st in side:
+                st.wait_event(e0)
+            for _ in range(steps):
+                for k, j in plan:
+                    graphs[k].launch(side[j])
+            for st in side:
+                stream.wait_stream(st)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[S] = e0.elapsed_time(e1) / steps
+        for it in items:
+            code = srbe_amd.srbe_sync_status(it["sys"].h)
+            if code != 0:
+                raise RuntimeError(srbe_amd.srbe_last_error(it["sys"].h))
+        for gr in graphs:
+            gr.close()
+        S = min(res, key=res.get)
+        ms = res[S]
+        out[name] = {"ms_per_batch_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "streams": S,
+                     "ms_by_streams": {str(k): round(v, 4) for k, v in res.items()}}
+        log(f"uneven batch {name}: {ms:.3f} ms per step of all systems ({S} streams; by streams {res})")
+    for it in items:
+        it["sys"].close()
     return out
 
 

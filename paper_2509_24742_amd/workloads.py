@@ -29,6 +29,13 @@ equilibration run this project does not have):
   1100 + r and voltages drawn uniformly from [0, 4] V.
 * per-step jitter: N(0, 0.01^2 nm^2) per axis and site; x, y wrap, z reflects
   back into the electrolyte interval.
+* uneven batch: 32 systems (seed 4000), N log-uniform in [2e3, 2e5]; electrodes
+  2 n^2 with n = round(sqrt(0.075 N)) on two n x n square walls; N_ion = N - 2 n^2
+  made even (half +0.78 e, half -0.78 e); aspect Lz / Lx = lambda mu uniform in
+  [3, 12] with lambda = 3; the electrolyte at 10 ions per nm^3 gives
+  Lx = Ly = (3 N_ion / (10 lambda mu))^(1/3) and H = lambda mu Lx / 3; ions by
+  RSA (0.3 nm) in z in [0.4, H - 0.4]; alpha = 3 /nm, eta = 1/19.79 nm,
+  rc = 1.2 nm, M = ceil(lambda mu), P = round(100 sqrt(N / 1e4)), dpsi = 2 V.
 * large slab: two n x n square walls (spacing Lx / n) at z = 0 and z = H in an
   Lx x Lx cell; n_ion ions of +-0.78 e (half each) by RSA (0.3 nm) in
   z in [0.4, H - 0.4]; alpha = 3 /nm, eta = 1/19.79 nm, rc = 1.2 nm.  The full
@@ -142,6 +149,37 @@ def large_slab(n_side=256, n_ion=917504, Lx=30.0, H=100.0, M=64, P=500, seed=100
     params = dict(Lx=Lx, Ly=Lx, H=H, lam=3.0, alpha=3.0, eta=1.0 / 19.79, rc=1.2,
                   coulomb_k=COULOMB_K, M=M, P=P)
     return dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=float(dpsi))
+
+
+def uneven_batch(n_systems=32, seed=4000, place=True):
+    """Systems of the uneven-batch recipe (a list of workload dicts, each with its own box).
+
+    place: True places every system's ions; False none (ion_pos None: the sizes and
+    boxes alone); a collection of indices, those systems only.  Each system's placement
+    has its own generator (seed + 1 + index), so a system is the same whichever others
+    are placed.
+    """
+    rng = np.random.default_rng(seed)
+    N = np.exp(rng.uniform(np.log(2e3), np.log(2e5), n_systems)).astype(np.int64)
+    aspect = rng.uniform(3.0, 12.0, n_systems)
+    out = []
+    for k in range(n_systems):
+        n = int(round(np.sqrt(0.075 * N[k])))
+        n_ion = int(N[k]) - 2 * n * n
+        n_ion -= n_ion % 2
+        Lx = (3.0 * n_ion / (10.0 * aspect[k])) ** (1.0 / 3.0)
+        H = aspect[k] * Lx / 3.0
+        a = Lx / n
+        ele = np.vstack([square_wall(n, a, 0.0), square_wall(n, a, H)])
+        side = np.array([-1] * n * n + [1] * n * n, dtype=np.int8)
+        todo = place if isinstance(place, bool) else k in place
+        ion = _rsa_sites_batched(np.random.default_rng(seed + 1 + k), n_ion, Lx, Lx, 0.4, H - 0.4, 0.3) if todo else None
+        q = np.array([0.78] * (n_ion // 2) + [-0.78] * (n_ion // 2))
+        params = dict(Lx=Lx, Ly=Lx, H=H, lam=3.0, alpha=3.0, eta=1.0 / 19.79, rc=1.2, coulomb_k=COULOMB_K,
+                      M=int(np.ceil(aspect[k])), P=int(round(100.0 * np.sqrt(N[k] / 1e4))))
+        out.append(dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=2.0,
+                        n_total=int(n_ion + 2 * n * n)))
+    return out
 
 
 CATION_Q = (0.1135, 0.2, 0.4665)
