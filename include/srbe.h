@@ -94,7 +94,8 @@ typedef struct srbe_system srbe_system;
  * built, stays complete).
  * With SRBE_FLAG_LATTICE_SOLVE set, the electrodes must form two walls (two distinct
  * z), each a complete nx x ny rectangular lattice of spacing (Lx/nx, Ly/ny) with the
- * same nx, ny on both walls and any in-plane offset per wall, and rc < min(Lx, Ly)/2.
+ * same nx, ny (at most 768 each) on both walls and any in-plane offset per wall, and
+ * rc < min(Lx, Ly)/2.
  * A (Eq. (18)) is then block-circulant over the lattice: it is never formed, and the
  * charge update of Eqs. (9)-(11) runs per in-plane lattice mode (p, q) as a 2 x 2
  * solve between discrete Fourier transforms over the walls, with O(n_ele) memory.

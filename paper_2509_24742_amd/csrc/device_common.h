@@ -63,6 +63,10 @@ constexpr int kRsumParts = 16;
 // this many partials, all requested at once).
 constexpr int kMaxGemmSplit = 16;
 constexpr int kRsumStride = 4 * kRsumParts;
+// Replicas above kEnergyLarge ions have the energy's ion sum q phi taken in partial
+// sums over tiles of kEnergyTile ions by many blocks (added in tile order).
+constexpr int kEnergyLarge = 8192;
+constexpr int kEnergyTile = 4096;
 
 // Cell of a position (x, y wrapped by the caller into fractions sx, sy in [0,1)).
 __device__ __forceinline__ int cell_index(const Geom& g, double sx, double sy, double z) {

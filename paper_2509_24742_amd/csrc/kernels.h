@@ -29,7 +29,7 @@ struct BigSort {
 // Charge solve over two electrode lattices (SRBE_FLAG_LATTICE_SOLVE; nx 0: not used).
 // Sites (w, iy, ix) of wall w; modes (p, q) with p along x.
 struct LatticeSolve {
-  int nx, ny;               // sites per wall along x and y (<= 1024 each)
+  int nx, ny;               // sites per wall along x and y (<= 768 each: LDS of the column launch)
   const int* site;          // 2*ny*nx electrode index of site (w, iy, ix)
   const double2* tw_x;      // nx: exp(-2 pi i j / nx)
   const double2* tw_y;      // ny: exp(-2 pi i j / ny)
@@ -116,6 +116,8 @@ struct StepBufs {
   unsigned* status;
   BigSort bigsort;          // multi-block cell sort workspace (count null: one-block sort)
   LatticeSolve lat;         // lattice charge solve (lat.nx 0: the dense GEMM)
+  double* eparts;           // R*etiles partial sums of q phi over tiles of kEnergyTile ions
+  int etiles;               // tiles per replica (0: the energy sums the ions itself)
   // outputs
   double* Q_out;
   double* F_out;

@@ -40,20 +40,30 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // a conj(b)
 
 constexpr int kLatThreads = 256;
 
-// Launch 1: block (r, w, iy); the row of v in LDS, thread p sums over ix.
+// Every launch stages its twiddle table in LDS beside the data, so the sums' loads
+// are LDS reads rather than a chain of dependent global loads.
+
+// Launch 1: block (r, w, iy); the row of v and the x twiddles in LDS, thread p sums
+// over ix.  LDS: nx doubles + nx double2.
 __global__ __launch_bounds__(kLatThreads) void k_lat_fwd_x(LatticeSolve L, const double* __restrict__ V, int ldv) {
-  extern __shared__ double row[];
+  extern __shared__ double2 lds_fx[];
   const int nx = L.nx, ny = L.ny;
+  double2* tw = lds_fx;
+  double* row = reinterpret_cast<double*>(lds_fx + nx);
   const int b = blockIdx.x, r = b / (2 * ny), wy = b - r * 2 * ny;  // wy = w ny + iy
   const int* site = L.site + (size_t)wy * nx;
-  for (int ix = threadIdx.x; ix < nx; ix += kLatThreads) row[ix] = V[(size_t)r * ldv + site[ix]];
+  for (int ix = threadIdx.x; ix < nx; ix += kLatThreads) {
+    row[ix] = V[(size_t)r * ldv + site[ix]];
+    tw[ix] = L.tw_x[ix];
+  }
   __syncthreads();
   double2* T = L.T + ((size_t)r * 2 * ny + wy) * nx;
   for (int p = threadIdx.x; p < nx; p += kLatThreads) {
     double2 acc = make_double2(0.0, 0.0);
     int ph = 0;  // p ix mod nx
+#pragma unroll 8
     for (int ix = 0; ix < nx; ++ix) {
-      const double2 t = L.tw_x[ph];
+      const double2 t = tw[ph];
       acc.x += row[ix] * t.x;
       acc.y += row[ix] * t.y;
       ph += p;
@@ -63,20 +73,24 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_fwd_x(LatticeSolve L, const
   }
 }
 
-// Launch 2: block (r, p); both walls' column p through LDS.
+// Launch 2: block (r, p); both walls' column p and the y twiddles through LDS.
+// LDS: 5 ny double2 ([2][ny] input column, [2][ny] solved modes, ny twiddles).
 __global__ __launch_bounds__(kLatThreads) void k_lat_column(LatticeSolve L, double* __restrict__ Qext, int n) {
-  extern __shared__ double2 col[];  // [2][ny] input column, then [2][ny] solved modes
+  extern __shared__ double2 col[];
   const int nx = L.nx, ny = L.ny;
   const int b = blockIdx.x, r = b / nx, p = b - r * nx;
   double2* cin = col;
   double2* cu = col + 2 * ny;
+  double2* tw = col + 4 * ny;
   for (int u = threadIdx.x; u < 2 * ny; u += kLatThreads) cin[u] = L.T[((size_t)r * 2 * ny + u) * nx + p];
+  for (int u = threadIdx.x; u < ny; u += kLatThreads) tw[u] = L.tw_y[u];
   __syncthreads();
   for (int q = threadIdx.x; q < ny; q += kLatThreads) {
     double2 v0 = make_double2(0.0, 0.0), v1 = make_double2(0.0, 0.0);
     int ph = 0;  // q iy mod ny
+#pragma unroll 4
     for (int iy = 0; iy < ny; ++iy) {
-      const double2 t = L.tw_y[ph];
+      const double2 t = tw[ph];
       const double2 a0 = cmul(cin[iy], t), a1 = cmul(cin[ny + iy], t);
       v0.x += a0.x;
       v0.y += a0.y;
@@ -103,8 +117,9 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_column(LatticeSolve L, doub
   for (int iy = threadIdx.x; iy < ny; iy += kLatThreads) {
     double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
     int ph = 0;
+#pragma unroll 4
     for (int q = 0; q < ny; ++q) {
-      const double2 t = L.tw_y[ph];
+      const double2 t = tw[ph];
       const double2 a0 = cmulc(cu[q], t), a1 = cmulc(cu[ny + q], t);
       s0.x += a0.x;
       s0.y += a0.y;
@@ -118,22 +133,27 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_column(LatticeSolve L, doub
   }
 }
 
-// Launch 3: block (r, w, iy); the row of half-inverted modes in LDS, thread ix sums
-// over p and writes the charge of its site.
+// Launch 3: block (r, w, iy); the row of half-inverted modes and the x twiddles in
+// LDS, thread ix sums over p and writes the charge of its site.  LDS: 2 nx double2.
 __global__ __launch_bounds__(kLatThreads) void k_lat_inv_x(LatticeSolve L, double* __restrict__ Qext, int n) {
   extern __shared__ double2 rowc[];
   const int nx = L.nx, ny = L.ny;
+  double2* tw = rowc + nx;
   const int b = blockIdx.x, r = b / (2 * ny), wy = b - r * 2 * ny;
   const double2* U = L.U + ((size_t)r * 2 * ny + wy) * nx;
-  for (int p = threadIdx.x; p < nx; p += kLatThreads) rowc[p] = U[p];
+  for (int p = threadIdx.x; p < nx; p += kLatThreads) {
+    rowc[p] = U[p];
+    tw[p] = L.tw_x[p];
+  }
   __syncthreads();
   const int* site = L.site + (size_t)wy * nx;
   const double scale = 1.0 / ((double)nx * ny);
   for (int ix = threadIdx.x; ix < nx; ix += kLatThreads) {
     double acc = 0.0;
     int ph = 0;
+#pragma unroll 8
     for (int p = 0; p < nx; ++p) {
-      const double2 t = L.tw_x[ph];
+      const double2 t = tw[ph];
       acc += rowc[p].x * t.x + rowc[p].y * t.y;  // Re(U conj(t))
       ph += ix;
       if (ph >= nx) ph -= nx;
@@ -147,11 +167,11 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_inv_x(LatticeSolve L, doubl
 void launch_lattice_solve(const Geom& g, const StepBufs& b, hipStream_t s) {
   const LatticeSolve& L = b.lat;
   const int R = b.R, n = g.n_ele;
-  hipLaunchKernelGGL(k_lat_fwd_x, dim3((unsigned)R * 2 * L.ny), dim3(kLatThreads), (size_t)L.nx * sizeof(double), s,
-                     L, (const double*)b.V, ldcp(n));
-  hipLaunchKernelGGL(k_lat_column, dim3((unsigned)R * L.nx), dim3(kLatThreads), (size_t)4 * L.ny * sizeof(double2),
+  hipLaunchKernelGGL(k_lat_fwd_x, dim3((unsigned)R * 2 * L.ny), dim3(kLatThreads),
+                     (size_t)L.nx * (sizeof(double) + sizeof(double2)), s, L, (const double*)b.V, ldcp(n));
+  hipLaunchKernelGGL(k_lat_column, dim3((unsigned)R * L.nx), dim3(kLatThreads), (size_t)5 * L.ny * sizeof(double2),
                      s, L, b.Qext, n);
-  hipLaunchKernelGGL(k_lat_inv_x, dim3((unsigned)R * 2 * L.ny), dim3(kLatThreads), (size_t)L.nx * sizeof(double2),
+  hipLaunchKernelGGL(k_lat_inv_x, dim3((unsigned)R * 2 * L.ny), dim3(kLatThreads), (size_t)2 * L.nx * sizeof(double2),
                      s, L, b.Qext, n);
 }
 

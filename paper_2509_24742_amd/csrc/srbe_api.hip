@@ -384,7 +384,7 @@ std::string detect_lattice(srbe_system* h, const double* xyz, int n, std::vector
     }
   }
   if ((size_t)nx * ny != members[0].size()) return "a wall is not a complete rectangular lattice";
-  if (nx > 1024 || ny > 1024) return "more than 1024 sites along an axis";
+  if (nx > 768 || ny > 768) return "more than 768 sites along an axis";
   const double ax = Lx / nx, ay = Ly / ny;
   site.assign((size_t)2 * nx * ny, -1);
   for (int w = 0; w < 2; ++w) {
@@ -710,6 +710,9 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.nchunk_ion = chunks_for(max_nrep);
   b.nchunk_ele = chunks_for(n);
   b.ksplit = h->lattice ? 1 : tp[SRBE_TUNE_GEMM_SPLIT];  // the lattice solve writes one k-range
+  // the energy's ion sum in tile partials for large replicas (steps that solve the charges)
+  b.etiles = (!a.Q_in && max_nrep > kEnergyLarge) ? (int)((max_nrep + kEnergyTile - 1) / kEnergyTile) : 0;
+  b.eparts = nullptr;
   b.lat = LatticeSolve{};
   if (h->lattice) {
     b.lat.nx = h->lat_nx;
@@ -814,6 +817,7 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.bigsort.tsum, b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0},
       {(void**)&b.bigsort.ctot, b.bigsort.ntile ? (size_t)R * b.bigsort.nchunk * sizeof(int) : 0},
       {(void**)&b.lat.T, b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0},
+      {(void**)&b.eparts, (size_t)R * b.etiles * sizeof(double)},
       {(void**)&b.lat.U, b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0},
   };
   size_t total = 0;

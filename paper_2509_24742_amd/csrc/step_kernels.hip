@@ -1863,6 +1863,18 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) 
 
 static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * b.ii_ipw); }
 
+// Partial sums of q_i phi_i over tiles of kEnergyTile ions of each replica (large
+// replicas), so the energy's ion sum is spread over many CUs: block (r, t).
+__global__ __launch_bounds__(256) void k_energy_partials(StepBufs b) {
+  __shared__ double sh[1][4];
+  const int r = blockIdx.x / b.etiles, t = blockIdx.x - r * b.etiles;
+  const int64_t i0 = b.off[r] + (int64_t)t * kEnergyTile, i1 = min(b.off[r + 1], i0 + kEnergyTile);
+  double v[1] = {0.0};
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) v[0] += b.ion_q[i] * b.phi[i];
+  block_sum<256, 1>(v, sh);
+  if (threadIdx.x == 0) b.eparts[(size_t)r * b.etiles + t] = v[0];
+}
+
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   const int tiles = real_ii_tiles(b);
@@ -1871,6 +1883,7 @@ void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
     hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b, tiles);
   else
     hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b, tiles);
+  if (b.etiles) hipLaunchKernelGGL(k_energy_partials, dim3((unsigned)b.R * b.etiles), dim3(256), 0, s, b);
 }
 
 // Block bx of the nbx blocks that one replica's reach ranges are split over; the
@@ -2143,8 +2156,12 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
     return;
   }
   if (b.real) {  // the ion-ion real-space energy (left out in k-space-only steps)
+    if (b.etiles) {  // large replicas: the tiles' partial sums, in tile order
+      for (int t = threadIdx.x; t < b.etiles; t += 256) v[0] += b.eparts[(size_t)r * b.etiles + t];
+    } else {
 #pragma unroll 8
-    for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
+      for (int64_t i = off[r] + threadIdx.x; i < off[r + 1]; i += 256) v[0] += ion_q[i] * phi[i];
+    }
   }
   for (int k = threadIdx.x; k < g.K; k += 256) {
     const double2 s = b.S1[(size_t)r * g.K + k];
