@@ -177,6 +177,26 @@ int srbe_graph_set_step(srbe_graph* g, uint64_t step, void* stream);
 void srbe_graph_destroy(srbe_graph* g);
 
 /*
+ * srbe_electrode_forces -- forces on the electrode atoms from the estimator of the last
+ * srbe_step on this handle: F_j = -Q_j grad Phi*(R_j), with the same sampled modes,
+ * charges and positions.  Its parts:
+ *   - the Fourier force of Eq. (25) with Q_j in place of q_i, and the slab force;
+ *   - the real-space forces of Eq. (13) from the ions (ion-Gaussian kernel) and from
+ *     the other electrodes (Gaussian-Gaussian kernel), in FP64 for both precisions.
+ * The Fourier part runs in the step's precision.  With the ion forces it conserves
+ * momentum per sample: the sum of all forces vanishes.
+ * n_rep       the replica count of that step (checked).
+ * F_ele_out   device, 3*n_rep*n_ele doubles SoA (x of every replica's electrodes, then y,
+ *             then z); replica-major, electrodes in srbe_create order.
+ * Must follow an srbe_step (eagerly, not a graph replay) on the same stream, whose
+ * input, Q_out and F_out buffers are still valid, with no other srbe_step on the handle
+ * in between.  Allocates and frees scratch, and blocks until done.
+ * Errors: SRBE_EINVAL (no preceding step, another n_rep, NULL output), SRBE_ENOMEM,
+ * SRBE_EHIP.
+ */
+int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void* stream);
+
+/*
  * srbe_sample -- only the sampler of a step (Sec. 3, Eqs. (26)-(29)): writes the
  * n_rep*P*3 int32 modes the step with the same (seed, step) would use.
  * seed device n_rep uint64; kset_out device.  Returns SRBE_EINVAL on bad arguments.

@@ -96,6 +96,8 @@ def lib():
     L.srbe_get_tuning.restype = ctypes.c_int
     L.srbe_set_tuning.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]
     L.srbe_set_tuning.restype = ctypes.c_int
+    L.srbe_electrode_forces.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+    L.srbe_electrode_forces.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -103,7 +105,7 @@ def lib():
 EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string", "srbe_step", "srbe_sample",
             "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
             "srbe_phase_name", "srbe_graph_create", "srbe_graph_launch", "srbe_graph_set_step",
-            "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning"]
+            "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning", "srbe_electrode_forces"]
 SRBE_N_PHASES = 16
 
 
@@ -277,6 +279,15 @@ def srbe_tune(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, iters=10, s
                               _dev(seed, torch.uint64, R, "seed", allow_none=True), int(iters), out.ctypes.data,
                               ms.ctypes.data, _stream(stream)))
     return [int(v) for v in out], float(ms[0]), float(ms[1])
+
+
+def srbe_electrode_forces(h, n_rep, F_ele_out, stream=None):
+    """Forces on the electrodes from the last srbe_step on h, a step of n_rep replicas.
+
+    F_ele_out: device float64 tensor of 3 * n_rep * n_ele (SoA, replica-major)."""
+    import torch
+    ptr = _dev(F_ele_out, torch.float64, 3 * int(n_rep) * srbe_n_ele(h), "F_ele_out")
+    _check(h, lib().srbe_electrode_forces(h, int(n_rep), ptr, _stream(stream)))
 
 
 def srbe_get_tuning(h, precision, ion_offsets):

@@ -145,6 +145,10 @@ int ele_split(int units);
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
 // the lattice charge solve: (Q; psibar) of every replica into Qext (one k-range)
 void launch_lattice_solve(const Geom& g, const StepBufs& b, hipStream_t s);
+// forces on the electrodes from the state b of a finished step: F (SoA, 3 R n_ele);
+// eoff: R + 1 int64 scratch, recs: R n_ele records (uint4 FP32 / double4 FP64) scratch
+void launch_electrode_forces(const Geom& g, const StepBufs& b, int fp32, double* F, int64_t* eoff, void* recs,
+                             hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);

@@ -55,6 +55,10 @@ struct srbe_system {
   double2* lat_tw = nullptr;   // nx + ny twiddles (x then y)
   double2* lat_linv = nullptr; // ny*nx*4 inverse 2 x 2 blocks
   double lat_c[2] = {0.0, 0.0}, lat_etc = 0.0;
+  // the state of the last eager step (srbe_electrode_forces reads it)
+  StepBufs last{};
+  bool last_valid = false;
+  int last_fp32 = 0;
   unsigned* status = nullptr;
   rocblas_handle blas = nullptr;
   // the step is a small DAG over three streams: the caller's (records, k-space chain,
@@ -1239,6 +1243,7 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
               const double* Q_in, double* Q_out, double* F_out, double* b_out, double* psibar_out,
               double* energy_out, int32_t* kset_out, void* stream) {
   if (!h) return SRBE_EINVAL;
+  h->last_valid = false;
   const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, kset_in,
                    Q_in, Q_out, F_out, b_out, psibar_out, energy_out, kset_out};
   int64_t max_nrep = 0;
@@ -1269,7 +1274,38 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
     h->off_cache.assign(ion_offsets, ion_offsets + R + 1);
   }
   b.off = h->off_dev;
-  return enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, s);
+  rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, s);
+  if (rc == SRBE_OK) {
+    h->last = b;
+    h->last_valid = true;
+    h->last_fp32 = precision == SRBE_FP32;
+  }
+  return rc;
+}
+
+int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void* stream) {
+  if (!h) return SRBE_EINVAL;
+  if (!F_ele_out) return set_err(h, SRBE_EINVAL, "F_ele_out is NULL");
+  if (!h->last_valid) return set_err(h, SRBE_EINVAL, "srbe_electrode_forces: no preceding srbe_step on this handle");
+  if (n_rep != h->last.R) return set_err(h, SRBE_EINVAL, "srbe_electrode_forces: n_rep differs from the last step's");
+  hipStream_t s = (hipStream_t)stream;
+  const StepBufs& b = h->last;
+  const size_t NE = (size_t)b.R * h->n_ele;
+  int64_t* eoff = nullptr;
+  void* recs = nullptr;
+  hipError_t e = hipMalloc((void**)&eoff, ((size_t)b.R + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&recs, std::max<size_t>(NE, 1) * (h->last_fp32 ? sizeof(uint4) : sizeof(double4)));
+  if (e == hipSuccess) {
+    launch_electrode_forces(h->g, b, h->last_fp32, F_ele_out, eoff, recs, s);
+    e = hipGetLastError();
+  }
+  const hipError_t e2 = hipStreamSynchronize(s);  // the scratch is freed below
+  if (eoff) (void)hipFree(eoff);
+  if (recs) (void)hipFree(recs);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess)
+    return set_err(h, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, hipGetErrorString(e));
+  return SRBE_OK;
 }
 
 int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
