@@ -16,6 +16,8 @@ constant-potential simulation of electrochemical systems" (arXiv 2509.24742):
 * ``cp``      -- the constant-potential charge solve (Sec. 2, Eqs. (9)-(11));
 * ``srbe``    -- the SRBE estimators for a given sample of Fourier modes
                  (Sec. 3, Eqs. (24)-(27)) and the energy they imply;
+* ``langevin`` -- the Euler-Maruyama step of the Langevin thermostat (Sec. 3)
+                 with reflecting walls (a reading) and Philox normal deviates;
 * ``sampler`` -- the Metropolis sampler of Sec. 3 (Eqs. (28)-(29)) driven by
                  ``philox``, a counter-based generator written from its published
                  definition;

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 from scipy.stats import norm
 
-from oracle import cp, ewald, ewald2d, philox, sampler, srbe
+from oracle import cp, ewald, ewald2d, langevin, philox, sampler, srbe
 
 
 # ---------------------------------------------------------------- helpers
@@ -473,3 +473,45 @@ def test_srbe_weight_normalisation():
     z = (tot.mean() - exact) / (tot.std() / np.sqrt(B))
     assert abs(z) < 5.0
     assert abs(tot.mean() / exact - 1.0) < 0.02
+
+
+# ---------------------------------------------------------------- Langevin update (Sec. 3)
+
+
+def test_langevin_noiseless_step_is_explicit_euler():
+    # beta -> infinity removes the noise: the update is r + v dt, v + (F - gamma v) dt / m
+    rng = np.random.default_rng(3)
+    n = 50
+    pos = np.column_stack([rng.uniform(0, 2, n), rng.uniform(0, 3, n), rng.uniform(1, 4, n)])
+    vel, F, m = rng.normal(size=(n, 3)) * 0.01, rng.normal(size=(n, 3)), rng.uniform(1, 3, n)
+    dt, gamma = 1e-3, 2.0
+    r, v = langevin.euler_maruyama(pos, vel, F, m, gamma, np.inf, dt, 2.0, 3.0, 0.5, 4.5, 7, 0)
+    assert np.allclose(r, pos + vel * dt, rtol=0, atol=1e-15)
+    assert np.allclose(v, vel + (F - gamma * vel) * dt / m[:, None], rtol=0, atol=1e-15)
+
+
+def test_langevin_noise_has_the_fluctuation_dissipation_variance():
+    # at zero force and velocity the velocity change is sqrt(2 gamma / beta) dW / m, dW ~ N(0, dt):
+    # variance 2 gamma dt / (beta m^2) per component, uncorrelated across components
+    n = 200000
+    m, gamma, beta, dt = 2.0, 3.0, 0.5, 1e-2
+    pos = np.tile([1.0, 1.0, 2.0], (n, 1))
+    _, v = langevin.euler_maruyama(pos, np.zeros((n, 3)), np.zeros((n, 3)), np.full(n, m), gamma, beta, dt,
+                                   4.0, 4.0, 0.0, 4.0, 11, 5)
+    var = 2.0 * gamma * dt / (beta * m * m)
+    assert np.allclose(v.var(axis=0) / var, 1.0, atol=0.02)
+    assert np.allclose(v.mean(axis=0) / np.sqrt(var), 0.0, atol=0.02)
+    c = np.corrcoef(v.T)
+    assert np.all(np.abs(c[np.triu_indices(3, 1)]) < 0.02)
+
+
+def test_langevin_walls_reflect_and_wrap():
+    # ion 0 leaves through x = 0 and z = zlo, ion 1 through x = Lx, y = Ly and z = zhi
+    pos = np.array([[0.005, 0.2, 0.52], [1.995, 2.995, 4.45]])
+    vel = np.array([[-1.0, -1.0, -10.0], [1.0, 1.0, 10.0]])
+    r, v = langevin.euler_maruyama(pos, vel, np.zeros((2, 3)), np.ones(2), 0.0, np.inf, 0.01, 2.0, 3.0, 0.5, 4.5,
+                                   1, 0)
+    assert np.allclose(r[:, 0], [2.0 - 0.005, 0.005], atol=1e-14)
+    assert np.allclose(r[:, 1], [0.19, 0.005], atol=1e-14)
+    assert np.allclose(r[:, 2], [2 * 0.5 - 0.42, 2 * 4.5 - 4.55], atol=1e-14)
+    assert np.allclose(v[:, 2], [10.0, -10.0]) and np.allclose(v[:, :2], vel[:, :2])
