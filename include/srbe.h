@@ -197,6 +197,25 @@ void srbe_graph_destroy(srbe_graph* g);
 int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void* stream);
 
 /*
+ * srbe_langevin_update -- one Euler-Maruyama step of the Langevin thermostat (Sec. 3)
+ * for n ions, in place, from the forces of a step:
+ *   r <- r + v dt;  v <- v + (F - gamma v) dt / m + sqrt(2 gamma / beta) dW / m,
+ * dW ~ N(0, dt) per component.  x and y wrap into [0, Lx) and [0, Ly); z is reflected
+ * into [zlo, zhi] and v_z changes sign (a stand-in for the wall force field; ion-ion
+ * repulsion is not modelled: dynamics need a short-range force field added to F).
+ * xyz, vel  device, 3n doubles SoA each, updated in place.
+ * F         device, 3n doubles SoA (e.g. F_out of srbe_step).
+ * mass      device, n doubles.
+ * gamma >= 0 friction, beta > 0 inverse temperature (infinity: no noise), dt > 0.
+ * Deviates: Philox4x64-10, key (seed, 1), counter (ion index, step, 3, 0), uniforms
+ * ((w >> 12) + 1/2) 2^-52, Box-Muller (z_x, z_y from words 0, 1; z_z from 2, 3).
+ * Enqueued on stream; no handle.  Errors: SRBE_EINVAL (arguments), SRBE_EHIP.
+ */
+int srbe_langevin_update(int64_t n, double* xyz, double* vel, const double* F, const double* mass, double gamma,
+                         double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
+                         uint64_t step, void* stream);
+
+/*
  * srbe_sample -- only the sampler of a step (Sec. 3, Eqs. (26)-(29)): writes the
  * n_rep*P*3 int32 modes the step with the same (seed, step) would use.
  * seed device n_rep uint64; kset_out device.  Returns SRBE_EINVAL on bad arguments.

@@ -14,7 +14,8 @@ from .binding import (SRBE_FLAG_KSPACE_ONLY, SRBE_FLAG_LATTICE_SOLVE, SRBE_FLAG_
                       srbe_error_string, srbe_graph_create, srbe_graph_destroy, srbe_graph_launch,
                       srbe_graph_set_step, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
                       srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status,
-                      SRBE_TUNE_NAMES, srbe_electrode_forces, srbe_get_tuning, srbe_set_tuning, srbe_tune)
+                      SRBE_TUNE_NAMES, srbe_electrode_forces, srbe_get_tuning, srbe_langevin_update, srbe_set_tuning,
+                      srbe_tune)
 
 
 class System:

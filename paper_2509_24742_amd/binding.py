@@ -98,6 +98,10 @@ def lib():
     L.srbe_set_tuning.restype = ctypes.c_int
     L.srbe_electrode_forces.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
     L.srbe_electrode_forces.restype = ctypes.c_int
+    L.srbe_langevin_update.argtypes = [ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _vp]
+    L.srbe_langevin_update.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -105,7 +109,8 @@ def lib():
 EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string", "srbe_step", "srbe_sample",
             "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
             "srbe_phase_name", "srbe_graph_create", "srbe_graph_launch", "srbe_graph_set_step",
-            "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning", "srbe_electrode_forces"]
+            "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning", "srbe_electrode_forces",
+            "srbe_langevin_update"]
 SRBE_N_PHASES = 16
 
 
@@ -288,6 +293,18 @@ def srbe_electrode_forces(h, n_rep, F_ele_out, stream=None):
     import torch
     ptr = _dev(F_ele_out, torch.float64, 3 * int(n_rep) * srbe_n_ele(h), "F_ele_out")
     _check(h, lib().srbe_electrode_forces(h, int(n_rep), ptr, _stream(stream)))
+
+
+def srbe_langevin_update(xyz, vel, F, mass, gamma, beta, dt, Lx, Ly, zlo, zhi, seed, step, stream=None):
+    """One Euler-Maruyama Langevin step in place (see include/srbe.h); device float64 tensors."""
+    import torch
+    n = int(mass.numel())
+    args = [_dev(xyz, torch.float64, 3 * n, "xyz"), _dev(vel, torch.float64, 3 * n, "vel"),
+            _dev(F, torch.float64, 3 * n, "F"), _dev(mass, torch.float64, n, "mass")]
+    code = lib().srbe_langevin_update(n, *args, float(gamma), float(beta), float(dt), float(Lx), float(Ly),
+                                      float(zlo), float(zhi), int(seed) & (2 ** 64 - 1), int(step), _stream(stream))
+    if code != SRBE_OK:
+        raise SrbeError(code, srbe_error_string(code))
 
 
 def srbe_get_tuning(h, precision, ion_offsets):

@@ -1283,6 +1283,16 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   return rc;
 }
 
+int srbe_langevin_update(int64_t n, double* xyz, double* vel, const double* F, const double* mass, double gamma,
+                         double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
+                         uint64_t step, void* stream) {
+  if (n < 0 || (n > 0 && (!xyz || !vel || !F || !mass))) return SRBE_EINVAL;
+  if (!(dt > 0.0) || !(gamma >= 0.0) || !(beta > 0.0) || !(Lx > 0.0) || !(Ly > 0.0) || !(zlo <= zhi))
+    return SRBE_EINVAL;
+  launch_langevin(n, xyz, vel, F, mass, gamma, beta, dt, Lx, Ly, zlo, zhi, seed, step, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? SRBE_OK : SRBE_EHIP;
+}
+
 int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void* stream) {
   if (!h) return SRBE_EINVAL;
   if (!F_ele_out) return set_err(h, SRBE_EINVAL, "F_ele_out is NULL");

@@ -1,0 +1,62 @@
+"""The Euler-Maruyama Langevin update (srbe_langevin_update) against the oracle's.
+
+10,000 ions with random positions, velocities, forces and masses: one update on the
+device and in ``oracle.langevin`` with the same seed and step (the same Philox
+deviates) must agree to 1e-12 relative max-norm in positions and velocities (FP64;
+the only differences are the rounding of sin, cos, log and the order of a few
+products).  Also the noiseless limit (beta = infinity), and ions that leave through
+every boundary (x and y wrap, z reflects with v_z reversed).
+"""
+
+import numpy as np
+import pytest
+
+from helpers import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BOX = dict(Lx=3.4, Ly=3.7, zlo=1.07, zhi=10.93)
+
+
+def run(pos, vel, F, m, gamma, beta, dt, seed, step):
+    from paper_2509_24742_amd import binding
+    dev = torch.device("cuda")
+    to = lambda a: torch.tensor(np.ascontiguousarray(np.asarray(a).T).ravel(), dtype=torch.float64, device=dev)
+    x, v, f = to(pos), to(vel), to(F)
+    mt = torch.tensor(m, dtype=torch.float64, device=dev)
+    binding.srbe_langevin_update(x, v, f, mt, gamma, beta, dt, BOX["Lx"], BOX["Ly"], BOX["zlo"], BOX["zhi"],
+                                 seed, step)
+    torch.cuda.synchronize()
+    n = len(m)
+    return x.cpu().numpy().reshape(3, n).T, v.cpu().numpy().reshape(3, n).T
+
+
+@pytest.mark.parametrize("beta", [38.68, np.inf])
+def test_langevin_update_matches_oracle(beta):
+    from oracle import langevin
+    rng = np.random.default_rng(12)
+    n = 10000
+    pos = np.column_stack([rng.uniform(0, BOX["Lx"], n), rng.uniform(0, BOX["Ly"], n),
+                           rng.uniform(BOX["zlo"], BOX["zhi"], n)])
+    vel = rng.normal(size=(n, 3)) * 0.5
+    F = rng.normal(size=(n, 3)) * 20.0
+    m = rng.uniform(0.1, 2.0, n)
+    args = (0.5, beta, 2e-3)
+    x, v = run(pos, vel, F, m, *args, 99, 7)
+    xr, vr = langevin.euler_maruyama(pos, vel, F, m, *args, BOX["Lx"], BOX["Ly"], BOX["zlo"], BOX["zhi"], 99, 7)
+    print(f"beta {beta}: positions {rel_inf(x, xr):.2e}, velocities {rel_inf(v, vr):.2e}", flush=True)
+    assert rel_inf(x, xr) < 1e-12 and rel_inf(v, vr) < 1e-12
+
+
+def test_langevin_boundaries():
+    from oracle import langevin
+    pos = np.array([[0.005, 0.2, 1.09], [3.395, 3.695, 10.92], [1.0, 1.0, 5.0]])
+    vel = np.array([[-1.0, -1.0, -10.0], [1.0, 1.0, 10.0], [0.0, 0.0, 0.0]])
+    F, m = np.zeros((3, 3)), np.ones(3)
+    x, v = run(pos, vel, F, m, 0.0, np.inf, 0.01, 1, 0)
+    xr, vr = langevin.euler_maruyama(pos, vel, F, m, 0.0, np.inf, 0.01, BOX["Lx"], BOX["Ly"], BOX["zlo"],
+                                     BOX["zhi"], 1, 0)
+    assert np.allclose(x, xr, rtol=0, atol=1e-13) and np.allclose(v, vr, rtol=0, atol=1e-13)
+    assert np.all((x[:, 2] >= BOX["zlo"]) & (x[:, 2] <= BOX["zhi"]))
