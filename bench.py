@@ -104,8 +104,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the step has no multi-GPU path "
-              f"in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU "
+              f"path (replicas would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     import torch
 
