@@ -220,18 +220,16 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   return g;
 }
 
-// Build A (Eq. (18)), factorise, and form S_ext on the device.
-int build_electrode_solve(srbe_system* h, hipStream_t s) {
-  const srbe_params& p = h->p;
-  const Geom& g = h->g;
-  const int n = h->n_ele;
-  // half-space modes (m and -m give the same cos), weight doubled
+// The reciprocal modes of A (Eq. (18)): every k with exp(-k^2/(4 alpha^2)) >= kspace_tol,
+// taken in the half space (m and -m give the same cosine), mx >= 0 then my, mz ascending;
+// fn(mx, my, mz, kx, ky, kz, w) with w = 4 pi exp(-k^2/(4 alpha^2)) / (V k^2).  The dense
+// and the lattice builds both take their modes from here.
+template <class Fn>
+void for_each_half_mode(const srbe_params& p, const Geom& g, Fn fn) {
   const double k2max = 4.0 * p.alpha * p.alpha * std::log(1.0 / p.kspace_tol);
   const double Ls[3] = {p.Lx, p.Ly, g.Lz};
   int mmax[3];
   for (int d = 0; d < 3; ++d) mmax[d] = (int)std::floor(std::sqrt(k2max) * Ls[d] / (2.0 * M_PI));
-  std::vector<int> modes;
-  std::vector<double> sqrtw;
   for (int mx = 0; mx <= mmax[0]; ++mx)
     for (int my = -mmax[1]; my <= mmax[1]; ++my)
       for (int mz = -mmax[2]; mz <= mmax[2]; ++mz) {
@@ -240,12 +238,24 @@ int build_electrode_solve(srbe_system* h, hipStream_t s) {
         const double kx = 2.0 * M_PI * mx / p.Lx, ky = 2.0 * M_PI * my / p.Ly, kz = 2.0 * M_PI * mz / g.Lz;
         const double k2 = kx * kx + ky * ky + kz * kz;
         if (k2 > k2max) continue;
-        const double w = 4.0 * M_PI * std::exp(-k2 / (4.0 * p.alpha * p.alpha)) / (g.V * k2);
-        modes.push_back(mx);
-        modes.push_back(my);
-        modes.push_back(mz);
-        sqrtw.push_back(std::sqrt(2.0 * p.coulomb_k * w));
+        fn(mx, my, mz, kx, ky, kz, 4.0 * M_PI * std::exp(-k2 / (4.0 * p.alpha * p.alpha)) / (g.V * k2));
       }
+}
+
+// Build A (Eq. (18)), factorise, and form S_ext on the device.
+int build_electrode_solve(srbe_system* h, hipStream_t s) {
+  const srbe_params& p = h->p;
+  const Geom& g = h->g;
+  const int n = h->n_ele;
+  // half-space modes, weight doubled
+  std::vector<int> modes;
+  std::vector<double> sqrtw;
+  for_each_half_mode(p, g, [&](int mx, int my, int mz, double, double, double, double w) {
+    modes.push_back(mx);
+    modes.push_back(my);
+    modes.push_back(mz);
+    sqrtw.push_back(std::sqrt(2.0 * p.coulomb_k * w));
+  });
   const int nk_total = (int)sqrtw.size();
   const int chunk = std::max(256, std::min(nk_total, (int)(16 * 1024 * 1024 / std::max(n, 1))));
   double *A = nullptr, *E = nullptr, *dsw = nullptr, *gv = nullptr;
@@ -437,35 +447,18 @@ int build_lattice_solve(srbe_system* h, const std::vector<int>& site) {
   std::vector<double> L00(nm, 0.0), L11(nm, 0.0);
   std::vector<cd> L01(nm, 0.0);  // L10 = conj(L01)
   // k-space, the dense build's mode set
-  const double k2max = 4.0 * p.alpha * p.alpha * std::log(1.0 / p.kspace_tol);
-  const double Ls[3] = {p.Lx, p.Ly, g.Lz};
-  int mmax[3];
-  for (int d = 0; d < 3; ++d) mmax[d] = (int)std::floor(std::sqrt(k2max) * Ls[d] / (2.0 * M_PI));
   const double scale = ke * (double)nm;
-  for (int mx = 0; mx <= mmax[0]; ++mx)
-    for (int my = -mmax[1]; my <= mmax[1]; ++my) {
-      const size_t cp = (size_t)((my % ny + ny) % ny) * nx + (size_t)(mx % nx);
-      const size_t cm = (size_t)(((-my) % ny + ny) % ny) * nx + (size_t)(((-mx) % nx + nx) % nx);
-      const double kx = 2.0 * M_PI * mx / p.Lx, ky = 2.0 * M_PI * my / p.Ly;
-      double sd = 0.0;
-      cd s01 = 0.0;
-      for (int mz = -mmax[2]; mz <= mmax[2]; ++mz) {
-        const bool half = mx > 0 || (mx == 0 && my > 0) || (mx == 0 && my == 0 && mz > 0);
-        if (!half) continue;
-        const double kz = 2.0 * M_PI * mz / g.Lz;
-        const double k2 = kx * kx + ky * ky + kz * kz;
-        if (k2 > k2max) continue;
-        const double w = 4.0 * M_PI * std::exp(-k2 / (4.0 * p.alpha * p.alpha)) / (V * k2);
-        sd += w;
-        s01 += w * std::exp(cd(0.0, kx * dox + ky * doy + kz * doz));
-      }
-      L00[cp] += scale * sd;
-      L00[cm] += scale * sd;
-      L11[cp] += scale * sd;
-      L11[cm] += scale * sd;
-      L01[cp] += scale * s01;
-      L01[cm] += scale * std::conj(s01);
-    }
+  for_each_half_mode(p, g, [&](int mx, int my, int, double kx, double ky, double kz, double w) {
+    const size_t cp = (size_t)((my % ny + ny) % ny) * nx + (size_t)(mx % nx);
+    const size_t cm = (size_t)(((-my) % ny + ny) % ny) * nx + (size_t)(((-mx) % nx + nx) % nx);
+    const cd s01 = w * std::exp(cd(0.0, kx * dox + ky * doy + kz * doz));
+    L00[cp] += scale * w;
+    L00[cm] += scale * w;
+    L11[cp] += scale * w;
+    L11[cm] += scale * w;
+    L01[cp] += scale * s01;
+    L01[cm] += scale * std::conj(s01);
+  });
   // real space, transformed directly over the few displacements within rc
   std::vector<cd> twx(nx), twy(ny);
   for (int j = 0; j < nx; ++j) twx[j] = std::exp(cd(0.0, -2.0 * M_PI * j / nx));
