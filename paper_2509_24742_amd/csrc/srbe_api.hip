@@ -187,13 +187,18 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   g.n_ele = n_ele;
   // real-space cells at least rc wide in x and y and rc / nzs thick in z (the
   // z-stencil then reaches nzs cells each way); coarsened, never below those
-  // widths, to stay within kMaxGridCells
-  g.nzs = 3;
+  // widths, to stay within kMaxGridCells.  When the 3 x 3 stencil covers the whole
+  // x-y plane (at most 3 cells each way), a cell's neighbours are one run of
+  // consecutive cells whatever nzs is, and thin cells (nzs = 3) trim the candidates
+  // in z; in a wider plane the neighbours come as one run per row and z-layer, and
+  // cells rc thick (nzs = 1) give 9 runs three times as long instead of 21
+  // (~28 % more candidates, scanned in fuller rounds).
   // (the 1e-9 margin keeps cells strictly wider than rc and rc / nzs, so rounding in
   // the cell index never puts a pair closer than rc outside the stencil)
   const double shrink = 1.0 - 1e-9;
   g.ncx = std::max(1, (int)std::floor(p.Lx / p.rc * shrink));
   g.ncy = std::max(1, (int)std::floor(p.Ly / p.rc * shrink));
+  g.nzs = (g.ncx <= 3 && g.ncy <= 3) ? 3 : 1;
   g.ncz = std::max(1, (int)std::floor(p.H * g.nzs / p.rc * shrink));
   while ((int64_t)g.ncx * g.ncy * g.ncz > kMaxGridCells) {
     if (g.ncz >= g.ncx && g.ncz >= g.ncy)
