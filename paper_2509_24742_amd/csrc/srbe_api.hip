@@ -643,7 +643,9 @@ void default_tuning(const srbe_system* h, int precision, int R, int64_t max_nrep
   p[SRBE_TUNE_SF_BLOCKS] = 1024;
   p[SRBE_TUNE_WAVES] = 4;
   p[SRBE_TUNE_UNROLL] = 4;
-  p[SRBE_TUNE_II_IONS] = (int)std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)R * max_nrep + slots - 1) / slots));
+  // (at most 32 ions per wave: on the 917k-ion slab two hand sweeps found 32 ~5 % faster than 64
+  // in FP32 and equal in FP64; a graph-timed run found them within its ~3 % noise)
+  p[SRBE_TUNE_II_IONS] = (int)std::max<int64_t>(1, std::min<int64_t>(32, ((int64_t)R * max_nrep + slots - 1) / slots));
   p[SRBE_TUNE_IE_BLOCKS] = (int)std::max<int64_t>(
       1, std::min<int64_t>(std::max<int64_t>(1, (max_nrep + 3) / 4), slots / 4 / std::max(R, 1)));
   p[SRBE_TUNE_ELE_SPLIT] = ele_split(h->n_ele_chunks * R);
