@@ -201,8 +201,9 @@ int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void
  * for n ions, in place, from the forces of a step:
  *   r <- r + v dt;  v <- v + (F - gamma v) dt / m + sqrt(2 gamma / beta) dW / m,
  * dW ~ N(0, dt) per component.  x and y wrap into [0, Lx) and [0, Ly); z is reflected
- * into [zlo, zhi] and v_z changes sign (a stand-in for the wall force field; ion-ion
- * repulsion is not modelled: dynamics need a short-range force field added to F).
+ * specularly into [zlo, zhi] as many times as it takes to land inside (zlo < zhi), v_z
+ * changing sign once per reflection (a stand-in for the wall force field; ion-ion
+ * repulsion is not modelled here: dynamics need a short-range force field added to F).
  * xyz, vel  device, 3n doubles SoA each, updated in place.
  * F         device, 3n doubles SoA (e.g. F_out of srbe_step).
  * mass      device, n doubles.

@@ -11,7 +11,11 @@ SRBE-driven dynamics): for every ion,
 
 The confinement is a reading (the paper's force field holds the ions between the
 walls; none is modelled here): x and y wrap into [0, L); z is reflected specularly
-into [zlo, zhi] (z -> 2 zlo - z below, 2 zhi - z above, and v_z changes sign).
+into [zlo, zhi] as often as it takes to land inside: with W = zhi - zlo,
+k = floor((z - zlo) / W) reflections and t = (z - zlo) - k W, z becomes zlo + t for
+even k and zhi - t for odd k (then clamped into [zlo, zhi] against rounding), and
+v_z changes sign once per reflection.  One reflection is z -> 2 zlo - z below or
+2 zhi - z above.  A z already inside is left unchanged.
 
 Normal deviates: Philox4x64-10 with key (seed, 1) and counter (ion index, step, 3, 0);
 the four words map to uniforms in (0, 1) by ((w >> 12) + 1/2) 2^-52, and Box-Muller
@@ -50,8 +54,11 @@ def euler_maruyama(pos, vel, F, mass, gamma, beta, dt, Lx, Ly, zlo, zhi, seed, s
     v = vel + (F - gamma * vel) * dt / m + np.sqrt(2.0 * gamma / beta) * dW / m
     r[:, 0] = np.mod(r[:, 0], Lx)
     r[:, 1] = np.mod(r[:, 1], Ly)
-    below, above = r[:, 2] < zlo, r[:, 2] > zhi
-    r[below, 2] = 2.0 * zlo - r[below, 2]
-    r[above, 2] = 2.0 * zhi - r[above, 2]
-    v[below | above, 2] *= -1.0
+    out = (r[:, 2] < zlo) | (r[:, 2] > zhi)
+    W = zhi - zlo
+    k = np.floor((r[out, 2] - zlo) / W)
+    t = np.clip((r[out, 2] - zlo) - k * W, 0.0, W)
+    odd = np.fmod(k, 2.0) != 0.0
+    r[out, 2] = np.clip(np.where(odd, zhi - t, zlo + t), zlo, zhi)
+    v[out, 2] *= np.where(odd, -1.0, 1.0)
     return r, v

@@ -3,8 +3,11 @@
 //   r <- r + v dt
 //   v <- v + (F - gamma v) dt / m + sqrt(2 gamma / beta) dW / m,   dW ~ N(0, dt) per component
 //
-// x and y wrap into the periodic cell; z is reflected specularly into [zlo, zhi] (v_z
-// changes sign), a stand-in for the wall force field.  The deviates come from
+// x and y wrap into the periodic cell; z is reflected specularly into [zlo, zhi] as often
+// as it takes to land inside (v_z changes sign once per reflection), a stand-in for the
+// wall force field: with W = zhi - zlo, k = floor((z - zlo) / W) reflections and
+// t = (z - zlo) - k W, z becomes zlo + t for even k and zhi - t for odd k, clamped into
+// [zlo, zhi] against rounding.  The deviates come from
 // Philox4x64-10 with key (seed, 1) and counter (ion, step, 3, 0) -- the sampler uses key
 // (seed, 0) -- through Box-Muller on the four words mapped into (0, 1).  FP64.
 #include <hip/hip_runtime.h>
@@ -41,12 +44,13 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, double* __restrict_
   }
   r[0] -= Lx * floor(r[0] / Lx);
   r[1] -= Ly * floor(r[1] / Ly);
-  if (r[2] < zlo) {
-    r[2] = 2.0 * zlo - r[2];
-    v[2] = -v[2];
-  } else if (r[2] > zhi) {
-    r[2] = 2.0 * zhi - r[2];
-    v[2] = -v[2];
+  if (r[2] < zlo || r[2] > zhi) {
+    const double W = zhi - zlo;
+    const double k = floor((r[2] - zlo) / W);
+    const double t = fmin(fmax((r[2] - zlo) - k * W, 0.0), W);
+    const bool odd = fmod(k, 2.0) != 0.0;
+    r[2] = fmin(fmax(odd ? zhi - t : zlo + t, zlo), zhi);
+    if (odd) v[2] = -v[2];
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {

@@ -1287,7 +1287,7 @@ int srbe_langevin_update(int64_t n, double* xyz, double* vel, const double* F, c
                          double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
                          uint64_t step, void* stream) {
   if (n < 0 || (n > 0 && (!xyz || !vel || !F || !mass))) return SRBE_EINVAL;
-  if (!(dt > 0.0) || !(gamma >= 0.0) || !(beta > 0.0) || !(Lx > 0.0) || !(Ly > 0.0) || !(zlo <= zhi))
+  if (!(dt > 0.0) || !(gamma >= 0.0) || !(beta > 0.0) || !(Lx > 0.0) || !(Ly > 0.0) || !(zlo < zhi))
     return SRBE_EINVAL;
   launch_langevin(n, xyz, vel, F, mass, gamma, beta, dt, Lx, Ly, zlo, zhi, seed, step, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? SRBE_OK : SRBE_EHIP;

@@ -52,9 +52,12 @@ def test_langevin_update_matches_oracle(beta):
 
 def test_langevin_boundaries():
     from oracle import langevin
-    pos = np.array([[0.005, 0.2, 1.09], [3.395, 3.695, 10.92], [1.0, 1.0, 5.0]])
-    vel = np.array([[-1.0, -1.0, -10.0], [1.0, 1.0, 10.0], [0.0, 0.0, 0.0]])
-    F, m = np.zeros((3, 3)), np.ones(3)
+    # the last two cross the electrolyte more than once in one step (repeated reflections)
+    pos = np.array([[0.005, 0.2, 1.09], [3.395, 3.695, 10.92], [1.0, 1.0, 5.0], [1.0, 1.0, 5.0],
+                    [2.0, 2.0, 9.0]])
+    vel = np.array([[-1.0, -1.0, -10.0], [1.0, 1.0, 10.0], [0.0, 0.0, 0.0], [0.0, 0.0, 1234.5],
+                    [0.0, 0.0, -3000.0]])
+    F, m = np.zeros((5, 3)), np.ones(5)
     x, v = run(pos, vel, F, m, 0.0, np.inf, 0.01, 1, 0)
     xr, vr = langevin.euler_maruyama(pos, vel, F, m, 0.0, np.inf, 0.01, BOX["Lx"], BOX["Ly"], BOX["zlo"],
                                      BOX["zhi"], 1, 0)

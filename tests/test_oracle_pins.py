@@ -475,6 +475,64 @@ def test_srbe_weight_normalisation():
     assert abs(tot.mean() / exact - 1.0) < 0.02
 
 
+def small_cell(seed=4):
+    """0.8 x 0.8 x 1.0 cell, two 2 x 2 Gaussian walls and four ions: few enough modes to
+    evaluate the estimator once per mode of the whole reciprocal lattice."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly, H = 0.8, 0.8, 1.0
+    g = (np.arange(2) + 0.5) * 0.4
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    wall = np.column_stack([X.ravel(), Y.ravel()])
+    ele = np.vstack([np.column_stack([wall, np.zeros(4)]), np.column_stack([wall, np.full(4, H)])])
+    ion = np.column_stack([rng.uniform(0, Lx, 4), rng.uniform(0, Ly, 4), rng.uniform(0.3, H - 0.3, 4)])
+    q = np.array([0.8, -0.8, 0.5, -0.5])
+    p = ewald.Params(Lx=Lx, Ly=Ly, H=H, lam=3.0, alpha=5.0, eta=0.08, rc=0.4, coulomb_k=1.44, M=3, P=1,
+                     kspace_tol=1e-10)
+    Q = rng.normal(size=len(ele)) * 0.1
+    return p, ion, q, ele, Q
+
+
+def test_srbe_energy_expectation_over_every_mode_is_the_full_ewald_energy():
+    # E* at fixed Q (reading R6) is the deterministic part plus (1/P) sum_l of a term of the
+    # sampled mode, so its expectation under the sampling law exp(-k^2/4a^2)/G on L_k \ I
+    # (Eqs. (26)-(27), Theorems 3.1-3.2) can be taken exactly: weight the one-mode estimate
+    # E*({k}) of every mode by its probability, and give the probability mass beyond the
+    # truncated lattice to the empty-batch estimate (the deterministic part alone).  That
+    # must be the complete energy U_c = 1/2 Q^T A Q - b^T Q + c of Eqs. (13), (16), (17),
+    # with every position-independent term (the ion self term -a/sqrt(pi) sum q^2, the
+    # Gaussian self term, the slab term) included: a finite-difference force check
+    # cancels those terms, this identity does not.
+    p, ion, q, ele, Q = small_cell()
+    modes = ewald.enumerate_modes(p)
+    A = ewald.electrode_matrix(p, ele, modes)
+    mv = modes[sampler.valid(p, modes)]
+    prob = np.exp(-np.sum(ewald.kvectors(p, mv) ** 2, axis=1) / (4 * p.alpha ** 2)) / srbe.normaliser_G(p)
+    assert 1.0 - 1e-8 < prob.sum() < 1.0
+    expect = sum(pr * srbe.srbe_energy(p, A, k[None, :], ion, q, ele, Q) for k, pr in zip(mv, prob))
+    expect += (1.0 - prob.sum()) * srbe.srbe_energy(p, A, np.zeros((0, 3)), ion, q, ele, Q)
+    full = ewald.energy(p, ion, q, ele, Q, modes)["total"]
+    assert abs(expect - full) < 1e-13 * abs(full)
+    # the same identity for c* alone (no electrode charges): c of Eq. (5)
+    expect_c = sum(pr * srbe.srbe_constant(p, k[None, :], ion, q) for k, pr in zip(mv, prob))
+    expect_c += (1.0 - prob.sum()) * srbe.srbe_constant(p, np.zeros((0, 3)), ion, q)
+    c = ewald.constant_term(p, ion, q, modes)
+    assert abs(expect_c - c) < 1e-13 * abs(c)
+
+
+def test_srbe_energy_sample_mean_is_the_full_ewald_energy():
+    # The same statement through the sampler itself: the mean of E* over 2000 batches drawn
+    # by the Metropolis chain (fixed Q) equals the complete energy within 5 standard errors.
+    p, ion, q, ele, side = tiny_system(M=3, P=10, tol=1e-16)
+    modes = ewald.enumerate_modes(p)
+    A = ewald.electrode_matrix(p, ele, modes)
+    Q = np.random.default_rng(6).normal(size=len(ele)) * 0.1
+    full = ewald.energy(p, ion, q, ele, Q, modes)["total"]
+    B = 2000
+    Es = np.array([srbe.srbe_energy(p, A, sampler.draw_kset(p, 41, 0, t)[0], ion, q, ele, Q) for t in range(B)])
+    z = (Es.mean() - full) / (Es.std() / np.sqrt(B))
+    assert abs(z) < 5.0
+
+
 # ---------------------------------------------------------------- Langevin update (Sec. 3)
 
 
@@ -515,3 +573,25 @@ def test_langevin_walls_reflect_and_wrap():
     assert np.allclose(r[:, 1], [0.19, 0.005], atol=1e-14)
     assert np.allclose(r[:, 2], [2 * 0.5 - 0.42, 2 * 4.5 - 4.55], atol=1e-14)
     assert np.allclose(v[:, 2], [10.0, -10.0]) and np.allclose(v[:, :2], vel[:, :2])
+
+
+def test_langevin_large_overshoot_lands_inside():
+    # a step that crosses the electrolyte more than once is folded back by repeated
+    # reflections: the mirror images of the straight path in the walls, v_z flipped once
+    # per reflection
+    zlo, zhi = 0.5, 4.5
+    W = zhi - zlo
+    z0 = np.array([4.0, 1.0, 2.0, 3.0, 1.0])
+    vz = np.array([9.0, -30.0, 10.0 * W, -1e4, 0.0])  # dt = 0.1: 0.4 past zhi by 0.5 W, ...
+    pos = np.column_stack([np.ones(5), np.ones(5), z0])
+    vel = np.column_stack([np.zeros(5), np.zeros(5), vz])
+    r, v = langevin.euler_maruyama(pos, vel, np.zeros((5, 3)), np.ones(5), 0.0, np.inf, 0.1, 2.0, 2.0, zlo, zhi, 1, 0)
+    assert np.all((r[:, 2] >= zlo) & (r[:, 2] <= zhi))
+    # brute force: reflect one wall at a time until inside
+    for z, u, zr, vr in zip(z0 + 0.1 * vz, vz, r[:, 2], v[:, 2]):
+        n = 0
+        while z < zlo or z > zhi:
+            z = 2 * zlo - z if z < zlo else 2 * zhi - z
+            n += 1
+        assert zr == pytest.approx(z, abs=1e-9)
+        assert vr == (-u if n % 2 else u)
