@@ -154,6 +154,28 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
               double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, void* stream);
 
 /*
+ * srbe_step_noalloc -- srbe_step without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks, kernels and results as srbe_step (bitwise equal).
+ * The step's workspace and its copy of ion_offsets live in a fixed device array of
+ * 64 MiB inside the library, one per GPU, held until the process ends; a step needing
+ * more (about 100 bytes per ion plus per-replica and per-mode terms: some 28 MB for 64
+ * paper-shaped cells) is refused with SRBE_EINVAL (srbe_last_error gives the size)
+ * before anything is enqueued.  Every call on one GPU, from any handle, shares that
+ * array, so calls whose work overlaps in time on one GPU (other streams, other threads)
+ * race and give wrong results: order them on one stream or synchronise between them.
+ * ion_offsets is copied to the device by an asynchronous copy on stream (pageable host
+ * memory is read before the call returns; pinned memory must stay unchanged until the
+ * stream reaches the copy).  srbe_electrode_forces cannot follow this call (its state
+ * is in the shared array).  No per-phase timing.  Calls no hipMalloc or hipFree.
+ * Errors: as srbe_step.
+ */
+int srbe_step_noalloc(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                      const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
+                      uint64_t step, const int32_t* kset_in, const double* Q_in, double* Q_out, double* F_out,
+                      double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, void* stream);
+
+/*
  * Captured steps.  srbe_graph_create records one srbe_step with fixed arguments
  * (the same meaning and checks as srbe_step, all device pointers kept by the
  * graph) into a HIP graph with its own workspace; srbe_graph_launch replays it on

@@ -66,6 +66,8 @@ def lib():
     L.srbe_step.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64,
                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.srbe_step.restype = ctypes.c_int
+    L.srbe_step_noalloc.argtypes = L.srbe_step.argtypes
+    L.srbe_step_noalloc.restype = ctypes.c_int
     L.srbe_sample.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_uint64, _vp, _vp, _vp]
     L.srbe_sample.restype = ctypes.c_int
     L.srbe_sync_status.argtypes = [_vp]
@@ -110,7 +112,7 @@ EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string
             "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
             "srbe_phase_name", "srbe_graph_create", "srbe_graph_launch", "srbe_graph_set_step",
             "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning", "srbe_electrode_forces",
-            "srbe_langevin_update"]
+            "srbe_langevin_update", "srbe_step_noalloc"]
 SRBE_N_PHASES = 16
 
 
@@ -226,6 +228,17 @@ def srbe_step(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out
     off, args = _step_args(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in, Q_in,
                            b_out, psibar_out, energy_out, kset_out)
     code = lib().srbe_step(*args, _stream(stream))
+    if check:
+        _check(h, code)
+    return code
+
+
+def srbe_step_noalloc(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in=None,
+                      Q_in=None, b_out=None, psibar_out=None, energy_out=None, kset_out=None, stream=None, check=True):
+    """One step whose workspace is the library's fixed device scratch array (no allocation)."""
+    off, args = _step_args(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, kset_in, Q_in,
+                           b_out, psibar_out, energy_out, kset_out)
+    code = lib().srbe_step_noalloc(*args, _stream(stream))
     if check:
         _check(h, code)
     return code

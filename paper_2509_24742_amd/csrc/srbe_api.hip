@@ -11,6 +11,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/srbe.h"
@@ -100,7 +101,18 @@ struct srbe_graph {
   uint64_t* step_dev = nullptr; // step counter read by the sampler, advanced by each replay
 };
 
+// Workspace of srbe_step_noalloc: a file-scope device array, one copy per GPU, held
+// until the process ends.  Host code never uses the array's name as an address: the
+// device address of each GPU's copy comes from hipGetSymbolAddress (with that device
+// current) and is kept in scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+void* scratch_ptr[kMaxScratchDevices] = {};
+std::mutex scratch_mu;
 
 int set_err(srbe_system* h, int code, const std::string& msg) {
   if (h) h->err = msg;
@@ -1280,6 +1292,60 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
     h->last_valid = true;
     h->last_fp32 = precision == SRBE_FP32;
   }
+  return rc;
+}
+
+int srbe_step_noalloc(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                      const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
+                      uint64_t step, const int32_t* kset_in, const double* Q_in, double* Q_out, double* F_out,
+                      double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, void* stream) {
+  if (!h) return SRBE_EINVAL;
+  h->last_valid = false;  // the scratch is shared: srbe_electrode_forces cannot follow this call
+  const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, kset_in,
+                   Q_in, Q_out, F_out, b_out, psibar_out, energy_out, kset_out};
+  int64_t max_nrep = 0;
+  int rc = check_step(h, a, max_nrep);
+  if (rc != SRBE_OK) return rc;
+  StepBufs b{};
+  fill_bufs(h, a, max_nrep, b);
+  const size_t off_bytes = align_up((size_t)(n_rep + 1) * sizeof(int64_t));
+  const size_t total = off_bytes + ws_layout(h, a, b, nullptr);
+  if (total > kScratchBytes)
+    return set_err(h, SRBE_EINVAL, "srbe_step_noalloc: the step needs " + std::to_string(total) +
+                                       " bytes of workspace, more than the " + std::to_string(kScratchBytes) +
+                                       " bytes of the fixed scratch array; use srbe_step");
+  if (h->device < 0 || h->device >= kMaxScratchDevices)
+    return set_err(h, SRBE_EINVAL, "srbe_step_noalloc: device index beyond the scratch table");
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[h->device]) {
+      // once per device, with that device current
+      int prev = 0;
+      hipError_t e = hipGetDevice(&prev);
+      if (e == hipSuccess) e = hipSetDevice(h->device);
+      void* ptr = nullptr;
+      if (e == hipSuccess) {
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        (void)hipSetDevice(prev);
+      }
+      if (e != hipSuccess || !ptr)
+        return set_err(h, SRBE_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      scratch_ptr[h->device] = ptr;
+    }
+    base = (char*)scratch_ptr[h->device];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // CSR offsets at the head of the scratch, copied on every call (another call may have
+  // used the scratch since); the step workspace after them
+  int64_t* off_dev = (int64_t*)base;
+  HIP_OK(h, hipMemcpyAsync(off_dev, ion_offsets, (size_t)(n_rep + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  ws_layout(h, a, b, base + off_bytes);
+  b.off = off_dev;
+  const bool prof = h->prof;
+  h->prof = false;  // phase timing would create events: off for this call
+  rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, s);
+  h->prof = prof;
   return rc;
 }
 
