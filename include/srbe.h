@@ -265,9 +265,15 @@ int srbe_sync_status(srbe_system* h);
  * (then resets).  Phases, in order: sample, cellsort (particle records and their
  * sort by cell), sf_ions, real_ele, real_ii, ele_potential, cp_gemm, post_charges,
  * sf_ele, real_ie, ion_force (the k-space and slab force), energy (the energy and the
- * real-space sums added to the forces); the remaining slots are unused ("").
+ * real-space sums added to the forces), sf_ions_finalize and sf_ele_finalize (the
+ * launches that add the structure-factor partial sums; sf_ions and sf_ele time the
+ * partial-sum launches alone); the remaining slots are unused ("").
  * srbe_phase_name(i) returns the name of phase i.  Captured steps (srbe_graph_*)
- * record no phase events.
+ * record no phase events.  srbe_profile_enable(h, n) with n > 1 launches every phase
+ * but energy (whose launch adds to F) n times in a row between its two events (the
+ * phases are idempotent: the step's results are unchanged), so that the events' own
+ * cost is spread over n launches; the counts read back are launches, so total ms /
+ * launches is the time of one launch.  n = 1 times single launches; n = 0 disables.
  */
 #define SRBE_N_PHASES 16
 int srbe_profile_enable(srbe_system* h, int32_t enable);

@@ -79,7 +79,9 @@ class System:
                 with open(cache) as f:
                     entries = json.load(f)
             if key in entries:
-                params = [int(entries[key]["params"][name]) for name in SRBE_TUNE_NAMES]
+                # a parameter the entry predates keeps the value the library would choose
+                dflt = dict(zip(SRBE_TUNE_NAMES, srbe_get_tuning(self.h, precision, off)))
+                params = [int(entries[key]["params"].get(name, dflt[name])) for name in SRBE_TUNE_NAMES]
                 srbe_set_tuning(self.h, precision, off, params)
                 return dict(params=params, ms_default=entries[key].get("ms_default"),
                             ms_tuned=entries[key].get("ms_tuned"), cached=True)

@@ -352,7 +352,9 @@ def srbe_sample(h, seed, step, kset_out, n_accepted_out=None, stream=None):
 
 
 def srbe_profile_enable(h, enable=True):
-    _check(h, lib().srbe_profile_enable(h, 1 if enable else 0))
+    """enable: False/0 off, True/1 one launch per phase, n > 1 n launches per phase between its events."""
+    n = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+    _check(h, lib().srbe_profile_enable(h, n))
 
 
 def srbe_phase_name(i):

@@ -82,8 +82,10 @@ struct srbe_system {
   std::vector<int64_t> off_cache;
   // per-phase timing
   bool prof = false;
+  int prof_rep = 1;                  // launches of each repeatable phase between its events
   std::vector<hipEvent_t> ev_pool;   // pairs (start, stop) recorded but not yet read
   std::vector<int> ev_phase;         // phase of each recorded pair
+  std::vector<int> ev_reps;          // launches between each recorded pair
   size_t ev_used = 0;                // pairs in use
   double prof_ms[SRBE_N_PHASES] = {0};
   int64_t prof_n[SRBE_N_PHASES] = {0};
@@ -566,7 +568,7 @@ inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 const char* kPhaseNames[SRBE_N_PHASES] = {"sample",       "cellsort", "sf_ions", "real_ele",  "real_ii",
                                           "ele_potential", "cp_gemm",  "post_charges", "sf_ele", "real_ie",
-                                          "ion_force",    "energy",   "",        "",          "",
+                                          "ion_force",    "energy",   "sf_ions_finalize", "sf_ele_finalize", "",
                                           ""};
 
 // Record an event pair around a phase when profiling is enabled.
@@ -591,7 +593,9 @@ struct PhaseTimer {
     }
     slot = h->ev_used++;
     if (h->ev_phase.size() < h->ev_used) h->ev_phase.resize(h->ev_used);
+    if (h->ev_reps.size() < h->ev_used) h->ev_reps.resize(h->ev_used);
     h->ev_phase[slot] = phase;
+    h->ev_reps[slot] = 1;
     (void)hipEventRecord(h->ev_pool[2 * slot], s);
   }
   ~PhaseTimer() {
@@ -847,7 +851,7 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
 enum { EV_CS = 0, EV_POST, EV_AUX };
 enum {
   PH_SAMPLE = 0, PH_CELLSORT, PH_SF_IONS, PH_REAL_ELE, PH_REAL_II, PH_ELE_POTENTIAL, PH_CP_GEMM, PH_POST_CHARGES,
-  PH_SF_ELE, PH_REAL_IE, PH_ION_FORCE, PH_ENERGY
+  PH_SF_ELE, PH_REAL_IE, PH_ION_FORCE, PH_ENERGY, PH_SF_IONS_FIN, PH_SF_ELE_FIN
 };
 
 // The step (Algorithm 1's order) on the caller's stream, with the real-space force
@@ -870,9 +874,14 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   const Geom& g = h->g;
   hipStream_t s1 = h->aux[1];
   const bool split = h->prof && !h->capturing;
+  // with phase timing, every phase but the last (which adds to F) is idempotent and is
+  // launched prof_rep times between its events, so that the events' own overhead is
+  // spread over the launches
   auto part = [&](int phase, hipStream_t st, auto&& launch) {
     PhaseTimer t(h, st, phase);
-    launch();
+    const int reps = (t.on && phase != PH_ENERGY) ? h->prof_rep : 1;
+    for (int i = 0; i < reps; ++i) launch();
+    if (t.on) h->ev_reps[t.slot] = reps;
   };
   if (split) {
     part(PH_SAMPLE, s, [&] { launch_front(g, b, fp32, FRONT_SAMPLE, s); });
@@ -883,10 +892,8 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   const bool real = b.real != 0;  // else k-space only: no real-space passes, no side stream
   if (real) HIP_OK(h, hipEventRecord(h->ev[EV_CS], s));
   if (split) {
-    part(PH_SF_IONS, s, [&] {
-      launch_stage_ions(g, b, fp32, STAGE_SF, s);
-      launch_sf_finalize(g, b, fp32, 1, s);
-    });
+    part(PH_SF_IONS, s, [&] { launch_stage_ions(g, b, fp32, STAGE_SF, s); });
+    part(PH_SF_IONS_FIN, s, [&] { launch_sf_finalize(g, b, fp32, 1, s); });
   } else {
     launch_stage_ions(g, b, fp32, real ? STAGE_SF | STAGE_REAL : STAGE_SF, s);
   }
@@ -909,10 +916,8 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
     });
   part(PH_POST_CHARGES, s, [&] { launch_post_charges(g, b, fixedQ, fp32, s); });
   if (real) HIP_OK(h, hipEventRecord(h->ev[EV_POST], s));
-  part(PH_SF_ELE, s, [&] {
-    launch_stage_ele(g, b, fp32, STAGE_SF, s);
-    launch_sf_finalize(g, b, fp32, 2, s);
-  });
+  part(PH_SF_ELE, s, [&] { launch_stage_ele(g, b, fp32, STAGE_SF, s); });
+  part(PH_SF_ELE_FIN, s, [&] { launch_sf_finalize(g, b, fp32, 2, s); });
   if (real) {
     HIP_OK(h, hipStreamWaitEvent(s1, h->ev[EV_POST], 0));
     part(PH_REAL_IE, s1, [&] { launch_stage_ele(g, b, fp32, STAGE_REAL, s1); });
@@ -1631,7 +1636,9 @@ const char* srbe_phase_name(int32_t phase) {
 
 int srbe_profile_enable(srbe_system* h, int32_t enable) {
   if (!h) return SRBE_EINVAL;
+  if (enable < 0) return set_err(h, SRBE_EINVAL, "srbe_profile_enable: negative count");
   h->prof = enable != 0;
+  h->prof_rep = enable > 1 ? enable : 1;
   return SRBE_OK;
 }
 
@@ -1642,7 +1649,7 @@ int srbe_profile_read(srbe_system* h, double* ms_out, int64_t* launches_out) {
     float ms = 0.f;
     HIP_OK(h, hipEventElapsedTime(&ms, h->ev_pool[2 * i], h->ev_pool[2 * i + 1]));
     h->prof_ms[h->ev_phase[i]] += ms;
-    h->prof_n[h->ev_phase[i]] += 1;
+    h->prof_n[h->ev_phase[i]] += h->ev_reps[i];
   }
   h->ev_used = 0;
   for (int p = 0; p < SRBE_N_PHASES; ++p) {

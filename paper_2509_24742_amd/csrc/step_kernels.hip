@@ -632,24 +632,11 @@ void launch_set_step(uint64_t* step_dev, uint64_t v, hipStream_t s) {
 // new charges, S = S1 + S2.  (A last-arriving-block reduction would need an
 // agent-scope release fence per block, which writes back L2 and costs far more
 // than the extra launch on a multi-XCD device.)
-__device__ __forceinline__ void finalize_tile(const Geom& g, int r, int k, const double2* part, int nchunk,
+// S (and the coefficients, mode records) of mode k of replica r from its sums (sr, si)
+// over the particles of this stage.
+__device__ __forceinline__ void finalize_mode(const Geom& g, int r, int k, double sr, double si,
                                               const int4* modes, const double* w, double2* S1, double2* coef,
                                               ModeRec32* rec, int stage, unsigned* status) {
-  if (k >= g.K) return;
-  // chunks 16 at a time, all requested before the first add, added in chunk order
-  double sr = 0.0, si = 0.0;
-  for (int c = 0; c < nchunk; c += 16) {
-    double2 p[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      p[u] = c + u < nchunk ? part[((size_t)r * nchunk + c + u) * g.K + k] : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (c + u < nchunk) {
-        sr += p[u].x;
-        si += p[u].y;
-      }
-  }
   const size_t idx = (size_t)r * g.K + k;
   if (stage == 1) {
     S1[idx] = make_double2(sr, si);
@@ -676,6 +663,83 @@ __device__ __forceinline__ void finalize_tile(const Geom& g, int r, int k, const
   }
 }
 
+__device__ __forceinline__ void finalize_tile(const Geom& g, int r, int k, const double2* part, int nchunk,
+                                              const int4* modes, const double* w, double2* S1, double2* coef,
+                                              ModeRec32* rec, int stage, unsigned* status) {
+  if (k >= g.K) return;
+  // chunks 16 at a time, all requested before the first add, added in chunk order
+  double sr = 0.0, si = 0.0;
+  for (int c = 0; c < nchunk; c += 16) {
+    double2 p[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      p[u] = c + u < nchunk ? part[((size_t)r * nchunk + c + u) * g.K + k] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (c + u < nchunk) {
+        sr += p[u].x;
+        si += p[u].y;
+      }
+  }
+  finalize_mode(g, r, k, sr, si, modes, w, S1, coef, rec, stage, status);
+}
+
+// Sum over particles [j0, j1) of q_j exp(i 2 pi m.s_j) for one mode (FP64 fractions).
+template <bool ION>
+__device__ __forceinline__ double2 sf64_sum(const double4* __restrict__ pts, const double* __restrict__ qq, int4 m,
+                                            int j0, int j1) {
+  const double mx = m.x, my = m.y, mz = m.z;
+  double sr = 0.0, si = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double4 p = pts[j];
+    double t = fma(mx, p.x, fma(my, p.y, mz * p.z));
+    t -= rint(t);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    const double qj = ION ? p.w : qq[j];
+    sr = fma(qj, cs, sr);
+    si = fma(qj, sn, si);
+  }
+  return make_double2(sr, si);
+}
+
+// FP32: exact integer phase m.u mod 2^32 (u = 32-bit fixed-point fractions), the
+// hardware sin/cos of the phase in revolutions, FP32 sums over blocks of 64
+// particles carried in FP64.
+template <bool ION>
+__device__ __forceinline__ double2 sf32_sum(const uint4* __restrict__ pts, const float* __restrict__ qq, int4 m,
+                                            int j0, int j1) {
+  const uint32_t mx = (uint32_t)m.x, my = (uint32_t)m.y, mz = (uint32_t)m.z;
+  double dr = 0.0, di = 0.0;
+  for (int jb = j0; jb < j1; jb += 64) {
+    const int je = min(j1, jb + 64);
+    float ar = 0.f, ai = 0.f;
+    int j = jb;
+    for (; j + 4 <= je; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint4 p = pts[j + u];
+        const float qj = ION ? __uint_as_float(p.w) : qq[j + u];
+        const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
+        const float x = (float)(int32_t)ph * 0x1.0p-32f;
+        ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
+        ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
+      }
+    }
+    for (; j < je; ++j) {
+      const uint4 p = pts[j];
+      const float qj = ION ? __uint_as_float(p.w) : qq[j];
+      const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
+      const float x = (float)(int32_t)ph * 0x1.0p-32f;
+      ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
+      ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
+    }
+    dr += (double)ar;
+    di += (double)ai;
+  }
+  return make_double2(dr, di);
+}
+
 // Block (tile, chunk, r) of the partial sums: modes [256 tile, 256 tile + 256) over
 // the particle chunk.
 template <bool ION>
@@ -690,27 +754,9 @@ __device__ __forceinline__ void sf64_block(const Geom& g, const int64_t* __restr
   const int j0 = b + ch * chunk;
   const int j1 = min(e, j0 + chunk);
   const double* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
-  double sr = 0.0, si = 0.0;
-  if (k < g.K) {
-    const int4 m = modes[(size_t)r * g.K + k];
-    const double mx = m.x, my = m.y, mz = m.z;
-    for (int j = j0; j < j1; ++j) {
-      const double4 p = pts[j];
-      double t = fma(mx, p.x, fma(my, p.y, mz * p.z));
-      t -= rint(t);
-      double sn, cs;
-      sincospi(2.0 * t, &sn, &cs);
-      const double qj = ION ? p.w : qq[j];
-      sr = fma(qj, cs, sr);
-      si = fma(qj, sn, si);
-    }
-    part[((size_t)r * nchunk + ch) * g.K + k] = make_double2(sr, si);
-  }
+  if (k < g.K) part[((size_t)r * nchunk + ch) * g.K + k] = sf64_sum<ION>(pts, qq, modes[(size_t)r * g.K + k], j0, j1);
 }
 
-// FP32: exact integer phase m.u mod 2^32 (u = 32-bit fixed-point fractions), the
-// hardware sin/cos of the phase in revolutions, FP32 sums over blocks of 64
-// particles carried in FP64.
 template <bool ION>
 __device__ __forceinline__ void sf32_block(const Geom& g, const int64_t* __restrict__ off,
                                            const uint4* __restrict__ pts, const float* __restrict__ qe,
@@ -723,38 +769,7 @@ __device__ __forceinline__ void sf32_block(const Geom& g, const int64_t* __restr
   const int j0 = b + ch * chunk;
   const int j1 = min(e, j0 + chunk);
   const float* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
-  if (k < g.K) {
-    const int4 m = modes[(size_t)r * g.K + k];
-    const uint32_t mx = (uint32_t)m.x, my = (uint32_t)m.y, mz = (uint32_t)m.z;
-    double dr = 0.0, di = 0.0;
-    for (int jb = j0; jb < j1; jb += 64) {
-      const int je = min(j1, jb + 64);
-      float ar = 0.f, ai = 0.f;
-      int j = jb;
-      for (; j + 4 <= je; j += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const uint4 p = pts[j + u];
-          const float qj = ION ? __uint_as_float(p.w) : qq[j + u];
-          const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
-          const float x = (float)(int32_t)ph * 0x1.0p-32f;
-          ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
-          ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
-        }
-      }
-      for (; j < je; ++j) {
-        const uint4 p = pts[j];
-        const float qj = ION ? __uint_as_float(p.w) : qq[j];
-        const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
-        const float x = (float)(int32_t)ph * 0x1.0p-32f;
-        ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
-        ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
-      }
-      dr += (double)ar;
-      di += (double)ai;
-    }
-    part[((size_t)r * nchunk + ch) * g.K + k] = make_double2(dr, di);
-  }
+  if (k < g.K) part[((size_t)r * nchunk + ch) * g.K + k] = sf32_sum<ION>(pts, qq, modes[(size_t)r * g.K + k], j0, j1);
 }
 
 // Partial-sum block lb of stage 1 (ions, ION) or 2 (electrodes with the new charges),
@@ -1181,8 +1196,8 @@ __global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf,
 }
 
 void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
-  const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ion * b.R : 0;
   const int units = b.n_ele_chunks * b.R, esplit = b.esplit;
+  const int nsf = (parts & STAGE_SF && g.K > 0) ? b.ktiles * b.nchunk_ion * b.R : 0;
   const int nre = (parts & STAGE_REAL && g.n_ele > 0) ? (units * esplit + 3) / 4 : 0;
   if (nsf + nre == 0) return;
   if (fp32)

@@ -106,7 +106,8 @@ def test_split_launches_match_fused(precision):
         assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
         _same(got, ref)
         for name in ("sample", "cellsort", "sf_ions", "real_ele", "real_ii", "ele_potential", "cp_gemm",
-                     "post_charges", "sf_ele", "real_ie", "ion_force", "energy"):
+                     "post_charges", "sf_ele", "real_ie", "ion_force", "energy", "sf_ions_finalize",
+                     "sf_ele_finalize"):
             assert prof[name][1] == 1, (name, prof[name])
     finally:
         sysm.close()
