@@ -199,6 +199,53 @@ int srbe_graph_set_step(srbe_graph* g, uint64_t step, void* stream);
 void srbe_graph_destroy(srbe_graph* g);
 
 /*
+ * Batches of systems of different geometry (Sec. 2-3 for each system; the same step as
+ * srbe_step).  srbe_batch_create groups existing handles (each its own box, electrodes,
+ * alpha, M, P, precision-independent set-up); a batch step then runs every replica of
+ * every system through the step with ONE launch per phase for all systems together (each
+ * launch's blocks look up their system in a per-system table of geometry and buffers),
+ * instead of one launch per phase and system.  Results equal srbe_step's for each system
+ * to rounding order (the same kernels and per-system launch shapes).
+ *
+ * srbe_batch_create -- systems: host array of n_systems handles (1..4096, all on one
+ * device), not owned: they must outlive the batch and its graphs.
+ * srbe_batch_step -- n_rep replicas, replica r belonging to system system_of_replica[r]
+ * (host int32, non-decreasing, so each system's replicas are consecutive).
+ * ion_offsets host n_rep + 1 int64 CSR over all replicas (ion_offsets[0] = 0); ion_xyz
+ * (device 3N SoA), ion_q (N), F_out (3N SoA) as in srbe_step over the whole batch.
+ * Per replica: dpsi, seed (device, n_rep; seed may be NULL only if no system has P > 0),
+ * psibar_out (device, n_rep, required), energy_out (device, n_rep, or NULL).  Electrode
+ * arrays are CSR over replicas: replica r's n_ele(system) entries start at the sum of
+ * the n_ele of the replicas before it -- Q_out (required), Q_in (fixed charges, or NULL
+ * for the constant-potential solve), b_out (or NULL).  Launch shapes: each system's
+ * stored or default parameters for its (precision, replica count, largest replica),
+ * with 4 waves and unroll 4 in the potential and force passes and 16-wide GEMM blocks
+ * for all.  The modes are sampled on the device (no kset_in / kset_out).  Asynchronous
+ * on stream; device faults land in each system's status word (srbe_batch_sync_status).
+ * Errors: SRBE_EINVAL, SRBE_ENOMEM, SRBE_EHIP (srbe_batch_last_error gives a message).
+ * srbe_batch_graph_* -- the batch step captured with fixed arguments, as srbe_graph_*.
+ * srbe_batch_sync_status -- srbe_sync_status of every system (the first fault found).
+ */
+typedef struct srbe_batch srbe_batch;
+typedef struct srbe_batch_graph srbe_batch_graph;
+int srbe_batch_create(srbe_system* const* systems, int32_t n_systems, srbe_batch** out);
+void srbe_batch_destroy(srbe_batch* b);
+const char* srbe_batch_last_error(const srbe_batch* b);
+int srbe_batch_sync_status(srbe_batch* b);
+int srbe_batch_step(srbe_batch* b, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                    const int32_t* system_of_replica, const double* ion_xyz, const double* ion_q, const double* dpsi,
+                    const uint64_t* seed, uint64_t step, const double* Q_in, double* Q_out, double* F_out,
+                    double* b_out, double* psibar_out, double* energy_out, void* stream);
+int srbe_batch_graph_create(srbe_batch* b, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                            const int32_t* system_of_replica, const double* ion_xyz, const double* ion_q,
+                            const double* dpsi, const uint64_t* seed, uint64_t first_step, const double* Q_in,
+                            double* Q_out, double* F_out, double* b_out, double* psibar_out, double* energy_out,
+                            srbe_batch_graph** out);
+int srbe_batch_graph_launch(srbe_batch_graph* g, void* stream);
+int srbe_batch_graph_set_step(srbe_batch_graph* g, uint64_t step, void* stream);
+void srbe_batch_graph_destroy(srbe_batch_graph* g);
+
+/*
  * srbe_electrode_forces -- forces on the electrode atoms from the estimator of the last
  * srbe_step on this handle: F_j = -Q_j grad Phi*(R_j), with the same sampled modes,
  * charges and positions.  Its parts:

@@ -104,6 +104,26 @@ def lib():
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _vp]
     L.srbe_langevin_update.restype = ctypes.c_int
+    L.srbe_batch_create.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]
+    L.srbe_batch_create.restype = ctypes.c_int
+    L.srbe_batch_destroy.argtypes = [_vp]
+    L.srbe_batch_destroy.restype = None
+    L.srbe_batch_last_error.argtypes = [_vp]
+    L.srbe_batch_last_error.restype = ctypes.c_char_p
+    L.srbe_batch_sync_status.argtypes = [_vp]
+    L.srbe_batch_sync_status.restype = ctypes.c_int
+    L.srbe_batch_step.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64,
+                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.srbe_batch_step.restype = ctypes.c_int
+    L.srbe_batch_graph_create.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+    L.srbe_batch_graph_create.restype = ctypes.c_int
+    L.srbe_batch_graph_launch.argtypes = [_vp, _vp]
+    L.srbe_batch_graph_launch.restype = ctypes.c_int
+    L.srbe_batch_graph_set_step.argtypes = [_vp, ctypes.c_uint64, _vp]
+    L.srbe_batch_graph_set_step.restype = ctypes.c_int
+    L.srbe_batch_graph_destroy.argtypes = [_vp]
+    L.srbe_batch_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -112,7 +132,9 @@ EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string
             "srbe_sync_status", "srbe_normaliser", "srbe_n_ele", "srbe_profile_enable", "srbe_profile_read",
             "srbe_phase_name", "srbe_graph_create", "srbe_graph_launch", "srbe_graph_set_step",
             "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning", "srbe_electrode_forces",
-            "srbe_langevin_update", "srbe_step_noalloc"]
+            "srbe_langevin_update", "srbe_step_noalloc", "srbe_batch_create", "srbe_batch_destroy",
+            "srbe_batch_last_error", "srbe_batch_sync_status", "srbe_batch_step", "srbe_batch_graph_create",
+            "srbe_batch_graph_launch", "srbe_batch_graph_set_step", "srbe_batch_graph_destroy"]
 SRBE_N_PHASES = 16
 
 
@@ -367,3 +389,98 @@ def srbe_profile_read(h):
     n = np.zeros(SRBE_N_PHASES, dtype=np.int64)
     _check(h, lib().srbe_profile_read(h, ms.ctypes.data, n.ctypes.data))
     return {srbe_phase_name(i): (float(ms[i]), int(n[i])) for i in range(SRBE_N_PHASES)}
+
+
+# ---------------------------------------------------------------- batches of systems
+
+_batch_members = {}  # batch handle value -> (handles, their electrode counts, their P)
+
+
+def _bcheck(bt, code):
+    if code != SRBE_OK:
+        msg = lib().srbe_batch_last_error(bt).decode() if bt else ""
+        raise SrbeError(code, msg or lib().srbe_error_string(code).decode())
+
+
+def srbe_batch_create(handles):
+    """A batch over the given system handles (a list; they must outlive the batch)."""
+    arr = (_vp * len(handles))(*[h.value for h in handles])
+    bt = _vp()
+    code = lib().srbe_batch_create(arr, len(handles), ctypes.byref(bt))
+    if code != SRBE_OK:
+        raise SrbeError(code, lib().srbe_error_string(code).decode())
+    _batch_members[bt.value] = ([srbe_n_ele(h) for h in handles], [_batch_size[h.value] for h in handles])
+    return bt
+
+
+def srbe_batch_destroy(bt):
+    _batch_members.pop(bt.value, None)
+    lib().srbe_batch_destroy(bt)
+
+
+def srbe_batch_last_error(bt):
+    return lib().srbe_batch_last_error(bt).decode()
+
+
+def srbe_batch_sync_status(bt):
+    return lib().srbe_batch_sync_status(bt)
+
+
+def _batch_args(bt, precision, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out, Q_in,
+                b_out, psibar_out, energy_out):
+    import torch
+    off = np.ascontiguousarray(np.asarray(ion_offsets, dtype=np.int64))
+    sor = np.ascontiguousarray(np.asarray(system_of_replica, dtype=np.int32))
+    R = off.shape[0] - 1
+    if sor.shape != (R,):
+        raise ValueError("system_of_replica must have one entry per replica")
+    N = int(off[-1])
+    n_ele, _ = _batch_members[bt.value]
+    nq = int(sum(n_ele[k] for k in sor))
+    return (off, sor), [
+        bt, int(precision), R, off.ctypes.data, sor.ctypes.data,
+        _dev(ion_xyz, torch.float64, 3 * N, "ion_xyz", allow_none=N == 0),
+        _dev(ion_q, torch.float64, N, "ion_q", allow_none=N == 0),
+        _dev(dpsi, torch.float64, R, "dpsi"),
+        _dev(seed, torch.uint64, R, "seed", allow_none=True),
+        ctypes.c_uint64(int(step)),
+        _dev(Q_in, torch.float64, nq, "Q_in", allow_none=True),
+        _dev(Q_out, torch.float64, nq, "Q_out"),
+        _dev(F_out, torch.float64, 3 * N, "F_out", allow_none=N == 0),
+        _dev(b_out, torch.float64, nq, "b_out", allow_none=True),
+        _dev(psibar_out, torch.float64, R, "psibar_out"),
+        _dev(energy_out, torch.float64, R, "energy_out", allow_none=True),
+    ]
+
+
+def srbe_batch_step(bt, precision, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, step, Q_out, F_out,
+                    psibar_out, Q_in=None, b_out=None, energy_out=None, stream=None):
+    """One step of every replica of a batch of systems (see include/srbe.h)."""
+    keep, args = _batch_args(bt, precision, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, step, Q_out,
+                             F_out, Q_in, b_out, psibar_out, energy_out)
+    _bcheck(bt, lib().srbe_batch_step(*args, _stream(stream)))
+
+
+def srbe_batch_graph_create(bt, precision, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, first_step,
+                            Q_out, F_out, psibar_out, Q_in=None, b_out=None, energy_out=None):
+    keep, args = _batch_args(bt, precision, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, first_step,
+                             Q_out, F_out, Q_in, b_out, psibar_out, energy_out)
+    gr = _vp()
+    _bcheck(bt, lib().srbe_batch_graph_create(*args, ctypes.byref(gr)))
+    return gr
+
+
+def srbe_batch_graph_launch(gr, stream=None):
+    code = lib().srbe_batch_graph_launch(gr, _stream(stream))
+    if code != SRBE_OK:
+        raise SrbeError(code, lib().srbe_error_string(code).decode())
+
+
+def srbe_batch_graph_set_step(gr, step, stream=None):
+    code = lib().srbe_batch_graph_set_step(gr, ctypes.c_uint64(int(step)), _stream(stream))
+    if code != SRBE_OK:
+        raise SrbeError(code, lib().srbe_error_string(code).decode())
+
+
+def srbe_batch_graph_destroy(gr):
+    lib().srbe_batch_graph_destroy(gr)

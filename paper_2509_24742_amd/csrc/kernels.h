@@ -126,7 +126,63 @@ struct StepBufs {
   int32_t* kset_out;
   int32_t* nacc_out;
   const double* Q_in;
+  const double* Sext;       // the dense charge solve's S_ext (null: lattice solve or fixed charges)
 };
+
+// Multi-system launches: one launch runs a phase of the step for every system of a
+// batch (systems of different geometry, each with its own replicas).  Block L of the
+// launch belongs to system s with start[s] <= L < start[s + 1] and runs that system's
+// block L - start[s] with its descriptor d[s] (the Geom and StepBufs a single-system
+// launch would take) and its integer arguments iarg[kMultiArgs s ..].
+struct SysDesc {
+  Geom g;
+  StepBufs b;
+};
+constexpr int kMultiArgs = 4;
+struct MultiLaunch {
+  const SysDesc* d;   // nsys
+  const int* start;   // nsys + 1
+  const int* iarg;    // nsys x kMultiArgs
+  int nsys;
+  uint64_t* step_adv; // the final phase's first block advances this counter (graph replays), or null
+};
+
+// The system of block L (wave-uniform binary search over the block starts).
+__device__ __forceinline__ int multi_system(const MultiLaunch& m, int L) {
+  int lo = 0, hi = m.nsys;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (m.start[mid] <= L) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Phases of the multi-system launches (launch_multi).
+enum MultiPhase {
+  MP_FRONT = 0,        // iarg: nsamp (sampler blocks before the one-block sorts)
+  MP_BS_ZERO,          // multi-block sort: clear the counts (blocks of 256 counts)
+  MP_BS_COUNT, MP_BS_SCAN_CHUNKS, MP_BS_SCAN_TOTALS, MP_BS_SCAN_OFFSETS, MP_BS_SCATTER, MP_BS_RANK,
+  MP_STAGE_IONS,       // iarg: nsf, nre, esplit
+  MP_SF_FINALIZE,      // iarg: stage
+  MP_ELEPOT,           // iarg: electrode tiles of 64
+  MP_CP_GEMM,          // iarg: row tiles, replica tiles
+  MP_POST_CHARGES,     // iarg: fixedQ
+  MP_STAGE_ELE,        // iarg: nsf, nie
+  MP_ION_FORCE,        // iarg: ion tiles of 64
+  MP_REAL_II,          // iarg: tiles
+  MP_ENERGY_PARTS,
+  MP_FINAL,            // iarg: ne, fixedQ, first ion, ions
+};
+// Launch one phase for the systems of m (nblocks = m's start[nsys]); fp32, W (waves per
+// block of the potential and force passes), U (their unroll) and KB (GEMM contraction
+// block) select the kernel and must be the same for every system.
+void launch_multi(int phase, int fp32, int W, int U, int KB, const MultiLaunch& m, int nblocks, size_t lds,
+                  hipStream_t s);
+// The lattice solve's three launches (step 0, 1, 2) for the lattice systems of m; grid of
+// one system's step: lattice_grid.
+void launch_multi_lattice(int step, const MultiLaunch& m, int nblocks, size_t lds, hipStream_t s);
+void lattice_grid(const StepBufs& b, int step, int& blocks, size_t& lds);
+size_t sample_lds_bytes(int P);
 
 // Parts of the fused launches (bit masks).  A step runs each fused launch whole; with
 // phase timing on, each part is launched on its own so that it can be timed.

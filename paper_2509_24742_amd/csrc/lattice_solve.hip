@@ -45,12 +45,14 @@ constexpr int kLatThreads = 256;
 
 // Launch 1: block (r, w, iy); the row of v and the x twiddles in LDS, thread p sums
 // over ix.  LDS: nx doubles + nx double2.
-__global__ __launch_bounds__(kLatThreads) void k_lat_fwd_x(LatticeSolve L, const double* __restrict__ V, int ldv) {
+// (each launch's body takes its block index b; a multi-system launch passes the block's
+// index within its system)
+__device__ __forceinline__ void lat_fwd_x_body(const LatticeSolve& L, const double* __restrict__ V, int ldv, int b) {
   extern __shared__ double2 lds_fx[];
   const int nx = L.nx, ny = L.ny;
   double2* tw = lds_fx;
   double* row = reinterpret_cast<double*>(lds_fx + nx);
-  const int b = blockIdx.x, r = b / (2 * ny), wy = b - r * 2 * ny;  // wy = w ny + iy
+  const int r = b / (2 * ny), wy = b - r * 2 * ny;  // wy = w ny + iy
   const int* site = L.site + (size_t)wy * nx;
   for (int ix = threadIdx.x; ix < nx; ix += kLatThreads) {
     row[ix] = V[(size_t)r * ldv + site[ix]];
@@ -73,12 +75,16 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_fwd_x(LatticeSolve L, const
   }
 }
 
+__global__ __launch_bounds__(kLatThreads) void k_lat_fwd_x(LatticeSolve L, const double* __restrict__ V, int ldv) {
+  lat_fwd_x_body(L, V, ldv, blockIdx.x);
+}
+
 // Launch 2: block (r, p); both walls' column p and the y twiddles through LDS.
 // LDS: 5 ny double2 ([2][ny] input column, [2][ny] solved modes, ny twiddles).
-__global__ __launch_bounds__(kLatThreads) void k_lat_column(LatticeSolve L, double* __restrict__ Qext, int n) {
+__device__ __forceinline__ void lat_column_body(const LatticeSolve& L, double* __restrict__ Qext, int n, int b) {
   extern __shared__ double2 col[];
   const int nx = L.nx, ny = L.ny;
-  const int b = blockIdx.x, r = b / nx, p = b - r * nx;
+  const int r = b / nx, p = b - r * nx;
   double2* cin = col;
   double2* cu = col + 2 * ny;
   double2* tw = col + 4 * ny;
@@ -133,13 +139,17 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_column(LatticeSolve L, doub
   }
 }
 
+__global__ __launch_bounds__(kLatThreads) void k_lat_column(LatticeSolve L, double* __restrict__ Qext, int n) {
+  lat_column_body(L, Qext, n, blockIdx.x);
+}
+
 // Launch 3: block (r, w, iy); the row of half-inverted modes and the x twiddles in
 // LDS, thread ix sums over p and writes the charge of its site.  LDS: 2 nx double2.
-__global__ __launch_bounds__(kLatThreads) void k_lat_inv_x(LatticeSolve L, double* __restrict__ Qext, int n) {
+__device__ __forceinline__ void lat_inv_x_body(const LatticeSolve& L, double* __restrict__ Qext, int n, int b) {
   extern __shared__ double2 rowc[];
   const int nx = L.nx, ny = L.ny;
   double2* tw = rowc + nx;
-  const int b = blockIdx.x, r = b / (2 * ny), wy = b - r * 2 * ny;
+  const int r = b / (2 * ny), wy = b - r * 2 * ny;
   const double2* U = L.U + ((size_t)r * 2 * ny + wy) * nx;
   for (int p = threadIdx.x; p < nx; p += kLatThreads) {
     rowc[p] = U[p];
@@ -162,7 +172,43 @@ __global__ __launch_bounds__(kLatThreads) void k_lat_inv_x(LatticeSolve L, doubl
   }
 }
 
+__global__ __launch_bounds__(kLatThreads) void k_lat_inv_x(LatticeSolve L, double* __restrict__ Qext, int n) {
+  lat_inv_x_body(L, Qext, n, blockIdx.x);
+}
+
+// The three launches for every lattice system of a batch at once (see MultiLaunch).
+template <int STEP>
+__global__ __launch_bounds__(kLatThreads) void k_multi_lattice(MultiLaunch m) {
+  const int s = multi_system(m, blockIdx.x), lb = blockIdx.x - m.start[s];
+  const StepBufs& b = m.d[s].b;
+  const int n = m.d[s].g.n_ele;
+  if constexpr (STEP == 0)
+    lat_fwd_x_body(b.lat, b.V, ldcp(n), lb);
+  else if constexpr (STEP == 1)
+    lat_column_body(b.lat, b.Qext, n, lb);
+  else
+    lat_inv_x_body(b.lat, b.Qext, n, lb);
+}
+
 }  // namespace
+
+void lattice_grid(const StepBufs& b, int step, int& blocks, size_t& lds) {
+  const LatticeSolve& L = b.lat;
+  blocks = step == 1 ? b.R * L.nx : b.R * 2 * L.ny;
+  lds = step == 0 ? (size_t)L.nx * (sizeof(double) + sizeof(double2))
+        : step == 1 ? (size_t)5 * L.ny * sizeof(double2)
+                    : (size_t)2 * L.nx * sizeof(double2);
+}
+
+void launch_multi_lattice(int step, const MultiLaunch& m, int nblocks, size_t lds, hipStream_t s) {
+  if (nblocks == 0) return;
+  if (step == 0)
+    hipLaunchKernelGGL(k_multi_lattice<0>, dim3(nblocks), dim3(kLatThreads), lds, s, m);
+  else if (step == 1)
+    hipLaunchKernelGGL(k_multi_lattice<1>, dim3(nblocks), dim3(kLatThreads), lds, s, m);
+  else
+    hipLaunchKernelGGL(k_multi_lattice<2>, dim3(nblocks), dim3(kLatThreads), lds, s, m);
+}
 
 void launch_lattice_solve(const Geom& g, const StepBufs& b, hipStream_t s) {
   const LatticeSolve& L = b.lat;

@@ -94,6 +94,29 @@ struct srbe_system {
   std::string err;
 };
 
+// A batch of systems of different geometry (srbe_batch_*): the handles are the caller's.
+struct srbe_batch {
+  std::vector<srbe_system*> sys;
+  int device = 0;
+  hipStream_t aux = nullptr;  // the real-space force passes beside the chain
+  hipEvent_t ev[3] = {};
+  void* ws = nullptr;         // eager steps' workspace and descriptor tables (grown on demand)
+  size_t ws_bytes = 0;
+  void* tab = nullptr;
+  size_t tab_bytes = 0;
+  bool capturing = false;
+  std::string err;
+};
+
+struct srbe_batch_graph {
+  srbe_batch* bt = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  void* tab = nullptr;
+  uint64_t* step_dev = nullptr;
+};
+
 struct srbe_graph {
   srbe_system* h = nullptr;
   hipGraph_t graph = nullptr;
@@ -790,55 +813,64 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.kset_out = a.kset_out;
   b.nacc_out = nullptr;
   b.Q_in = a.Q_in;
+  b.Sext = h->Sext;
 }
 
 // Workspace layout: returns the bytes needed; with a base pointer, also assigns the
-// workspace members of b (caller-given b_out / energy_out are kept).
-size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* base) {
+// workspace members of b (caller-given b_out / energy_out are kept).  parts selects the
+// per-ion arrays (1; n_ions of them, default all of the call's ions) and the per-replica
+// arrays (2): a batch of systems shares one set of per-ion arrays indexed by the ions'
+// positions in the whole batch, and gives every system its own per-replica arrays.
+size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* base, int parts = 3,
+                 int64_t n_ions = -1, bool any_big_sort = false) {
   const Geom& g = h->g;
   const int R = a.n_rep, K = std::max(g.K, 1), n = h->n_ele;
-  const int64_t N1 = std::max<int64_t>(a.ion_offsets[R], 1);
+  const int64_t N1 = std::max<int64_t>(n_ions >= 0 ? n_ions : a.ion_offsets[R], 1);
   const bool fp32 = a.precision == SRBE_FP32, fixedQ = a.Q_in != nullptr;
+  const bool ion = parts & 1, rep = parts & 2;
+  const bool big = b.bigsort.ntile != 0 || any_big_sort;
   const int nch = std::max(b.nchunk_ion, b.nchunk_ele);
   struct Item {
     void** ptr;
     size_t bytes;
   };
+  auto I = [&](size_t v) { return ion ? v : 0; };  // per-ion sizes
+  auto P = [&](size_t v) { return rep ? v : 0; };  // per-replica sizes
   const Item items[] = {
-      {(void**)&b.scal, (size_t)R * 4 * sizeof(double)},
-      {(void**)&b.modes, (size_t)R * K * sizeof(int4)},
-      {(void**)&b.w, (size_t)R * K * sizeof(double)},
-      {(void**)&b.ion_fx, fp32 ? (size_t)N1 * sizeof(uint4) : 0},
-      {(void**)&b.ion_d4, fp32 ? 0 : (size_t)N1 * sizeof(double4)},
-      {(void**)&b.keys, (size_t)N1 * sizeof(unsigned)},
-      {(void**)&b.perm, (size_t)N1 * sizeof(int)},
-      {(void**)&b.scell, (size_t)N1 * sizeof(int)},
-      {(void**)&b.cstart, (size_t)R * (g.ncell + 1) * sizeof(int)},
-      {(void**)&b.sfx, fp32 ? (size_t)(N1 + kScanPad) * sizeof(uint4) : 0},
-      {(void**)&b.sd4, fp32 ? 0 : (size_t)(N1 + kScanPad) * sizeof(double4)},
-      {(void**)&b.part, (size_t)R * nch * K * sizeof(double2)},
-      {(void**)&b.S1, (size_t)R * K * sizeof(double2)},
-      {(void**)&b.coef, (size_t)R * K * sizeof(double2)},
-      {(void**)&b.rec, fp32 ? (size_t)R * K * sizeof(ModeRec32) : 0},
-      {(void**)&b.bN, (size_t)R * n * sizeof(double)},
-      {(void**)&b.bstar, a.b_out ? 0 : (size_t)R * n * sizeof(double)},
-      {(void**)&b.V, (size_t)R * ldcp(n) * sizeof(double)},
-      {(void**)&b.Qext, fixedQ ? 0 : (size_t)b.ksplit * R * (n + 1) * sizeof(double)},
-      {(void**)&b.Qf, fp32 ? (size_t)R * n * sizeof(float) : 0},
-      {(void**)&b.Qsf, fp32 ? ((size_t)R * n + kScanPad) * sizeof(float) : 0},
-      {(void**)&b.Qsd, fp32 ? 0 : ((size_t)R * n + kScanPad) * sizeof(double)},
-      {(void**)&b.rsum, (size_t)R * kRsumStride * sizeof(double)},
-      {(void**)&b.phi, (size_t)N1 * sizeof(double)},
-      {(void**)&b.Fii, (size_t)3 * N1 * sizeof(double)},
-      {(void**)&b.Fie, (size_t)3 * N1 * sizeof(double)},
-      {(void**)&b.energy_out, a.energy_out ? 0 : (size_t)R * sizeof(double)},
-      {(void**)&b.bigsort.count, b.bigsort.ntile ? (size_t)R * (g.ncell + 1) * sizeof(int) : 0},
-      {(void**)&b.bigsort.prov, b.bigsort.ntile ? (size_t)N1 * sizeof(int) : 0},
-      {(void**)&b.bigsort.tsum, b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0},
-      {(void**)&b.bigsort.ctot, b.bigsort.ntile ? (size_t)R * b.bigsort.nchunk * sizeof(int) : 0},
-      {(void**)&b.lat.T, b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0},
-      {(void**)&b.eparts, (size_t)R * b.etiles * sizeof(double)},
-      {(void**)&b.lat.U, b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0},
+      {(void**)&b.scal, P((size_t)R * 4 * sizeof(double))},
+      {(void**)&b.modes, P((size_t)R * K * sizeof(int4))},
+      {(void**)&b.w, P((size_t)R * K * sizeof(double))},
+      {(void**)&b.ion_fx, I(fp32 ? (size_t)N1 * sizeof(uint4) : 0)},
+      {(void**)&b.ion_d4, I(fp32 ? 0 : (size_t)N1 * sizeof(double4))},
+      {(void**)&b.keys, I((size_t)N1 * sizeof(unsigned))},
+      {(void**)&b.perm, I((size_t)N1 * sizeof(int))},
+      {(void**)&b.scell, I((size_t)N1 * sizeof(int))},
+      {(void**)&b.cstart, P((size_t)R * (g.ncell + 1) * sizeof(int))},
+      {(void**)&b.sfx, I(fp32 ? (size_t)(N1 + kScanPad) * sizeof(uint4) : 0)},
+      {(void**)&b.sd4, I(fp32 ? 0 : (size_t)(N1 + kScanPad) * sizeof(double4))},
+      {(void**)&b.part, P((size_t)R * nch * K * sizeof(double2))},
+      {(void**)&b.S1, P((size_t)R * K * sizeof(double2))},
+      {(void**)&b.coef, P((size_t)R * K * sizeof(double2))},
+      {(void**)&b.rec, P(fp32 ? (size_t)R * K * sizeof(ModeRec32) : 0)},
+      {(void**)&b.bN, P((size_t)R * n * sizeof(double))},
+      {(void**)&b.bstar, P(a.b_out ? 0 : (size_t)R * n * sizeof(double))},
+      {(void**)&b.V, P((size_t)R * ldcp(n) * sizeof(double))},
+      {(void**)&b.Qext, P(fixedQ ? 0 : (size_t)b.ksplit * R * (n + 1) * sizeof(double))},
+      {(void**)&b.Qf, P(fp32 ? (size_t)R * n * sizeof(float) : 0)},
+      {(void**)&b.Qsf, P(fp32 ? ((size_t)R * n + kScanPad) * sizeof(float) : 0)},
+      {(void**)&b.Qsd, P(fp32 ? 0 : ((size_t)R * n + kScanPad) * sizeof(double))},
+      {(void**)&b.rsum, P((size_t)R * kRsumStride * sizeof(double))},
+      {(void**)&b.phi, I((size_t)N1 * sizeof(double))},
+      {(void**)&b.Fii, I((size_t)3 * N1 * sizeof(double))},
+      {(void**)&b.Fie, I((size_t)3 * N1 * sizeof(double))},
+      {(void**)&b.energy_out, P(a.energy_out ? 0 : (size_t)R * sizeof(double))},
+      {(void**)&b.bigsort.count, P(b.bigsort.ntile ? (size_t)R * (g.ncell + 1) * sizeof(int) : 0)},
+      {(void**)&b.bigsort.prov, I(big ? (size_t)N1 * sizeof(int) : 0)},
+      {(void**)&b.bigsort.tsum, P(b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0)},
+      {(void**)&b.bigsort.ctot, P(b.bigsort.ntile ? (size_t)R * b.bigsort.nchunk * sizeof(int) : 0)},
+      {(void**)&b.lat.T, P(b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0)},
+      {(void**)&b.eparts, P((size_t)R * b.etiles * sizeof(double))},
+      {(void**)&b.lat.U, P(b.lat.nx && !fixedQ ? (size_t)R * 2 * b.lat.ny * b.lat.nx * sizeof(double2) : 0)},
   };
   size_t total = 0;
   for (const Item& it : items) {
@@ -927,6 +959,339 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
   if (real) HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
   part(PH_ENERGY, s, [&] { launch_final(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());
+  return SRBE_OK;
+}
+
+// ------------------------------------------------------------ batches of systems
+// One batch step runs every system's replicas through the step's phases with one launch
+// per phase (MultiLaunch): the per-ion workspace is shared (ions indexed by their place
+// in the whole batch), each system has its own per-replica workspace, and a table of
+// per-system descriptors (Geom + StepBufs) and per-phase block starts and arguments,
+// built here and uploaded with the step, tells each block what to run.
+struct BatchArgs {
+  int32_t precision, n_rep;
+  const int64_t* off;         // host, n_rep + 1
+  const int32_t* sor;         // host, n_rep: system of each replica (non-decreasing)
+  const double* xyz;
+  const double* q;
+  const double* dpsi;
+  const uint64_t* seed;
+  uint64_t step;
+  const double* Q_in;
+  double* Q_out;
+  double* F_out;
+  double* b_out;
+  double* psibar_out;
+  double* energy_out;
+};
+
+enum {
+  BP_FRONT = 0, BP_BS_ZERO, BP_BS_COUNT, BP_BS_SCAN_CHUNKS, BP_BS_SCAN_TOTALS, BP_BS_SCAN_OFFSETS, BP_BS_SCATTER,
+  BP_BS_RANK, BP_STAGE_IONS, BP_REAL_II, BP_ENERGY_PARTS, BP_FIN1, BP_ELEPOT, BP_CP_GEMM, BP_LAT0, BP_LAT1, BP_LAT2,
+  BP_POST, BP_SF_ELE, BP_FIN2, BP_REAL_IE, BP_ION_FORCE, BP_FINAL, BP_N
+};
+
+struct BatchPlan {
+  struct Sys {
+    srbe_system* h;
+    int r0, R;
+    int64_t max_nrep;
+    StepArgs a;
+    StepBufs b;
+    size_t rep_at;  // its per-replica workspace, bytes from the workspace base
+  };
+  std::vector<Sys> ss;
+  int64_t N = 0;
+  bool fp32 = false, fixedQ = false, any_real = false;
+  size_t ion_bytes = 0, ws_bytes = 0;
+  // table: SysDesc[nsys] | int64 offsets[n_rep + 1] | per phase: start[nsys + 1], iarg[kMultiArgs nsys]
+  size_t desc_at = 0, off_at = 0, tab_bytes = 0;
+  struct Phase {
+    int nblocks = 0;
+    size_t lds = 0;
+    size_t start_at = 0, iarg_at = 0;
+  } ph[BP_N];
+  std::vector<char> tab;
+};
+
+int bset_err(srbe_batch* bt, int code, const std::string& msg) {
+  if (bt) bt->err = msg;
+  return code;
+}
+
+// Checks, grouping and sizes (no device work).  On success p.ws_bytes and p.tab_bytes
+// give the buffers a step needs.
+int batch_plan(srbe_batch* bt, const BatchArgs& a, BatchPlan& p) {
+  const int nsys = (int)bt->sys.size();
+  if (a.precision != SRBE_FP64 && a.precision != SRBE_FP32) return bset_err(bt, SRBE_EINVAL, "unknown precision");
+  if (a.n_rep <= 0 || a.n_rep > 65535 || !a.off || !a.sor)
+    return bset_err(bt, SRBE_EINVAL, "n_rep must be in [1, 65535], offsets and systems given");
+  if (a.off[0] != 0) return bset_err(bt, SRBE_EINVAL, "ion_offsets[0] must be 0");
+  for (int r = 0; r < a.n_rep; ++r) {
+    if (a.off[r + 1] < a.off[r]) return bset_err(bt, SRBE_EINVAL, "ion_offsets must be non-decreasing");
+    if (a.sor[r] < 0 || a.sor[r] >= nsys) return bset_err(bt, SRBE_EINVAL, "system_of_replica out of range");
+    if (r > 0 && a.sor[r] < a.sor[r - 1]) return bset_err(bt, SRBE_EINVAL, "system_of_replica must be non-decreasing");
+  }
+  p.N = a.off[a.n_rep];
+  if (p.N > (int64_t)INT32_MAX - kScanPad) return bset_err(bt, SRBE_EINVAL, "more than 2^31 - 193 ions in one call");
+  if (p.N > 0 && (!a.xyz || !a.q)) return bset_err(bt, SRBE_EINVAL, "ion arrays are NULL");
+  if (!a.dpsi || !a.Q_out || (p.N > 0 && !a.F_out) || !a.psibar_out)
+    return bset_err(bt, SRBE_EINVAL, "dpsi, Q_out, F_out and psibar_out are required");
+  p.fp32 = a.precision == SRBE_FP32;
+  p.fixedQ = a.Q_in != nullptr;
+  p.ss.clear();
+  int64_t qoff = 0;
+  for (int r0 = 0; r0 < a.n_rep;) {
+    const int sid = a.sor[r0];
+    int r1 = r0;
+    while (r1 < a.n_rep && a.sor[r1] == sid) ++r1;
+    srbe_system* h = bt->sys[sid];
+    if (h->p.P > 0 && !a.seed) return bset_err(bt, SRBE_EINVAL, "seed is required");
+    if (!a.Q_in && !h->has_cp) return bset_err(bt, SRBE_EINVAL, "a system built without the CP solve: pass Q_in");
+    BatchPlan::Sys y{};
+    y.h = h;
+    y.r0 = r0;
+    y.R = r1 - r0;
+    y.max_nrep = 0;
+    for (int r = r0; r < r1; ++r) y.max_nrep = std::max<int64_t>(y.max_nrep, a.off[r + 1] - a.off[r]);
+    y.a = StepArgs{a.precision, y.R, a.off + r0, a.xyz, a.q, a.dpsi + r0, a.seed ? a.seed + r0 : nullptr, a.step,
+                   nullptr, a.Q_in ? a.Q_in + qoff : nullptr, a.Q_out + qoff, a.F_out,
+                   a.b_out ? a.b_out + qoff : nullptr, a.psibar_out + r0,
+                   a.energy_out ? a.energy_out + r0 : nullptr, nullptr};
+    fill_bufs(h, y.a, y.max_nrep, y.b);
+    y.b.N = p.N;
+    y.b.R = y.R;
+    if (y.b.real) p.any_real = true;
+    p.ss.push_back(y);
+    qoff += (int64_t)y.R * h->n_ele;
+    r0 = r1;
+  }
+  bool any_big = false;
+  for (auto& y : p.ss) any_big = any_big || y.b.bigsort.ntile != 0;
+  {
+    StepBufs tmp{};
+    p.ion_bytes = align_up(ws_layout(p.ss[0].h, p.ss[0].a, tmp, nullptr, 1, p.N, any_big));
+  }
+  size_t at = p.ion_bytes;
+  for (auto& y : p.ss) {
+    y.rep_at = at;
+    at += align_up(ws_layout(y.h, y.a, y.b, nullptr, 2));
+  }
+  p.ws_bytes = std::max<size_t>(at, 256);
+  // table layout
+  const int ns = (int)p.ss.size();
+  size_t t = 0;
+  p.desc_at = t;
+  t += align_up((size_t)ns * sizeof(SysDesc));
+  p.off_at = t;
+  t += align_up((size_t)(a.n_rep + 1) * sizeof(int64_t));
+  for (int ph = 0; ph < BP_N; ++ph) {
+    p.ph[ph].start_at = t;
+    t += align_up((size_t)(ns + 1) * sizeof(int));
+    p.ph[ph].iarg_at = t;
+    t += align_up((size_t)ns * kMultiArgs * sizeof(int));
+  }
+  p.tab_bytes = t;
+  return SRBE_OK;
+}
+
+// Assigns the workspace (ws) and table (tab, device) addresses and fills the host image
+// of the table.  step_dev: a graph's step counter, or null.
+void batch_fill(BatchPlan& p, const BatchArgs& a, char* ws, char* tab, uint64_t* step_dev) {
+  const int ns = (int)p.ss.size();
+  StepBufs ionb{};
+  bool any_big = false;
+  for (auto& y : p.ss) any_big = any_big || y.b.bigsort.ntile != 0;
+  ws_layout(p.ss[0].h, p.ss[0].a, ionb, ws, 1, p.N, any_big);
+  p.tab.assign(p.tab_bytes, 0);
+  const int64_t* dev_off = (const int64_t*)(tab + p.off_at);
+  std::memcpy(p.tab.data() + p.off_at, a.off, (size_t)(a.n_rep + 1) * sizeof(int64_t));
+  for (int k = 0; k < ns; ++k) {
+    auto& y = p.ss[k];
+    ws_layout(y.h, y.a, y.b, ws + y.rep_at, 2);
+    StepBufs& b = y.b;
+    b.ion_fx = ionb.ion_fx;
+    b.ion_d4 = ionb.ion_d4;
+    b.keys = ionb.keys;
+    b.perm = ionb.perm;
+    b.scell = ionb.scell;
+    b.sfx = ionb.sfx;
+    b.sd4 = ionb.sd4;
+    b.phi = ionb.phi;
+    b.Fii = ionb.Fii;
+    b.Fie = ionb.Fie;
+    b.bigsort.prov = ionb.bigsort.prov;
+    b.off = dev_off + y.r0;
+    b.step_dev = step_dev;
+    b.step_adv = nullptr;
+    SysDesc d{y.h->g, b};
+    std::memcpy(p.tab.data() + p.desc_at + (size_t)k * sizeof(SysDesc), &d, sizeof(SysDesc));
+  }
+  // per phase and system: blocks, arguments and LDS, as the single-system launchers size them
+  for (int ph = 0; ph < BP_N; ++ph) {
+    int* start = (int*)(p.tab.data() + p.ph[ph].start_at);
+    int* iarg = (int*)(p.tab.data() + p.ph[ph].iarg_at);
+    int total = 0;
+    size_t lds = 0;
+    for (int k = 0; k < ns; ++k) {
+      const auto& y = p.ss[k];
+      const Geom& g = y.h->g;
+      const StepBufs& b = y.b;
+      const int R = y.R;
+      int* ia = iarg + (size_t)k * kMultiArgs;
+      int nb = 0;
+      const bool big = b.bigsort.count != nullptr;
+      switch (ph) {
+        case BP_FRONT:
+          ia[0] = R;
+          nb = R + (big ? 0 : R);
+          if (g.P > 0) lds = std::max(lds, sample_lds_bytes(g.P));
+          break;
+        case BP_BS_ZERO: nb = big ? (int)(((int64_t)R * (g.ncell + 1) + 255) / 256) : 0; break;
+        case BP_BS_COUNT:
+        case BP_BS_SCATTER:
+        case BP_BS_RANK: nb = big ? R * b.bigsort.ntile : 0; break;
+        case BP_BS_SCAN_CHUNKS:
+        case BP_BS_SCAN_OFFSETS: nb = big ? R * b.bigsort.nchunk : 0; break;
+        case BP_BS_SCAN_TOTALS: nb = big ? R : 0; break;
+        case BP_STAGE_IONS: {
+          const int nsf = g.K > 0 ? b.ktiles * b.nchunk_ion * R : 0;
+          const int units = b.n_ele_chunks * R;
+          const int nre = (b.real && g.n_ele > 0) ? (units * b.esplit + 3) / 4 : 0;
+          ia[0] = nsf;
+          ia[1] = nre;
+          ia[2] = b.esplit;
+          nb = nsf + nre;
+          break;
+        }
+        case BP_REAL_II: {
+          if (!b.real || b.max_nrep == 0) break;
+          const int tiles = (int)((std::max(b.max_nrep, 1) + 4 * b.ii_ipw - 1) / (4 * b.ii_ipw));
+          ia[0] = tiles;
+          nb = R >= 8 ? 8 * ((R + 7) / 8) * tiles : 8 * ((R * tiles + 7) / 8);
+          break;
+        }
+        case BP_ENERGY_PARTS: nb = (b.real && b.etiles) ? R * b.etiles : 0; break;
+        case BP_FIN1:
+        case BP_FIN2:
+          ia[0] = ph == BP_FIN1 ? 1 : 2;
+          nb = g.K > 0 ? b.ktiles * R : 0;
+          break;
+        case BP_ELEPOT:
+          ia[0] = (g.n_ele + 63) / 64;
+          nb = ia[0] * R;
+          break;
+        case BP_CP_GEMM:
+          if (p.fixedQ || b.lat.nx || !b.Sext) break;
+          ia[0] = (g.n_ele + 1 + 63) / 64;
+          ia[1] = (R + 63) / 64;
+          nb = ia[0] * ia[1] * b.ksplit;
+          break;
+        case BP_LAT0:
+        case BP_LAT1:
+        case BP_LAT2:
+          if (p.fixedQ || !b.lat.nx) break;
+          {
+            size_t l = 0;
+            lattice_grid(b, ph - BP_LAT0, nb, l);
+            lds = std::max(lds, l);
+          }
+          break;
+        case BP_POST:
+          ia[0] = p.fixedQ ? 1 : 0;
+          nb = R * kRsumParts;
+          break;
+        case BP_SF_ELE:
+          ia[0] = g.K > 0 ? b.ktiles * b.nchunk_ele * R : 0;
+          ia[1] = 0;
+          nb = ia[0];
+          break;
+        case BP_REAL_IE:
+          ia[0] = 0;
+          ia[1] = (b.real && b.max_nrep > 0 && b.nreach > 0) ? b.ie_nbx * R : 0;
+          nb = ia[1];
+          break;
+        case BP_ION_FORCE:
+          ia[0] = (std::max(b.max_nrep, 1) + 63) / 64;
+          nb = b.max_nrep > 0 ? ia[0] * R : 0;
+          break;
+        case BP_FINAL: {
+          const int64_t i0 = a.off[y.r0], i1 = a.off[y.r0 + R];
+          ia[0] = R;  // energies (the workspace holds them when energy_out is null)
+          ia[1] = p.fixedQ ? 1 : 0;
+          ia[2] = (int)i0;
+          ia[3] = (int)(i1 - i0);
+          nb = R + (b.real ? (int)((i1 - i0 + 255) / 256) : 0);
+          break;
+        }
+        default: break;
+      }
+      start[k] = total;
+      total += nb;
+    }
+    start[ns] = total;
+    if (ph == BP_FINAL && step_dev && total == 0) {  // a replayed graph's step counter still advances
+      start[ns] = total = 1;
+    }
+    p.ph[ph].nblocks = total;
+    p.ph[ph].lds = lds;
+  }
+}
+
+// The batch step's launches (the order and streams of enqueue_step).
+int enqueue_batch(srbe_batch* bt, const BatchPlan& p, char* tab, uint64_t* step_adv, hipStream_t s) {
+  hipStream_t s1 = bt->aux;
+  const int ns = (int)p.ss.size();
+  const int fp32 = p.fp32 ? 1 : 0;
+  auto ml = [&](int ph) {
+    return MultiLaunch{(const SysDesc*)(tab + p.desc_at), (const int*)(tab + p.ph[ph].start_at),
+                       (const int*)(tab + p.ph[ph].iarg_at), ns, ph == BP_FINAL ? step_adv : nullptr};
+  };
+  auto go = [&](int ph, int mp, hipStream_t st) {
+    launch_multi(mp, fp32, 4, 4, 16, ml(ph), p.ph[ph].nblocks, p.ph[ph].lds, st);
+  };
+#define BHIP(call)                                                                                          \
+  do {                                                                                                      \
+    hipError_t e_ = (call);                                                                                 \
+    if (e_ != hipSuccess) return bset_err(bt, SRBE_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  go(BP_FRONT, MP_FRONT, s);
+  go(BP_BS_ZERO, MP_BS_ZERO, s);
+  go(BP_BS_COUNT, MP_BS_COUNT, s);
+  go(BP_BS_SCAN_CHUNKS, MP_BS_SCAN_CHUNKS, s);
+  go(BP_BS_SCAN_TOTALS, MP_BS_SCAN_TOTALS, s);
+  go(BP_BS_SCAN_OFFSETS, MP_BS_SCAN_OFFSETS, s);
+  go(BP_BS_SCATTER, MP_BS_SCATTER, s);
+  go(BP_BS_RANK, MP_BS_RANK, s);
+  const bool real = p.any_real;
+  if (real) BHIP(hipEventRecord(bt->ev[EV_CS], s));
+  go(BP_STAGE_IONS, MP_STAGE_IONS, s);
+  if (real) {
+    BHIP(hipStreamWaitEvent(s1, bt->ev[EV_CS], 0));
+    go(BP_REAL_II, MP_REAL_II, s1);
+    go(BP_ENERGY_PARTS, MP_ENERGY_PARTS, s1);
+  }
+  go(BP_FIN1, MP_SF_FINALIZE, s);
+  go(BP_ELEPOT, MP_ELEPOT, s);
+  if (!p.fixedQ) {
+    go(BP_CP_GEMM, MP_CP_GEMM, s);
+    for (int k = 0; k < 3; ++k)
+      launch_multi_lattice(k, ml(BP_LAT0 + k), p.ph[BP_LAT0 + k].nblocks, p.ph[BP_LAT0 + k].lds, s);
+  }
+  go(BP_POST, MP_POST_CHARGES, s);
+  if (real) BHIP(hipEventRecord(bt->ev[EV_POST], s));
+  go(BP_SF_ELE, MP_STAGE_ELE, s);
+  go(BP_FIN2, MP_SF_FINALIZE, s);
+  if (real) {
+    BHIP(hipStreamWaitEvent(s1, bt->ev[EV_POST], 0));
+    go(BP_REAL_IE, MP_STAGE_ELE, s1);
+    BHIP(hipEventRecord(bt->ev[EV_AUX], s1));
+  }
+  go(BP_ION_FORCE, MP_ION_FORCE, s);
+  if (real) BHIP(hipStreamWaitEvent(s, bt->ev[EV_AUX], 0));
+  go(BP_FINAL, MP_FINAL, s);
+  BHIP(hipGetLastError());
+#undef BHIP
   return SRBE_OK;
 }
 
@@ -1628,6 +1993,186 @@ int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
     ms_out[1] = best;
   }
   return SRBE_OK;
+}
+
+int srbe_batch_create(srbe_system* const* systems, int32_t n_systems, srbe_batch** out) {
+  if (!out) return SRBE_EINVAL;
+  *out = nullptr;
+  if (!systems || n_systems <= 0 || n_systems > 4096) return SRBE_EINVAL;
+  int dev = -1;
+  for (int k = 0; k < n_systems; ++k) {
+    if (!systems[k]) return SRBE_EINVAL;
+    if (k == 0) dev = systems[k]->device;
+    else if (systems[k]->device != dev) return SRBE_EINVAL;  // one device per batch
+  }
+  srbe_batch* bt = new srbe_batch();
+  bt->sys.assign(systems, systems + n_systems);
+  bt->device = dev;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  bool ok = hipSetDevice(dev) == hipSuccess && hipStreamCreateWithFlags(&bt->aux, hipStreamNonBlocking) == hipSuccess;
+  for (hipEvent_t& e : bt->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  (void)hipSetDevice(prev);
+  if (!ok) {
+    srbe_batch_destroy(bt);
+    return SRBE_EHIP;
+  }
+  *out = bt;
+  return SRBE_OK;
+}
+
+void srbe_batch_destroy(srbe_batch* bt) {
+  if (!bt) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(bt->device);
+  (void)hipDeviceSynchronize();
+  for (hipEvent_t e : bt->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (bt->aux) (void)hipStreamDestroy(bt->aux);
+  if (bt->ws) (void)hipFree(bt->ws);
+  if (bt->tab) (void)hipFree(bt->tab);
+  (void)hipSetDevice(prev);
+  delete bt;
+}
+
+const char* srbe_batch_last_error(const srbe_batch* bt) { return bt ? bt->err.c_str() : "null batch"; }
+
+int srbe_batch_sync_status(srbe_batch* bt) {
+  if (!bt) return SRBE_EINVAL;
+  int worst = SRBE_OK;
+  for (srbe_system* h : bt->sys) {
+    const int rc = srbe_sync_status(h);
+    if (rc != SRBE_OK && worst == SRBE_OK) {
+      worst = rc;
+      bt->err = h->err;
+    }
+  }
+  return worst;
+}
+
+int srbe_batch_step(srbe_batch* bt, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                    const int32_t* system_of_replica, const double* ion_xyz, const double* ion_q, const double* dpsi,
+                    const uint64_t* seed, uint64_t step, const double* Q_in, double* Q_out, double* F_out,
+                    double* b_out, double* psibar_out, double* energy_out, void* stream) {
+  if (!bt) return SRBE_EINVAL;
+  const BatchArgs a{precision, n_rep, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, step,
+                    Q_in, Q_out, F_out, b_out, psibar_out, energy_out};
+  BatchPlan p;
+  int rc = batch_plan(bt, a, p);
+  if (rc != SRBE_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // the table is uploaded below with an asynchronous copy: earlier steps on this batch
+  // must be done with the old one before it is overwritten or freed
+  if (p.ws_bytes > bt->ws_bytes || p.tab_bytes > bt->tab_bytes) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return bset_err(bt, SRBE_EHIP, hipGetErrorString(e));
+  }
+  auto grow = [&](void*& ptr, size_t& cap, size_t need) -> hipError_t {
+    if (need <= cap) return hipSuccess;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    const hipError_t e = hipMalloc(&ptr, need);
+    if (e == hipSuccess) cap = need;
+    return e;
+  };
+  hipError_t e = grow(bt->ws, bt->ws_bytes, p.ws_bytes);
+  if (e == hipSuccess) e = grow(bt->tab, bt->tab_bytes, p.tab_bytes);
+  if (e != hipSuccess) return bset_err(bt, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, hipGetErrorString(e));
+  batch_fill(p, a, (char*)bt->ws, (char*)bt->tab, nullptr);
+  // the previous step may still read the table: order the copy after it on the stream
+  // (pageable host memory: the copy is staged before the call returns)
+  e = hipMemcpyAsync(bt->tab, p.tab.data(), p.tab_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return bset_err(bt, SRBE_EHIP, hipGetErrorString(e));
+  for (auto& y : p.ss) y.h->last_valid = false;
+  return enqueue_batch(bt, p, (char*)bt->tab, nullptr, s);
+}
+
+int srbe_batch_graph_create(srbe_batch* bt, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                            const int32_t* system_of_replica, const double* ion_xyz, const double* ion_q,
+                            const double* dpsi, const uint64_t* seed, uint64_t first_step, const double* Q_in,
+                            double* Q_out, double* F_out, double* b_out, double* psibar_out, double* energy_out,
+                            srbe_batch_graph** out) {
+  if (!bt || !out) return SRBE_EINVAL;
+  *out = nullptr;
+  const BatchArgs a{precision, n_rep, ion_offsets, system_of_replica, ion_xyz, ion_q, dpsi, seed, first_step,
+                    Q_in, Q_out, F_out, b_out, psibar_out, energy_out};
+  BatchPlan p;
+  int rc = batch_plan(bt, a, p);
+  if (rc != SRBE_OK) return rc;
+  srbe_batch_graph* gr = new srbe_batch_graph();
+  gr->bt = bt;
+  auto fail = [&](int code) {
+    srbe_batch_graph_destroy(gr);
+    return code;
+  };
+  hipError_t e = hipMalloc(&gr->ws, p.ws_bytes);
+  if (e == hipSuccess) e = hipMalloc(&gr->tab, p.tab_bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&gr->step_dev, sizeof(uint64_t));
+  if (e == hipSuccess) batch_fill(p, a, (char*)gr->ws, (char*)gr->tab, gr->step_dev);
+  if (e == hipSuccess) e = hipMemcpy(gr->tab, p.tab.data(), p.tab_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(gr->step_dev, &first_step, sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    bset_err(bt, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, hipGetErrorString(e));
+    return fail(e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP);
+  }
+  hipStream_t cap = nullptr;
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) {
+    bset_err(bt, SRBE_EHIP, hipGetErrorString(e));
+    return fail(SRBE_EHIP);
+  }
+  if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    bset_err(bt, SRBE_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    return fail(SRBE_EHIP);
+  }
+  rc = enqueue_batch(bt, p, (char*)gr->tab, gr->step_dev, cap);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cap, &graph);
+  (void)hipStreamDestroy(cap);
+  if (rc != SRBE_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc == SRBE_OK) bset_err(bt, SRBE_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    return fail(rc != SRBE_OK ? rc : SRBE_EHIP);
+  }
+  gr->graph = graph;
+  if ((e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+    bset_err(bt, SRBE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return fail(SRBE_EHIP);
+  }
+  *out = gr;
+  return SRBE_OK;
+}
+
+int srbe_batch_graph_launch(srbe_batch_graph* gr, void* stream) {
+  if (!gr || !gr->exec) return SRBE_EINVAL;
+  const hipError_t e = hipGraphLaunch(gr->exec, (hipStream_t)stream);
+  return e == hipSuccess ? SRBE_OK : bset_err(gr->bt, SRBE_EHIP, hipGetErrorString(e));
+}
+
+int srbe_batch_graph_set_step(srbe_batch_graph* gr, uint64_t step, void* stream) {
+  if (!gr || !gr->step_dev) return SRBE_EINVAL;
+  launch_set_step(gr->step_dev, step, (hipStream_t)stream);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SRBE_OK : bset_err(gr->bt, SRBE_EHIP, hipGetErrorString(e));
+}
+
+void srbe_batch_graph_destroy(srbe_batch_graph* gr) {
+  if (!gr) return;
+  if (gr->bt) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(gr->bt->device);
+    (void)hipDeviceSynchronize();
+    (void)hipSetDevice(prev);
+  }
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  if (gr->ws) (void)hipFree(gr->ws);
+  if (gr->tab) (void)hipFree(gr->tab);
+  if (gr->step_dev) (void)hipFree(gr->step_dev);
+  delete gr;
 }
 
 const char* srbe_phase_name(int32_t phase) {

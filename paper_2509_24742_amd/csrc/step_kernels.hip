@@ -191,10 +191,12 @@ __global__ __launch_bounds__(256) void k_zero_int(int* __restrict__ p, int64_t n
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0;
 }
 
+// Each big-sort launch's body takes its block index lb (a multi-system launch passes the
+// block's index within its system).
 template <int REC>
-__global__ __launch_bounds__(256) void k_bigsort_count(Geom g, SortArgs a, BigSort bs) {
+__device__ __forceinline__ void bigsort_count_body(const Geom& g, const SortArgs& a, const BigSort& bs, int lb) {
   __shared__ double red[4][4];
-  const int r = blockIdx.x / bs.ntile, tile = blockIdx.x - r * bs.ntile;
+  const int r = lb / bs.ntile, tile = lb - r * bs.ntile;
   const int64_t b0 = a.off[r];
   const int n = (int)(a.off[r + 1] - b0);
   const int k = tile * 256 + (int)threadIdx.x;
@@ -209,6 +211,11 @@ __global__ __launch_bounds__(256) void k_bigsort_count(Geom g, SortArgs a, BigSo
     if (threadIdx.x == 0)
       for (int u = 0; u < 4; ++u) bs.tsum[((size_t)r * bs.ntile + tile) * 4 + u] = v[u];
   }
+}
+
+template <int REC>
+__global__ __launch_bounds__(256) void k_bigsort_count(Geom g, SortArgs a, BigSort bs) {
+  bigsort_count_body<REC>(g, a, bs, blockIdx.x);
 }
 
 // Exclusive scan of the cell counts in three launches, so that the counts (just
@@ -236,9 +243,9 @@ __device__ __forceinline__ int block_exclusive_scan_1024(int x, int& total, int*
   return below + incl - x;
 }
 
-__global__ __launch_bounds__(1024) void k_bigsort_scan_chunks(Geom g, SortArgs a, BigSort bs) {
+__device__ __forceinline__ void bigsort_scan_chunks_body(const Geom& g, const SortArgs& a, const BigSort& bs, int lb) {
   __shared__ int wtot[16];
-  const int r = blockIdx.x / bs.nchunk, ch = blockIdx.x - r * bs.nchunk;
+  const int r = lb / bs.nchunk, ch = lb - r * bs.nchunk;
   const int c = ch * 1024 + (int)threadIdx.x;
   const int* cnt = bs.count + (size_t)r * (g.ncell + 1);
   int total;
@@ -247,11 +254,15 @@ __global__ __launch_bounds__(1024) void k_bigsort_scan_chunks(Geom g, SortArgs a
   if (threadIdx.x == 0) bs.ctot[(size_t)r * bs.nchunk + ch] = total;
 }
 
+__global__ __launch_bounds__(1024) void k_bigsort_scan_chunks(Geom g, SortArgs a, BigSort bs) {
+  bigsort_scan_chunks_body(g, a, bs, blockIdx.x);
+}
+
 template <int REC>
-__global__ __launch_bounds__(1024) void k_bigsort_scan_totals(Geom g, SortArgs a, BigSort bs) {
+__device__ __forceinline__ void bigsort_scan_totals_body(const Geom& g, const SortArgs& a, const BigSort& bs, int lb) {
   __shared__ double red[4][16];
   __shared__ int wtot[16];
-  const int r = blockIdx.x, t = threadIdx.x;
+  const int r = lb, t = threadIdx.x;
   if constexpr (REC != 3) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int u = t; u < bs.ntile; u += 1024)
@@ -268,8 +279,13 @@ __global__ __launch_bounds__(1024) void k_bigsort_scan_totals(Geom g, SortArgs a
   if (t < bs.nchunk) ct[t] = excl;
 }
 
-__global__ __launch_bounds__(1024) void k_bigsort_scan_offsets(Geom g, SortArgs a, BigSort bs) {
-  const int r = blockIdx.x / bs.nchunk, ch = blockIdx.x - r * bs.nchunk;
+template <int REC>
+__global__ __launch_bounds__(1024) void k_bigsort_scan_totals(Geom g, SortArgs a, BigSort bs) {
+  bigsort_scan_totals_body<REC>(g, a, bs, blockIdx.x);
+}
+
+__device__ __forceinline__ void bigsort_scan_offsets_body(const Geom& g, const SortArgs& a, const BigSort& bs, int lb) {
+  const int r = lb / bs.nchunk, ch = lb - r * bs.nchunk;
   const int c = ch * 1024 + (int)threadIdx.x;
   if (c > g.ncell) return;
   const size_t at = (size_t)r * (g.ncell + 1) + c;
@@ -278,9 +294,13 @@ __global__ __launch_bounds__(1024) void k_bigsort_scan_offsets(Geom g, SortArgs 
   bs.count[at] = start;  // cursor
 }
 
+__global__ __launch_bounds__(1024) void k_bigsort_scan_offsets(Geom g, SortArgs a, BigSort bs) {
+  bigsort_scan_offsets_body(g, a, bs, blockIdx.x);
+}
+
 template <int REC>
-__global__ __launch_bounds__(256) void k_bigsort_scatter(Geom g, SortArgs a, BigSort bs) {
-  const int r = blockIdx.x / bs.ntile, tile = blockIdx.x - r * bs.ntile;
+__device__ __forceinline__ void bigsort_scatter_body(const Geom& g, const SortArgs& a, const BigSort& bs, int lb) {
+  const int r = lb / bs.ntile, tile = lb - r * bs.ntile;
   const int64_t b0 = a.off[r];
   const int n = (int)(a.off[r + 1] - b0);
   const int k = tile * 256 + (int)threadIdx.x;
@@ -290,8 +310,13 @@ __global__ __launch_bounds__(256) void k_bigsort_scatter(Geom g, SortArgs a, Big
 }
 
 template <int REC>
-__global__ __launch_bounds__(256) void k_bigsort_rank(Geom g, SortArgs a, BigSort bs) {
-  const int r = blockIdx.x / bs.ntile, tile = blockIdx.x - r * bs.ntile;
+__global__ __launch_bounds__(256) void k_bigsort_scatter(Geom g, SortArgs a, BigSort bs) {
+  bigsort_scatter_body<REC>(g, a, bs, blockIdx.x);
+}
+
+template <int REC>
+__device__ __forceinline__ void bigsort_rank_body(const Geom& g, const SortArgs& a, const BigSort& bs, int lb) {
+  const int r = lb / bs.ntile, tile = lb - r * bs.ntile;
   const int64_t b0 = a.off[r];
   const int n = (int)(a.off[r + 1] - b0);
   const int p = tile * 256 + (int)threadIdx.x;
@@ -309,6 +334,11 @@ __global__ __launch_bounds__(256) void k_bigsort_rank(Geom g, SortArgs a, BigSor
   a.scell[b0 + pos] = c;
   if (REC & 1) a.sfx[b0 + pos] = a.fx[i];
   if (REC & 2) a.sd4[b0 + pos] = a.d4[i];
+}
+
+template <int REC>
+__global__ __launch_bounds__(256) void k_bigsort_rank(Geom g, SortArgs a, BigSort bs) {
+  bigsort_rank_body<REC>(g, a, bs, blockIdx.x);
 }
 
 template <int REC>
@@ -563,14 +593,19 @@ size_t sample_lds_bytes(int P) { return (size_t)P * (8 + 8 + 4 + 6) + 16; }
 // [nsamp, nsamp + nsort) make and sort the replicas' particle records (the two are
 // independent; one launch runs them side by side).
 template <int REC>
-__global__ __launch_bounds__(1024) void k_front(Geom g, StepBufs b, SortArgs sa, int nsamp) {
-  if ((int)blockIdx.x < nsamp)
-    sample_block<1024>(g, blockIdx.x, b);
+__device__ __forceinline__ void front_body(const Geom& g, const StepBufs& b, const SortArgs& sa, int nsamp, int lb) {
+  if (lb < nsamp)
+    sample_block<1024>(g, lb, b);
   else
-    sort_block<REC>(g, blockIdx.x - nsamp, sa);
+    sort_block<REC>(g, lb - nsamp, sa);
 }
 
-static SortArgs ion_sort_args(const StepBufs& b) {
+template <int REC>
+__global__ __launch_bounds__(1024) void k_front(Geom g, StepBufs b, SortArgs sa, int nsamp) {
+  front_body<REC>(g, b, sa, nsamp, blockIdx.x);
+}
+
+__host__ __device__ inline SortArgs ion_sort_args(const StepBufs& b) {
   return SortArgs{b.off,  b.ion_xyz, b.ion_q, b.N,    b.keys,  b.ion_fx, b.ion_d4,
                   b.scal, b.perm,    b.scell, b.cstart, b.sfx, b.sd4,    b.status};
 }
@@ -789,6 +824,12 @@ __device__ __forceinline__ void sf_block(const Geom& g, const StepBufs& b, int l
     else
       sf64_block<false>(g, b.off, b.ele_d4, b.Q_out, b.modes, b.part, nchunk, tile, ch, r);
   }
+}
+
+__device__ __forceinline__ void sf_finalize_body(const Geom& g, const StepBufs& b, int stage, int lb) {
+  const int r = lb / b.ktiles, tile = lb - r * b.ktiles;
+  finalize_tile(g, r, tile * 256 + threadIdx.x, b.part, stage == 1 ? b.nchunk_ion : b.nchunk_ele, b.modes, b.w,
+                b.S1, b.coef, b.rec, stage, b.status);
 }
 
 __global__ __launch_bounds__(256) void k_sf_finalize(Geom g, const double2* __restrict__ part, int nchunk,
@@ -1180,9 +1221,9 @@ __device__ __forceinline__ void real_ele_wave(const Geom& g, const StepBufs& bb,
 // blocks.  The real-space waves are latency-bound, so they are dispatched first and
 // the arithmetic-bound partial blocks fill the issue slots they leave.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf, int nre, int esplit) {
+__device__ __forceinline__ void stage_ions_body(const Geom& g, const StepBufs& b, int nsf, int nre, int esplit,
+                                                int bid) {
   __shared__ double part_sums[4 * 64];
-  const int bid = blockIdx.x;
   if (bid < nre) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int units = b.n_ele_chunks * b.R;
@@ -1193,6 +1234,11 @@ __global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf,
   } else {
     sf_block<FP32, true>(g, b, bid - nre);
   }
+}
+
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_stage_ions(Geom g, StepBufs b, int nsf, int nre, int esplit) {
+  stage_ions_body<FP32>(g, b, nsf, nre, esplit, blockIdx.x);
 }
 
 void launch_stage_ions(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
@@ -1264,16 +1310,21 @@ __device__ __forceinline__ void elepot_write(const Geom& g, int r, int j, double
   }
 }
 
+// Block (tile, r): electrodes 64 tile .. 64 tile + 63 of replica r.
 template <int W>
-__global__ __launch_bounds__(64 * W) void k_elepot64(Geom g, const double* __restrict__ ele_xyz,
-                                                  const double4* __restrict__ ele_d4,
-                                                  const double* __restrict__ ele_d, const int4* __restrict__ modes,
-                                                  const double2* __restrict__ coef, const double* __restrict__ scal,
-                                                  const double* __restrict__ dpsi, const double* __restrict__ bN,
-                                                  double* __restrict__ bstar, double* __restrict__ V) {
+__device__ __forceinline__ void elepot64_body(const Geom& g, const StepBufs& b, int tile, int r) {
+  const double* __restrict__ ele_xyz = b.ele_xyz;
+  const double4* __restrict__ ele_d4 = b.ele_d4;
+  const double* __restrict__ ele_d = b.ele_d;
+  const int4* __restrict__ modes = b.modes;
+  const double2* __restrict__ coef = b.coef;
+  const double* __restrict__ scal = b.scal;
+  const double* __restrict__ dpsi = b.dpsi;
+  const double* __restrict__ bN = b.real ? b.bN : nullptr;
+  double* __restrict__ bstar = b.bstar;
+  double* __restrict__ V = b.V;
   __shared__ double sh[W][64];
-  const int r = blockIdx.y;
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = tile * 64 + (threadIdx.x & 63);
   const double4 p = j < g.n_ele ? ele_d4[j] : make_double4(0, 0, 0, 0);
   int lo, hi;
   mode_part<W>(g.K, lo, hi);
@@ -1292,15 +1343,24 @@ __global__ __launch_bounds__(64 * W) void k_elepot64(Geom g, const double* __res
   elepot_write<W>(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
 }
 
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_elepot64(Geom g, StepBufs b) {
+  elepot64_body<W>(g, b, blockIdx.x, blockIdx.y);
+}
+
 template <int W, int U>
-__global__ __launch_bounds__(64 * W) void k_elepot32(Geom g, const uint4* __restrict__ ele_fx,
-                                                  const double* __restrict__ ele_xyz, const double* __restrict__ ele_d,
-                                                  const ModeRec32* __restrict__ rec, const double* __restrict__ scal,
-                                                  const double* __restrict__ dpsi, const double* __restrict__ bN,
-                                                  double* __restrict__ bstar, double* __restrict__ V) {
+__device__ __forceinline__ void elepot32_body(const Geom& g, const StepBufs& b, int tile, int r) {
+  const uint4* __restrict__ ele_fx = b.ele_fx;
+  const double* __restrict__ ele_xyz = b.ele_xyz;
+  const double* __restrict__ ele_d = b.ele_d;
+  const ModeRec32* __restrict__ rec = b.rec;
+  const double* __restrict__ scal = b.scal;
+  const double* __restrict__ dpsi = b.dpsi;
+  const double* __restrict__ bN = b.real ? b.bN : nullptr;
+  double* __restrict__ bstar = b.bstar;
+  double* __restrict__ V = b.V;
   __shared__ double sh[W][64];
-  const int r = blockIdx.y;
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = tile * 64 + (threadIdx.x & 63);
   const uint4 pe = j < g.n_ele ? ele_fx[j] : make_uint4(0, 0, 0, 0);
   int lo, hi;
   mode_part<W>(g.K, lo, hi);
@@ -1332,16 +1392,19 @@ __global__ __launch_bounds__(64 * W) void k_elepot32(Geom g, const uint4* __rest
   elepot_write<W>(g, r, j, acc, sh, ele_xyz, ele_d, scal, dpsi, bN, bstar, V);
 }
 
+template <int W, int U>
+__global__ __launch_bounds__(64 * W) void k_elepot32(Geom g, StepBufs b) {
+  elepot32_body<W, U>(g, b, blockIdx.x, blockIdx.y);
+}
+
 void launch_ele_potential(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   const dim3 grid(cdiv64(g.n_ele, 64), b.R);
   with_wu(b.kw, fp32 ? b.unroll : 4, [&](auto W, auto U) {
     constexpr int w = decltype(W)::value, u = decltype(U)::value;
     if (fp32)
-      hipLaunchKernelGGL((k_elepot32<w, u>), grid, dim3(64 * w), 0, s, g, b.ele_fx, b.ele_xyz, b.ele_d, b.rec, b.scal,
-                         b.dpsi, b.real ? b.bN : nullptr, b.bstar, b.V);
+      hipLaunchKernelGGL((k_elepot32<w, u>), grid, dim3(64 * w), 0, s, g, b);
     else if constexpr (u == 4)  // the FP64 loop has no unroll parameter
-      hipLaunchKernelGGL((k_elepot64<w>), grid, dim3(64 * w), 0, s, g, b.ele_xyz, b.ele_d4, b.ele_d, b.modes, b.coef,
-                         b.scal, b.dpsi, b.real ? b.bN : nullptr, b.bstar, b.V);
+      hipLaunchKernelGGL((k_elepot64<w>), grid, dim3(64 * w), 0, s, g, b);
   });
 }
 
@@ -1506,15 +1569,24 @@ __device__ __forceinline__ double solved_q(const double* __restrict__ Qext, int 
 // Block (r, pc): electrodes [j0, j1) of replica r, at most one per thread; their
 // positions in the cell-sorted order come from the set-up's inverse permutation, so
 // every load is independent of every other.
-__global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __restrict__ Qext, int ksplit,
-                                                      const double* __restrict__ Q_in, const double* __restrict__ ele_xyz,
-                                                      const double* __restrict__ ele_d, const int* __restrict__ ele_iperm,
-                                                      const double* __restrict__ bstar, double* __restrict__ Q_out,
-                                                      float* __restrict__ Qf, float* __restrict__ Qsf,
-                                                      double* __restrict__ Qsd, double* __restrict__ psibar,
-                                                      double* __restrict__ rsum, unsigned* status) {
+__device__ __forceinline__ void post_charges_body(const Geom& g, const StepBufs& b, int fixedQ, int fp32, int r,
+                                                  int pc) {
+  const double* __restrict__ Qext = b.Qext;
+  const int ksplit = b.ksplit;
+  const double* __restrict__ Q_in = fixedQ ? b.Q_in : nullptr;
+  const double* __restrict__ ele_xyz = b.ele_xyz;
+  const double* __restrict__ ele_d = b.ele_d;
+  const int* __restrict__ ele_iperm = b.ele_iperm;
+  const double* __restrict__ bstar = b.bstar;
+  double* __restrict__ Q_out = b.Q_out;
+  float* __restrict__ Qf = fp32 ? b.Qf : nullptr;
+  float* __restrict__ Qsf = fp32 ? b.Qsf : nullptr;
+  double* __restrict__ Qsd = fp32 ? nullptr : b.Qsd;
+  double* __restrict__ psibar = b.psibar_out;
+  double* __restrict__ rsum = b.rsum;
+  unsigned* status = b.status;
   __shared__ double sh[3][4];
-  const int r = blockIdx.x, pc = blockIdx.y, R = gridDim.x;
+  const int R = b.R;
   const int n = g.n_ele;
   const int j0 = (int)((int64_t)n * pc / kRsumParts), j1 = (int)((int64_t)n * (pc + 1) / kRsumParts);
   double v[3] = {0.0, 0.0, 0.0};
@@ -1542,10 +1614,12 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, const double* __re
   }
 }
 
+__global__ __launch_bounds__(256) void k_post_charges(Geom g, StepBufs b, int fixedQ, int fp32) {
+  post_charges_body(g, b, fixedQ, fp32, blockIdx.x, blockIdx.y);
+}
+
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s) {
-  hipLaunchKernelGGL(k_post_charges, dim3(b.R, kRsumParts), dim3(256), 0, s, g, b.Qext, b.ksplit, fixedQ ? b.Q_in : nullptr, b.ele_xyz,
-                     b.ele_d, b.ele_iperm, b.bstar, b.Q_out, fp32 ? b.Qf : nullptr, fp32 ? b.Qsf : nullptr,
-                     fp32 ? nullptr : b.Qsd, b.psibar_out, b.rsum, b.status);
+  hipLaunchKernelGGL(k_post_charges, dim3(b.R, kRsumParts), dim3(256), 0, s, g, b, fixedQ, fp32);
 }
 
 // ============================================================ ion forces, reciprocal part
@@ -1857,9 +1931,9 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
 // (plus the stencil's reach) rather than of the whole system.  A wave's work depends
 // only on (r, bx), so the mapping does not change results.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) {
+__device__ __forceinline__ void real_ii_body(const Geom& g, const StepBufs& b, int tiles, int L) {
   __shared__ __align__(16) unsigned char lds[ring_bytes<FP32>()];
-  const int L = blockIdx.x, j = L >> 3;
+  const int j = L >> 3;
   int r, bx;
   if (b.R >= 8) {
     const int m = j / tiles;
@@ -1876,19 +1950,26 @@ __global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) 
   real_ii_block<FP32>(g, b, bx, r, lds);
 }
 
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) {
+  real_ii_body<FP32>(g, b, tiles, blockIdx.x);
+}
+
 static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * b.ii_ipw); }
 
 // Partial sums of q_i phi_i over tiles of kEnergyTile ions of each replica (large
 // replicas), so the energy's ion sum is spread over many CUs: block (r, t).
-__global__ __launch_bounds__(256) void k_energy_partials(StepBufs b) {
+__device__ __forceinline__ void energy_partials_body(const StepBufs& b, int lb) {
   __shared__ double sh[1][4];
-  const int r = blockIdx.x / b.etiles, t = blockIdx.x - r * b.etiles;
+  const int r = lb / b.etiles, t = lb - r * b.etiles;
   const int64_t i0 = b.off[r] + (int64_t)t * kEnergyTile, i1 = min(b.off[r + 1], i0 + kEnergyTile);
   double v[1] = {0.0};
   for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) v[0] += b.ion_q[i] * b.phi[i];
   block_sum<256, 1>(v, sh);
   if (threadIdx.x == 0) b.eparts[(size_t)r * b.etiles + t] = v[0];
 }
+
+__global__ __launch_bounds__(256) void k_energy_partials(StepBufs b) { energy_partials_body(b, blockIdx.x); }
 
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
@@ -2094,21 +2175,29 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
 // the grid: being latency-bound they start their chains at once, and the
 // arithmetic-bound blocks fill the issue slots they leave.
 template <bool FP32>
-__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie) {
-  const int bid = blockIdx.x;
+__device__ __forceinline__ void stage_ele_body(const Geom& g, const StepBufs& b, int nsf, int nie, int bid) {
   if (bid < nie)
     real_ie_block<FP32>(g, b, bid % b.ie_nbx, b.ie_nbx, bid / b.ie_nbx);
   else
     sf_block<FP32, false>(g, b, bid - nie);
 }
 
+template <bool FP32>
+__global__ __launch_bounds__(256) void k_stage_ele(Geom g, StepBufs b, int nsf, int nie) {
+  stage_ele_body<FP32>(g, b, nsf, nie, blockIdx.x);
+}
+
 template <bool FP32, int W, int U>
-__global__ __launch_bounds__(64 * W) void k_ion_force(Geom g, StepBufs b, int ftiles) {
-  const int u = blockIdx.x;
+__device__ __forceinline__ void ion_force_body(const Geom& g, const StepBufs& b, int ftiles, int u) {
   if constexpr (FP32)
     ionforce32_block<W, U>(g, b, u % ftiles, u / ftiles);
   else
     ionforce64_block<W>(g, b, u % ftiles, u / ftiles);
+}
+
+template <bool FP32, int W, int U>
+__global__ __launch_bounds__(64 * W) void k_ion_force(Geom g, StepBufs b, int ftiles) {
+  ion_force_body<FP32, W, U>(g, b, ftiles, blockIdx.x);
 }
 
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s) {
@@ -2196,14 +2285,17 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
 // blocks [ne, ne + nf) add the real-space sums to the forces,
 //   F_i += ke q_i (Fii_i + Fie_i)   (Fie only for ions of reach cells),
 // and block 0 advances a replayed graph's step counter.
-__global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int fixedQ) {
-  if (b.step_adv && blockIdx.x == 0 && threadIdx.x == 0) *b.step_adv += 1;
-  if ((int)blockIdx.x < ne) {
-    energy_block(g, blockIdx.x, b, fixedQ);
+// (a multi-system launch passes the index of the ion's first entry, ion0, of the system,
+// whose ions are [ion0, ion0 + nion); a single system has ion0 = 0 and nion = N)
+__device__ __forceinline__ void final_body(const Geom& g, const StepBufs& b, int ne, int fixedQ, int64_t ion0,
+                                           int64_t nion, int lb) {
+  if ((int)lb < ne) {
+    energy_block(g, lb, b, fixedQ);
     return;
   }
   const int64_t N = b.N;
-  const int64_t i = (int64_t)(blockIdx.x - ne) * 256 + threadIdx.x;
+  const int64_t i = ion0 + (int64_t)(lb - ne) * 256 + threadIdx.x;
+  if (i >= ion0 + nion) return;
   if (!b.real || i >= N) return;
   const double kq = g.ke * b.ion_q[i];
   double rx = b.Fii[i], ry = b.Fii[N + i], rz = b.Fii[2 * N + i];
@@ -2222,6 +2314,133 @@ __global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int f
   F[i] += kq * rx;
   F[N + i] += kq * ry;
   F[2 * N + i] += kq * rz;
+}
+
+__global__ __launch_bounds__(256) void k_final(Geom g, StepBufs b, int ne, int fixedQ) {
+  if (b.step_adv && blockIdx.x == 0 && threadIdx.x == 0) *b.step_adv += 1;
+  final_body(g, b, ne, fixedQ, 0, b.N, blockIdx.x);
+}
+
+// ============================================================ multi-system launches
+// One launch per phase for every system of a batch (MultiLaunch in kernels.h): each block
+// finds its system, then runs that system's block of the phase with the system's Geom
+// and StepBufs (read from the descriptor table) exactly as the single-system kernel would.
+template <int PH, int V1, int W>
+constexpr int multi_threads() {
+  return (PH == MP_FRONT || PH == MP_BS_SCAN_CHUNKS || PH == MP_BS_SCAN_TOTALS || PH == MP_BS_SCAN_OFFSETS) ? 1024
+         : (PH == MP_ELEPOT || PH == MP_ION_FORCE)                                                         ? 64 * W
+                                                                                                           : 256;
+}
+
+// PH: the phase; V1: FP32 (1) or FP64 (0) path (the front and sort phases: record kind
+// REC = 1 or 2); W, U: waves and unroll of the potential and force passes; KB: GEMM block.
+template <int PH, int V1, int W, int U, int KB>
+__global__ __launch_bounds__((multi_threads<PH, V1, W>())) void k_multi(MultiLaunch m) {
+  const int s = multi_system(m, blockIdx.x), lb = blockIdx.x - m.start[s];
+  const Geom& g = m.d[s].g;
+  const StepBufs& b = m.d[s].b;
+  const int* ia = m.iarg + (size_t)kMultiArgs * s;
+  constexpr bool FP32 = V1 == 1;
+  if constexpr (PH == MP_FRONT) {
+    front_body<V1>(g, b, ion_sort_args(b), ia[0], lb);
+  } else if constexpr (PH == MP_BS_ZERO) {
+    const int64_t i = (int64_t)lb * 256 + threadIdx.x;
+    if (i < (int64_t)b.R * (g.ncell + 1)) b.bigsort.count[i] = 0;
+  } else if constexpr (PH == MP_BS_COUNT) {
+    bigsort_count_body<V1>(g, ion_sort_args(b), b.bigsort, lb);
+  } else if constexpr (PH == MP_BS_SCAN_CHUNKS) {
+    bigsort_scan_chunks_body(g, ion_sort_args(b), b.bigsort, lb);
+  } else if constexpr (PH == MP_BS_SCAN_TOTALS) {
+    bigsort_scan_totals_body<V1>(g, ion_sort_args(b), b.bigsort, lb);
+  } else if constexpr (PH == MP_BS_SCAN_OFFSETS) {
+    bigsort_scan_offsets_body(g, ion_sort_args(b), b.bigsort, lb);
+  } else if constexpr (PH == MP_BS_SCATTER) {
+    bigsort_scatter_body<V1>(g, ion_sort_args(b), b.bigsort, lb);
+  } else if constexpr (PH == MP_BS_RANK) {
+    bigsort_rank_body<V1>(g, ion_sort_args(b), b.bigsort, lb);
+  } else if constexpr (PH == MP_STAGE_IONS) {
+    stage_ions_body<FP32>(g, b, ia[0], ia[1], ia[2], lb);
+  } else if constexpr (PH == MP_SF_FINALIZE) {
+    sf_finalize_body(g, b, ia[0], lb);
+  } else if constexpr (PH == MP_ELEPOT) {
+    if constexpr (FP32)
+      elepot32_body<W, U>(g, b, lb % ia[0], lb / ia[0]);
+    else
+      elepot64_body<W>(g, b, lb % ia[0], lb / ia[0]);
+  } else if constexpr (PH == MP_CP_GEMM) {
+    __shared__ __align__(16) unsigned char lds[gemm_lds_bytes<KB>()];
+    cp_gemm_tile<KB>(g.n_ele, b.R, b.Sext, b.V, b.Qext, lb % ia[0], (lb / ia[0]) % ia[1], lb / (ia[0] * ia[1]),
+                     b.ksplit, lds);
+  } else if constexpr (PH == MP_POST_CHARGES) {
+    post_charges_body(g, b, ia[0], V1, lb % b.R, lb / b.R);
+  } else if constexpr (PH == MP_STAGE_ELE) {
+    stage_ele_body<FP32>(g, b, ia[0], ia[1], lb);
+  } else if constexpr (PH == MP_ION_FORCE) {
+    ion_force_body<FP32, W, U>(g, b, ia[0], lb);
+  } else if constexpr (PH == MP_REAL_II) {
+    real_ii_body<FP32>(g, b, ia[0], lb);
+  } else if constexpr (PH == MP_ENERGY_PARTS) {
+    energy_partials_body(b, lb);
+  } else if constexpr (PH == MP_FINAL) {
+    if (m.step_adv && blockIdx.x == 0 && threadIdx.x == 0) *m.step_adv += 1;
+    final_body(g, b, ia[0], ia[1], ia[2], ia[3], lb);
+  }
+}
+
+template <int PH, int V1, int W, int U, int KB>
+static void multi_go(const MultiLaunch& m, int nblocks, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_multi<PH, V1, W, U, KB>), dim3(nblocks), dim3(multi_threads<PH, V1, W>()), lds, s, m);
+}
+
+// phases whose kernel depends only on the path: v = 1 is the FP32 path (record kind 1),
+// v = 0 the FP64 path (record kind 2 for the front and sort phases)
+template <int PH>
+static void multi_v(int v, const MultiLaunch& m, int nblocks, size_t lds, hipStream_t s) {
+  constexpr int kFp64 = PH <= MP_BS_RANK ? 2 : 0;
+  if (v == 1)
+    multi_go<PH, 1, 4, 4, 16>(m, nblocks, lds, s);
+  else
+    multi_go<PH, kFp64, 4, 4, 16>(m, nblocks, lds, s);
+}
+
+void launch_multi(int phase, int fp32, int W, int U, int KB, const MultiLaunch& m, int nblocks, size_t lds,
+                  hipStream_t s) {
+  if (nblocks == 0) return;
+  switch (phase) {
+    case MP_FRONT: multi_v<MP_FRONT>(fp32, m, nblocks, lds, s); break;
+    case MP_BS_ZERO: multi_go<MP_BS_ZERO, 1, 4, 4, 16>(m, nblocks, lds, s); break;
+    case MP_BS_COUNT: multi_v<MP_BS_COUNT>(fp32, m, nblocks, lds, s); break;
+    case MP_BS_SCAN_CHUNKS: multi_go<MP_BS_SCAN_CHUNKS, 1, 4, 4, 16>(m, nblocks, lds, s); break;
+    case MP_BS_SCAN_TOTALS: multi_v<MP_BS_SCAN_TOTALS>(fp32, m, nblocks, lds, s); break;
+    case MP_BS_SCAN_OFFSETS: multi_go<MP_BS_SCAN_OFFSETS, 1, 4, 4, 16>(m, nblocks, lds, s); break;
+    case MP_BS_SCATTER: multi_v<MP_BS_SCATTER>(fp32, m, nblocks, lds, s); break;
+    case MP_BS_RANK: multi_v<MP_BS_RANK>(fp32, m, nblocks, lds, s); break;
+    case MP_STAGE_IONS: multi_v<MP_STAGE_IONS>(fp32, m, nblocks, lds, s); break;
+    case MP_SF_FINALIZE: multi_go<MP_SF_FINALIZE, 1, 4, 4, 16>(m, nblocks, lds, s); break;
+    case MP_ELEPOT:
+    case MP_ION_FORCE:
+      with_wu(W, fp32 ? U : 4, [&](auto Wc, auto Uc) {
+        constexpr int w = decltype(Wc)::value, u = decltype(Uc)::value;
+        if (phase == MP_ELEPOT) {
+          if (fp32) multi_go<MP_ELEPOT, 1, w, u, 16>(m, nblocks, lds, s);
+          else if constexpr (u == 4) multi_go<MP_ELEPOT, 0, w, 4, 16>(m, nblocks, lds, s);
+        } else {
+          if (fp32) multi_go<MP_ION_FORCE, 1, w, u, 16>(m, nblocks, lds, s);
+          else if constexpr (u == 4) multi_go<MP_ION_FORCE, 0, w, 4, 16>(m, nblocks, lds, s);
+        }
+      });
+      break;
+    case MP_CP_GEMM:
+      if (KB == 32) multi_go<MP_CP_GEMM, 1, 4, 4, 32>(m, nblocks, lds, s);
+      else multi_go<MP_CP_GEMM, 1, 4, 4, 16>(m, nblocks, lds, s);
+      break;
+    case MP_POST_CHARGES: multi_v<MP_POST_CHARGES>(fp32, m, nblocks, lds, s); break;
+    case MP_STAGE_ELE: multi_v<MP_STAGE_ELE>(fp32, m, nblocks, lds, s); break;
+    case MP_REAL_II: multi_v<MP_REAL_II>(fp32, m, nblocks, lds, s); break;
+    case MP_ENERGY_PARTS: multi_go<MP_ENERGY_PARTS, 1, 4, 4, 16>(m, nblocks, lds, s); break;
+    case MP_FINAL: multi_go<MP_FINAL, 1, 4, 4, 16>(m, nblocks, lds, s); break;
+    default: break;
+  }
 }
 
 void launch_final(const Geom& g, const StepBufs& b, int fixedQ, hipStream_t s) {
