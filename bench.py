@@ -98,13 +98,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error check")
     ap.add_argument("--no-tune", action="store_true",
                     help="time with the default launch parameters")
-    ap.add_argument("--large-slab", type=int, default=0, metavar="P",
-                    help="also time the full-size large slab (917,504 ions, 131,072 electrodes, M=64) with this "
-                         "batch size P (500 or 2000), charges by the lattice solve; reported as large_slab")
-    ap.add_argument("--uneven", action="store_true",
-                    help="also time the uneven batch (32 systems of 2e3-2e5 particles, each its own box, charges "
-                         "by the lattice solve): one step of every system, graph replays in turn; reported as "
-                         "uneven_batch")
+    ap.add_argument("--large-slab", type=int, nargs="*", default=[500, 2000], metavar="P",
+                    help="batch sizes P at which to time the full-size large slab (917,504 ions, 131,072 electrodes, "
+                         "M=64, charges by the lattice solve); reported as large_slab (default: 500 2000)")
+    ap.add_argument("--no-large-slab", action="store_true", help="skip the large slab")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven batch (32 systems of 2e3-2e5 particles, each its own box, charges by the "
+                         "lattice solve), otherwise timed and reported as uneven_batch")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -333,9 +333,9 @@ def main():
         "launch_tuning": tuning,
     }
 
-    if args.large_slab:
+    if args.large_slab and not args.no_large_slab:
         result["large_slab"] = large_slab_bench(args, srbe_amd, stream)
-    if args.uneven:
+    if not args.no_uneven:
         result["uneven_batch"] = uneven_bench(args, srbe_amd, stream)
 
     if not args.no_cpu:
@@ -351,58 +351,127 @@ def main():
     sysm.close()
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _rel_rms(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
 def large_slab_bench(args, srbe_amd, stream):
     """Steps of the full-size large slab (one system; the charge update by the lattice solve,
-    since the dense one would need a 131,072^2 matrix), FP32 and FP64, as graph replays."""
+    since the dense one would need a 131,072^2 matrix), FP32 and FP64, as graph replays, at
+    each batch size P; the FP32 errors against the FP64 oracle: forces and b* at sampled
+    targets of the full size at fixed charges, and charges, energy, forces and b* of the
+    constant-potential step of the same recipe at 1/8 scale (values written by the
+    scripts in tests/golden)."""
+    import json
     import torch
     from paper_2509_24742_amd import workloads as wl
     t0 = time.time()
-    w = wl.large_slab(P=args.large_slab)
+    w = wl.large_slab()
     gen_s = time.time() - t0
-    wp = dict(w["params"], kspace_tol=1e-16)
-    t0 = time.time()
-    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
-    setup_s = time.time() - t0
     dev = torch.device("cuda")
     n_ion, n_ele = len(w["ion_q"]), len(w["ele_side"])
     off = np.array([0, n_ion], dtype=np.int64)
     xyz = torch.tensor(np.ascontiguousarray(w["ion_pos"].T).ravel(), dtype=torch.float64, device=dev)
     q = torch.tensor(w["ion_q"], dtype=torch.float64, device=dev)
     dp = torch.tensor([w["dpsi"]], dtype=torch.float64, device=dev)
-    sd = torch.tensor([81], dtype=torch.int64, device=dev).view(torch.uint64)
     steps = max(5, min(args.steps, 50))
-    out = {"workload": f"large slab: {n_ion} ions, {n_ele} electrode atoms (2x256x256), 30x30x100 nm, "
-                       f"M={wp['M']}, P={wp['P']}, constant potential (lattice charge solve)", "steps": steps,
-           "workload_generation_s": gen_s, "setup_s": setup_s}
-    pairs = (n_ion + n_ele) * (wp["M"] + wp["P"])
-    for name, prec in [("fp32", srbe_amd.SRBE_FP32), ("fp64", srbe_amd.SRBE_FP64)]:
-        gr = sysm.capture(off, xyz, q, dp, sd, 0, precision=prec, want_kset=False)
-        for _ in range(3):
-            gr.launch()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            gr.launch()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        code = srbe_amd.srbe_sync_status(sysm.h)
-        if code != 0:
-            raise RuntimeError(srbe_amd.srbe_last_error(sysm.h))
-        gr.close()
-        ms = e0.elapsed_time(e1) / steps
-        out[name] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "steps_per_s": 1e3 / ms}
-        log(f"large slab {name}: {ms:.3f} ms/step")
-    out["pairs_per_step"] = pairs
-    sysm.close()
+    out = {"workload": f"large slab: {n_ion} ions, {n_ele} electrode atoms (2x256x256), 30x30x100 nm, M=64, "
+                       f"constant potential (lattice charge solve)", "steps": steps, "workload_generation_s": gen_s}
+    rs = np.random.default_rng(9)
+    Qfix = w["ele_side"] * 0.004 + 0.001 * rs.normal(size=n_ele)  # the goldens' fixed charges (seed 9)
+    for P in args.large_slab:
+        wp = dict(w["params"], kspace_tol=1e-16, P=int(P))
+        t0 = time.time()
+        sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
+        res = {"setup_s": time.time() - t0}
+        sd = torch.tensor([81], dtype=torch.int64, device=dev).view(torch.uint64)
+        pairs = (n_ion + n_ele) * (wp["M"] + wp["P"])
+        for name, prec in [("fp32", srbe_amd.SRBE_FP32), ("fp64", srbe_amd.SRBE_FP64)]:
+            gr = sysm.capture(off, xyz, q, dp, sd, 0, precision=prec, want_kset=False)
+            for _ in range(3):
+                gr.launch()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                gr.launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            code = srbe_amd.srbe_sync_status(sysm.h)
+            if code != 0:
+                raise RuntimeError(srbe_amd.srbe_last_error(sysm.h))
+            gr.close()
+            ms = e0.elapsed_time(e1) / steps
+            res[name] = {"ms_per_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "steps_per_s": 1e3 / ms}
+            log(f"large slab P={P} {name}: {ms:.3f} ms/step")
+        sysm.close()
+        res["pairs_per_step"] = pairs
+        # FP32 error at the full size: fixed charges, sampled targets
+        gname = "large_slab_sample.json" if P == 500 else f"large_slab_sample_P{P}.json"
+        gpath = os.path.join(GOLDEN, gname)
+        if os.path.exists(gpath):
+            with open(gpath) as f:
+                ref = json.load(f)
+            fixed = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
+            sdg = torch.tensor([ref["seed"]], dtype=torch.int64, device=dev).view(torch.uint64)
+            o = fixed.step(off, xyz, q, dp, sdg, ref["step"], precision=srbe_amd.SRBE_FP32,
+                           Q_in=torch.tensor(Qfix, dtype=torch.float64, device=dev), want_kset=False)
+            torch.cuda.synchronize()
+            ii, ie = np.asarray(ref["ion_index"]), np.asarray(ref["ele_index"])
+            F = o["F"].cpu().numpy().reshape(3, n_ion)[:, ii].T
+            b = o["b"].cpu().numpy()[ie]
+            res["fp32_error_vs_fp64_oracle_full_size"] = {
+                "force_rel_rms": _rel_rms(F, ref["F"]), "b_rel_rms": _rel_rms(b, ref["b"]),
+                "targets": f"{len(ii)} ions, {len(ie)} electrodes (fixed charges; {gname})"}
+            fixed.close()
+        out[f"P{P}"] = res
+    # FP32 errors at 1/8 scale, constant potential, every quantity
+    mpath = os.path.join(GOLDEN, "large_slab_mid.json")
+    if os.path.exists(mpath):
+        with open(mpath) as f:
+            mref = json.load(f)
+        sz = mref["size"]
+        for P in args.large_slab:
+            if str(P) not in mref:
+                continue
+            wm = wl.large_slab(P=int(P), **sz)
+            wpm = dict(wm["params"], kspace_tol=1e-16)
+            sm = srbe_amd.System(wpm, wm["ele_pos"], wm["ele_side"], flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
+            nm = len(wm["ion_q"])
+            offm = np.array([0, nm], dtype=np.int64)
+            xm = torch.tensor(np.ascontiguousarray(wm["ion_pos"].T).ravel(), dtype=torch.float64, device=dev)
+            qm = torch.tensor(wm["ion_q"], dtype=torch.float64, device=dev)
+            sdm = torch.tensor([mref["seed"]], dtype=torch.int64, device=dev).view(torch.uint64)
+            o = sm.step(offm, xm, qm, dp, sdm, mref["step"], precision=srbe_amd.SRBE_FP32, want_kset=False)
+            torch.cuda.synchronize()
+            r = mref[str(P)]
+            ii, ie = np.asarray(mref["ion_index"]), np.asarray(mref["ele_index"])
+            Q = o["Q"].cpu().numpy()
+            out[f"P{P}"]["fp32_error_vs_fp64_oracle_eighth_scale"] = {
+                "charge_rel_rms": _rel_rms(Q, r["Q"]), "energy_rel": abs(float(o["E"][0]) - r["E"]) / abs(r["E"]),
+                "force_rel_rms": _rel_rms(o["F"].cpu().numpy().reshape(3, nm)[:, ii].T, r["F"]),
+                "b_rel_rms": _rel_rms(o["b"].cpu().numpy()[ie], r["b"]),
+                "psibar_abs": abs(float(o["psibar"][0]) - r["psibar"]),
+                "system": f"{nm} ions, {len(wm['ele_side'])} electrode atoms (2x32x32), 3.75x3.75x12.5 nm, "
+                          f"constant potential; oracle's dense solve (large_slab_mid.json)"}
+            sm.close()
     return out
 
 
 def uneven_bench(args, srbe_amd, stream):
-    """One step of each of the 32 uneven-batch systems (each its own handle and box, the
-    lattice charge solve), captured per system and replayed in turn, FP32 and FP64."""
+    """One step of each of the 32 uneven-batch systems (each its own box and handle, the
+    lattice charge solve), FP32 and FP64: all systems in one batch step with one launch per
+    phase (srbe_batch, captured), and beside it the systems' own captured steps spread over
+    streams.  FP32 errors against the FP64 oracle: the three smallest systems in full (the
+    oracle's dense solve, computed here), the largest at sampled targets (fixed charges;
+    tests/golden/uneven_largest.json)."""
+    import json
     import torch
+    from paper_2509_24742_amd import binding
     from paper_2509_24742_amd import workloads as wl
     t0 = time.time()
     systems = wl.uneven_batch()
@@ -428,31 +497,73 @@ def uneven_bench(args, srbe_amd, stream):
                        f"(2e3-2e5 each, log-uniform), aspect 3-12, P = round(100 sqrt(N/1e4)), M = ceil(aspect), "
                        f"constant potential (lattice charge solve)", "systems": len(items), "steps": steps,
            "pairs_per_batch_step": pairs, "workload_generation_s": gen_s, "setup_s": setup_s}
-    # the systems' graphs go to S streams (default priority), largest first, each to the
-    # stream with the least work so far; the batch step ends when every stream has
+    # the whole batch as one input set (CSR over the systems, one replica each)
+    sizes = [len(w["ion_q"]) for w in systems]
+    boff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    sor = np.arange(len(systems), dtype=np.int32)
+    bxyz = torch.tensor(np.ascontiguousarray(np.concatenate([w["ion_pos"] for w in systems]).T).ravel(),
+                        dtype=torch.float64, device=dev)
+    bq = torch.tensor(np.concatenate([w["ion_q"] for w in systems]), dtype=torch.float64, device=dev)
+    bdp = torch.tensor([w["dpsi"] for w in systems], dtype=torch.float64, device=dev)
+    bsd = torch.tensor(4100 + np.arange(len(systems)), dtype=torch.int64, device=dev).view(torch.uint64)
+    n_eles = [len(w["ele_side"]) for w in systems]
+    nq, N = int(sum(n_eles)), int(boff[-1])
+    bt = binding.srbe_batch_create([it["sys"].h for it in items])
+
+    def timed_replays(launch):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    # the systems' own graphs go to S streams (default priority), largest first, each to
+    # the stream with the least work so far; the batch step ends when every stream has
     order = sorted(range(len(items)), key=lambda k: -items[k]["pairs"])
+    bout = None
     for name, prec in [("fp32", srbe_amd.SRBE_FP32), ("fp64", srbe_amd.SRBE_FP64)]:
+        o = dict(Q=torch.empty(nq, dtype=torch.float64, device=dev),
+                 F=torch.empty(3 * N, dtype=torch.float64, device=dev),
+                 psibar=torch.empty(len(systems), dtype=torch.float64, device=dev),
+                 E=torch.empty(len(systems), dtype=torch.float64, device=dev))
+        bg = binding.srbe_batch_graph_create(bt, prec, boff, sor, bxyz, bq, bdp, bsd, 0, o["Q"], o["F"], o["psibar"],
+                                             energy_out=o["E"])
+        for _ in range(2):
+            binding.srbe_batch_graph_launch(bg)
+        torch.cuda.synchronize()
+        ms_batch = timed_replays(lambda: binding.srbe_batch_graph_launch(bg))
+        if binding.srbe_batch_sync_status(bt) != 0:
+            raise RuntimeError(binding.srbe_batch_last_error(bt))
+        binding.srbe_batch_graph_destroy(bg)
+        log(f"uneven batch {name}: {ms_batch:.3f} ms per step of all systems (one launch per phase)")
         graphs = [it["sys"].capture(it["off"], it["xyz"], it["q"], it["dp"], it["sd"], 0, precision=prec,
                                     want_kset=False) for it in items]
         for gr in graphs:
             gr.launch()
         torch.cuda.synchronize()
         res = {}
-        for S in (1, 2, 4, 8):
+        for S in (1, 4):
             side = [torch.cuda.Stream() for _ in range(S)]
             load, plan = [0] * S, []
             for k in order:
                 j = min(range(S), key=lambda u: load[u])
                 load[j] += items[k]["pairs"]
                 plan.append((k, j))
+
+            def launch_all():
+                for k, j in plan:
+                    graphs[k].launch(side[j])
+
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for st in side:
                 st.wait_event(e0)
             for _ in range(steps):
-                for k, j in plan:
-                    graphs[k].launch(side[j])
+                launch_all()
             for st in side:
                 stream.wait_stream(st)
             e1.record(stream)
@@ -464,11 +575,53 @@ def uneven_bench(args, srbe_amd, stream):
                 raise RuntimeError(srbe_amd.srbe_last_error(it["sys"].h))
         for gr in graphs:
             gr.close()
-        S = min(res, key=res.get)
-        ms = res[S]
-        out[name] = {"ms_per_batch_step": ms, "pairs_per_s": pairs / (ms * 1e-3), "streams": S,
-                     "ms_by_streams": {str(k): round(v, 4) for k, v in res.items()}}
-        log(f"uneven batch {name}: {ms:.3f} ms per step of all systems ({S} streams; by streams {res})")
+        out[name] = {"ms_per_batch_step": ms_batch, "pairs_per_s": pairs / (ms_batch * 1e-3),
+                     "schedule": "one batch step: one launch per phase for all 32 systems (captured)",
+                     "per_system_graphs_ms_by_streams": {str(k): round(v, 4) for k, v in res.items()}}
+        log(f"uneven batch {name}: per-system graphs over streams {res}")
+        if name == "fp32":
+            bout = {k: v.cpu().numpy() for k, v in o.items()}
+    binding.srbe_batch_destroy(bt)
+    # FP32 errors: the three smallest systems in full against the oracle's dense solve
+    from oracle import cp, ewald, sampler, srbe
+    errs = {}
+    qoff = np.concatenate([[0], np.cumsum(n_eles)])
+    F32 = bout["F"].reshape(3, N)
+    for k in sorted(range(len(systems)), key=lambda u: systems[u]["n_total"])[:3]:
+        w = systems[k]
+        wp = w["params"]
+        p = ewald.Params(Lx=wp["Lx"], Ly=wp["Ly"], H=wp["H"], lam=wp["lam"], alpha=wp["alpha"], eta=wp["eta"],
+                         rc=wp["rc"], coulomb_k=wp["coulomb_k"], M=int(wp["M"]), P=int(wp["P"]), kspace_tol=1e-16)
+        ks, _ = sampler.draw_kset(p, 4100 + k, 0, 0)
+        ref = srbe.srbe_step(p, cp.Solver(ewald.electrode_matrix(p, w["ele_pos"])), ks, w["ion_pos"], w["ion_q"],
+                             w["ele_pos"], w["ele_side"], w["dpsi"])
+        errs[f"system_{k}_{w['n_total']}_particles"] = {
+            "force_rel_rms": _rel_rms(F32[:, boff[k]:boff[k + 1]].T, ref["F"]),
+            "charge_rel_rms": _rel_rms(bout["Q"][qoff[k]:qoff[k + 1]], ref["Q"]),
+            "energy_rel": abs(float(bout["E"][k]) - ref["E"]) / abs(ref["E"])}
+    gpath = os.path.join(GOLDEN, "uneven_largest.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            ref = json.load(f)
+        k = ref["system"]
+        it = items[k]
+        w = systems[k]
+        rs = np.random.default_rng(9)
+        Qfix = w["ele_side"] * 0.004 + 0.001 * rs.normal(size=len(w["ele_side"]))
+        fixed = srbe_amd.System(dict(w["params"], kspace_tol=1e-16), w["ele_pos"], w["ele_side"],
+                                flags=srbe_amd.SRBE_FLAG_NO_CP)
+        sdg = torch.tensor([ref["seed"]], dtype=torch.int64, device=dev).view(torch.uint64)
+        o = fixed.step(it["off"], it["xyz"], it["q"], it["dp"], sdg, ref["step"], precision=srbe_amd.SRBE_FP32,
+                       Q_in=torch.tensor(Qfix, dtype=torch.float64, device=dev), want_kset=False)
+        torch.cuda.synchronize()
+        nk = len(w["ion_q"])
+        F = o["F"].cpu().numpy().reshape(3, nk)[:, ref["ion_index"]].T
+        errs[f"system_{k}_{w['n_total']}_particles_sampled"] = {
+            "force_rel_rms": _rel_rms(F, ref["F"]),
+            "b_rel_rms": _rel_rms(o["b"].cpu().numpy()[ref["ele_index"]], ref["b"]),
+            "targets": "64 ions, 64 electrodes, fixed charges (uneven_largest.json)"}
+        fixed.close()
+    out["fp32_error_vs_fp64_oracle"] = errs
     for it in items:
         it["sys"].close()
     return out

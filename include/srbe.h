@@ -286,6 +286,60 @@ int srbe_langevin_update(int64_t n, double* xyz, double* vel, const double* F, c
                          uint64_t step, void* stream);
 
 /*
+ * Dynamics.  The paper's coarse-grained force field is not given; srbe_ff is a stand-in
+ * that keeps ions apart, between the walls and in their molecules so that SRBE-driven
+ * Langevin dynamics (Sec. 3) can run (charging curves):
+ *   - WCA between sites of different molecules: 4 eps [(s/r)^12 - (s/r)^6] + eps for
+ *     r < 2^(1/6) s (which must not exceed rc);
+ *   - 9-3 walls at z = wall_zlo (acting upward) and z = wall_zhi (downward):
+ *     eps_w [(2/15)(s_w/d)^9 - (s_w/d)^3], cut and shifted at its minimum d = (2/5)^(1/6) s_w;
+ *   - harmonic bonds (bond_k / 2)(r - r0)^2 between listed sites.
+ */
+typedef struct srbe_ff {
+  double wca_eps, wca_sigma;   /* energy, length                          */
+  double wall_eps, wall_sigma; /* energy, length                          */
+  double wall_zlo, wall_zhi;   /* wall planes                             */
+  double bond_k;               /* energy / length^2                       */
+} srbe_ff;
+
+/*
+ * srbe_ff_forces -- adds the force field's forces to F (device 3N SoA, e.g. F_out of the
+ * step) for the ions of the last srbe_step on this handle (eager, same n_rep; its inputs
+ * still valid and unchanged), over that step's cell lists.  mol: device N int32, molecule
+ * of each ion (no WCA within a molecule); bond: device 2N int32, up to two bonded partner
+ * ions per ion (global ion index, -1 for none; list each bond at both ends); bond_r0:
+ * device 2N doubles, their rest lengths.  e_ion: device N doubles or NULL, each ion's
+ * energy (half of its pair and bond terms, all of its wall terms).  FP64, deterministic.
+ * Errors: SRBE_EINVAL (no preceding step, other n_rep, NULL arrays, WCA range above rc).
+ */
+int srbe_ff_forces(srbe_system* h, int32_t n_rep, const srbe_ff* ff, const int32_t* mol, const int32_t* bond,
+                   const double* bond_r0, double* F, double* e_ion, void* stream);
+
+/*
+ * srbe_md_graph_create -- one step of SRBE-driven Langevin dynamics captured as a graph
+ * (replayed with srbe_graph_launch, its step counter reset by srbe_graph_set_step,
+ * destroyed with srbe_graph_destroy): the SRBE step of srbe_graph_create (sampling with
+ * the counter's step, b*, the charge solve, the forces of Eq. (25) and real space) into
+ * Q_out, F_out, psibar_out, energy_out; then F_out += the force field's forces
+ * (srbe_ff_forces); then the Euler-Maruyama update of srbe_langevin_update of ion_xyz and
+ * vel in place with the counter's step (noise key md->noise_seed).  Each replay advances
+ * the dynamics by dt; F_out and Q_out hold the forces and charges at the positions before
+ * the update.  Arguments as for srbe_graph_create, srbe_ff_forces and srbe_langevin_update
+ * (mass: device N doubles).  Errors: as those calls.
+ */
+typedef struct srbe_md {
+  srbe_ff ff;
+  double gamma, beta, dt; /* Langevin friction, inverse temperature, time step        */
+  double zlo, zhi;        /* reflecting bounds of z (a safety net behind the walls)   */
+  uint64_t noise_seed;
+} srbe_md;
+int srbe_md_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                         double* ion_xyz, double* vel, const double* ion_q, const double* mass, const int32_t* mol,
+                         const int32_t* bond, const double* bond_r0, const double* dpsi, const uint64_t* seed,
+                         uint64_t first_step, const srbe_md* md, double* Q_out, double* F_out, double* psibar_out,
+                         double* energy_out, srbe_graph** out);
+
+/*
  * srbe_sample -- only the sampler of a step (Sec. 3, Eqs. (26)-(29)): writes the
  * n_rep*P*3 int32 modes the step with the same (seed, step) would use.
  * seed device n_rep uint64; kset_out device.  Returns SRBE_EINVAL on bad arguments.

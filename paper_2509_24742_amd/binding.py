@@ -36,6 +36,16 @@ class srbe_params(ctypes.Structure):
     ]
 
 
+class srbe_ff(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("wca_eps", "wca_sigma", "wall_eps", "wall_sigma", "wall_zlo",
+                                                "wall_zhi", "bond_k")]
+
+
+class srbe_md(ctypes.Structure):
+    _fields_ = [("ff", srbe_ff), ("gamma", ctypes.c_double), ("beta", ctypes.c_double), ("dt", ctypes.c_double),
+                ("zlo", ctypes.c_double), ("zhi", ctypes.c_double), ("noise_seed", ctypes.c_uint64)]
+
+
 class SrbeError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"SRBE error {code}: {msg}")
@@ -45,6 +55,10 @@ class SrbeError(RuntimeError):
 _lib = None
 _vp = ctypes.c_void_p
 _batch_size = {}  # handle value -> P, so that mode buffers can be size-checked
+# captured graph value -> the tensors whose device memory it reads and writes at every
+# replay: held here until the graph is destroyed, so that none is freed (and its memory
+# reused) while the graph can still run
+_graph_refs = {}
 
 
 def lib():
@@ -124,6 +138,12 @@ def lib():
     L.srbe_batch_graph_set_step.restype = ctypes.c_int
     L.srbe_batch_graph_destroy.argtypes = [_vp]
     L.srbe_batch_graph_destroy.restype = None
+    L.srbe_ff_forces.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(srbe_ff), _vp, _vp, _vp, _vp, _vp, _vp]
+    L.srbe_ff_forces.restype = ctypes.c_int
+    L.srbe_md_graph_create.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       _vp, _vp, ctypes.c_uint64, ctypes.POINTER(srbe_md), _vp, _vp, _vp, _vp,
+                                       ctypes.POINTER(_vp)]
+    L.srbe_md_graph_create.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -134,7 +154,8 @@ EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string
             "srbe_graph_destroy", "srbe_tune", "srbe_get_tuning", "srbe_set_tuning", "srbe_electrode_forces",
             "srbe_langevin_update", "srbe_step_noalloc", "srbe_batch_create", "srbe_batch_destroy",
             "srbe_batch_last_error", "srbe_batch_sync_status", "srbe_batch_step", "srbe_batch_graph_create",
-            "srbe_batch_graph_launch", "srbe_batch_graph_set_step", "srbe_batch_graph_destroy"]
+            "srbe_batch_graph_launch", "srbe_batch_graph_set_step", "srbe_batch_graph_destroy", "srbe_ff_forces",
+            "srbe_md_graph_create"]
 SRBE_N_PHASES = 16
 
 
@@ -273,6 +294,8 @@ def srbe_graph_create(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, fir
                            Q_in, b_out, psibar_out, energy_out, kset_out)
     gr = _vp()
     _check(h, lib().srbe_graph_create(*args, ctypes.byref(gr)))
+    _graph_refs[gr.value] = (ion_xyz, ion_q, dpsi, seed, Q_out, F_out, kset_in, Q_in, b_out, psibar_out, energy_out,
+                             kset_out)
     return gr
 
 
@@ -290,6 +313,7 @@ def srbe_graph_set_step(gr, step, stream=None):
 
 def srbe_graph_destroy(gr):
     lib().srbe_graph_destroy(gr)
+    _graph_refs.pop(gr.value, None)
 
 
 SRBE_TUNE_NAMES = ["sf_blocks", "waves", "unroll", "ii_ions", "ie_blocks", "ele_split", "gemm_split",
@@ -467,6 +491,7 @@ def srbe_batch_graph_create(bt, precision, ion_offsets, system_of_replica, ion_x
                              Q_out, F_out, Q_in, b_out, psibar_out, energy_out)
     gr = _vp()
     _bcheck(bt, lib().srbe_batch_graph_create(*args, ctypes.byref(gr)))
+    _graph_refs[gr.value] = (ion_xyz, ion_q, dpsi, seed, Q_out, F_out, Q_in, b_out, psibar_out, energy_out)
     return gr
 
 
@@ -484,3 +509,50 @@ def srbe_batch_graph_set_step(gr, step, stream=None):
 
 def srbe_batch_graph_destroy(gr):
     lib().srbe_batch_graph_destroy(gr)
+    _graph_refs.pop(gr.value, None)
+
+
+# ---------------------------------------------------------------- dynamics
+
+
+def make_ff(d):
+    """srbe_ff from a dict with keys wca_eps, wca_sigma, wall_eps, wall_sigma, wall_zlo, wall_zhi, bond_k."""
+    return srbe_ff(**{k: float(d[k]) for k, _ in srbe_ff._fields_})
+
+
+def srbe_ff_forces(h, n_rep, ff, mol, bond, bond_r0, F, e_ion=None, stream=None):
+    """Add the force field's forces to F after an srbe_step on h (see include/srbe.h)."""
+    import torch
+    N = int(mol.numel())
+    f = ff if isinstance(ff, srbe_ff) else make_ff(ff)
+    _check(h, lib().srbe_ff_forces(h, int(n_rep), ctypes.byref(f), _dev(mol, torch.int32, N, "mol"),
+                                   _dev(bond, torch.int32, 2 * N, "bond"), _dev(bond_r0, torch.float64, 2 * N, "bond_r0"),
+                                   _dev(F, torch.float64, 3 * N, "F"),
+                                   _dev(e_ion, torch.float64, N, "e_ion", allow_none=True), _stream(stream)))
+
+
+def srbe_md_graph_create(h, precision, ion_offsets, ion_xyz, vel, ion_q, mass, mol, bond, bond_r0, dpsi, seed,
+                         first_step, md, Q_out, F_out, psibar_out=None, energy_out=None):
+    """Capture one SRBE-driven Langevin step (see include/srbe.h); md: dict of ff (dict), gamma, beta, dt,
+    zlo, zhi, noise_seed.  Returns the graph handle (srbe_graph_launch / _set_step / _destroy)."""
+    import torch
+    off = np.ascontiguousarray(np.asarray(ion_offsets, dtype=np.int64))
+    R = off.shape[0] - 1
+    N = int(off[-1])
+    n = srbe_n_ele(h)
+    m = md if isinstance(md, srbe_md) else srbe_md(ff=make_ff(md["ff"]), gamma=float(md["gamma"]),
+                                                    beta=float(md["beta"]), dt=float(md["dt"]), zlo=float(md["zlo"]),
+                                                    zhi=float(md["zhi"]), noise_seed=int(md["noise_seed"]))
+    gr = _vp()
+    _check(h, lib().srbe_md_graph_create(
+        h, int(precision), R, off.ctypes.data, _dev(ion_xyz, torch.float64, 3 * N, "ion_xyz"),
+        _dev(vel, torch.float64, 3 * N, "vel"), _dev(ion_q, torch.float64, N, "ion_q"),
+        _dev(mass, torch.float64, N, "mass"), _dev(mol, torch.int32, N, "mol"), _dev(bond, torch.int32, 2 * N, "bond"),
+        _dev(bond_r0, torch.float64, 2 * N, "bond_r0"), _dev(dpsi, torch.float64, R, "dpsi"),
+        _dev(seed, torch.uint64, R, "seed", allow_none=True), ctypes.c_uint64(int(first_step)), ctypes.byref(m),
+        _dev(Q_out, torch.float64, R * n, "Q_out"), _dev(F_out, torch.float64, 3 * N, "F_out"),
+        _dev(psibar_out, torch.float64, R, "psibar_out", allow_none=True),
+        _dev(energy_out, torch.float64, R, "energy_out", allow_none=True), ctypes.byref(gr)))
+    _graph_refs[gr.value] = (ion_xyz, vel, ion_q, mass, mol, bond, bond_r0, dpsi, seed, Q_out, F_out, psibar_out,
+                             energy_out)
+    return gr

@@ -201,10 +201,19 @@ int ele_split(int units);
 void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStream_t s);
 // the lattice charge solve: (Q; psibar) of every replica into Qext (one k-range)
 void launch_lattice_solve(const Geom& g, const StepBufs& b, hipStream_t s);
-// one Euler-Maruyama step of the Langevin thermostat for n ions (SoA, in place)
+// the short-range force field of the dynamics (srbe_ff in srbe.h)
+struct FFParams {
+  double wca_eps, wca_sigma, wall_eps, wall_sigma, wall_zlo, wall_zhi, bond_k;
+};
+// adds the force field's forces to F (SoA 3N) over the cell lists of the step b; e_ion: N or null
+void launch_ff_forces(const Geom& g, const StepBufs& b, const FFParams& ff, const int* mol, const int* bond,
+                      const double* bond_r0, double* F, double* e_ion, hipStream_t s);
+// one Euler-Maruyama step of the Langevin thermostat for n ions (SoA, in place); with
+// step_dev set, the step index is *step_dev - 1 (a captured dynamics step reads the
+// counter its SRBE step has just advanced)
 void launch_langevin(int64_t n, double* xyz, double* vel, const double* F, const double* mass, double gamma,
                      double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
-                     uint64_t step, hipStream_t s);
+                     uint64_t step, hipStream_t s, const uint64_t* step_dev = nullptr);
 // forces on the electrodes from the state b of a finished step: F (SoA, 3 R n_ele);
 // eoff: R + 1 int64 scratch, recs: R n_ele records (uint4 FP32 / double4 FP64) scratch
 void launch_electrode_forces(const Geom& g, const StepBufs& b, int fp32, double* F, int64_t* eoff, void* recs,

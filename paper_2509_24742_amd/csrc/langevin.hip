@@ -22,12 +22,13 @@ namespace {
 __global__ __launch_bounds__(256) void k_langevin(int64_t n, double* __restrict__ xyz, double* __restrict__ vel,
                                                    const double* __restrict__ F, const double* __restrict__ mass,
                                                    double gamma, double noise, double dt, double Lx, double Ly,
-                                                   double zlo, double zhi, uint64_t seed, uint64_t step) {
+                                                   double zlo, double zhi, uint64_t seed, uint64_t step,
+                                                   const uint64_t* __restrict__ step_dev) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   U64x4 c;
   c.v[0] = (uint64_t)i;
-  c.v[1] = step;
+  c.v[1] = step_dev ? *step_dev - 1 : step;
   c.v[2] = 3;
   c.v[3] = 0;
   const U64x4 w = philox4x64_10(c, seed, 1);
@@ -63,11 +64,11 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, double* __restrict_
 
 void launch_langevin(int64_t n, double* xyz, double* vel, const double* F, const double* mass, double gamma,
                      double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
-                     uint64_t step, hipStream_t s) {
+                     uint64_t step, hipStream_t s, const uint64_t* step_dev) {
   if (n == 0) return;
   const double noise = sqrt(2.0 * gamma / beta);  // 0 for beta = infinity
   hipLaunchKernelGGL(k_langevin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xyz, vel, F, mass, gamma,
-                     noise, dt, Lx, Ly, zlo, zhi, seed, step);
+                     noise, dt, Lx, Ly, zlo, zhi, seed, step, step_dev);
 }
 
 }  // namespace srbe

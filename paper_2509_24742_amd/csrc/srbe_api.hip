@@ -1754,14 +1754,28 @@ int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void
   return SRBE_OK;
 }
 
-int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
-                      const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
-                      uint64_t first_step, const int32_t* kset_in, const double* Q_in, double* Q_out, double* F_out,
-                      double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, srbe_graph** out) {
-  if (!h || !out) return SRBE_EINVAL;
-  *out = nullptr;
-  const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, kset_in,
-                   Q_in, Q_out, F_out, b_out, psibar_out, energy_out, kset_out};
+}  // extern "C"
+
+namespace {
+
+// The dynamics after a captured step (srbe_md_graph_create).
+struct MdTail {
+  FFParams ff;
+  const int32_t* mol;
+  const int32_t* bond;
+  const double* bond_r0;
+  double* xyz;
+  double* vel;
+  const double* mass;
+  double gamma, beta, dt, zlo, zhi;
+  uint64_t noise_seed;
+};
+
+int graph_create_impl(srbe_system* h, const StepArgs& a, const MdTail* md, srbe_graph** out) {
+  const int32_t precision = a.precision, n_rep = a.n_rep;
+  const int64_t* ion_offsets = a.ion_offsets;
+  const uint64_t first_step = a.step;
+  const double* Q_in = a.Q_in;
   int64_t max_nrep = 0;
   int rc = check_step(h, a, max_nrep);
   if (rc != SRBE_OK) return rc;
@@ -1794,6 +1808,12 @@ int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const in
   }
   h->capturing = true;
   rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, h->cap);
+  if (rc == SRBE_OK && md) {
+    launch_ff_forces(h->g, b, md->ff, md->mol, md->bond, md->bond_r0, a.F_out, nullptr, h->cap);
+    launch_langevin(b.N, md->xyz, md->vel, a.F_out, md->mass, md->gamma, md->beta, md->dt, h->p.Lx, h->p.Ly, md->zlo,
+                    md->zhi, md->noise_seed, 0, h->cap, gr->step_dev);
+    if (hipGetLastError() != hipSuccess) rc = set_err(h, SRBE_EHIP, "dynamics launches failed");
+  }
   h->capturing = false;
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(h->cap, &graph);
@@ -1811,6 +1831,70 @@ int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const in
     return fail(SRBE_EHIP);
   }
   *out = gr;
+  return SRBE_OK;
+}
+
+std::string check_ff(const srbe_system* h, const srbe_ff* ff) {
+  if (!ff) return "ff is NULL";
+  const double v[] = {ff->wca_eps, ff->wca_sigma, ff->wall_eps, ff->wall_sigma, ff->wall_zlo, ff->wall_zhi, ff->bond_k};
+  for (double x : v)
+    if (!std::isfinite(x)) return "non-finite force-field parameter";
+  if (ff->wca_eps < 0 || ff->wall_eps < 0 || ff->bond_k < 0 || !(ff->wca_sigma > 0) || !(ff->wall_sigma > 0))
+    return "force-field energies must be >= 0 and lengths > 0";
+  if (std::pow(2.0, 1.0 / 6.0) * ff->wca_sigma > h->p.rc) return "the WCA range 2^(1/6) sigma exceeds rc";
+  return "";
+}
+
+FFParams ff_params(const srbe_ff* ff) {
+  return FFParams{ff->wca_eps, ff->wca_sigma, ff->wall_eps, ff->wall_sigma, ff->wall_zlo, ff->wall_zhi, ff->bond_k};
+}
+
+}  // namespace
+
+extern "C" {
+
+int srbe_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                      const double* ion_xyz, const double* ion_q, const double* dpsi, const uint64_t* seed,
+                      uint64_t first_step, const int32_t* kset_in, const double* Q_in, double* Q_out, double* F_out,
+                      double* b_out, double* psibar_out, double* energy_out, int32_t* kset_out, srbe_graph** out) {
+  if (!h || !out) return SRBE_EINVAL;
+  *out = nullptr;
+  const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, kset_in,
+                   Q_in, Q_out, F_out, b_out, psibar_out, energy_out, kset_out};
+  return graph_create_impl(h, a, nullptr, out);
+}
+
+int srbe_md_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
+                         double* ion_xyz, double* vel, const double* ion_q, const double* mass, const int32_t* mol,
+                         const int32_t* bond, const double* bond_r0, const double* dpsi, const uint64_t* seed,
+                         uint64_t first_step, const srbe_md* md, double* Q_out, double* F_out, double* psibar_out,
+                         double* energy_out, srbe_graph** out) {
+  if (!h || !out) return SRBE_EINVAL;
+  *out = nullptr;
+  if (!md) return set_err(h, SRBE_EINVAL, "md is NULL");
+  const std::string why = check_ff(h, &md->ff);
+  if (!why.empty()) return set_err(h, SRBE_EINVAL, why);
+  const int64_t N = (n_rep > 0 && ion_offsets) ? ion_offsets[n_rep] : 0;
+  if (N > 0 && (!vel || !mass || !mol || !bond || !bond_r0)) return set_err(h, SRBE_EINVAL, "dynamics arrays are NULL");
+  if (!(md->dt > 0.0) || !(md->gamma >= 0.0) || !(md->beta > 0.0) || !(md->zlo < md->zhi))
+    return set_err(h, SRBE_EINVAL, "bad Langevin parameters");
+  const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, nullptr,
+                   nullptr, Q_out, F_out, nullptr, psibar_out, energy_out, nullptr};
+  const MdTail tail{ff_params(&md->ff), mol, bond, bond_r0, ion_xyz, vel, mass, md->gamma, md->beta, md->dt,
+                    md->zlo, md->zhi, md->noise_seed};
+  return graph_create_impl(h, a, &tail, out);
+}
+
+int srbe_ff_forces(srbe_system* h, int32_t n_rep, const srbe_ff* ff, const int32_t* mol, const int32_t* bond,
+                   const double* bond_r0, double* F, double* e_ion, void* stream) {
+  if (!h) return SRBE_EINVAL;
+  const std::string why = check_ff(h, ff);
+  if (!why.empty()) return set_err(h, SRBE_EINVAL, why);
+  if (!h->last_valid) return set_err(h, SRBE_EINVAL, "srbe_ff_forces: no preceding srbe_step on this handle");
+  if (n_rep != h->last.R) return set_err(h, SRBE_EINVAL, "srbe_ff_forces: n_rep differs from the last step's");
+  if (h->last.N > 0 && (!mol || !bond || !bond_r0 || !F)) return set_err(h, SRBE_EINVAL, "srbe_ff_forces: NULL array");
+  launch_ff_forces(h->g, h->last, ff_params(ff), mol, bond, bond_r0, F, e_ion, (hipStream_t)stream);
+  HIP_OK(h, hipGetLastError());
   return SRBE_OK;
 }
 

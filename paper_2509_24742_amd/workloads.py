@@ -249,6 +249,38 @@ def paper_cell(seed=1001, dpsi=2.0, n_pairs=320):
     return dict(params=params, ion_pos=ion, ion_q=q, ele_pos=ele, ele_side=side, dpsi=float(dpsi))
 
 
+# masses (amu) of the coarse-grained ions of the paper's electrolyte: [BMIm]+ split over
+# its three sites, [PF6]-
+CATION_MASS = 139.22
+ANION_MASS = 144.96
+
+
+def paper_cell_topology(n_pairs=320):
+    """Molecules, bonds and masses of paper_cell's sites (inputs of the dynamics).
+
+    Sites are ordered as paper_cell places them: the three sites of every cation, then the
+    anions.  Returns mol (molecule index per site), bond (two partner sites per site, -1
+    none), bond_r0 (rest lengths: the template's 0.30 nm bonds and 0.52 nm between the end
+    sites, which keeps the 120 degree angle) and mass (amu per site).
+    """
+    n = 4 * n_pairs
+    mol = np.concatenate([np.repeat(np.arange(n_pairs), 3), n_pairs + np.arange(n_pairs)]).astype(np.int32)
+    bond = np.full((n, 2), -1, dtype=np.int32)
+    r0 = np.zeros((n, 2))
+    tmpl = _cation_template()
+    d_end = float(np.linalg.norm(tmpl[0] - tmpl[2]))
+    for c in range(n_pairs):
+        a, m, e = 3 * c, 3 * c + 1, 3 * c + 2
+        bond[a] = (m, e)
+        r0[a] = (0.30, d_end)
+        bond[m] = (a, e)
+        r0[m] = (0.30, 0.30)
+        bond[e] = (m, a)
+        r0[e] = (0.30, d_end)
+    mass = np.concatenate([np.full(3 * n_pairs, CATION_MASS / 3.0), np.full(n_pairs, ANION_MASS)])
+    return dict(mol=mol, bond=bond.ravel(), bond_r0=r0.ravel(), mass=mass)
+
+
 def replica_batch(R=64, base_seed=1100, dpsi_seed=3000, n_pairs=320):
     """R paper-shaped cells sharing one electrode geometry; per-replica ions and voltage."""
     reps = [paper_cell(seed=base_seed + r, n_pairs=n_pairs) for r in range(R)]

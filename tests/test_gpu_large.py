@@ -130,7 +130,7 @@ def full():
     sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
     inputs = gpu_inputs([w["ion_pos"]], [w["ion_q"]], [w["dpsi"]], [ref["seed"]])
     yield dict(sys=sysm, ref=ref, inputs=inputs, qin=torch.tensor(Q, device="cuda"), p=oracle_params(wp),
-               ii=ii, ie=ie)
+               ii=ii, ie=ie, w=w)
     sysm.close()
 
 
@@ -194,5 +194,95 @@ def test_full_size_large_slab_lattice_charge_solve(full):
         assert rel_inf(d2, d1) < 1e-7
         assert np.sum(d1[side > 0]) > 0 > np.sum(d1[side < 0])
         assert e32 < 1e-4
+    finally:
+        sysm.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_large_slab_P2000_at_sampled_targets(full, precision):
+    # the same slab, charges and sampled targets with a batch of P = 2000 modes
+    # (tests/golden/large_slab_sample_P2000.json, written by make_large_slab_sample.py 2000)
+    import json
+    import os
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import binding
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(gdir, "large_slab_sample_P2000.json")) as f:
+        ref = json.load(f)
+    assert ref["P"] == 2000 and ref["ion_index"] == full["ii"].tolist() and ref["ele_index"] == full["ie"].tolist()
+    w = full["w"]
+    wp = dict(w["params"], kspace_tol=1e-16, P=2000)
+    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
+    try:
+        off, xyz, q, dp, sd = full["inputs"]
+        sd = torch.tensor([ref["seed"]], dtype=torch.int64, device="cuda").view(torch.uint64)
+        print(f"full-size large slab, P = 2000, precision {precision}", flush=True)
+        out = sysm.step(off, xyz, q, dp, sd, ref["step"], precision=precision, Q_in=full["qin"])
+        torch.cuda.synchronize()
+        assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+        ks, _ = sampler.draw_kset(oracle_params(wp), ref["seed"], 0, ref["step"])
+        assert np.array_equal(out["kset"].cpu().numpy(), ks.astype(np.int32).ravel())
+        F = forces_from_soa(out["F"], off, 0)[full["ii"]]
+        b = out["b"].cpu().numpy()[full["ie"]]
+        Fr, br = np.asarray(ref["F"]), np.asarray(ref["b"])
+        print(f"  sampled force {rel_rms(F, Fr):.2e} rms {rel_inf(F, Fr):.2e} max, b {rel_rms(b, br):.2e} rms",
+              flush=True)
+        if precision == 0:
+            assert rel_inf(F, Fr) < 1e-11 and rel_inf(b, br) < 1e-11
+        else:
+            assert rel_rms(F, Fr) < 1e-5 and rel_rms(b, br) < 3e-5
+    finally:
+        sysm.close()
+
+
+# ---------------------------------------------------------------- the large-slab recipe at 1/8 scale
+
+@pytest.fixture(scope="module")
+def mid():
+    # 2 x 32 x 32 square walls (2,048 atoms), 1,792 ions, 3.75 x 3.75 x 12.5 nm (aspect 10):
+    # the constant-potential step by the lattice charge solve against the oracle's dense
+    # solve (tests/golden/large_slab_mid.json, written by make_large_slab_mid.py beside it)
+    import json
+    import os
+    import sys
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gdir)
+    import make_large_slab_mid as golden
+    with open(os.path.join(gdir, "large_slab_mid.json")) as f:
+        ref = json.load(f)
+    w, ii, ie = golden.inputs(500)
+    assert float(np.sum(w["ion_pos"] * np.arange(1, 4))) == ref["ion_pos_checksum"]
+    assert ii.tolist() == ref["ion_index"] and ie.tolist() == ref["ele_index"]
+    yield dict(w=w, ref=ref, ii=ii, ie=ie)
+
+
+@pytest.mark.parametrize("P", [500, 2000])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mid_size_slab_constant_potential_matches_oracle(mid, P, precision):
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import binding
+    w, ref = mid["w"], mid["ref"][str(P)]
+    wp = dict(w["params"], kspace_tol=1e-16, P=P)
+    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_LATTICE_SOLVE)
+    try:
+        off, xyz, q, dp, sd = gpu_inputs([w["ion_pos"]], [w["ion_q"]], [w["dpsi"]], [mid["ref"]["seed"]])
+        out = sysm.step(off, xyz, q, dp, sd, mid["ref"]["step"], precision=precision)
+        torch.cuda.synchronize()
+        assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+        Q = out["Q"].cpu().numpy()
+        F = forces_from_soa(out["F"], off, 0)[mid["ii"]]
+        b = out["b"].cpu().numpy()[mid["ie"]]
+        E, psibar = float(out["E"][0]), float(out["psibar"][0])
+        Qr, Fr, br = np.asarray(ref["Q"]), np.asarray(ref["F"]), np.asarray(ref["b"])
+        eE = abs(E - ref["E"]) / abs(ref["E"])
+        print(f"mid-size slab P {P} precision {precision}: Q {rel_rms(Q, Qr):.2e} rms {rel_inf(Q, Qr):.2e} max, "
+              f"F {rel_rms(F, Fr):.2e}, b {rel_rms(b, br):.2e}, E {eE:.2e}, psibar {abs(psibar - ref['psibar']):.2e}",
+              flush=True)
+        if precision == 0:
+            assert rel_inf(Q, Qr) < 1e-10 and rel_inf(F, Fr) < 1e-11 and rel_inf(b, br) < 1e-11
+            assert eE < 1e-11 and abs(psibar - ref["psibar"]) < 1e-11 * max(1.0, abs(ref["psibar"]))
+        else:
+            assert rel_rms(F, Fr) < 1e-5 and rel_rms(b, br) < 3e-5 and rel_rms(Q, Qr) < 1e-4
+            assert abs(np.sum(Q)) < 1e-12 * np.sum(np.abs(Q))
     finally:
         sysm.close()

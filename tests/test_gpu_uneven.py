@@ -60,3 +60,41 @@ def test_uneven_system_matches_oracle(system, precision):
     else:
         assert rel_rms(F, ref["F"]) < 1e-5
         assert rel_rms(b, ref["b"]) < 3e-5 and rel_rms(Q, ref["Q"]) < 3e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_uneven_system_at_sampled_targets(precision):
+    # the largest system (162,990 particles: multi-block cell sort) at fixed charges against
+    # the oracle at 64 sampled ions and electrodes (tests/golden/uneven_largest.json,
+    # written by make_uneven_largest.py beside it)
+    import json
+    import os
+    import sys
+    import paper_2509_24742_amd as srbe_amd
+    from paper_2509_24742_amd import binding
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gdir)
+    import make_uneven_largest as golden
+    with open(os.path.join(gdir, "uneven_largest.json")) as f:
+        ref = json.load(f)
+    w, Q, ii, ie = golden.inputs()
+    assert float(np.sum(w["ion_pos"] * np.arange(1, 4))) == ref["ion_pos_checksum"]
+    wp = dict(w["params"], kspace_tol=1e-16)
+    sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"], flags=srbe_amd.SRBE_FLAG_NO_CP)
+    try:
+        off, xyz, q, dp, sd = gpu_inputs([w["ion_pos"]], [w["ion_q"]], [w["dpsi"]], [ref["seed"]])
+        out = sysm.step(off, xyz, q, dp, sd, ref["step"], precision=precision,
+                        Q_in=torch.tensor(Q, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+        F = forces_from_soa(out["F"], off, 0)[ii]
+        b = out["b"].cpu().numpy()[ie]
+        Fr, br = np.asarray(ref["F"]), np.asarray(ref["b"])
+        print(f"largest uneven system precision {precision}: F {rel_rms(F, Fr):.2e} rms {rel_inf(F, Fr):.2e} max, "
+              f"b {rel_rms(b, br):.2e}", flush=True)
+        if precision == 0:
+            assert rel_inf(F, Fr) < 1e-11 and rel_inf(b, br) < 1e-11
+        else:
+            assert rel_rms(F, Fr) < 1e-5 and rel_rms(b, br) < 3e-5
+    finally:
+        sysm.close()

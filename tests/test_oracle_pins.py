@@ -595,3 +595,55 @@ def test_langevin_large_overshoot_lands_inside():
             n += 1
         assert zr == pytest.approx(z, abs=1e-9)
         assert vr == (-u if n % 2 else u)
+
+
+# ---------------------------------------------------------------- short-range force field (dynamics)
+
+
+def _ff():
+    return dict(wca_eps=0.05, wca_sigma=0.3, wall_eps=0.2, wall_sigma=0.35, wall_zlo=0.5, wall_zhi=3.5, bond_k=500.0)
+
+
+def test_forcefield_terms_closed_forms():
+    from oracle import forcefield
+    ff = _ff()
+    s = ff["wca_sigma"]
+    u, _ = forcefield.wca(0.05, s, s)
+    assert u == pytest.approx(0.05, rel=1e-14)  # 4 eps (1 - 1) + eps
+    rc = 2 ** (1 / 6) * s
+    u, du = forcefield.wca(0.05, s, rc * (1 - 1e-12))
+    assert abs(u) < 1e-12 and abs(du) < 1e-9  # continuous with zero force at the cut
+    dmin = (2 / 5) ** (1 / 6) * ff["wall_sigma"]
+    u, du = forcefield.wall93(0.2, ff["wall_sigma"], dmin * (1 - 1e-12))
+    assert abs(u) < 1e-12 and abs(du) < 1e-9  # cut and shifted at the minimum
+    u, du = forcefield.wall93(0.2, ff["wall_sigma"], 0.5 * dmin)
+    assert u > 0 and du < 0  # repulsive
+
+
+def test_forcefield_forces_are_minus_gradient():
+    from oracle import forcefield
+    # sites on a jittered 0.31 nm grid (some pairs inside the WCA range, none closer than
+    # ~0.26 nm), within the walls' reach at both ends, x and y across the periodic boundary
+    rng = np.random.default_rng(11)
+    Lx = Ly = 1.24
+    g = np.array([[ix, iy, iz] for ix in range(2) for iy in range(2) for iz in range(4)], dtype=float)[:14]
+    pos = g * 0.31 + rng.uniform(-0.02, 0.02, (14, 3)) + np.array([1.1, 0.05, 0.0])
+    pos[:, 2] = np.where(g[:, 2] < 2, 0.75 + 0.31 * g[:, 2], 3.25 - 0.31 * (g[:, 2] - 2)) + rng.uniform(-0.02, 0.02, 14)
+    pos[:, :2] %= Lx
+    n = len(pos)
+    mol = np.array([0, 0, 0, 1, 2, 3, 4, 4, 5, 6, 7, 8, 9, 10])
+    bonds = [(0, 1, 0.3), (1, 2, 0.3), (0, 2, 0.52), (6, 7, 0.25)]
+    ff = _ff()
+    F = forcefield.forces(pos, mol, bonds, ff, Lx, Ly)
+    assert np.any(F != 0)
+    h = 1e-6
+    for i in range(n):
+        for d in range(3):
+            p1, p0 = pos.copy(), pos.copy()
+            p1[i, d] += h
+            p0[i, d] -= h
+            fd = -(forcefield.energy(p1, mol, bonds, ff, Lx, Ly) - forcefield.energy(p0, mol, bonds, ff, Lx, Ly)) / (2 * h)
+            assert abs(fd - F[i, d]) < 1e-5 * (1 + abs(F[i, d]))
+    # without walls the pair and bond forces cancel (Newton's third law)
+    ffw = dict(ff, wall_eps=0.0)
+    assert np.max(np.abs(forcefield.forces(pos, mol, bonds, ffw, Lx, Ly).sum(axis=0))) < 1e-10
