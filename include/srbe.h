@@ -322,7 +322,9 @@ int srbe_ff_forces(srbe_system* h, int32_t n_rep, const srbe_ff* ff, const int32
  * the counter's step, b*, the charge solve, the forces of Eq. (25) and real space) into
  * Q_out, F_out, psibar_out, energy_out; then F_out += the force field's forces
  * (srbe_ff_forces); then the Euler-Maruyama update of srbe_langevin_update of ion_xyz and
- * vel in place with the counter's step (noise key md->noise_seed).  Each replay advances
+ * vel in place with the counter's step (noise key md->noise_seed; md->symplectic = 1 moves
+ * the positions with the updated velocity, r + v_new dt, the symplectic ordering of the
+ * same update: the printed r + v dt gains energy on stiff contacts, 0 keeps it).  Each replay advances
  * the dynamics by dt; F_out and Q_out hold the forces and charges at the positions before
  * the update.  Arguments as for srbe_graph_create, srbe_ff_forces and srbe_langevin_update
  * (mass: device N doubles).  Errors: as those calls.
@@ -332,6 +334,8 @@ typedef struct srbe_md {
   double gamma, beta, dt; /* Langevin friction, inverse temperature, time step        */
   double zlo, zhi;        /* reflecting bounds of z (a safety net behind the walls)   */
   uint64_t noise_seed;
+  int32_t symplectic;     /* 1: r <- r + v_new dt; 0: r <- r + v dt (as printed)     */
+  int32_t reserved;       /* must be 0                                                */
 } srbe_md;
 int srbe_md_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* ion_offsets,
                          double* ion_xyz, double* vel, const double* ion_q, const double* mass, const int32_t* mol,

@@ -43,7 +43,8 @@ class srbe_ff(ctypes.Structure):
 
 class srbe_md(ctypes.Structure):
     _fields_ = [("ff", srbe_ff), ("gamma", ctypes.c_double), ("beta", ctypes.c_double), ("dt", ctypes.c_double),
-                ("zlo", ctypes.c_double), ("zhi", ctypes.c_double), ("noise_seed", ctypes.c_uint64)]
+                ("zlo", ctypes.c_double), ("zhi", ctypes.c_double), ("noise_seed", ctypes.c_uint64),
+                ("symplectic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SrbeError(RuntimeError):
@@ -542,7 +543,8 @@ def srbe_md_graph_create(h, precision, ion_offsets, ion_xyz, vel, ion_q, mass, m
     n = srbe_n_ele(h)
     m = md if isinstance(md, srbe_md) else srbe_md(ff=make_ff(md["ff"]), gamma=float(md["gamma"]),
                                                     beta=float(md["beta"]), dt=float(md["dt"]), zlo=float(md["zlo"]),
-                                                    zhi=float(md["zhi"]), noise_seed=int(md["noise_seed"]))
+                                                    zhi=float(md["zhi"]), noise_seed=int(md["noise_seed"]),
+                                                    symplectic=int(md.get("symplectic", 0)), reserved=0)
     gr = _vp()
     _check(h, lib().srbe_md_graph_create(
         h, int(precision), R, off.ctypes.data, _dev(ion_xyz, torch.float64, 3 * N, "ion_xyz"),

@@ -10,7 +10,10 @@ first run at dpsi = 0 for --equil steps, then dpsi steps to 2 V and the charge o
 negative electrode, Q_neg(t), is averaged over every window of --every steps.  The
 dynamics are the Euler-Maruyama Langevin update of Sec. 3 at 500 K with dt = 1 fs (the
 paper's) and friction --gamma (mass/ps; strong enough that the thermostat, not the
-random-batch force noise, sets the temperature), driven by the SRBE forces plus a
+random-batch force noise, sets the temperature), positions moved with the updated
+velocity (the symplectic ordering of the update; as printed, r + v^n dt gains energy on
+the stiff contacts, by 1 + (omega dt)^2 per step, and the dynamics run away), driven by
+the SRBE forces plus a
 stand-in short-range force field
 (the paper's is not given): WCA between molecules (eps = 0.05 eV, sigma = 0.3 nm), 9-3
 walls at the innermost electrode layers (eps = 0.2 eV, sigma = 0.45 nm) and harmonic
@@ -41,6 +44,11 @@ def main():
     ap.add_argument("--steps", type=int, default=9000)
     ap.add_argument("--every", type=int, default=500)
     ap.add_argument("--gamma", type=float, default=10.0)
+    ap.add_argument("--dt", type=float, default=0.001, help="time step (ps)")
+    ap.add_argument("--wca-eps", type=float, default=0.05, help="WCA energy (eV)")
+    ap.add_argument("--printed-order", action="store_true",
+                    help="move the positions with the old velocity, as the update is printed (unstable on the "
+                         "stiff contacts; the default moves them with the new velocity)")
     ap.add_argument("--P", type=int, default=50)
     ap.add_argument("--dpsi", type=float, default=2.0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -73,9 +81,10 @@ def main():
     dp = torch.zeros(R, dtype=torch.float64, device=dev)
     sd = torch.tensor(2100 + np.arange(R), dtype=torch.int64, device=dev).view(torch.uint64)
     H = wp["H"]
-    ff = dict(wca_eps=0.05, wca_sigma=0.3, wall_eps=0.2, wall_sigma=0.45, wall_zlo=0.67, wall_zhi=H - 0.67,
+    ff = dict(wca_eps=args.wca_eps, wca_sigma=0.3, wall_eps=0.2, wall_sigma=0.45, wall_zlo=0.67, wall_zhi=H - 0.67,
               bond_k=500.0)
-    md = dict(ff=ff, gamma=args.gamma, beta=1.0 / (KB_EV * T), dt=0.001, zlo=1.0, zhi=H - 1.0, noise_seed=77)
+    md = dict(ff=ff, gamma=args.gamma, beta=1.0 / (KB_EV * T), dt=args.dt, zlo=1.0, zhi=H - 1.0, noise_seed=77,
+              symplectic=0 if args.printed_order else 1)
     n = sysm.n_ele
     Q = torch.empty(R * n, dtype=torch.float64, device=dev)
     F = torch.empty(3 * N, dtype=torch.float64, device=dev)
@@ -91,8 +100,11 @@ def main():
     def report(k, dpsi):
         qn = acc.cpu().numpy() / args.every
         acc.zero_()
+        ke = (torch.tensor(mass, device=dev)[None, :] * v.view(3, N) ** 2).sum(dim=0).cpu().numpy() / 3.0
         row = {"t_end_ps": round(k * md["dt"], 4), "window_ps": args.every * md["dt"], "dpsi": dpsi,
-               "Q_neg_mean": float(qn.mean()), "Q_neg_se": float(qn.std(ddof=1) / np.sqrt(R))}
+               "Q_neg_mean": float(qn.mean()), "Q_neg_se": float(qn.std(ddof=1) / np.sqrt(R)),
+               "kinetic_T_median_K": float(np.median(ke)) / KB_EV,
+               "sites_above_100kT": int(np.sum(ke > 100.0 * KB_EV * T))}
         print(json.dumps(row), flush=True)
         return row
 

@@ -213,7 +213,7 @@ void launch_ff_forces(const Geom& g, const StepBufs& b, const FFParams& ff, cons
 // counter its SRBE step has just advanced)
 void launch_langevin(int64_t n, double* xyz, double* vel, const double* F, const double* mass, double gamma,
                      double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
-                     uint64_t step, hipStream_t s, const uint64_t* step_dev = nullptr);
+                     uint64_t step, hipStream_t s, const uint64_t* step_dev = nullptr, int symplectic = 0);
 // forces on the electrodes from the state b of a finished step: F (SoA, 3 R n_ele);
 // eoff: R + 1 int64 scratch, recs: R n_ele records (uint4 FP32 / double4 FP64) scratch
 void launch_electrode_forces(const Geom& g, const StepBufs& b, int fp32, double* F, int64_t* eoff, void* recs,

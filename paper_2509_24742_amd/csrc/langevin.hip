@@ -3,6 +3,10 @@
 //   r <- r + v dt
 //   v <- v + (F - gamma v) dt / m + sqrt(2 gamma / beta) dW / m,   dW ~ N(0, dt) per component
 //
+// or, with the symplectic ordering (a reading for dynamics: the printed ordering gains
+// energy on every stiff oscillation by 1 + (omega dt)^2 per step), the same velocity
+// update first and r <- r + v_new dt.
+//
 // x and y wrap into the periodic cell; z is reflected specularly into [zlo, zhi] as often
 // as it takes to land inside (v_z changes sign once per reflection), a stand-in for the
 // wall force field: with W = zhi - zlo, k = floor((z - zlo) / W) reflections and
@@ -23,7 +27,7 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, double* __restrict_
                                                    const double* __restrict__ F, const double* __restrict__ mass,
                                                    double gamma, double noise, double dt, double Lx, double Ly,
                                                    double zlo, double zhi, uint64_t seed, uint64_t step,
-                                                   const uint64_t* __restrict__ step_dev) {
+                                                   const uint64_t* __restrict__ step_dev, int symplectic) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   U64x4 c;
@@ -40,8 +44,8 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, double* __restrict_
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double x = xyz[d * n + i], u = vel[d * n + i];
-    r[d] = x + u * dt;
     v[d] = u + (F[d * n + i] - gamma * u) * dt / m + noise * (sdt * z[d]) / m;
+    r[d] = x + (symplectic ? v[d] : u) * dt;
   }
   r[0] -= Lx * floor(r[0] / Lx);
   r[1] -= Ly * floor(r[1] / Ly);
@@ -64,11 +68,11 @@ __global__ __launch_bounds__(256) void k_langevin(int64_t n, double* __restrict_
 
 void launch_langevin(int64_t n, double* xyz, double* vel, const double* F, const double* mass, double gamma,
                      double beta, double dt, double Lx, double Ly, double zlo, double zhi, uint64_t seed,
-                     uint64_t step, hipStream_t s, const uint64_t* step_dev) {
+                     uint64_t step, hipStream_t s, const uint64_t* step_dev, int symplectic) {
   if (n == 0) return;
   const double noise = sqrt(2.0 * gamma / beta);  // 0 for beta = infinity
   hipLaunchKernelGGL(k_langevin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, xyz, vel, F, mass, gamma,
-                     noise, dt, Lx, Ly, zlo, zhi, seed, step, step_dev);
+                     noise, dt, Lx, Ly, zlo, zhi, seed, step, step_dev, symplectic);
 }
 
 }  // namespace srbe

@@ -1769,6 +1769,7 @@ struct MdTail {
   const double* mass;
   double gamma, beta, dt, zlo, zhi;
   uint64_t noise_seed;
+  int symplectic;
 };
 
 int graph_create_impl(srbe_system* h, const StepArgs& a, const MdTail* md, srbe_graph** out) {
@@ -1811,7 +1812,7 @@ int graph_create_impl(srbe_system* h, const StepArgs& a, const MdTail* md, srbe_
   if (rc == SRBE_OK && md) {
     launch_ff_forces(h->g, b, md->ff, md->mol, md->bond, md->bond_r0, a.F_out, nullptr, h->cap);
     launch_langevin(b.N, md->xyz, md->vel, a.F_out, md->mass, md->gamma, md->beta, md->dt, h->p.Lx, h->p.Ly, md->zlo,
-                    md->zhi, md->noise_seed, 0, h->cap, gr->step_dev);
+                    md->zhi, md->noise_seed, 0, h->cap, gr->step_dev, md->symplectic);
     if (hipGetLastError() != hipSuccess) rc = set_err(h, SRBE_EHIP, "dynamics launches failed");
   }
   h->capturing = false;
@@ -1876,12 +1877,13 @@ int srbe_md_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const
   if (!why.empty()) return set_err(h, SRBE_EINVAL, why);
   const int64_t N = (n_rep > 0 && ion_offsets) ? ion_offsets[n_rep] : 0;
   if (N > 0 && (!vel || !mass || !mol || !bond || !bond_r0)) return set_err(h, SRBE_EINVAL, "dynamics arrays are NULL");
-  if (!(md->dt > 0.0) || !(md->gamma >= 0.0) || !(md->beta > 0.0) || !(md->zlo < md->zhi))
+  if (!(md->dt > 0.0) || !(md->gamma >= 0.0) || !(md->beta > 0.0) || !(md->zlo < md->zhi) ||
+      (md->symplectic != 0 && md->symplectic != 1) || md->reserved != 0)
     return set_err(h, SRBE_EINVAL, "bad Langevin parameters");
   const StepArgs a{precision, n_rep, ion_offsets, ion_xyz, ion_q, dpsi, seed, first_step, nullptr,
                    nullptr, Q_out, F_out, nullptr, psibar_out, energy_out, nullptr};
   const MdTail tail{ff_params(&md->ff), mol, bond, bond_r0, ion_xyz, vel, mass, md->gamma, md->beta, md->dt,
-                    md->zlo, md->zhi, md->noise_seed};
+                    md->zlo, md->zhi, md->noise_seed, md->symplectic};
   return graph_create_impl(h, a, &tail, out);
 }
 

@@ -73,11 +73,13 @@ def _tiny_md():
     return w, vel, mass, md, top
 
 
-def test_md_graph_one_step_matches_oracle():
+@pytest.mark.parametrize("symplectic", [0, 1])
+def test_md_graph_one_step_matches_oracle(symplectic):
     import paper_2509_24742_amd as srbe_amd
     from oracle import forcefield, langevin
     from paper_2509_24742_amd import binding
     w, vel, mass, md, top = _tiny_md()
+    md = dict(md, symplectic=symplectic)
     wp = dict(w["params"], kspace_tol=1e-16)
     p = oracle_params(wp)
     sysm = srbe_amd.System(wp, w["ele_pos"], w["ele_side"])
@@ -98,7 +100,8 @@ def test_md_graph_one_step_matches_oracle():
                           w["ele_side"], w["dpsi"])
         Ft = ref["F"] + forcefield.forces(w["ion_pos"], top["mol"], [], md["ff"], wp["Lx"], wp["Ly"])
         r1, v1 = langevin.euler_maruyama(w["ion_pos"], vel, Ft, mass, md["gamma"], md["beta"], md["dt"], wp["Lx"],
-                                         wp["Ly"], md["zlo"], md["zhi"], md["noise_seed"], 4)
+                                         wp["Ly"], md["zlo"], md["zhi"], md["noise_seed"], 4,
+                                         symplectic=bool(symplectic))
         got_F = F.cpu().numpy().reshape(3, n).T
         got_r = xyz.cpu().numpy().reshape(3, n).T
         got_v = v.cpu().numpy().reshape(3, n).T

@@ -647,3 +647,19 @@ def test_forcefield_forces_are_minus_gradient():
     # without walls the pair and bond forces cancel (Newton's third law)
     ffw = dict(ff, wall_eps=0.0)
     assert np.max(np.abs(forcefield.forces(pos, mol, bonds, ffw, Lx, Ly).sum(axis=0))) < 1e-10
+
+
+def test_langevin_update_orderings_on_a_harmonic_oscillator():
+    # noiseless, frictionless one-step maps of x'' = -omega^2 x (F = -k x, m = 1): the
+    # printed ordering (r + v^n dt) has determinant 1 + (omega dt)^2, so it gains energy
+    # every step; the symplectic ordering (r + v^{n+1} dt) has determinant 1 exactly
+    k, dt = 400.0, 0.01
+    def step(x, v, sym):
+        r, u = langevin.euler_maruyama(np.array([[1.0, 1.0, x]]), np.array([[0.0, 0.0, v]]),
+                                       np.array([[0.0, 0.0, -k * x]]), np.ones(1), 0.0, np.inf, dt, 5.0, 5.0,
+                                       -1e3, 1e3, 1, 0, symplectic=sym)
+        return r[0, 2], u[0, 2]
+    for sym, det in ((False, 1.0 + k * dt * dt), (True, 1.0)):
+        a = step(1.0, 0.0, sym)
+        b = step(0.0, 1.0, sym)
+        assert a[0] * b[1] - a[1] * b[0] == pytest.approx(det, rel=1e-13)
