@@ -58,6 +58,8 @@ extern "C" {
 #define SRBE_FLAG_KSPACE_ONLY 2 /* leave out the real-space erfc terms (see below)   */
 #define SRBE_FLAG_LATTICE_SOLVE 4 /* electrodes on two rectangular lattices: solve the
                                      charges in lattice Fourier space (see below)     */
+#define SRBE_FLAG_ENERGY_PARTS 8 /* energy_out holds E* and its four parts per replica
+                                    (see srbe_step)                                   */
 
 typedef struct srbe_params {
   double Lx, Ly, H;   /* box (length); electrodes and ions have 0 <= z <= H           */
@@ -143,7 +145,15 @@ const char* srbe_error_string(int code);
  * psibar_out  device, n_rep doubles or NULL (NaN in fixed-charge steps).
  * energy_out  device, n_rep doubles or NULL: E* = 1/2 Q^T A Q - b*^T Q + c*, with
  *             c* the ion-ion energy using the same estimator (requires the CP
- *             solve; NaN in fixed-charge steps).
+ *             solve; NaN in fixed-charge steps).  With SRBE_FLAG_ENERGY_PARTS set at
+ *             creation: 5 doubles per replica, [total E*, real, fourier, self, slab],
+ *             split as U_c is in Eqs. (13), (16), (17): real = every erfc pair term
+ *             (ion-ion, ion-electrode, electrode-electrode; 0 with KSPACE_ONLY), self
+ *             and slab = the two terms of Eq. (17) over ions and electrodes, fourier =
+ *             the rest (the only part the sample changes; its mean over samples is the
+ *             complete Fourier energy of Eq. (16)).  The electrode-electrode pair sum
+ *             adds one pass over the electrodes' neighbours per step.  Not allowed in a
+ *             batch of systems (srbe_batch_create refuses such handles).
  * kset_out    device, n_rep*P*3 int32 or NULL: the modes used.
  * stream      hipStream_t on which all work is enqueued (NULL = default stream).
  * Errors: SRBE_EINVAL (synchronous); device-data errors via srbe_sync_status.
@@ -208,7 +218,8 @@ void srbe_graph_destroy(srbe_graph* g);
  * to rounding order (the same kernels and per-system launch shapes).
  *
  * srbe_batch_create -- systems: host array of n_systems handles (1..4096, all on one
- * device), not owned: they must outlive the batch and its graphs.
+ * device, none created with SRBE_FLAG_ENERGY_PARTS), not owned: they must outlive the
+ * batch and its graphs.
  * srbe_batch_step -- n_rep replicas, replica r belonging to system system_of_replica[r]
  * (host int32, non-decreasing, so each system's replicas are consecutive).
  * ion_offsets host n_rep + 1 int64 CSR over all replicas (ion_offsets[0] = 0); ion_xyz

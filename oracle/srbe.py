@@ -207,6 +207,44 @@ def srbe_energy(p, A, kset, ion_pos, ion_q, ele_pos, Q, b=None):
     return 0.5 * Q @ (A @ Q) - b @ Q + srbe_constant(p, kset, ion_pos, ion_q)
 
 
+def srbe_energy_parts(p, kset, ion_pos, ion_q, ele_pos, Q, modes=None):
+    """E* split as U_c is in Eqs. (13), (16), (17): real, fourier, self, slab, total (times coulomb_k).
+
+    The SRBE changes only the Fourier part, so each other part is the complete one:
+      real    = 1/2 q.phi_ii + Q.phi_ig + 1/2 Q.phi_gg      (erfc kernels, r < rc, Eq. (13))
+      self    = c_g sum Q^2 - c_i sum q^2                    (Eq. (17))
+      slab    = (2 pi / V) (sum q z + sum Q Z)^2             (Eq. (17))
+      fourier = 1/2 sum_all w |S2|^2 + sum_est w Re(S1 conj S2) + 1/2 sum_est w |S1|^2,
+    the electrode-electrode Fourier term exact (A is), the ion-electrode and ion-ion ones
+    over the deterministic modes and the sample (Eq. (24) and c*).  `modes` is the
+    complete mode set of A (default: ewald.enumerate_modes).
+    """
+    ion_pos = np.asarray(ion_pos, dtype=np.float64).reshape(-1, 3)
+    ele_pos = np.asarray(ele_pos, dtype=np.float64).reshape(-1, 3)
+    ion_q = np.asarray(ion_q, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    modes = ewald.enumerate_modes(p) if modes is None else modes
+    phi_ii, _ = ewald.real_space(p, "ii", ion_pos, ion_pos, ion_q, same=True)
+    phi_ig, _ = ewald.real_space(p, "ig", ele_pos, ion_pos, ion_q)
+    phi_gg, _ = ewald.real_space(p, "gg", ele_pos, ele_pos, Q, same=True)
+    u_real = 0.5 * ion_q @ phi_ii + Q @ phi_ig + 0.5 * Q @ phi_gg
+    k2 = np.sum(ewald.kvectors(p, modes) ** 2, axis=1)
+    S2_all = ewald.structure_factor(p, modes, ele_pos, Q)
+    u_gg = 0.5 * np.sum(ewald.ewald_weight(p, k2) * np.abs(S2_all) ** 2)
+    m, w = _combined(p, kset)
+    S1 = ewald.structure_factor(p, m, ion_pos, ion_q)
+    S2 = ewald.structure_factor(p, m, ele_pos, Q)
+    u_four = u_gg + np.sum(w * np.real(S1 * np.conj(S2))) + 0.5 * np.sum(w * np.abs(S1) ** 2)
+    cg, ci = ewald.self_constants(p)
+    u_self = cg * np.sum(Q ** 2) - ci * np.sum(ion_q ** 2)
+    Mz = ion_q @ ion_pos[:, 2] + Q @ ele_pos[:, 2]
+    u_slab = (2.0 * np.pi / p.V) * Mz ** 2 if p.slab else 0.0
+    ke = p.coulomb_k
+    out = dict(real=ke * u_real, fourier=ke * u_four, self=ke * u_self, slab=ke * u_slab)
+    out["total"] = out["real"] + out["fourier"] + out["self"] + out["slab"]
+    return out
+
+
 def srbe_step(p, solver, kset, ion_pos, ion_q, ele_pos, ele_side, dpsi, Q_fixed=None):
     """One SRBE step without integration (Algorithm 1, steps 'compute b, update Q, compute forces').
 

@@ -10,7 +10,7 @@ library has not been built.
 import numpy as np
 
 from . import binding
-from .binding import (SRBE_FLAG_KSPACE_ONLY, SRBE_FLAG_LATTICE_SOLVE, SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
+from .binding import (SRBE_FLAG_ENERGY_PARTS, SRBE_FLAG_KSPACE_ONLY, SRBE_FLAG_LATTICE_SOLVE, SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
                       srbe_error_string, srbe_graph_create, srbe_graph_destroy, srbe_graph_launch,
                       srbe_graph_set_step, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
                       srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status,
@@ -23,6 +23,7 @@ class System:
 
     def __init__(self, params, ele_pos, ele_side, flags=0):
         self.params = dict(params)
+        self.flags = int(flags)
         self.h = srbe_create(self.params, ele_pos, ele_side, flags=flags)
         self.n_ele = srbe_n_ele(self.h)
         self.G = srbe_normaliser(self.h)
@@ -50,7 +51,9 @@ class System:
             F=torch.empty(3 * N, dtype=torch.float64, device=device),
             b=torch.empty(R * self.n_ele, dtype=torch.float64, device=device) if want_b else None,
             psibar=torch.empty(R, dtype=torch.float64, device=device),
-            E=torch.empty(R, dtype=torch.float64, device=device),
+            # with SRBE_FLAG_ENERGY_PARTS: [total, real, fourier, self, slab] per replica
+            E=torch.empty(R * (5 if self.flags & SRBE_FLAG_ENERGY_PARTS else 1), dtype=torch.float64,
+                          device=device),
             kset=torch.empty(R * P * 3, dtype=torch.int32, device=device) if (want_kset and P) else None,
         )
 

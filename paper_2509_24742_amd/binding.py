@@ -23,6 +23,7 @@ SRBE_FP32 = 1
 SRBE_FLAG_NO_CP = 1
 SRBE_FLAG_KSPACE_ONLY = 2
 SRBE_FLAG_LATTICE_SOLVE = 4
+SRBE_FLAG_ENERGY_PARTS = 8
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsrbe.so")
 
@@ -56,6 +57,7 @@ class SrbeError(RuntimeError):
 _lib = None
 _vp = ctypes.c_void_p
 _batch_size = {}  # handle value -> P, so that mode buffers can be size-checked
+_energy_stride = {}  # handle value -> energy_out values per replica (5 with SRBE_FLAG_ENERGY_PARTS)
 # captured graph value -> the tensors whose device memory it reads and writes at every
 # replay: held here until the graph is destroyed, so that none is freed (and its memory
 # reused) while the graph can still run
@@ -206,11 +208,13 @@ def srbe_create(params, ele_xyz, ele_side, flags=0):
     if code != SRBE_OK:
         raise SrbeError(code, lib().srbe_error_string(code).decode())
     _batch_size[h.value] = int(p.P)
+    _energy_stride[h.value] = 5 if int(p.flags) & SRBE_FLAG_ENERGY_PARTS else 1
     return h
 
 
 def srbe_destroy(h):
     _batch_size.pop(h.value, None)
+    _energy_stride.pop(h.value, None)
     lib().srbe_destroy(h)
 
 
@@ -261,7 +265,7 @@ def _step_args(h, precision, ion_offsets, ion_xyz, ion_q, dpsi, seed, step, Q_ou
         _dev(F_out, torch.float64, 3 * N, "F_out", allow_none=N == 0),
         _dev(b_out, torch.float64, R * n, "b_out", allow_none=True),
         _dev(psibar_out, torch.float64, R, "psibar_out", allow_none=True),
-        _dev(energy_out, torch.float64, R, "energy_out", allow_none=True),
+        _dev(energy_out, torch.float64, R * _energy_stride[h.value], "energy_out", allow_none=True),
         _dev(kset_out, torch.int32, R * P * 3, "kset_out", allow_none=True),
     ]
 
@@ -554,7 +558,8 @@ def srbe_md_graph_create(h, precision, ion_offsets, ion_xyz, vel, ion_q, mass, m
         _dev(seed, torch.uint64, R, "seed", allow_none=True), ctypes.c_uint64(int(first_step)), ctypes.byref(m),
         _dev(Q_out, torch.float64, R * n, "Q_out"), _dev(F_out, torch.float64, 3 * N, "F_out"),
         _dev(psibar_out, torch.float64, R, "psibar_out", allow_none=True),
-        _dev(energy_out, torch.float64, R, "energy_out", allow_none=True), ctypes.byref(gr)))
+        _dev(energy_out, torch.float64, R * _energy_stride[h.value], "energy_out", allow_none=True),
+        ctypes.byref(gr)))
     _graph_refs[gr.value] = (ion_xyz, vel, ion_q, mass, mol, bond, bond_r0, dpsi, seed, Q_out, F_out, psibar_out,
                              energy_out)
     return gr

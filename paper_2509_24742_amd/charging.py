@@ -1,29 +1,33 @@
 """Charging of the paper-shaped cell after a voltage step, by SRBE-driven Langevin dynamics.
 
-    python -m paper_2509_24742_amd.charging [--replicas 32] [--equil 3000] [--steps 9000]
-                                            [--every 500] [--P 50] [--gamma 10] [--precision fp32]
+    python -m paper_2509_24742_amd.charging [--replicas 16] [--equil 20000] [--steps 200000]
+                                            [--every 10000] [--P 50] [--M 13] [--gamma 1]
+                                            [--alpha 1.87] [--rc 1.6] [--precision fp32]
 
 The analogue of the paper's charging curve (Sec. 4, Fig. 2) on the paper-shaped cell
 (3.4 x 3.7 x 12 nm, three honeycomb layers per electrode, 320 three-site cations and 320
-anions; alpha = 3.5/nm, M = 13, P = 50).  Each replica (its own placement and seeds) is
-first run at dpsi = 0 for --equil steps, then dpsi steps to 2 V and the charge on the
-negative electrode, Q_neg(t), is averaged over every window of --every steps.  The
-dynamics are the Euler-Maruyama Langevin update of Sec. 3 at 500 K with dt = 1 fs (the
-paper's) and friction --gamma (mass/ps; strong enough that the thermostat, not the
-random-batch force noise, sets the temperature), positions moved with the updated
-velocity (the symplectic ordering of the update; as printed, r + v^n dt gains energy on
-the stiff contacts, by 1 + (omega dt)^2 per step, and the dynamics run away), driven by
-the SRBE forces plus a
-stand-in short-range force field
-(the paper's is not given): WCA between molecules (eps = 0.05 eV, sigma = 0.3 nm), 9-3
-walls at the innermost electrode layers (eps = 0.2 eV, sigma = 0.45 nm) and harmonic
-bonds (500 eV/nm^2) holding each cation's three sites, with reflecting bounds 1 nm from
-the box ends behind the walls.  Units: nm, ps, e, V, eV; masses
-in amu enter as m / 96.485 (so that eV/nm / mass is nm/ps^2).  Every replica runs in one
-captured dynamics step (srbe_md_graph_create) replayed once per time step.
+anions) with the paper's dynamics parameters: alpha = 1.87/nm, rc = 1.6 nm, M = 13,
+P = 50, 500 K, dt = 1 fs.  Each replica (its own placement and seeds) is first run at
+dpsi = 0 for --equil steps, then dpsi steps to 2 V and the charge on the negative
+electrode, Q_neg(t), is averaged over every window of --every steps.  The dynamics are
+the Euler-Maruyama Langevin update of Sec. 3 with friction --gamma (eV ps/nm^2; 1 gives
+a velocity relaxation time m/gamma of about 1.5 ps for the anion), positions moved with
+the updated velocity (the symplectic ordering of the update; as printed, r + v^n dt gains
+energy on the stiff contacts, by 1 + (omega dt)^2 per step, and the dynamics run away),
+driven by the SRBE forces plus a stand-in short-range force field (the paper's is not
+given): WCA between molecules (eps = 0.05 eV, sigma = 0.3 nm), 9-3 walls at the innermost
+electrode layers (eps = 0.2 eV, sigma = 0.45 nm) and harmonic bonds (500 eV/nm^2) holding
+each cation's three sites, with reflecting bounds 1 nm from the box ends behind the walls.
+The random-batch force noise heats the ions in proportion to dt Var(F*) / gamma; with the
+paper's alpha it stays far below the thermostat's control (the kinetic temperature is
+reported), while with alpha = 3.5/nm at P = 50 the larger Fourier share of the forces
+overheats them at small gamma.  Units: nm, ps, e, V, eV; masses in amu enter as
+m / 96.485 (so that eV/nm / mass is nm/ps^2).  Every replica runs in one captured
+dynamics step (srbe_md_graph_create) replayed once per time step.
 
 Prints, per window, the mean over the replicas of their window-averaged Q_neg and its
-standard error over the replicas.
+standard error over the replicas, the median per-site kinetic temperature (0.79 T for a
+Maxwell distribution) and the count of sites above 100 kT.
 """
 
 import argparse
@@ -39,17 +43,20 @@ KB_EV = 8.617333262e-5
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--replicas", type=int, default=32)
-    ap.add_argument("--equil", type=int, default=3000)
-    ap.add_argument("--steps", type=int, default=9000)
-    ap.add_argument("--every", type=int, default=500)
-    ap.add_argument("--gamma", type=float, default=10.0)
+    ap.add_argument("--replicas", type=int, default=16)
+    ap.add_argument("--equil", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=200000)
+    ap.add_argument("--every", type=int, default=10000)
+    ap.add_argument("--gamma", type=float, default=1.0)
     ap.add_argument("--dt", type=float, default=0.001, help="time step (ps)")
     ap.add_argument("--wca-eps", type=float, default=0.05, help="WCA energy (eV)")
     ap.add_argument("--printed-order", action="store_true",
                     help="move the positions with the old velocity, as the update is printed (unstable on the "
                          "stiff contacts; the default moves them with the new velocity)")
     ap.add_argument("--P", type=int, default=50)
+    ap.add_argument("--M", type=int, default=13, help="deterministic kz modes |m| <= M")
+    ap.add_argument("--alpha", type=float, default=1.87, help="Ewald splitting (1/nm)")
+    ap.add_argument("--rc", type=float, default=1.6, help="real-space cutoff (nm)")
     ap.add_argument("--dpsi", type=float, default=2.0)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     args = ap.parse_args()
@@ -62,7 +69,7 @@ def main():
     R = args.replicas
     wb = wl.replica_batch(R=R)
     top = wl.paper_cell_topology()
-    wp = dict(wb["params"], kspace_tol=1e-16, P=args.P)
+    wp = dict(wb["params"], kspace_tol=1e-16, P=args.P, M=args.M, alpha=args.alpha, rc=args.rc)
     sysm = srbe_amd.System(wp, wb["ele_pos"], wb["ele_side"])
     dev = torch.device("cuda")
     n1 = len(wb["ion_q"][0])
@@ -130,7 +137,8 @@ def main():
     zs = xyz.view(3, N)[2].cpu().numpy()
     vv = v.view(3, N).cpu().numpy()
     kT = float(np.mean(mass[None, :] * vv * vv))  # equipartition: <m v^2> = kT per component
-    print(json.dumps({"replicas": R, "P": args.P, "M": int(wp["M"]), "precision": args.precision,
+    print(json.dumps({"replicas": R, "P": args.P, "M": int(wp["M"]), "alpha": args.alpha, "rc": args.rc,
+                      "precision": args.precision,
                       "gamma": args.gamma, "kinetic_T_K": kT / KB_EV,
                       "ms_per_dynamics_step_all_replicas": e0.elapsed_time(e1) / args.steps,
                       "wall_s": time.time() - t0, "z_range_nm": [float(zs.min()), float(zs.max())]}), flush=True)

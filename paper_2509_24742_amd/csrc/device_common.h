@@ -51,9 +51,10 @@ constexpr int kRunMax = 42;
 // entries past the run's end; the values read there are never used).  Such arrays
 // are allocated with this many extra entries.
 constexpr int kScanPad = 192;
-// Per-replica sums after the charge solve (sum Q Z, sum Q d, sum Q b*) are kept as
-// kRsumParts partial sums, one per block of the pass that writes them, at
-// rsum[r kRsumStride + 4 part + q], and always added in part order.
+// Per-replica sums after the charge solve (slot 0: sum Q Z, 1: sum Q d, 2: sum Q b*,
+// 3: sum Q^2, 4: sum Q bN) are kept as kRsumParts partial sums, one per block of the
+// pass that writes them, at rsum[r kRsumStride + kRsumSlots part + slot], and always
+// added in part order.
 // Resident waves per SIMD of the real-space passes (their register use allows this
 // many; the grids are sized from it).
 constexpr int kRealWavesPerSimd32 = 7;
@@ -62,7 +63,8 @@ constexpr int kRsumParts = 16;
 // Most k-ranges the charge-solve GEMM may be split into (the copy-out adds at most
 // this many partials, all requested at once).
 constexpr int kMaxGemmSplit = 16;
-constexpr int kRsumStride = 4 * kRsumParts;
+constexpr int kRsumSlots = 8;
+constexpr int kRsumStride = kRsumSlots * kRsumParts;
 // Replicas above kEnergyLarge ions have the energy's ion sum q phi taken in partial
 // sums over tiles of kEnergyTile ions by many blocks (added in tile order).
 constexpr int kEnergyLarge = 8192;

@@ -109,7 +109,7 @@ struct StepBufs {
   float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
   float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
   double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)
-  double* rsum;             // R*kRsumStride per-replica sums after the charge solve (kRsumParts partials of 3)
+  double* rsum;             // R*kRsumStride per-replica sums after the charge solve (kRsumParts partials)
   double* phi;              // N real-space ion-ion potential per ion
   double* Fii;              // 3N ion-ion real-space force sums (SoA, input order), before the ke q_i factor
   double* Fie;              // 3N ion-electrode real-space force sums, written for ions of reach cells only
@@ -118,6 +118,10 @@ struct StepBufs {
   LatticeSolve lat;         // lattice charge solve (lat.nx 0: the dense GEMM)
   double* eparts;           // R*etiles partial sums of q phi over tiles of kEnergyTile ions
   int etiles;               // tiles per replica (0: the energy sums the ions itself)
+  int estride;              // energy_out values per replica: 1 (E*) or 5 (E* and its parts)
+  double* epair;            // R*epair_nb partial sums of the electrode-electrode real-space
+                            // energy (parts only), one per block of 256 electrodes
+  int epair_nb;
   // outputs
   double* Q_out;
   double* F_out;
@@ -219,6 +223,7 @@ void launch_langevin(int64_t n, double* xyz, double* vel, const double* F, const
 void launch_electrode_forces(const Geom& g, const StepBufs& b, int fp32, double* F, int64_t* eoff, void* recs,
                              hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
+void launch_ele_pair_energy(const Geom& g, const StepBufs& b, hipStream_t s);
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);

@@ -192,7 +192,8 @@ std::string check_params(const srbe_params* p) {
   if (!(p->kspace_tol > 0.0 && p->kspace_tol < 1.0)) return "kspace_tol must lie in (0, 1)";
   if (p->M < 0 || p->P < 0) return "M and P must be >= 0";
   if (p->P > 2048) return "P must be <= 2048";
-  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY | SRBE_FLAG_LATTICE_SOLVE)) return "unknown flag";
+  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY | SRBE_FLAG_LATTICE_SOLVE | SRBE_FLAG_ENERGY_PARTS))
+    return "unknown flag";
   if (p->reserved != 0) return "reserved must be 0";
   return "";
 }
@@ -769,6 +770,9 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
     b.lat.etc = h->lat_etc;
   }
   b.real = (h->p.flags & SRBE_FLAG_KSPACE_ONLY) ? 0 : 1;
+  b.estride = (h->p.flags & SRBE_FLAG_ENERGY_PARTS) ? 5 : 1;
+  b.epair_nb = (h->n_ele + 255) / 256;
+  b.epair = nullptr;
   b.gemm_depth = tp[SRBE_TUNE_GEMM_DEPTH];
   b.kw = tp[SRBE_TUNE_WAVES];
   b.unroll = tp[SRBE_TUNE_UNROLL];
@@ -863,7 +867,8 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
       {(void**)&b.phi, I((size_t)N1 * sizeof(double))},
       {(void**)&b.Fii, I((size_t)3 * N1 * sizeof(double))},
       {(void**)&b.Fie, I((size_t)3 * N1 * sizeof(double))},
-      {(void**)&b.energy_out, P(a.energy_out ? 0 : (size_t)R * sizeof(double))},
+      {(void**)&b.energy_out, P(a.energy_out ? 0 : (size_t)R * b.estride * sizeof(double))},
+      {(void**)&b.epair, P(b.estride == 5 && b.real && !fixedQ ? (size_t)R * b.epair_nb * sizeof(double) : 0)},
       {(void**)&b.bigsort.count, P(b.bigsort.ntile ? (size_t)R * (g.ncell + 1) * sizeof(int) : 0)},
       {(void**)&b.bigsort.prov, I(big ? (size_t)N1 * sizeof(int) : 0)},
       {(void**)&b.bigsort.tsum, P(b.bigsort.ntile ? (size_t)R * b.bigsort.ntile * 4 * sizeof(double) : 0)},
@@ -956,6 +961,7 @@ int enqueue_step(srbe_system* h, const StepBufs& b, int fp32, int fixedQ, hipStr
     HIP_OK(h, hipEventRecord(h->ev[EV_AUX], s1));
   }
   part(PH_ION_FORCE, s, [&] { launch_ion_force(g, b, fp32, s); });
+  if (b.epair && !fixedQ) launch_ele_pair_energy(g, b, s);
   if (real) HIP_OK(h, hipStreamWaitEvent(s, h->ev[EV_AUX], 0));
   part(PH_ENERGY, s, [&] { launch_final(g, b, fixedQ, s); });
   HIP_OK(h, hipGetLastError());
@@ -2088,6 +2094,7 @@ int srbe_batch_create(srbe_system* const* systems, int32_t n_systems, srbe_batch
   int dev = -1;
   for (int k = 0; k < n_systems; ++k) {
     if (!systems[k]) return SRBE_EINVAL;
+    if (systems[k]->p.flags & SRBE_FLAG_ENERGY_PARTS) return SRBE_EINVAL;  // one energy per replica
     if (k == 0) dev = systems[k]->device;
     else if (systems[k]->device != dev) return SRBE_EINVAL;  // one device per batch
   }

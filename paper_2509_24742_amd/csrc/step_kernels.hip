@@ -1543,12 +1543,12 @@ void launch_cp_gemm(const Geom& g, const StepBufs& b, const double* Sext, hipStr
 // ============================================================ after the charge solve
 // Per replica: copy Q (and psibar) out of the GEMM result (or the fixed charges);
 // the copies of Q the later passes read (FP32 original order and cell-sorted
-// order); sums of Q Z (slab term), d.Q and b*.Q (energy).
+// order); sums of Q Z (slab term), d.Q and b*.Q (energy), and Q^2 and bN.Q (its parts).
 __device__ __forceinline__ double rsum_total(const double* rsum, int r, int q) {
   const double* rs = rsum + (size_t)r * kRsumStride + q;
   double t = rs[0];
 #pragma unroll
-  for (int p = 1; p < kRsumParts; ++p) t += rs[4 * p];
+  for (int p = 1; p < kRsumParts; ++p) t += rs[kRsumSlots * p];
   return t;
 }
 
@@ -1585,11 +1585,12 @@ __device__ __forceinline__ void post_charges_body(const Geom& g, const StepBufs&
   double* __restrict__ psibar = b.psibar_out;
   double* __restrict__ rsum = b.rsum;
   unsigned* status = b.status;
-  __shared__ double sh[3][4];
+  const double* __restrict__ bN = b.real ? b.bN : nullptr;
+  __shared__ double sh[5][4];
   const int R = b.R;
   const int n = g.n_ele;
   const int j0 = (int)((int64_t)n * pc / kRsumParts), j1 = (int)((int64_t)n * (pc + 1) / kRsumParts);
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int bad = 0;
   for (int j = j0 + threadIdx.x; j < j1; j += 256) {
     const int k = ele_iperm[j];
@@ -1602,14 +1603,15 @@ __device__ __forceinline__ void post_charges_body(const Geom& g, const StepBufs&
     v[0] += Qj * ele_xyz[2 * n + j];
     v[1] += Qj * ele_d[j];
     v[2] += Qj * bstar[(size_t)r * n + j];
+    v[3] += Qj * Qj;
+    if (bN) v[4] += Qj * bN[(size_t)r * n + j];
   }
   if (bad) atomicOr(status, ST_NUMERIC);
-  block_sum<256, 3>(v, sh);
+  block_sum<256, 5>(v, sh);
   if (threadIdx.x == 0) {
-    double* rs = rsum + (size_t)r * kRsumStride + 4 * pc;
-    rs[0] = v[0];
-    rs[1] = v[1];
-    rs[2] = v[2];
+    double* rs = rsum + (size_t)r * kRsumStride + kRsumSlots * pc;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) rs[q] = v[q];
     if (psibar && pc == 0) psibar[r] = Q_in ? (double)NAN : solved_q(Qext, ksplit, R, r, n, n);
   }
 }
@@ -1620,6 +1622,51 @@ __global__ __launch_bounds__(256) void k_post_charges(Geom g, StepBufs b, int fi
 
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s) {
   hipLaunchKernelGGL(k_post_charges, dim3(b.R, kRsumParts), dim3(256), 0, s, g, b, fixedQ, fp32);
+}
+
+// Electrode-electrode real-space energy (the Gaussian-Gaussian term of Eq. (13)),
+// 1/2 ke sum_j Q_j sum_{k != j, r < rc} Q_k [erfc(alpha r) - erfc(r / (sqrt 2 eta))] / r,
+// for the energy's parts only (E* itself takes 1/2 Q^T A Q from the solve's identity).
+// Block (x, r): electrodes j of [256 x, 256 x + 256) of replica r, one per thread, over
+// the electrode runs of j's cell (every electrode within rc of the cell), minimum image
+// in x, y, FP64 throughout.  Each block leaves its sum (fixed tree order) in epair.
+__global__ __launch_bounds__(256) void k_ele_pair_energy(Geom g, StepBufs b) {
+  __shared__ double sh[1][4];
+  const int r = blockIdx.y, n = g.n_ele;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  double v[1] = {0.0};
+  if (j < n) {
+    const double* __restrict__ X = b.ele_xyz;
+    const double* __restrict__ Q = b.Q_out + (size_t)r * n;
+    const double xj = X[j], yj = X[n + j], zj = X[2 * n + j];
+    const int c = b.ele_scell[b.ele_iperm[j]];
+    const double a = g.alpha, bg = 1.0 / (sqrt(2.0) * g.eta), rc2 = g.rc * g.rc;
+    double t = 0.0;
+    for (int u = 0; u < kRunMax; ++u) {
+      const int4 run = b.ele_rr[(size_t)kRunMax * c + u];
+      if (run.x < 0) break;
+      for (int e = run.x; e < run.y; ++e) {
+        const int k = b.ele_perm[e];
+        if (k == j) continue;
+        double dx = xj - X[k], dy = yj - X[n + k];
+        const double dz = zj - X[2 * n + k];
+        dx -= g.Lx * rint(dx * g.invLx);
+        dy -= g.Ly * rint(dy * g.invLy);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= rc2) continue;
+        const double rr = sqrt(r2);
+        t += Q[k] * (erfc(a * rr) - erfc(bg * rr)) / rr;
+      }
+    }
+    v[0] = 0.5 * g.ke * Q[j] * t;
+  }
+  block_sum<256, 1>(v, sh);
+  if (threadIdx.x == 0) b.epair[(size_t)r * gridDim.x + blockIdx.x] = v[0];
+}
+
+void launch_ele_pair_energy(const Geom& g, const StepBufs& b, hipStream_t s) {
+  if (!b.epair || g.n_ele == 0) return;
+  hipLaunchKernelGGL(k_ele_pair_energy, dim3(b.epair_nb, b.R), dim3(256), 0, s, g, b);
 }
 
 // ============================================================ ion forces, reciprocal part
@@ -2247,16 +2294,22 @@ void launch_cell_zrange(const Geom& g, const int* cstart, const double* ele_xyz,
 // E* = 1/2 dpsi d.Q - 1/2 b*.Q + c*,  c* = 1/2 sum_i q_i phi_i + 1/2 sum_k w_k |S1_k|^2
 //      - ke alpha/sqrt(pi) sum q^2 + ke (2 pi / V) (sum q z)^2
 // (1/2 Q^T A Q - b*^T Q + c* at the constrained charges, where Q^T A Q = b*.Q + dpsi d.Q).
+// Its parts (estride 5), as U_c is split in Eqs. (13), (16), (17):
+//   real  = 1/2 q.phi + Q.bN + (electrode-electrode real space, epair)
+//   self  = ke [(1/(sqrt(2 pi) eta) - alpha/sqrt(pi)) sum Q^2 - alpha/sqrt(pi) sum q^2]
+//   slab  = ke (2 pi / V) (sum q z + sum Q Z)^2
+//   fourier = E* - real - self - slab (the only part the sample changes).
 __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBufs& b, int fixedQ) {
-  __shared__ double sh[2][4];
+  __shared__ double sh[3][4];
   const int64_t* __restrict__ off = b.off;
   const double* __restrict__ ion_q = b.ion_q;
   const double* __restrict__ phi = b.phi;
   const double* __restrict__ scal = b.scal;
   const double* __restrict__ rsum = b.rsum;
-  double v[2] = {0.0, 0.0};
+  double v[3] = {0.0, 0.0, 0.0};
+  const int es = b.estride;
   if (fixedQ) {  // no energy without the charge solve: nothing to sum
-    if (threadIdx.x == 0) b.energy_out[r] = (double)NAN;
+    if (threadIdx.x < es) b.energy_out[(size_t)es * r + threadIdx.x] = (double)NAN;
     return;
   }
   if (b.real) {  // the ion-ion real-space energy (left out in k-space-only steps)
@@ -2271,13 +2324,27 @@ __device__ __forceinline__ void energy_block(const Geom& g, int r, const StepBuf
     const double2 s = b.S1[(size_t)r * g.K + k];
     v[1] += b.w[(size_t)r * g.K + k] * (s.x * s.x + s.y * s.y);
   }
-  block_sum<256, 2>(v, sh);
+  if (b.epair)
+    for (int t = threadIdx.x; t < b.epair_nb; t += 256) v[2] += b.epair[(size_t)r * b.epair_nb + t];
+  block_sum<256, 3>(v, sh);
   if (threadIdx.x == 0) {
-    const double c = 0.5 * v[0] + 0.5 * v[1] - g.ke * g.alpha * INV_SQRT_PI * scal[4 * r + 3] +
-                     g.ke * (2.0 * M_PI / g.V) * scal[4 * r + 2] * scal[4 * r + 2];
+    const double self_i = -g.ke * g.alpha * INV_SQRT_PI * scal[4 * r + 3];
+    const double c = 0.5 * v[0] + 0.5 * v[1] + self_i + g.ke * (2.0 * M_PI / g.V) * scal[4 * r + 2] * scal[4 * r + 2];
     const double E = 0.5 * b.dpsi[r] * rsum_total(rsum, r, 1) - 0.5 * rsum_total(rsum, r, 2) + c;
     if (!isfinite(E)) atomicOr(b.status, ST_NUMERIC);
-    b.energy_out[r] = E;
+    double* out = b.energy_out + (size_t)es * r;
+    out[0] = E;
+    if (es == 5) {
+      const double real = b.real ? 0.5 * v[0] + rsum_total(rsum, r, 4) + v[2] : 0.0;
+      const double cg = 1.0 / (sqrt(2.0 * M_PI) * g.eta) - g.alpha * INV_SQRT_PI;
+      const double self = g.ke * cg * rsum_total(rsum, r, 3) + self_i;
+      const double Mz = scal[4 * r + 2] + rsum_total(rsum, r, 0);
+      const double slab = g.ke * (2.0 * M_PI / g.V) * Mz * Mz;
+      out[1] = real;
+      out[2] = E - real - self - slab;
+      out[3] = self;
+      out[4] = slab;
+    }
   }
 }
 

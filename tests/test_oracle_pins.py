@@ -519,6 +519,35 @@ def test_srbe_energy_expectation_over_every_mode_is_the_full_ewald_energy():
     assert abs(expect_c - c) < 1e-13 * abs(c)
 
 
+def test_srbe_energy_parts():
+    # The split of E* into real, Fourier, self and slab parts, computed from each part's own
+    # definition: (1) the parts add up to E* = 1/2 Q^T A Q - b*^T Q + c* for any sample;
+    # (2) the SRBE leaves the real, self and slab parts of U_c (Eqs. (13), (17)) untouched,
+    # so they equal the complete energy's own parts exactly, and (3) the Fourier part's
+    # expectation over every mode (as in the pin above) is the complete Fourier energy
+    # of Eq. (16).
+    p, ion, q, ele, Q = small_cell()
+    modes = ewald.enumerate_modes(p)
+    A = ewald.electrode_matrix(p, ele, modes)
+    full = ewald.energy(p, ion, q, ele, Q, modes)
+    mv = modes[sampler.valid(p, modes)]
+    prob = np.exp(-np.sum(ewald.kvectors(p, mv) ** 2, axis=1) / (4 * p.alpha ** 2)) / srbe.normaliser_G(p)
+    expect = 0.0
+    for k, pr in zip(mv, prob):
+        parts = srbe.srbe_energy_parts(p, k[None, :], ion, q, ele, Q, modes)
+        expect += pr * parts["fourier"]
+    empty = srbe.srbe_energy_parts(p, np.zeros((0, 3)), ion, q, ele, Q, modes)
+    expect += (1.0 - prob.sum()) * empty["fourier"]
+    assert abs(expect - full["fourier"]) < 1e-13 * abs(full["total"])
+    kset = np.array([mv[3], mv[7], mv[3]])
+    parts = srbe.srbe_energy_parts(p, kset, ion, q, ele, Q, modes)
+    E = srbe.srbe_energy(p, A, kset, ion, q, ele, Q)
+    assert abs(parts["total"] - E) < 1e-13 * abs(E)
+    for name in ("real", "self", "slab"):
+        assert abs(parts[name] - full[name]) < 1e-13 * abs(full["total"]), name
+        assert abs(full[name]) > 1e-4 * abs(full["total"]), name  # each part is really there
+
+
 def test_srbe_energy_sample_mean_is_the_full_ewald_energy():
     # The same statement through the sampler itself: the mean of E* over 2000 batches drawn
     # by the Metropolis chain (fixed Q) equals the complete energy within 5 standard errors.
