@@ -220,6 +220,8 @@ def main():
     log(f"FP32 batch (graph): {ms_fp32 * 1e3:.1f} us/step")
     ms_fp32_eager, out = timed(srbe_amd.SRBE_FP32, off, xyz, q, dpsi, seeds)
     log(f"FP32 batch (eager): {ms_fp32_eager * 1e3:.1f} us/step")
+    ms_bf16 = timed_graph(srbe_amd.SRBE_BF16, off, xyz, q, dpsi, seeds)
+    log(f"BF16 hi/lo structure-factor variant (graph): {ms_bf16 * 1e3:.1f} us/step")
 
     # ---- per-phase durations (HIP events recorded by the library on the stream that runs
     # each phase; every phase but the last is launched PROF_REPS times between its events,
@@ -345,6 +347,13 @@ def main():
                "b": o["b"].cpu().numpy()}
         side, refs = cpu_side(wb, wp, acc, R, sizes, n_ele, K)
         result.update(side)
+        # the BF16 hi/lo structure-factor variant on the same step: an error report
+        ob = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_BF16, want_kset=False)
+        torch.cuda.synchronize()
+        accb = {"off": off, "F": ob["F"].cpu().numpy(), "Q": ob["Q"].cpu().numpy(), "E": ob["E"].cpu().numpy(),
+                "b": ob["b"].cpu().numpy()}
+        result["bf16_error_vs_fp64_oracle"] = dict(errors_vs_oracle(refs, accb, n_ele),
+                                                   ms_per_step=ms_bf16, variant=BF16_VARIANT)
         result["fp32_error_vs_fp64_oracle"].update(error_split(srbe_amd, sysm, wb, wp, refs, off, xyz, q, dpsi,
                                                                seeds, n_ele))
     print(json.dumps(result), flush=True)
@@ -352,6 +361,9 @@ def main():
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
+BF16_VARIANT = ("SRBE_BF16: the FP32 step with each product q cos, q sin of the structure factors formed from "
+                "BF16 hi/lo halves (q_hi c_hi + q_hi c_lo + q_lo c_hi, FP32 accumulation), as BF16 matrix cores "
+                "would; replicas at their own constant-potential charges, step 0")
 
 
 def _rel_rms(a, b):
@@ -668,20 +680,52 @@ def cpu_side(wb, wp, acc, R, sizes, n_ele, K):
     solver = cp.Solver(ewald.electrode_matrix(p, wb["ele_pos"]))
     oracle_setup_s = time.time() - t0
     log(f"oracle A in {oracle_setup_s:.1f} s; timing oracle steps")
-    ru0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.time()
-    refs = []
-    for r in range(R):
-        ks, _ = sampler.draw_kset(p, 2100 + r, 0, 0)
-        refs.append(srbe.srbe_step(p, solver, ks, wb["ion_pos"][r], wb["ion_q"][r], wb["ele_pos"], wb["ele_side"],
-                                   float(wb["dpsi"][r])))
-        if time.time() - t0 > 15.0:
-            break
-    wall = time.time() - t0
-    ru1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu = (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+    def oracle_steps(limit_s, count=None):
+        ru0 = resource.getrusage(resource.RUSAGE_SELF)
+        t0 = time.time()
+        out = []
+        for r in range(R if count is None else count):
+            ks, _ = sampler.draw_kset(p, 2100 + r, 0, 0)
+            out.append(srbe.srbe_step(p, solver, ks, wb["ion_pos"][r], wb["ion_q"][r], wb["ele_pos"],
+                                      wb["ele_side"], float(wb["dpsi"][r])))
+            if time.time() - t0 > limit_s:
+                break
+        wall = time.time() - t0
+        ru1 = resource.getrusage(resource.RUSAGE_SELF)
+        return out, wall, (ru1.ru_utime - ru0.ru_utime) + (ru1.ru_stime - ru0.ru_stime)
+
+    refs, wall, cpu = oracle_steps(15.0)
     nsample = len(refs)
     pairs = sum(sizes[r] + n_ele for r in range(nsample)) * K
+    # the same replicas again with every thread pool of the process limited to one thread
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        refs1, wall1, cpu1 = oracle_steps(30.0, count=nsample)
+    pairs1 = sum(sizes[r] + n_ele for r in range(len(refs1))) * K
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    errs = errors_vs_oracle(refs, acc, n_ele)
+    return {
+        "fp32_error_vs_fp64_oracle": dict(errs, target_force_rel_rms=1e-5),
+        "cpu_baseline": {"value": pairs / wall, "unit": "pairs/s", "cores": max(1, round(cpu / wall)),
+                         "kind": "oracle",
+                         "sample": f"FP64 numpy oracle SRBE step (sample, b*, CP solve, forces, energy) on "
+                                   f"{nsample} of the {R} replicas, one step each (about 15 s); A built once "
+                                   f"beforehand ({oracle_setup_s:.1f} s, not timed); cpu_time/wall = "
+                                   f"{cpu / wall:.2f}; host threads available: {os.cpu_count()}",
+                         "cpu_model": model, "host_threads": os.cpu_count(),
+                         "one_thread": {"value": pairs1 / wall1, "unit": "pairs/s", "replicas": len(refs1),
+                                        "cpu_time_over_wall": cpu1 / wall1}},
+        "oracle_setup_s": oracle_setup_s,
+    }, refs
+
+
+def errors_vs_oracle(refs, acc, n_ele):
+    """Relative errors of one GPU step (host copies in acc) against the oracle's steps refs."""
     off = acc["off"]
     N = int(off[-1])
     F = acc["F"].reshape(3, N)
@@ -697,19 +741,9 @@ def cpu_side(wb, wp, acc, R, sizes, n_ele, K):
         errQ.append(np.linalg.norm(Qg - ref["Q"]) / np.linalg.norm(ref["Q"]))
         neut.append(abs(np.sum(Qg)) / np.sum(np.abs(Qg)))
         errE.append(abs(acc["E"][r] - ref["E"]) / abs(ref["E"]))
-    return {
-        "fp32_error_vs_fp64_oracle": {"force_rel_rms_max": max(errF), "force_max_ion_over_rms_max": max(errFmax),
-                                      "b_rel_rms_max": max(errb), "charge_rel_rms_max": max(errQ),
-                                      "charge_sum_over_l1_max": max(neut), "energy_rel_max": max(errE),
-                                      "replicas_checked": nsample, "target_force_rel_rms": 1e-5},
-        "cpu_baseline": {"value": pairs / wall, "unit": "pairs/s", "cores": max(1, round(cpu / wall)),
-                         "kind": "oracle",
-                         "sample": f"FP64 numpy oracle SRBE step (sample, b*, CP solve, forces, energy) on "
-                                   f"{nsample} of the {R} replicas, one step each (about 15 s); A built once "
-                                   f"beforehand ({oracle_setup_s:.1f} s, not timed); cpu_time/wall = "
-                                   f"{cpu / wall:.2f}; host threads available: {os.cpu_count()}"},
-        "oracle_setup_s": oracle_setup_s,
-    }, refs
+    return {"force_rel_rms_max": max(errF), "force_max_ion_over_rms_max": max(errFmax), "b_rel_rms_max": max(errb),
+            "charge_rel_rms_max": max(errQ), "charge_sum_over_l1_max": max(neut), "energy_rel_max": max(errE),
+            "replicas_checked": len(refs)}
 
 
 def error_split(srbe_amd, sysm, wb, wp, refs, off, xyz, q, dpsi, seeds, n_ele, nsplit=8):

@@ -53,6 +53,11 @@ extern "C" {
 #define SRBE_FP64 0 /* every pass in FP64                                              */
 #define SRBE_FP32 1 /* structure factors, potentials and forces in FP32 with exact
                        integer phases and FP64 carries; CP solve and energy in FP64   */
+#define SRBE_BF16 2 /* SRBE_FP32 with every product q cos, q sin of the structure
+                       factors (Eq. (15)) formed from BF16 hi/lo halves, q_hi c_hi +
+                       q_hi c_lo + q_lo c_hi with FP32 accumulation: the arithmetic of a
+                       BF16 matrix-core structure factor, for an error report (single
+                       systems and srbe_step / srbe_graph_create only)                */
 
 #define SRBE_FLAG_NO_CP 1 /* skip the electrode matrix: only fixed-charge steps      */
 #define SRBE_FLAG_KSPACE_ONLY 2 /* leave out the real-space erfc terms (see below)   */
@@ -126,7 +131,7 @@ const char* srbe_error_string(int code);
  * (Algorithm 1: sample P modes, compute b* by Eq. (24), update Q by Eq. (10),
  * compute the forces of Eq. (25) and the real-space forces; no integration).
  *
- * precision   SRBE_FP64 or SRBE_FP32.
+ * precision   SRBE_FP64, SRBE_FP32 or SRBE_BF16.
  * n_rep       number of replicas, 1 <= n_rep <= 65535.
  * ion_offsets host, n_rep+1 int64, CSR offsets: replica r owns ions
  *             [ion_offsets[r], ion_offsets[r+1]); ion_offsets[0] == 0.

@@ -20,6 +20,7 @@ SRBE_EHIP = -6
 SRBE_ENUMERIC = -7
 SRBE_FP64 = 0
 SRBE_FP32 = 1
+SRBE_BF16 = 2
 SRBE_FLAG_NO_CP = 1
 SRBE_FLAG_KSPACE_ONLY = 2
 SRBE_FLAG_LATTICE_SOLVE = 4

@@ -106,6 +106,7 @@ struct StepBufs {
   int esplit;               // electrode-potential real-space pass: waves per electrode chunk (1, 2, 4)
   int gemm_depth;           // charge-solve GEMM: contraction block of 16 gemm_depth (1 or 2)
   int real;                 // 1: the real-space terms are part of the step; 0: k-space only
+  int bf16;                 // FP32 path with the structure factors' products from BF16 hi/lo halves
   float* Qf;                // R*n_ele FP32 copy of Q, original order (FP32 path)
   float* Qsf;               // R*n_ele FP32 Q in sorted electrode order (FP32 path)
   double* Qsd;              // R*n_ele FP64 Q in sorted electrode order (FP64 path)

@@ -648,7 +648,8 @@ struct StepArgs {
 
 // Precision and batch shape (host offsets); max_nrep: the largest replica's ion count.
 int check_shape(srbe_system* h, int precision, int n_rep, const int64_t* ion_offsets, int64_t& max_nrep) {
-  if (precision != SRBE_FP64 && precision != SRBE_FP32) return set_err(h, SRBE_EINVAL, "unknown precision");
+  if (precision != SRBE_FP64 && precision != SRBE_FP32 && precision != SRBE_BF16)
+    return set_err(h, SRBE_EINVAL, "unknown precision");
   if (n_rep <= 0 || !ion_offsets) return set_err(h, SRBE_EINVAL, "n_rep must be positive and offsets given");
   if (n_rep > 65535) return set_err(h, SRBE_EINVAL, "n_rep must be <= 65535");
   if (ion_offsets[0] != 0) return set_err(h, SRBE_EINVAL, "ion_offsets[0] must be 0");
@@ -679,7 +680,7 @@ int check_step(srbe_system* h, const StepArgs& a, int64_t& max_nrep) {
 // kRealWavesPerSimd resident per SIMD) once, so that no second, mostly empty round of
 // blocks follows the first.
 void default_tuning(const srbe_system* h, int precision, int R, int64_t max_nrep, int* p) {
-  const int64_t slots = (int64_t)h->ncu * 4 * (precision == SRBE_FP32 ? kRealWavesPerSimd32 : kRealWavesPerSimd64);
+  const int64_t slots = (int64_t)h->ncu * 4 * (precision != SRBE_FP64 ? kRealWavesPerSimd32 : kRealWavesPerSimd64);
   p[SRBE_TUNE_SF_BLOCKS] = 1024;
   p[SRBE_TUNE_WAVES] = 4;
   p[SRBE_TUNE_UNROLL] = 4;
@@ -770,6 +771,7 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
     b.lat.etc = h->lat_etc;
   }
   b.real = (h->p.flags & SRBE_FLAG_KSPACE_ONLY) ? 0 : 1;
+  b.bf16 = a.precision == SRBE_BF16 ? 1 : 0;
   b.estride = (h->p.flags & SRBE_FLAG_ENERGY_PARTS) ? 5 : 1;
   b.epair_nb = (h->n_ele + 255) / 256;
   b.epair = nullptr;
@@ -830,7 +832,7 @@ size_t ws_layout(const srbe_system* h, const StepArgs& a, StepBufs& b, char* bas
   const Geom& g = h->g;
   const int R = a.n_rep, K = std::max(g.K, 1), n = h->n_ele;
   const int64_t N1 = std::max<int64_t>(n_ions >= 0 ? n_ions : a.ion_offsets[R], 1);
-  const bool fp32 = a.precision == SRBE_FP32, fixedQ = a.Q_in != nullptr;
+  const bool fp32 = a.precision != SRBE_FP64, fixedQ = a.Q_in != nullptr;
   const bool ion = parts & 1, rep = parts & 2;
   const bool big = b.bigsort.ntile != 0 || any_big_sort;
   const int nch = std::max(b.nchunk_ion, b.nchunk_ele);
@@ -1662,11 +1664,11 @@ int srbe_step(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
     h->off_cache.assign(ion_offsets, ion_offsets + R + 1);
   }
   b.off = h->off_dev;
-  rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, s);
+  rc = enqueue_step(h, b, precision != SRBE_FP64, Q_in != nullptr, s);
   if (rc == SRBE_OK) {
     h->last = b;
     h->last_valid = true;
-    h->last_fp32 = precision == SRBE_FP32;
+    h->last_fp32 = precision != SRBE_FP64;
   }
   return rc;
 }
@@ -1720,7 +1722,7 @@ int srbe_step_noalloc(srbe_system* h, int32_t precision, int32_t n_rep, const in
   b.off = off_dev;
   const bool prof = h->prof;
   h->prof = false;  // phase timing would create events: off for this call
-  rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, s);
+  rc = enqueue_step(h, b, precision != SRBE_FP64, Q_in != nullptr, s);
   h->prof = prof;
   return rc;
 }
@@ -1814,7 +1816,7 @@ int graph_create_impl(srbe_system* h, const StepArgs& a, const MdTail* md, srbe_
     return fail(SRBE_EHIP);
   }
   h->capturing = true;
-  rc = enqueue_step(h, b, precision == SRBE_FP32, Q_in != nullptr, h->cap);
+  rc = enqueue_step(h, b, precision != SRBE_FP64, Q_in != nullptr, h->cap);
   if (rc == SRBE_OK && md) {
     launch_ff_forces(h->g, b, md->ff, md->mol, md->bond, md->bond_r0, a.F_out, nullptr, h->cap);
     launch_langevin(b.N, md->xyz, md->vel, a.F_out, md->mass, md->gamma, md->beta, md->dt, h->p.Lx, h->p.Ly, md->zlo,
@@ -1997,7 +1999,8 @@ int srbe_tune(srbe_system* h, int32_t precision, int32_t n_rep, const int64_t* i
   hipError_t e = hipMalloc(&Q, std::max<size_t>(1, (size_t)n_rep * n) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&F, std::max<int64_t>(1, 3 * N) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&psi, (size_t)n_rep * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&E, (size_t)n_rep * sizeof(double));
+  const size_t estride = (h->p.flags & SRBE_FLAG_ENERGY_PARTS) ? 5 : 1;
+  if (e == hipSuccess) e = hipMalloc(&E, (size_t)n_rep * estride * sizeof(double));
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) {

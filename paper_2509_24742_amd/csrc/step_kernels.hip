@@ -741,7 +741,38 @@ __device__ __forceinline__ double2 sf64_sum(const double4* __restrict__ pts, con
 // FP32: exact integer phase m.u mod 2^32 (u = 32-bit fixed-point fractions), the
 // hardware sin/cos of the phase in revolutions, FP32 sums over blocks of 64
 // particles carried in FP64.
-template <bool ION>
+//
+// BF16 (the hi/lo variant, an error report): each factor x of a product q cos, q sin
+// is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi), and the product is taken as
+// q_hi c_hi + q_hi c_lo + q_lo c_hi with FP32 accumulation -- the arithmetic of a
+// structure factor on BF16 matrix cores (three BF16 products of hi/lo halves, FP32
+// accumulate; each BF16 x BF16 product is exact in FP32), carried out on the VALU.
+__device__ __forceinline__ float bf16_round(float x) {
+  // round to nearest even at 8 mantissa bits (finite x)
+  const uint32_t u = __float_as_uint(x);
+  return __uint_as_float((u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u);
+}
+
+template <bool BF16>
+__device__ __forceinline__ void sf32_term(float qj, float x, float& ar, float& ai) {
+  const float c = __builtin_amdgcn_cosf(x), s = __builtin_amdgcn_sinf(x);
+  if constexpr (BF16) {
+    const float qh = bf16_round(qj), ql = bf16_round(qj - qh);
+    const float ch = bf16_round(c), cl = bf16_round(c - ch);
+    const float sh = bf16_round(s), sl = bf16_round(s - sh);
+    ar = fmaf(qh, ch, ar);
+    ar = fmaf(qh, cl, ar);
+    ar = fmaf(ql, ch, ar);
+    ai = fmaf(qh, sh, ai);
+    ai = fmaf(qh, sl, ai);
+    ai = fmaf(ql, sh, ai);
+  } else {
+    ar = fmaf(qj, c, ar);
+    ai = fmaf(qj, s, ai);
+  }
+}
+
+template <bool ION, bool BF16 = false>
 __device__ __forceinline__ double2 sf32_sum(const uint4* __restrict__ pts, const float* __restrict__ qq, int4 m,
                                             int j0, int j1) {
   const uint32_t mx = (uint32_t)m.x, my = (uint32_t)m.y, mz = (uint32_t)m.z;
@@ -756,18 +787,14 @@ __device__ __forceinline__ double2 sf32_sum(const uint4* __restrict__ pts, const
         const uint4 p = pts[j + u];
         const float qj = ION ? __uint_as_float(p.w) : qq[j + u];
         const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
-        const float x = (float)(int32_t)ph * 0x1.0p-32f;
-        ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
-        ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
+        sf32_term<BF16>(qj, (float)(int32_t)ph * 0x1.0p-32f, ar, ai);
       }
     }
     for (; j < je; ++j) {
       const uint4 p = pts[j];
       const float qj = ION ? __uint_as_float(p.w) : qq[j];
       const uint32_t ph = mx * p.x + my * p.y + mz * p.z;
-      const float x = (float)(int32_t)ph * 0x1.0p-32f;
-      ar = fmaf(qj, __builtin_amdgcn_cosf(x), ar);
-      ai = fmaf(qj, __builtin_amdgcn_sinf(x), ai);
+      sf32_term<BF16>(qj, (float)(int32_t)ph * 0x1.0p-32f, ar, ai);
     }
     dr += (double)ar;
     di += (double)ai;
@@ -792,7 +819,7 @@ __device__ __forceinline__ void sf64_block(const Geom& g, const int64_t* __restr
   if (k < g.K) part[((size_t)r * nchunk + ch) * g.K + k] = sf64_sum<ION>(pts, qq, modes[(size_t)r * g.K + k], j0, j1);
 }
 
-template <bool ION>
+template <bool ION, bool BF16 = false>
 __device__ __forceinline__ void sf32_block(const Geom& g, const int64_t* __restrict__ off,
                                            const uint4* __restrict__ pts, const float* __restrict__ qe,
                                            const int4* __restrict__ modes, double2* __restrict__ part, int nchunk,
@@ -804,7 +831,8 @@ __device__ __forceinline__ void sf32_block(const Geom& g, const int64_t* __restr
   const int j0 = b + ch * chunk;
   const int j1 = min(e, j0 + chunk);
   const float* qq = ION ? nullptr : qe + (size_t)r * g.n_ele;
-  if (k < g.K) part[((size_t)r * nchunk + ch) * g.K + k] = sf32_sum<ION>(pts, qq, modes[(size_t)r * g.K + k], j0, j1);
+  if (k < g.K)
+    part[((size_t)r * nchunk + ch) * g.K + k] = sf32_sum<ION, BF16>(pts, qq, modes[(size_t)r * g.K + k], j0, j1);
 }
 
 // Partial-sum block lb of stage 1 (ions, ION) or 2 (electrodes with the new charges),
@@ -814,10 +842,17 @@ __device__ __forceinline__ void sf_block(const Geom& g, const StepBufs& b, int l
   const int nchunk = ION ? b.nchunk_ion : b.nchunk_ele;
   const int tile = lb % b.ktiles, ch = (lb / b.ktiles) % nchunk, r = lb / (b.ktiles * nchunk);
   if constexpr (FP32) {
-    if constexpr (ION)
-      sf32_block<true>(g, b.off, b.ion_fx, nullptr, b.modes, b.part, nchunk, tile, ch, r);
-    else
-      sf32_block<false>(g, b.off, b.ele_fx, b.Qf, b.modes, b.part, nchunk, tile, ch, r);
+    if (b.bf16) {
+      if constexpr (ION)
+        sf32_block<true, true>(g, b.off, b.ion_fx, nullptr, b.modes, b.part, nchunk, tile, ch, r);
+      else
+        sf32_block<false, true>(g, b.off, b.ele_fx, b.Qf, b.modes, b.part, nchunk, tile, ch, r);
+    } else {
+      if constexpr (ION)
+        sf32_block<true>(g, b.off, b.ion_fx, nullptr, b.modes, b.part, nchunk, tile, ch, r);
+      else
+        sf32_block<false>(g, b.off, b.ele_fx, b.Qf, b.modes, b.part, nchunk, tile, ch, r);
+    }
   } else {
     if constexpr (ION)
       sf64_block<true>(g, b.off, b.ion_d4, nullptr, b.modes, b.part, nchunk, tile, ch, r);
