@@ -282,6 +282,31 @@ void srbe_batch_graph_destroy(srbe_batch_graph* g);
 int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void* stream);
 
 /*
+ * srbe_virial -- the electrostatic virial tensor W = -dE/d(epsilon) of the last
+ * srbe_step's estimator on this handle, for the pressure tensor
+ * P = (sum_i m_i v_i v_i^T + W + W_short-range) / V (kinetic and short-range parts are the
+ * caller's).  The paper gives forces (Eqs. (21), (25)) but no virial; this is the
+ * derivative under an affine strain of every position and of the box, at fixed
+ * charges, with the kernels' alpha and Gaussian width fixed:
+ *   - Fourier part: over the step's modes and weights (deterministic kz modes and the
+ *     sample, as in Eq. (24)), sum 1/2 w |S|^2 [I - 2 (1 + k^2/(4 alpha^2)) k k^T / k^2]
+ *     with S = S1 + S2 of the step (unbiased for the complete Fourier virial);
+ *   - real part (Eq. (13)): -sum over pairs within rc of q_a q_b K'(r) r r^T / r over
+ *     ion-ion, ion-Gaussian and Gaussian-Gaussian pairs (none with KSPACE_ONLY);
+ *   - slab term of Eq. (17): (2 pi / V) M_z^2 diag(1, 1, -1), M_z = sum q z + sum Q Z.
+ * FP64 throughout, in both precisions (the Fourier part from the step's FP64 S).
+ * n_rep       the replica count of that step (checked).
+ * W_out       device, 6*n_rep doubles: [xx, yy, zz, xy, xz, yz] per replica, times
+ *             coulomb_k (energy units).
+ * Must follow an srbe_step (eagerly, not a graph replay) on the same stream, whose
+ * input and Q_out buffers are still valid, with no other srbe_step on the handle in
+ * between.  Allocates and frees scratch, and blocks until done.
+ * Errors: SRBE_EINVAL (no preceding step, another n_rep, NULL output), SRBE_ENOMEM,
+ * SRBE_EHIP.
+ */
+int srbe_virial(srbe_system* h, int32_t n_rep, double* W_out, void* stream);
+
+/*
  * srbe_langevin_update -- one Euler-Maruyama step of the Langevin thermostat (Sec. 3)
  * for n ions, in place, from the forces of a step:
  *   r <- r + v dt;  v <- v + (F - gamma v) dt / m + sqrt(2 gamma / beta) dW / m,

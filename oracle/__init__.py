@@ -21,6 +21,8 @@ constant-potential simulation of electrochemical systems" (arXiv 2509.24742):
 * ``sampler`` -- the Metropolis sampler of Sec. 3 (Eqs. (28)-(29)) driven by
                  ``philox``, a counter-based generator written from its published
                  definition;
+* ``virial``  -- the electrostatic virial (pressure) tensor of the complete energy
+                 and its SRBE estimate (a reading: the paper gives none);
 * ``ewald2d`` -- the exact quasi-2D Ewald sum (Eq. (14), k_z integral done in
                  closed form) and brute-force 2-D image sums, used only as pins.
 
@@ -31,4 +33,4 @@ Readings of places where the paper is silent or inconsistent are listed in the
 functions that take them; each one is pinned by a test in ``tests/``.
 """
 
-from . import philox, ewald, cp, srbe, sampler, ewald2d  # noqa: F401
+from . import philox, ewald, cp, srbe, sampler, ewald2d, virial  # noqa: F401

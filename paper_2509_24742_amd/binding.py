@@ -118,6 +118,8 @@ def lib():
     L.srbe_set_tuning.restype = ctypes.c_int
     L.srbe_electrode_forces.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
     L.srbe_electrode_forces.restype = ctypes.c_int
+    L.srbe_virial.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+    L.srbe_virial.restype = ctypes.c_int
     L.srbe_langevin_update.argtypes = [ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, _vp]
@@ -159,7 +161,7 @@ EXPORTED = ["srbe_create", "srbe_destroy", "srbe_last_error", "srbe_error_string
             "srbe_langevin_update", "srbe_step_noalloc", "srbe_batch_create", "srbe_batch_destroy",
             "srbe_batch_last_error", "srbe_batch_sync_status", "srbe_batch_step", "srbe_batch_graph_create",
             "srbe_batch_graph_launch", "srbe_batch_graph_set_step", "srbe_batch_graph_destroy", "srbe_ff_forces",
-            "srbe_md_graph_create"]
+            "srbe_md_graph_create", "srbe_virial"]
 SRBE_N_PHASES = 16
 
 
@@ -358,6 +360,14 @@ def srbe_electrode_forces(h, n_rep, F_ele_out, stream=None):
     import torch
     ptr = _dev(F_ele_out, torch.float64, 3 * int(n_rep) * srbe_n_ele(h), "F_ele_out")
     _check(h, lib().srbe_electrode_forces(h, int(n_rep), ptr, _stream(stream)))
+
+
+def srbe_virial(h, n_rep, W_out, stream=None):
+    """Electrostatic virial tensor of the last srbe_step on h (n_rep replicas): W_out, device float64
+    tensor of 6 * n_rep, [xx, yy, zz, xy, xz, yz] per replica."""
+    import torch
+    ptr = _dev(W_out, torch.float64, 6 * int(n_rep), "W_out")
+    _check(h, lib().srbe_virial(h, int(n_rep), ptr, _stream(stream)))
 
 
 def srbe_langevin_update(xyz, vel, F, mass, gamma, beta, dt, Lx, Ly, zlo, zhi, seed, step, stream=None):

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsrbe.so")
-SOURCES = ["step_kernels.hip", "setup_kernels.hip", "lattice_solve.hip", "electrode_forces.hip", "langevin.hip", "forcefield.hip", "srbe_api.hip"]
+SOURCES = ["step_kernels.hip", "setup_kernels.hip", "lattice_solve.hip", "electrode_forces.hip", "langevin.hip", "forcefield.hip", "virial.hip", "srbe_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Werror=return-type", "-Wno-unused-function",

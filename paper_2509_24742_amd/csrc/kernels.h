@@ -225,6 +225,8 @@ void launch_electrode_forces(const Geom& g, const StepBufs& b, int fp32, double*
                              hipStream_t s);
 void launch_post_charges(const Geom& g, const StepBufs& b, int fixedQ, int fp32, hipStream_t s);
 void launch_ele_pair_energy(const Geom& g, const StepBufs& b, hipStream_t s);
+size_t virial_scratch_doubles(const Geom& g, const StepBufs& b);
+void launch_virial(const Geom& g, const StepBufs& b, double* scratch, double* W, hipStream_t s);
 void launch_stage_ele(const Geom& g, const StepBufs& b, int fp32, int parts, hipStream_t s);
 void launch_ion_force(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);
 void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s);

@@ -1762,6 +1762,27 @@ int srbe_electrode_forces(srbe_system* h, int32_t n_rep, double* F_ele_out, void
   return SRBE_OK;
 }
 
+int srbe_virial(srbe_system* h, int32_t n_rep, double* W_out, void* stream) {
+  if (!h) return SRBE_EINVAL;
+  if (!W_out) return set_err(h, SRBE_EINVAL, "W_out is NULL");
+  if (!h->last_valid) return set_err(h, SRBE_EINVAL, "srbe_virial: no preceding srbe_step on this handle");
+  if (n_rep != h->last.R) return set_err(h, SRBE_EINVAL, "srbe_virial: n_rep differs from the last step's");
+  hipStream_t s = (hipStream_t)stream;
+  const StepBufs& b = h->last;
+  double* scratch = nullptr;
+  hipError_t e = hipMalloc((void**)&scratch, std::max<size_t>(1, virial_scratch_doubles(h->g, b)) * sizeof(double));
+  if (e == hipSuccess) {
+    launch_virial(h->g, b, scratch, W_out, s);
+    e = hipGetLastError();
+  }
+  const hipError_t e2 = hipStreamSynchronize(s);  // the scratch is freed below
+  if (scratch) (void)hipFree(scratch);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess)
+    return set_err(h, e == hipErrorOutOfMemory ? SRBE_ENOMEM : SRBE_EHIP, hipGetErrorString(e));
+  return SRBE_OK;
+}
+
 }  // extern "C"
 
 namespace {

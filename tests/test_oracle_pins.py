@@ -562,6 +562,122 @@ def test_srbe_energy_sample_mean_is_the_full_ewald_energy():
     assert abs(z) < 5.0
 
 
+# ---------------------------------------------------------------- virial (pressure) tensor
+
+
+def _strain_energy_pins_system():
+    rng = np.random.default_rng(21)
+    p, ion, q, ele, Q = small_cell(seed=9)
+    return p, ion, q, ele, Q, rng
+
+
+def test_fourier_virial_is_minus_the_strain_derivative():
+    # Under r -> (I + e) r with the box strained alike, fractional coordinates and S(k)
+    # stay, k -> (I + e)^-T k and V -> det(I + e) V: U_F(e) = 1/2 sum w(k(e), V(e)) |S|^2.
+    # Its central finite difference in each of the nine strain components must be
+    # minus the analytic virial (which is symmetric).
+    from oracle import virial
+    p, ion, q, ele, Q, _ = _strain_energy_pins_system()
+    modes = ewald.enumerate_modes(p)
+    S = ewald.structure_factor(p, modes, ion, q) + ewald.structure_factor(p, modes, ele, Q)
+    k0 = ewald.kvectors(p, modes)
+
+    def UF(eps):
+        F = np.eye(3) + eps
+        k = k0 @ np.linalg.inv(F)  # rows: (F^-T k)^T = k^T F^-1
+        k2 = np.sum(k * k, axis=1)
+        V = p.V * np.linalg.det(F)
+        return 0.5 * np.sum(4 * np.pi * np.exp(-k2 / (4 * p.alpha ** 2)) / (V * k2) * np.abs(S) ** 2)
+
+    k2 = np.sum(k0 ** 2, axis=1)
+    W = virial.fourier_virial(p, modes, ewald.ewald_weight(p, k2), S)
+    h = 1e-6
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = h
+            fd = -(UF(e) - UF(-e)) / (2 * h)
+            assert abs(fd - W[a, b]) < 1e-7 * np.max(np.abs(W)), (a, b, fd, W[a, b])
+    assert np.max(np.abs(W - W.T)) < 1e-12 * np.max(np.abs(W))
+
+
+def test_real_and_slab_virial_are_minus_the_strain_derivative():
+    # Every pair vector within rc stretches with the strain, the kernels do not; the
+    # slab term changes through V and M_z.  Finite differences of the strained sums.
+    from oracle import virial
+    p, ion, q, ele, Q, _ = _strain_energy_pins_system()
+    pos = np.concatenate([ion, ele])
+    qq = np.concatenate([q, Q])
+    kind = np.array(["i"] * len(ion) + ["g"] * len(ele))
+    pairs = []
+    for i in range(len(pos)):
+        for j in range(i + 1, len(pos)):
+            d = pos[i] - pos[j]
+            d[0] -= p.Lx * np.round(d[0] / p.Lx)
+            d[1] -= p.Ly * np.round(d[1] / p.Ly)
+            if np.linalg.norm(d) < p.rc:
+                K = {"ii": ewald.kernel_ion_ion, "ig": ewald.kernel_ion_gauss, "gi": ewald.kernel_ion_gauss,
+                     "gg": ewald.kernel_gauss_gauss}[kind[i] + kind[j]]
+                pairs.append((d, qq[i] * qq[j], K))
+    assert len(pairs) > 10
+
+    def UN(eps):
+        return sum(c * K(p, np.linalg.norm((np.eye(3) + eps) @ d)) for d, c, K in pairs)
+
+    W = virial.real_virial(p, ion, q, ele, Q)
+    Mz = q @ ion[:, 2] + Q @ ele[:, 2]
+
+    def Us(eps):
+        F = np.eye(3) + eps
+        return 2 * np.pi / (p.V * np.linalg.det(F)) * (F[2, 2] * Mz) ** 2
+
+    Ws = virial.slab_virial(p, ion, q, ele, Q)
+    h = 1e-6
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = h
+            fd = -(UN(e) - UN(-e)) / (2 * h)
+            assert abs(fd - W[a, b]) < 1e-7 * np.max(np.abs(W)), (a, b, fd, W[a, b])
+        e = np.zeros((3, 3))
+        e[a, a] = h
+        fd = -(Us(e) - Us(-e)) / (2 * h)
+        assert abs(fd - Ws[a, a]) < 1e-7 * abs(Ws[0, 0])
+
+
+def test_virial_trace_is_the_coulomb_energy():
+    # Point charges alone: the complete Coulomb energy is homogeneous of degree -1 in
+    # the lengths, so the trace of its virial equals the energy (independently of how
+    # Ewald splits it).  alpha rc = 6 keeps the real-space cut below 1e-16.
+    from oracle import virial
+    rng = np.random.default_rng(8)
+    p = ewald.Params(Lx=2.4, Ly=2.4, H=2.0, lam=3.0, alpha=5.0, eta=0.05, rc=1.2, coulomb_k=1.44,
+                     kspace_tol=1e-16)
+    n = 16
+    ion = np.column_stack([rng.uniform(0, p.Lx, n), rng.uniform(0, p.Ly, n), rng.uniform(0.3, p.H - 0.3, n)])
+    q = np.where(np.arange(n) % 2 == 0, 0.8, -0.8)
+    none = np.zeros((0, 3))
+    W = virial.complete_virial(p, ion, q, none, np.zeros(0))
+    U = ewald.energy(p, ion, q, none, np.zeros(0))["total"]
+    assert abs(W[0] + W[1] + W[2] - U) < 1e-10 * abs(U), (W[:3].sum(), U)
+
+
+def test_srbe_virial_expectation_over_every_mode_is_the_complete_virial():
+    # As for E*: weighting the one-mode estimate by each mode's sampling probability
+    # (the empty-batch estimate for the mass beyond the truncation) gives the virial of
+    # the complete energy, every component, to 1e-13.
+    from oracle import virial
+    p, ion, q, ele, Q = small_cell()
+    modes = ewald.enumerate_modes(p)
+    full = virial.complete_virial(p, ion, q, ele, Q, modes)
+    mv = modes[sampler.valid(p, modes)]
+    prob = np.exp(-np.sum(ewald.kvectors(p, mv) ** 2, axis=1) / (4 * p.alpha ** 2)) / srbe.normaliser_G(p)
+    expect = sum(pr * virial.srbe_virial(p, k[None, :], ion, q, ele, Q) for k, pr in zip(mv, prob))
+    expect = expect + (1.0 - prob.sum()) * virial.srbe_virial(p, np.zeros((0, 3)), ion, q, ele, Q)
+    assert np.max(np.abs(expect - full)) < 1e-13 * np.max(np.abs(full))
+    assert np.max(np.abs(full[3:])) > 1e-3 * np.max(np.abs(full))  # shear components present
+
+
 # ---------------------------------------------------------------- Langevin update (Sec. 3)
 
 
