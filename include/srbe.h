@@ -65,6 +65,8 @@ extern "C" {
                                      charges in lattice Fourier space (see below)     */
 #define SRBE_FLAG_ENERGY_PARTS 8 /* energy_out holds E* and its four parts per replica
                                     (see srbe_step)                                   */
+#define SRBE_FLAG_IID_SAMPLER 16 /* draw the P modes i.i.d. by rejection sampling instead
+                                    of by the Metropolis chain (see srbe_sample)      */
 
 typedef struct srbe_params {
   double Lx, Ly, H;   /* box (length); electrodes and ions have 0 <= z <= H           */
@@ -387,7 +389,17 @@ int srbe_md_graph_create(srbe_system* h, int32_t precision, int32_t n_rep, const
 /*
  * srbe_sample -- only the sampler of a step (Sec. 3, Eqs. (26)-(29)): writes the
  * n_rep*P*3 int32 modes the step with the same (seed, step) would use.
- * seed device n_rep uint64; kset_out device.  Returns SRBE_EINVAL on bad arguments.
+ * seed device n_rep uint64; kset_out device; n_accepted_out device n_rep int32 or NULL:
+ * the Metropolis chain's accepted proposals.  Returns SRBE_EINVAL on bad arguments.
+ * The chain: the proposal of Eq. (28) per axis, acceptance by Eq. (29), a fresh chain
+ * per (seed, step) started at the first valid proposal of a 64-try start sequence.
+ * With SRBE_FLAG_IID_SAMPLER the P modes are instead independent draws from the same
+ * target by rejection sampling: attempt a (counter (a, step, 3, 0) for its proposal,
+ * (a, step, 4, 0) for its uniform) is accepted when its mode lies outside I and the
+ * origin and log U < log r(m) - log r(0), r the ratio of Eq. (29); the sample is the
+ * accepted proposals in attempt order (n_accepted_out: the attempts used).  After
+ * 65536 attempts the rest of the sample is (1, 0, 0) and the step flags SRBE_ENUMERIC
+ * (only when most of the proposal's mass lies on I or the origin).
  */
 int srbe_sample(srbe_system* h, int32_t n_rep, const uint64_t* seed, uint64_t step, int32_t* kset_out,
                 int32_t* n_accepted_out, void* stream);

@@ -40,7 +40,10 @@ from . import philox
 PURPOSE_PROPOSAL = 0
 PURPOSE_ACCEPT = 1
 PURPOSE_START = 2
+PURPOSE_IID_PROPOSAL = 3
+PURPOSE_IID_ACCEPT = 4
 START_TRIES = 64
+IID_MAX_ATTEMPTS = 65536
 
 
 def proposal_sigma(p):
@@ -131,3 +134,42 @@ def draw_kset(p, seed, stream, step, P=None):
                 nacc += 1
         out[l] = x
     return out, nacc
+
+
+def iid_draw_kset(p, seed, stream, step, P=None):
+    """P independent draws from the same target by rejection sampling (the i.i.d. option).
+
+    Attempt a draws its proposal m = round(sigma z) exactly as above from counter
+    (a, step, 3, 0) and its uniform U from word 0 of counter (a, step, 4, 0).  Per axis
+    exp(-m^2/(2 sigma_d^2)) / q_d(m) is largest at m = 0 (q_d(m) is the target's density
+    integrated over [m - 1/2, m + 1/2], which shrinks more slowly than the density as |m|
+    grows), so r(m) <= r(0) with r the ratio of Eq. (29), and accepting a proposal in
+    L_k \\ I when log U < log r(m) - log r(0) gives exact draws from the target.  The
+    sample is the accepted proposals in attempt order.  After IID_MAX_ATTEMPTS attempts
+    the rest of the sample is (1, 0, 0) (reachable only when the bound is loose, e.g.
+    with most of the proposal's mass on I).
+
+    Returns (kset, attempts): attempts = the index of the attempt that completed the
+    sample, plus one (IID_MAX_ATTEMPTS if it was not completed).
+    """
+    P = p.P if P is None else P
+    out = np.zeros((P, 3), dtype=np.int64)
+    if P == 0:
+        return out, 0
+    l0 = float(log_ratio(p, np.zeros((1, 3)))[0])
+    filled = 0
+    chunk = 1024
+    for a0 in range(0, IID_MAX_ATTEMPTS, chunk):
+        idx = np.arange(a0, a0 + chunk)
+        y = proposals(p, seed, stream, step, PURPOSE_IID_PROPOSAL, idx)
+        w = _blocks(seed, stream, step, PURPOSE_IID_ACCEPT, idx)
+        lU = np.log(philox.u01_open(w[:, 0]))
+        ok = valid(p, y)
+        ok[ok] = lU[ok] < log_ratio(p, y[ok]) - l0
+        for a in np.nonzero(ok)[0]:
+            out[filled] = y[a]
+            filled += 1
+            if filled == P:
+                return out, a0 + int(a) + 1
+    out[filled:] = (1, 0, 0)
+    return out, IID_MAX_ATTEMPTS

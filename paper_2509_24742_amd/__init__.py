@@ -10,7 +10,7 @@ library has not been built.
 import numpy as np
 
 from . import binding
-from .binding import (SRBE_BF16, SRBE_FLAG_ENERGY_PARTS, SRBE_FLAG_KSPACE_ONLY, SRBE_FLAG_LATTICE_SOLVE, SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
+from .binding import (SRBE_BF16, SRBE_FLAG_ENERGY_PARTS, SRBE_FLAG_IID_SAMPLER, SRBE_FLAG_KSPACE_ONLY, SRBE_FLAG_LATTICE_SOLVE, SRBE_FLAG_NO_CP, SRBE_FP32, SRBE_FP64, SrbeError, srbe_create, srbe_destroy,  # noqa: F401
                       srbe_error_string, srbe_graph_create, srbe_graph_destroy, srbe_graph_launch,
                       srbe_graph_set_step, srbe_last_error, srbe_n_ele, srbe_normaliser, srbe_phase_name,
                       srbe_profile_enable, srbe_profile_read, srbe_sample, srbe_step, srbe_sync_status,

@@ -25,6 +25,7 @@ SRBE_FLAG_NO_CP = 1
 SRBE_FLAG_KSPACE_ONLY = 2
 SRBE_FLAG_LATTICE_SOLVE = 4
 SRBE_FLAG_ENERGY_PARTS = 8
+SRBE_FLAG_IID_SAMPLER = 16
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsrbe.so")
 

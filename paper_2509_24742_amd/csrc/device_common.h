@@ -23,6 +23,7 @@ struct Geom {
   double sig[3];   // proposal standard deviation per axis (in units of m)
   int qmax[3];     // log q_d(m) is tabulated for |m| <= qmax[d]
   int M, P, K;     // K = M + P modes per replica
+  int iid;         // 1: the sample is drawn i.i.d. by rejection instead of by the Metropolis chain
   int n_ele;
   // real-space cell grid: ncx x ncy cells over the periodic x, y extent, ncz over
   // z in [0, H]; cells are wider than rc in x, y and than rc / nzs in z, so all pairs

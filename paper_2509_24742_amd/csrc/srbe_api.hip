@@ -192,7 +192,8 @@ std::string check_params(const srbe_params* p) {
   if (!(p->kspace_tol > 0.0 && p->kspace_tol < 1.0)) return "kspace_tol must lie in (0, 1)";
   if (p->M < 0 || p->P < 0) return "M and P must be >= 0";
   if (p->P > 2048) return "P must be <= 2048";
-  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY | SRBE_FLAG_LATTICE_SOLVE | SRBE_FLAG_ENERGY_PARTS))
+  if (p->flags & ~(SRBE_FLAG_NO_CP | SRBE_FLAG_KSPACE_ONLY | SRBE_FLAG_LATTICE_SOLVE | SRBE_FLAG_ENERGY_PARTS |
+                   SRBE_FLAG_IID_SAMPLER))
     return "unknown flag";
   if (p->reserved != 0) return "reserved must be 0";
   return "";
@@ -222,6 +223,7 @@ Geom make_geom(const srbe_params& p, int n_ele) {
   g.M = p.M;
   g.P = p.P;
   g.K = p.M + p.P;
+  g.iid = (p.flags & SRBE_FLAG_IID_SAMPLER) ? 1 : 0;
   g.n_ele = n_ele;
   // real-space cells at least rc wide in x and y and rc / nzs thick in z (the
   // z-stencil then reaches nzs cells each way); coarsened, never below those

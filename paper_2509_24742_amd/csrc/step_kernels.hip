@@ -443,6 +443,77 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// The i.i.d. option: rejection sampling with the same proposal and target.  Attempt a
+// draws its proposal from counter (a, step, 3, 0) as above and its uniform from word 0
+// of counter (a, step, 4, 0); it is accepted when the proposal lies in L_k \ I and
+// log U < log r(y) - log r(0), r the ratio of Eq. (29) (exp(-m^2/(2 sigma^2)) / q_d(m)
+// is largest at m = 0 on every axis, so r(0) bounds r).  The accepted proposals in
+// attempt order are the sample.  The block makes NT attempts per round, each thread
+// one, and places the accepted ones by a block-wide count; after kIidMaxRounds rounds
+// the rest of the sample is (1, 0, 0) and the status word flags a numeric error.
+constexpr int kIidMaxRounds = 64;
+
+#pragma clang fp contract(off)
+template <int NT>
+__device__ void sample_iid(const Geom& g, int r, const StepBufs& b, uint64_t seed, uint64_t step) {
+  __shared__ int wcount[NT / 64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int P = g.P, M = g.M, K = g.K;
+  const double l0 = log_ratio_tab(g, b.logq, 0, 0, 0);
+  int filled = 0;  // block-uniform
+  for (int round = 0; round < kIidMaxRounds && filled < P; ++round) {
+    const uint64_t a = (uint64_t)round * NT + t;
+    int mx, my, mz;
+    proposal(g, seed, step, 3, a, mx, my, mz);
+    U64x4 c;
+    c.v[0] = a;
+    c.v[1] = step;
+    c.v[2] = 4;
+    c.v[3] = 0;
+    const U64x4 wa = philox4x64_10(c, seed, 0);
+    bool ok = valid_mode(g, mx, my, mz);
+    if (ok) ok = log(u01_open(wa.v[0])) < log_ratio_tab(g, b.logq, mx, my, mz) - l0;
+    const uint64_t m = __ballot(ok);
+    if (lane == 0) wcount[w] = __popcll(m);
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int u = 0; u < NT / 64; ++u) {
+      before += u < w ? wcount[u] : 0;
+      total += wcount[u];
+    }
+    const int slot = filled + before + __popcll(m & ((1ull << lane) - 1));
+    if (ok && slot < P) {
+      b.modes[(size_t)r * K + M + slot] = make_int4(mx, my, mz, 0);
+      b.w[(size_t)r * K + M + slot] = sampled_weight(g, mx, my, mz);
+      if (b.kset_out) {
+        int32_t* o = b.kset_out + ((size_t)r * P + slot) * 3;
+        o[0] = mx;
+        o[1] = my;
+        o[2] = mz;
+      }
+      if (slot == P - 1 && b.nacc_out) b.nacc_out[r] = (int)(a + 1);
+    }
+    filled += total;
+    __syncthreads();  // wcount is rewritten by the next round
+  }
+  for (int l = filled + t; l < P; l += NT) {
+    b.modes[(size_t)r * K + M + l] = make_int4(1, 0, 0, 0);
+    b.w[(size_t)r * K + M + l] = sampled_weight(g, 1, 0, 0);
+    if (b.kset_out) {
+      int32_t* o = b.kset_out + ((size_t)r * P + l) * 3;
+      o[0] = 1;
+      o[1] = 0;
+      o[2] = 0;
+    }
+  }
+  if (t == 0 && filled < P) {
+    atomicOr(b.status, ST_NUMERIC);
+    if (b.nacc_out) b.nacc_out[r] = kIidMaxRounds * NT;
+  }
+}
+#pragma clang fp contract(fast)
+
 // One block of NT threads per replica: wave 0 draws the 64 start tries while the
 // other waves draw the P proposals; then wave 0 runs the chain.
 template <int NT>
@@ -488,6 +559,10 @@ __device__ __forceinline__ void sample_block(const Geom& g, int r, const StepBuf
     return;
   }
   const uint64_t seed = seeds[r];
+  if (g.iid) {
+    sample_iid<NT>(g, r, b, seed, step);
+    return;
+  }
   // LDS: ly[P], lu[P] (double), state[P] (int), ym[P][3] (int16).  An invalid
   // proposal (target probability zero) has ly = NaN, which fails both accept tests.
   double* ly = reinterpret_cast<double*>(smem);

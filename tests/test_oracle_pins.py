@@ -113,6 +113,41 @@ def test_sampler_distribution_chi2():
     assert chi2 < 90.0  # 40 degrees of freedom: p ~ 1e-5
 
 
+def test_iid_sampler_distribution_and_acceptance():
+    # The i.i.d. option draws every mode exactly from P(k) = exp(-k^2/4a^2)/G on L_k \ I
+    # (no chain, no thinning): chi^2 of the counts against P(k); and its acceptance is the
+    # rejection sampler's exact rate, sum over L_k \ I of q(m) r(m)/r(0) = G prod_d q_d(0),
+    # which the attempt counts must reproduce within 5 standard errors.
+    p = ewald.Params(Lx=1.2, Ly=1.2, H=1.5, lam=2.0, alpha=3.0, M=2)
+    P, draws = 200, 400
+    counts = {}
+    attempts = 0
+    for c in range(draws):
+        ks, att = sampler.iid_draw_kset(p, seed=42, stream=c, step=3, P=P)
+        assert np.all(sampler.valid(p, ks))
+        attempts += att
+        for row in map(tuple, ks):
+            counts[row] = counts.get(row, 0) + 1
+    n = sum(counts.values())
+    G = srbe.normaliser_G(p)
+    allm = ewald.enumerate_modes(p, tol=1e-30)
+    allm = allm[sampler.valid(p, allm)]
+    pk = np.exp(-np.sum(ewald.kvectors(p, allm) ** 2, axis=1) / (4 * p.alpha ** 2)) / G
+    order = np.argsort(-pk)[:40]
+    obs = np.array([counts.get(tuple(allm[i]), 0) for i in order], dtype=float)
+    exp = n * pk[order]
+    obs = np.append(obs, n - obs.sum())
+    exp = np.append(exp, n - exp.sum())
+    chi2 = np.sum((obs - exp) ** 2 / exp)
+    assert chi2 < 90.0  # 40 degrees of freedom: p ~ 1e-5
+    rate = G * np.prod([sampler.q_axis(0, p.alpha, L) for L in p.L])
+    assert 0.0 < rate < 1.0
+    # draws of P accepted: attempts - P is negative binomial, mean P (1 - rate) / rate
+    mean = draws * P / rate
+    sd = np.sqrt(draws * P * (1.0 - rate)) / rate
+    assert abs(attempts - mean) < 5.0 * sd, (attempts, mean, sd)
+
+
 def test_sampler_never_returns_deterministic_modes():
     p = ewald.Params(Lx=3.4, Ly=3.7, H=12.0, lam=3.0, alpha=3.5, M=13)
     for step in range(5):
