@@ -105,6 +105,9 @@ def parse():
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven batch (32 systems of 2e3-2e5 particles, each its own box, charges by the "
                          "lattice solve), otherwise timed and reported as uneven_batch")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the voltage sweep (the paper-shaped cell at 0..4 V, 1000 steps with 0.01 nm "
+                         "positional jitter), otherwise reported as voltage_sweep")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run a plain device copy of COPY_BYTES (the reference that HBM byte counters "
                          "are scaled by)")
@@ -339,6 +342,11 @@ def main():
         result["large_slab"] = large_slab_bench(args, srbe_amd, stream)
     if not args.no_uneven:
         result["uneven_batch"] = uneven_bench(args, srbe_amd, stream)
+    if not args.no_sweep:
+        # the paper-shaped cell at 0, 0.5, ..., 4 V for 1000 steps with 0.01 nm jitter per step
+        from paper_2509_24742_amd import voltage_sweep
+        log("voltage sweep (9 voltages x 1000 jittered steps) ...")
+        result["voltage_sweep"] = voltage_sweep.run(steps=1000, sigma=0.01, precision="fp32")
 
     if not args.no_cpu:
         o = sysm.step(off, xyz, q, dpsi, seeds, 0, precision=srbe_amd.SRBE_FP32, want_kset=False)
