@@ -63,6 +63,8 @@ PROF_REPS = 10     # launches of each phase between its timing events
 # on: its SHA-256 is recorded beside them, and a changed source reports null.
 COPY_BYTES = 1 << 29
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kernel_traffic_replica_batch64.md")
+# VALU instruction counts per launch (rocprofv3 SQ counters), same SHA-256 rule
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "kernel_counters_replica_batch64.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_24742_amd", "csrc", "step_kernels.hip")
 # launch parameters chosen by srbe_tune's timing of these workloads on an MI355X
 TUNING_CACHE = os.path.join(ROOT, "paper_2509_24742_amd", "tuning_cache.json")
@@ -83,6 +85,24 @@ def measured_traffic():
     if rec.get("sha") != sha:
         return {}
     return {k: float(v) for k, v in rec.items() if k != "sha"}
+
+
+def measured_counters():
+    """{phase: (VALU instructions, ratio to algorithmic, issue fraction)} if recorded for the current source."""
+    try:
+        lines = open(COUNTER_PROFILE).read().splitlines()
+    except OSError:
+        return {}
+    rec, sha = {}, None
+    for ln in lines:
+        parts = ln.split()
+        if ln.startswith("source_sha256 "):
+            sha = parts[-1]
+        elif ln.startswith("valu ") and len(parts) == 7:
+            rec[parts[1]] = (float(parts[2]), float(parts[4]), float(parts[6]))
+    if sha != hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest():
+        return {}
+    return rec
 
 
 def log(msg):
@@ -273,15 +293,26 @@ def main():
                     "work": f"{units[kdom]} {'unordered ion-ion pairs' if kdom == 'real_ii' else 'units'} x "
                             f"{SLOTS[kdom]} VALU slots per launch",
                     "us_per_launch": round(dur * 1e6, 2)}
-    if kdom.startswith("real"):
-        roofline["bound_evidence"] = ("VALU-issue bound, not HBM: the pass's HBM bytes per launch are ~1.3x its "
-                                      "16-byte record read + 32-byte result write per ion (under 0.2 TB/s), while "
-                                      "its VALU instruction count is several times the algorithmic one "
-                                      "(profiles/kernel_counters_replica_batch64.md)")
     traffic = measured_traffic()
     if kdom in traffic:
         roofline["traffic"] = traffic[kdom]
         roofline["traffic_unit"] = "HBM bytes per launch"
+    counters = measured_counters()
+    if kdom in counters:
+        vi, ratio, issue = counters[kdom]
+        roofline["valu_instructions_per_launch"] = vi
+        roofline["valu_instructions_over_algorithmic"] = ratio
+        roofline["valu_issue_fraction"] = issue
+    if kdom.startswith("real"):
+        tb = f"{traffic[kdom] / dur / 1e12:.2f} TB/s" if kdom in traffic else "unmeasured"
+        ev = (f"ALU-issue bound, not HBM: HBM traffic per launch {tb} of 8 TB/s "
+              f"(profiles/kernel_traffic_replica_batch64.md)")
+        if kdom in counters:
+            ev += (f"; {counters[kdom][0]:.3g} VALU wave instructions per launch, {counters[kdom][1]:.1f}x the "
+                   f"algorithmic count, issued at {counters[kdom][2]:.2f} of one per CU per cycle "
+                   f"(profiles/kernel_counters_replica_batch64.md): the candidate tests and bookkeeping, "
+                   f"not the pair terms, take the issue slots")
+        roofline["bound_evidence"] = ev
     other = {}
     for k in cands:
         d = phases[k]["avg_us"] * 1e-6
