@@ -631,6 +631,13 @@ def uneven_bench(args, srbe_amd, stream):
                      "per_system_graphs_ms_by_streams": {str(k): round(v, 4) for k, v in res.items()}}
         log(f"uneven batch {name}: per-system graphs over streams {res}")
         if name == "fp32":
+            # the replays above ran steps 0, 1, ...: the error check takes an eager batch step at
+            # step 0, the oracle's sample
+            binding.srbe_batch_step(bt, prec, boff, sor, bxyz, bq, bdp, bsd, 0, o["Q"], o["F"], o["psibar"],
+                                    energy_out=o["E"])
+            torch.cuda.synchronize()
+            if binding.srbe_batch_sync_status(bt) != 0:
+                raise RuntimeError(binding.srbe_batch_last_error(bt))
             bout = {k: v.cpu().numpy() for k, v in o.items()}
     binding.srbe_batch_destroy(bt)
     # FP32 errors: the three smallest systems in full against the oracle's dense solve
