@@ -1085,6 +1085,13 @@ constexpr int ring_bytes() {
   return 4 * kRingAlloc * (FP32 ? (int)sizeof(float4) : (int)sizeof(double4));
 }
 
+// A home cell's candidate list (ion-ion pass): when a cell's neighbours form several runs,
+// the wave writes the record indices of all of them, in run order, into a list of up to
+// kListCap 16-bit offsets from the first run's start, so that its ions' scans take full
+// rounds of 64 list entries instead of topping up rounds from short runs.
+constexpr int kListCap = 1024;
+constexpr int kListBytes = 4 * kListCap * (int)sizeof(uint16_t);
+
 static_assert(kRunMax < 64, "one lane per run, and a terminator lane");
 
 // Lane s turns run s of a -1-terminated run list into a record range [rb, re) with
@@ -1181,6 +1188,75 @@ __device__ __forceinline__ void wave_scan(int rb, int re, Entry* __restrict__ ri
     const int jj = valid ? j : base[0];  // lane 0 always holds a valid record
     round(load(jj), jj, valid);
   }
+}
+
+// The same scan over a candidate list (see kListCap): candidate q is record base + list[q],
+// q < total.  Rounds of 64 list entries, the records of the next two rounds in flight (a
+// request past the list's end repeats its last record and is not used).  The candidates
+// come in the order wave_scan takes them, so the hits reach the ring in the same order
+// and the results are the same bit for bit.
+template <class Entry, class LoadF, class TestF, class EvalF>
+__device__ __forceinline__ void wave_scan_list(const uint16_t* __restrict__ list, int total, int base,
+                                               Entry* __restrict__ ring, unsigned& head, unsigned& tail,
+                                               LoadF load, TestF test, EvalF eval_block) {
+  const int lane = threadIdx.x & 63;
+  auto round = [&](const auto& rec, int j, bool valid) {
+    Entry ent;
+    const bool hit = test(rec, j, ent) & valid;
+    const uint64_t m = __ballot(hit);
+    if (hit) ring[lanes_below(m, tail) & (kRing - 1)] = ent;
+    tail += (unsigned)__popcll(m);
+    if (tail - head >= 64) {
+      __builtin_amdgcn_wave_barrier();
+      eval_block(head, head + 64);
+      head += 64;
+    }
+  };
+  const int nr = (total + 63) >> 6;
+  auto jof = [&](int t) { return base + (int)list[min(64 * t + lane, total - 1)]; };
+  int jA = jof(0), jB = jof(1), jC = jof(2);
+  auto A = load(jA), B = load(jB), C = load(jC);
+  int t = 0;
+  for (; t + 3 <= nr; t += 3) {
+    round(A, jA, 64 * t + lane < total);
+    jA = jof(t + 3);
+    A = load(jA);
+    round(B, jB, 64 * (t + 1) + lane < total);
+    jB = jof(t + 4);
+    B = load(jB);
+    round(C, jC, 64 * (t + 2) + lane < total);
+    jC = jof(t + 5);
+    C = load(jC);
+  }
+  if (t < nr) round(A, jA, 64 * t + lane < total);
+  if (t + 1 < nr) round(B, jB, 64 * (t + 1) + lane < total);
+}
+
+// Builds the candidate list of a home cell from its runs (lane s: run s as [rb, re)) when
+// there are at least two and they fit (at most kListCap records, spanning under 2^16);
+// returns false otherwise.  total and base: the list's length and offset base.
+__device__ __forceinline__ bool build_list(int rb, int re, uint16_t* __restrict__ list, int& total, int& base) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t live = __ballot(rb < re);
+  if (__popcll(live) < 2) return false;
+  base = __builtin_amdgcn_readlane(rb, __builtin_ctzll(live));
+  const int last = __builtin_amdgcn_readlane(re, 63 - __builtin_clzll(live));
+  int n = 0;
+  for (uint64_t m = live; m; m &= m - 1) {
+    const int s = __builtin_ctzll(m);
+    n += __builtin_amdgcn_readlane(re, s) - __builtin_amdgcn_readlane(rb, s);
+  }
+  if (n > kListCap || last - base > 65535) return false;
+  int at = 0;
+  for (uint64_t m = live; m; m &= m - 1) {
+    const int s = __builtin_ctzll(m);
+    const int b0 = __builtin_amdgcn_readlane(rb, s), len = __builtin_amdgcn_readlane(re, s) - b0;
+    for (int t = lane; t < len; t += 64) list[at + t] = (uint16_t)(b0 - base + t);
+    at += len;
+  }
+  total = n;
+  __builtin_amdgcn_wave_barrier();
+  return true;
 }
 
 // The electrode-potential pass can split each chunk's candidate records over esplit
@@ -1956,7 +2032,7 @@ struct CarriedSums {
 };
 
 // Ion-ion pass, block (bx, r): waves 4 bx .. 4 bx + 3 of replica r, each taking
-// bb.ii_ipw consecutive sorted ions.  lds: ring_bytes<FP32>() bytes.
+// bb.ii_ipw consecutive sorted ions.  lds: ring_bytes<FP32>() + kListBytes bytes.
 template <bool FP32>
 __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb, int bx, int r, void* lds) {
   const int64_t* __restrict__ off = bb.off;
@@ -1979,6 +2055,8 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
   if (kbeg >= b1) return;  // whole wave
   const int kend = min(b1, kbeg + ipw);
   Entry* ring = reinterpret_cast<Entry*>(lds) + w * kRingAlloc;
+  uint16_t* list = reinterpret_cast<uint16_t*>(reinterpret_cast<unsigned char*>(lds) + ring_bytes<FP32>()) +
+                   w * kListCap;
   const int* cs = cstart + (size_t)r * (g.ncell + 1);
   auto ion_range = [&](int, int2 rc, int& b, int& e) {
     b = b0 + cs[rc.x];
@@ -2023,12 +2101,14 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
       phi[i] = g.ke * ph;
     }
   };
-  int home = -1, rb = 0, re = 0;
+  int home = -1, rb = 0, re = 0, ltotal = 0, lbase = 0;
+  bool use_list = false;
   for (int k = kbeg; k < kend; ++k) {
     const int hk = __builtin_amdgcn_readfirstlane(scell[k]);
     if (hk != home) {
       home = hk;
       resolve_runs(ion_runs + kRunMax * home, ion_range, rb, re);
+      use_list = build_list(rb, re, list, ltotal, lbase);
     }
     if constexpr (FP32) {
       const uint4 pi_ = sfx[k];
@@ -2037,32 +2117,36 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
       // is not negative); r = 0 is the ion itself (two ions at one point have no
       // finite pair term)
       const unsigned rc2m1 = __float_as_uint((float)(g.rc * g.rc)) - 1u;
-      wave_scan(rb, re, ring, head, tail, [&](int j) { return sfx[j]; },
-                [&](int j0) { return (sfx + j0)[lane]; },
-                [&](const uint4& p, int, float4& ent) {
-                  ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
-                  ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
-                  ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
-                  ent.w = __uint_as_float(p.w);
-                  return __float_as_uint(ent.x * ent.x + ent.y * ent.y + ent.z * ent.z) - 1u < rc2m1;
-                },
-                eval_block);
+      auto load = [&](int j) { return sfx[j]; };
+      auto test = [&](const uint4& p, int, float4& ent) {
+        ent.x = (float)(int32_t)(pi_.x - p.x) * lx;
+        ent.y = (float)(int32_t)(pi_.y - p.y) * ly;
+        ent.z = (float)(int32_t)(pi_.z - p.z) * lz;
+        ent.w = __uint_as_float(p.w);
+        return __float_as_uint(ent.x * ent.x + ent.y * ent.y + ent.z * ent.z) - 1u < rc2m1;
+      };
+      if (use_list)
+        wave_scan_list(list, ltotal, lbase, ring, head, tail, load, test, eval_block);
+      else
+        wave_scan(rb, re, ring, head, tail, load, [&](int j0) { return (sfx + j0)[lane]; }, test, eval_block);
     } else {
       const double4 pi_ = sd4[k];
       const double rc2 = g.rc * g.rc;
-      wave_scan(rb, re, ring, head, tail, [&](int j) { return sd4[j]; },
-                [&](int j0) { return (sd4 + j0)[lane]; },
-                [&](const double4& p, int j, double4& ent) {
-                  double sx = pi_.x - p.x, sy = pi_.y - p.y;
-                  sx -= rint(sx);
-                  sy -= rint(sy);
-                  ent.x = sx * g.Lx;
-                  ent.y = sy * g.Ly;
-                  ent.z = (pi_.z - p.z) * g.Lz;
-                  ent.w = p.w;
-                  return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
-                },
-                eval_block);
+      auto load = [&](int j) { return sd4[j]; };
+      auto test = [&](const double4& p, int j, double4& ent) {
+        double sx = pi_.x - p.x, sy = pi_.y - p.y;
+        sx -= rint(sx);
+        sy -= rint(sy);
+        ent.x = sx * g.Lx;
+        ent.y = sy * g.Ly;
+        ent.z = (pi_.z - p.z) * g.Lz;
+        ent.w = p.w;
+        return (ent.x * ent.x + ent.y * ent.y + ent.z * ent.z < rc2) & (j != k);
+      };
+      if (use_list)
+        wave_scan_list(list, ltotal, lbase, ring, head, tail, load, test, eval_block);
+      else
+        wave_scan(rb, re, ring, head, tail, load, [&](int j0) { return (sd4 + j0)[lane]; }, test, eval_block);
     }
     if (k > kbeg) {  // the previous ion is complete once its last entries are evaluated
       if (head < acc.bound) {
@@ -2089,7 +2173,7 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
 // only on (r, bx), so the mapping does not change results.
 template <bool FP32>
 __device__ __forceinline__ void real_ii_body(const Geom& g, const StepBufs& b, int tiles, int L) {
-  __shared__ __align__(16) unsigned char lds[ring_bytes<FP32>()];
+  __shared__ __align__(16) unsigned char lds[ring_bytes<FP32>() + kListBytes];
   const int j = L >> 3;
   int r, bx;
   if (b.R >= 8) {
