@@ -957,12 +957,46 @@ void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, h
 }
 
 // ============================================================ real-space kernels
+// FP64 erfc(x) for x >= 0, with E = exp(-x^2) beside it for the derivative: erfc(x) =
+// E t p(u), t = 1 / (1 + x/2), u = (2 t - 1 - t0) / (1 - t0) with t0 = t(27), p of degree
+// 20 fitted to erfcx(x) / t on [0, 27] (coefficients from fit_erfc.py beside this file;
+// relative error 1.3e-14 in FP64, plus that of exp(-x^2) from the rounded x^2, ~1e-16 x^2).
+// Beyond x = 27, E and so the result are below the smallest FP64 subnormal.
+__device__ __forceinline__ double erfc_e64(double x, double& E) {
+  E = exp(-x * x);
+  const double t = 1.0 / fma(0.5, x, 1.0);
+  const double u = fma(t, 29.0 / 13.5, -15.5 / 13.5);
+  double p = 5.18322347079050235e-09;
+  p = fma(p, u, 9.15908983234418801e-09);
+  p = fma(p, u, -5.96955725824229679e-08);
+  p = fma(p, u, -1.83108728307537812e-08);
+  p = fma(p, u, 3.12694522697253297e-07);
+  p = fma(p, u, -3.29070948319133605e-07);
+  p = fma(p, u, -7.35054674846839475e-07);
+  p = fma(p, u, 2.72720061601437206e-06);
+  p = fma(p, u, -1.71507364475183724e-06);
+  p = fma(p, u, -1.05829830498160832e-05);
+  p = fma(p, u, 2.76972235614982518e-05);
+  p = fma(p, u, 1.44669835925712893e-05);
+  p = fma(p, u, -1.85052166647616797e-04);
+  p = fma(p, u, 1.42801899132745516e-04);
+  p = fma(p, u, 1.10927368016556236e-03);
+  p = fma(p, u, -1.79400388641047948e-03);
+  p = fma(p, u, -8.83472414082498228e-03);
+  p = fma(p, u, 1.21948287907252696e-02);
+  p = fma(p, u, 1.24119759473117527e-01);
+  p = fma(p, u, 3.38058442287577476e-01);
+  p = fma(p, u, 5.35156895807327726e-01);
+  return E * t * p;
+}
+
 // Eq. (13): ion-ion erfc(alpha r)/r and ion-Gaussian [erfc(alpha r) - erfc(r/eta)]/r.
 __device__ __forceinline__ void erfc_over_r(double a, double r, double& f, double& df) {
-  const double e = erfc(a * r);
+  double E;
+  const double e = erfc_e64(a * r, E);
   const double inv = 1.0 / r;
   f = e * inv;
-  df = -e * inv * inv - 2.0 * a * INV_SQRT_PI * exp(-(a * r) * (a * r)) * inv;
+  df = -e * inv * inv - 2.0 * a * INV_SQRT_PI * E * inv;
 }
 
 // FP32 pair kernel: with x = a r, f = erfc(x) / r and h = -(1/r) d/dr [erfc(x) / r]
@@ -2648,6 +2682,14 @@ __global__ __launch_bounds__((multi_threads<PH, V1, W>())) void k_multi(MultiLau
   }
 }
 
+template <bool FP32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_multi_real_ii(MultiLaunch m) {
+  const int s = multi_system(m, blockIdx.x);
+  const Geom g = m.d[s].g;  // copies: only the fields the pass reads are loaded
+  const StepBufs b = m.d[s].b;
+  real_ii_body<FP32>(g, b, m.iarg[(size_t)kMultiArgs * s], blockIdx.x - m.start[s]);
+}
+
 template <int PH, int V1, int W, int U, int KB>
 static void multi_go(const MultiLaunch& m, int nblocks, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((k_multi<PH, V1, W, U, KB>), dim3(nblocks), dim3(multi_threads<PH, V1, W>()), lds, s, m);
@@ -2697,7 +2739,13 @@ void launch_multi(int phase, int fp32, int W, int U, int KB, const MultiLaunch& 
       break;
     case MP_POST_CHARGES: multi_v<MP_POST_CHARGES>(fp32, m, nblocks, lds, s); break;
     case MP_STAGE_ELE: multi_v<MP_STAGE_ELE>(fp32, m, nblocks, lds, s); break;
-    case MP_REAL_II: multi_v<MP_REAL_II>(fp32, m, nblocks, lds, s); break;
+    case MP_REAL_II:
+      // a kernel of its own: the FP64 pass then gets the registers of the single-system one
+      if (fp32)
+        hipLaunchKernelGGL(k_multi_real_ii<true>, dim3(nblocks), dim3(256), lds, s, m);
+      else
+        hipLaunchKernelGGL(k_multi_real_ii<false>, dim3(nblocks), dim3(256), lds, s, m);
+      break;
     case MP_ENERGY_PARTS: multi_go<MP_ENERGY_PARTS, 1, 4, 4, 16>(m, nblocks, lds, s); break;
     case MP_FINAL: multi_go<MP_FINAL, 1, 4, 4, 16>(m, nblocks, lds, s); break;
     default: break;
