@@ -4,10 +4,10 @@ Four systems: the tiny slab (dense charge solve; two replicas of different sizes
 small systems of the uneven batch (square-lattice walls, lattice charge solve; aspect
 ratios 12 and 12, one and two replicas) and its largest system (162,990 particles: the
 multi-block cell sort, the energy's tiled ion sums; one replica).  The batch step runs
-the same kernels with the same per-system launch shapes as a single-system srbe_step,
-so its outputs must equal those of one srbe_step per system with the same seeds and
-step index (FP64 to 1e-13 relative max-norm, FP32 force to 1e-6 relative RMS -- in
-practice bit for bit).  The tiny slab's replicas and the smallest uneven system are
+the same kernels as a single-system srbe_step, so its outputs must equal those of one
+srbe_step per system with the same seeds and step index: FP64 to 1e-13 relative
+max-norm; FP32 to the FP32 tolerances (the batch sizes some grids from the whole batch,
+which reorders FP32 sums).  The tiny slab's replicas and the smallest uneven system are
 also compared with the FP64 oracle (tolerances of test_gpu_step.py).  A captured batch
 step replays to the eager step's results; fixed-charge batch steps match single ones.
 """
@@ -118,21 +118,37 @@ def _split(batch, off, sor, got, r):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_equals_single_system_steps(batch, precision):
+    """FP64: equal to 1e-13 (the sums' order aside, the same arithmetic).  FP32: a batch
+    sizes the real-space work splits and the structure-factor chunks from the whole batch,
+    so its FP32 sums run in another order than a lone system's; the two then agree to the
+    FP32 tolerances against the oracle (force 1e-5 relative RMS, Q and b 3e-5), psibar to
+    that tolerance on b (it takes up the uniform part of b's rounding, which Q does not
+    see), and the energy to 1e-4 of its magnitude (it is assembled from terms some 30 times
+    its size, each good to a few 1e-7 relative)."""
     off, sor, got = _run_batch(batch, precision)
     ref = _run_single(batch, precision)
-    tolF = 1e-13 if precision == 0 else 1e-6
     same = True
     for r in range(len(sor)):
         g = _split(batch, off, sor, got, r)
         s = ref[r]
         F1 = s["F"].reshape(3, -1).T
         same &= bool(np.array_equal(g["F"], F1) and np.array_equal(g["Q"], s["Q"]))
+        dpsi_bar = abs(g["psibar"] - s["psibar"][0])
+        dE = abs(g["E"] - s["E"][0])
         print(f"precision {precision} replica {r} (system {sor[r]}): F {rel_rms(g['F'], F1):.1e}, "
-              f"Q {rel_inf(g['Q'], s['Q']):.1e}, E {abs(g['E'] - s['E'][0]):.1e}", flush=True)
-        assert rel_rms(g["F"], F1) <= tolF and rel_inf(g["F"], F1) <= 100 * tolF
-        assert rel_inf(g["Q"], s["Q"]) <= 10 * tolF and rel_inf(g["b"], s["b"]) <= 10 * tolF
-        assert abs(g["psibar"] - s["psibar"][0]) <= 10 * tolF * max(1.0, abs(s["psibar"][0]))
-        assert abs(g["E"] - s["E"][0]) <= 10 * tolF * abs(s["E"][0])
+              f"Q {rel_inf(g['Q'], s['Q']):.1e}, b {rel_rms(g['b'], s['b']):.1e}, psibar {dpsi_bar:.1e} "
+              f"(max |b| {np.abs(s['b']).max():.2f}), E {dE:.1e} of {abs(s['E'][0]):.2f}", flush=True)
+        if precision == 0:
+            tol = 1e-13
+            assert rel_rms(g["F"], F1) <= tol and rel_inf(g["F"], F1) <= 100 * tol
+            assert rel_inf(g["Q"], s["Q"]) <= 10 * tol and rel_inf(g["b"], s["b"]) <= 10 * tol
+            assert dpsi_bar <= 10 * tol * max(1.0, abs(s["psibar"][0]))
+            assert dE <= 10 * tol * abs(s["E"][0])
+        else:
+            assert rel_rms(g["F"], F1) <= 1e-5
+            assert rel_rms(g["Q"], s["Q"]) <= 3e-5 and rel_rms(g["b"], s["b"]) <= 3e-5
+            assert dpsi_bar <= 3e-5 * np.abs(s["b"]).max()
+            assert dE <= 1e-4 * abs(s["E"][0])
     print(f"precision {precision}: bitwise equal to the single-system steps: {same}", flush=True)
 
 
