@@ -236,9 +236,11 @@ void srbe_graph_destroy(srbe_graph* g);
  * arrays are CSR over replicas: replica r's n_ele(system) entries start at the sum of
  * the n_ele of the replicas before it -- Q_out (required), Q_in (fixed charges, or NULL
  * for the constant-potential solve), b_out (or NULL).  Launch shapes: each system's
- * stored or default parameters for its (precision, replica count, largest replica),
- * with 4 waves and unroll 4 in the potential and force passes and 16-wide GEMM blocks
- * for all.  The modes are sampled on the device (no kset_in / kset_out).  Asynchronous
+ * stored parameters for its (precision, replica count, largest replica), else its
+ * defaults, with 4 waves and unroll 4 in the potential and force passes and 16-wide
+ * GEMM blocks for all; in FP32 the defaults' real-space work splits and structure-factor
+ * chunks are sized from the whole batch (each system its share of the batch's ions),
+ * so FP32 sums may run in another order than in a single-system step.  The modes are sampled on the device (no kset_in / kset_out).  Asynchronous
  * on stream; device faults land in each system's status word (srbe_batch_sync_status).
  * Errors: SRBE_EINVAL, SRBE_ENOMEM, SRBE_EHIP (srbe_batch_last_error gives a message).
  * srbe_batch_graph_* -- the batch step captured with fixed arguments, as srbe_graph_*.
