@@ -17,7 +17,7 @@ kernel there is ~1e-7 of the force).
 import numpy as np
 import pytest
 
-from helpers import gpu_inputs, oracle_params, oracle_solver, oracle_step, rel_inf, rel_rms
+from helpers import forces_from_soa, gpu_inputs, oracle_params, oracle_solver, oracle_step, rel_inf, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -86,3 +86,36 @@ def test_electrode_forces_need_a_step(tiny):
         assert ei.value.code == binding.SRBE_EINVAL
     finally:
         fresh.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_electrode_forces_with_a_replica_without_ions(tiny, precision):
+    """A batch whose middle replica has no ions (in FP32 its electrode records come from
+    the ion-force launch's first block of that replica, which has no ions to move)."""
+    from oracle import srbe
+    from paper_2509_24742_amd import binding
+    w, p, sysm = tiny["w"], tiny["p"], tiny["sys"]
+    ion, q, ele = np.asarray(w["ion_pos"]), np.asarray(w["ion_q"]), np.asarray(w["ele_pos"])
+    none_xyz, none_q = np.zeros((0, 3)), np.zeros(0)
+    ions, qs = [ion, none_xyz, ion], [q, none_q, q]
+    off, xyz, qt, dp, sd = gpu_inputs(ions, qs, DPSI, SEEDS)
+    # the call reads the step's charges from its output buffers: `out` keeps them alive
+    out = sysm.step(off, xyz, qt, dp, sd, STEP, precision=precision)
+    n = len(ele)
+    Fe = torch.empty(3 * 3 * n, dtype=torch.float64, device="cuda")
+    binding.srbe_electrode_forces(sysm.h, 3, Fe)
+    torch.cuda.synchronize()
+    assert binding.srbe_sync_status(sysm.h) == 0, binding.srbe_last_error(sysm.h)
+    Fe = Fe.cpu().numpy().reshape(3, 3 * n)
+    err = []
+    for r, (seed, dpsi) in enumerate(zip(SEEDS, DPSI)):
+        ref = oracle_step(p, tiny["solver"], seed, STEP, ions[r], qs[r], ele, w["ele_side"], dpsi)
+        Fref = srbe.srbe_ele_forces(p, ref["kset"], ions[r], qs[r], ele, ref["Q"])
+        got = Fe[:, r * n:(r + 1) * n].T
+        err.append(rel_rms(got, Fref))
+        Qg = out["Q"].cpu().numpy()[r * n:(r + 1) * n]
+        print(f"  Q {rel_rms(Qg, ref['Q']):.2e}", flush=True)
+        if len(qs[r]):
+            print(f"  F {rel_rms(forces_from_soa(out['F'], off, r), ref['F']):.2e}", flush=True)
+        print(f"precision {precision} replica {r} ({len(qs[r])} ions): electrode force {err[-1]:.2e} rms", flush=True)
+    assert max(err) < (1e-11 if precision == 0 else 1e-5), err
