@@ -950,20 +950,22 @@ __global__ __launch_bounds__(256) void k_sf_finalize(Geom g, const double2* __re
 }
 
 // The same for many chunks per mode (large replicas, where one thread per mode would
-// walk hundreds of dependent load rounds): block (tile of 64 modes, r), its wave w adding
-// the chunks [w nchunk / 16, (w + 1) nchunk / 16) in chunk order, then wave 0 the 16
-// wave sums in wave order.
+// walk hundreds of dependent load rounds): block (tile of 16 modes, r) of 256 threads,
+// thread (slice s, mode m) adding the chunks [s nchunk / 16, (s + 1) nchunk / 16) of its
+// mode in chunk order, then the first 16 threads the 16 slice sums in slice order.
+// Small blocks, since the launch usually runs beside the ion-ion pass, whose waves hold
+// most of the wave slots: a block of 16 waves waited there for a compute unit to drain.
 constexpr int kWideFinalizeChunks = 64;  // above this many chunks per mode
 
-__global__ __launch_bounds__(1024) void k_sf_finalize_wide(Geom g, const double2* __restrict__ part, int nchunk,
-                                                           const int4* __restrict__ modes,
-                                                           const double* __restrict__ w, double2* __restrict__ S1,
-                                                           double2* __restrict__ coef, ModeRec32* __restrict__ rec,
-                                                           int stage, unsigned* status) {
-  __shared__ double2 ws[16][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int r = blockIdx.y, k = blockIdx.x * 64 + lane;
-  const int c0 = (int)((int64_t)wv * nchunk / 16), c1 = (int)((int64_t)(wv + 1) * nchunk / 16);
+__global__ __launch_bounds__(256) void k_sf_finalize_wide(Geom g, const double2* __restrict__ part, int nchunk,
+                                                          const int4* __restrict__ modes,
+                                                          const double* __restrict__ w, double2* __restrict__ S1,
+                                                          double2* __restrict__ coef, ModeRec32* __restrict__ rec,
+                                                          int stage, unsigned* status) {
+  __shared__ double2 ws[16][16];
+  const int m = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int r = blockIdx.y, k = blockIdx.x * 16 + m;
+  const int c0 = (int)((int64_t)sl * nchunk / 16), c1 = (int)((int64_t)(sl + 1) * nchunk / 16);
   double sr = 0.0, si = 0.0;
   if (k < g.K) {
     for (int c = c0; c < c1; c += 16) {
@@ -979,15 +981,15 @@ __global__ __launch_bounds__(1024) void k_sf_finalize_wide(Geom g, const double2
         }
     }
   }
-  ws[wv][lane] = make_double2(sr, si);
+  ws[sl][m] = make_double2(sr, si);
   __syncthreads();
-  if (wv == 0 && k < g.K) {
-    sr = ws[0][lane].x;
-    si = ws[0][lane].y;
+  if (sl == 0 && k < g.K) {
+    sr = ws[0][m].x;
+    si = ws[0][m].y;
 #pragma unroll
     for (int u = 1; u < 16; ++u) {
-      sr += ws[u][lane].x;
-      si += ws[u][lane].y;
+      sr += ws[u][m].x;
+      si += ws[u][m].y;
     }
     finalize_mode(g, r, k, sr, si, modes, w, S1, coef, rec, stage, status);
   }
@@ -997,7 +999,7 @@ void launch_sf_finalize(const Geom& g, const StepBufs& b, int fp32, int stage, h
   if (g.K == 0) return;
   const int nchunk = stage == 1 ? b.nchunk_ion : b.nchunk_ele;
   if (nchunk > kWideFinalizeChunks)
-    hipLaunchKernelGGL(k_sf_finalize_wide, dim3((g.K + 63) / 64, b.R), dim3(1024), 0, s, g, b.part, nchunk, b.modes,
+    hipLaunchKernelGGL(k_sf_finalize_wide, dim3((g.K + 15) / 16, b.R), dim3(256), 0, s, g, b.part, nchunk, b.modes,
                        b.w, b.S1, b.coef, fp32 ? b.rec : nullptr, stage, b.status);
   else
     hipLaunchKernelGGL(k_sf_finalize, dim3(b.ktiles, b.R), dim3(256), 0, s, g, b.part, nchunk, b.modes, b.w, b.S1,
