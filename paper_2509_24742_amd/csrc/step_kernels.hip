@@ -1318,8 +1318,13 @@ __device__ __forceinline__ void wave_scan_list(const uint16_t* __restrict__ list
 
 // Builds the candidate list of a home cell from its runs (lane s: run s as [rb, re)) when
 // there are at least two and they fit (at most kListCap records, spanning under 2^16);
-// returns false otherwise.  total and base: the list's length and offset base.
-__device__ __forceinline__ bool build_list(int rb, int re, uint16_t* __restrict__ list, int& total, int& base) {
+// returns false otherwise.  total and base: the list's length and offset base.  keep(j)
+// drops record j from the list when false: the caller passes a test that is false only
+// for records no ion of the home cell can reach, so the list still holds every partner,
+// in the same order.
+template <class KeepF>
+__device__ __forceinline__ bool build_list(int rb, int re, uint16_t* __restrict__ list, int& total, int& base,
+                                           KeepF keep) {
   const int lane = threadIdx.x & 63;
   const uint64_t live = __ballot(rb < re);
   if (__popcll(live) < 2) return false;
@@ -1335,10 +1340,16 @@ __device__ __forceinline__ bool build_list(int rb, int re, uint16_t* __restrict_
   for (uint64_t m = live; m; m &= m - 1) {
     const int s = __builtin_ctzll(m);
     const int b0 = __builtin_amdgcn_readlane(rb, s), len = __builtin_amdgcn_readlane(re, s) - b0;
-    for (int t = lane; t < len; t += 64) list[at + t] = (uint16_t)(b0 - base + t);
-    at += len;
+#pragma unroll 1
+    for (int t0 = 0; t0 < len; t0 += 64) {
+      const int t = t0 + lane;
+      const bool k = t < len && keep(b0 + t);
+      const uint64_t km = __ballot(k);
+      if (k) list[at + lanes_below(km, 0)] = (uint16_t)(b0 - base + t);
+      at += __popcll(km);
+    }
   }
-  total = n;
+  total = at;
   __builtin_amdgcn_wave_barrier();
   return true;
 }
@@ -2117,7 +2128,10 @@ struct CarriedSums {
 
 // Ion-ion pass, block (bx, r): waves 4 bx .. 4 bx + 3 of replica r, each taking
 // bb.ii_ipw consecutive sorted ions.  lds: ring_bytes<FP32>() + kListBytes bytes.
-template <bool FP32>
+// CULL: the home cells' candidate lists leave out the records out of reach of the
+// cell (grids whose cells have several neighbour runs; the test's registers would
+// cost the one-run grids a wave per SIMD).
+template <bool FP32, bool CULL>
 __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb, int bx, int r, void* lds) {
   const int64_t* __restrict__ off = bb.off;
   const int64_t N = bb.N;
@@ -2192,7 +2206,55 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
     if (hk != home) {
       home = hk;
       resolve_runs(ion_runs + kRunMax * home, ion_range, rb, re);
-      use_list = build_list(rb, re, list, ltotal, lbase);
+      if constexpr (!CULL) {
+        use_list = build_list(rb, re, list, ltotal, lbase, [](int) { return true; });
+      } else {
+      // the list keeps the records within rc (with a margin) of the home cell's box
+      // [c / n_d, (c + 1) / n_d) per axis (z: of the slab height H), a bound on the
+      // distance of every ion of the cell; about a quarter of an rc-cell neighbourhood
+      // lies farther
+      const int cx = home % g.ncx, cy = (home / g.ncx) % g.ncy, cz = home / (g.ncx * g.ncy);
+      const double zc = (cz + 0.5) * g.H / g.ncz * g.invLz, hz = 0.5 * g.H / g.ncz * g.invLz;
+      if constexpr (FP32) {
+        // fixed point: centre and half-width in units of 2^-32 of the box, the half-width
+        // widened by 2^8 units for the records' rounding; lengths squared with a 1e-3 margin
+        // (wave-uniform: kept in scalar registers, so the carried sums keep the vector ones)
+        auto su = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+        const uint32_t Xc = su((uint32_t)((cx + 0.5) / g.ncx * 0x1.0p32)), Yc = su((uint32_t)((cy + 0.5) / g.ncy * 0x1.0p32));
+        const uint32_t Zc = su((uint32_t)(zc * 0x1.0p32));
+        const uint32_t Hx = su((uint32_t)(0x1.0p31 / g.ncx) + 256u), Hy = su((uint32_t)(0x1.0p31 / g.ncy) + 256u);
+        const uint32_t Hz = su((uint32_t)(hz * 0x1.0p32) + 256u);
+        const float lx = (float)(g.Lx * 0x1.0p-32), ly = (float)(g.Ly * 0x1.0p-32), lz = (float)(g.Lz * 0x1.0p-32);
+        const float cut2 = (float)(g.rc * g.rc * 1.001);
+        auto gap = [](uint32_t a, uint32_t c, uint32_t h, float l) {
+          const int32_t d = (int32_t)(a - c);
+          const uint32_t ad = d < 0 ? 0u - (uint32_t)d : (uint32_t)d;
+          return (float)(ad > h ? ad - h : 0u) * l;
+        };
+        use_list = build_list(rb, re, list, ltotal, lbase, [&](int j) {
+          const uint4 q = sfx[j];
+          const float ex = gap(q.x, Xc, Hx, lx), ey = gap(q.y, Yc, Hy, ly), ez = gap(q.z, Zc, Hz, lz);
+          return ex * ex + ey * ey + ez * ez <= cut2;
+        });
+      } else {
+        auto sd = [](double v) {  // wave-uniform, into scalar registers
+          return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                                  __builtin_amdgcn_readfirstlane(__double2loint(v)));
+        };
+        const double xc = sd((cx + 0.5) / g.ncx), yc = sd((cy + 0.5) / g.ncy), zcs = sd(zc);
+        const double hx = sd(0.5 / g.ncx * (1.0 + 1e-9)), hy = sd(0.5 / g.ncy * (1.0 + 1e-9)), hzz = sd(hz * (1.0 + 1e-9));
+        const double cut2 = g.rc * g.rc * (1.0 + 1e-9);
+        use_list = build_list(rb, re, list, ltotal, lbase, [&](int j) {
+          const double4 q = sd4[j];
+          double dx = q.x - xc, dy = q.y - yc;
+          dx -= rint(dx);
+          dy -= rint(dy);
+          const double ex = fmax(fabs(dx) - hx, 0.0) * g.Lx, ey = fmax(fabs(dy) - hy, 0.0) * g.Ly;
+          const double ez = fmax(fabs(q.z - zcs) - hzz, 0.0) * g.Lz;
+          return ex * ex + ey * ey + ez * ez <= cut2;
+        });
+      }
+      }
     }
     if constexpr (FP32) {
       const uint4 pi_ = sfx[k];
@@ -2255,7 +2317,7 @@ __device__ __forceinline__ void real_ii_block(const Geom& g, const StepBufs& bb,
 // ranges, one per XCD, so each L2 holds the records of a slab of consecutive cells
 // (plus the stencil's reach) rather than of the whole system.  A wave's work depends
 // only on (r, bx), so the mapping does not change results.
-template <bool FP32>
+template <bool FP32, bool CULL>
 __device__ __forceinline__ void real_ii_body(const Geom& g, const StepBufs& b, int tiles, int L) {
   __shared__ __align__(16) unsigned char lds[ring_bytes<FP32>() + kListBytes];
   const int j = L >> 3;
@@ -2272,12 +2334,15 @@ __device__ __forceinline__ void real_ii_body(const Geom& g, const StepBufs& b, i
     bx = item - r * tiles;
   }
   if (r >= b.R) return;
-  real_ii_block<FP32>(g, b, bx, r, lds);
+  real_ii_block<FP32, CULL>(g, b, bx, r, lds);
 }
 
-template <bool FP32>
-__global__ __launch_bounds__(256) void k_real_ii(Geom g, StepBufs b, int tiles) {
-  real_ii_body<FP32>(g, b, tiles, blockIdx.x);
+// (8 waves per SIMD in FP32, 3 in FP64: the culling variant spills a few registers
+// rather than give up a wave)
+template <bool FP32, bool CULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FP32 ? 8 : 3))) void k_real_ii(Geom g, StepBufs b,
+                                                                                                     int tiles) {
+  real_ii_body<FP32, CULL>(g, b, tiles, blockIdx.x);
 }
 
 static int real_ii_tiles(const StepBufs& b) { return cdiv64(std::max(b.max_nrep, 1), 4 * b.ii_ipw); }
@@ -2300,10 +2365,15 @@ void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
   if (b.max_nrep == 0) return;
   const int tiles = real_ii_tiles(b);
   const dim3 grid(b.R >= 8 ? 8 * ((b.R + 7) / 8) * tiles : 8 * ((b.R * tiles + 7) / 8));
-  if (fp32)
-    hipLaunchKernelGGL(k_real_ii<true>, grid, dim3(256), 0, s, g, b, tiles);
+  const bool cull = g.ncx > 3 || g.ncy > 3;  // else every cell's neighbours are one run: no lists
+  if (fp32 && cull)
+    hipLaunchKernelGGL((k_real_ii<true, true>), grid, dim3(256), 0, s, g, b, tiles);
+  else if (fp32)
+    hipLaunchKernelGGL((k_real_ii<true, false>), grid, dim3(256), 0, s, g, b, tiles);
+  else if (cull)
+    hipLaunchKernelGGL((k_real_ii<false, true>), grid, dim3(256), 0, s, g, b, tiles);
   else
-    hipLaunchKernelGGL(k_real_ii<false>, grid, dim3(256), 0, s, g, b, tiles);
+    hipLaunchKernelGGL((k_real_ii<false, false>), grid, dim3(256), 0, s, g, b, tiles);
   if (b.etiles) hipLaunchKernelGGL(k_energy_partials, dim3((unsigned)b.R * b.etiles), dim3(256), 0, s, b);
 }
 
@@ -2723,7 +2793,7 @@ __global__ __launch_bounds__((multi_threads<PH, V1, W>())) void k_multi(MultiLau
   } else if constexpr (PH == MP_ION_FORCE) {
     ion_force_body<FP32, W, U>(g, b, ia[0], lb);
   } else if constexpr (PH == MP_REAL_II) {
-    real_ii_body<FP32>(g, b, ia[0], lb);
+    real_ii_body<FP32, true>(g, b, ia[0], lb);
   } else if constexpr (PH == MP_ENERGY_PARTS) {
     energy_partials_body(b, lb);
   } else if constexpr (PH == MP_FINAL) {
@@ -2737,7 +2807,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int s = multi_system(m, blockIdx.x);
   const Geom g = m.d[s].g;  // copies: only the fields the pass reads are loaded
   const StepBufs b = m.d[s].b;
-  real_ii_body<FP32>(g, b, m.iarg[(size_t)kMultiArgs * s], blockIdx.x - m.start[s]);
+  real_ii_body<FP32, true>(g, b, m.iarg[(size_t)kMultiArgs * s], blockIdx.x - m.start[s]);
 }
 
 template <int PH, int V1, int W, int U, int KB>
