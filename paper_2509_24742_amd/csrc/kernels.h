@@ -68,8 +68,6 @@ struct StepBufs {
   const int2* ion_runs;     // ncell x kRunMax neighbour runs [c0, c1), merged across z; c0 = -1 ends
   const int4* ele_rr;       // ncell x kRunMax electrode runs (one z-layer each): sorted range [x, y),
                             // z-extent as float bits (z, w); x = -1 ends a cell's list
-  const float4* ele_rxy;    // ncell x kRunMax: the runs' x-y extents (centre, half-width of the fractional
-                            // x, then of y)
   const int2* reach;        // cell ranges [c0, c1) whose ions can be within rc of an electrode
   int nreach;
   const unsigned char* reach_cell;  // ncell flags: 1 for the cells of those ranges

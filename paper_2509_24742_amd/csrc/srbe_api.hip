@@ -45,8 +45,6 @@ struct srbe_system {
   int2* ion_runs = nullptr;    // ncell x kRunMax neighbour runs, merged across z-layers
   int4* ele_rr = nullptr;      // ncell x kRunMax electrode neighbour runs (one z-layer each) as sorted
                                // ranges [x, y) with their z-extent (z, w: float bits); x = -1 ends
-  float4* ele_rxy = nullptr;   // ncell x kRunMax: the runs' x-y extents (centre and half-width of the
-                               // fractional x, then of y)
   uint4* ele_sfx = nullptr;    // sorted fixed point
   double4* ele_sd4 = nullptr;  // sorted fractional coordinates
   double* Sext = nullptr;      // (n+1) x ldcp(n) row-major: J A^-1 and the psibar row
@@ -813,7 +811,6 @@ void fill_bufs(srbe_system* h, const StepArgs& a, int64_t max_nrep, StepBufs& b)
   b.ele_czr = h->ele_czr;
   b.ion_runs = h->ion_runs;
   b.ele_rr = h->ele_rr;
-  b.ele_rxy = h->ele_rxy;
   b.reach = h->reach;
   b.nreach = h->nreach;
   b.reach_cell = h->reach_cell;
@@ -1388,7 +1385,7 @@ void srbe_destroy(srbe_system* h) {
     if (st) (void)hipStreamDestroy(st);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   void* bufs[] = {h->bin_keys, h->reach, h->reach_cell, h->ele_chunks, h->logq, h->ele_xyz, h->ele_d,   h->ele_fx,  h->ele_d4, h->ele_perm, h->ele_iperm, h->ele_scell, h->ele_cstart,
-                  h->ele_czr, h->ion_runs, h->ele_rr, h->ele_rxy, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev,
+                  h->ele_czr, h->ion_runs, h->ele_rr, h->ele_sfx, h->ele_sd4, h->Sext, h->status, h->ws, h->off_dev,
                   h->lat_site, h->lat_tw, h->lat_linv};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -1456,7 +1453,6 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
     al((void**)&h->ele_czr, (size_t)g.ncell * sizeof(double2));
     al((void**)&h->ion_runs, (size_t)g.ncell * kRunMax * sizeof(int2));
     al((void**)&h->ele_rr, (size_t)g.ncell * kRunMax * sizeof(int4));
-    al((void**)&h->ele_rxy, (size_t)g.ncell * kRunMax * sizeof(float4));
     al((void**)&h->ele_sfx, (n + kScanPad) * sizeof(uint4));
     al((void**)&h->ele_sd4, (n + kScanPad) * sizeof(double4));
     al((void**)&h->status, sizeof(unsigned));
@@ -1580,28 +1576,7 @@ int srbe_create(const srbe_params* params, int32_t n_ele, const double* ele_xyz,
         memcpy(&err[u].z, &lo, 4);
         memcpy(&err[u].w, &hi, 4);
       }
-    // and their x-y extents: centre and half-width of the electrodes' fractional x and y
-    // (a run lies in one row of cells, so it does not wrap), the half-width widened for
-    // its FP32 rounding; an empty run keeps an empty box (its z-extent skips it anyway)
-    std::vector<float4> rxy(eruns.size(), make_float4(0.f, 0.f, 0.f, 0.f));
-    for (size_t u = 0; u < eruns.size(); ++u) {
-      if (eruns[u].x < 0) continue;
-      double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
-      for (int q = ecs[eruns[u].x]; q < ecs[eruns[u].y]; ++q) {
-        const int j = perm[q];
-        double sx = ele_xyz[j] / g.Lx, sy = ele_xyz[n + j] / g.Ly;
-        sx -= std::floor(sx);
-        sy -= std::floor(sy);
-        if (sx >= 1.0) sx -= 1.0;
-        if (sy >= 1.0) sy -= 1.0;
-        x0 = std::min(x0, sx), x1 = std::max(x1, sx), y0 = std::min(y0, sy), y1 = std::max(y1, sy);
-      }
-      if (x0 > x1) continue;
-      rxy[u] = make_float4((float)(0.5 * (x0 + x1)), (float)(0.5 * (x1 - x0) + 1e-6),
-                           (float)(0.5 * (y0 + y1)), (float)(0.5 * (y1 - y0) + 1e-6));
-    }
-    if (hipMemcpy(h->ele_rr, err.data(), err.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->ele_rxy, rxy.data(), rxy.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(h->ele_rr, err.data(), err.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
       return fail(SRBE_EHIP);
     std::vector<int4> chunks;
     for (int c = 0; c < g.ncell; ++c)

@@ -2381,9 +2381,9 @@ void launch_real_ii(const Geom& g, const StepBufs& b, int fp32, hipStream_t s) {
 // block's waves take the replica's ions in turn, one ion per visit.  The pass is
 // latency-bound, so each wave loads the next ion's cell and record while it scans the
 // current one, and an ion's electrode runs come from a set-up table of sorted ranges
-// with their z-extent and x-y extent (two 16-byte loads per run, all runs at once).  A
-// run whose box lies farther than rc from the ion cannot hold a partner and is skipped
-// (the extents are stored in FP32; the margin below covers their rounding).
+// with their z-extent (one 16-byte load per run, all runs at once).  A run whose
+// z-extent lies farther than rc from the ion cannot hold a partner and is skipped
+// (the extent is stored in FP32; the margin below covers its rounding).
 template <bool FP32>
 __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb, int bx, int nbx, int r) {
   const int64_t* __restrict__ off = bb.off;
@@ -2394,7 +2394,6 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
   const int* __restrict__ perm = bb.perm;
   const int* __restrict__ scell = bb.scell;
   const int4* __restrict__ ele_rr = bb.ele_rr;
-  const float4* __restrict__ ele_rxy = bb.ele_rxy;
   const uint4* __restrict__ sfx = bb.sfx;
   const double4* __restrict__ sd4 = bb.sd4;
   const uint4* __restrict__ ele_sfx = bb.ele_sfx;
@@ -2487,26 +2486,14 @@ __device__ __forceinline__ void real_ie_block(const Geom& g, const StepBufs& bb,
     int rb = 0, re = 0;
     {
       const int4 t = lane < kRunMax ? ele_rr[kRunMax * hc + lane] : make_int4(-1, -1, 0, 0);
-      const float4 bx_ = lane < kRunMax ? ele_rxy[kRunMax * hc + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
       const uint64_t term = __ballot(t.x < 0);  // non-zero: the lanes >= kRunMax count as terminators
       const uint64_t listed = (1ull << __builtin_ctzll(term)) - 1;
-      double xi, yi, zi;
-      if constexpr (FP32) {
-        xi = (double)pc.x * 0x1.0p-32, yi = (double)pc.y * 0x1.0p-32, zi = (double)pc.z * (g.Lz * 0x1.0p-32);
-      } else {
-        xi = pc.x, yi = pc.y, zi = pc.z * g.Lz;
-      }
+      double zi;
+      if constexpr (FP32) zi = (double)pc.z * (g.Lz * 0x1.0p-32); else zi = pc.z * g.Lz;
       if ((listed >> lane) & 1) {
-        // the run's box (z-extent, and the x-y extent of its electrodes, periodic) lies at
-        // least zlim from the ion: no partner in it
         const double zlo = (double)__int_as_float(t.z), zhi = (double)__int_as_float(t.w);
-        double dx = xi - (double)bx_.x, dy = yi - (double)bx_.z;
-        dx -= rint(dx);
-        dy -= rint(dy);
-        const double ex = fmax(fabs(dx) - (double)bx_.y, 0.0) * g.Lx, ey = fmax(fabs(dy) - (double)bx_.w, 0.0) * g.Ly;
-        const double ez = fmax(fmax(zlo - zi, zi - zhi), 0.0);
         rb = t.x;
-        re = (ex * ex + ey * ey + ez * ez >= zlim * zlim) ? t.x : t.y;
+        re = (zlo - zi >= zlim || zi - zhi >= zlim) ? t.x : t.y;
       }
     }
     if constexpr (FP32) {
